@@ -1,0 +1,205 @@
+/*
+ * bloch.h -- C ABI of the MI355X (gfx950) Bloch-Maxwell eigensolver.
+ *
+ * The library computes the smallest non-zero eigenvalues lambda and eigenvectors of the
+ * two-dimensional Maxwell problem  curl (1/eps) curl u = lambda u  on the periodic unit
+ * cell [0,a] x [0,b] with Bloch boundary conditions for the parameter k = (k1, k2)
+ * (Boerm, Koehl, Talebi, "Computing Maxwell eigenmodes with Bloch boundary conditions",
+ * arXiv 2304.00337: problem statement in Section 1, Bloch conditions in Section 1 and 2).
+ * Discretisation: lowest-order Nedelec edge elements on an n x m grid with the Bloch-phase
+ * modified basis of Section 3, giving the Hermitian pencil A e = lambda M e.  Method:
+ * block preconditioned inverse iteration with null-space elimination and Ritz step
+ * (Section 4), a geometric multigrid V-cycle for A + mu M as preconditioner and a nodal
+ * multigrid for the null-space projection (Section 5), Rayleigh-quotient extrapolation of
+ * starting blocks across k (Section 6) and throw-away vectors (Section 7).
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ * Indices are 0-based.  Cell (c1,c2) is [c1 h1,(c1+1) h1] x [c2 h2,(c2+1) h2], h1 = a/n,
+ * h2 = b/m, stored at c2*n + c1.  Edge degrees of freedom are line integrals along the
+ * edges: x-edge (j1,j2) from node (j1,j2) to (j1+1,j2) at index j2*n + j1, y-edge (j1,j2)
+ * from (j1,j2) to (j1,j2+1) at index n*m + j2*n + j1 (N_e = 2nm).  Node (j1,j2) sits at
+ * (j1 h1, j2 h2), index j2*n + j1 (N_v = nm).  The Bloch phases are alpha = exp(i k1 a),
+ * beta = exp(i k2 b); a Gamma point (k1 a and k2 b multiples of 2 pi within 1e-14) uses
+ * alpha = beta = 1 exactly and the k = 0 treatment of the null space.
+ *
+ * Device block layout ("planar column blocks"): a block of `ncols` complex vectors of
+ * length N is ncols consecutive columns; column j holds N real parts followed by N
+ * imaginary parts: re(i,j) = base[j*2N + i], im(i,j) = base[j*2N + N + i].  FP64 blocks
+ * are double, FP32 blocks float.  All device pointers are caller-owned device memory on
+ * the device that was current at bl_create; they must not overlap unless stated.
+ *
+ * Host arrays are caller-owned and only read or written during the call.  The solver
+ * handle owns all of its internal device memory and frees it in bl_destroy.  One handle
+ * must not be used from two threads at once; work is issued on the stream given at
+ * creation (NULL = the legacy default stream) and every call returns after that stream
+ * has been synchronised, except where stated.
+ *
+ * Return codes: BL_OK (0) on success, a negative BL_E* code otherwise; bl_strerror gives
+ * a message.  On BL_ENOCONV the outputs hold the current best approximations and their
+ * residuals.
+ */
+#ifndef BLOCH_H_
+#define BLOCH_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BL_OK 0
+#define BL_EINVAL (-1)   /* invalid argument (sizes, eps, k, options, null pointers) */
+#define BL_ENOMEM (-2)   /* device or host allocation failed                          */
+#define BL_EHIP (-3)     /* a HIP runtime call failed                                 */
+#define BL_ENOCONV (-4)  /* max_iter reached before the wanted residuals met tol      */
+#define BL_EAGAIN (-5)   /* result not ready (serving)                                */
+#define BL_ESTATE (-6)   /* call not valid in the handle's current state              */
+
+typedef struct bl_solver bl_solver;
+
+/* The unit cell and its mesh (Section 3): n x m rectangles of the cell a x b. */
+typedef struct bl_grid {
+  int32_t n, m; /* cells per direction; >= 2, even on every smoothed multigrid level   */
+  double a, b;  /* lattice periods, > 0                                                */
+} bl_grid;
+
+/* Options of the iteration.  bl_default_opts fills every field; zero-valued optional
+ * fields select the defaults stated here. */
+typedef struct bl_opts {
+  int32_t nev;          /* wanted smallest non-zero eigenpairs (Section 4), >= 1           */
+  int32_t nthrow;       /* additional throw-away vectors (Section 7), >= 0; p = nev+nthrow */
+  int32_t max_iter;     /* iteration cap per Bloch parameter (default 200)                 */
+  int32_t levels;       /* maximum multigrid levels, 0 = coarsen while possible            */
+  int32_t coarsest_min; /* stop coarsening below this many cells per direction (8)         */
+  int32_t nu_pre;       /* pre-smoothing sweeps of the edge and nodal V-cycles (1)         */
+  int32_t nu_post;      /* post-smoothing sweeps (1)                                       */
+  int32_t nodal_cycles; /* nodal V-cycles per null-space projection (Section 5) (2)        */
+  int32_t variant;      /* 0 = gradient method [E_hat, E], 1 = LOBPCG (Section 4)          */
+  int32_t precision;    /* 0 = FP64 throughout, 1 = mixed: V-cycle and nodal projection in
+                           complex FP32, residuals, Gram, Ritz and extrapolation in FP64   */
+  int32_t extrap_depth; /* previous Bloch parameters used for extrapolation, 1..3 (3)      */
+  int32_t reserved0;
+  double tol;           /* stop when ||A e_i - lambda_i M e_i||_2 / (lambda_i ||M e_i||_2)
+                           <= tol for the first nev vectors (1e-8)                         */
+  double mu;            /* regularisation of the preconditioned A + mu M (Section 5);
+                           <= 0 selects mu = lambda_p(eps_min) / 10 of the homogeneous
+                           cell at k = 0, p = nev + nthrow                                 */
+  double zero_rel;      /* extrapolation skips Ritz values below zero_rel times the
+                           smallest eigenvalue of the previous parameter (1e-2)            */
+} bl_opts;
+
+/* Read-only facts about a solver handle. */
+typedef struct bl_info {
+  int32_t n, m, p, nev, levels, precision;
+  int32_t level_n[16], level_m[16];
+  double mu;
+  size_t device_bytes;  /* device memory held by the handle */
+  int64_t kernel_launches; /* launches issued since creation */
+} bl_info;
+
+/* Fill *opts with the defaults for `nev` wanted eigenpairs (nthrow = nev/2). */
+void bl_default_opts(bl_opts* opts, int32_t nev);
+
+/* Create a solver for the grid and permittivity (Section 1: eps periodic; Section 3:
+ * piecewise constant per cell).  eps_cells: host array of n*m values > 0, finite, in cell
+ * order; it is copied.  opts may be NULL (defaults for nev = 8).  stream: a hipStream_t
+ * or NULL.  Sets up the multigrid hierarchy (bisection, Section 5) and the stabilised
+ * node-patch factors (Section 5).  Errors: BL_EINVAL (sizes, eps, options), BL_ENOMEM,
+ * BL_EHIP.  *out is NULL on error. */
+int bl_create(const bl_grid* grid, const double* eps_cells, const bl_opts* opts,
+              void* stream, bl_solver** out);
+
+/* Free everything the handle owns.  NULL is allowed. */
+void bl_destroy(bl_solver* s);
+
+/* Device memory a solver for (grid, opts) will hold, in bytes (admission control). */
+size_t bl_footprint_bytes(const bl_grid* grid, const bl_opts* opts);
+
+int bl_get_info(const bl_solver* s, bl_info* out);
+
+/* Solve for one Bloch parameter k (Section 4 iteration).
+ * start_dev: device FP64 planar block of p = nev+nthrow columns of length N_e used as the
+ *   starting block (it is null-space projected, M-orthonormalised and Ritz-rotated), or
+ *   NULL to extrapolate from the eigenvector blocks of the previously solved parameters
+ *   kept in the handle (Section 6); BL_ESTATE if NULL and no history exists.
+ * evals (host, nev), relres (host, nev): results; iters (host, 1): iterations used.
+ * evecs_dev: NULL or device FP64 planar block of nev columns receiving M-orthonormal
+ *   eigenvectors (each column's phase is arbitrary).
+ * The solved block is pushed onto the handle's history (depth extrap_depth). */
+int bl_solve_k(bl_solver* s, double k1, double k2, const void* start_dev, double* evals,
+               double* relres, int32_t* iters, void* evecs_dev);
+
+/* Band path: bl_solve_k for ks[2*t], ks[2*t+1], t = 0..nk-1, the first from start_dev
+ * (or from the history when start_dev is NULL), every later one extrapolated from up to
+ * extrap_depth predecessors (Section 6).  evals, relres: host nk*nev (row t = point t);
+ * iters: host nk.  evecs_last_dev: NULL or device block of nev columns for the last
+ * point.  Returns the first non-OK status, after finishing the path (BL_ENOCONV points
+ * keep their best approximations). */
+int bl_solve_path(bl_solver* s, const double* ks, int32_t nk, const void* start_dev,
+                  double* evals, double* relres, int32_t* iters, void* evecs_last_dev);
+
+/* Forget the extrapolation history. */
+int bl_reset_history(bl_solver* s);
+
+/* Per-iteration record of the last bl_solve_k: up to `cap` entries of nev relative
+ * residuals each (host, row = iteration 0..), returns the number of rows written. */
+int bl_last_residual_history(const bl_solver* s, double* relres, int32_t cap);
+
+/* ---- Operator-level entry points (kernel tests and measurement) ------------------------
+ * bl_set_k fixes the Bloch parameter for bl_apply (and assembles the coarse factors).
+ * bl_apply runs one operator on `ncols` columns.  `prec` 0 = FP64 blocks, 1 = FP32.
+ * `level` indexes the multigrid hierarchy (0 = finest).  Shapes per op:
+ *   BL_OP_A, BL_OP_M, BL_OP_K    out = A x, M x, (A + mu M) x          edge -> edge
+ *   BL_OP_LIFT                   out = L x (gradient of a nodal field) nodal -> edge
+ *   BL_OP_LHM                    out = L^* M x                         edge -> nodal
+ *   BL_OP_P                      out = L^* M L x (9-point, Section 5)  nodal -> nodal
+ *   BL_OP_EDGE_SMOOTH            out (in/out, edge) <- one forward colour sweep 0..3 of
+ *                                node-patch block Gauss-Seidel for K x = y (y = rhs)
+ *   BL_OP_EDGE_SMOOTH_BACK       same with colours 3..0
+ *   BL_OP_NODAL_SMOOTH           out (in/out, nodal) <- forward point GS sweep for P
+ *   BL_OP_EDGE_VCYCLE            out = V-cycle(K, level) applied to x (zero start)
+ *   BL_OP_NODAL_VCYCLE           out = V-cycle(P, level) applied to x (zero start)
+ *   BL_OP_EDGE_PROLONG           out(level) = Pr x(level+1)            edge
+ *   BL_OP_EDGE_RESTRICT          out(level+1) = Pr^* x(level)          edge
+ *   BL_OP_NODAL_PROLONG          out(level) = Pn x(level+1)            nodal
+ *   BL_OP_NODAL_RESTRICT         out(level+1) = Pn^* x(level)          nodal
+ *   BL_OP_PROJECT                out = x - L Phi, Phi from nodal_cycles V-cycles for
+ *                                P Phi = L^* M x (and the k = 0 deflation) (Section 4)
+ *   BL_OP_COARSE_EDGE            out = K_c^{-1} x on the coarsest level
+ *   BL_OP_COARSE_NODAL           out = P_c^{+} x on the coarsest level
+ * x, y, out: device blocks (y only for the smoothers).  Errors: BL_EINVAL, BL_ESTATE
+ * (no k set), BL_EHIP. */
+enum {
+  BL_OP_A = 0, BL_OP_M = 1, BL_OP_K = 2, BL_OP_LIFT = 3, BL_OP_LHM = 4, BL_OP_P = 5,
+  BL_OP_EDGE_SMOOTH = 6, BL_OP_EDGE_SMOOTH_BACK = 7, BL_OP_NODAL_SMOOTH = 8,
+  BL_OP_EDGE_VCYCLE = 9, BL_OP_NODAL_VCYCLE = 10, BL_OP_EDGE_PROLONG = 11,
+  BL_OP_EDGE_RESTRICT = 12, BL_OP_NODAL_PROLONG = 13, BL_OP_NODAL_RESTRICT = 14,
+  BL_OP_PROJECT = 15, BL_OP_COARSE_EDGE = 16, BL_OP_COARSE_NODAL = 17
+};
+int bl_set_k(bl_solver* s, double k1, double k2);
+int bl_apply(bl_solver* s, int32_t op, int32_t level, int32_t prec, int32_t ncols,
+             const void* x, const void* y, void* out);
+
+/* Dense FP64 helpers of the Ritz step (Section 4), exposed for tests.
+ * bl_gram: out (host q x r, row-major complex interleaved re,im) = X^* W for device
+ *   planar FP64 blocks X (q columns) and W (r columns) of length len.
+ * bl_ritz_small: generalized Hermitian eigenproblem H y = theta G y for host q x q
+ *   row-major interleaved complex G (Hermitian positive semi-definite) and H (Hermitian):
+ *   directions with relative G-eigenvalue below 1e-12 are dropped, the `want` smallest
+ *   Ritz values above zero_thr are returned in theta (host) and their G-orthonormal
+ *   coefficient vectors in Y (host q x want, row-major interleaved).  Runs on the GPU.
+ *   Returns the number of values found (>= 0) or an error. */
+int bl_gram(bl_solver* s, const void* X, int32_t q, const void* W, int32_t r, int64_t len,
+            double* out);
+int bl_ritz_small(bl_solver* s, const double* G, const double* H, int32_t q, int32_t want,
+                  double zero_thr, double* theta, double* Y);
+
+const char* bl_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BLOCH_H_ */
