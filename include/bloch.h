@@ -197,6 +197,8 @@ int bl_ritz_small(bl_solver* s, const double* G, const double* H, int32_t q, int
                   double zero_thr, double* theta, double* Y);
 
 const char* bl_strerror(int code);
+/* Message of the most recent error on the calling thread (static storage). */
+const char* bl_last_error(void);
 
 #ifdef __cplusplus
 }

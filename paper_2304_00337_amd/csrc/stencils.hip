@@ -1,0 +1,784 @@
+// Edge and nodal stencil kernels for gfx950: the Bloch-phase Nedelec curl-curl and mass
+// operators (Section 3), the node-patch block Gauss-Seidel smoother with the stabilised
+// 4x4 solve and the grid transfers of the bisection hierarchy (Section 5), the null-space
+// projection operators L, L^* M and P = L^* M L (Section 4 and 5).
+//
+// All kernels work in "extended" coordinates: a vector index outside [0,n) x [0,m) is
+// read through the Bloch extension u(j1 + s1 n, j2 + s2 m) = alpha^s1 beta^s2 u(j1, j2),
+// so every stencil is the plain translation-invariant one and the phases enter only
+// through the reads (and writes) that cross the cell boundary.  The local patch matrices
+// are therefore real and independent of k.
+#include "internal.h"
+
+#include <cmath>
+
+namespace bl {
+
+template <typename T>
+struct Cx {
+  T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ Cx<T> operator+(Cx<T> a, Cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ Cx<T> operator-(Cx<T> a, Cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ Cx<T> operator*(T s, Cx<T> a) { return {s * a.re, s * a.im}; }
+template <typename T>
+__device__ __forceinline__ Cx<T> cmul(Cx<T> a, T br, T bi) {
+  return {a.re * br - a.im * bi, a.re * bi + a.im * br};
+}
+
+// Phases in the kernel's arithmetic type.
+template <typename T>
+struct Ph {
+  T ar, ai, br, bi;
+};
+template <typename T>
+__host__ __device__ inline Ph<T> cast_phase(const Phase& p) {
+  return {(T)p.ar, (T)p.ai, (T)p.br, (T)p.bi};
+}
+
+// Read component `off` (0 for x-edges / nodes, nm for y-edges) at extended (j1, j2),
+// j1 in [-n, 2n), j2 in [-m, 2m).
+template <typename TS, typename T>
+__device__ __forceinline__ Cx<T> fetch(const TS* __restrict__ col, int64_t N, int n, int m,
+                                       int64_t off, int j1, int j2, const Ph<T>& p) {
+  int s1 = 0, s2 = 0;
+  if (j1 < 0) { j1 += n; s1 = -1; } else if (j1 >= n) { j1 -= n; s1 = 1; }
+  if (j2 < 0) { j2 += m; s2 = -1; } else if (j2 >= m) { j2 -= m; s2 = 1; }
+  const int64_t i = off + (int64_t)j2 * n + j1;
+  Cx<T> v = {(T)col[i], (T)col[N + i]};
+  if (s1 > 0) v = cmul(v, p.ar, p.ai);
+  else if (s1 < 0) v = cmul(v, p.ar, -p.ai);
+  if (s2 > 0) v = cmul(v, p.br, p.bi);
+  else if (s2 < 0) v = cmul(v, p.br, -p.bi);
+  return v;
+}
+
+// Add delta (given in extended coordinates) to the stored value at extended (j1, j2),
+// j1 in [-1, n), j2 in [-1, m): u_can = conj(phase) * u_ext.
+template <typename TS, typename T>
+__device__ __forceinline__ void add_ext(TS* __restrict__ col, int64_t N, int n, int m, int64_t off,
+                                        int j1, int j2, Cx<T> d, const Ph<T>& p) {
+  if (j1 < 0) { j1 += n; d = cmul(d, p.ar, p.ai); }
+  if (j2 < 0) { j2 += m; d = cmul(d, p.br, p.bi); }
+  const int64_t i = off + (int64_t)j2 * n + j1;
+  col[i] = (TS)((T)col[i] + d.re);
+  col[N + i] = (TS)((T)col[N + i] + d.im);
+}
+
+__device__ __forceinline__ int wrapi(int j, int n) { return j < 0 ? j + n : (j >= n ? j - n : j); }
+
+template <typename T>
+__device__ __forceinline__ T kap(const double* k64, const float* k32, int64_t i);
+template <>
+__device__ __forceinline__ double kap<double>(const double* k64, const float*, int64_t i) { return k64[i]; }
+template <>
+__device__ __forceinline__ float kap<float>(const double*, const float* k32, int64_t i) { return k32[i]; }
+
+// Cell curl (circulation) of cell (c1, c2), extended c in [-1, n).
+template <typename TS, typename T>
+__device__ __forceinline__ Cx<T> cell_curl(const TS* col, int64_t N, int n, int m, int64_t nm,
+                                           int c1, int c2, const Ph<T>& p) {
+  return fetch<TS, T>(col, N, n, m, 0, c1, c2 + 1, p) - fetch<TS, T>(col, N, n, m, 0, c1, c2, p) +
+         fetch<TS, T>(col, N, n, m, nm, c1, c2, p) - fetch<TS, T>(col, N, n, m, nm, c1 + 1, c2, p);
+}
+
+// ------------------------------------------------------------------------------------------
+// Edge operators: A (curl-curl with kappa = 1/eps), M (mass), K = A + mu M and residuals.
+// Thread per (edge, column); T is the arithmetic type (double, or float with float data).
+template <typename TI, typename TO, typename T, int MODE>
+__global__ __launch_bounds__(256) void k_edge_apply(const TI* __restrict__ x, const TI* __restrict__ b,
+                                                    TO* __restrict__ out, const double* __restrict__ k64,
+                                                    const float* __restrict__ k32,
+                                                    const double* __restrict__ lam, Geo g, Phase php,
+                                                    double mud, double* __restrict__ partial) {
+  const int col = blockIdx.y;
+  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = g.n, m = g.m;
+  const int64_t nm = g.nm, N = g.ne;
+  const Ph<T> p = cast_phase<T>(php);
+  const TI* xc = x + (int64_t)col * 2 * N;
+  T rr = 0, mm = 0;
+  if (d < N) {
+    Cx<T> Au, Mu;
+    const T s = (T)g.s;
+    const T two3 = (T)(2.0 / 3.0), one6 = (T)(1.0 / 6.0);
+    if (d < nm) {
+      const int j1 = (int)(d % n), j2 = (int)(d / n);
+      const Cx<T> wlo = cell_curl<TI, T>(xc, N, n, m, nm, j1, j2 - 1, p);
+      const Cx<T> whi = cell_curl<TI, T>(xc, N, n, m, nm, j1, j2, p);
+      const T klo = kap<T>(k64, k32, (int64_t)wrapi(j2 - 1, m) * n + j1);
+      const T khi = kap<T>(k64, k32, (int64_t)j2 * n + j1);
+      Au = s * ((klo * wlo) - (khi * whi));
+      const Cx<T> u0 = {(T)xc[d], (T)xc[N + d]};
+      Mu = (T)g.mx * ((two3 * u0) + one6 * (fetch<TI, T>(xc, N, n, m, 0, j1, j2 + 1, p) +
+                                            fetch<TI, T>(xc, N, n, m, 0, j1, j2 - 1, p)));
+    } else {
+      const int64_t e = d - nm;
+      const int j1 = (int)(e % n), j2 = (int)(e / n);
+      const Cx<T> wr = cell_curl<TI, T>(xc, N, n, m, nm, j1, j2, p);
+      const Cx<T> wl = cell_curl<TI, T>(xc, N, n, m, nm, j1 - 1, j2, p);
+      const T kr = kap<T>(k64, k32, (int64_t)j2 * n + j1);
+      const T kl = kap<T>(k64, k32, (int64_t)j2 * n + wrapi(j1 - 1, n));
+      Au = s * ((kr * wr) - (kl * wl));
+      const Cx<T> u0 = {(T)xc[d], (T)xc[N + d]};
+      Mu = (T)g.my * ((two3 * u0) + one6 * (fetch<TI, T>(xc, N, n, m, nm, j1 + 1, j2, p) +
+                                            fetch<TI, T>(xc, N, n, m, nm, j1 - 1, j2, p)));
+    }
+    Cx<T> r;
+    if (MODE == EM_A) {
+      r = Au;
+    } else if (MODE == EM_M) {
+      r = Mu;
+    } else if (MODE == EM_K) {
+      r = Au + ((T)mud * Mu);
+    } else if (MODE == EM_RESID_K) {
+      const TI* bc = b + (int64_t)col * 2 * N;
+      r = Cx<T>{(T)bc[d], (T)bc[N + d]} - (Au + ((T)mud * Mu));
+    } else {
+      r = Au - ((T)lam[col] * Mu);
+      rr = r.re * r.re + r.im * r.im;
+      mm = Mu.re * Mu.re + Mu.im * Mu.im;
+    }
+    TO* oc = out + (int64_t)col * 2 * N;
+    oc[d] = (TO)r.re;
+    oc[N + d] = (TO)r.im;
+  }
+  if (MODE == EM_EIGRES) {
+    // block reduction of the two squared norms, one partial per block
+    __shared__ double sh[2][256 / 64];
+    double a = rr, c = mm;
+    for (int o = 32; o > 0; o >>= 1) {
+      a += __shfl_down(a, o, 64);
+      c += __shfl_down(c, o, 64);
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) { sh[0][wv] = a; sh[1][wv] = c; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double ta = 0, tc = 0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { ta += sh[0][w]; tc += sh[1][w]; }
+      double* pp = partial + ((int64_t)col * gridDim.x + blockIdx.x) * 2;
+      pp[0] = ta;
+      pp[1] = tc;
+    }
+  }
+}
+
+template <typename TI, typename TO>
+void edge_apply(int mode, const TI* x, const TI* b, TO* out, const double* kappa64,
+                const float* kappa32, const double* lam, const Geo& g, const Phase& ph,
+                double mu, int ncols, double* norms_partial, int* nblk_out, hipStream_t st) {
+  using T = typename std::conditional<std::is_same<TI, double>::value, double, float>::type;
+  const int bs = 256;
+  dim3 grid((unsigned)((g.ne + bs - 1) / bs), (unsigned)ncols);
+  if (nblk_out) *nblk_out = (int)grid.x;
+  switch (mode) {
+    case EM_A: k_edge_apply<TI, TO, T, EM_A><<<grid, bs, 0, st>>>(x, b, out, kappa64, kappa32, lam, g, ph, mu, norms_partial); break;
+    case EM_M: k_edge_apply<TI, TO, T, EM_M><<<grid, bs, 0, st>>>(x, b, out, kappa64, kappa32, lam, g, ph, mu, norms_partial); break;
+    case EM_K: k_edge_apply<TI, TO, T, EM_K><<<grid, bs, 0, st>>>(x, b, out, kappa64, kappa32, lam, g, ph, mu, norms_partial); break;
+    case EM_RESID_K: k_edge_apply<TI, TO, T, EM_RESID_K><<<grid, bs, 0, st>>>(x, b, out, kappa64, kappa32, lam, g, ph, mu, norms_partial); break;
+    default: k_edge_apply<TI, TO, T, EM_EIGRES><<<grid, bs, 0, st>>>(x, b, out, kappa64, kappa32, lam, g, ph, mu, norms_partial); break;
+  }
+}
+
+template void edge_apply<double, double>(int, const double*, const double*, double*, const double*, const float*, const double*, const Geo&, const Phase&, double, int, double*, int*, hipStream_t);
+template void edge_apply<double, float>(int, const double*, const double*, float*, const double*, const float*, const double*, const Geo&, const Phase&, double, int, double*, int*, hipStream_t);
+template void edge_apply<float, float>(int, const float*, const float*, float*, const double*, const float*, const double*, const Geo&, const Phase&, double, int, double*, int*, hipStream_t);
+
+// Sum per-block partials: out[j*nval + v] = sum_b partial[(j*nblk + b)*nval + v].
+__global__ void k_reduce_partials(const double* __restrict__ partial, int nblk, int nval,
+                                  double* __restrict__ out) {
+  const int col = blockIdx.x;
+  __shared__ double sh[4][256];
+  for (int v = 0; v < nval; ++v) {
+    double a = 0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) a += partial[((int64_t)col * nblk + b) * nval + v];
+    sh[v][threadIdx.x] = a;
+  }
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int v = 0; v < nval; ++v) sh[v][threadIdx.x] += sh[v][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int v = 0; v < nval; ++v) out[(int64_t)col * nval + v] = sh[v][0];
+}
+
+void reduce_partials(const double* partial, int nblk, int ncols, int nval, double* out,
+                     hipStream_t st) {
+  k_reduce_partials<<<ncols, 256, 0, st>>>(partial, nblk, nval, out);
+}
+
+// ------------------------------------------------------------------------------------------
+// Node-patch block Gauss-Seidel (Section 5): for every node of one colour, the residual of
+// K = A + mu M on the four edges touching the node (e0 = right x-edge, e1 = left x-edge,
+// e2 = upper y-edge, e3 = lower y-edge, extended coordinates) is computed, the 4x4 patch
+// system is solved in the stabilised form  delta = T diag(1/mu, S^{-1}) T^T r  (the first
+// column of T spans the node's gradient, on which K acts as mu times the mass), and the
+// four edges are updated.  Same-colour patches are uncoupled, so the nodes of a colour are
+// processed in parallel with the same result as one after the other.
+template <typename T>
+__device__ __forceinline__ const T* pick(const double* a, const float* b);
+template <>
+__device__ __forceinline__ const double* pick<double>(const double* a, const float*) { return a; }
+template <>
+__device__ __forceinline__ const float* pick<float>(const double*, const float* b) { return b; }
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_edge_gs(T* __restrict__ x, const T* __restrict__ b,
+                                                 const double* __restrict__ k64,
+                                                 const float* __restrict__ k32,
+                                                 const double* __restrict__ si64,
+                                                 const float* __restrict__ si32, Geo g, Phase php,
+                                                 double mud, PatchT T4, int colour) {
+  const int col = blockIdx.y;
+  const int n = g.n, m = g.m, nh = n >> 1, mh = m >> 1;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)nh * mh) return;
+  const int p1 = 2 * (int)(t % nh) + (colour & 1);
+  const int p2 = 2 * (int)(t / nh) + (colour >> 1);
+  const int64_t nm = g.nm, N = g.ne;
+  const Ph<T> p = cast_phase<T>(php);
+  T* xc = x + (int64_t)col * 2 * N;
+  const T* bc = b + (int64_t)col * 2 * N;
+  const Cx<T> X00 = fetch<T, T>(xc, N, n, m, 0, p1, p2, p);
+  const Cx<T> X01 = fetch<T, T>(xc, N, n, m, 0, p1, p2 + 1, p);
+  const Cx<T> X0m = fetch<T, T>(xc, N, n, m, 0, p1, p2 - 1, p);
+  const Cx<T> Xm0 = fetch<T, T>(xc, N, n, m, 0, p1 - 1, p2, p);
+  const Cx<T> Xm1 = fetch<T, T>(xc, N, n, m, 0, p1 - 1, p2 + 1, p);
+  const Cx<T> Xmm = fetch<T, T>(xc, N, n, m, 0, p1 - 1, p2 - 1, p);
+  const Cx<T> Y00 = fetch<T, T>(xc, N, n, m, nm, p1, p2, p);
+  const Cx<T> Y10 = fetch<T, T>(xc, N, n, m, nm, p1 + 1, p2, p);
+  const Cx<T> Ym0 = fetch<T, T>(xc, N, n, m, nm, p1 - 1, p2, p);
+  const Cx<T> Y0m = fetch<T, T>(xc, N, n, m, nm, p1, p2 - 1, p);
+  const Cx<T> Y1m = fetch<T, T>(xc, N, n, m, nm, p1 + 1, p2 - 1, p);
+  const Cx<T> Ymm = fetch<T, T>(xc, N, n, m, nm, p1 - 1, p2 - 1, p);
+  const Cx<T> wne = X01 - X00 + Y00 - Y10;
+  const Cx<T> wnw = Xm1 - Xm0 + Ym0 - Y00;
+  const Cx<T> wsw = Xm0 - Xmm + Ymm - Y0m;
+  const Cx<T> wse = X00 - X0m + Y0m - Y1m;
+  const int p1m = wrapi(p1 - 1, n), p2m = wrapi(p2 - 1, m);
+  const T kne = kap<T>(k64, k32, (int64_t)p2 * n + p1);
+  const T knw = kap<T>(k64, k32, (int64_t)p2 * n + p1m);
+  const T ksw = kap<T>(k64, k32, (int64_t)p2m * n + p1m);
+  const T kse = kap<T>(k64, k32, (int64_t)p2m * n + p1);
+  const T s = (T)g.s, mu = (T)mud;
+  const T two3 = (T)(2.0 / 3.0), one6 = (T)(1.0 / 6.0);
+  const T mmx = mu * (T)g.mx, mmy = mu * (T)g.my;
+  Cx<T> r[4];
+  r[0] = fetch<T, T>(bc, N, n, m, 0, p1, p2, p) -
+         ((s * ((kse * wse) - (kne * wne))) + mmx * ((two3 * X00) + one6 * (X01 + X0m)));
+  r[1] = fetch<T, T>(bc, N, n, m, 0, p1 - 1, p2, p) -
+         ((s * ((ksw * wsw) - (knw * wnw))) + mmx * ((two3 * Xm0) + one6 * (Xm1 + Xmm)));
+  r[2] = fetch<T, T>(bc, N, n, m, nm, p1, p2, p) -
+         ((s * ((kne * wne) - (knw * wnw))) + mmy * ((two3 * Y00) + one6 * (Y10 + Ym0)));
+  r[3] = fetch<T, T>(bc, N, n, m, nm, p1, p2 - 1, p) -
+         ((s * ((kse * wse) - (ksw * wsw))) + mmy * ((two3 * Y0m) + one6 * (Y1m + Ymm)));
+  // y = T^T r
+  Cx<T> y[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    Cx<T> acc = {0, 0};
+#pragma unroll
+    for (int l = 0; l < 4; ++l) acc = acc + ((T)T4.t[l * 4 + a] * r[l]);
+    y[a] = acc;
+  }
+  const T* si = pick<T>(si64, si32) + 6 * ((int64_t)p2 * n + p1);
+  const T s00 = si[0], s01 = si[1], s02 = si[2], s11 = si[3], s12 = si[4], s22 = si[5];
+  Cx<T> z[4];
+  z[0] = ((T)1 / mu) * y[0];
+  z[1] = (s00 * y[1]) + (s01 * y[2]) + (s02 * y[3]);
+  z[2] = (s01 * y[1]) + (s11 * y[2]) + (s12 * y[3]);
+  z[3] = (s02 * y[1]) + (s12 * y[2]) + (s22 * y[3]);
+  Cx<T> dl[4];
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    Cx<T> acc = {0, 0};
+#pragma unroll
+    for (int a = 0; a < 4; ++a) acc = acc + ((T)T4.t[l * 4 + a] * z[a]);
+    dl[l] = acc;
+  }
+  add_ext<T, T>(xc, N, n, m, 0, p1, p2, dl[0], p);
+  add_ext<T, T>(xc, N, n, m, 0, p1 - 1, p2, dl[1], p);
+  add_ext<T, T>(xc, N, n, m, nm, p1, p2, dl[2], p);
+  add_ext<T, T>(xc, N, n, m, nm, p1, p2 - 1, dl[3], p);
+}
+
+template <typename T>
+void edge_gs(T* x, const T* b, const double* kappa64, const float* kappa32,
+             const double* sinv64, const float* sinv32, const Geo& g, const Phase& ph,
+             double mu, const PatchT& T4, int colour, int ncols, hipStream_t st) {
+  const int64_t cnt = (int64_t)(g.n / 2) * (g.m / 2);
+  dim3 grid((unsigned)((cnt + 255) / 256), (unsigned)ncols);
+  k_edge_gs<T><<<grid, 256, 0, st>>>(x, b, kappa64, kappa32, sinv64, sinv32, g, ph, mu, T4, colour);
+}
+template void edge_gs<double>(double*, const double*, const double*, const float*, const double*, const float*, const Geo&, const Phase&, double, const PatchT&, int, int, hipStream_t);
+template void edge_gs<float>(float*, const float*, const double*, const float*, const double*, const float*, const Geo&, const Phase&, double, const PatchT&, int, int, hipStream_t);
+
+// Per-node inverse of the 3x3 block S = (Q'^T D^{-1/2} A_loc D^{-1/2} Q') + mu I of the
+// stabilised patch system, Q' = columns 2..4 of the orthogonal Q (passed row-major in q).
+// A_loc = (1/(h1 h2)) sum over the four cells of kappa_c c_c c_c^T with the cell
+// circulation vectors c over (e0, e1, e2, e3): NE (-1,0,1,0), NW (0,-1,-1,0),
+// SW (0,1,0,-1), SE (1,0,0,1).  Stored as (s00, s01, s02, s11, s12, s22).
+struct Q16 {
+  double q[16];
+};
+__global__ void k_patch_setup(const double* __restrict__ kappa, Geo g, Q16 Q, double mu,
+                              double* __restrict__ s64, float* __restrict__ s32) {
+  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (node >= g.nm) return;
+  const int n = g.n, m = g.m;
+  const int p1 = (int)(node % n), p2 = (int)(node / n);
+  const int p1m = wrapi(p1 - 1, n), p2m = wrapi(p2 - 1, m);
+  const double kc[4] = {kappa[(int64_t)p2 * n + p1], kappa[(int64_t)p2 * n + p1m],
+                        kappa[(int64_t)p2m * n + p1m], kappa[(int64_t)p2m * n + p1]};
+  const double cv[4][4] = {{-1, 0, 1, 0}, {0, -1, -1, 0}, {0, 1, 0, -1}, {1, 0, 0, 1}};
+  const double dx = g.mx * 2.0 / 3.0, dy = g.my * 2.0 / 3.0;
+  const double dinv[4] = {1.0 / sqrt(dx), 1.0 / sqrt(dx), 1.0 / sqrt(dy), 1.0 / sqrt(dy)};
+  double Ah[4][4];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      double a = 0;
+      for (int c = 0; c < 4; ++c) a += kc[c] * cv[c][i] * cv[c][j];
+      Ah[i][j] = a * g.s * dinv[i] * dinv[j];
+    }
+  double S[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int bb = 0; bb < 3; ++bb) {
+      double v = 0;
+      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) v += Q.q[i * 4 + a + 1] * Ah[i][j] * Q.q[j * 4 + bb + 1];
+      S[a][bb] = v + (a == bb ? mu : 0.0);
+    }
+  // symmetric 3x3 inverse by cofactors (S is SPD and well conditioned)
+  const double c00 = S[1][1] * S[2][2] - S[1][2] * S[2][1];
+  const double c01 = S[1][2] * S[2][0] - S[1][0] * S[2][2];
+  const double c02 = S[1][0] * S[2][1] - S[1][1] * S[2][0];
+  const double det = S[0][0] * c00 + S[0][1] * c01 + S[0][2] * c02;
+  const double id = 1.0 / det;
+  const double i00 = c00 * id, i01 = c01 * id, i02 = c02 * id;
+  const double i11 = (S[0][0] * S[2][2] - S[0][2] * S[2][0]) * id;
+  const double i12 = (S[0][2] * S[1][0] - S[0][0] * S[1][2]) * id;
+  const double i22 = (S[0][0] * S[1][1] - S[0][1] * S[1][0]) * id;
+  const double out[6] = {i00, i01, i02, i11, i12, i22};
+  for (int i = 0; i < 6; ++i) {
+    s64[node * 6 + i] = out[i];
+    s32[node * 6 + i] = (float)out[i];
+  }
+}
+
+void patch_setup(const double* kappa, const Geo& g, const PatchT& T4, const double* q,
+                 double mu, double* sinv64, float* sinv32, hipStream_t st) {
+  (void)T4;
+  Q16 Q;
+  for (int i = 0; i < 16; ++i) Q.q[i] = q[i];
+  k_patch_setup<<<(unsigned)((g.nm + 255) / 256), 256, 0, st>>>(kappa, g, Q, mu, sinv64, sinv32);
+}
+
+// kappa on the next coarser level: mean over the 2x2 children (Galerkin coarse operator
+// of the edge embedding equals rediscretisation with this coefficient).
+__global__ void k_coarsen_kappa(const double* __restrict__ kf, int nf, double* __restrict__ kc,
+                                int nc, int mc) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= (int64_t)nc * mc) return;
+  const int c1 = (int)(c % nc), c2 = (int)(c / nc);
+  const int64_t f = (int64_t)(2 * c2) * nf + 2 * c1;
+  kc[c] = 0.25 * (kf[f] + kf[f + 1] + kf[f + nf] + kf[f + nf + 1]);
+}
+void coarsen_kappa(const double* kf, const Geo& gf, double* kc, hipStream_t st) {
+  const int nc = gf.n / 2, mc = gf.m / 2;
+  k_coarsen_kappa<<<(unsigned)(((int64_t)nc * mc + 255) / 256), 256, 0, st>>>(kf, gf.n, kc, nc, mc);
+}
+
+__global__ void k_to_float(const double* __restrict__ in, float* __restrict__ out, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) out[i] = (float)in[i];
+}
+void to_float(const double* in, float* out, int64_t count, hipStream_t st) {
+  k_to_float<<<(unsigned)((count + 255) / 256), 256, 0, st>>>(in, out, count);
+}
+
+// ------------------------------------------------------------------------------------------
+// Edge grid transfers.  The prolongation is the embedding of the coarse Nedelec space:
+// a coarse x-edge contributes 1/2 to its two collinear fine x-edges and 1/4 to the four
+// parallel fine x-edges half a coarse cell above and below (y-edges alike); the
+// restriction is its adjoint.
+template <typename T>
+__global__ __launch_bounds__(256) void k_edge_restrict(const T* __restrict__ rf, Geo gf,
+                                                       T* __restrict__ bc, Geo gc, Phase php) {
+  const int col = blockIdx.y;
+  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= gc.ne) return;
+  const Ph<T> p = cast_phase<T>(php);
+  const T* r = rf + (int64_t)col * 2 * gf.ne;
+  const int nf = gf.n, mf = gf.m;
+  const int64_t Nf = gf.ne, nmf = gf.nm;
+  const T h = (T)0.5, q = (T)0.25;
+  Cx<T> v;
+  if (d < gc.nm) {
+    const int J1 = (int)(d % gc.n), J2 = (int)(d / gc.n);
+    const int f1 = 2 * J1, f2 = 2 * J2;
+    v = h * (fetch<T, T>(r, Nf, nf, mf, 0, f1, f2, p) + fetch<T, T>(r, Nf, nf, mf, 0, f1 + 1, f2, p)) +
+        q * (fetch<T, T>(r, Nf, nf, mf, 0, f1, f2 + 1, p) + fetch<T, T>(r, Nf, nf, mf, 0, f1 + 1, f2 + 1, p) +
+             fetch<T, T>(r, Nf, nf, mf, 0, f1, f2 - 1, p) + fetch<T, T>(r, Nf, nf, mf, 0, f1 + 1, f2 - 1, p));
+  } else {
+    const int64_t e = d - gc.nm;
+    const int J1 = (int)(e % gc.n), J2 = (int)(e / gc.n);
+    const int f1 = 2 * J1, f2 = 2 * J2;
+    v = h * (fetch<T, T>(r, Nf, nf, mf, nmf, f1, f2, p) + fetch<T, T>(r, Nf, nf, mf, nmf, f1, f2 + 1, p)) +
+        q * (fetch<T, T>(r, Nf, nf, mf, nmf, f1 + 1, f2, p) + fetch<T, T>(r, Nf, nf, mf, nmf, f1 + 1, f2 + 1, p) +
+             fetch<T, T>(r, Nf, nf, mf, nmf, f1 - 1, f2, p) + fetch<T, T>(r, Nf, nf, mf, nmf, f1 - 1, f2 + 1, p));
+  }
+  T* o = bc + (int64_t)col * 2 * gc.ne;
+  o[d] = v.re;
+  o[gc.ne + d] = v.im;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_edge_prolong_add(const T* __restrict__ xc, Geo gc,
+                                                          T* __restrict__ xf, Geo gf, Phase php) {
+  const int col = blockIdx.y;
+  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= gf.ne) return;
+  const Ph<T> p = cast_phase<T>(php);
+  const T* c = xc + (int64_t)col * 2 * gc.ne;
+  const int nc = gc.n, mc = gc.m;
+  const int64_t Nc = gc.ne, nmc = gc.nm;
+  Cx<T> v;
+  if (d < gf.nm) {
+    const int f1 = (int)(d % gf.n), f2 = (int)(d / gf.n);
+    const int J1 = f1 >> 1;
+    if ((f2 & 1) == 0) {
+      v = (T)0.5 * fetch<T, T>(c, Nc, nc, mc, 0, J1, f2 >> 1, p);
+    } else {
+      v = (T)0.25 * (fetch<T, T>(c, Nc, nc, mc, 0, J1, f2 >> 1, p) + fetch<T, T>(c, Nc, nc, mc, 0, J1, (f2 >> 1) + 1, p));
+    }
+  } else {
+    const int64_t e = d - gf.nm;
+    const int f1 = (int)(e % gf.n), f2 = (int)(e / gf.n);
+    const int J2 = f2 >> 1;
+    if ((f1 & 1) == 0) {
+      v = (T)0.5 * fetch<T, T>(c, Nc, nc, mc, nmc, f1 >> 1, J2, p);
+    } else {
+      v = (T)0.25 * (fetch<T, T>(c, Nc, nc, mc, nmc, f1 >> 1, J2, p) + fetch<T, T>(c, Nc, nc, mc, nmc, (f1 >> 1) + 1, J2, p));
+    }
+  }
+  T* o = xf + (int64_t)col * 2 * gf.ne;
+  o[d] += v.re;
+  o[gf.ne + d] += v.im;
+}
+
+template <typename T>
+void edge_restrict(const T* rf, const Geo& gf, T* bc, const Geo& gc, const Phase& ph, int ncols,
+                   hipStream_t st) {
+  dim3 grid((unsigned)((gc.ne + 255) / 256), (unsigned)ncols);
+  k_edge_restrict<T><<<grid, 256, 0, st>>>(rf, gf, bc, gc, ph);
+}
+template <typename T>
+void edge_prolong_add(const T* xc, const Geo& gc, T* xf, const Geo& gf, const Phase& ph,
+                      int ncols, hipStream_t st) {
+  dim3 grid((unsigned)((gf.ne + 255) / 256), (unsigned)ncols);
+  k_edge_prolong_add<T><<<grid, 256, 0, st>>>(xc, gc, xf, gf, ph);
+}
+template void edge_restrict<double>(const double*, const Geo&, double*, const Geo&, const Phase&, int, hipStream_t);
+template void edge_restrict<float>(const float*, const Geo&, float*, const Geo&, const Phase&, int, hipStream_t);
+template void edge_prolong_add<double>(const double*, const Geo&, double*, const Geo&, const Phase&, int, hipStream_t);
+template void edge_prolong_add<float>(const float*, const Geo&, float*, const Geo&, const Phase&, int, hipStream_t);
+
+// ------------------------------------------------------------------------------------------
+// Nodal operators.  P = L^* M L is the 9-point Bloch Q1 Laplacian; its coefficients depend
+// only on h2/h1, which bisection keeps, so every level uses the same stencil.
+template <typename T>
+__device__ __forceinline__ Cx<T> nodal_stencil(const T* c, int64_t N, int n, int m, int p1, int p2,
+                                               const NodalStencil& s, const Ph<T>& p) {
+  const Cx<T> u = {c[(int64_t)p2 * n + p1], c[N + (int64_t)p2 * n + p1]};
+  const Cx<T> ex = fetch<T, T>(c, N, n, m, 0, p1 + 1, p2, p) + fetch<T, T>(c, N, n, m, 0, p1 - 1, p2, p);
+  const Cx<T> ey = fetch<T, T>(c, N, n, m, 0, p1, p2 + 1, p) + fetch<T, T>(c, N, n, m, 0, p1, p2 - 1, p);
+  const Cx<T> ed = fetch<T, T>(c, N, n, m, 0, p1 + 1, p2 + 1, p) + fetch<T, T>(c, N, n, m, 0, p1 - 1, p2 + 1, p) +
+                   fetch<T, T>(c, N, n, m, 0, p1 + 1, p2 - 1, p) + fetch<T, T>(c, N, n, m, 0, p1 - 1, p2 - 1, p);
+  return ((T)s.c0 * u) + ((T)s.cx * ex) + ((T)s.cy * ey) + ((T)s.cd * ed);
+}
+
+template <typename T, bool RESID>
+__global__ __launch_bounds__(256) void k_nodal_apply(const T* __restrict__ x, const T* __restrict__ b,
+                                                     T* __restrict__ out, Geo g, Phase php,
+                                                     NodalStencil s) {
+  const int col = blockIdx.y;
+  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= g.nm) return;
+  const Ph<T> p = cast_phase<T>(php);
+  const int64_t N = g.nm;
+  const T* xc = x + (int64_t)col * 2 * N;
+  Cx<T> v = nodal_stencil<T>(xc, N, g.n, g.m, (int)(d % g.n), (int)(d / g.n), s, p);
+  if (RESID) {
+    const T* bc = b + (int64_t)col * 2 * N;
+    v = Cx<T>{bc[d], bc[N + d]} - v;
+  }
+  T* o = out + (int64_t)col * 2 * N;
+  o[d] = v.re;
+  o[N + d] = v.im;
+}
+
+template <typename T>
+void nodal_apply(const T* x, const T* b, T* out, const Geo& g, const Phase& ph,
+                 const NodalStencil& c, bool resid, int ncols, hipStream_t st) {
+  dim3 grid((unsigned)((g.nm + 255) / 256), (unsigned)ncols);
+  if (resid) k_nodal_apply<T, true><<<grid, 256, 0, st>>>(x, b, out, g, ph, c);
+  else k_nodal_apply<T, false><<<grid, 256, 0, st>>>(x, b, out, g, ph, c);
+}
+template void nodal_apply<double>(const double*, const double*, double*, const Geo&, const Phase&, const NodalStencil&, bool, int, hipStream_t);
+template void nodal_apply<float>(const float*, const float*, float*, const Geo&, const Phase&, const NodalStencil&, bool, int, hipStream_t);
+
+// Point Gauss-Seidel for P on the nodes of one colour (same-colour nodes are not
+// neighbours of the 9-point stencil).
+template <typename T>
+__global__ __launch_bounds__(256) void k_nodal_gs(T* __restrict__ x, const T* __restrict__ b, Geo g,
+                                                  Phase php, NodalStencil s, int colour) {
+  const int col = blockIdx.y;
+  const int nh = g.n >> 1, mh = g.m >> 1;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)nh * mh) return;
+  const int p1 = 2 * (int)(t % nh) + (colour & 1);
+  const int p2 = 2 * (int)(t / nh) + (colour >> 1);
+  const Ph<T> p = cast_phase<T>(php);
+  const int64_t N = g.nm;
+  T* xc = x + (int64_t)col * 2 * N;
+  const T* bc = b + (int64_t)col * 2 * N;
+  const int64_t i = (int64_t)p2 * g.n + p1;
+  const Cx<T> r = Cx<T>{bc[i], bc[N + i]} - nodal_stencil<T>(xc, N, g.n, g.m, p1, p2, s, p);
+  const T inv = (T)1 / (T)s.c0;
+  xc[i] += inv * r.re;
+  xc[N + i] += inv * r.im;
+}
+
+template <typename T>
+void nodal_gs(T* x, const T* b, const Geo& g, const Phase& ph, const NodalStencil& c, int colour,
+              int ncols, hipStream_t st) {
+  const int64_t cnt = (int64_t)(g.n / 2) * (g.m / 2);
+  dim3 grid((unsigned)((cnt + 255) / 256), (unsigned)ncols);
+  k_nodal_gs<T><<<grid, 256, 0, st>>>(x, b, g, ph, c, colour);
+}
+template void nodal_gs<double>(double*, const double*, const Geo&, const Phase&, const NodalStencil&, int, int, hipStream_t);
+template void nodal_gs<float>(float*, const float*, const Geo&, const Phase&, const NodalStencil&, int, int, hipStream_t);
+
+// Nodal transfers: bilinear interpolation of the coarse Q1 function (embedding) and its
+// adjoint (full weighting with Bloch phases).
+template <typename T>
+__global__ __launch_bounds__(256) void k_nodal_restrict(const T* __restrict__ rf, Geo gf,
+                                                        T* __restrict__ bc, Geo gc, Phase php) {
+  const int col = blockIdx.y;
+  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= gc.nm) return;
+  const Ph<T> p = cast_phase<T>(php);
+  const T* r = rf + (int64_t)col * 2 * gf.nm;
+  const int J1 = (int)(d % gc.n), J2 = (int)(d / gc.n);
+  Cx<T> v = {0, 0};
+#pragma unroll
+  for (int d2 = -1; d2 <= 1; ++d2)
+#pragma unroll
+    for (int d1 = -1; d1 <= 1; ++d1) {
+      const T w = (T)((d1 == 0 ? 1.0 : 0.5) * (d2 == 0 ? 1.0 : 0.5));
+      v = v + (w * fetch<T, T>(r, gf.nm, gf.n, gf.m, 0, 2 * J1 + d1, 2 * J2 + d2, p));
+    }
+  T* o = bc + (int64_t)col * 2 * gc.nm;
+  o[d] = v.re;
+  o[gc.nm + d] = v.im;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_nodal_prolong_add(const T* __restrict__ xc, Geo gc,
+                                                           T* __restrict__ xf, Geo gf, Phase php) {
+  const int col = blockIdx.y;
+  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= gf.nm) return;
+  const Ph<T> p = cast_phase<T>(php);
+  const T* c = xc + (int64_t)col * 2 * gc.nm;
+  const int f1 = (int)(d % gf.n), f2 = (int)(d / gf.n);
+  const int J1 = f1 >> 1, J2 = f2 >> 1;
+  const bool o1 = f1 & 1, o2 = f2 & 1;
+  Cx<T> v;
+  const Cx<T> c00 = fetch<T, T>(c, gc.nm, gc.n, gc.m, 0, J1, J2, p);
+  if (!o1 && !o2) {
+    v = c00;
+  } else if (o1 && !o2) {
+    v = (T)0.5 * (c00 + fetch<T, T>(c, gc.nm, gc.n, gc.m, 0, J1 + 1, J2, p));
+  } else if (!o1 && o2) {
+    v = (T)0.5 * (c00 + fetch<T, T>(c, gc.nm, gc.n, gc.m, 0, J1, J2 + 1, p));
+  } else {
+    v = (T)0.25 * (c00 + fetch<T, T>(c, gc.nm, gc.n, gc.m, 0, J1 + 1, J2, p) +
+                   fetch<T, T>(c, gc.nm, gc.n, gc.m, 0, J1, J2 + 1, p) +
+                   fetch<T, T>(c, gc.nm, gc.n, gc.m, 0, J1 + 1, J2 + 1, p));
+  }
+  T* o = xf + (int64_t)col * 2 * gf.nm;
+  o[d] += v.re;
+  o[gf.nm + d] += v.im;
+}
+
+template <typename T>
+void nodal_restrict(const T* rf, const Geo& gf, T* bc, const Geo& gc, const Phase& ph, int ncols,
+                    hipStream_t st) {
+  dim3 grid((unsigned)((gc.nm + 255) / 256), (unsigned)ncols);
+  k_nodal_restrict<T><<<grid, 256, 0, st>>>(rf, gf, bc, gc, ph);
+}
+template <typename T>
+void nodal_prolong_add(const T* xc, const Geo& gc, T* xf, const Geo& gf, const Phase& ph,
+                       int ncols, hipStream_t st) {
+  dim3 grid((unsigned)((gf.nm + 255) / 256), (unsigned)ncols);
+  k_nodal_prolong_add<T><<<grid, 256, 0, st>>>(xc, gc, xf, gf, ph);
+}
+template void nodal_restrict<double>(const double*, const Geo&, double*, const Geo&, const Phase&, int, hipStream_t);
+template void nodal_restrict<float>(const float*, const Geo&, float*, const Geo&, const Phase&, int, hipStream_t);
+template void nodal_prolong_add<double>(const double*, const Geo&, double*, const Geo&, const Phase&, int, hipStream_t);
+template void nodal_prolong_add<float>(const float*, const Geo&, float*, const Geo&, const Phase&, int, hipStream_t);
+
+// out (nodal) = L^* M u (edge).  (L^* v)(p) = v_x(p1-1,p2) - v_x(p1,p2) + v_y(p1,p2-1) - v_y(p1,p2)
+// in extended coordinates, with v = M u evaluated on the fly.  Arithmetic in FP64 when the
+// input is FP64 (the right-hand side of the projection keeps the outer precision).
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void k_lhm(const TI* __restrict__ u, TO* __restrict__ out, Geo g,
+                                             Phase php) {
+  using T = double;
+  const int col = blockIdx.y;
+  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= g.nm) return;
+  const Ph<T> p = cast_phase<T>(php);
+  const int n = g.n, m = g.m;
+  const int64_t N = g.ne, nm = g.nm;
+  const TI* c = u + (int64_t)col * 2 * N;
+  const int p1 = (int)(d % n), p2 = (int)(d / n);
+  const T two3 = 2.0 / 3.0, one6 = 1.0 / 6.0;
+  auto mx_at = [&](int j1, int j2) {
+    return (T)g.mx * ((two3 * fetch<TI, T>(c, N, n, m, 0, j1, j2, p)) +
+                      one6 * (fetch<TI, T>(c, N, n, m, 0, j1, j2 + 1, p) + fetch<TI, T>(c, N, n, m, 0, j1, j2 - 1, p)));
+  };
+  auto my_at = [&](int j1, int j2) {
+    return (T)g.my * ((two3 * fetch<TI, T>(c, N, n, m, nm, j1, j2, p)) +
+                      one6 * (fetch<TI, T>(c, N, n, m, nm, j1 + 1, j2, p) + fetch<TI, T>(c, N, n, m, nm, j1 - 1, j2, p)));
+  };
+  const Cx<T> v = mx_at(p1 - 1, p2) - mx_at(p1, p2) + my_at(p1, p2 - 1) - my_at(p1, p2);
+  TO* o = out + (int64_t)col * 2 * nm;
+  o[d] = (TO)v.re;
+  o[nm + d] = (TO)v.im;
+}
+
+template <typename TI, typename TO>
+void lhm(const TI* u, TO* out, const Geo& g, const Phase& ph, int ncols, hipStream_t st) {
+  dim3 grid((unsigned)((g.nm + 255) / 256), (unsigned)ncols);
+  k_lhm<TI, TO><<<grid, 256, 0, st>>>(u, out, g, ph);
+}
+template void lhm<double, double>(const double*, double*, const Geo&, const Phase&, int, hipStream_t);
+template void lhm<double, float>(const double*, float*, const Geo&, const Phase&, int, hipStream_t);
+template void lhm<float, float>(const float*, float*, const Geo&, const Phase&, int, hipStream_t);
+template void lhm<float, double>(const float*, double*, const Geo&, const Phase&, int, hipStream_t);
+
+// out (edge) = u - L phi, (L phi)_x(j1,j2) = phi(j1+1,j2) - phi(j1,j2),
+// (L phi)_y(j1,j2) = phi(j1,j2+1) - phi(j1,j2) (extended reads).  FP64 arithmetic.
+template <typename TI, typename TP, typename TO, bool SUB>
+__global__ __launch_bounds__(256) void k_lift(const TI* __restrict__ u, const TP* __restrict__ phi,
+                                              TO* __restrict__ out, Geo g, Phase php) {
+  using T = double;
+  const int col = blockIdx.y;
+  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= g.ne) return;
+  const Ph<T> p = cast_phase<T>(php);
+  const int n = g.n, m = g.m;
+  const int64_t N = g.ne, nm = g.nm;
+  const TP* f = phi + (int64_t)col * 2 * nm;
+  Cx<T> lp;
+  if (d < nm) {
+    const int j1 = (int)(d % n), j2 = (int)(d / n);
+    lp = fetch<TP, T>(f, nm, n, m, 0, j1 + 1, j2, p) - fetch<TP, T>(f, nm, n, m, 0, j1, j2, p);
+  } else {
+    const int64_t e = d - nm;
+    const int j1 = (int)(e % n), j2 = (int)(e / n);
+    lp = fetch<TP, T>(f, nm, n, m, 0, j1, j2 + 1, p) - fetch<TP, T>(f, nm, n, m, 0, j1, j2, p);
+  }
+  Cx<T> v = lp;
+  if (SUB) {
+    const TI* uc = u + (int64_t)col * 2 * N;
+    v = Cx<T>{(T)uc[d], (T)uc[N + d]} - lp;
+  }
+  TO* o = out + (int64_t)col * 2 * N;
+  o[d] = (TO)v.re;
+  o[N + d] = (TO)v.im;
+}
+
+template <typename TI, typename TP, typename TO>
+void lift_sub(const TI* u, const TP* phi, TO* out, const Geo& g, const Phase& ph, int ncols,
+              hipStream_t st) {
+  dim3 grid((unsigned)((g.ne + 255) / 256), (unsigned)ncols);
+  k_lift<TI, TP, TO, true><<<grid, 256, 0, st>>>(u, phi, out, g, ph);
+}
+template <typename TI, typename TO>
+void lift(const TI* phi, TO* out, const Geo& g, const Phase& ph, int ncols, hipStream_t st) {
+  dim3 grid((unsigned)((g.ne + 255) / 256), (unsigned)ncols);
+  k_lift<TO, TI, TO, false><<<grid, 256, 0, st>>>(nullptr, phi, out, g, ph);
+}
+template void lift_sub<double, double, double>(const double*, const double*, double*, const Geo&, const Phase&, int, hipStream_t);
+template void lift_sub<double, float, double>(const double*, const float*, double*, const Geo&, const Phase&, int, hipStream_t);
+template void lift_sub<float, float, double>(const float*, const float*, double*, const Geo&, const Phase&, int, hipStream_t);
+template void lift_sub<float, double, double>(const float*, const double*, double*, const Geo&, const Phase&, int, hipStream_t);
+template void lift_sub<float, float, float>(const float*, const float*, float*, const Geo&, const Phase&, int, hipStream_t);
+template void lift<double, double>(const double*, double*, const Geo&, const Phase&, int, hipStream_t);
+template void lift<float, float>(const float*, float*, const Geo&, const Phase&, int, hipStream_t);
+
+// k = 0: remove the constant x- and y-edge fields M-orthogonally.  With alpha = beta = 1,
+// M applied to a constant x-field is h2/h1 times it, so the M-projection onto the constant
+// fields subtracts the mean of the x-part and of the y-part of every column.
+__global__ void k_col_means(const double* __restrict__ u, Geo g, double* __restrict__ out) {
+  const int col = blockIdx.x;
+  const int64_t N = g.ne, nm = g.nm;
+  const double* c = u + (int64_t)col * 2 * N;
+  double a[4] = {0, 0, 0, 0};
+  for (int64_t i = threadIdx.x; i < nm; i += blockDim.x) {
+    a[0] += c[i];
+    a[1] += c[N + i];
+    a[2] += c[nm + i];
+    a[3] += c[N + nm + i];
+  }
+  __shared__ double sh[4][256];
+  for (int v = 0; v < 4; ++v) sh[v][threadIdx.x] = a[v];
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int v = 0; v < 4; ++v) sh[v][threadIdx.x] += sh[v][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int v = 0; v < 4; ++v) out[col * 4 + v] = sh[v][0] / (double)nm;
+}
+__global__ void k_sub_means(double* __restrict__ u, Geo g, const double* __restrict__ mean) {
+  const int col = blockIdx.y;
+  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= g.ne) return;
+  const int64_t N = g.ne;
+  double* c = u + (int64_t)col * 2 * N;
+  const int part = d < g.nm ? 0 : 2;
+  c[d] -= mean[col * 4 + part];
+  c[N + d] -= mean[col * 4 + part + 1];
+}
+void gamma_deflate(double* u, const Geo& g, int ncols, double* scratch, hipStream_t st) {
+  k_col_means<<<ncols, 256, 0, st>>>(u, g, scratch);
+  dim3 grid((unsigned)((g.ne + 255) / 256), (unsigned)ncols);
+  k_sub_means<<<grid, 256, 0, st>>>(u, g, scratch);
+}
+
+template <typename T>
+__global__ void k_fill_zero(T* __restrict__ p, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = (T)0;
+}
+template <typename T>
+void fill_zero(T* p, int64_t count, hipStream_t st) {
+  if (count <= 0) return;
+  k_fill_zero<T><<<(unsigned)((count + 255) / 256), 256, 0, st>>>(p, count);
+}
+template void fill_zero<double>(double*, int64_t, hipStream_t);
+template void fill_zero<float>(float*, int64_t, hipStream_t);
+
+}  // namespace bl

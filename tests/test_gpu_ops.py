@@ -1,0 +1,190 @@
+"""Operator-level parity of the gfx950 kernels (through bl_apply) against the oracle's
+sparse matrices and multigrid, element by element on seeded inputs: FP64 to 1e-12
+relative (norm-wise), FP32 to 2e-5.  Grids with ragged tails (edge counts not multiples of
+the 256-thread blocks), rectangular cells, and k generic / Gamma / zone corner."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import fem
+from oracle.multigrid import Hierarchy
+from oracle.pinvit import Projector
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # n, m, a, b, coarsest_min, k
+    (20, 12, 1.0, 0.8, 3, (0.7, -1.3)),
+    (20, 12, 1.0, 0.8, 3, (0.0, 0.0)),
+    (32, 32, 1.0, 1.0, 8, (math.pi, math.pi)),
+    (24, 16, 1.3, 1.0, 4, (math.pi / 2, 0.4)),
+]
+MU = 5.0
+
+
+def _setup(case, nodal_cycles=2):
+    import torch  # noqa: F401
+    from paper_2304_00337_amd import Solver
+    n, m, a, b, cmin, k = case
+    rng = np.random.default_rng(n * 100 + m)
+    eps = rng.uniform(1.0, 12.0, n * m)
+    d = fem.Discretization(n, m, a, b, eps, *k)
+    H = Hierarchy(d, mu=MU, coarsest_min=cmin)
+    s = Solver(n, m, a, b, eps, nev=4, nthrow=2, mu=MU, coarsest_min=cmin, nodal_cycles=nodal_cycles)
+    assert s.info()["levels"] == H.nlevels
+    assert s.info()["sizes"] == [tuple(x) for x in H.sizes]
+    s.set_k(*k)
+    return d, H, s, rng
+
+
+def _rand(rng, N, c):
+    return rng.standard_normal((N, c)) + 1j * rng.standard_normal((N, c))
+
+
+def _gpu(s, op, X, level=0, Y=None, out_rows=None, fp32=False, init=None):
+    import torch
+    from paper_2304_00337_amd import from_device_block, to_device_block
+    dt = torch.float32 if fp32 else torch.float64
+    x = to_device_block(X, dtype=dt)
+    y = to_device_block(Y, dtype=dt) if Y is not None else None
+    c = X.shape[1]
+    if init is not None:
+        out = to_device_block(init, dtype=dt)
+    else:
+        out = torch.zeros((c, 2, out_rows), dtype=dt, device="cuda")
+    s.apply(op, x, y=y, out=out, level=level)
+    return from_device_block(out)
+
+
+def _close(got, ref, tol):
+    err = np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300)
+    assert err <= tol, f"relative error {err:.3e} > {tol:.1e}"
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("fp32", [False, True])
+def test_edge_and_nodal_operators(case, fp32):
+    d, H, s, rng = _setup(case)
+    tol = 2e-5 if fp32 else 1e-12
+    Ne, Nv = d.n_edges, d.n_nodes
+    X = _rand(rng, Ne, 3)
+    F = _rand(rng, Nv, 3)
+    _close(_gpu(s, "A", X, out_rows=Ne, fp32=fp32), d.A @ X, tol)
+    _close(_gpu(s, "M", X, out_rows=Ne, fp32=fp32), d.M @ X, tol)
+    _close(_gpu(s, "K", X, out_rows=Ne, fp32=fp32), (d.A + MU * d.M) @ X, tol)
+    _close(_gpu(s, "LIFT", F, out_rows=Ne, fp32=fp32), d.L @ F, tol)
+    _close(_gpu(s, "LHM", X, out_rows=Nv, fp32=fp32), d.L.conj().T @ (d.M @ X), tol)
+    _close(_gpu(s, "P", F, out_rows=Nv, fp32=fp32), d.P @ F, tol)
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_every_level_operators_and_transfers(case):
+    d, H, s, rng = _setup(case)
+    for lvl in range(H.nlevels - 1):
+        lv, nl = H.edge[lvl], H.nodal[lvl]
+        Ne = 2 * lv.n * lv.m
+        Nv = lv.n * lv.m
+        X = _rand(rng, Ne, 2)
+        _close(_gpu(s, "K", X, level=lvl, out_rows=Ne), lv.K @ X, 1e-12)
+        F = _rand(rng, Nv, 2)
+        _close(_gpu(s, "P", F, level=lvl, out_rows=Nv), nl.P @ F, 1e-12)
+        Pe, Pn = H.Pe[lvl], H.Pn[lvl]
+        Xc = _rand(rng, Pe.shape[1], 2)
+        _close(_gpu(s, "EDGE_PROLONG", Xc, level=lvl, out_rows=Ne), Pe @ Xc, 1e-13)
+        _close(_gpu(s, "EDGE_RESTRICT", X, level=lvl, out_rows=Pe.shape[1]), Pe.conj().T @ X, 1e-13)
+        Fc = _rand(rng, Pn.shape[1], 2)
+        _close(_gpu(s, "NODAL_PROLONG", Fc, level=lvl, out_rows=Nv), Pn @ Fc, 1e-13)
+        _close(_gpu(s, "NODAL_RESTRICT", F, level=lvl, out_rows=Pn.shape[1]), Pn.conj().T @ F, 1e-13)
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("fp32", [False, True])
+def test_smoothers_match_oracle_gauss_seidel(case, fp32):
+    d, H, s, rng = _setup(case)
+    tol = 5e-5 if fp32 else 1e-11
+    lv = H.edge[0]
+    Ne = d.n_edges
+    B = _rand(rng, Ne, 2)
+    X0 = _rand(rng, Ne, 2)
+    ref = X0.copy()
+    for c in (0, 1, 2, 3):
+        ref = lv.gs_colour(ref, B, c)
+    got = _gpu(s, "EDGE_SMOOTH", B, Y=B, init=X0, fp32=fp32)
+    _close(got, ref, tol)
+    ref = X0.copy()
+    for c in (3, 2, 1, 0):
+        ref = lv.gs_colour(ref, B, c)
+    _close(_gpu(s, "EDGE_SMOOTH_BACK", B, Y=B, init=X0, fp32=fp32), ref, tol)
+    nl = H.nodal[0]
+    Bn = _rand(rng, d.n_nodes, 2)
+    F0 = _rand(rng, d.n_nodes, 2)
+    ref = F0.copy()
+    for c in (0, 1, 2, 3):
+        ref = nl.gs_colour(ref, Bn, c)
+    _close(_gpu(s, "NODAL_SMOOTH", Bn, Y=Bn, init=F0, fp32=fp32), ref, tol)
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("fp32", [False, True])
+def test_vcycles_coarse_solves_and_projection(case, fp32):
+    d, H, s, rng = _setup(case)
+    tol = 5e-5 if fp32 else 1e-11
+    B = _rand(rng, d.n_edges, 3)
+    _close(_gpu(s, "EDGE_VCYCLE", B, out_rows=d.n_edges, fp32=fp32), H.edge_vcycle(B), tol)
+    Bn = _rand(rng, d.n_nodes, 3)
+    if d.gamma:
+        Bn = Bn - Bn.mean(axis=0, keepdims=True)     # consistent right-hand side
+    ref = H.nodal_vcycle(Bn)
+    got = _gpu(s, "NODAL_VCYCLE", Bn, out_rows=d.n_nodes, fp32=fp32)
+    if d.gamma:   # the solution is defined up to a constant potential
+        ref = ref - ref.mean(axis=0, keepdims=True)
+        got = got - got.mean(axis=0, keepdims=True)
+    _close(got, ref, tol)
+    lc = H.nlevels - 1
+    nc, mc = H.sizes[lc]
+    Bc = _rand(rng, 2 * nc * mc, 2)
+    _close(_gpu(s, "COARSE_EDGE", Bc, level=lc, out_rows=2 * nc * mc, fp32=fp32),
+           np.linalg.solve(H._coarse_edge, Bc), tol)
+    if not fp32:
+        U = _rand(rng, d.n_edges, 4)
+        ref = Projector(d, H, 2)(U)
+        _close(_gpu(s, "PROJECT", U, out_rows=d.n_edges), ref, 1e-11)
+
+
+def test_gram_and_ritz_small():
+    import torch  # noqa: F401
+    from paper_2304_00337_amd import to_device_block
+    d, H, s, rng = _setup(CASES[0])
+    X = _rand(rng, 3001, 37)
+    W = _rand(rng, 3001, 70)
+    G = s.gram(to_device_block(X), to_device_block(W))
+    _close(G, X.conj().T @ W, 1e-13)
+    # generalized Hermitian eigenproblem with a nearly dependent, badly scaled G
+    q = 30
+    Z = _rand(rng, 200, q)
+    Z[:, 7] = Z[:, 3] * 1e3 + 1e-9 * Z[:, 8]
+    Gm = Z.conj().T @ Z
+    A0 = _rand(rng, 200, 200)
+    A0 = A0 @ A0.conj().T
+    Hm = Z.conj().T @ A0 @ Z
+    th, Y = s.ritz_small(Gm, Hm, 10)
+    assert len(th) == 10
+    # reference: the same pencil restricted to the well-determined directions
+    w, V = np.linalg.eigh(Gm / np.sqrt(np.outer(np.diag(Gm).real, np.diag(Gm).real)))
+    assert np.all(np.diff(th) >= -1e-12)
+    # Y is G-orthonormal and H-diagonal
+    assert np.abs(Y.conj().T @ Gm @ Y - np.eye(10)).max() < 1e-8
+    HY = Y.conj().T @ Hm @ Y
+    assert np.abs(HY - np.diag(th)).max() < 1e-8 * np.abs(th).max()
+    # with a well-conditioned G the values are the generalized eigenvalues
+    Z2 = _rand(rng, 200, 12)
+    G2 = Z2.conj().T @ Z2
+    H2 = Z2.conj().T @ A0 @ Z2
+    import scipy.linalg as sla
+    ref = sla.eigh(H2, G2, eigvals_only=True)
+    th2, _ = s.ritz_small(G2, H2, 12)
+    _close(th2, ref, 1e-12)
+    th3, _ = s.ritz_small(G2, H2, 5, zero_thr=ref[2] * 1.0000001)
+    _close(th3, ref[3:8], 1e-12)

@@ -1,0 +1,146 @@
+"""Solver-level parity of the GPU path (bl_solve_k / bl_solve_path through the C ABI)
+against the oracle: eigenvalues to 1e-9 relative in FP64 and 1e-6 in mixed precision,
+eigenvector subspaces (cluster-wise M-principal angles) to 1e-5, iteration counts close to
+the oracle's iteration with the same options."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import fem
+from oracle.closed_form import discrete_nonzero
+from oracle.dense import dense_eigs
+from oracle.extrapolation import solve_path
+from oracle.multigrid import Hierarchy
+from oracle.pinvit import Projector, initial_block, pinvit
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _solver(prob, precision="fp64", **kw):
+    from paper_2304_00337_amd import Solver
+    opts = dict(nthrow=prob.nthrow, precision=precision, tol=prob.tol)
+    opts.update(kw)
+    return Solver(prob.n, prob.m, prob.a, prob.b, prob.eps, nev=prob.nev, **opts)
+
+
+def _clusters(lam, gap=1e-3):
+    """Split ascending values into clusters at relative gaps > gap."""
+    cl, cur = [], [0]
+    for j in range(1, len(lam)):
+        if (lam[j] - lam[j - 1]) / lam[j - 1] > gap:
+            cl.append(cur)
+            cur = [j]
+        else:
+            cur.append(j)
+    cl.append(cur)
+    return cl
+
+
+def _subspace_check(E_gpu, V_ref, M, lam_ref, nev, tol=1e-5):
+    """Cluster-wise M-principal angles; clusters straddling nev are skipped."""
+    for cl in _clusters(lam_ref):
+        if cl[-1] >= nev:
+            break
+        s = np.linalg.svd(E_gpu[:, cl].conj().T @ (M @ V_ref[:, cl]), compute_uv=False)
+        ang = np.arccos(np.clip(s.min(), -1, 1))
+        assert ang < tol, f"cluster {cl}: angle {ang:.2e}"
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_c1_disc_against_dense(precision):
+    from paper_2304_00337_amd import from_device_block
+    prob = synth.config_c1()
+    with open(os.path.join(GOLDEN, "c1_dense.json")) as f:
+        gold = np.array(json.load(f)["disc"])
+    s = _solver(prob, precision, levels=3, max_iter=400)
+    assert s.info()["levels"] == 3
+    r = s.solve_k(*prob.ks[0], start=prob.start(), want_vectors=True)
+    assert r["converged"]
+    tol = 1e-9 if precision == "fp64" else 1e-6
+    rel = np.abs(r["evals"] - gold[:8]) / gold[:8]
+    assert rel.max() < tol, rel
+    d = fem.Discretization(prob.n, prob.m, prob.a, prob.b, prob.eps, *prob.ks[0])
+    lam, V, _ = dense_eigs(d, 9)
+    _subspace_check(from_device_block(r["evecs"]), V, d.M, lam, 8)
+
+
+def test_c1_eps_one_closed_form():
+    prob = synth.config_c1(eps_one=True)
+    s = _solver(prob, "fp64", levels=3, max_iter=400)
+    r = s.solve_k(*prob.ks[0], start=prob.start())
+    assert r["converged"]
+    cf = discrete_nonzero(32, 32, 1.0, 1.0, 1.0, math.pi / 2, 0.0, 8)
+    assert np.max(np.abs(r["evals"] - cf) / cf) < 1e-9
+
+
+@pytest.mark.parametrize("k", [(0.9, -0.6), (0.0, 0.0), (math.pi, math.pi)])
+def test_iteration_matches_oracle_iteration(k):
+    """Same start block, same options: eigenvalues, residual decrease and iteration count."""
+    n = 32
+    eps = synth.eps_disc(n, n, 1.0, 1.0, 8.9, 0.3)
+    nev, nthrow, mu = 6, 4, 10.0
+    d = fem.Discretization(n, n, 1.0, 1.0, eps, *k)
+    H = Hierarchy(d, mu=mu, coarsest_min=4)
+    pr = Projector(d, H, 2)
+    E0 = synth.start_block(d.n_edges, nev + nthrow, 5)
+    lam0, Eo = initial_block(d, pr, E0, nev + nthrow)
+    lam_o, E_o, rel_o, it_o, conv_o = pinvit(d, H, pr, Eo, lam0, nev, 1e-9, 200)
+    assert conv_o
+    from paper_2304_00337_amd import Solver
+    s = Solver(n, n, 1.0, 1.0, eps, nev=nev, nthrow=nthrow, mu=mu, coarsest_min=4, tol=1e-9,
+               max_iter=200)
+    r = s.solve_k(*k, start=E0)
+    assert r["converged"]
+    assert np.max(np.abs(r["evals"] - lam_o[:nev]) / lam_o[:nev]) < 1e-9
+    assert abs(r["iterations"] - it_o) <= 2, (r["iterations"], it_o)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_short_path_matches_oracle_path(precision):
+    n = 32
+    eps = synth.eps_disc_lattice(n, n, 1.0, 1.0, 12.0, 0.3)
+    ks = synth.path_gxmg(3)[:7]      # Gamma .. X .. toward M
+    nev, nthrow = 6, 3
+    start = synth.start_block(2 * n * n, nev + nthrow, 1)
+    from paper_2304_00337_amd import Solver
+    s = Solver(n, n, 1.0, 1.0, eps, nev=nev, nthrow=nthrow, mu=10.0, precision=precision,
+               tol=1e-9, max_iter=300)
+    r = s.solve_path(ks, start=start)
+    assert r["converged"]
+    for t, k in enumerate(ks):
+        d = fem.Discretization(n, n, 1.0, 1.0, eps, *k)
+        ref, _, _ = dense_eigs(d, nev)
+        tol = 1e-9 if precision == "fp64" else 1e-6
+        assert np.max(np.abs(r["evals"][t] - ref) / ref) < tol, (t, r["evals"][t], ref)
+    # warm starts by extrapolation need fewer iterations than the cold first point
+    assert np.median(r["iterations"][2:]) < r["iterations"][0]
+
+
+def test_mixed_equals_fp64_and_alone_equals_repeat():
+    prob = synth.config_c1()
+    s64 = _solver(prob, "fp64", levels=3, nthrow=4, max_iter=300)
+    s32 = _solver(prob, "mixed", levels=3, nthrow=4, max_iter=300)
+    E0 = synth.start_block(prob.n_edges, 12, 0)
+    a = s64.solve_k(*prob.ks[0], start=E0)
+    b = s32.solve_k(*prob.ks[0], start=E0)
+    assert np.max(np.abs(a["evals"] - b["evals"]) / a["evals"]) < 1e-6
+    c = s64.solve_k(*prob.ks[0], start=E0)
+    assert np.max(np.abs(a["evals"] - c["evals"]) / a["evals"]) < 1e-12
+
+
+def test_errors_are_reported():
+    from paper_2304_00337_amd import Solver
+    from paper_2304_00337_amd.native import BlochError
+    n = 16
+    s = Solver(n, n, 1.0, 1.0, np.ones(n * n), nev=4, nthrow=2, max_iter=1)
+    with pytest.raises(BlochError):
+        s.solve_k(0.3, 0.2)              # no start block and no history
+    r = s.solve_k(0.3, 0.2, start=synth.start_block(2 * n * n, 6, 0), allow_noconv=True)
+    assert not r["converged"] and r["iterations"] == 1
+    with pytest.raises(BlochError):
+        s.solve_k(float("nan"), 0.0, start=synth.start_block(2 * n * n, 6, 0))
