@@ -182,12 +182,22 @@ int bl_set_k(bl_solver* s, double k1, double k2);
 int bl_apply(bl_solver* s, int32_t op, int32_t level, int32_t prec, int32_t ncols,
              const void* x, const void* y, void* out);
 
+/* Measurement: with timing enabled, every launch of the finest-level edge smoother (one
+ * colour pass of the node-patch block Gauss-Seidel, the V-cycle's dominant kernel) is
+ * bracketed by HIP events on the handle's stream; bl_get_timing returns the summed
+ * duration in ms, the number of timed launches and the summed column count of those
+ * launches since timing was (re)enabled.  Enabling allocates 4096 events (BL_EHIP on
+ * failure); at most 2048 launches are timed between two residual evaluations. */
+int bl_set_timing(bl_solver* s, int32_t enable);
+int bl_get_timing(const bl_solver* s, double* total_ms, int64_t* launches, int64_t* columns);
+
 /* Dense FP64 helpers of the Ritz step (Section 4), exposed for tests.
  * bl_gram: out (host q x r, row-major complex interleaved re,im) = X^* W for device
  *   planar FP64 blocks X (q columns) and W (r columns) of length len.
  * bl_ritz_small: generalized Hermitian eigenproblem H y = theta G y for host q x q
  *   row-major interleaved complex G (Hermitian positive semi-definite) and H (Hermitian):
- *   directions with relative G-eigenvalue below 1e-12 are dropped, the `want` smallest
+ *   G is orthonormalised by pivoted Cholesky of its unit-diagonal scaling; directions whose
+ *   squared distance from the kept ones is below 1e-10 (relative) are dropped; the `want` smallest
  *   Ritz values above zero_thr are returned in theta (host) and their G-orthonormal
  *   coefficient vectors in Y (host q x want, row-major interleaved).  Runs on the GPU.
  *   Returns the number of values found (>= 0) or an error. */

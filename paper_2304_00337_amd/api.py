@@ -169,6 +169,17 @@ class Solver:
             self.h, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), cap), "bl_last_residual_history")
         return buf[:rows]
 
+    def set_timing(self, enable=True):
+        check(self.lib.bl_set_timing(self.h, 1 if enable else 0), "bl_set_timing")
+
+    def timing(self) -> dict:
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        cols = ctypes.c_int64()
+        check(self.lib.bl_get_timing(self.h, ctypes.byref(ms), ctypes.byref(cnt), ctypes.byref(cols)),
+              "bl_get_timing")
+        return {"total_ms": ms.value, "launches": cnt.value, "columns": cols.value}
+
     # -- operator level ----------------------------------------------------------------------
     def set_k(self, k1, k2):
         check(self.lib.bl_set_k(self.h, float(k1), float(k2)), "bl_set_k")

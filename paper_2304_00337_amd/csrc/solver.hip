@@ -24,7 +24,10 @@ void split_gram(const double* GH, int q, double* G, double* H, hipStream_t st);
 namespace {
 
 constexpr int kMaxLevels = 16;
-constexpr int64_t kMaxCoarse = 2048;   // largest coarsest-level edge count solved densely
+constexpr int64_t kMaxCoarse = 2048;
+// Ritz step: basis directions whose squared M-distance from the previously kept ones is
+// below this fraction of their squared M-norm are dropped as numerically dependent.
+constexpr double kDropRel = 1e-10;   // largest coarsest-level edge count solved densely
 
 struct Level {
   Geo g{};
@@ -136,6 +139,13 @@ struct bl_solver {
   int64_t launches = 0;
   std::vector<double> res_hist;
   int res_rows = 0;
+  // opt-in HIP-event timing of the finest-level smoother launches
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  int ev_used = 0;
+  double timed_ms = 0.0;
+  int64_t timed_count = 0;
+  int64_t timed_cols = 0;
 };
 
 namespace {
@@ -205,6 +215,32 @@ template <typename T>
 const void* pc_inv(const bl_solver* s) { return PrecOf<T>::v ? (const void*)s->pc_inv32 : (const void*)s->pc_inv64; }
 
 // ---- edge V-cycle for K = A + mu M with zero initial guess: x = V(b) ---------------------
+// Event pairs around the finest-level smoother launches (opt-in, see bl_set_timing).
+void timing_begin(bl_solver* s, int l) {
+  if (!s->timing || l != 0) return;
+  if (s->ev_used + 2 > (int)s->ev_pool.size()) return;
+  (void)hipEventRecord(s->ev_pool[s->ev_used], s->st);
+}
+void timing_end(bl_solver* s, int l, int ncols) {
+  if (!s->timing || l != 0) return;
+  if (s->ev_used + 2 > (int)s->ev_pool.size()) return;
+  (void)hipEventRecord(s->ev_pool[s->ev_used + 1], s->st);
+  s->ev_used += 2;
+  s->timed_cols += ncols;
+}
+void timing_collect(bl_solver* s) {
+  if (!s->timing) return;
+  for (int i = 0; i + 1 < s->ev_used; i += 2) {
+    float ms = 0.f;
+    if (hipEventSynchronize(s->ev_pool[i + 1]) == hipSuccess &&
+        hipEventElapsedTime(&ms, s->ev_pool[i], s->ev_pool[i + 1]) == hipSuccess) {
+      s->timed_ms += ms;
+      s->timed_count += 1;
+    }
+  }
+  s->ev_used = 0;
+}
+
 template <typename T>
 void vcycle_edge(bl_solver* s, int l, const T* b, T* x, int ncols) {
   const int pr = PrecOf<T>::v;
@@ -217,8 +253,11 @@ void vcycle_edge(bl_solver* s, int l, const T* b, T* x, int ncols) {
   }
   fill_zero<T>(x, (int64_t)ncols * 2 * L.g.ne, s->st);
   for (int it = 0; it < s->opts.nu_pre; ++it)
-    for (int c = 0; c < 4; ++c)
+    for (int c = 0; c < 4; ++c) {
+      timing_begin(s, l);
       edge_gs<T>(x, b, L.kappa64, L.kappa32, L.sinv64, L.sinv32, L.g, s->ph, s->mu, L.T4, c, ncols, s->st);
+      timing_end(s, l, ncols);
+    }
   T* r = static_cast<T*>(L.er[pr]);
   edge_apply<T, T>(EM_RESID_K, x, b, r, L.kappa64, L.kappa32, nullptr, L.g, s->ph, s->mu, ncols, nullptr, nullptr, s->st);
   Level& C = s->lv[l + 1];
@@ -228,9 +267,12 @@ void vcycle_edge(bl_solver* s, int l, const T* b, T* x, int ncols) {
   vcycle_edge<T>(s, l + 1, bc, xc, ncols);
   edge_prolong_add<T>(xc, C.g, x, L.g, s->ph, ncols, s->st);
   for (int it = 0; it < s->opts.nu_post; ++it)
-    for (int c = 3; c >= 0; --c)
+    for (int c = 3; c >= 0; --c) {
+      timing_begin(s, l);
       edge_gs<T>(x, b, L.kappa64, L.kappa32, L.sinv64, L.sinv32, L.g, s->ph, s->mu, L.T4, c, ncols, s->st);
-  s->launches += 4 + 4 * (s->opts.nu_pre + s->opts.nu_post);
+      timing_end(s, l, ncols);
+    }
+  s->launches += 4 + 4 * (s->opts.nu_post + s->opts.nu_pre);
 }
 
 // ---- nodal V-cycle for P = L^* M L ----------------------------------------------------------
@@ -343,7 +385,7 @@ int ritz_step(bl_solver* s, int q, int want, double zero_thr, int* found) {
   edge_apply<double, double>(EM_A, s->S, nullptr, WA, L.kappa64, L.kappa32, nullptr, g, s->ph, s->mu, q, nullptr, nullptr, s->st);
   gram(s->S, q, s->W, 2 * q, g.ne, s->gram_partial, s->gram_cap, s->GH, s->st);
   split_gram(s->GH, q, s->Gm, s->Hm, s->st);
-  ritz_small(s->Gm, s->Hm, q, want, zero_thr, 1e-12, s->ritz_work, s->Yd, s->theta_d, s->count_d, s->st);
+  ritz_small(s->Gm, s->Hm, q, want, zero_thr, kDropRel, s->ritz_work, s->Yd, s->theta_d, s->count_d, s->st);
   block_combine(s->S, q, s->Yd, want, g.ne, s->Enew, s->st);
   s->launches += 7;
   std::swap(s->E, s->Enew);
@@ -557,6 +599,7 @@ int residuals(bl_solver* s, void* Rbuf, int inner_prec, std::vector<double>& lam
   HIP_OK(hipMemcpyAsync(nr.data(), s->norms, nr.size() * 8, hipMemcpyDeviceToHost, s->st));
   HIP_OK(hipMemcpyAsync(lam.data(), s->lam_d, lam.size() * 8, hipMemcpyDeviceToHost, s->st));
   HIP_OK(hipStreamSynchronize(s->st));
+  timing_collect(s);
   int rc = check_hip(s);
   if (rc) return rc;
   rel.resize(s->p);
@@ -821,6 +864,7 @@ void bl_destroy(bl_solver* s) {
   if (s->st) (void)hipStreamSynchronize(s->st);
   else (void)hipDeviceSynchronize();
   for (void* p : s->allocs) (void)hipFree(p);
+  for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
   delete s;
 }
 
@@ -881,6 +925,28 @@ int bl_last_residual_history(const bl_solver* s, double* relres, int32_t cap) {
   return rows;
 }
 
+int bl_set_timing(bl_solver* s, int32_t enable) {
+  if (!s) return set_error(BL_EINVAL, "solver is NULL%s");
+  if (enable && s->ev_pool.empty()) {
+    s->ev_pool.resize(4096);
+    for (auto& e : s->ev_pool) HIP_OK(hipEventCreate(&e));
+  }
+  s->timing = enable != 0;
+  s->timed_ms = 0.0;
+  s->timed_count = 0;
+  s->timed_cols = 0;
+  s->ev_used = 0;
+  return BL_OK;
+}
+
+int bl_get_timing(const bl_solver* s, double* total_ms, int64_t* launches, int64_t* columns) {
+  if (!s || !total_ms || !launches || !columns) return set_error(BL_EINVAL, "NULL argument%s");
+  *total_ms = s->timed_ms;
+  *launches = s->timed_count;
+  *columns = s->timed_cols;
+  return BL_OK;
+}
+
 int bl_set_k(bl_solver* s, double k1, double k2) {
   if (!s) return set_error(BL_EINVAL, "solver is NULL%s");
   int rc = setup_k(s, k1, k2);
@@ -933,7 +999,7 @@ int bl_ritz_small(bl_solver* s, const double* G, const double* H, int32_t q, int
   HIP_OK(hipMalloc(&dc, sizeof(int)));
   HIP_OK(hipMemcpyAsync(dG, G, m2, hipMemcpyHostToDevice, s->st));
   HIP_OK(hipMemcpyAsync(dH, H, m2, hipMemcpyHostToDevice, s->st));
-  ritz_small(dG, dH, q, want, zero_thr, 1e-12, dW, dY, dT, dc, s->st);
+  ritz_small(dG, dH, q, want, zero_thr, kDropRel, dW, dY, dT, dc, s->st);
   int cnt = 0;
   hipError_t e = hipMemcpyAsync(Y, dY, (size_t)q * want * 2 * 8, hipMemcpyDeviceToHost, s->st);
   if (e == hipSuccess) e = hipMemcpyAsync(theta, dT, (size_t)want * 8, hipMemcpyDeviceToHost, s->st);

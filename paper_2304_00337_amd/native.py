@@ -58,6 +58,8 @@ EXPORTED = {
     "bl_reset_history": (c_int32, [c_void_p]),
     "bl_last_residual_history": (c_int32, [c_void_p, P(c_double), c_int32]),
     "bl_set_k": (c_int32, [c_void_p, c_double, c_double]),
+    "bl_set_timing": (c_int32, [c_void_p, c_int32]),
+    "bl_get_timing": (c_int32, [c_void_p, P(c_double), P(c_int64), P(c_int64)]),
     "bl_apply": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p, c_void_p,
                            c_void_p]),
     "bl_gram": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_int32, c_int64, P(c_double)]),
