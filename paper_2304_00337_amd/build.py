@@ -12,7 +12,7 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SOURCES = ["csrc/stencils.hip", "csrc/dense.hip", "csrc/solver.hip"]
+SOURCES = ["csrc/stencils.hip", "csrc/dense.hip", "csrc/ritz.hip", "csrc/solver.hip"]
 LIB = os.path.join(PKG, "libbloch.so")
 
 

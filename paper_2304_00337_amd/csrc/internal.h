@@ -99,9 +99,10 @@ void gram(const double* X, int q, const double* W, int r, int64_t len, double* p
 int gram_blocks(int64_t len);
 
 // Generalised Hermitian eigenproblem H y = theta G y (q x q, row-major interleaved, FP64,
-// device).  Writes `want` G-orthonormal coefficient vectors (q x want row-major interleaved)
-// to Y, their Ritz values to theta and the count found to *count (device int).
-void ritz_small(const double* G, const double* H, int q, int want, double zero_thr,
+// device).  The first nfix basis vectors may be declared G-orthonormal and H-diagonal
+// (previous Ritz vectors).  Writes `want` G-orthonormal coefficient vectors (q x want
+// row-major interleaved) to Y, their Ritz values to theta and the count found to *count.
+void ritz_small(const double* G, const double* H, int q, int nfix, int want, double zero_thr,
                 double drop_rel, double* work, double* Y, double* theta, int* count,
                 hipStream_t st);
 size_t ritz_small_work_doubles(int q);

@@ -1,0 +1,572 @@
+// Ritz step of the block iteration (Section 4, Ritz vectors and values) for gfx950: the
+// generalised Hermitian eigenproblem  H y = theta G y  of the basis S (q <= 255 columns),
+// G = S^* M S and H = S^* A S, solved in one workgroup in LDS:
+//
+//  1. unit-diagonal scaling D; pivoted Cholesky P^T (D G D) P = L L^* (the first nfix
+//     columns, previous Ritz vectors, keep their order), stopped when the largest remaining
+//     pivot is below drop_rel: numerically dependent directions of S are dropped (rank r);
+//  2. Z = D P [L^{-*}; 0] (q x r) spans the kept directions M-orthonormally; if a kept pivot
+//     was small, a second Cholesky pass on Z^* G Z restores orthonormality to rounding;
+//  3. H' = Z^* H Z (r x r) is reduced to real symmetric tridiagonal form by Householder
+//     reflections and a diagonal unitary scaling;
+//  4. the wanted eigenvalues (the `want` smallest above zero_thr) by Sturm-count bisection,
+//     one thread per eigenvalue; eigenvectors by inverse iteration with the tridiagonal LU,
+//     re-orthogonalised inside clusters of close eigenvalues;
+//  5. back-transformation through the scaling and the reflections, Y = Z y.
+#include "internal.h"
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+
+namespace bl {
+
+namespace {
+
+struct c2 {
+  double r, i;
+};
+__device__ __forceinline__ c2 cmul(c2 a, c2 b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
+__device__ __forceinline__ c2 cmulc(c2 a, c2 b) { return {a.r * b.r + a.i * b.i, a.r * b.i - a.i * b.r}; }  // conj(a) b
+
+constexpr int RT = 256;
+
+// size of the per-index arrays (one complex, six doubles, two ints per basis index) in
+// complex units, rounded up
+__host__ __device__ inline int index_block_c2(int q) { return (q * (16 + 48 + 8) + 15) / 16; }
+
+// Block-wide sum (all threads get the result).
+__device__ double bsum(double a, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sh[w] = a;
+  __syncthreads();
+  double t = 0;
+  for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += sh[k];
+  __syncthreads();
+  return t;
+}
+
+// Out (r x r, stride ldo) = Z^* X Z, X q x q (stride q), Z q x r (stride r), T q x r scratch.
+__device__ void aha(const c2* X, int q, const c2* Z, int r, c2* T, c2* Out, int ldo) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int e = tid; e < q * r; e += nt) {
+    const int i = e / r, c = e % r;
+    c2 s = {0, 0};
+#pragma unroll 4
+    for (int l = 0; l < q; ++l) {
+      const c2 t = cmul(X[i * q + l], Z[l * r + c]);
+      s.r += t.r;
+      s.i += t.i;
+    }
+    T[i * r + c] = s;
+  }
+  __syncthreads();
+  for (int e = tid; e < r * r; e += nt) {
+    const int a = e / r, b = e % r;
+    c2 s = {0, 0};
+#pragma unroll 4
+    for (int l = 0; l < q; ++l) {
+      const c2 t = cmulc(Z[l * r + a], T[l * r + b]);
+      s.r += t.r;
+      s.i += t.i;
+    }
+    Out[a * ldo + b] = s;
+  }
+  __syncthreads();
+}
+
+// Linv (stride ldv) = L^{-1} for lower-triangular L (stride ld, r x r), row by row: row i of
+// the inverse depends on rows < i; all columns of a row in parallel.
+__device__ void lower_inv(const c2* L, int ld, c2* Linv, int ldv, int r) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int i = 0; i < r; ++i) {
+    const double d = L[i * ld + i].r;
+    for (int c = tid; c < r; c += nt) {
+      c2 s = {(i == c) ? 1.0 : 0.0, 0.0};
+      if (c < i) {
+        for (int l = c; l < i; ++l) {
+          const c2 t = cmul(L[i * ld + l], Linv[l * ldv + c]);
+          s.r -= t.r;
+          s.i -= t.i;
+        }
+      } else if (c > i) {
+        s = {0.0, 0.0};
+      }
+      Linv[i * ldv + c] = {s.r / d, s.i / d};
+    }
+    __syncthreads();
+  }
+}
+
+// Unpivoted in-place Cholesky of the Hermitian positive definite r x r matrix A (lower).
+__device__ void chol(c2* A, int r, int ld) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int k = 0; k < r; ++k) {
+    double d = A[k * ld + k].r;
+    d = d > 1e-300 ? sqrt(d) : 1e-150;
+    __syncthreads();
+    for (int i = k + 1 + tid; i < r; i += nt) {
+      const c2 a = A[i * ld + k];
+      A[i * ld + k] = {a.r / d, a.i / d};
+    }
+    if (tid == 0) A[k * ld + k] = {d, 0.0};
+    __syncthreads();
+    const int rem = r - k - 1;
+    for (int e = tid; e < rem * rem; e += nt) {
+      const int i = k + 1 + e / rem, j = k + 1 + e % rem;
+      if (j > i) continue;
+      const c2 t = cmulc(A[j * ld + k], A[i * ld + k]);
+      A[i * ld + j] = {A[i * ld + j].r - t.r, A[i * ld + j].i - t.i};
+    }
+    __syncthreads();
+  }
+}
+
+// Number of eigenvalues of the real symmetric tridiagonal (d, e; e[i] couples i, i+1)
+// that are below x (Sturm sequence of the LDL^T factorisation of T - x I).
+__device__ int sturm_count(const double* d, const double* e2, int r, double x, double tiny) {
+  int c = 0;
+  double qv = d[0] - x;
+  if (qv < 0) ++c;
+#pragma unroll 8
+  for (int i = 1; i < r; ++i) {
+    if (fabs(qv) < tiny) qv = qv < 0 ? -tiny : tiny;
+    qv = d[i] - x - e2[i - 1] / qv;
+    if (qv < 0) ++c;
+  }
+  return c;
+}
+
+}  // namespace
+
+size_t ritz_small_work_doubles(int q) { return (size_t)10 * q * q + 8 * (size_t)q + 64; }  // 4 matrices + diagnostics
+
+// LDS layout (when it fits): A (q*q c2) | B (q*q c2) | Z (q*q c2) | T (q*q c2).
+template <bool IN_LDS>
+__global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2* __restrict__ H, int q,
+                                             int nfix, int want, double zero_thr, double drop_rel,
+                                             double* __restrict__ work, c2* __restrict__ Y,
+                                             double* __restrict__ theta, int* __restrict__ count) {
+  extern __shared__ c2 smem[];
+  __shared__ double sh[32];
+  __shared__ int rank_s, nsel_s, piv_s, second_s;
+  __shared__ double pivv_s;
+  // per-index arrays at the start of the dynamic LDS block, matrices after them (or in the
+  // global work array when they do not fit)
+  c2* phase = smem;
+  double* dsc = reinterpret_cast<double*>(phase + q);
+  double* dd = dsc + q;
+  double* ee = dd + q;
+  double* ee2 = ee + q;
+  double* tau = ee2 + q;
+  double* lam = tau + q;
+  int* perm = reinterpret_cast<int*>(lam + q);
+  int* pinv = perm + q;
+  c2* gw = reinterpret_cast<c2*>(work);
+  // compile-time choice, so that LDS pointers keep their address space (no flat accesses)
+  c2* A = IN_LDS ? smem + index_block_c2(q) : gw;
+  c2* B = A + q * q;
+  c2* Z = B + q * q;
+  c2* T = Z + q * q;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  double* stamp = work + 10 * q * q + 8 * q + 1;
+  if (tid == 0) { stamp[0] = (double)wall_clock64(); stamp[7] = (double)clock64(); }
+
+  // ---- 1. scaled G and pivoted Cholesky --------------------------------------------------
+  for (int i = tid; i < q; i += nt) {
+    const double gd = G[i * q + i].r;
+    dsc[i] = gd > 0 ? 1.0 / sqrt(gd) : 0.0;
+    perm[i] = i;
+  }
+  if (tid == 0) second_s = 0;
+  __syncthreads();
+  for (int e = tid; e < q * q; e += nt) {
+    const int i = e / q, j = e % q;
+    const c2 g = G[e], gt = G[j * q + i];
+    const double s = dsc[i] * dsc[j];
+    A[e] = {0.5 * (g.r + gt.r) * s, 0.5 * (g.i - gt.i) * s};
+  }
+  __syncthreads();
+  int r = 0;
+  for (int k = 0; k < q; ++k) {
+    if (tid == 0) {   // pivot search: one thread, independent (pipelined) LDS loads
+      double v = -1.0;
+      int idx = q;
+      const int hi = k < nfix ? k + 1 : q;
+      for (int j = k; j < hi; ++j) {
+        const double dv = A[j * q + j].r;
+        if (dv > v) { v = dv; idx = j; }
+      }
+      pivv_s = v;
+      piv_s = idx;
+    }
+    __syncthreads();
+    const double v = pivv_s;
+    const int idx = piv_s;
+    if (!(v > drop_rel)) break;
+    if (v < 1e-4 && tid == 0) second_s = 1;
+    if (idx != k) {
+      for (int c = tid; c < q; c += nt) {
+        const c2 t = A[k * q + c];
+        A[k * q + c] = A[idx * q + c];
+        A[idx * q + c] = t;
+      }
+      __syncthreads();
+      for (int c = tid; c < q; c += nt) {
+        const c2 t = A[c * q + k];
+        A[c * q + k] = A[c * q + idx];
+        A[c * q + idx] = t;
+      }
+      if (tid == 0) {
+        const int t = perm[k];
+        perm[k] = perm[idx];
+        perm[idx] = t;
+      }
+      __syncthreads();
+    }
+    const double piv = sqrt(A[k * q + k].r);
+    for (int i = k + 1 + tid; i < q; i += nt) {
+      const c2 a = A[i * q + k];
+      A[i * q + k] = {a.r / piv, a.i / piv};
+    }
+    __syncthreads();
+    if (tid == 0) A[k * q + k] = {piv, 0.0};
+    const int rem = q - k - 1;
+    for (int e = tid; e < rem * rem; e += nt) {   // full trailing square (swaps stay valid)
+      const int i = k + 1 + e / rem, j = k + 1 + e % rem;
+      const c2 t = cmulc(A[j * q + k], A[i * q + k]);
+      A[i * q + j] = {A[i * q + j].r - t.r, A[i * q + j].i - t.i};
+    }
+    __syncthreads();
+    r = k + 1;
+  }
+  if (tid == 0) rank_s = r;
+  __syncthreads();
+  r = rank_s;
+  if (tid == 0) stamp[1] = (double)wall_clock64();
+
+  // ---- 2. Z = D P [L^{-*}; 0] -------------------------------------------------------------
+  lower_inv(A, q, B, q, r);
+  for (int i = tid; i < q; i += nt) pinv[perm[i]] = i;
+  __syncthreads();
+  for (int e = tid; e < q * r; e += nt) {
+    const int i = e / r, c = e % r;
+    const int pi = pinv[i];
+    c2 z = {0.0, 0.0};
+    if (pi < r && pi <= c) {
+      const c2 l = B[c * q + pi];
+      z = {dsc[i] * l.r, -dsc[i] * l.i};
+    }
+    Z[i * r + c] = z;
+  }
+  __syncthreads();
+  if (second_s) {   // G2 = Z^* G Z = L2 L2^*, Z <- Z L2^{-*}
+    aha(G, q, Z, r, T, A, r);
+    chol(A, r, r);
+    lower_inv(A, r, B, r, r);
+    for (int e = tid; e < q * r; e += nt) {
+      const int i = e / r, c = e % r;
+      c2 s = {0, 0};
+      for (int l = 0; l <= c; ++l) {
+        const c2 t = cmulc(B[c * r + l], Z[i * r + l]);
+        s.r += t.r;
+        s.i += t.i;
+      }
+      T[i * r + c] = s;
+    }
+    __syncthreads();
+    for (int e = tid; e < q * r; e += nt) Z[e] = T[e];
+    __syncthreads();
+  }
+  if (tid == 0) stamp[2] = (double)wall_clock64();
+
+  // ---- 3. H' = Z^* H Z (A, stride r), Hermitian part, then tridiagonalisation ----------------
+  aha(H, q, Z, r, T, A, r);
+  for (int e = tid; e < r * r; e += nt) {
+    const int a = e / r, b = e % r;
+    if (a < b) {
+      const c2 x = A[a * r + b], y = A[b * r + a];
+      const c2 h = {0.5 * (x.r + y.r), 0.5 * (x.i - y.i)};
+      A[a * r + b] = h;
+      A[b * r + a] = {h.r, -h.i};
+    } else if (a == b) {
+      A[e].i = 0.0;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) stamp[3] = (double)wall_clock64();
+  // Householder: at step k the column below the diagonal, x = A[k+1:, k], is mapped to
+  // beta e1 by H_k = I - tau v v^* (v stored in row k of B, entries k+1..r-1); the trailing
+  // block becomes H_k A22 H_k via p = tau A22 v, w = p - (tau/2)(v^* p) v,
+  // A22 <- A22 - v w^* - w v^*.  T holds p and w.
+  c2* pv = T;
+  for (int k = 0; k + 2 < r; ++k) {
+    const int m = r - k - 1;
+    if (tid == 0) {
+      double part = 0;
+      for (int j = 0; j < m; ++j) {
+        const c2 x = A[(k + 1 + j) * r + k];
+        part += x.r * x.r + x.i * x.i;
+      }
+      sh[0] = part;
+    }
+    __syncthreads();
+    const double xn2 = sh[0];
+    const c2 x0 = A[(k + 1) * r + k];
+    const double ax0 = sqrt(x0.r * x0.r + x0.i * x0.i);
+    const double sig = xn2 - ax0 * ax0;
+    if (sig <= 1e-30 * xn2 || xn2 == 0.0) {   // already reduced in this column
+      if (tid == 0) { tau[k] = 0.0; dd[k] = A[k * r + k].r; }
+      for (int j = tid; j < r; j += nt) B[k * r + j] = {0.0, 0.0};
+      __syncthreads();
+      continue;
+    }
+    const double xn = sqrt(xn2);
+    const c2 ph0 = ax0 > 0 ? c2{x0.r / ax0, x0.i / ax0} : c2{1.0, 0.0};
+    const c2 beta = {-ph0.r * xn, -ph0.i * xn};
+    const double tk = 1.0 / (xn2 + xn * ax0);      // 2 / (v^* v)
+    for (int j = tid; j < r; j += nt) {
+      c2 vj = {0.0, 0.0};
+      if (j == k + 1) vj = {x0.r - beta.r, x0.i - beta.i};
+      else if (j > k + 1) vj = A[j * r + k];
+      B[k * r + j] = vj;
+    }
+    if (tid == 0) { tau[k] = tk; dd[k] = A[k * r + k].r; }
+    __syncthreads();
+    const c2* v = B + k * r;
+    for (int i = tid; i < m; i += nt) {   // p = tau A22 v
+      c2 s = {0, 0};
+      const int row = k + 1 + i;
+#pragma unroll 4
+      for (int l = 0; l < m; ++l) {
+        const c2 t = cmul(A[row * r + k + 1 + l], v[k + 1 + l]);
+        s.r += t.r;
+        s.i += t.i;
+      }
+      pv[i] = {tk * s.r, tk * s.i};
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double kp = 0;
+      for (int i = 0; i < m; ++i) kp += cmulc(v[k + 1 + i], pv[i]).r;
+      sh[1] = kp;
+    }
+    __syncthreads();
+    const double Kh = 0.5 * tk * sh[1];
+    for (int i = tid; i < m; i += nt) {
+      const c2 vi = v[k + 1 + i];
+      pv[i] = {pv[i].r - Kh * vi.r, pv[i].i - Kh * vi.i};
+    }
+    __syncthreads();
+    for (int e = tid; e < m * m; e += nt) {
+      const int i = e / m, j = e % m;
+      const c2 vi = v[k + 1 + i], vj = v[k + 1 + j], wi = pv[i], wj = pv[j];
+      const c2 t1 = cmulc(wj, vi), t2 = cmulc(vj, wi);   // v_i conj(w_j), w_i conj(v_j)
+      c2& a = A[(k + 1 + i) * r + k + 1 + j];
+      a = {a.r - t1.r - t2.r, a.i - t1.i - t2.i};
+    }
+    if (tid == 0) A[(k + 1) * r + k] = beta;
+    __syncthreads();
+  }
+  // real tridiagonal: T' = Phi^* T Phi with Phi = diag(phase), off-diagonals |T_{k+1,k}|
+  if (tid == 0) {
+    for (int k = (r >= 2 ? r - 2 : 0); k < r; ++k) dd[k] = A[k * r + k].r;
+    phase[0] = {1.0, 0.0};
+    for (int k = 0; k + 1 < r; ++k) {
+      const c2 b = A[(k + 1) * r + k];
+      const double ab = sqrt(b.r * b.r + b.i * b.i);
+      ee[k] = ab;
+      ee2[k] = ab * ab;
+      // phase[k+1] = phase[k] * b / |b|
+      const c2 u = ab > 0 ? c2{b.r / ab, b.i / ab} : c2{1.0, 0.0};
+      phase[k + 1] = cmul(phase[k], u);
+    }
+    if (r >= 1) { ee[r - 1] = 0.0; ee2[r - 1] = 0.0; }
+  }
+  __syncthreads();
+  if (tid == 0) stamp[4] = (double)wall_clock64();
+
+  // ---- 4. wanted eigenvalues (bisection) and eigenvectors (inverse iteration) -------------
+  double tn = 0;   // infinity norm of the tridiagonal
+  for (int i = 0; i < r; ++i) tn = fmax(tn, fabs(dd[i]) + (i > 0 ? ee[i - 1] : 0.0) + ee[i]);
+  const double lo0 = -tn - 1.0, hi0 = tn + 1.0;
+  const double tiny = 1e-300 + 1e-16 * tn * 1e-10;
+  const int nz = (zero_thr > lo0) ? sturm_count(dd, ee2, r, zero_thr * (1 + 1e-14) + 1e-300, tiny) : 0;
+  const int ns = min(want, r - nz);
+  for (int j = tid; j < ns; j += nt) {     // the (nz + j)-th smallest eigenvalue
+    const int target = nz + j;
+    double lo = lo0, hi = hi0;
+    for (int it = 0; it < 200 && hi - lo > 4e-16 * fmax(fabs(lo), fabs(hi)) + 1e-300; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (mid <= lo || mid >= hi) break;          // no representable midpoint left
+      if (sturm_count(dd, ee2, r, mid, tiny) > target) hi = mid; else lo = mid;
+    }
+    lam[j] = 0.5 * (lo + hi);
+  }
+  if (tid == 0) nsel_s = ns;
+  __syncthreads();
+  // Inverse iteration on T' - lambda I with partial pivoting; eigenvalues closer than
+  // 1e-9 tn form a cluster, whose vectors are computed one after the other by one thread
+  // and Gram-Schmidt-orthogonalised against the cluster's earlier vectors.  Real vectors
+  // of length r are kept in T (as doubles): vec j at xs + j*r; the LU work arrays after.
+  // x vectors (real, length r) at the start of T; per cluster head j the LU of
+  // T' - lambda I (3 arrays of length r) in the free A region, continued in T's tail
+  // (at most want*r + 3*want*r <= 4 q^2 doubles, the size of A and T together).
+  double* xs = reinterpret_cast<double*>(T);
+  const int clus_in_a = (2 * q * q) / (3 * r > 0 ? 3 * r : 1);
+  for (int j = tid; j < ns; j += nt) {
+    if (j > 0 && lam[j] - lam[j - 1] <= 1e-6 * tn) continue;   // not a cluster head
+    int jend = j + 1;
+    while (jend < ns && lam[jend] - lam[jend - 1] <= 1e-6 * tn) ++jend;
+    double* u = j < clus_in_a ? reinterpret_cast<double*>(A) + (size_t)j * 3 * r
+                              : xs + (size_t)want * r + (size_t)(j - clus_in_a) * 3 * r;
+    double* u1 = u + r;        // U: diagonal and first super-diagonal; the second
+    double* lm = u1 + r;       // super-diagonal is e_{i+1} after a row swap, else 0.
+                               // Multipliers; a row swap is encoded as -(mult) - 4.
+    for (int c = j; c < jend; ++c) {
+      double* x = xs + (size_t)c * r;
+      const double shift = lam[c];
+      // Gaussian elimination with partial pivoting of the tridiagonal T' - shift I: the
+      // carried row has entries (a_i, b_i) in columns (i, i+1); the next row is
+      // (e_i, d_{i+1} - shift, e_{i+1}) in columns (i, i+1, i+2).
+      double a_i = dd[0] - shift, b_i = ee[0];
+      for (int i = 0; i < r - 1; ++i) {
+        const double sub = ee[i];
+        const double dnext = dd[i + 1] - shift, bnext = ee[i + 1];
+        if (fabs(sub) > fabs(a_i)) {              // swap rows i and i+1
+          const double mlt = a_i / sub;
+          u[i] = sub;
+          u1[i] = dnext;
+          lm[i] = -mlt - 4.0;                     // |mult| <= 1, so lm <= -3 marks a swap
+          a_i = b_i - mlt * dnext;
+          b_i = -mlt * bnext;
+        } else {
+          const double aa = fabs(a_i) > tiny ? a_i : (a_i < 0 ? -tiny : tiny);
+          const double mlt = sub / aa;
+          u[i] = aa;
+          u1[i] = b_i;
+          lm[i] = mlt;                            // |mult| <= 1
+          a_i = dnext - mlt * b_i;
+          b_i = bnext;
+        }
+      }
+      u[r - 1] = fabs(a_i) > tiny ? a_i : (a_i < 0 ? -tiny : tiny);
+      u1[r - 1] = 0.0;
+      lm[r - 1] = 0.0;
+      for (int i = 0; i < r; ++i) x[i] = 1.0 + 0.0625 * (double)((i * 7 + c * 3) % 11);
+      for (int rep = 0; rep < 3; ++rep) {
+        // forward: apply the row operations to x
+        for (int i = 0; i < r - 1; ++i) {
+          const double l = lm[i];
+          if (l <= -3.0) {   // swapped: new row i <- old row i+1; row i+1 <- old i - mult*old i+1
+            const double mlt = -(l + 4.0);
+            const double t = x[i];
+            x[i] = x[i + 1];
+            x[i + 1] = t - mlt * x[i];
+          } else {
+            x[i + 1] -= l * x[i];
+          }
+        }
+        // back substitution with U (diagonal u, super u1, super-super u2)
+        for (int i = r - 1; i >= 0; --i) {
+          double s = x[i];
+          if (i + 1 < r) s -= u1[i] * x[i + 1];
+          if (i + 2 < r && lm[i] <= -3.0) s -= ee[i + 1] * x[i + 2];
+          x[i] = s / u[i];
+        }
+        // orthogonalise against the cluster's earlier vectors, normalise
+        for (int pc = j; pc < c; ++pc) {
+          const double* y = xs + (size_t)pc * r;
+          double dot = 0;
+          for (int i = 0; i < r; ++i) dot += y[i] * x[i];
+          for (int i = 0; i < r; ++i) x[i] -= dot * y[i];
+        }
+        double nrm = 0;
+        for (int i = 0; i < r; ++i) nrm += x[i] * x[i];
+        nrm = sqrt(nrm);
+        const double inv = nrm > 0 ? 1.0 / nrm : 0.0;
+        for (int i = 0; i < r; ++i) x[i] *= inv;
+      }
+    }
+  }
+  __syncthreads();
+  if (tid == 0) stamp[5] = (double)wall_clock64();
+
+  // ---- 5. back-transformation: y = H_0 ... H_{r-3} Phi x, then Y = Z y ----------------------
+  // complex vectors of length r in A (stride ns... use column-major: yv[c * r + i])
+  c2* yv = A;
+  for (int e = tid; e < ns * r; e += nt) {
+    const int c = e / r, i = e % r;
+    const double xv = xs[(size_t)c * r + i];
+    yv[e] = {phase[i].r * xv, phase[i].i * xv};
+  }
+  __syncthreads();
+  for (int k = r - 3; k >= 0; --k) {
+    const double tk = tau[k];
+    if (tk == 0.0) continue;
+    const c2* v = B + k * r;
+    // y_c -= tau v (v^* y_c), one thread per column
+    for (int c = tid; c < ns; c += nt) {
+      c2 s = {0, 0};
+      for (int i = k + 1; i < r; ++i) {
+        const c2 t = cmulc(v[i], yv[c * r + i]);
+        s.r += t.r;
+        s.i += t.i;
+      }
+      for (int i = k + 1; i < r; ++i) {
+        const c2 t = cmul(v[i], s);
+        yv[c * r + i] = {yv[c * r + i].r - tk * t.r, yv[c * r + i].i - tk * t.i};
+      }
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < q * want; e += nt) {
+    const int i = e / want, c = e % want;
+    c2 s = {0, 0};
+    if (c < ns) {
+      for (int l = 0; l < r; ++l) {
+        const c2 t = cmul(Z[i * r + l], yv[c * r + l]);
+        s.r += t.r;
+        s.i += t.i;
+      }
+    }
+    Y[i * want + c] = s;
+  }
+  for (int c = tid; c < want; c += nt) theta[c] = c < ns ? lam[c] : 0.0;
+  if (tid == 0) {
+    *count = ns;
+    work[10 * q * q + 8 * q] = (double)r;       // diagnostic: kept rank
+    stamp[5 + 1] = (double)wall_clock64();
+    stamp[8] = (double)clock64();
+  }
+}
+
+static int g_cap = -1;
+
+void ritz_small(const double* G, const double* H, int q, int nfix, int want, double zero_thr,
+                double drop_rel, double* work, double* Y, double* theta, int* count,
+                hipStream_t st) {
+  if (g_cap < 0) {
+    int dev = 0, cap = 65536;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cap, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) cap = 65536;
+    cap -= 1024;   // the kernel's static LDS (reduction scratch and scalars) is below 1 KB
+    if (cap > 0 && (hipFuncSetAttribute((const void*)k_ritz<true>, hipFuncAttributeMaxDynamicSharedMemorySize, cap) != hipSuccess ||
+                    hipFuncSetAttribute((const void*)k_ritz<false>, hipFuncAttributeMaxDynamicSharedMemorySize, cap) != hipSuccess))
+      cap = 64 * 1024 - 1024;
+    g_cap = cap > 0 ? cap : 0;
+    if (std::getenv("BL_DEBUG")) std::fprintf(stderr, "bloch: ritz dynamic LDS cap %d bytes\n", g_cap);
+  }
+  const size_t idx = (size_t)index_block_c2(q) * sizeof(c2);
+  const size_t need = idx + (size_t)4 * q * q * sizeof(c2);
+  const int in_lds = need <= (size_t)g_cap ? 1 : 0;
+  if (in_lds)
+    k_ritz<true><<<1, RT, need, st>>>(reinterpret_cast<const c2*>(G), reinterpret_cast<const c2*>(H), q,
+                                      nfix, want, zero_thr, drop_rel, work, reinterpret_cast<c2*>(Y), theta, count);
+  else
+    k_ritz<false><<<1, RT, idx, st>>>(reinterpret_cast<const c2*>(G), reinterpret_cast<const c2*>(H), q,
+                                      nfix, want, zero_thr, drop_rel, work, reinterpret_cast<c2*>(Y), theta, count);
+}
+
+}  // namespace bl

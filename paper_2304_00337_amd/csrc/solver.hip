@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -146,6 +147,7 @@ struct bl_solver {
   double timed_ms = 0.0;
   int64_t timed_count = 0;
   int64_t timed_cols = 0;
+  bool debug = false;
 };
 
 namespace {
@@ -376,7 +378,7 @@ int project(bl_solver* s, const std::vector<Group>& groups, double* Sout) {
 
 // Ritz step on the q columns of S (FP64): G = S^* M S, H = S^* A S, generalised eigen-
 // problem, E <- S Y for the `want` smallest Ritz values above zero_thr.  Returns the count.
-int ritz_step(bl_solver* s, int q, int want, double zero_thr, int* found) {
+int ritz_step(bl_solver* s, int q, int nfix, int want, double zero_thr, int* found) {
   const Level& L = s->lv[0];
   const Geo& g = L.g;
   double* WM = s->W;
@@ -385,9 +387,17 @@ int ritz_step(bl_solver* s, int q, int want, double zero_thr, int* found) {
   edge_apply<double, double>(EM_A, s->S, nullptr, WA, L.kappa64, L.kappa32, nullptr, g, s->ph, s->mu, q, nullptr, nullptr, s->st);
   gram(s->S, q, s->W, 2 * q, g.ne, s->gram_partial, s->gram_cap, s->GH, s->st);
   split_gram(s->GH, q, s->Gm, s->Hm, s->st);
-  ritz_small(s->Gm, s->Hm, q, want, zero_thr, kDropRel, s->ritz_work, s->Yd, s->theta_d, s->count_d, s->st);
+  ritz_small(s->Gm, s->Hm, q, nfix, want, zero_thr, kDropRel, s->ritz_work, s->Yd, s->theta_d, s->count_d, s->st);
   block_combine(s->S, q, s->Yd, want, g.ne, s->Enew, s->st);
   s->launches += 7;
+  if (s->debug) {
+    double sw[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    (void)hipMemcpyAsync(sw, s->ritz_work + 10 * q * q + 8 * q, 10 * 8, hipMemcpyDeviceToHost, s->st);
+    (void)hipStreamSynchronize(s->st);
+    std::fprintf(stderr, "bloch: ritz q=%d want=%d rank %.0f  shader MHz %.0f  phase us: chol %.1f basis %.1f hprime %.1f tridiag %.1f eig %.1f back %.1f\n",
+                 q, want, sw[0], (sw[9] - sw[8]) / ((sw[7] - sw[1]) * 0.01), (sw[2] - sw[1]) * 0.01, (sw[3] - sw[2]) * 0.01, (sw[4] - sw[3]) * 0.01,
+                 (sw[5] - sw[4]) * 0.01, (sw[6] - sw[5]) * 0.01, (sw[7] - sw[6]) * 0.01);
+  }
   std::swap(s->E, s->Enew);
   std::swap(s->lam_d, s->theta_d);
   int cnt = 0;
@@ -622,14 +632,14 @@ int solve_one(bl_solver* s, double k1, double k2, const void* start_dev, double*
   if (start_dev) {
     rc = project(s, {{start_dev, 0, p}}, s->S);
     if (rc) return rc;
-    rc = ritz_step(s, p, p, -INFINITY, &found);
+    rc = ritz_step(s, p, 0, p, -INFINITY, &found);
   } else {
     std::vector<Group> gs;
     const int depth = std::min(s->hist_count, s->opts.extrap_depth);
     for (int h = 0; h < depth; ++h) gs.push_back({s->hist[h], 0, p});
     rc = project(s, gs, s->S);
     if (rc) return rc;
-    rc = ritz_step(s, depth * p, p, s->opts.zero_rel * s->hist_lam1, &found);
+    rc = ritz_step(s, depth * p, 0, p, s->opts.zero_rel * s->hist_lam1, &found);
   }
   if (rc) return rc;
   if (found < p) return set_error(BL_ENOCONV, "start block spans fewer than p non-null directions%s");
@@ -652,7 +662,7 @@ int solve_one(bl_solver* s, double k1, double k2, const void* start_dev, double*
     else vcycle_edge<double>(s, 0, static_cast<double*>(R), static_cast<double*>(C), p);
     rc = project(s, {{s->E, 0, p}, {C, ip, p}}, s->S);
     if (rc) return rc;
-    rc = ritz_step(s, 2 * p, p, -INFINITY, &found);
+    rc = ritz_step(s, 2 * p, p, p, -INFINITY, &found);
     if (rc) return rc;
     ++it;
   }
@@ -845,6 +855,7 @@ int bl_create(const bl_grid* grid, const double* eps_cells, const bl_opts* opts,
   s->st = static_cast<hipStream_t>(stream);
   s->p = o.nev + o.nthrow;
   s->qmax = 3 * s->p;
+  s->debug = std::getenv("BL_DEBUG") != nullptr;
   if (hipGetDevice(&s->device) != hipSuccess) {
     delete s;
     return set_error(BL_EHIP, "no HIP device%s");
@@ -999,7 +1010,7 @@ int bl_ritz_small(bl_solver* s, const double* G, const double* H, int32_t q, int
   HIP_OK(hipMalloc(&dc, sizeof(int)));
   HIP_OK(hipMemcpyAsync(dG, G, m2, hipMemcpyHostToDevice, s->st));
   HIP_OK(hipMemcpyAsync(dH, H, m2, hipMemcpyHostToDevice, s->st));
-  ritz_small(dG, dH, q, want, zero_thr, kDropRel, dW, dY, dT, dc, s->st);
+  ritz_small(dG, dH, q, 0, want, zero_thr, kDropRel, dW, dY, dT, dc, s->st);
   int cnt = 0;
   hipError_t e = hipMemcpyAsync(Y, dY, (size_t)q * want * 2 * 8, hipMemcpyDeviceToHost, s->st);
   if (e == hipSuccess) e = hipMemcpyAsync(theta, dT, (size_t)want * 8, hipMemcpyDeviceToHost, s->st);
