@@ -206,6 +206,88 @@ int bl_gram(bl_solver* s, const void* X, int32_t q, const void* W, int32_t r, in
 int bl_ritz_small(bl_solver* s, const double* G, const double* H, int32_t q, int32_t want,
                   double zero_thr, double* theta, double* Y);
 
+/* ---- Batched solves (many problems in the same launches) --------------------------------
+ * Problems of equal shape (n, m, a, b and block width p = nev + nthrow) share one engine:
+ * every kernel launch of an iteration round covers all of its problem slots, each with its
+ * own permittivity, mu, Bloch parameter, coarse solvers and eigenvector history.  Shapes
+ * run on separate streams.  A problem's results do not depend on the other problems of the
+ * batch (each slot's arithmetic and reduction order is the same as when it is solved alone). */
+typedef struct bl_problem {
+  bl_grid grid;
+  const double* eps;      /* host, n*m cell values > 0 (read during the call)               */
+  int32_t nev, nthrow;    /* wanted pairs and throw-away vectors; p = nev + nthrow <= 80     */
+  int32_t nk;             /* Bloch parameters on the path, >= 1                              */
+  int32_t reserved0;
+  const double* ks;       /* host, 2*nk: k1, k2 per point, solved in order with extrapolation */
+  const void* start_dev;  /* device FP64 planar block of p columns of length N_e (required)  */
+  double* evals;          /* host out, nk*nev (row t = point t)                              */
+  double* relres;         /* host out, nk*nev                                                */
+  int32_t* iters;         /* host out, nk                                                    */
+  void* evecs_dev;        /* NULL or device FP64 planar block of nev columns, last point     */
+  int32_t status;         /* out: BL_OK, BL_ENOCONV, BL_EINVAL, BL_ENOMEM                    */
+  int32_t reserved1;
+} bl_problem;
+
+/* Solve `count` problems with the common options `opts` (nev and nthrow are taken from each
+ * problem; NULL = defaults).  max_slots: most slots per shape engine (0 = as many as the
+ * problems of that shape, within 90% of the free device memory).  stream: synchronised
+ * before the start blocks are read; the work runs on streams of the library's own.
+ * Returns BL_OK when every problem succeeded, else the first failing status (per-problem
+ * statuses in bl_problem.status; results of BL_ENOCONV problems hold the best values). */
+int bl_batch_solve(const bl_opts* opts, bl_problem* probs, int32_t count, int32_t max_slots,
+                   void* stream);
+
+/* ---- Serving: asynchronous requests with continuous batching -----------------------------
+ * A server owns a worker thread that admits requests by device-memory footprint (engines of
+ * the request's shape with a free slot, or a new engine within hbm_budget bytes; idle
+ * engines of other shapes are released to make room), runs iteration rounds over every busy
+ * engine, and lets requests that arrive while others run join at the next round. */
+typedef struct bl_server bl_server;
+
+typedef struct bl_request {
+  bl_grid grid;
+  const double* eps;      /* host, n*m (copied by bl_server_submit)                          */
+  int32_t nev, nthrow, nk, reserved0;
+  const double* ks;       /* host, 2*nk (copied)                                             */
+  const void* start_dev;  /* device FP64 planar block of p columns, written completely
+                             before the call (the server reads it on a stream of its own);
+                             must stay valid and unchanged until the result is polled       */
+} bl_request;
+
+typedef struct bl_request_info {
+  int32_t status;         /* the request's status (as returned by bl_server_poll)            */
+  int32_t total_iters;    /* iterations summed over the path                                 */
+  double queue_s;         /* submit -> admitted to a slot, seconds                           */
+  double run_s;           /* admitted -> results complete                                    */
+  double latency_s;       /* submit -> results complete                                      */
+} bl_request_info;
+
+typedef struct bl_server_counters {
+  int64_t rounds;          /* iteration rounds run                                           */
+  int64_t kernel_launches; /* launches issued by all engines                                 */
+  size_t device_bytes;     /* device memory held by the live engines                          */
+  int32_t engines;         /* live engines                                                   */
+  int32_t queued;          /* requests waiting for admission                                  */
+  int32_t pending;         /* requests submitted and not yet polled                           */
+  int32_t reserved;
+} bl_server_counters;
+
+/* opts: common options (nev, nthrow from each request; NULL = defaults).  hbm_budget: device
+ * bytes the engines may hold (0 = 90% of the free memory).  max_slots: most slots per
+ * engine (0 = 256).  The server works on the device current at creation. */
+int bl_server_create(const bl_opts* opts, size_t hbm_budget, int32_t max_slots, bl_server** out);
+/* Queue a request; *ticket identifies it.  Validation errors are returned here. */
+int bl_server_submit(bl_server* s, const bl_request* req, uint64_t* ticket);
+/* BL_EAGAIN while the request runs; otherwise copies the results (evals, relres nk*nev,
+ * iters nk, each may be NULL), fills *info (may be NULL), forgets the ticket and returns
+ * the request's status.  BL_EINVAL for an unknown ticket. */
+int bl_server_poll(bl_server* s, uint64_t ticket, double* evals, double* relres,
+                   int32_t* iters, bl_request_info* info);
+/* Counters; returns the worker's error (BL_OK while it runs). */
+int bl_server_stats(bl_server* s, bl_server_counters* out);
+/* Stop the worker and free every engine; results not polled are lost. */
+void bl_server_destroy(bl_server* s);
+
 const char* bl_strerror(int code);
 /* Message of the most recent error on the calling thread (static storage). */
 const char* bl_last_error(void);

@@ -7,9 +7,10 @@ import ctypes
 import numpy as np
 
 from . import native
-from .native import BlGrid, BlInfo, BlOpts, check
+from .native import (BlGrid, BlInfo, BlOpts, BlProblem, BlRequest, BlRequestInfo,
+                     BlServerCounters, check)
 
-__all__ = ["Solver", "to_device_block", "from_device_block"]
+__all__ = ["Solver", "Server", "batch_solve", "to_device_block", "from_device_block"]
 
 
 def _torch():
@@ -38,6 +39,151 @@ def from_device_block(t) -> np.ndarray:
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _make_opts(nev=8, **opts) -> BlOpts:
+    lib = native.load()
+    o = BlOpts()
+    lib.bl_default_opts(ctypes.byref(o), int(nev))
+    for k, v in opts.items():
+        if k == "precision" and isinstance(v, str):
+            v = {"fp64": 0, "mixed": 1}[v]
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def _start_block(start, p, n_edges):
+    torch = _torch()
+    if isinstance(start, np.ndarray):
+        start = to_device_block(start)
+    if start.dtype != torch.float64 or not start.is_contiguous() or start.numel() != p * 2 * n_edges:
+        raise ValueError("start must be a contiguous FP64 planar block of p columns")
+    return start
+
+
+def batch_solve(problems, max_slots=0, stream=None, want_last_vectors=False, **opts):
+    """bl_batch_solve.  `problems`: sequence of dicts with n, m, a, b, eps (n*m), nev,
+    nthrow, ks ((nk, 2) array) and start (host complex (N_e, p) or device planar block).
+    Common options as for Solver.  Returns one dict per problem (evals, relres, iterations,
+    status, evecs)."""
+    torch = _torch()
+    lib = native.load()
+    o = _make_opts(**opts)
+    keep = []
+    arr = (BlProblem * len(problems))()
+    outs = []
+    for i, pr in enumerate(problems):
+        n, m = int(pr["n"]), int(pr["m"])
+        nev, nthrow = int(pr["nev"]), int(pr["nthrow"])
+        p, ne = nev + nthrow, 2 * n * m
+        eps = np.ascontiguousarray(pr["eps"], dtype=np.float64)
+        ks = np.ascontiguousarray(pr["ks"], dtype=np.float64).reshape(-1, 2)
+        st = _start_block(pr["start"], p, ne)
+        ev = np.zeros((ks.shape[0], nev))
+        rr = np.zeros((ks.shape[0], nev))
+        its = np.zeros(ks.shape[0], dtype=np.int32)
+        vec = torch.empty((nev, 2, ne), dtype=torch.float64, device="cuda") if want_last_vectors else None
+        keep += [eps, ks, st, ev, rr, its, vec]
+        b = arr[i]
+        b.grid = BlGrid(n, m, float(pr["a"]), float(pr["b"]))
+        b.eps = _dptr(eps)
+        b.nev, b.nthrow, b.nk = nev, nthrow, ks.shape[0]
+        b.ks = _dptr(ks)
+        b.start_dev = st.data_ptr()
+        b.evals, b.relres = _dptr(ev), _dptr(rr)
+        b.iters = its.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        b.evecs_dev = vec.data_ptr() if vec is not None else None
+        outs.append((ev, rr, its, vec))
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    rc = lib.bl_batch_solve(ctypes.byref(o), arr, len(problems), int(max_slots), ctypes.c_void_p(stream.cuda_stream))
+    if rc not in (native.BL_OK, native.BL_ENOCONV, native.BL_EINVAL, native.BL_ENOMEM):
+        check(rc, "bl_batch_solve")
+    res = []
+    for i, (ev, rr, its, vec) in enumerate(outs):
+        res.append({"evals": ev, "relres": rr, "iterations": its, "status": int(arr[i].status),
+                    "converged": arr[i].status == 0, "evecs": vec})
+    return res
+
+
+class Server:
+    """bl_server_*: asynchronous requests with footprint admission and continuous batching.
+    Keyword options as for Solver (nev/nthrow come with each request)."""
+
+    def __init__(self, hbm_budget=0, max_slots=0, **opts):
+        self.lib = native.load()
+        o = _make_opts(**opts)
+        h = ctypes.c_void_p()
+        check(self.lib.bl_server_create(ctypes.byref(o), int(hbm_budget), int(max_slots), ctypes.byref(h)),
+              "bl_server_create")
+        self.h = h
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.bl_server_destroy(self.h)
+            self.h = None
+            self._keep = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def submit(self, n, m, a, b, eps, nev, nthrow, ks, start) -> int:
+        """Queue a request; returns its ticket.  The start block is kept alive until polled."""
+        eps = np.ascontiguousarray(eps, dtype=np.float64)
+        ks = np.ascontiguousarray(ks, dtype=np.float64).reshape(-1, 2)
+        st = _start_block(start, int(nev) + int(nthrow), 2 * int(n) * int(m))
+        r = BlRequest()
+        r.grid = BlGrid(int(n), int(m), float(a), float(b))
+        r.eps = _dptr(eps)
+        r.nev, r.nthrow, r.nk = int(nev), int(nthrow), ks.shape[0]
+        r.ks = _dptr(ks)
+        r.start_dev = st.data_ptr()
+        _torch().cuda.current_stream().synchronize()   # the server reads it on its own stream
+        t = ctypes.c_uint64()
+        check(self.lib.bl_server_submit(self.h, ctypes.byref(r), ctypes.byref(t)), "bl_server_submit")
+        self._keep[t.value] = (st, ks.shape[0], int(nev))
+        return t.value
+
+    def poll(self, ticket):
+        """None while the request runs, else a result dict."""
+        st, nk, nev = self._keep[ticket]
+        ev = np.zeros((nk, nev))
+        rr = np.zeros((nk, nev))
+        its = np.zeros(nk, dtype=np.int32)
+        info = BlRequestInfo()
+        rc = self.lib.bl_server_poll(self.h, ctypes.c_uint64(ticket), _dptr(ev), _dptr(rr),
+                                     its.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(info))
+        if rc == native.BL_EAGAIN:
+            return None
+        del self._keep[ticket]
+        if rc not in (native.BL_OK, native.BL_ENOCONV):
+            check(rc, "bl_server_poll")
+        return {"evals": ev, "relres": rr, "iterations": its, "status": int(rc),
+                "converged": rc == 0, "queue_s": info.queue_s, "run_s": info.run_s,
+                "latency_s": info.latency_s, "total_iters": info.total_iters}
+
+    def stats(self) -> dict:
+        c = BlServerCounters()
+        rc = self.lib.bl_server_stats(self.h, ctypes.byref(c))
+        check(rc, "bl_server_stats")
+        return {"rounds": c.rounds, "kernel_launches": c.kernel_launches, "device_bytes": c.device_bytes,
+                "engines": c.engines, "queued": c.queued, "pending": c.pending}
 
 
 class Solver:

@@ -1,0 +1,246 @@
+// C ABI of bloch.h for single problems: a handle is an engine with one slot.
+#include "engine.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace bl {
+const char* last_error_message();
+}
+
+using namespace bl;
+
+namespace {
+
+#define HIP_OK(expr)                                                               \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess) return set_error(BL_EHIP, "HIP error: %s", hipGetErrorString(e_)); \
+  } while (0)
+
+int check_hip() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(BL_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
+  return BL_OK;
+}
+
+// Run one task on slot 0 to the end; outputs stay valid on BL_ENOCONV.
+int run_task(bl_solver* s, Task& t) {
+  int rc = engine_assign(s, 0, &t);
+  if (rc) return rc;
+  rc = engine_run(s);
+  if (rc) return rc;
+  if (t.status != BL_OK) return set_error(t.status, "%s", t.message.c_str());
+  return BL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void bl_default_opts(bl_opts* o, int32_t nev) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->nev = nev > 0 ? nev : 8;
+  o->nthrow = o->nev / 2;
+  o->max_iter = 200;
+  o->levels = 0;
+  o->coarsest_min = 8;
+  o->nu_pre = 1;
+  o->nu_post = 1;
+  o->nodal_cycles = 2;
+  o->variant = 0;
+  o->precision = 0;
+  o->extrap_depth = 3;
+  o->tol = 1e-8;
+  o->mu = 0.0;
+  o->zero_rel = 1e-2;
+}
+
+const char* bl_strerror(int code) {
+  switch (code) {
+    case BL_OK: return "ok";
+    case BL_EINVAL: return "invalid argument";
+    case BL_ENOMEM: return "out of memory";
+    case BL_EHIP: return "HIP runtime error";
+    case BL_ENOCONV: return "not converged";
+    case BL_EAGAIN: return "not ready";
+    case BL_ESTATE: return "invalid state";
+    default: return "unknown error";
+  }
+}
+
+const char* bl_last_error(void) { return last_error_message(); }
+
+size_t bl_footprint_bytes(const bl_grid* grid, const bl_opts* opts) {
+  if (!grid) return 0;
+  bl_opts o;
+  if (opts) o = *opts; else bl_default_opts(&o, 8);
+  fill_defaults(&o);
+  return engine_footprint(grid, &o, 1);
+}
+
+int bl_create(const bl_grid* grid, const double* eps_cells, const bl_opts* opts, void* stream,
+              bl_solver** out) {
+  if (!eps_cells) return set_error(BL_EINVAL, "eps is NULL%s");
+  return engine_create(grid, opts, 1, static_cast<hipStream_t>(stream), eps_cells, out);
+}
+
+void bl_destroy(bl_solver* s) { engine_destroy(s); }
+
+int bl_get_info(const bl_solver* s, bl_info* out) {
+  if (!s || !out) return set_error(BL_EINVAL, "NULL argument%s");
+  std::memset(out, 0, sizeof(*out));
+  out->n = s->grid.n;
+  out->m = s->grid.m;
+  out->p = s->p;
+  out->nev = s->opts.nev;
+  out->levels = (int)s->lv.size();
+  out->precision = s->opts.precision;
+  for (size_t l = 0; l < s->lv.size() && l < 16; ++l) {
+    out->level_n[l] = s->lv[l].g.n;
+    out->level_m[l] = s->lv[l].g.m;
+  }
+  out->mu = s->mu_h.empty() ? 0.0 : s->mu_h[0];
+  out->device_bytes = s->dev_bytes;
+  out->kernel_launches = s->launches;
+  return BL_OK;
+}
+
+int bl_solve_k(bl_solver* s, double k1, double k2, const void* start_dev, double* evals,
+               double* relres, int32_t* iters, void* evecs_dev) {
+  if (!s) return set_error(BL_EINVAL, "solver is NULL%s");
+  Task t;
+  t.ks = {k1, k2};
+  t.start_dev = start_dev;
+  t.nev = s->opts.nev;
+  t.evecs_dev = evecs_dev;
+  const int rc = run_task(s, t);
+  if (rc != BL_OK && rc != BL_ENOCONV) return rc;
+  const int nev = s->opts.nev;
+  if (evals) std::memcpy(evals, t.evals.data(), (size_t)nev * 8);
+  if (relres) std::memcpy(relres, t.relres.data(), (size_t)nev * 8);
+  if (iters) *iters = t.iters[0];
+  return rc;
+}
+
+int bl_solve_path(bl_solver* s, const double* ks, int32_t nk, const void* start_dev,
+                  double* evals, double* relres, int32_t* iters, void* evecs_last_dev) {
+  if (!s || !ks || nk < 1) return set_error(BL_EINVAL, "invalid path arguments%s");
+  Task t;
+  t.ks.assign(ks, ks + 2 * (size_t)nk);
+  t.start_dev = start_dev;
+  t.nev = s->opts.nev;
+  t.evecs_dev = evecs_last_dev;
+  const int rc = run_task(s, t);
+  if (rc != BL_OK && rc != BL_ENOCONV) return rc;
+  const size_t cnt = (size_t)nk * s->opts.nev;
+  if (evals) std::memcpy(evals, t.evals.data(), cnt * 8);
+  if (relres) std::memcpy(relres, t.relres.data(), cnt * 8);
+  if (iters) std::memcpy(iters, t.iters.data(), (size_t)nk * 4);
+  return rc;
+}
+
+int bl_reset_history(bl_solver* s) {
+  if (!s) return set_error(BL_EINVAL, "solver is NULL%s");
+  for (auto& ss : s->slot) ss.hist_count = 0;
+  return BL_OK;
+}
+
+int bl_last_residual_history(const bl_solver* s, double* relres, int32_t cap) {
+  if (!s || !relres) return set_error(BL_EINVAL, "NULL argument%s");
+  const int nev = s->opts.nev;
+  const int rows = std::min(cap, s->last_res_rows);
+  std::memcpy(relres, s->last_res_hist.data(), (size_t)rows * nev * 8);
+  return rows;
+}
+
+int bl_set_timing(bl_solver* s, int32_t enable) {
+  if (!s) return set_error(BL_EINVAL, "solver is NULL%s");
+  if (enable && s->ev_pool.empty()) {
+    s->ev_pool.resize(4096);
+    for (auto& e : s->ev_pool) HIP_OK(hipEventCreate(&e));
+  }
+  s->timing = enable != 0;
+  s->timed_ms = 0.0;
+  s->timed_count = 0;
+  s->timed_cols = 0;
+  s->ev_used = 0;
+  return BL_OK;
+}
+
+int bl_get_timing(const bl_solver* s, double* total_ms, int64_t* launches, int64_t* columns) {
+  if (!s || !total_ms || !launches || !columns) return set_error(BL_EINVAL, "NULL argument%s");
+  *total_ms = s->timed_ms;
+  *launches = s->timed_count;
+  *columns = s->timed_cols;
+  return BL_OK;
+}
+
+int bl_set_k(bl_solver* s, double k1, double k2) {
+  if (!s) return set_error(BL_EINVAL, "solver is NULL%s");
+  return engine_set_k0(s, k1, k2);
+}
+
+int bl_apply(bl_solver* s, int32_t op, int32_t level, int32_t prec, int32_t ncols, const void* x,
+             const void* y, void* out) {
+  if (!s || !x || !out || ncols < 1) return set_error(BL_EINVAL, "invalid apply arguments%s");
+  return engine_apply(s, op, level, prec, ncols, x, y, out);
+}
+
+int bl_gram(bl_solver* s, const void* X, int32_t q, const void* W, int32_t r, int64_t len,
+            double* out) {
+  if (!s || !X || !W || !out || q < 1 || r < 1 || len < 1) return set_error(BL_EINVAL, "invalid gram arguments%s");
+  double *part = nullptr, *res = nullptr;
+  const int64_t cap = (int64_t)gram_blocks(len) * q * r * 2;
+  HIP_OK(hipMalloc(&part, cap * 8));
+  HIP_OK(hipMalloc(&res, (size_t)q * r * 2 * 8));
+  const Launch L{nullptr, 1, 0, s->st};
+  gram(View<const double>{static_cast<const double*>(X), q, 0}, q, View<const double>{static_cast<const double*>(W), r, 0}, r,
+       len, part, cap, res, L);
+  hipError_t e = hipMemcpyAsync(out, res, (size_t)q * r * 2 * 8, hipMemcpyDeviceToHost, s->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  (void)hipFree(part);
+  (void)hipFree(res);
+  if (e != hipSuccess) return set_error(BL_EHIP, "HIP error: %s", hipGetErrorString(e));
+  return check_hip();
+}
+
+int bl_ritz_small(bl_solver* s, const double* G, const double* H, int32_t q, int32_t want,
+                  double zero_thr, double* theta, double* Y) {
+  if (!s || !G || !H || !theta || !Y || q < 1 || q > 255 || want < 1 || want > q)
+    return set_error(BL_EINVAL, "invalid ritz arguments%s");
+  double *dG, *dH, *dW, *dY, *dT, *dZ;
+  int* dc;
+  const size_t m2 = (size_t)q * q * 2 * 8;
+  HIP_OK(hipMalloc(&dG, m2));
+  HIP_OK(hipMalloc(&dH, m2));
+  HIP_OK(hipMalloc(&dW, ritz_small_work_doubles(q) * 8));
+  HIP_OK(hipMalloc(&dY, (size_t)q * want * 2 * 8));
+  HIP_OK(hipMalloc(&dT, (size_t)want * 8));
+  HIP_OK(hipMalloc(&dZ, 8));
+  HIP_OK(hipMalloc(&dc, sizeof(int)));
+  HIP_OK(hipMemcpyAsync(dG, G, m2, hipMemcpyHostToDevice, s->st));
+  HIP_OK(hipMemcpyAsync(dH, H, m2, hipMemcpyHostToDevice, s->st));
+  HIP_OK(hipMemcpyAsync(dZ, &zero_thr, 8, hipMemcpyHostToDevice, s->st));
+  const Launch L{nullptr, 1, 0, s->st};
+  ritz_small(dG, dH, q, 0, want, dZ, 1e-10, dW, 0, dY, dT, dc, L);
+  int cnt = 0;
+  hipError_t e = hipMemcpyAsync(Y, dY, (size_t)q * want * 2 * 8, hipMemcpyDeviceToHost, s->st);
+  if (e == hipSuccess) e = hipMemcpyAsync(theta, dT, (size_t)want * 8, hipMemcpyDeviceToHost, s->st);
+  if (e == hipSuccess) e = hipMemcpyAsync(&cnt, dc, sizeof(int), hipMemcpyDeviceToHost, s->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  (void)hipFree(dG);
+  (void)hipFree(dH);
+  (void)hipFree(dW);
+  (void)hipFree(dY);
+  (void)hipFree(dT);
+  (void)hipFree(dZ);
+  (void)hipFree(dc);
+  if (e != hipSuccess) return set_error(BL_EHIP, "HIP error: %s", hipGetErrorString(e));
+  int rc = check_hip();
+  return rc ? rc : cnt;
+}
+
+}  // extern "C"

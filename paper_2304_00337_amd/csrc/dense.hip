@@ -31,31 +31,40 @@ void identity_block(double* out, int64_t n, hipStream_t st) {
   k_identity_block<<<grid, 256, 0, st>>>(out, n);
 }
 
-// mat (row-major interleaved) [i][j] = column j of the probe result at row i
-__global__ void k_planar_to_matrix(const double* __restrict__ cols, int64_t n, double* __restrict__ mat) {
+// mat_s (row-major interleaved) [i][j] = column j of slot s's probe result at row i
+__global__ void k_planar_to_matrix(const double* __restrict__ cols, int64_t n, double* __restrict__ mat,
+                                   const int* __restrict__ slots) {
   const int64_t j = blockIdx.y;
+  const int64_t s = slots ? slots[blockIdx.z] : blockIdx.z;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  mat[2 * (i * n + j)] = cols[j * 2 * n + i];
-  mat[2 * (i * n + j) + 1] = cols[j * 2 * n + n + i];
+  const double* c = cols + s * n * 2 * n;
+  double* o = mat + s * n * n * 2;
+  o[2 * (i * n + j)] = c[j * 2 * n + i];
+  o[2 * (i * n + j) + 1] = c[j * 2 * n + n + i];
 }
-void planar_to_matrix(const double* cols, int64_t n, double* mat, hipStream_t st) {
-  dim3 grid((unsigned)((n + 255) / 256), (unsigned)n);
-  k_planar_to_matrix<<<grid, 256, 0, st>>>(cols, n, mat);
+void planar_to_matrix(const double* cols, int64_t n, double* mat, const Launch& L) {
+  if (L.nact <= 0) return;
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)n, (unsigned)L.nact);
+  k_planar_to_matrix<<<grid, 256, 0, L.st>>>(cols, n, mat, L.slots);
 }
 
-__global__ void k_add_rank_one(double* __restrict__ mat, int64_t n, double gamma) {
+__global__ void k_add_rank_one(double* __restrict__ mat, int64_t n, double gamma, const int* __restrict__ slots) {
+  const int64_t s = slots ? slots[blockIdx.y] : blockIdx.y;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < n * n) mat[2 * e] += gamma / (double)n;
+  if (e < n * n) mat[s * n * n * 2 + 2 * e] += gamma / (double)n;
 }
-void add_constant_rank_one(double* mat, int64_t n, double gamma, hipStream_t st) {
-  k_add_rank_one<<<(unsigned)((n * n + 255) / 256), 256, 0, st>>>(mat, n, gamma);
+void add_constant_rank_one(double* mat, int64_t n, double gamma, const Launch& L) {
+  if (L.nact <= 0) return;
+  k_add_rank_one<<<dim3((unsigned)((n * n + 255) / 256), (unsigned)L.nact), 256, 0, L.st>>>(mat, n, gamma, L.slots);
 }
 
-// In-place Gauss-Jordan inversion of a Hermitian positive definite matrix (no pivoting).
-__global__ __launch_bounds__(1024) void k_invert(c2* __restrict__ A, int n) {
+// In-place Gauss-Jordan inversion of a Hermitian positive definite matrix (no pivoting),
+// one workgroup per slot.
+__global__ __launch_bounds__(1024) void k_invert(c2* __restrict__ A, int n, const int* __restrict__ slots) {
   extern __shared__ c2 colk[];
   __shared__ c2 piv;
+  A += (int64_t)(slots ? slots[blockIdx.x] : (int)blockIdx.x) * n * n;
   for (int k = 0; k < n; ++k) {
     if (threadIdx.x == 0) {
       const c2 a = A[(int64_t)k * n + k];
@@ -85,55 +94,66 @@ __global__ __launch_bounds__(1024) void k_invert(c2* __restrict__ A, int n) {
     __syncthreads();
   }
 }
-void invert_hpd(double* mat, int64_t n, hipStream_t st) {
-  k_invert<<<1, 1024, (size_t)n * sizeof(c2), st>>>(reinterpret_cast<c2*>(mat), (int)n);
+void invert_hpd(double* mat, int64_t n, const Launch& L) {
+  if (L.nact <= 0) return;
+  k_invert<<<L.nact, 1024, (size_t)n * sizeof(c2), L.st>>>(reinterpret_cast<c2*>(mat), (int)n, L.slots);
 }
 
-__global__ void k_mat_to_float(const double* __restrict__ in, float* __restrict__ out, int64_t count) {
+__global__ void k_mat_to_float(const double* __restrict__ in, float* __restrict__ out, int64_t count,
+                               const int* __restrict__ slots) {
+  const int64_t s = slots ? slots[blockIdx.y] : blockIdx.y;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) out[i] = (float)in[i];
+  if (i < count) out[s * count + i] = (float)in[s * count + i];
 }
-void matrix_to_float(const double* mat, float* out, int64_t count, hipStream_t st) {
-  k_mat_to_float<<<(unsigned)((count + 255) / 256), 256, 0, st>>>(mat, out, count);
+void matrix_to_float(const double* mat, float* out, int64_t count, const Launch& L) {
+  if (L.nact <= 0) return;
+  k_mat_to_float<<<dim3((unsigned)((count + 255) / 256), (unsigned)L.nact), 256, 0, L.st>>>(mat, out, count, L.slots);
 }
 
-// x = Inv b for a Hermitian Inv (row-major interleaved); row i of Inv is read as the
+// x = Inv_s b for a Hermitian Inv_s (row-major interleaved); row i of Inv_s is read as the
 // conjugate of column i, so that consecutive threads read consecutive entries.
 template <typename T>
-__global__ __launch_bounds__(256) void k_dense_apply(const T* __restrict__ inv, int64_t n,
-                                                     const T* __restrict__ b, T* __restrict__ x) {
-  const int col = blockIdx.y;
+__global__ __launch_bounds__(256) void k_dense_apply(const T* __restrict__ inv, int64_t n, View<const T> bv,
+                                                     View<T> xv, const int* __restrict__ slots, int ncps) {
+  const int si = (int)blockIdx.y / ncps;
+  const int slot = slots ? slots[si] : si, col = (int)blockIdx.y % ncps;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const T* bc = b + (int64_t)col * 2 * n;
-  T sr = 0, si = 0;
+  inv += (int64_t)slot * n * n * 2;
+  const T* bc = bv.p + ((int64_t)slot * bv.cps + bv.off + col) * 2 * n;
+  T sr = 0, si_ = 0;
   for (int64_t l = 0; l < n; ++l) {
     const T ar = inv[2 * (l * n + i)], ai = -inv[2 * (l * n + i) + 1];
     const T br = bc[l], bi = bc[n + l];
     sr += ar * br - ai * bi;
-    si += ar * bi + ai * br;
+    si_ += ar * bi + ai * br;
   }
-  T* xc = x + (int64_t)col * 2 * n;
+  T* xc = xv.p + ((int64_t)slot * xv.cps + xv.off + col) * 2 * n;
   xc[i] = sr;
-  xc[n + i] = si;
+  xc[n + i] = si_;
 }
 template <typename T>
-void dense_apply(const void* inv, int64_t n, const T* b, T* x, int ncols, hipStream_t st) {
-  dim3 grid((unsigned)((n + 255) / 256), (unsigned)ncols);
-  k_dense_apply<T><<<grid, 256, 0, st>>>(reinterpret_cast<const T*>(inv), n, b, x);
+void dense_apply(const void* inv, int64_t n, View<const T> b, View<T> x, const Launch& L) {
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)(L.nact * L.ncps));
+  if (grid.y == 0) return;
+  k_dense_apply<T><<<grid, 256, 0, L.st>>>(reinterpret_cast<const T*>(inv), n, b, x, L.slots, L.ncps);
 }
-template void dense_apply<double>(const void*, int64_t, const double*, double*, int, hipStream_t);
-template void dense_apply<float>(const void*, int64_t, const float*, float*, int, hipStream_t);
+template void dense_apply<double>(const void*, int64_t, View<const double>, View<double>, const Launch&);
+template void dense_apply<float>(const void*, int64_t, View<const float>, View<float>, const Launch&);
 
 // ------------------------------------------------------------------------------------------
 // Gram products.  Block (16 x 16 threads) computes a 64 x 64 tile of X^* W over a range of
 // rows; rows are staged through LDS 16 at a time; each thread owns a 4 x 4 register tile.
 constexpr int GB = 64, GTR = 16;
 
-__global__ __launch_bounds__(256) void k_gram(const double* __restrict__ X, int q,
-                                              const double* __restrict__ W, int r, int64_t len,
-                                              int64_t rows_per_blk, double* __restrict__ partial) {
+__global__ __launch_bounds__(256) void k_gram(View<const double> Xv, int q, View<const double> Wv, int r,
+                                              int64_t len, int64_t rows_per_blk,
+                                              double* __restrict__ partial,
+                                              const int* __restrict__ slots) {
   __shared__ double xr[GTR][GB], xi[GTR][GB], wr[GTR][GB], wi[GTR][GB];
+  const int slot = slots ? slots[blockIdx.z] : (int)blockIdx.z;
+  const double* X = Xv.p + ((int64_t)slot * Xv.cps + Xv.off) * 2 * len;
+  const double* W = Wv.p + ((int64_t)slot * Wv.cps + Wv.off) * 2 * len;
   const int ntj = (r + GB - 1) / GB;
   const int i0 = (blockIdx.y / ntj) * GB, j0 = (blockIdx.y % ntj) * GB;
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
@@ -173,7 +193,7 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ X, int 
     }
     __syncthreads();
   }
-  double* pp = partial + (int64_t)blockIdx.x * q * r * 2;
+  double* pp = partial + ((int64_t)blockIdx.z * gridDim.x + blockIdx.x) * q * r * 2;
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -186,43 +206,56 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ X, int 
     }
 }
 
+// out_s = sum over the row blocks of the launch entry z (slot s = slots[z]) in block order
 __global__ void k_gram_reduce(const double* __restrict__ partial, int nblk, int64_t count,
-                              double* __restrict__ out) {
+                              double* __restrict__ out, const int* __restrict__ slots) {
+  const int z = blockIdx.y;
+  const int64_t slot = slots ? slots[z] : z;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= count) return;
+  const double* p = partial + (int64_t)z * nblk * count;
   double s = 0;
-  for (int b = 0; b < nblk; ++b) s += partial[(int64_t)b * count + e];
-  out[e] = s;
+  for (int b = 0; b < nblk; ++b) s += p[(int64_t)b * count + e];
+  out[slot * count + e] = s;
 }
 
+// Row blocks of one Gram product: a function of the vector length only, so that a slot's
+// sums do not depend on which other slots share the launch.
 int gram_blocks(int64_t len) {
   int64_t nb = (len + 1023) / 1024;
   if (nb > 256) nb = 256;
   if (nb < 1) nb = 1;
-  return (int)nb;
-}
-
-void gram(const double* X, int q, const double* W, int r, int64_t len, double* partial,
-          int64_t partial_cap, double* out, hipStream_t st) {
-  int nb = gram_blocks(len);
-  while ((int64_t)nb * q * r * 2 > partial_cap && nb > 1) nb /= 2;
   int64_t rpb = (len + nb - 1) / nb;
   rpb = (rpb + GTR - 1) / GTR * GTR;
-  nb = (int)((len + rpb - 1) / rpb);
+  return (int)((len + rpb - 1) / rpb);
+}
+
+int gram(View<const double> X, int q, View<const double> W, int r, int64_t len, double* partial,
+         int64_t partial_cap, double* out, const Launch& L) {
+  if (L.nact <= 0) return 0;
+  const int nb = gram_blocks(len);
+  if ((int64_t)nb * q * r * 2 * L.nact > partial_cap) return -1;
+  int64_t rpb = (len + nb - 1) / nb;
+  rpb = (rpb + GTR - 1) / GTR * GTR;
   const int nti = (q + GB - 1) / GB, ntj = (r + GB - 1) / GB;
-  dim3 grid((unsigned)nb, (unsigned)(nti * ntj));
-  k_gram<<<grid, 256, 0, st>>>(X, q, W, r, len, rpb, partial);
+  dim3 grid((unsigned)nb, (unsigned)(nti * ntj), (unsigned)L.nact);
+  k_gram<<<grid, 256, 0, L.st>>>(X, q, W, r, len, rpb, partial, L.slots);
   const int64_t count = (int64_t)q * r * 2;
-  k_gram_reduce<<<(unsigned)((count + 255) / 256), 256, 0, st>>>(partial, nb, count, out);
+  k_gram_reduce<<<dim3((unsigned)((count + 255) / 256), (unsigned)L.nact), 256, 0, L.st>>>(partial, nb, count, out, L.slots);
+  return 0;
 }
 
 // ------------------------------------------------------------------------------------------
-// out[:, j] = sum_l S[:, l] Y[l][j]; thread per row, 8 output columns per block row.
+// out_s[:, j] = sum_l S_s[:, l] Y_s[l][j]; thread per row, 8 output columns per block row.
 constexpr int CB = 8;
-__global__ __launch_bounds__(256) void k_block_combine(const double* __restrict__ S, int q,
+__global__ __launch_bounds__(256) void k_block_combine(View<const double> Sv, int q,
                                                        const c2* __restrict__ Y, int want, int64_t len,
-                                                       double* __restrict__ out) {
+                                                       View<double> ov, const int* __restrict__ slots) {
   extern __shared__ c2 ys[];   // q x CB
+  const int slot = slots ? slots[blockIdx.z] : (int)blockIdx.z;
+  const double* S = Sv.p + ((int64_t)slot * Sv.cps + Sv.off) * 2 * len;
+  double* out = ov.p + ((int64_t)slot * ov.cps + ov.off) * 2 * len;
+  Y += (int64_t)slot * q * want;
   const int j0 = blockIdx.y * CB;
   for (int e = threadIdx.x; e < q * CB; e += blockDim.x) {
     const int l = e / CB, c = e % CB;
@@ -252,11 +285,12 @@ __global__ __launch_bounds__(256) void k_block_combine(const double* __restrict_
   }
 }
 
-void block_combine(const double* S, int q, const double* Y, int want, int64_t len, double* out,
-                   hipStream_t st) {
-  dim3 grid((unsigned)((len + 255) / 256), (unsigned)((want + CB - 1) / CB));
-  k_block_combine<<<grid, 256, (size_t)q * CB * sizeof(c2), st>>>(S, q, reinterpret_cast<const c2*>(Y),
-                                                                   want, len, out);
+void block_combine(View<const double> S, int q, const double* Y, int want, int64_t len,
+                   View<double> out, const Launch& L) {
+  if (L.nact <= 0) return;
+  dim3 grid((unsigned)((len + 255) / 256), (unsigned)((want + CB - 1) / CB), (unsigned)L.nact);
+  k_block_combine<<<grid, 256, (size_t)q * CB * sizeof(c2), L.st>>>(S, q, reinterpret_cast<const c2*>(Y),
+                                                                    want, len, out, L.slots);
 }
 
 }  // namespace bl

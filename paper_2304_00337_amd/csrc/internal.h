@@ -36,79 +36,115 @@ struct NodalStencil {
 
 enum EdgeMode { EM_A = 0, EM_M = 1, EM_K = 2, EM_RESID_K = 3, EM_EIGRES = 4 };
 
-// ---- launch wrappers (all asynchronous on `st`) ------------------------------------------
-// out = op(x) for `ncols` columns; EM_RESID_K: out = b - (A + mu M) x;
-// EM_EIGRES: out = A x - lam[j] M x, and norms_partial[j][blk] = (|out|^2, |M x|^2).
+// Batched launches.  A solver holds `slots` independent problems of one grid shape; slot s
+// has its own Bloch phases (ph[s]), shift mu (mu[s], device), permittivity (kappa and patch
+// factors at offset s * nm of every level) and coarse inverses.  A launch covers `nact` slots (the device list `slots`,
+// or slots 0..nact-1 when it is null) and `ncps` columns per slot: grid.y = nact * ncps.
+struct Launch {
+  const int* slots;
+  int nact;
+  int ncps;
+  hipStream_t st;
+};
+// Columns of a slot-major buffer: column j of slot s is at base + (s * cps + off + j) * 2N.
+template <typename T>
+struct View {
+  T* p;
+  int cps;
+  int off;
+};
+template <typename T>
+inline View<T> view(T* p, int cps, int off = 0) { return View<T>{p, cps, off}; }
+template <typename T>
+inline View<const T> cview(const T* p, int cps, int off = 0) { return View<const T>{p, cps, off}; }
+
+// ---- launch wrappers (all asynchronous on L.st) --------------------------------------------
+// out = op(x); EM_RESID_K: out = b - (A + mu M) x; EM_EIGRES: out = A x - lam M x with lam of
+// the column at lam[s * lam_cps + j], and partial[(y * nblk + block) * 2 + {0,1}] =
+// (|out|^2, |M x|^2) block sums, y = the launch column index blockIdx.y.
 template <typename TI, typename TO>
-void edge_apply(int mode, const TI* x, const TI* b, TO* out, const double* kappa64,
-                const float* kappa32, const double* lam, const Geo& g, const Phase& ph,
-                double mu, int ncols, double* norms_partial, int* nblk_out, hipStream_t st);
+void edge_apply(int mode, View<const TI> x, View<const TI> b, View<TO> out, const double* kappa64,
+                const float* kappa32, const double* lam, int lam_cps, const Geo& g,
+                const Phase* ph, const double* mu, const Launch& L, double* partial, int* nblk_out);
 void reduce_partials(const double* partial, int nblk, int ncols, int nval, double* out,
                      hipStream_t st);
 
 template <typename T>
-void edge_gs(T* x, const T* b, const double* kappa64, const float* kappa32,
-             const double* sinv64, const float* sinv32, const Geo& g, const Phase& ph,
-             double mu, const PatchT& T4, int colour, int ncols, hipStream_t st);
-void patch_setup(const double* kappa, const Geo& g, const PatchT& T4, const double* q,
-                 double mu, double* sinv64, float* sinv32, hipStream_t st);
-void coarsen_kappa(const double* kf, const Geo& gf, double* kc, hipStream_t st);
+void edge_gs(View<T> x, View<const T> b, const double* kappa64, const float* kappa32,
+             const double* sinv64, const float* sinv32, const Geo& g, const Phase* ph,
+             const double* mu, const PatchT& T4, int colour, const Launch& L);
+void patch_setup(const double* kappa, const Geo& g, const double* q, const double* mu, double* sinv64,
+                 float* sinv32, int nslots, hipStream_t st);
+void coarsen_kappa(const double* kf, const Geo& gf, double* kc, int nslots, hipStream_t st);
 void to_float(const double* in, float* out, int64_t count, hipStream_t st);
 
 template <typename T>
-void edge_restrict(const T* rf, const Geo& gf, T* bc, const Geo& gc, const Phase& ph,
-                   int ncols, hipStream_t st);
+void edge_restrict(View<const T> rf, const Geo& gf, View<T> bc, const Geo& gc, const Phase* ph,
+                   const Launch& L);
 template <typename T>
-void edge_prolong_add(const T* xc, const Geo& gc, T* xf, const Geo& gf, const Phase& ph,
-                      int ncols, hipStream_t st);
+void edge_prolong_add(View<const T> xc, const Geo& gc, View<T> xf, const Geo& gf,
+                      const Phase* ph, const Launch& L);
 
 template <typename T>
-void nodal_apply(const T* x, const T* b, T* out, const Geo& g, const Phase& ph,
-                 const NodalStencil& c, bool resid, int ncols, hipStream_t st);
+void nodal_apply(View<const T> x, View<const T> b, View<T> out, const Geo& g, const Phase* ph,
+                 const NodalStencil& c, bool resid, const Launch& L);
 template <typename T>
-void nodal_gs(T* x, const T* b, const Geo& g, const Phase& ph, const NodalStencil& c,
-              int colour, int ncols, hipStream_t st);
+void nodal_gs(View<T> x, View<const T> b, const Geo& g, const Phase* ph, const NodalStencil& c,
+              int colour, const Launch& L);
 template <typename T>
-void nodal_restrict(const T* rf, const Geo& gf, T* bc, const Geo& gc, const Phase& ph,
-                    int ncols, hipStream_t st);
+void nodal_restrict(View<const T> rf, const Geo& gf, View<T> bc, const Geo& gc, const Phase* ph,
+                    const Launch& L);
 template <typename T>
-void nodal_prolong_add(const T* xc, const Geo& gc, T* xf, const Geo& gf, const Phase& ph,
-                       int ncols, hipStream_t st);
+void nodal_prolong_add(View<const T> xc, const Geo& gc, View<T> xf, const Geo& gf,
+                       const Phase* ph, const Launch& L);
 template <typename TI, typename TO>
-void lhm(const TI* u, TO* out, const Geo& g, const Phase& ph, int ncols, hipStream_t st);
+void lhm(View<const TI> u, View<TO> out, const Geo& g, const Phase* ph, const Launch& L);
 template <typename TI, typename TP, typename TO>
-void lift_sub(const TI* u, const TP* phi, TO* out, const Geo& g, const Phase& ph, int ncols,
-              hipStream_t st);
+void lift_sub(View<const TI> u, View<const TP> phi, View<TO> out, const Geo& g, const Phase* ph,
+              const Launch& L);
 template <typename TI, typename TO>
-void lift(const TI* phi, TO* out, const Geo& g, const Phase& ph, int ncols, hipStream_t st);
-void gamma_deflate(double* u, const Geo& g, int ncols, double* scratch, hipStream_t st);
+void lift(View<const TI> phi, View<TO> out, const Geo& g, const Phase* ph, const Launch& L);
+// k = 0 deflation of the constant edge fields on the launch's columns of u.
+void gamma_deflate(View<double> u, const Geo& g, double* scratch, const Launch& L);
+template <typename T>
+void axpy(View<T> y, View<const T> x, int64_t len, const Launch& L);
 
 template <typename T>
 void fill_zero(T* p, int64_t count, hipStream_t st);
-void identity_block(double* out, int64_t n, hipStream_t st);
-void planar_to_matrix(const double* cols, int64_t n, double* mat, hipStream_t st);
-void add_constant_rank_one(double* mat, int64_t n, double gamma, hipStream_t st);
-void invert_hpd(double* mat, int64_t n, hipStream_t st);
-void matrix_to_float(const double* mat, float* out, int64_t count, hipStream_t st);
 template <typename T>
-void dense_apply(const void* inv, int64_t n, const T* b, T* x, int ncols, hipStream_t st);
+void zero_cols(View<T> x, int64_t len, const Launch& L);
+// Coarsest-level direct solvers.  Probe columns: n shared unit vectors (identity_block);
+// per slot s the probe results (n columns) at cols + s * n * 2n and the matrices (row-major
+// interleaved complex) at mat + s * n * n * 2.
+void identity_block(double* out, int64_t n, hipStream_t st);
+void planar_to_matrix(const double* cols, int64_t n, double* mat, const Launch& L);
+void add_constant_rank_one(double* mat, int64_t n, double gamma, const Launch& L);
+void invert_hpd(double* mat, int64_t n, const Launch& L);
+// out[s * count + i] = (float) mat[s * count + i] on the launch's slots
+void matrix_to_float(const double* mat, float* out, int64_t count, const Launch& L);
+// x = Inv_s b per column, Inv_s = inv + s * n * n (complex, Hermitian)
+template <typename T>
+void dense_apply(const void* inv, int64_t n, View<const T> b, View<T> x, const Launch& L);
 
-// G (q x r, row-major interleaved complex) = X^* W, X and W planar FP64 blocks of length len.
-void gram(const double* X, int q, const double* W, int r, int64_t len, double* partial,
-          int64_t partial_cap, double* out, hipStream_t st);
+// Per slot: G_s (q x r, row-major interleaved complex, at out + s * q * r * 2) = X_s^* W_s of
+// planar FP64 column views of length len.  Returns -1 (nothing launched) when partial_cap
+// (doubles) is below gram_blocks(len) * q * r * 2 * nact.
+int gram(View<const double> X, int q, View<const double> W, int r, int64_t len, double* partial,
+         int64_t partial_cap, double* out, const Launch& L);
 int gram_blocks(int64_t len);
 
-// Generalised Hermitian eigenproblem H y = theta G y (q x q, row-major interleaved, FP64,
-// device).  The first nfix basis vectors may be declared G-orthonormal and H-diagonal
-// (previous Ritz vectors).  Writes `want` G-orthonormal coefficient vectors (q x want
-// row-major interleaved) to Y, their Ritz values to theta and the count found to *count.
-void ritz_small(const double* G, const double* H, int q, int nfix, int want, double zero_thr,
-                double drop_rel, double* work, double* Y, double* theta, int* count,
-                hipStream_t st);
+// Generalised Hermitian eigenproblem H y = theta G y per slot (q x q, row-major interleaved,
+// FP64, at G/H + s * q * q * 2), one workgroup per slot.  The first nfix basis vectors may
+// be declared G-orthonormal (previous Ritz vectors).  Writes `want` G-orthonormal coefficient
+// vectors (q x want, at Y + s * q * want * 2), their Ritz values (theta + s * want) and the
+// count found (count[s]).  zero_thr per slot (zthr[s]), or -inf when zthr is null.
+void ritz_small(const double* G, const double* H, int q, int nfix, int want, const double* zthr,
+                double drop_rel, double* work, size_t work_stride, double* Y, double* theta,
+                int* count, const Launch& L);
 size_t ritz_small_work_doubles(int q);
 
-// out (planar, want columns) = S (planar, q columns) * Y (q x want, row-major interleaved).
-void block_combine(const double* S, int q, const double* Y, int want, int64_t len, double* out,
-                   hipStream_t st);
+// out_s (want columns) = S_s (q columns) * Y_s (q x want, at Y + s * q * want * 2).
+void block_combine(View<const double> S, int q, const double* Y, int want, int64_t len,
+                   View<double> out, const Launch& L);
 
 }  // namespace bl

@@ -145,10 +145,21 @@ size_t ritz_small_work_doubles(int q) { return (size_t)10 * q * q + 8 * (size_t)
 // LDS layout (when it fits): A (q*q c2) | B (q*q c2) | Z (q*q c2) | T (q*q c2).
 template <bool IN_LDS>
 __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2* __restrict__ H, int q,
-                                             int nfix, int want, double zero_thr, double drop_rel,
-                                             double* __restrict__ work, c2* __restrict__ Y,
-                                             double* __restrict__ theta, int* __restrict__ count) {
+                                             int nfix, int want, const double* __restrict__ zthr,
+                                             double drop_rel, double* __restrict__ work,
+                                             size_t work_stride, c2* __restrict__ Y,
+                                             double* __restrict__ theta, int* __restrict__ count,
+                                             const int* __restrict__ slots) {
   extern __shared__ c2 smem[];
+  // one workgroup per problem slot
+  const int slot = slots ? slots[blockIdx.x] : (int)blockIdx.x;
+  G += (size_t)slot * q * q;
+  H += (size_t)slot * q * q;
+  work += (size_t)slot * work_stride;
+  Y += (size_t)slot * q * want;
+  theta += (size_t)slot * want;
+  count += slot;
+  const double zero_thr = zthr ? zthr[slot] : -INFINITY;
   __shared__ double sh[32];
   __shared__ int rank_s, nsel_s, piv_s, second_s;
   __shared__ double pivv_s;
@@ -544,9 +555,9 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
 
 static int g_cap = -1;
 
-void ritz_small(const double* G, const double* H, int q, int nfix, int want, double zero_thr,
-                double drop_rel, double* work, double* Y, double* theta, int* count,
-                hipStream_t st) {
+void ritz_small(const double* G, const double* H, int q, int nfix, int want, const double* zthr,
+                double drop_rel, double* work, size_t work_stride, double* Y, double* theta,
+                int* count, const Launch& L) {
   if (g_cap < 0) {
     int dev = 0, cap = 65536;
     (void)hipGetDevice(&dev);
@@ -558,15 +569,18 @@ void ritz_small(const double* G, const double* H, int q, int nfix, int want, dou
     g_cap = cap > 0 ? cap : 0;
     if (std::getenv("BL_DEBUG")) std::fprintf(stderr, "bloch: ritz dynamic LDS cap %d bytes\n", g_cap);
   }
+  if (L.nact <= 0) return;
   const size_t idx = (size_t)index_block_c2(q) * sizeof(c2);
   const size_t need = idx + (size_t)4 * q * q * sizeof(c2);
   const int in_lds = need <= (size_t)g_cap ? 1 : 0;
   if (in_lds)
-    k_ritz<true><<<1, RT, need, st>>>(reinterpret_cast<const c2*>(G), reinterpret_cast<const c2*>(H), q,
-                                      nfix, want, zero_thr, drop_rel, work, reinterpret_cast<c2*>(Y), theta, count);
+    k_ritz<true><<<L.nact, RT, need, L.st>>>(reinterpret_cast<const c2*>(G), reinterpret_cast<const c2*>(H), q,
+                                             nfix, want, zthr, drop_rel, work, work_stride,
+                                             reinterpret_cast<c2*>(Y), theta, count, L.slots);
   else
-    k_ritz<false><<<1, RT, idx, st>>>(reinterpret_cast<const c2*>(G), reinterpret_cast<const c2*>(H), q,
-                                      nfix, want, zero_thr, drop_rel, work, reinterpret_cast<c2*>(Y), theta, count);
+    k_ritz<false><<<L.nact, RT, idx, L.st>>>(reinterpret_cast<const c2*>(G), reinterpret_cast<const c2*>(H), q,
+                                             nfix, want, zthr, drop_rel, work, work_stride,
+                                             reinterpret_cast<c2*>(Y), theta, count, L.slots);
 }
 
 }  // namespace bl

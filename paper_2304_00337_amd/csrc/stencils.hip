@@ -71,6 +71,19 @@ __device__ __forceinline__ void add_ext(TS* __restrict__ col, int64_t N, int n, 
 
 __device__ __forceinline__ int wrapi(int j, int n) { return j < 0 ? j + n : (j >= n ? j - n : j); }
 
+// Slot and in-slot column of this block (grid.y = active slots * columns per slot).
+struct SJ {
+  int slot, j;
+};
+__device__ __forceinline__ SJ slot_col(const int* slots, int ncps) {
+  const int si = (int)blockIdx.y / ncps;
+  return {slots ? slots[si] : si, (int)blockIdx.y % ncps};
+}
+template <typename T>
+__device__ __forceinline__ T* colp(View<T> v, SJ s, int64_t N) {
+  return v.p + ((int64_t)s.slot * v.cps + v.off + s.j) * 2 * N;
+}
+
 template <typename T>
 __device__ __forceinline__ T kap(const double* k64, const float* k32, int64_t i);
 template <>
@@ -90,17 +103,22 @@ __device__ __forceinline__ Cx<T> cell_curl(const TS* col, int64_t N, int n, int 
 // Edge operators: A (curl-curl with kappa = 1/eps), M (mass), K = A + mu M and residuals.
 // Thread per (edge, column); T is the arithmetic type (double, or float with float data).
 template <typename TI, typename TO, typename T, int MODE>
-__global__ __launch_bounds__(256) void k_edge_apply(const TI* __restrict__ x, const TI* __restrict__ b,
-                                                    TO* __restrict__ out, const double* __restrict__ k64,
+__global__ __launch_bounds__(256) void k_edge_apply(View<const TI> xv, View<const TI> bv, View<TO> ov,
+                                                    const double* __restrict__ k64,
                                                     const float* __restrict__ k32,
-                                                    const double* __restrict__ lam, Geo g, Phase php,
-                                                    double mud, double* __restrict__ partial) {
-  const int col = blockIdx.y;
+                                                    const double* __restrict__ lam, int lam_cps,
+                                                    Geo g, const Phase* __restrict__ phs,
+                                                    const double* __restrict__ mus,
+                                                    const int* __restrict__ slots, int ncps,
+                                                    double* __restrict__ partial) {
+  const SJ sj = slot_col(slots, ncps);
   const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int n = g.n, m = g.m;
   const int64_t nm = g.nm, N = g.ne;
-  const Ph<T> p = cast_phase<T>(php);
-  const TI* xc = x + (int64_t)col * 2 * N;
+  const Ph<T> p = cast_phase<T>(phs[sj.slot]);
+  const TI* xc = colp(xv, sj, N);
+  k64 += (int64_t)sj.slot * nm;
+  k32 += (int64_t)sj.slot * nm;
   T rr = 0, mm = 0;
   if (d < N) {
     Cx<T> Au, Mu;
@@ -134,16 +152,16 @@ __global__ __launch_bounds__(256) void k_edge_apply(const TI* __restrict__ x, co
     } else if (MODE == EM_M) {
       r = Mu;
     } else if (MODE == EM_K) {
-      r = Au + ((T)mud * Mu);
+      r = Au + ((T)mus[sj.slot] * Mu);
     } else if (MODE == EM_RESID_K) {
-      const TI* bc = b + (int64_t)col * 2 * N;
-      r = Cx<T>{(T)bc[d], (T)bc[N + d]} - (Au + ((T)mud * Mu));
+      const TI* bc = colp(bv, sj, N);
+      r = Cx<T>{(T)bc[d], (T)bc[N + d]} - (Au + ((T)mus[sj.slot] * Mu));
     } else {
-      r = Au - ((T)lam[col] * Mu);
+      r = Au - ((T)lam[(int64_t)sj.slot * lam_cps + sj.j] * Mu);
       rr = r.re * r.re + r.im * r.im;
       mm = Mu.re * Mu.re + Mu.im * Mu.im;
     }
-    TO* oc = out + (int64_t)col * 2 * N;
+    TO* oc = colp(ov, sj, N);
     oc[d] = (TO)r.re;
     oc[N + d] = (TO)r.im;
   }
@@ -161,7 +179,7 @@ __global__ __launch_bounds__(256) void k_edge_apply(const TI* __restrict__ x, co
     if (threadIdx.x == 0) {
       double ta = 0, tc = 0;
       for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { ta += sh[0][w]; tc += sh[1][w]; }
-      double* pp = partial + ((int64_t)col * gridDim.x + blockIdx.x) * 2;
+      double* pp = partial + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * 2;
       pp[0] = ta;
       pp[1] = tc;
     }
@@ -169,25 +187,28 @@ __global__ __launch_bounds__(256) void k_edge_apply(const TI* __restrict__ x, co
 }
 
 template <typename TI, typename TO>
-void edge_apply(int mode, const TI* x, const TI* b, TO* out, const double* kappa64,
-                const float* kappa32, const double* lam, const Geo& g, const Phase& ph,
-                double mu, int ncols, double* norms_partial, int* nblk_out, hipStream_t st) {
+void edge_apply(int mode, View<const TI> x, View<const TI> b, View<TO> out, const double* kappa64,
+                const float* kappa32, const double* lam, int lam_cps, const Geo& g,
+                const Phase* ph, const double* mu, const Launch& L, double* partial, int* nblk_out) {
   using T = typename std::conditional<std::is_same<TI, double>::value, double, float>::type;
   const int bs = 256;
-  dim3 grid((unsigned)((g.ne + bs - 1) / bs), (unsigned)ncols);
+  dim3 grid((unsigned)((g.ne + bs - 1) / bs), (unsigned)(L.nact * L.ncps));
   if (nblk_out) *nblk_out = (int)grid.x;
+  if (grid.y == 0) return;
+#define BL_EA(MD) k_edge_apply<TI, TO, T, MD><<<grid, bs, 0, L.st>>>(x, b, out, kappa64, kappa32, lam, lam_cps, g, ph, mu, L.slots, L.ncps, partial)
   switch (mode) {
-    case EM_A: k_edge_apply<TI, TO, T, EM_A><<<grid, bs, 0, st>>>(x, b, out, kappa64, kappa32, lam, g, ph, mu, norms_partial); break;
-    case EM_M: k_edge_apply<TI, TO, T, EM_M><<<grid, bs, 0, st>>>(x, b, out, kappa64, kappa32, lam, g, ph, mu, norms_partial); break;
-    case EM_K: k_edge_apply<TI, TO, T, EM_K><<<grid, bs, 0, st>>>(x, b, out, kappa64, kappa32, lam, g, ph, mu, norms_partial); break;
-    case EM_RESID_K: k_edge_apply<TI, TO, T, EM_RESID_K><<<grid, bs, 0, st>>>(x, b, out, kappa64, kappa32, lam, g, ph, mu, norms_partial); break;
-    default: k_edge_apply<TI, TO, T, EM_EIGRES><<<grid, bs, 0, st>>>(x, b, out, kappa64, kappa32, lam, g, ph, mu, norms_partial); break;
+    case EM_A: BL_EA(EM_A); break;
+    case EM_M: BL_EA(EM_M); break;
+    case EM_K: BL_EA(EM_K); break;
+    case EM_RESID_K: BL_EA(EM_RESID_K); break;
+    default: BL_EA(EM_EIGRES); break;
   }
+#undef BL_EA
 }
 
-template void edge_apply<double, double>(int, const double*, const double*, double*, const double*, const float*, const double*, const Geo&, const Phase&, double, int, double*, int*, hipStream_t);
-template void edge_apply<double, float>(int, const double*, const double*, float*, const double*, const float*, const double*, const Geo&, const Phase&, double, int, double*, int*, hipStream_t);
-template void edge_apply<float, float>(int, const float*, const float*, float*, const double*, const float*, const double*, const Geo&, const Phase&, double, int, double*, int*, hipStream_t);
+template void edge_apply<double, double>(int, View<const double>, View<const double>, View<double>, const double*, const float*, const double*, int, const Geo&, const Phase*, const double*, const Launch&, double*, int*);
+template void edge_apply<double, float>(int, View<const double>, View<const double>, View<float>, const double*, const float*, const double*, int, const Geo&, const Phase*, const double*, const Launch&, double*, int*);
+template void edge_apply<float, float>(int, View<const float>, View<const float>, View<float>, const double*, const float*, const double*, int, const Geo&, const Phase*, const double*, const Launch&, double*, int*);
 
 // Sum per-block partials: out[j*nval + v] = sum_b partial[(j*nblk + b)*nval + v].
 __global__ void k_reduce_partials(const double* __restrict__ partial, int nblk, int nval,
@@ -211,6 +232,7 @@ __global__ void k_reduce_partials(const double* __restrict__ partial, int nblk, 
 
 void reduce_partials(const double* partial, int nblk, int ncols, int nval, double* out,
                      hipStream_t st) {
+  if (ncols <= 0) return;
   k_reduce_partials<<<ncols, 256, 0, st>>>(partial, nblk, nval, out);
 }
 
@@ -230,22 +252,26 @@ template <>
 __device__ __forceinline__ const float* pick<float>(const double*, const float* b) { return b; }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_edge_gs(T* __restrict__ x, const T* __restrict__ b,
+__global__ __launch_bounds__(256) void k_edge_gs(View<T> xv, View<const T> bv,
                                                  const double* __restrict__ k64,
                                                  const float* __restrict__ k32,
                                                  const double* __restrict__ si64,
-                                                 const float* __restrict__ si32, Geo g, Phase php,
-                                                 double mud, PatchT T4, int colour) {
-  const int col = blockIdx.y;
+                                                 const float* __restrict__ si32, Geo g,
+                                                 const Phase* __restrict__ phs,
+                                                 const double* __restrict__ mus, PatchT T4, int colour, const int* __restrict__ slots,
+                                                 int ncps) {
+  const SJ sj = slot_col(slots, ncps);
   const int n = g.n, m = g.m, nh = n >> 1, mh = m >> 1;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)nh * mh) return;
   const int p1 = 2 * (int)(t % nh) + (colour & 1);
   const int p2 = 2 * (int)(t / nh) + (colour >> 1);
   const int64_t nm = g.nm, N = g.ne;
-  const Ph<T> p = cast_phase<T>(php);
-  T* xc = x + (int64_t)col * 2 * N;
-  const T* bc = b + (int64_t)col * 2 * N;
+  const Ph<T> p = cast_phase<T>(phs[sj.slot]);
+  T* xc = colp(xv, sj, N);
+  const T* bc = colp(bv, sj, N);
+  k64 += (int64_t)sj.slot * nm;
+  k32 += (int64_t)sj.slot * nm;
   const Cx<T> X00 = fetch<T, T>(xc, N, n, m, 0, p1, p2, p);
   const Cx<T> X01 = fetch<T, T>(xc, N, n, m, 0, p1, p2 + 1, p);
   const Cx<T> X0m = fetch<T, T>(xc, N, n, m, 0, p1, p2 - 1, p);
@@ -267,7 +293,7 @@ __global__ __launch_bounds__(256) void k_edge_gs(T* __restrict__ x, const T* __r
   const T knw = kap<T>(k64, k32, (int64_t)p2 * n + p1m);
   const T ksw = kap<T>(k64, k32, (int64_t)p2m * n + p1m);
   const T kse = kap<T>(k64, k32, (int64_t)p2m * n + p1);
-  const T s = (T)g.s, mu = (T)mud;
+  const T s = (T)g.s, mu = (T)mus[sj.slot];
   const T two3 = (T)(2.0 / 3.0), one6 = (T)(1.0 / 6.0);
   const T mmx = mu * (T)g.mx, mmy = mu * (T)g.my;
   Cx<T> r[4];
@@ -288,7 +314,7 @@ __global__ __launch_bounds__(256) void k_edge_gs(T* __restrict__ x, const T* __r
     for (int l = 0; l < 4; ++l) acc = acc + ((T)T4.t[l * 4 + a] * r[l]);
     y[a] = acc;
   }
-  const T* si = pick<T>(si64, si32) + 6 * ((int64_t)p2 * n + p1);
+  const T* si = pick<T>(si64, si32) + 6 * ((int64_t)sj.slot * nm + (int64_t)p2 * n + p1);
   const T s00 = si[0], s01 = si[1], s02 = si[2], s11 = si[3], s12 = si[4], s22 = si[5];
   Cx<T> z[4];
   z[0] = ((T)1 / mu) * y[0];
@@ -310,28 +336,33 @@ __global__ __launch_bounds__(256) void k_edge_gs(T* __restrict__ x, const T* __r
 }
 
 template <typename T>
-void edge_gs(T* x, const T* b, const double* kappa64, const float* kappa32,
-             const double* sinv64, const float* sinv32, const Geo& g, const Phase& ph,
-             double mu, const PatchT& T4, int colour, int ncols, hipStream_t st) {
+void edge_gs(View<T> x, View<const T> b, const double* kappa64, const float* kappa32,
+             const double* sinv64, const float* sinv32, const Geo& g, const Phase* ph,
+             const double* mu, const PatchT& T4, int colour, const Launch& L) {
   const int64_t cnt = (int64_t)(g.n / 2) * (g.m / 2);
-  dim3 grid((unsigned)((cnt + 255) / 256), (unsigned)ncols);
-  k_edge_gs<T><<<grid, 256, 0, st>>>(x, b, kappa64, kappa32, sinv64, sinv32, g, ph, mu, T4, colour);
+  dim3 grid((unsigned)((cnt + 255) / 256), (unsigned)(L.nact * L.ncps));
+  if (grid.y == 0) return;
+  k_edge_gs<T><<<grid, 256, 0, L.st>>>(x, b, kappa64, kappa32, sinv64, sinv32, g, ph, mu, T4, colour, L.slots, L.ncps);
 }
-template void edge_gs<double>(double*, const double*, const double*, const float*, const double*, const float*, const Geo&, const Phase&, double, const PatchT&, int, int, hipStream_t);
-template void edge_gs<float>(float*, const float*, const double*, const float*, const double*, const float*, const Geo&, const Phase&, double, const PatchT&, int, int, hipStream_t);
+template void edge_gs<double>(View<double>, View<const double>, const double*, const float*, const double*, const float*, const Geo&, const Phase*, const double*, const PatchT&, int, const Launch&);
+template void edge_gs<float>(View<float>, View<const float>, const double*, const float*, const double*, const float*, const Geo&, const Phase*, const double*, const PatchT&, int, const Launch&);
 
 // Per-node inverse of the 3x3 block S = (Q'^T D^{-1/2} A_loc D^{-1/2} Q') + mu I of the
 // stabilised patch system, Q' = columns 2..4 of the orthogonal Q (passed row-major in q).
 // A_loc = (1/(h1 h2)) sum over the four cells of kappa_c c_c c_c^T with the cell
 // circulation vectors c over (e0, e1, e2, e3): NE (-1,0,1,0), NW (0,-1,-1,0),
-// SW (0,1,0,-1), SE (1,0,0,1).  Stored as (s00, s01, s02, s11, s12, s22).
+// SW (0,1,0,-1), SE (1,0,0,1).  Stored as (s00, s01, s02, s11, s12, s22).  Thread per
+// (node, slot); kappa and the output are slot-major.
 struct Q16 {
   double q[16];
 };
-__global__ void k_patch_setup(const double* __restrict__ kappa, Geo g, Q16 Q, double mu,
-                              double* __restrict__ s64, float* __restrict__ s32) {
-  const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (node >= g.nm) return;
+__global__ void k_patch_setup(const double* __restrict__ kappa, Geo g, Q16 Q, const double* __restrict__ mus,
+                              double* __restrict__ s64, float* __restrict__ s32, int nslots) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= g.nm * nslots) return;
+  const int64_t slot = gid / g.nm, node = gid % g.nm;
+  kappa += slot * g.nm;
+  const double mu = mus[slot];
   const int n = g.n, m = g.m;
   const int p1 = (int)(node % n), p2 = (int)(node / n);
   const int p1m = wrapi(p1 - 1, n), p2m = wrapi(p2 - 1, m);
@@ -367,32 +398,36 @@ __global__ void k_patch_setup(const double* __restrict__ kappa, Geo g, Q16 Q, do
   const double i22 = (S[0][0] * S[1][1] - S[0][1] * S[1][0]) * id;
   const double out[6] = {i00, i01, i02, i11, i12, i22};
   for (int i = 0; i < 6; ++i) {
-    s64[node * 6 + i] = out[i];
-    s32[node * 6 + i] = (float)out[i];
+    s64[gid * 6 + i] = out[i];
+    s32[gid * 6 + i] = (float)out[i];
   }
 }
 
-void patch_setup(const double* kappa, const Geo& g, const PatchT& T4, const double* q,
-                 double mu, double* sinv64, float* sinv32, hipStream_t st) {
-  (void)T4;
+void patch_setup(const double* kappa, const Geo& g, const double* q, const double* mu, double* sinv64,
+                 float* sinv32, int nslots, hipStream_t st) {
   Q16 Q;
   for (int i = 0; i < 16; ++i) Q.q[i] = q[i];
-  k_patch_setup<<<(unsigned)((g.nm + 255) / 256), 256, 0, st>>>(kappa, g, Q, mu, sinv64, sinv32);
+  const int64_t cnt = g.nm * nslots;
+  k_patch_setup<<<(unsigned)((cnt + 255) / 256), 256, 0, st>>>(kappa, g, Q, mu, sinv64, sinv32, nslots);
 }
 
 // kappa on the next coarser level: mean over the 2x2 children (Galerkin coarse operator
-// of the edge embedding equals rediscretisation with this coefficient).
-__global__ void k_coarsen_kappa(const double* __restrict__ kf, int nf, double* __restrict__ kc,
-                                int nc, int mc) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= (int64_t)nc * mc) return;
+// of the edge embedding equals rediscretisation with this coefficient); slot-major.
+__global__ void k_coarsen_kappa(const double* __restrict__ kf, int nf, int mf, double* __restrict__ kc,
+                                int nc, int mc, int nslots) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t ncm = (int64_t)nc * mc;
+  if (gid >= ncm * nslots) return;
+  const int64_t slot = gid / ncm, c = gid % ncm;
   const int c1 = (int)(c % nc), c2 = (int)(c / nc);
+  const double* k = kf + slot * (int64_t)nf * mf;
   const int64_t f = (int64_t)(2 * c2) * nf + 2 * c1;
-  kc[c] = 0.25 * (kf[f] + kf[f + 1] + kf[f + nf] + kf[f + nf + 1]);
+  kc[gid] = 0.25 * (k[f] + k[f + 1] + k[f + nf] + k[f + nf + 1]);
 }
-void coarsen_kappa(const double* kf, const Geo& gf, double* kc, hipStream_t st) {
+void coarsen_kappa(const double* kf, const Geo& gf, double* kc, int nslots, hipStream_t st) {
   const int nc = gf.n / 2, mc = gf.m / 2;
-  k_coarsen_kappa<<<(unsigned)(((int64_t)nc * mc + 255) / 256), 256, 0, st>>>(kf, gf.n, kc, nc, mc);
+  const int64_t cnt = (int64_t)nc * mc * nslots;
+  k_coarsen_kappa<<<(unsigned)((cnt + 255) / 256), 256, 0, st>>>(kf, gf.n, gf.m, kc, nc, mc, nslots);
 }
 
 __global__ void k_to_float(const double* __restrict__ in, float* __restrict__ out, int64_t count) {
@@ -400,6 +435,7 @@ __global__ void k_to_float(const double* __restrict__ in, float* __restrict__ ou
   if (i < count) out[i] = (float)in[i];
 }
 void to_float(const double* in, float* out, int64_t count, hipStream_t st) {
+  if (count <= 0) return;
   k_to_float<<<(unsigned)((count + 255) / 256), 256, 0, st>>>(in, out, count);
 }
 
@@ -409,13 +445,14 @@ void to_float(const double* in, float* out, int64_t count, hipStream_t st) {
 // parallel fine x-edges half a coarse cell above and below (y-edges alike); the
 // restriction is its adjoint.
 template <typename T>
-__global__ __launch_bounds__(256) void k_edge_restrict(const T* __restrict__ rf, Geo gf,
-                                                       T* __restrict__ bc, Geo gc, Phase php) {
-  const int col = blockIdx.y;
+__global__ __launch_bounds__(256) void k_edge_restrict(View<const T> rv, Geo gf, View<T> bv, Geo gc,
+                                                       const Phase* __restrict__ phs,
+                                                       const int* __restrict__ slots, int ncps) {
+  const SJ sj = slot_col(slots, ncps);
   const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (d >= gc.ne) return;
-  const Ph<T> p = cast_phase<T>(php);
-  const T* r = rf + (int64_t)col * 2 * gf.ne;
+  const Ph<T> p = cast_phase<T>(phs[sj.slot]);
+  const T* r = colp(rv, sj, gf.ne);
   const int nf = gf.n, mf = gf.m;
   const int64_t Nf = gf.ne, nmf = gf.nm;
   const T h = (T)0.5, q = (T)0.25;
@@ -434,19 +471,20 @@ __global__ __launch_bounds__(256) void k_edge_restrict(const T* __restrict__ rf,
         q * (fetch<T, T>(r, Nf, nf, mf, nmf, f1 + 1, f2, p) + fetch<T, T>(r, Nf, nf, mf, nmf, f1 + 1, f2 + 1, p) +
              fetch<T, T>(r, Nf, nf, mf, nmf, f1 - 1, f2, p) + fetch<T, T>(r, Nf, nf, mf, nmf, f1 - 1, f2 + 1, p));
   }
-  T* o = bc + (int64_t)col * 2 * gc.ne;
+  T* o = colp(bv, sj, gc.ne);
   o[d] = v.re;
   o[gc.ne + d] = v.im;
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_edge_prolong_add(const T* __restrict__ xc, Geo gc,
-                                                          T* __restrict__ xf, Geo gf, Phase php) {
-  const int col = blockIdx.y;
+__global__ __launch_bounds__(256) void k_edge_prolong_add(View<const T> cv, Geo gc, View<T> fv, Geo gf,
+                                                          const Phase* __restrict__ phs,
+                                                          const int* __restrict__ slots, int ncps) {
+  const SJ sj = slot_col(slots, ncps);
   const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (d >= gf.ne) return;
-  const Ph<T> p = cast_phase<T>(php);
-  const T* c = xc + (int64_t)col * 2 * gc.ne;
+  const Ph<T> p = cast_phase<T>(phs[sj.slot]);
+  const T* c = colp(cv, sj, gc.ne);
   const int nc = gc.n, mc = gc.m;
   const int64_t Nc = gc.ne, nmc = gc.nm;
   Cx<T> v;
@@ -468,27 +506,29 @@ __global__ __launch_bounds__(256) void k_edge_prolong_add(const T* __restrict__ 
       v = (T)0.25 * (fetch<T, T>(c, Nc, nc, mc, nmc, f1 >> 1, J2, p) + fetch<T, T>(c, Nc, nc, mc, nmc, (f1 >> 1) + 1, J2, p));
     }
   }
-  T* o = xf + (int64_t)col * 2 * gf.ne;
+  T* o = colp(fv, sj, gf.ne);
   o[d] += v.re;
   o[gf.ne + d] += v.im;
 }
 
 template <typename T>
-void edge_restrict(const T* rf, const Geo& gf, T* bc, const Geo& gc, const Phase& ph, int ncols,
-                   hipStream_t st) {
-  dim3 grid((unsigned)((gc.ne + 255) / 256), (unsigned)ncols);
-  k_edge_restrict<T><<<grid, 256, 0, st>>>(rf, gf, bc, gc, ph);
+void edge_restrict(View<const T> rf, const Geo& gf, View<T> bc, const Geo& gc, const Phase* ph,
+                   const Launch& L) {
+  dim3 grid((unsigned)((gc.ne + 255) / 256), (unsigned)(L.nact * L.ncps));
+  if (grid.y == 0) return;
+  k_edge_restrict<T><<<grid, 256, 0, L.st>>>(rf, gf, bc, gc, ph, L.slots, L.ncps);
 }
 template <typename T>
-void edge_prolong_add(const T* xc, const Geo& gc, T* xf, const Geo& gf, const Phase& ph,
-                      int ncols, hipStream_t st) {
-  dim3 grid((unsigned)((gf.ne + 255) / 256), (unsigned)ncols);
-  k_edge_prolong_add<T><<<grid, 256, 0, st>>>(xc, gc, xf, gf, ph);
+void edge_prolong_add(View<const T> xc, const Geo& gc, View<T> xf, const Geo& gf,
+                      const Phase* ph, const Launch& L) {
+  dim3 grid((unsigned)((gf.ne + 255) / 256), (unsigned)(L.nact * L.ncps));
+  if (grid.y == 0) return;
+  k_edge_prolong_add<T><<<grid, 256, 0, L.st>>>(xc, gc, xf, gf, ph, L.slots, L.ncps);
 }
-template void edge_restrict<double>(const double*, const Geo&, double*, const Geo&, const Phase&, int, hipStream_t);
-template void edge_restrict<float>(const float*, const Geo&, float*, const Geo&, const Phase&, int, hipStream_t);
-template void edge_prolong_add<double>(const double*, const Geo&, double*, const Geo&, const Phase&, int, hipStream_t);
-template void edge_prolong_add<float>(const float*, const Geo&, float*, const Geo&, const Phase&, int, hipStream_t);
+template void edge_restrict<double>(View<const double>, const Geo&, View<double>, const Geo&, const Phase*, const Launch&);
+template void edge_restrict<float>(View<const float>, const Geo&, View<float>, const Geo&, const Phase*, const Launch&);
+template void edge_prolong_add<double>(View<const double>, const Geo&, View<double>, const Geo&, const Phase*, const Launch&);
+template void edge_prolong_add<float>(View<const float>, const Geo&, View<float>, const Geo&, const Phase*, const Launch&);
 
 // ------------------------------------------------------------------------------------------
 // Nodal operators.  P = L^* M L is the 9-point Bloch Q1 Laplacian; its coefficients depend
@@ -505,50 +545,53 @@ __device__ __forceinline__ Cx<T> nodal_stencil(const T* c, int64_t N, int n, int
 }
 
 template <typename T, bool RESID>
-__global__ __launch_bounds__(256) void k_nodal_apply(const T* __restrict__ x, const T* __restrict__ b,
-                                                     T* __restrict__ out, Geo g, Phase php,
-                                                     NodalStencil s) {
-  const int col = blockIdx.y;
+__global__ __launch_bounds__(256) void k_nodal_apply(View<const T> xv, View<const T> bv, View<T> ov,
+                                                     Geo g, const Phase* __restrict__ phs,
+                                                     NodalStencil s, const int* __restrict__ slots,
+                                                     int ncps) {
+  const SJ sj = slot_col(slots, ncps);
   const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (d >= g.nm) return;
-  const Ph<T> p = cast_phase<T>(php);
+  const Ph<T> p = cast_phase<T>(phs[sj.slot]);
   const int64_t N = g.nm;
-  const T* xc = x + (int64_t)col * 2 * N;
+  const T* xc = colp(xv, sj, N);
   Cx<T> v = nodal_stencil<T>(xc, N, g.n, g.m, (int)(d % g.n), (int)(d / g.n), s, p);
   if (RESID) {
-    const T* bc = b + (int64_t)col * 2 * N;
+    const T* bc = colp(bv, sj, N);
     v = Cx<T>{bc[d], bc[N + d]} - v;
   }
-  T* o = out + (int64_t)col * 2 * N;
+  T* o = colp(ov, sj, N);
   o[d] = v.re;
   o[N + d] = v.im;
 }
 
 template <typename T>
-void nodal_apply(const T* x, const T* b, T* out, const Geo& g, const Phase& ph,
-                 const NodalStencil& c, bool resid, int ncols, hipStream_t st) {
-  dim3 grid((unsigned)((g.nm + 255) / 256), (unsigned)ncols);
-  if (resid) k_nodal_apply<T, true><<<grid, 256, 0, st>>>(x, b, out, g, ph, c);
-  else k_nodal_apply<T, false><<<grid, 256, 0, st>>>(x, b, out, g, ph, c);
+void nodal_apply(View<const T> x, View<const T> b, View<T> out, const Geo& g, const Phase* ph,
+                 const NodalStencil& c, bool resid, const Launch& L) {
+  dim3 grid((unsigned)((g.nm + 255) / 256), (unsigned)(L.nact * L.ncps));
+  if (grid.y == 0) return;
+  if (resid) k_nodal_apply<T, true><<<grid, 256, 0, L.st>>>(x, b, out, g, ph, c, L.slots, L.ncps);
+  else k_nodal_apply<T, false><<<grid, 256, 0, L.st>>>(x, b, out, g, ph, c, L.slots, L.ncps);
 }
-template void nodal_apply<double>(const double*, const double*, double*, const Geo&, const Phase&, const NodalStencil&, bool, int, hipStream_t);
-template void nodal_apply<float>(const float*, const float*, float*, const Geo&, const Phase&, const NodalStencil&, bool, int, hipStream_t);
+template void nodal_apply<double>(View<const double>, View<const double>, View<double>, const Geo&, const Phase*, const NodalStencil&, bool, const Launch&);
+template void nodal_apply<float>(View<const float>, View<const float>, View<float>, const Geo&, const Phase*, const NodalStencil&, bool, const Launch&);
 
 // Point Gauss-Seidel for P on the nodes of one colour (same-colour nodes are not
 // neighbours of the 9-point stencil).
 template <typename T>
-__global__ __launch_bounds__(256) void k_nodal_gs(T* __restrict__ x, const T* __restrict__ b, Geo g,
-                                                  Phase php, NodalStencil s, int colour) {
-  const int col = blockIdx.y;
+__global__ __launch_bounds__(256) void k_nodal_gs(View<T> xv, View<const T> bv, Geo g,
+                                                  const Phase* __restrict__ phs, NodalStencil s,
+                                                  int colour, const int* __restrict__ slots, int ncps) {
+  const SJ sj = slot_col(slots, ncps);
   const int nh = g.n >> 1, mh = g.m >> 1;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)nh * mh) return;
   const int p1 = 2 * (int)(t % nh) + (colour & 1);
   const int p2 = 2 * (int)(t / nh) + (colour >> 1);
-  const Ph<T> p = cast_phase<T>(php);
+  const Ph<T> p = cast_phase<T>(phs[sj.slot]);
   const int64_t N = g.nm;
-  T* xc = x + (int64_t)col * 2 * N;
-  const T* bc = b + (int64_t)col * 2 * N;
+  T* xc = colp(xv, sj, N);
+  const T* bc = colp(bv, sj, N);
   const int64_t i = (int64_t)p2 * g.n + p1;
   const Cx<T> r = Cx<T>{bc[i], bc[N + i]} - nodal_stencil<T>(xc, N, g.n, g.m, p1, p2, s, p);
   const T inv = (T)1 / (T)s.c0;
@@ -557,25 +600,27 @@ __global__ __launch_bounds__(256) void k_nodal_gs(T* __restrict__ x, const T* __
 }
 
 template <typename T>
-void nodal_gs(T* x, const T* b, const Geo& g, const Phase& ph, const NodalStencil& c, int colour,
-              int ncols, hipStream_t st) {
+void nodal_gs(View<T> x, View<const T> b, const Geo& g, const Phase* ph, const NodalStencil& c,
+              int colour, const Launch& L) {
   const int64_t cnt = (int64_t)(g.n / 2) * (g.m / 2);
-  dim3 grid((unsigned)((cnt + 255) / 256), (unsigned)ncols);
-  k_nodal_gs<T><<<grid, 256, 0, st>>>(x, b, g, ph, c, colour);
+  dim3 grid((unsigned)((cnt + 255) / 256), (unsigned)(L.nact * L.ncps));
+  if (grid.y == 0) return;
+  k_nodal_gs<T><<<grid, 256, 0, L.st>>>(x, b, g, ph, c, colour, L.slots, L.ncps);
 }
-template void nodal_gs<double>(double*, const double*, const Geo&, const Phase&, const NodalStencil&, int, int, hipStream_t);
-template void nodal_gs<float>(float*, const float*, const Geo&, const Phase&, const NodalStencil&, int, int, hipStream_t);
+template void nodal_gs<double>(View<double>, View<const double>, const Geo&, const Phase*, const NodalStencil&, int, const Launch&);
+template void nodal_gs<float>(View<float>, View<const float>, const Geo&, const Phase*, const NodalStencil&, int, const Launch&);
 
 // Nodal transfers: bilinear interpolation of the coarse Q1 function (embedding) and its
 // adjoint (full weighting with Bloch phases).
 template <typename T>
-__global__ __launch_bounds__(256) void k_nodal_restrict(const T* __restrict__ rf, Geo gf,
-                                                        T* __restrict__ bc, Geo gc, Phase php) {
-  const int col = blockIdx.y;
+__global__ __launch_bounds__(256) void k_nodal_restrict(View<const T> rv, Geo gf, View<T> bv, Geo gc,
+                                                        const Phase* __restrict__ phs,
+                                                        const int* __restrict__ slots, int ncps) {
+  const SJ sj = slot_col(slots, ncps);
   const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (d >= gc.nm) return;
-  const Ph<T> p = cast_phase<T>(php);
-  const T* r = rf + (int64_t)col * 2 * gf.nm;
+  const Ph<T> p = cast_phase<T>(phs[sj.slot]);
+  const T* r = colp(rv, sj, gf.nm);
   const int J1 = (int)(d % gc.n), J2 = (int)(d / gc.n);
   Cx<T> v = {0, 0};
 #pragma unroll
@@ -585,19 +630,20 @@ __global__ __launch_bounds__(256) void k_nodal_restrict(const T* __restrict__ rf
       const T w = (T)((d1 == 0 ? 1.0 : 0.5) * (d2 == 0 ? 1.0 : 0.5));
       v = v + (w * fetch<T, T>(r, gf.nm, gf.n, gf.m, 0, 2 * J1 + d1, 2 * J2 + d2, p));
     }
-  T* o = bc + (int64_t)col * 2 * gc.nm;
+  T* o = colp(bv, sj, gc.nm);
   o[d] = v.re;
   o[gc.nm + d] = v.im;
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_nodal_prolong_add(const T* __restrict__ xc, Geo gc,
-                                                           T* __restrict__ xf, Geo gf, Phase php) {
-  const int col = blockIdx.y;
+__global__ __launch_bounds__(256) void k_nodal_prolong_add(View<const T> cv, Geo gc, View<T> fv, Geo gf,
+                                                           const Phase* __restrict__ phs,
+                                                           const int* __restrict__ slots, int ncps) {
+  const SJ sj = slot_col(slots, ncps);
   const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (d >= gf.nm) return;
-  const Ph<T> p = cast_phase<T>(php);
-  const T* c = xc + (int64_t)col * 2 * gc.nm;
+  const Ph<T> p = cast_phase<T>(phs[sj.slot]);
+  const T* c = colp(cv, sj, gc.nm);
   const int f1 = (int)(d % gf.n), f2 = (int)(d / gf.n);
   const int J1 = f1 >> 1, J2 = f2 >> 1;
   const bool o1 = f1 & 1, o2 = f2 & 1;
@@ -614,42 +660,45 @@ __global__ __launch_bounds__(256) void k_nodal_prolong_add(const T* __restrict__
                    fetch<T, T>(c, gc.nm, gc.n, gc.m, 0, J1, J2 + 1, p) +
                    fetch<T, T>(c, gc.nm, gc.n, gc.m, 0, J1 + 1, J2 + 1, p));
   }
-  T* o = xf + (int64_t)col * 2 * gf.nm;
+  T* o = colp(fv, sj, gf.nm);
   o[d] += v.re;
   o[gf.nm + d] += v.im;
 }
 
 template <typename T>
-void nodal_restrict(const T* rf, const Geo& gf, T* bc, const Geo& gc, const Phase& ph, int ncols,
-                    hipStream_t st) {
-  dim3 grid((unsigned)((gc.nm + 255) / 256), (unsigned)ncols);
-  k_nodal_restrict<T><<<grid, 256, 0, st>>>(rf, gf, bc, gc, ph);
+void nodal_restrict(View<const T> rf, const Geo& gf, View<T> bc, const Geo& gc, const Phase* ph,
+                    const Launch& L) {
+  dim3 grid((unsigned)((gc.nm + 255) / 256), (unsigned)(L.nact * L.ncps));
+  if (grid.y == 0) return;
+  k_nodal_restrict<T><<<grid, 256, 0, L.st>>>(rf, gf, bc, gc, ph, L.slots, L.ncps);
 }
 template <typename T>
-void nodal_prolong_add(const T* xc, const Geo& gc, T* xf, const Geo& gf, const Phase& ph,
-                       int ncols, hipStream_t st) {
-  dim3 grid((unsigned)((gf.nm + 255) / 256), (unsigned)ncols);
-  k_nodal_prolong_add<T><<<grid, 256, 0, st>>>(xc, gc, xf, gf, ph);
+void nodal_prolong_add(View<const T> xc, const Geo& gc, View<T> xf, const Geo& gf,
+                       const Phase* ph, const Launch& L) {
+  dim3 grid((unsigned)((gf.nm + 255) / 256), (unsigned)(L.nact * L.ncps));
+  if (grid.y == 0) return;
+  k_nodal_prolong_add<T><<<grid, 256, 0, L.st>>>(xc, gc, xf, gf, ph, L.slots, L.ncps);
 }
-template void nodal_restrict<double>(const double*, const Geo&, double*, const Geo&, const Phase&, int, hipStream_t);
-template void nodal_restrict<float>(const float*, const Geo&, float*, const Geo&, const Phase&, int, hipStream_t);
-template void nodal_prolong_add<double>(const double*, const Geo&, double*, const Geo&, const Phase&, int, hipStream_t);
-template void nodal_prolong_add<float>(const float*, const Geo&, float*, const Geo&, const Phase&, int, hipStream_t);
+template void nodal_restrict<double>(View<const double>, const Geo&, View<double>, const Geo&, const Phase*, const Launch&);
+template void nodal_restrict<float>(View<const float>, const Geo&, View<float>, const Geo&, const Phase*, const Launch&);
+template void nodal_prolong_add<double>(View<const double>, const Geo&, View<double>, const Geo&, const Phase*, const Launch&);
+template void nodal_prolong_add<float>(View<const float>, const Geo&, View<float>, const Geo&, const Phase*, const Launch&);
 
 // out (nodal) = L^* M u (edge).  (L^* v)(p) = v_x(p1-1,p2) - v_x(p1,p2) + v_y(p1,p2-1) - v_y(p1,p2)
-// in extended coordinates, with v = M u evaluated on the fly.  Arithmetic in FP64 when the
-// input is FP64 (the right-hand side of the projection keeps the outer precision).
+// in extended coordinates, with v = M u evaluated on the fly.  Arithmetic in FP64 (the
+// right-hand side of the projection keeps the outer precision).
 template <typename TI, typename TO>
-__global__ __launch_bounds__(256) void k_lhm(const TI* __restrict__ u, TO* __restrict__ out, Geo g,
-                                             Phase php) {
+__global__ __launch_bounds__(256) void k_lhm(View<const TI> uv, View<TO> ov, Geo g,
+                                             const Phase* __restrict__ phs,
+                                             const int* __restrict__ slots, int ncps) {
   using T = double;
-  const int col = blockIdx.y;
+  const SJ sj = slot_col(slots, ncps);
   const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (d >= g.nm) return;
-  const Ph<T> p = cast_phase<T>(php);
+  const Ph<T> p = cast_phase<T>(phs[sj.slot]);
   const int n = g.n, m = g.m;
   const int64_t N = g.ne, nm = g.nm;
-  const TI* c = u + (int64_t)col * 2 * N;
+  const TI* c = colp(uv, sj, N);
   const int p1 = (int)(d % n), p2 = (int)(d / n);
   const T two3 = 2.0 / 3.0, one6 = 1.0 / 6.0;
   auto mx_at = [&](int j1, int j2) {
@@ -661,34 +710,36 @@ __global__ __launch_bounds__(256) void k_lhm(const TI* __restrict__ u, TO* __res
                       one6 * (fetch<TI, T>(c, N, n, m, nm, j1 + 1, j2, p) + fetch<TI, T>(c, N, n, m, nm, j1 - 1, j2, p)));
   };
   const Cx<T> v = mx_at(p1 - 1, p2) - mx_at(p1, p2) + my_at(p1, p2 - 1) - my_at(p1, p2);
-  TO* o = out + (int64_t)col * 2 * nm;
+  TO* o = colp(ov, sj, nm);
   o[d] = (TO)v.re;
   o[nm + d] = (TO)v.im;
 }
 
 template <typename TI, typename TO>
-void lhm(const TI* u, TO* out, const Geo& g, const Phase& ph, int ncols, hipStream_t st) {
-  dim3 grid((unsigned)((g.nm + 255) / 256), (unsigned)ncols);
-  k_lhm<TI, TO><<<grid, 256, 0, st>>>(u, out, g, ph);
+void lhm(View<const TI> u, View<TO> out, const Geo& g, const Phase* ph, const Launch& L) {
+  dim3 grid((unsigned)((g.nm + 255) / 256), (unsigned)(L.nact * L.ncps));
+  if (grid.y == 0) return;
+  k_lhm<TI, TO><<<grid, 256, 0, L.st>>>(u, out, g, ph, L.slots, L.ncps);
 }
-template void lhm<double, double>(const double*, double*, const Geo&, const Phase&, int, hipStream_t);
-template void lhm<double, float>(const double*, float*, const Geo&, const Phase&, int, hipStream_t);
-template void lhm<float, float>(const float*, float*, const Geo&, const Phase&, int, hipStream_t);
-template void lhm<float, double>(const float*, double*, const Geo&, const Phase&, int, hipStream_t);
+template void lhm<double, double>(View<const double>, View<double>, const Geo&, const Phase*, const Launch&);
+template void lhm<double, float>(View<const double>, View<float>, const Geo&, const Phase*, const Launch&);
+template void lhm<float, float>(View<const float>, View<float>, const Geo&, const Phase*, const Launch&);
+template void lhm<float, double>(View<const float>, View<double>, const Geo&, const Phase*, const Launch&);
 
 // out (edge) = u - L phi, (L phi)_x(j1,j2) = phi(j1+1,j2) - phi(j1,j2),
 // (L phi)_y(j1,j2) = phi(j1,j2+1) - phi(j1,j2) (extended reads).  FP64 arithmetic.
 template <typename TI, typename TP, typename TO, bool SUB>
-__global__ __launch_bounds__(256) void k_lift(const TI* __restrict__ u, const TP* __restrict__ phi,
-                                              TO* __restrict__ out, Geo g, Phase php) {
+__global__ __launch_bounds__(256) void k_lift(View<const TI> uv, View<const TP> fv, View<TO> ov, Geo g,
+                                              const Phase* __restrict__ phs,
+                                              const int* __restrict__ slots, int ncps) {
   using T = double;
-  const int col = blockIdx.y;
+  const SJ sj = slot_col(slots, ncps);
   const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (d >= g.ne) return;
-  const Ph<T> p = cast_phase<T>(php);
+  const Ph<T> p = cast_phase<T>(phs[sj.slot]);
   const int n = g.n, m = g.m;
   const int64_t N = g.ne, nm = g.nm;
-  const TP* f = phi + (int64_t)col * 2 * nm;
+  const TP* f = colp(fv, sj, nm);
   Cx<T> lp;
   if (d < nm) {
     const int j1 = (int)(d % n), j2 = (int)(d / n);
@@ -700,40 +751,43 @@ __global__ __launch_bounds__(256) void k_lift(const TI* __restrict__ u, const TP
   }
   Cx<T> v = lp;
   if (SUB) {
-    const TI* uc = u + (int64_t)col * 2 * N;
+    const TI* uc = colp(uv, sj, N);
     v = Cx<T>{(T)uc[d], (T)uc[N + d]} - lp;
   }
-  TO* o = out + (int64_t)col * 2 * N;
+  TO* o = colp(ov, sj, N);
   o[d] = (TO)v.re;
   o[N + d] = (TO)v.im;
 }
 
 template <typename TI, typename TP, typename TO>
-void lift_sub(const TI* u, const TP* phi, TO* out, const Geo& g, const Phase& ph, int ncols,
-              hipStream_t st) {
-  dim3 grid((unsigned)((g.ne + 255) / 256), (unsigned)ncols);
-  k_lift<TI, TP, TO, true><<<grid, 256, 0, st>>>(u, phi, out, g, ph);
+void lift_sub(View<const TI> u, View<const TP> phi, View<TO> out, const Geo& g, const Phase* ph,
+              const Launch& L) {
+  dim3 grid((unsigned)((g.ne + 255) / 256), (unsigned)(L.nact * L.ncps));
+  if (grid.y == 0) return;
+  k_lift<TI, TP, TO, true><<<grid, 256, 0, L.st>>>(u, phi, out, g, ph, L.slots, L.ncps);
 }
 template <typename TI, typename TO>
-void lift(const TI* phi, TO* out, const Geo& g, const Phase& ph, int ncols, hipStream_t st) {
-  dim3 grid((unsigned)((g.ne + 255) / 256), (unsigned)ncols);
-  k_lift<TO, TI, TO, false><<<grid, 256, 0, st>>>(nullptr, phi, out, g, ph);
+void lift(View<const TI> phi, View<TO> out, const Geo& g, const Phase* ph, const Launch& L) {
+  dim3 grid((unsigned)((g.ne + 255) / 256), (unsigned)(L.nact * L.ncps));
+  if (grid.y == 0) return;
+  k_lift<TO, TI, TO, false><<<grid, 256, 0, L.st>>>(View<const TO>{nullptr, 0, 0}, phi, out, g, ph, L.slots, L.ncps);
 }
-template void lift_sub<double, double, double>(const double*, const double*, double*, const Geo&, const Phase&, int, hipStream_t);
-template void lift_sub<double, float, double>(const double*, const float*, double*, const Geo&, const Phase&, int, hipStream_t);
-template void lift_sub<float, float, double>(const float*, const float*, double*, const Geo&, const Phase&, int, hipStream_t);
-template void lift_sub<float, double, double>(const float*, const double*, double*, const Geo&, const Phase&, int, hipStream_t);
-template void lift_sub<float, float, float>(const float*, const float*, float*, const Geo&, const Phase&, int, hipStream_t);
-template void lift<double, double>(const double*, double*, const Geo&, const Phase&, int, hipStream_t);
-template void lift<float, float>(const float*, float*, const Geo&, const Phase&, int, hipStream_t);
+template void lift_sub<double, double, double>(View<const double>, View<const double>, View<double>, const Geo&, const Phase*, const Launch&);
+template void lift_sub<double, float, double>(View<const double>, View<const float>, View<double>, const Geo&, const Phase*, const Launch&);
+template void lift_sub<float, float, double>(View<const float>, View<const float>, View<double>, const Geo&, const Phase*, const Launch&);
+template void lift_sub<float, double, double>(View<const float>, View<const double>, View<double>, const Geo&, const Phase*, const Launch&);
+template void lift_sub<float, float, float>(View<const float>, View<const float>, View<float>, const Geo&, const Phase*, const Launch&);
+template void lift<double, double>(View<const double>, View<double>, const Geo&, const Phase*, const Launch&);
+template void lift<float, float>(View<const float>, View<float>, const Geo&, const Phase*, const Launch&);
 
 // k = 0: remove the constant x- and y-edge fields M-orthogonally.  With alpha = beta = 1,
 // M applied to a constant x-field is h2/h1 times it, so the M-projection onto the constant
 // fields subtracts the mean of the x-part and of the y-part of every column.
-__global__ void k_col_means(const double* __restrict__ u, Geo g, double* __restrict__ out) {
-  const int col = blockIdx.x;
+__global__ void k_col_means(View<const double> uv, Geo g, double* __restrict__ out,
+                            const int* __restrict__ slots, int ncps) {
+  const SJ sj = slot_col(slots, ncps);
   const int64_t N = g.ne, nm = g.nm;
-  const double* c = u + (int64_t)col * 2 * N;
+  const double* c = colp(uv, sj, N);
   double a[4] = {0, 0, 0, 0};
   for (int64_t i = threadIdx.x; i < nm; i += blockDim.x) {
     a[0] += c[i];
@@ -750,23 +804,42 @@ __global__ void k_col_means(const double* __restrict__ u, Geo g, double* __restr
     __syncthreads();
   }
   if (threadIdx.x == 0)
-    for (int v = 0; v < 4; ++v) out[col * 4 + v] = sh[v][0] / (double)nm;
+    for (int v = 0; v < 4; ++v) out[(int64_t)blockIdx.y * 4 + v] = sh[v][0] / (double)nm;
 }
-__global__ void k_sub_means(double* __restrict__ u, Geo g, const double* __restrict__ mean) {
-  const int col = blockIdx.y;
+__global__ void k_sub_means(View<double> uv, Geo g, const double* __restrict__ mean,
+                            const int* __restrict__ slots, int ncps) {
+  const SJ sj = slot_col(slots, ncps);
   const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (d >= g.ne) return;
   const int64_t N = g.ne;
-  double* c = u + (int64_t)col * 2 * N;
+  double* c = colp(uv, sj, N);
   const int part = d < g.nm ? 0 : 2;
-  c[d] -= mean[col * 4 + part];
-  c[N + d] -= mean[col * 4 + part + 1];
+  c[d] -= mean[(int64_t)blockIdx.y * 4 + part];
+  c[N + d] -= mean[(int64_t)blockIdx.y * 4 + part + 1];
 }
-void gamma_deflate(double* u, const Geo& g, int ncols, double* scratch, hipStream_t st) {
-  k_col_means<<<ncols, 256, 0, st>>>(u, g, scratch);
-  dim3 grid((unsigned)((g.ne + 255) / 256), (unsigned)ncols);
-  k_sub_means<<<grid, 256, 0, st>>>(u, g, scratch);
+void gamma_deflate(View<double> u, const Geo& g, double* scratch, const Launch& L) {
+  if (L.nact * L.ncps == 0) return;
+  k_col_means<<<dim3(1, (unsigned)(L.nact * L.ncps)), 256, 0, L.st>>>(View<const double>{u.p, u.cps, u.off}, g, scratch, L.slots, L.ncps);
+  dim3 grid((unsigned)((g.ne + 255) / 256), (unsigned)(L.nact * L.ncps));
+  k_sub_means<<<grid, 256, 0, L.st>>>(u, g, scratch, L.slots, L.ncps);
 }
+
+// y += x on the launch's columns (vectors of length len)
+template <typename T>
+__global__ void k_axpy(View<T> yv, View<const T> xv, int64_t len, const int* __restrict__ slots, int ncps) {
+  const SJ sj = slot_col(slots, ncps);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2 * len) return;
+  colp(yv, sj, len)[i] += colp(xv, sj, len)[i];
+}
+template <typename T>
+void axpy(View<T> y, View<const T> x, int64_t len, const Launch& L) {
+  dim3 grid((unsigned)((2 * len + 255) / 256), (unsigned)(L.nact * L.ncps));
+  if (grid.y == 0) return;
+  k_axpy<T><<<grid, 256, 0, L.st>>>(y, x, len, L.slots, L.ncps);
+}
+template void axpy<double>(View<double>, View<const double>, int64_t, const Launch&);
+template void axpy<float>(View<float>, View<const float>, int64_t, const Launch&);
 
 template <typename T>
 __global__ void k_fill_zero(T* __restrict__ p, int64_t count) {
@@ -780,5 +853,21 @@ void fill_zero(T* p, int64_t count, hipStream_t st) {
 }
 template void fill_zero<double>(double*, int64_t, hipStream_t);
 template void fill_zero<float>(float*, int64_t, hipStream_t);
+
+template <typename T>
+__global__ void k_zero_cols(View<T> xv, int64_t len, const int* __restrict__ slots, int ncps) {
+  const SJ sj = slot_col(slots, ncps);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2 * len) return;
+  colp(xv, sj, len)[i] = (T)0;
+}
+template <typename T>
+void zero_cols(View<T> x, int64_t len, const Launch& L) {
+  dim3 grid((unsigned)((2 * len + 255) / 256), (unsigned)(L.nact * L.ncps));
+  if (grid.y == 0) return;
+  k_zero_cols<T><<<grid, 256, 0, L.st>>>(x, len, L.slots, L.ncps);
+}
+template void zero_cols<double>(View<double>, int64_t, const Launch&);
+template void zero_cols<float>(View<float>, int64_t, const Launch&);
 
 }  // namespace bl

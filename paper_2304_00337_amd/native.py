@@ -6,7 +6,8 @@ from __future__ import annotations
 import ctypes
 import os
 
-__all__ = ["LIB_PATH", "load", "BlGrid", "BlOpts", "BlInfo", "EXPORTED", "OPS", "check"]
+__all__ = ["LIB_PATH", "load", "BlGrid", "BlOpts", "BlInfo", "BlProblem", "BlRequest",
+           "BlRequestInfo", "BlServerCounters", "EXPORTED", "OPS", "check"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbloch.so")
 
@@ -44,6 +45,28 @@ class BlInfo(ctypes.Structure):
                 ("kernel_launches", c_int64)]
 
 
+class BlProblem(ctypes.Structure):
+    _fields_ = [("grid", BlGrid), ("eps", P(c_double)), ("nev", c_int32), ("nthrow", c_int32),
+                ("nk", c_int32), ("reserved0", c_int32), ("ks", P(c_double)), ("start_dev", c_void_p),
+                ("evals", P(c_double)), ("relres", P(c_double)), ("iters", P(c_int32)),
+                ("evecs_dev", c_void_p), ("status", c_int32), ("reserved1", c_int32)]
+
+
+class BlRequest(ctypes.Structure):
+    _fields_ = [("grid", BlGrid), ("eps", P(c_double)), ("nev", c_int32), ("nthrow", c_int32),
+                ("nk", c_int32), ("reserved0", c_int32), ("ks", P(c_double)), ("start_dev", c_void_p)]
+
+
+class BlRequestInfo(ctypes.Structure):
+    _fields_ = [("status", c_int32), ("total_iters", c_int32), ("queue_s", c_double),
+                ("run_s", c_double), ("latency_s", c_double)]
+
+
+class BlServerCounters(ctypes.Structure):
+    _fields_ = [("rounds", c_int64), ("kernel_launches", c_int64), ("device_bytes", c_size_t),
+                ("engines", c_int32), ("queued", c_int32), ("pending", c_int32), ("reserved", c_int32)]
+
+
 # name -> (restype, argtypes); must match include/bloch.h
 EXPORTED = {
     "bl_default_opts": (None, [P(BlOpts), c_int32]),
@@ -65,6 +88,13 @@ EXPORTED = {
     "bl_gram": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_int32, c_int64, P(c_double)]),
     "bl_ritz_small": (c_int32, [c_void_p, P(c_double), P(c_double), c_int32, c_int32, c_double,
                                 P(c_double), P(c_double)]),
+    "bl_batch_solve": (c_int32, [P(BlOpts), P(BlProblem), c_int32, c_int32, c_void_p]),
+    "bl_server_create": (c_int32, [P(BlOpts), c_size_t, c_int32, P(c_void_p)]),
+    "bl_server_submit": (c_int32, [c_void_p, P(BlRequest), P(ctypes.c_uint64)]),
+    "bl_server_poll": (c_int32, [c_void_p, ctypes.c_uint64, P(c_double), P(c_double), P(c_int32),
+                                 P(BlRequestInfo)]),
+    "bl_server_stats": (c_int32, [c_void_p, P(BlServerCounters)]),
+    "bl_server_destroy": (None, [c_void_p]),
     "bl_strerror": (ctypes.c_char_p, [c_int32]),
     "bl_last_error": (ctypes.c_char_p, []),
 }

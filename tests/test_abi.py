@@ -52,3 +52,33 @@ def test_host_only_calls():
     g2 = native.BlGrid(2, 2, 1.0, 1.0)
     neg = (ctypes.c_double * 4)(1, -1, 1, 1)
     assert lib.bl_create(ctypes.byref(g2), neg, ctypes.byref(o), None, ctypes.byref(h)) == native.BL_EINVAL
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """sizeof and every field offset of the public structs, compiled from bloch.h with the
+    host C compiler, equal the ctypes declarations of the binding."""
+    import shutil
+    import subprocess
+    from paper_2304_00337_amd import native
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = {"bl_grid": native.BlGrid, "bl_opts": native.BlOpts, "bl_info": native.BlInfo,
+               "bl_problem": native.BlProblem, "bl_request": native.BlRequest,
+               "bl_request_info": native.BlRequestInfo, "bl_server_counters": native.BlServerCounters}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "bloch.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f in py._fields_:
+            lines.append(f'  printf("{cname} {f[0]} %zu\\n", offsetof({cname}, {f[0]}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f in py._fields_:
+            assert got[(cname, f[0])] == getattr(py, f[0]).offset, (cname, f[0])

@@ -1,0 +1,166 @@
+"""Batched solves and the serving loop through the C ABI (bl_batch_solve, bl_server_*):
+every problem's eigenvalues match the dense oracle, and a problem's results do not depend
+on the other problems it shares launches with (alone == in batch == in a served mix; the
+slots of an engine share kernels but not arithmetic, so the agreement is to the last bit)."""
+import math
+import time
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import fem
+from oracle.dense import dense_eigs
+
+pytestmark = pytest.mark.gpu
+
+
+def _problems():
+    """Two shapes (16x16 and 32x32, p = 6 and p = 9), different eps, nev and paths; two
+    of the 16x16 problems share p with different nev."""
+    out = []
+    specs = [
+        (16, 4, 2, synth.eps_disc(16, 16, 1.0, 1.0, 8.9, 0.3), [(0.9, -0.4), (1.1, -0.3)], 11),
+        (16, 5, 1, synth.eps_disc(16, 16, 1.0, 1.0, 4.0, 0.25), [(0.0, 0.0), (0.3, 0.0)], 12),
+        (32, 6, 3, synth.eps_disc_lattice(32, 32, 1.0, 1.0, 12.0, 0.3), [(math.pi, 0.5)], 13),
+        (16, 4, 2, np.ones(256), [(math.pi, math.pi), (2.8, 3.0), (2.6, 2.9)], 14),
+        (32, 6, 3, synth.eps_random_field(32, 32, 1.0, 1.0, 5), [(0.4, 1.9), (0.6, 1.8)], 15),
+    ]
+    for n, nev, nthrow, eps, ks, seed in specs:
+        out.append(dict(n=n, m=n, a=1.0, b=1.0, eps=eps, nev=nev, nthrow=nthrow,
+                        ks=np.array(ks, dtype=float),
+                        start=synth.start_block(2 * n * n, nev + nthrow, seed)))
+    return out
+
+
+OPTS = dict(tol=1e-9, max_iter=300, coarsest_min=4)
+_DENSE = {}
+
+
+def _dense(pr, t):
+    key = (pr["eps"].tobytes(), pr["n"], tuple(pr["ks"][t]), pr["nev"])
+    if key not in _DENSE:
+        d = fem.Discretization(pr["n"], pr["m"], 1.0, 1.0, pr["eps"], *pr["ks"][t])
+        _DENSE[key] = dense_eigs(d, pr["nev"])[0]
+    return _DENSE[key]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_matches_dense_and_alone(precision):
+    from paper_2304_00337_amd import batch_solve
+    probs = _problems()
+    together = batch_solve(probs, precision=precision, **OPTS)
+    tol = 1e-9 if precision == "fp64" else 1e-6
+    for pr, r in zip(probs, together):
+        assert r["status"] == 0, r
+        for t in range(len(pr["ks"])):
+            ref = _dense(pr, t)
+            assert np.max(np.abs(r["evals"][t] - ref) / ref) < tol, (t, r["evals"][t], ref)
+    # alone: each problem in a batch of its own, one slot per engine
+    for pr, r in zip(probs, together):
+        a = batch_solve([pr], precision=precision, **OPTS)[0]
+        assert np.array_equal(a["evals"], r["evals"])
+        assert np.array_equal(a["iterations"], r["iterations"])
+
+
+def test_batch_equals_single_handle_and_slot_limits():
+    """A batched problem equals the same path on a one-problem handle (bl_solve_path), and
+    engines with fewer slots than problems (slots re-used as problems finish) give the same
+    results."""
+    from paper_2304_00337_amd import Solver, batch_solve
+    probs = _problems()
+    full = batch_solve(probs, **OPTS)
+    tight = batch_solve(probs, max_slots=1, **OPTS)
+    for r, q in zip(full, tight):
+        assert np.array_equal(r["evals"], q["evals"])
+    pr = probs[2]
+    s = Solver(pr["n"], pr["m"], 1.0, 1.0, pr["eps"], nev=pr["nev"], nthrow=pr["nthrow"], **OPTS)
+    one = s.solve_path(pr["ks"], start=pr["start"])
+    assert np.array_equal(one["evals"], full[2]["evals"])
+    assert np.array_equal(one["iterations"], full[2]["iterations"])
+
+
+def test_batch_reports_invalid_problems_without_stopping_others():
+    from paper_2304_00337_amd import batch_solve
+    probs = _problems()[:2]
+    bad = dict(probs[0])
+    bad["ks"] = np.array([[float("nan"), 0.0]])
+    res = batch_solve([probs[0], bad, probs[1]], **OPTS)
+    assert res[0]["status"] == 0 and res[2]["status"] == 0
+    assert res[1]["status"] == -1
+
+
+def _serve(srv, reqs, rate_hz, seed):
+    """Submit at Poisson arrival times; poll until all are done."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate_hz, size=len(reqs))
+    tickets, results = [], {}
+    for g, rq in zip(gaps, reqs):
+        time.sleep(g)
+        tickets.append(srv.submit(**rq))
+        for t in tickets:
+            if t not in results:
+                r = srv.poll(t)
+                if r is not None:
+                    results[t] = r
+    deadline = time.time() + 120
+    while len(results) < len(tickets):
+        assert time.time() < deadline, "server did not finish"
+        for t in tickets:
+            if t not in results:
+                r = srv.poll(t)
+                if r is not None:
+                    results[t] = r
+        time.sleep(0.002)
+    return [results[t] for t in tickets]
+
+
+def test_server_alone_equals_in_mix():
+    from paper_2304_00337_amd import Server
+    probs = _problems()
+    reqs = [dict(n=p["n"], m=p["m"], a=1.0, b=1.0, eps=p["eps"], nev=p["nev"], nthrow=p["nthrow"],
+                 ks=p["ks"], start=p["start"]) for p in probs]
+    mix = reqs * 2     # every request twice, the copies arriving while the first ones run
+    with Server(max_slots=4, precision="mixed", **OPTS) as srv:
+        got = _serve(srv, mix, rate_hz=200.0, seed=0)
+        st = srv.stats()
+        assert st["pending"] == 0 and st["queued"] == 0
+    for r in got:
+        assert r["status"] == 0
+        assert r["latency_s"] >= r["run_s"] >= 0 and r["queue_s"] >= 0
+    for i in range(len(reqs)):
+        assert np.array_equal(got[i]["evals"], got[i + len(reqs)]["evals"])
+    with Server(precision="mixed", **OPTS) as srv:
+        alone = _serve(srv, [reqs[2]], rate_hz=1000.0, seed=1)[0]
+    assert np.array_equal(alone["evals"], got[2]["evals"])
+    assert np.array_equal(alone["iterations"], got[2]["iterations"])
+
+
+def test_server_small_budget_swaps_engines():
+    """A budget that holds one engine at a time: requests of two shapes still all finish,
+    the engines being released and created as the queue demands."""
+    from paper_2304_00337_amd import Server, Solver
+    probs = _problems()
+    reqs = [dict(n=p["n"], m=p["m"], a=1.0, b=1.0, eps=p["eps"], nev=p["nev"], nthrow=p["nthrow"],
+                 ks=p["ks"], start=p["start"]) for p in probs]
+    big = max(Solver.footprint_bytes(p["n"], p["m"], 1.0, 1.0, nev=p["nev"] + p["nthrow"], nthrow=0,
+                                     coarsest_min=4) for p in probs)
+    with Server(hbm_budget=int(big * 1.05), max_slots=1, **OPTS) as srv:
+        got = _serve(srv, reqs, rate_hz=1000.0, seed=2)
+    ref = __import__("paper_2304_00337_amd").batch_solve(probs, **OPTS)
+    for g, r in zip(got, ref):
+        assert g["status"] == 0
+        assert np.array_equal(g["evals"], r["evals"])
+
+
+def test_server_errors():
+    from paper_2304_00337_amd import Server
+    from paper_2304_00337_amd.native import BlochError
+    p = _problems()[0]
+    with Server(**OPTS) as srv:
+        with pytest.raises(BlochError):
+            srv.submit(n=p["n"], m=p["m"], a=1.0, b=1.0, eps=p["eps"], nev=p["nev"], nthrow=p["nthrow"],
+                       ks=np.array([[float("inf"), 0.0]]), start=p["start"])
+        from paper_2304_00337_amd.native import check
+        with pytest.raises(BlochError):
+            check(srv.lib.bl_server_poll(srv.h, 12345, None, None, None, None), "bl_server_poll")
