@@ -205,6 +205,12 @@ int bl_gram(bl_solver* s, const void* X, int32_t q, const void* W, int32_t r, in
             double* out);
 int bl_ritz_small(bl_solver* s, const double* G, const double* H, int32_t q, int32_t want,
                   double zero_thr, double* theta, double* Y);
+/* bl_rr_products: the Ritz step's products G = S^* M S and H = S^* A S (host q x q each,
+ *   row-major interleaved complex) for a device planar FP64 block S of q <= 3p columns of
+ *   length N_e, with the handle's permittivity and the Bloch parameter of bl_set_k; they
+ *   are formed straight from S (M S and A S are not stored).  Errors: BL_EINVAL, BL_ESTATE
+ *   (no k set), BL_EHIP. */
+int bl_rr_products(bl_solver* s, const void* S, int32_t q, double* G, double* H);
 
 /* ---- Batched solves (many problems in the same launches) --------------------------------
  * Problems of equal shape (n, m, a, b and block width p = nev + nthrow) share one engine:

@@ -349,6 +349,14 @@ class Solver:
                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "bl_gram")
         return out[..., 0] + 1j * out[..., 1]
 
+    def rr_products(self, S):
+        """(S^* M S, S^* A S) for a planar FP64 device block S (q, 2, N_e) (bl_rr_products)."""
+        q = S.shape[0]
+        G = np.zeros((q, q, 2))
+        H = np.zeros((q, q, 2))
+        check(self.lib.bl_rr_products(self.h, _ptr(S), q, _dptr(G), _dptr(H)), "bl_rr_products")
+        return G[..., 0] + 1j * G[..., 1], H[..., 0] + 1j * H[..., 1]
+
     def ritz_small(self, G: np.ndarray, H: np.ndarray, want: int, zero_thr: float = -np.inf):
         q = G.shape[0]
         g = np.ascontiguousarray(np.stack([G.real, G.imag], axis=-1), dtype=np.float64)

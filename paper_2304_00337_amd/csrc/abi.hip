@@ -207,6 +207,11 @@ int bl_gram(bl_solver* s, const void* X, int32_t q, const void* W, int32_t r, in
   return check_hip();
 }
 
+int bl_rr_products(bl_solver* s, const void* S, int32_t q, double* G, double* H) {
+  if (!s || !S || !G || !H) return set_error(BL_EINVAL, "NULL argument%s");
+  return engine_rr_products(s, S, q, G, H);
+}
+
 int bl_ritz_small(bl_solver* s, const double* G, const double* H, int32_t q, int32_t want,
                   double zero_thr, double* theta, double* Y) {
   if (!s || !G || !H || !theta || !Y || q < 1 || q > 255 || want < 1 || want > q)

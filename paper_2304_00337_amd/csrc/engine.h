@@ -119,7 +119,6 @@ struct bl_solver {
   // iteration blocks, slot-major
   double* E = nullptr;       // p columns per slot
   double* Sb = nullptr;      // qmax columns per slot
-  double* W = nullptr;       // 2 qmax columns per slot
   double* hist[3] = {nullptr, nullptr, nullptr};   // p columns per slot, most recent first
   double* lam_d = nullptr;   // p per slot
   int* count_d = nullptr;    // per slot
@@ -127,7 +126,6 @@ struct bl_solver {
   double* norms = nullptr;
   double* gram_partial = nullptr;
   int64_t gram_cap = 0;
-  double* GH = nullptr;
   double* Gm = nullptr;
   double* Hm = nullptr;
   double* Yd = nullptr;
@@ -191,5 +189,6 @@ int engine_sync_retired(bl_solver* s);
 int engine_set_k0(bl_solver* s, double k1, double k2);
 int engine_apply(bl_solver* s, int op, int level, int prec, int ncols, const void* x,
                  const void* y, void* out);
+int engine_rr_products(bl_solver* s, const void* S, int q, double* G, double* H);
 
 }  // namespace bl

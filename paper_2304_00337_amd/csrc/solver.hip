@@ -391,30 +391,13 @@ int project(bl_solver* s, const std::vector<Group>& groups, View<double> out,
 }  // namespace
 }  // namespace bl
 
-// small helper kernel of the Ritz step: split the q x 2q product [G | H] of each slot
-namespace {
-__global__ void k_split_gram(const double* __restrict__ GH, int q, double* __restrict__ G,
-                             double* __restrict__ H, const int* __restrict__ slots) {
-  const int64_t s = slots ? slots[blockIdx.y] : blockIdx.y;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)q * q) return;
-  const int i = (int)(e / q), j = (int)(e % q);
-  const double* gh = GH + s * (int64_t)q * 2 * q * 2;
-  double* g = G + s * (int64_t)q * q * 2;
-  double* h = H + s * (int64_t)q * q * 2;
-  g[2 * e] = gh[2 * ((int64_t)i * 2 * q + j)];
-  g[2 * e + 1] = gh[2 * ((int64_t)i * 2 * q + j) + 1];
-  h[2 * e] = gh[2 * ((int64_t)i * 2 * q + q + j)];
-  h[2 * e + 1] = gh[2 * ((int64_t)i * 2 * q + q + j) + 1];
-}
-}  // namespace
-
 namespace bl {
 namespace {
 
-void split_gram(const double* GH, int q, double* G, double* H, const Launch& L) {
-  if (L.nact <= 0) return;
-  k_split_gram<<<dim3((unsigned)(((int64_t)q * q + 255) / 256), (unsigned)L.nact), 256, 0, L.st>>>(GH, q, G, H, L.slots);
+// Output tile of the Rayleigh-Ritz products: the 48- or 64-wide tiling that pads q least.
+int rr_tile(int q) {
+  const int64_t p3 = (int64_t)((q + 47) / 48) * 48, p4 = (int64_t)((q + 63) / 64) * 64;
+  return p4 < p3 ? 4 : 3;
 }
 
 // Ritz step on the q columns of S (FP64) of the listed slots: G = S^* M S, H = S^* A S,
@@ -425,15 +408,12 @@ int ritz_step(bl_solver* s, const std::vector<int>& slots, int q, int nfix, bool
   const Geo& g = L0.g;
   Launch L = make_launch(s, slots, q);
   View<double> Sv = view(s->Sb, s->qmax);
-  edge_apply<double, double>(EM_M, cv(Sv), View<const double>{nullptr, 0, 0}, view(s->W, 2 * s->qmax, 0), L0.kappa64, L0.kappa32, nullptr, 0, g, s->ph_d, s->mu_d, L, nullptr, nullptr);
-  edge_apply<double, double>(EM_A, cv(Sv), View<const double>{nullptr, 0, 0}, view(s->W, 2 * s->qmax, q), L0.kappa64, L0.kappa32, nullptr, 0, g, s->ph_d, s->mu_d, L, nullptr, nullptr);
-  if (gram(cv(Sv), q, cview(s->W, 2 * s->qmax, 0), 2 * q, g.ne, s->gram_partial, s->gram_cap, s->GH, L) != 0)
+  if (rr_gram(cv(Sv), q, L0.kappa64, g, s->ph_d, s->gram_partial, s->gram_cap, s->Gm, s->Hm, rr_tile(q), L) != 0)
     return set_error(BL_EINVAL, "Gram scratch too small%s");
-  split_gram(s->GH, q, s->Gm, s->Hm, L);
   ritz_small(s->Gm, s->Hm, q, nfix, s->p, use_zthr ? s->zthr_d : nullptr, kDropRel, s->ritz_work,
              s->ritz_stride, s->Yd, s->lam_d, s->count_d, L);
   block_combine(cv(Sv), q, s->Yd, s->p, g.ne, view(s->E, s->p), L);
-  s->launches += 7;
+  s->launches += 4;
   if (s->debug && !slots.empty()) {
     double sw[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     const double* base = s->ritz_work + (size_t)slots[0] * s->ritz_stride;
@@ -597,12 +577,12 @@ size_t engine_footprint(const bl_grid* grid, const bl_opts* o, int nslots) {
   }
   Geo g0 = make_geo(grid->n, grid->m, grid->a, grid->b);
   const size_t col = (size_t)2 * g0.ne * 8;
-  per += col * (p + q + 2 * q + 3 * p);           // E, S, W, history
+  per += col * (p + q + 3 * p);                   // E, S, history
   per += nodal_block_bytes(g0, q, pr) * 2;        // nodal multi-cycle work
   Geo gc = make_geo(lv.back().first, lv.back().second, grid->a, grid->b);
   per += (size_t)gc.ne * gc.ne * 16 * 2 + (size_t)gc.nm * gc.nm * 16 * 2;   // inverses (FP64 + FP32)
   per += (size_t)gc.ne * gc.ne * 16;                                         // probe results
-  per += (size_t)gram_blocks(g0.ne) * q * 2 * q * 16 + (size_t)14 * q * q * 16;
+  per += (size_t)rr_blocks(g0.nm) * q * q * 32 + (size_t)10 * q * q * 16;
   per += (size_t)p * ((g0.ne + 255) / 256) * 16;
   fixed += (size_t)gc.ne * gc.ne * 16 + (size_t)gc.nm * gc.nm * 16;           // probes
   return fixed + per * (size_t)std::max(1, nslots);
@@ -681,16 +661,14 @@ int engine_create(const bl_grid* grid, const bl_opts* opts, int nslots, hipStrea
   if ((rc = dalloc_t(s, &s->zthr_d, S))) return fail(rc);
   if ((rc = dalloc_t(s, &s->E, col * p * S))) return fail(rc);
   if ((rc = dalloc_t(s, &s->Sb, col * q * S))) return fail(rc);
-  if ((rc = dalloc_t(s, &s->W, col * 2 * q * S))) return fail(rc);
   for (int h = 0; h < 3; ++h)
     if ((rc = dalloc_t(s, &s->hist[h], col * p * S))) return fail(rc);
   if ((rc = dalloc_t(s, &s->lam_d, (size_t)p * S))) return fail(rc);
   if ((rc = dalloc_t(s, &s->count_d, (size_t)S))) return fail(rc);
   if ((rc = dalloc_t(s, &s->partial, (size_t)p * S * ((g0.ne + 255) / 256) * 2))) return fail(rc);
   if ((rc = dalloc_t(s, &s->norms, (size_t)2 * p * S))) return fail(rc);
-  s->gram_cap = (int64_t)gram_blocks(g0.ne) * q * 2 * q * 2 * S;
+  s->gram_cap = (int64_t)rr_blocks(g0.nm) * q * q * 4 * S;
   if ((rc = dalloc_t(s, &s->gram_partial, s->gram_cap))) return fail(rc);
-  if ((rc = dalloc_t(s, &s->GH, (size_t)q * 2 * q * 2 * S))) return fail(rc);
   if ((rc = dalloc_t(s, &s->Gm, (size_t)q * q * 2 * S))) return fail(rc);
   if ((rc = dalloc_t(s, &s->Hm, (size_t)q * q * 2 * S))) return fail(rc);
   if ((rc = dalloc_t(s, &s->Yd, (size_t)q * q * 2 * S))) return fail(rc);
@@ -1025,6 +1003,20 @@ int apply_t(bl_solver* s, int op, int level, int ncols, const void* xv, const vo
   return BL_OK;
 }
 }  // namespace
+
+int engine_rr_products(bl_solver* s, const void* S, int q, double* G, double* H) {
+  if (!s->kset) return set_error(BL_ESTATE, "call bl_set_k first%s");
+  if (q < 1 || q > s->qmax) return set_error(BL_EINVAL, "q must be 1..3p%s");
+  const Level& L0 = s->lv[0];
+  const Launch L{nullptr, 1, q, s->st};
+  if (rr_gram(View<const double>{static_cast<const double*>(S), q, 0}, q, L0.kappa64, L0.g, s->ph_d, s->gram_partial,
+              s->gram_cap, s->Gm, s->Hm, rr_tile(q), L) != 0)
+    return set_error(BL_EINVAL, "Gram scratch too small%s");
+  HIP_OK(hipMemcpyAsync(G, s->Gm, (size_t)q * q * 16, hipMemcpyDeviceToHost, s->st));
+  HIP_OK(hipMemcpyAsync(H, s->Hm, (size_t)q * q * 16, hipMemcpyDeviceToHost, s->st));
+  HIP_OK(hipStreamSynchronize(s->st));
+  return check_hip();
+}
 
 int engine_apply(bl_solver* s, int op, int level, int prec, int ncols, const void* x,
                  const void* y, void* out) {

@@ -8,96 +8,11 @@
 // so every stencil is the plain translation-invariant one and the phases enter only
 // through the reads (and writes) that cross the cell boundary.  The local patch matrices
 // are therefore real and independent of k.
-#include "internal.h"
+#include "stencil_common.h"
 
 #include <cmath>
 
 namespace bl {
-
-template <typename T>
-struct Cx {
-  T re, im;
-};
-
-template <typename T>
-__device__ __forceinline__ Cx<T> operator+(Cx<T> a, Cx<T> b) { return {a.re + b.re, a.im + b.im}; }
-template <typename T>
-__device__ __forceinline__ Cx<T> operator-(Cx<T> a, Cx<T> b) { return {a.re - b.re, a.im - b.im}; }
-template <typename T>
-__device__ __forceinline__ Cx<T> operator*(T s, Cx<T> a) { return {s * a.re, s * a.im}; }
-template <typename T>
-__device__ __forceinline__ Cx<T> cmul(Cx<T> a, T br, T bi) {
-  return {a.re * br - a.im * bi, a.re * bi + a.im * br};
-}
-
-// Phases in the kernel's arithmetic type.
-template <typename T>
-struct Ph {
-  T ar, ai, br, bi;
-};
-template <typename T>
-__host__ __device__ inline Ph<T> cast_phase(const Phase& p) {
-  return {(T)p.ar, (T)p.ai, (T)p.br, (T)p.bi};
-}
-
-// Read component `off` (0 for x-edges / nodes, nm for y-edges) at extended (j1, j2),
-// j1 in [-n, 2n), j2 in [-m, 2m).
-template <typename TS, typename T>
-__device__ __forceinline__ Cx<T> fetch(const TS* __restrict__ col, int64_t N, int n, int m,
-                                       int64_t off, int j1, int j2, const Ph<T>& p) {
-  int s1 = 0, s2 = 0;
-  if (j1 < 0) { j1 += n; s1 = -1; } else if (j1 >= n) { j1 -= n; s1 = 1; }
-  if (j2 < 0) { j2 += m; s2 = -1; } else if (j2 >= m) { j2 -= m; s2 = 1; }
-  const int64_t i = off + (int64_t)j2 * n + j1;
-  Cx<T> v = {(T)col[i], (T)col[N + i]};
-  if (s1 > 0) v = cmul(v, p.ar, p.ai);
-  else if (s1 < 0) v = cmul(v, p.ar, -p.ai);
-  if (s2 > 0) v = cmul(v, p.br, p.bi);
-  else if (s2 < 0) v = cmul(v, p.br, -p.bi);
-  return v;
-}
-
-// Add delta (given in extended coordinates) to the stored value at extended (j1, j2),
-// j1 in [-1, n), j2 in [-1, m): u_can = conj(phase) * u_ext.
-template <typename TS, typename T>
-__device__ __forceinline__ void add_ext(TS* __restrict__ col, int64_t N, int n, int m, int64_t off,
-                                        int j1, int j2, Cx<T> d, const Ph<T>& p) {
-  if (j1 < 0) { j1 += n; d = cmul(d, p.ar, p.ai); }
-  if (j2 < 0) { j2 += m; d = cmul(d, p.br, p.bi); }
-  const int64_t i = off + (int64_t)j2 * n + j1;
-  col[i] = (TS)((T)col[i] + d.re);
-  col[N + i] = (TS)((T)col[N + i] + d.im);
-}
-
-__device__ __forceinline__ int wrapi(int j, int n) { return j < 0 ? j + n : (j >= n ? j - n : j); }
-
-// Slot and in-slot column of this block (grid.y = active slots * columns per slot).
-struct SJ {
-  int slot, j;
-};
-__device__ __forceinline__ SJ slot_col(const int* slots, int ncps) {
-  const int si = (int)blockIdx.y / ncps;
-  return {slots ? slots[si] : si, (int)blockIdx.y % ncps};
-}
-template <typename T>
-__device__ __forceinline__ T* colp(View<T> v, SJ s, int64_t N) {
-  return v.p + ((int64_t)s.slot * v.cps + v.off + s.j) * 2 * N;
-}
-
-template <typename T>
-__device__ __forceinline__ T kap(const double* k64, const float* k32, int64_t i);
-template <>
-__device__ __forceinline__ double kap<double>(const double* k64, const float*, int64_t i) { return k64[i]; }
-template <>
-__device__ __forceinline__ float kap<float>(const double*, const float* k32, int64_t i) { return k32[i]; }
-
-// Cell curl (circulation) of cell (c1, c2), extended c in [-1, n).
-template <typename TS, typename T>
-__device__ __forceinline__ Cx<T> cell_curl(const TS* col, int64_t N, int n, int m, int64_t nm,
-                                           int c1, int c2, const Ph<T>& p) {
-  return fetch<TS, T>(col, N, n, m, 0, c1, c2 + 1, p) - fetch<TS, T>(col, N, n, m, 0, c1, c2, p) +
-         fetch<TS, T>(col, N, n, m, nm, c1, c2, p) - fetch<TS, T>(col, N, n, m, nm, c1 + 1, c2, p);
-}
 
 // ------------------------------------------------------------------------------------------
 // Edge operators: A (curl-curl with kappa = 1/eps), M (mass), K = A + mu M and residuals.

@@ -88,6 +88,7 @@ EXPORTED = {
     "bl_gram": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_int32, c_int64, P(c_double)]),
     "bl_ritz_small": (c_int32, [c_void_p, P(c_double), P(c_double), c_int32, c_int32, c_double,
                                 P(c_double), P(c_double)]),
+    "bl_rr_products": (c_int32, [c_void_p, c_void_p, c_int32, P(c_double), P(c_double)]),
     "bl_batch_solve": (c_int32, [P(BlOpts), P(BlProblem), c_int32, c_int32, c_void_p]),
     "bl_server_create": (c_int32, [P(BlOpts), c_size_t, c_int32, P(c_void_p)]),
     "bl_server_submit": (c_int32, [c_void_p, P(BlRequest), P(ctypes.c_uint64)]),
