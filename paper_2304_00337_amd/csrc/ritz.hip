@@ -1,6 +1,6 @@
 // Ritz step of the block iteration (Section 4, Ritz vectors and values) for gfx950: the
 // generalised Hermitian eigenproblem  H y = theta G y  of the basis S (q <= 255 columns),
-// G = S^* M S and H = S^* A S, solved in one workgroup in LDS:
+// G = S^* M S and H = S^* A S, solved in one workgroup per problem slot, in LDS:
 //
 //  1. unit-diagonal scaling D; pivoted Cholesky P^T (D G D) P = L L^* (the first nfix
 //     columns, previous Ritz vectors, keep their order), stopped when the largest remaining
@@ -9,10 +9,15 @@
 //     was small, a second Cholesky pass on Z^* G Z restores orthonormality to rounding;
 //  3. H' = Z^* H Z (r x r) is reduced to real symmetric tridiagonal form by Householder
 //     reflections and a diagonal unitary scaling;
-//  4. the wanted eigenvalues (the `want` smallest above zero_thr) by Sturm-count bisection,
-//     one thread per eigenvalue; eigenvectors by inverse iteration with the tridiagonal LU,
-//     re-orthogonalised inside clusters of close eigenvalues;
-//  5. back-transformation through the scaling and the reflections, Y = Z y.
+//  4. the wanted eigenvalues (the `want` smallest above zero_thr) by Sturm-count
+//     multisection, eight lanes per eigenvalue; eigenvectors by inverse iteration with the
+//     tridiagonal LU, re-orthogonalised inside clusters of close eigenvalues;
+//  5. back-transformation through the scaling and the reflections (eight lanes per vector,
+//     each lane owning a fixed residue class of the rows), Y = Z y.
+//
+// The sequential parts (pivot steps, reflector steps) keep few barriers per step: pivot
+// searches and vector reductions are wave-level shuffle reductions, and every wave
+// computes the small reductions it needs itself instead of waiting for one thread.
 #include "internal.h"
 
 #include <cmath>
@@ -29,95 +34,132 @@ struct c2 {
 __device__ __forceinline__ c2 cmul(c2 a, c2 b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
 __device__ __forceinline__ c2 cmulc(c2 a, c2 b) { return {a.r * b.r + a.i * b.i, a.r * b.i - a.i * b.r}; }  // conj(a) b
 
-constexpr int RT = 256;
+constexpr int RT = 256;   // threads per workgroup
+constexpr int GS = 8;     // lanes per eigenvalue / eigenvector group
 
 // size of the per-index arrays (one complex, six doubles, two ints per basis index) in
 // complex units, rounded up
 __host__ __device__ inline int index_block_c2(int q) { return (q * (16 + 48 + 8) + 15) / 16; }
 
-// Block-wide sum (all threads get the result).
-__device__ double bsum(double a, double* sh) {
+__device__ __forceinline__ double wave_sum(double a) {
   for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (lane == 0) sh[w] = a;
-  __syncthreads();
-  double t = 0;
-  for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += sh[k];
-  __syncthreads();
-  return t;
+  return a;
 }
 
-// Out (r x r, stride ldo) = Z^* X Z, X q x q (stride q), Z q x r (stride r), T q x r scratch.
-__device__ void aha(const c2* X, int q, const c2* Z, int r, c2* T, c2* Out, int ldo) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int e = tid; e < q * r; e += nt) {
-    const int i = e / r, c = e % r;
-    c2 s = {0, 0};
-#pragma unroll 4
-    for (int l = 0; l < q; ++l) {
-      const c2 t = cmul(X[i * q + l], Z[l * r + c]);
-      s.r += t.r;
-      s.i += t.i;
+// C (M x N, stride ldc) = X (M x K, stride ldx) * Y (K x N, stride ldy); 3 x 3 register
+// blocks per thread.
+__device__ __forceinline__ void mm_nn(const c2* X, int ldx, const c2* Y, int ldy, c2* C, int ldc, int M, int N, int K) {
+  const int bm = (M + 2) / 3, bn = (N + 2) / 3;
+  for (int e = threadIdx.x; e < bm * bn; e += blockDim.x) {
+    const int i0 = (e / bn) * 3, j0 = (e % bn) * 3;
+    c2 acc[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) acc[a][b] = {0, 0};
+    for (int l = 0; l < K; ++l) {
+      c2 xa[3], yb[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) xa[a] = (i0 + a < M) ? X[(i0 + a) * ldx + l] : c2{0, 0};
+#pragma unroll
+      for (int b = 0; b < 3; ++b) yb[b] = (j0 + b < N) ? Y[l * ldy + j0 + b] : c2{0, 0};
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+          const c2 t = cmul(xa[a], yb[b]);
+          acc[a][b].r += t.r;
+          acc[a][b].i += t.i;
+        }
     }
-    T[i * r + c] = s;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+        if (i0 + a < M && j0 + b < N) C[(i0 + a) * ldc + j0 + b] = acc[a][b];
   }
-  __syncthreads();
-  for (int e = tid; e < r * r; e += nt) {
-    const int a = e / r, b = e % r;
-    c2 s = {0, 0};
-#pragma unroll 4
-    for (int l = 0; l < q; ++l) {
-      const c2 t = cmulc(Z[l * r + a], T[l * r + b]);
-      s.r += t.r;
-      s.i += t.i;
-    }
-    Out[a * ldo + b] = s;
-  }
-  __syncthreads();
 }
 
-// Linv (stride ldv) = L^{-1} for lower-triangular L (stride ld, r x r), row by row: row i of
-// the inverse depends on rows < i; all columns of a row in parallel.
-__device__ void lower_inv(const c2* L, int ld, c2* Linv, int ldv, int r) {
-  const int tid = threadIdx.x, nt = blockDim.x;
+// C (M x N, stride ldc) = X^* Y, X (K x M, stride ldx), Y (K x N, stride ldy).
+__device__ __forceinline__ void mm_cn(const c2* X, int ldx, const c2* Y, int ldy, c2* C, int ldc, int M, int N, int K) {
+  const int bm = (M + 2) / 3, bn = (N + 2) / 3;
+  for (int e = threadIdx.x; e < bm * bn; e += blockDim.x) {
+    const int i0 = (e / bn) * 3, j0 = (e % bn) * 3;
+    c2 acc[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) acc[a][b] = {0, 0};
+    for (int l = 0; l < K; ++l) {
+      c2 xa[3], yb[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) xa[a] = (i0 + a < M) ? X[l * ldx + i0 + a] : c2{0, 0};
+#pragma unroll
+      for (int b = 0; b < 3; ++b) yb[b] = (j0 + b < N) ? Y[l * ldy + j0 + b] : c2{0, 0};
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+          const c2 t = cmulc(xa[a], yb[b]);
+          acc[a][b].r += t.r;
+          acc[a][b].i += t.i;
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+        if (i0 + a < M && j0 + b < N) C[(i0 + a) * ldc + j0 + b] = acc[a][b];
+  }
+}
+
+// Linv (stride ldv) = L^{-1} for lower-triangular L (stride ld, r x r).  Row i of the
+// inverse depends on rows < i; four lanes share each column's inner sum.
+__device__ __forceinline__ void lower_inv(const c2* L, int ld, c2* Linv, int ldv, int r) {
+  const int tid = threadIdx.x, sub = tid & 3;
   for (int i = 0; i < r; ++i) {
     const double d = L[i * ld + i].r;
-    for (int c = tid; c < r; c += nt) {
-      c2 s = {(i == c) ? 1.0 : 0.0, 0.0};
-      if (c < i) {
-        for (int l = c; l < i; ++l) {
+    for (int cb = 0; cb < r; cb += (int)blockDim.x / 4) {
+      const int c = cb + tid / 4;
+      c2 s = {0, 0};
+      if (c < i)
+        for (int l = c + sub; l < i; l += 4) {
           const c2 t = cmul(L[i * ld + l], Linv[l * ldv + c]);
-          s.r -= t.r;
-          s.i -= t.i;
+          s.r += t.r;
+          s.i += t.i;
         }
-      } else if (c > i) {
-        s = {0.0, 0.0};
+      s.r += __shfl_xor(s.r, 1, 64);
+      s.i += __shfl_xor(s.i, 1, 64);
+      s.r += __shfl_xor(s.r, 2, 64);
+      s.i += __shfl_xor(s.i, 2, 64);
+      if (sub == 0 && c < r) {
+        c2 v = {0, 0};
+        if (c == i) v = {1.0, 0.0};
+        else if (c < i) v = {-s.r, -s.i};
+        Linv[i * ldv + c] = {v.r / d, v.i / d};
       }
-      Linv[i * ldv + c] = {s.r / d, s.i / d};
     }
     __syncthreads();
   }
 }
 
-// Unpivoted in-place Cholesky of the Hermitian positive definite r x r matrix A (lower).
-__device__ void chol(c2* A, int r, int ld) {
+// Unpivoted Cholesky of the Hermitian positive definite r x r matrix A (full square kept,
+// overwritten); the factor's columns go to L (stride ld, lower triangle).
+__device__ __forceinline__ void chol(c2* A, c2* L, int r, int ld) {
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int k = 0; k < r; ++k) {
     double d = A[k * ld + k].r;
-    d = d > 1e-300 ? sqrt(d) : 1e-150;
-    __syncthreads();
-    for (int i = k + 1 + tid; i < r; i += nt) {
-      const c2 a = A[i * ld + k];
-      A[i * ld + k] = {a.r / d, a.i / d};
-    }
-    if (tid == 0) A[k * ld + k] = {d, 0.0};
-    __syncthreads();
-    const int rem = r - k - 1;
+    d = d > 1e-300 ? d : 1e-300;
+    const double piv = sqrt(d), invd = 1.0 / d;
+    const int rem = r - k;
     for (int e = tid; e < rem * rem; e += nt) {
-      const int i = k + 1 + e / rem, j = k + 1 + e % rem;
-      if (j > i) continue;
-      const c2 t = cmulc(A[j * ld + k], A[i * ld + k]);
-      A[i * ld + j] = {A[i * ld + j].r - t.r, A[i * ld + j].i - t.i};
+      const int i = k + e / rem, j = k + e % rem;
+      if (j == k) {
+        L[i * ld + k] = (i == k) ? c2{piv, 0.0} : c2{A[i * ld + k].r / piv, A[i * ld + k].i / piv};
+      } else if (i > k) {
+        const c2 t = cmulc(A[j * ld + k], A[i * ld + k]);
+        A[i * ld + j] = {A[i * ld + j].r - t.r * invd, A[i * ld + j].i - t.i * invd};
+      }
     }
     __syncthreads();
   }
@@ -125,7 +167,7 @@ __device__ void chol(c2* A, int r, int ld) {
 
 // Number of eigenvalues of the real symmetric tridiagonal (d, e; e[i] couples i, i+1)
 // that are below x (Sturm sequence of the LDL^T factorisation of T - x I).
-__device__ int sturm_count(const double* d, const double* e2, int r, double x, double tiny) {
+__device__ __forceinline__ int sturm_count(const double* d, const double* e2, int r, double x, double tiny) {
   int c = 0;
   double qv = d[0] - x;
   if (qv < 0) ++c;
@@ -160,9 +202,7 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
   theta += (size_t)slot * want;
   count += slot;
   const double zero_thr = zthr ? zthr[slot] : -INFINITY;
-  __shared__ double sh[32];
-  __shared__ int rank_s, nsel_s, piv_s, second_s;
-  __shared__ double pivv_s;
+  __shared__ int rank_s, second_s;
   // per-index arrays at the start of the dynamic LDS block, matrices after them (or in the
   // global work array when they do not fit)
   c2* phase = smem;
@@ -180,11 +220,11 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
   c2* B = A + q * q;
   c2* Z = B + q * q;
   c2* T = Z + q * q;
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
   double* stamp = work + 10 * q * q + 8 * q + 1;
   if (tid == 0) { stamp[0] = (double)wall_clock64(); stamp[7] = (double)clock64(); }
 
-  // ---- 1. scaled G and pivoted Cholesky --------------------------------------------------
+  // ---- 1. scaled G and pivoted Cholesky (factor columns into B, rows in pivot order) -------
   for (int i = tid; i < q; i += nt) {
     const double gd = G[i * q + i].r;
     dsc[i] = gd > 0 ? 1.0 / sqrt(gd) : 0.0;
@@ -200,21 +240,30 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
   }
   __syncthreads();
   int r = 0;
+  const int ty = tid >> 4, tx = tid & 15;   // 16 x 16 layout for the trailing updates
   for (int k = 0; k < q; ++k) {
-    if (tid == 0) {   // pivot search: one thread, independent (pipelined) LDS loads
-      double v = -1.0;
-      int idx = q;
-      const int hi = k < nfix ? k + 1 : q;
-      for (int j = k; j < hi; ++j) {
+    // pivot: largest remaining diagonal (the first nfix stay in order); every wave finds
+    // it itself (same lanes, same order, identical result).  Below nfix only A[k][k] is
+    // read, which this step's update does not write.
+    double v;
+    int idx;
+    if (k < nfix) {
+      v = A[k * q + k].r;
+      idx = k;
+    } else {
+      v = -1.0;
+      idx = q;
+      for (int j = k + lane; j < q; j += 64) {
         const double dv = A[j * q + j].r;
         if (dv > v) { v = dv; idx = j; }
       }
-      pivv_s = v;
-      piv_s = idx;
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(v, o, 64);
+        const int oi = __shfl_xor(idx, o, 64);
+        if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+      }
+      __syncthreads();   // all waves have read the diagonal before it changes
     }
-    __syncthreads();
-    const double v = pivv_s;
-    const int idx = piv_s;
     if (!(v > drop_rel)) break;
     if (v < 1e-4 && tid == 0) second_s = 1;
     if (idx != k) {
@@ -222,6 +271,11 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
         const c2 t = A[k * q + c];
         A[k * q + c] = A[idx * q + c];
         A[idx * q + c] = t;
+        if (c < k) {
+          const c2 u = B[k * q + c];
+          B[k * q + c] = B[idx * q + c];
+          B[idx * q + c] = u;
+        }
       }
       __syncthreads();
       for (int c = tid; c < q; c += nt) {
@@ -236,18 +290,19 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
       }
       __syncthreads();
     }
-    const double piv = sqrt(A[k * q + k].r);
-    for (int i = k + 1 + tid; i < q; i += nt) {
-      const c2 a = A[i * q + k];
-      A[i * q + k] = {a.r / piv, a.i / piv};
-    }
-    __syncthreads();
-    if (tid == 0) A[k * q + k] = {piv, 0.0};
-    const int rem = q - k - 1;
-    for (int e = tid; e < rem * rem; e += nt) {   // full trailing square (swaps stay valid)
-      const int i = k + 1 + e / rem, j = k + 1 + e % rem;
-      const c2 t = cmulc(A[j * q + k], A[i * q + k]);
-      A[i * q + j] = {A[i * q + j].r - t.r, A[i * q + j].i - t.i};
+    // factor column k into B and the full trailing square of A in one pass (column k of A
+    // is only read here)
+    const double d = A[k * q + k].r;
+    const double piv = sqrt(d), invd = 1.0 / d;
+    if (tx == 0)
+      for (int i = k + ty; i < q; i += 16)
+        B[i * q + k] = (i == k) ? c2{piv, 0.0} : c2{A[i * q + k].r / piv, A[i * q + k].i / piv};
+    for (int i = k + 1 + ty; i < q; i += 16) {
+      const c2 aik = A[i * q + k];
+      for (int j = k + 1 + tx; j < q; j += 16) {
+        const c2 t = cmulc(A[j * q + k], aik);
+        A[i * q + j] = {A[i * q + j].r - t.r * invd, A[i * q + j].i - t.i * invd};
+      }
     }
     __syncthreads();
     r = k + 1;
@@ -258,7 +313,7 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
   if (tid == 0) stamp[1] = (double)wall_clock64();
 
   // ---- 2. Z = D P [L^{-*}; 0] -------------------------------------------------------------
-  lower_inv(A, q, B, q, r);
+  lower_inv(B, q, A, q, r);
   for (int i = tid; i < q; i += nt) pinv[perm[i]] = i;
   __syncthreads();
   for (int e = tid; e < q * r; e += nt) {
@@ -266,21 +321,24 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
     const int pi = pinv[i];
     c2 z = {0.0, 0.0};
     if (pi < r && pi <= c) {
-      const c2 l = B[c * q + pi];
+      const c2 l = A[c * q + pi];
       z = {dsc[i] * l.r, -dsc[i] * l.i};
     }
     Z[i * r + c] = z;
   }
   __syncthreads();
   if (second_s) {   // G2 = Z^* G Z = L2 L2^*, Z <- Z L2^{-*}
-    aha(G, q, Z, r, T, A, r);
-    chol(A, r, r);
-    lower_inv(A, r, B, r, r);
+    mm_nn(G, q, Z, r, T, r, q, r, q);
+    __syncthreads();
+    mm_cn(Z, r, T, r, A, r, r, r, q);
+    __syncthreads();
+    chol(A, B, r, r);
+    lower_inv(B, r, A, r, r);
     for (int e = tid; e < q * r; e += nt) {
       const int i = e / r, c = e % r;
       c2 s = {0, 0};
       for (int l = 0; l <= c; ++l) {
-        const c2 t = cmulc(B[c * r + l], Z[i * r + l]);
+        const c2 t = cmulc(A[c * r + l], Z[i * r + l]);
         s.r += t.r;
         s.i += t.i;
       }
@@ -293,7 +351,10 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
   if (tid == 0) stamp[2] = (double)wall_clock64();
 
   // ---- 3. H' = Z^* H Z (A, stride r), Hermitian part, then tridiagonalisation ----------------
-  aha(H, q, Z, r, T, A, r);
+  mm_nn(H, q, Z, r, T, r, q, r, q);
+  __syncthreads();
+  mm_cn(Z, r, T, r, A, r, r, r, q);
+  __syncthreads();
   for (int e = tid; e < r * r; e += nt) {
     const int a = e / r, b = e % r;
     if (a < b) {
@@ -310,20 +371,17 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
   // Householder: at step k the column below the diagonal, x = A[k+1:, k], is mapped to
   // beta e1 by H_k = I - tau v v^* (v stored in row k of B, entries k+1..r-1); the trailing
   // block becomes H_k A22 H_k via p = tau A22 v, w = p - (tau/2)(v^* p) v,
-  // A22 <- A22 - v w^* - w v^*.  T holds p and w.
+  // A22 <- A22 - v w^* - w v^*.  T holds p.  Every wave forms the column norm and v^* p
+  // itself (same lanes, same order: identical values in all waves).
   c2* pv = T;
   for (int k = 0; k + 2 < r; ++k) {
     const int m = r - k - 1;
-    if (tid == 0) {
-      double part = 0;
-      for (int j = 0; j < m; ++j) {
-        const c2 x = A[(k + 1 + j) * r + k];
-        part += x.r * x.r + x.i * x.i;
-      }
-      sh[0] = part;
+    double part = 0;
+    for (int j = lane; j < m; j += 64) {
+      const c2 x = A[(k + 1 + j) * r + k];
+      part += x.r * x.r + x.i * x.i;
     }
-    __syncthreads();
-    const double xn2 = sh[0];
+    const double xn2 = wave_sum(part);
     const c2 x0 = A[(k + 1) * r + k];
     const double ax0 = sqrt(x0.r * x0.r + x0.i * x0.i);
     const double sig = xn2 - ax0 * ax0;
@@ -346,38 +404,42 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
     if (tid == 0) { tau[k] = tk; dd[k] = A[k * r + k].r; }
     __syncthreads();
     const c2* v = B + k * r;
-    for (int i = tid; i < m; i += nt) {   // p = tau A22 v
-      c2 s = {0, 0};
-      const int row = k + 1 + i;
-#pragma unroll 4
-      for (int l = 0; l < m; ++l) {
-        const c2 t = cmul(A[row * r + k + 1 + l], v[k + 1 + l]);
-        s.r += t.r;
-        s.i += t.i;
+    {   // p = tau A22 v, four lanes per row
+      const int sub = tid & 3;
+      for (int rb = 0; rb < m; rb += nt / 4) {
+        const int i = rb + tid / 4;
+        c2 s = {0, 0};
+        if (i < m) {
+          const c2* row = A + (k + 1 + i) * r + k + 1;
+          for (int l = sub; l < m; l += 4) {
+            const c2 t = cmul(row[l], v[k + 1 + l]);
+            s.r += t.r;
+            s.i += t.i;
+          }
+        }
+        s.r += __shfl_xor(s.r, 1, 64);
+        s.i += __shfl_xor(s.i, 1, 64);
+        s.r += __shfl_xor(s.r, 2, 64);
+        s.i += __shfl_xor(s.i, 2, 64);
+        if (sub == 0 && i < m) pv[i] = {tk * s.r, tk * s.i};
       }
-      pv[i] = {tk * s.r, tk * s.i};
     }
     __syncthreads();
-    if (tid == 0) {
-      double kp = 0;
-      for (int i = 0; i < m; ++i) kp += cmulc(v[k + 1 + i], pv[i]).r;
-      sh[1] = kp;
-    }
-    __syncthreads();
-    const double Kh = 0.5 * tk * sh[1];
-    for (int i = tid; i < m; i += nt) {
+    double kp = 0;
+    for (int i = lane; i < m; i += 64) kp += cmulc(v[k + 1 + i], pv[i]).r;
+    const double Kh = 0.5 * tk * wave_sum(kp);
+    for (int i = ty; i < m; i += 16) {
       const c2 vi = v[k + 1 + i];
-      pv[i] = {pv[i].r - Kh * vi.r, pv[i].i - Kh * vi.i};
+      const c2 wi = {pv[i].r - Kh * vi.r, pv[i].i - Kh * vi.i};
+      for (int j = tx; j < m; j += 16) {
+        const c2 vj = v[k + 1 + j];
+        const c2 wj = {pv[j].r - Kh * vj.r, pv[j].i - Kh * vj.i};
+        const c2 t1 = cmulc(wj, vi), t2 = cmulc(vj, wi);   // v_i conj(w_j), w_i conj(v_j)
+        c2& a = A[(k + 1 + i) * r + k + 1 + j];
+        a = {a.r - t1.r - t2.r, a.i - t1.i - t2.i};
+      }
     }
-    __syncthreads();
-    for (int e = tid; e < m * m; e += nt) {
-      const int i = e / m, j = e % m;
-      const c2 vi = v[k + 1 + i], vj = v[k + 1 + j], wi = pv[i], wj = pv[j];
-      const c2 t1 = cmulc(wj, vi), t2 = cmulc(vj, wi);   // v_i conj(w_j), w_i conj(v_j)
-      c2& a = A[(k + 1 + i) * r + k + 1 + j];
-      a = {a.r - t1.r - t2.r, a.i - t1.i - t2.i};
-    }
-    if (tid == 0) A[(k + 1) * r + k] = beta;
+    if (tid == 0) A[(k + 1) * r + k] = beta;   // column k: outside the updated block
     __syncthreads();
   }
   // real tridiagonal: T' = Phi^* T Phi with Phi = diag(phase), off-diagonals |T_{k+1,k}|
@@ -398,31 +460,48 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
   __syncthreads();
   if (tid == 0) stamp[4] = (double)wall_clock64();
 
-  // ---- 4. wanted eigenvalues (bisection) and eigenvectors (inverse iteration) -------------
+  // ---- 4. wanted eigenvalues (multisection) and eigenvectors (inverse iteration) ----------
   double tn = 0;   // infinity norm of the tridiagonal
   for (int i = 0; i < r; ++i) tn = fmax(tn, fabs(dd[i]) + (i > 0 ? ee[i - 1] : 0.0) + ee[i]);
   const double lo0 = -tn - 1.0, hi0 = tn + 1.0;
   const double tiny = 1e-300 + 1e-16 * tn * 1e-10;
   const int nz = (zero_thr > lo0) ? sturm_count(dd, ee2, r, zero_thr * (1 + 1e-14) + 1e-300, tiny) : 0;
   const int ns = min(want, r - nz);
-  for (int j = tid; j < ns; j += nt) {     // the (nz + j)-th smallest eigenvalue
-    const int target = nz + j;
-    double lo = lo0, hi = hi0;
-    for (int it = 0; it < 200 && hi - lo > 4e-16 * fmax(fabs(lo), fabs(hi)) + 1e-300; ++it) {
-      const double mid = 0.5 * (lo + hi);
-      if (mid <= lo || mid >= hi) break;          // no representable midpoint left
-      if (sturm_count(dd, ee2, r, mid, tiny) > target) hi = mid; else lo = mid;
+  {
+    // eight lanes per eigenvalue: each round splits [lo, hi] at 7 interior points and keeps
+    // the eighth that holds the (nz + j)-th eigenvalue (all lanes of a group agree)
+    const int sub = tid % GS;
+    for (int jb = 0; jb < ns; jb += nt / GS) {
+      const int j = jb + tid / GS;
+      if (j < ns) {
+        const int target = nz + j;
+        double lo = lo0, hi = hi0;
+        for (int it = 0; it < 100; ++it) {
+          if (!(hi - lo > 4e-16 * fmax(fabs(lo), fabs(hi)) + 1e-300)) break;
+          const double x = lo + (hi - lo) * (double)(sub + 1) / (double)GS;
+          const bool inside = sub < GS - 1 && x > lo && x < hi;
+          const int c = inside ? sturm_count(dd, ee2, r, x, tiny) : -1;
+          double nlo = (inside && c <= target) ? x : lo;
+          double nhi = (inside && c > target) ? x : hi;
+          for (int o = 1; o < GS; o <<= 1) {
+            nlo = fmax(nlo, __shfl_xor(nlo, o, 64));
+            nhi = fmin(nhi, __shfl_xor(nhi, o, 64));
+          }
+          if (nlo == lo && nhi == hi) break;   // no representable interior point left
+          lo = nlo;
+          hi = nhi;
+        }
+        if (sub == 0) lam[j] = 0.5 * (lo + hi);
+      }
     }
-    lam[j] = 0.5 * (lo + hi);
   }
-  if (tid == 0) nsel_s = ns;
   __syncthreads();
+  if (tid == 0) stamp[9] = (double)wall_clock64();
   // Inverse iteration on T' - lambda I with partial pivoting; eigenvalues closer than
-  // 1e-9 tn form a cluster, whose vectors are computed one after the other by one thread
+  // 1e-6 tn form a cluster, whose vectors are computed one after the other by one thread
   // and Gram-Schmidt-orthogonalised against the cluster's earlier vectors.  Real vectors
-  // of length r are kept in T (as doubles): vec j at xs + j*r; the LU work arrays after.
-  // x vectors (real, length r) at the start of T; per cluster head j the LU of
-  // T' - lambda I (3 arrays of length r) in the free A region, continued in T's tail
+  // of length r are kept in T (as doubles): vec j at xs + j*r.  Per cluster head j the LU
+  // of T' - lambda I (3 arrays of length r) lies in the free A region, continued in T's tail
   // (at most want*r + 3*want*r <= 4 q^2 doubles, the size of A and T together).
   double* xs = reinterpret_cast<double*>(T);
   const int clus_in_a = (2 * q * q) / (3 * r > 0 ? 3 * r : 1);
@@ -479,7 +558,7 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
             x[i + 1] -= l * x[i];
           }
         }
-        // back substitution with U (diagonal u, super u1, super-super u2)
+        // back substitution with U (diagonal u, super u1, super-super e_{i+1} on swaps)
         for (int i = r - 1; i >= 0; --i) {
           double s = x[i];
           if (i + 1 < r) s -= u1[i] * x[i + 1];
@@ -505,7 +584,7 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
   if (tid == 0) stamp[5] = (double)wall_clock64();
 
   // ---- 5. back-transformation: y = H_0 ... H_{r-3} Phi x, then Y = Z y ----------------------
-  // complex vectors of length r in A (stride ns... use column-major: yv[c * r + i])
+  // complex vectors of length r, column-major in the A region: yv[c * r + i]
   c2* yv = A;
   for (int e = tid; e < ns * r; e += nt) {
     const int c = e / r, i = e % r;
@@ -513,36 +592,69 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
     yv[e] = {phase[i].r * xv, phase[i].i * xv};
   }
   __syncthreads();
-  for (int k = r - 3; k >= 0; --k) {
-    const double tk = tau[k];
-    if (tk == 0.0) continue;
-    const c2* v = B + k * r;
-    // y_c -= tau v (v^* y_c), one thread per column
-    for (int c = tid; c < ns; c += nt) {
-      c2 s = {0, 0};
-      for (int i = k + 1; i < r; ++i) {
-        const c2 t = cmulc(v[i], yv[c * r + i]);
-        s.r += t.r;
-        s.i += t.i;
-      }
-      for (int i = k + 1; i < r; ++i) {
-        const c2 t = cmul(v[i], s);
-        yv[c * r + i] = {yv[c * r + i].r - tk * t.r, yv[c * r + i].i - tk * t.i};
+  {
+    // eight lanes per vector; lane `sub` owns the rows i = sub mod 8 throughout, so the
+    // reflections need no barrier (v^* y is combined by shuffles inside the group)
+    const int sub = tid % GS;
+    for (int cb = 0; cb < ns; cb += nt / GS) {
+      const int c = cb + tid / GS;
+      if (c < ns) {
+        c2* y = yv + (size_t)c * r;
+        for (int k = r - 3; k >= 0; --k) {
+          const double tk = tau[k];
+          if (tk == 0.0) continue;
+          const c2* v = B + k * r;
+          const int i0 = k + 1 + ((sub - (k + 1)) % GS + GS) % GS;
+          c2 s = {0, 0};
+          for (int i = i0; i < r; i += GS) {
+            const c2 t = cmulc(v[i], y[i]);
+            s.r += t.r;
+            s.i += t.i;
+          }
+          for (int o = 1; o < GS; o <<= 1) {
+            s.r += __shfl_xor(s.r, o, 64);
+            s.i += __shfl_xor(s.i, o, 64);
+          }
+          for (int i = i0; i < r; i += GS) {
+            const c2 t = cmul(v[i], s);
+            y[i] = {y[i].r - tk * t.r, y[i].i - tk * t.i};
+          }
+        }
       }
     }
   }
   __syncthreads();
-  for (int e = tid; e < q * want; e += nt) {
-    const int i = e / want, c = e % want;
-    c2 s = {0, 0};
-    if (c < ns) {
+  // Y (q x want) = Z (q x r) y; columns ns..want-1 zero
+  {
+    const int bm = (q + 2) / 3, bn = (want + 2) / 3;
+    for (int e = tid; e < bm * bn; e += nt) {
+      const int i0 = (e / bn) * 3, j0 = (e % bn) * 3;
+      c2 acc[3][3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) acc[a][b] = {0, 0};
       for (int l = 0; l < r; ++l) {
-        const c2 t = cmul(Z[i * r + l], yv[c * r + l]);
-        s.r += t.r;
-        s.i += t.i;
+        c2 za[3], yb[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) za[a] = (i0 + a < q) ? Z[(i0 + a) * r + l] : c2{0, 0};
+#pragma unroll
+        for (int b = 0; b < 3; ++b) yb[b] = (j0 + b < ns) ? yv[(j0 + b) * r + l] : c2{0, 0};
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int b = 0; b < 3; ++b) {
+            const c2 t = cmul(za[a], yb[b]);
+            acc[a][b].r += t.r;
+            acc[a][b].i += t.i;
+          }
       }
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+          if (i0 + a < q && j0 + b < want) Y[(i0 + a) * want + j0 + b] = acc[a][b];
     }
-    Y[i * want + c] = s;
   }
   for (int c = tid; c < want; c += nt) theta[c] = c < ns ? lam[c] : 0.0;
   if (tid == 0) {
@@ -562,7 +674,7 @@ void ritz_small(const double* G, const double* H, int q, int nfix, int want, con
     int dev = 0, cap = 65536;
     (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&cap, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) cap = 65536;
-    cap -= 1024;   // the kernel's static LDS (reduction scratch and scalars) is below 1 KB
+    cap -= 1024;   // the kernel's static LDS (scalars) is below 1 KB
     if (cap > 0 && (hipFuncSetAttribute((const void*)k_ritz<true>, hipFuncAttributeMaxDynamicSharedMemorySize, cap) != hipSuccess ||
                     hipFuncSetAttribute((const void*)k_ritz<false>, hipFuncAttributeMaxDynamicSharedMemorySize, cap) != hipSuccess))
       cap = 64 * 1024 - 1024;

@@ -415,13 +415,13 @@ int ritz_step(bl_solver* s, const std::vector<int>& slots, int q, int nfix, bool
   block_combine(cv(Sv), q, s->Yd, s->p, g.ne, view(s->E, s->p), L);
   s->launches += 4;
   if (s->debug && !slots.empty()) {
-    double sw[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double sw[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     const double* base = s->ritz_work + (size_t)slots[0] * s->ritz_stride;
-    (void)hipMemcpyAsync(sw, base + 10 * q * q + 8 * q, 10 * 8, hipMemcpyDeviceToHost, s->st);
+    (void)hipMemcpyAsync(sw, base + 10 * q * q + 8 * q, 11 * 8, hipMemcpyDeviceToHost, s->st);
     (void)hipStreamSynchronize(s->st);
-    std::fprintf(stderr, "bloch: ritz q=%d slots=%zu rank %.0f  shader MHz %.0f  phase us: chol %.1f basis %.1f hprime %.1f tridiag %.1f eig %.1f back %.1f\n",
+    std::fprintf(stderr, "bloch: ritz q=%d slots=%zu rank %.0f  shader MHz %.0f  phase us: chol %.1f basis %.1f hprime %.1f tridiag %.1f bisect %.1f invit %.1f back %.1f\n",
                  q, slots.size(), sw[0], (sw[9] - sw[8]) / ((sw[7] - sw[1]) * 0.01), (sw[2] - sw[1]) * 0.01, (sw[3] - sw[2]) * 0.01, (sw[4] - sw[3]) * 0.01,
-                 (sw[5] - sw[4]) * 0.01, (sw[6] - sw[5]) * 0.01, (sw[7] - sw[6]) * 0.01);
+                 (sw[5] - sw[4]) * 0.01, (sw[10] - sw[5]) * 0.01, (sw[6] - sw[10]) * 0.01, (sw[7] - sw[6]) * 0.01);
   }
   return BL_OK;
 }
