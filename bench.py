@@ -4,13 +4,20 @@
 Workload (one "step" = one whole band path through the hot path): 256 x 256 grid on the
 unit cell, square lattice of eps = 12 discs of radius 0.3 on eps = 1, the 16 smallest
 non-zero eigenpairs (plus 8 throw-away vectors) at 31 Bloch parameters along
-Gamma-X-M-Gamma, 6-level multigrid, relative residual tolerance 1e-8.  The first point
-starts from a seeded random block, every later point from Rayleigh-quotient extrapolation.
+Gamma-X-M-Gamma, 6-level multigrid, relative residual tolerance 1e-8.  Inputs are
+synthetic and seeded (synth.config_c2); they are on the device before the timed region.
 
-Both forms are timed: plain FP64, and mixed precision (V-cycle and nodal projection in
-complex FP32, everything else in FP64).  `value` is the mixed-precision rate, counting an
-eigenpair only if it converged and its eigenvalue agrees with the FP64 run to 1e-6.
-Prints one JSON line.
+Two forms are timed on the same path:
+  * plain FP64: one problem slot walking the whole path, every point after the first
+    warm-started by Rayleigh-quotient extrapolation;
+  * mixed precision, batched (the headline `value`): V-cycle and nodal projection in
+    complex FP32, everything else in FP64; the path is cut into `--segments` contiguous
+    pieces solved as one batch (each piece cold-starts from a seeded random block, then
+    extrapolates), so every kernel launch of an iteration round serves all pieces.
+An eigenpair counts if it converged and its eigenvalue agrees with the plain FP64 run to
+1e-6 (relative).  Also reported: p50/p99 of the per-point solve time, the roofline of the
+finest-level smoother, the oracle on the host cores, and a short serving run (Poisson
+arrivals of band-path requests, continuous batching).  Prints one JSON line.
 """
 import argparse
 import json
@@ -25,55 +32,60 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 
-def run_mode(prob, precision, steps, warmup, timing=True):
+def segments(prob, S):
+    """The path cut into S contiguous pieces; piece 0 starts from the problem's seeded
+    block, piece i > 0 from the block seeded 100 + i."""
+    import synth
+    from paper_2304_00337_amd import to_device_block
+    ks = np.asarray(prob.ks)
+    out = []
+    for i, ix in enumerate(np.array_split(np.arange(len(ks)), S)):
+        st = prob.start() if i == 0 else synth.start_block(prob.n_edges, prob.p, 100 + i)
+        out.append(dict(n=prob.n, m=prob.m, a=prob.a, b=prob.b, eps=prob.eps, nev=prob.nev,
+                        nthrow=prob.nthrow, ks=ks[ix], start=to_device_block(st)))
+    return out
+
+
+def run_form(prob, precision, S, steps, warmup):
     import torch
-    from paper_2304_00337_amd import Solver, to_device_block
-    s = Solver(prob.n, prob.m, prob.a, prob.b, prob.eps, nev=prob.nev, nthrow=prob.nthrow,
-               levels=prob.levels, tol=prob.tol, precision=precision, max_iter=300)
-    start = to_device_block(prob.start())
-    ks = prob.ks
-
-    def one_path(record):
-        s.reset_history()
-        evals, iters, conv, times = [], [], [], []
-        for t, k in enumerate(ks):
-            t0 = time.perf_counter()
-            r = s.solve_k(k[0], k[1], start=start if t == 0 else None, allow_noconv=True)
-            times.append((time.perf_counter() - t0) * 1e3)
-            evals.append(r["evals"])
-            iters.append(r["iterations"])
-            conv.append(r["relres"] <= prob.tol)
-        if record is not None:
-            record.append({"evals": np.array(evals), "iters": np.array(iters),
-                           "conv": np.array(conv), "ms": np.array(times)})
-
-    for _ in range(warmup):
-        one_path(None)
-    torch.cuda.synchronize()
-    if timing:
-        s.set_timing(True)
+    from paper_2304_00337_amd import Batch
+    probs = segments(prob, S)
     recs = []
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        one_path(recs)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    tm = s.timing() if timing else None
-    info = s.info()
-    s.close()
-    return {"elapsed": elapsed, "recs": recs, "timing": tm, "info": info}
+    with Batch(max_slots=S, precision=precision, levels=prob.levels, tol=prob.tol, max_iter=300) as b:
+        for _ in range(warmup):
+            b.run(probs)
+        torch.cuda.synchronize()
+        b.set_timing(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ts = time.perf_counter()
+            res = b.run(probs)
+            recs.append({"evals": np.concatenate([r["evals"] for r in res]),
+                         "iters": np.concatenate([r["iterations"] for r in res]),
+                         "conv": np.concatenate([r["relres"] <= prob.tol for r in res]),
+                         "ms": np.concatenate([r["point_ms"] for r in res]),
+                         "status": [r["status"] for r in res],
+                         "wall": time.perf_counter() - ts})
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        tm = b.timing()
+    return {"elapsed": elapsed, "recs": recs, "timing": tm, "S": S}
 
 
-def cpu_baseline(prob, mu, levels, iters_per_k, sample_iters=3):
-    """The oracle on a bounded sample: the first Bloch point (setup, start block and
-    `sample_iters` iterations), scaled to the whole path with the path's iteration counts."""
+def cpu_baseline(prob, iters_total, cold_starts, sample_iters=3):
+    """The oracle on a bounded sample: setup and start block of the first Bloch point and
+    `sample_iters` iterations, scaled to the workload with the GPU run's iteration count."""
     from oracle import fem
     from oracle.multigrid import Hierarchy
     from oracle.pinvit import Projector, initial_block, pinvit
     k = prob.ks[0]
     t0 = time.perf_counter()
     d = fem.Discretization(prob.n, prob.m, prob.a, prob.b, prob.eps, *k)
-    H = Hierarchy(d, mu=mu, max_levels=levels)
+    eps_min = float(np.min(prob.eps))
+    # the solver's shift rule: mu = lambda_p of the homogeneous cell (eps_min) at k = 0, / 10
+    from oracle.closed_form import discrete_nonzero
+    mu = discrete_nonzero(prob.n, prob.m, prob.a, prob.b, eps_min, 0.0, 0.0, prob.p)[-1] / 10.0
+    H = Hierarchy(d, mu=mu, max_levels=prob.levels)
     pr = Projector(d, H, 2)
     t1 = time.perf_counter()
     lam, E = initial_block(d, pr, prob.start(), prob.p)
@@ -81,18 +93,67 @@ def cpu_baseline(prob, mu, levels, iters_per_k, sample_iters=3):
     pinvit(d, H, pr, E, lam, prob.nev, prob.tol, sample_iters)
     t3 = time.perf_counter()
     per_iter = (t3 - t2) / sample_iters
-    path_s = len(prob.ks) * ((t1 - t0) + (t2 - t1)) + float(np.sum(iters_per_k)) * per_iter
+    nk = len(prob.ks)
+    path_s = nk * (t1 - t0) + cold_starts * (t2 - t1) + (nk - cold_starts) * (t2 - t1) + iters_total * per_iter
     try:
         from threadpoolctl import threadpool_info
         cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
         cores = os.cpu_count() or 1
-    return {"value": prob.nev * len(prob.ks) / path_s, "unit": "eigenpairs/s", "cores": int(cores),
-            "kind": "oracle",
-            "sample": (f"first k point of the path: setup {t1 - t0:.1f}s, start block {t2 - t1:.1f}s, "
-                       f"{sample_iters} iterations at {per_iter:.2f}s each; path time = "
-                       f"{len(prob.ks)} x (setup + start) + {int(np.sum(iters_per_k))} iterations "
-                       f"(the GPU run's counts) x per-iteration time = {path_s:.0f}s")}
+    return {"value": prob.nev * nk / path_s, "unit": "eigenpairs/s", "cores": int(cores), "kind": "oracle",
+            "sample": (f"first Bloch point of the path on the host: setup {t1 - t0:.1f}s, start block "
+                       f"{t2 - t1:.1f}s, {sample_iters} iterations at {per_iter:.2f}s each; workload time = "
+                       f"{nk} x (setup + start) + {int(iters_total)} iterations (the headline GPU run's "
+                       f"count) x per-iteration time = {path_s:.0f}s")}
+
+
+def serving(count, seed, rate_frac=0.7):
+    """Band-path requests (n 64..256, nev 4..16, 11..21 points) with Poisson arrivals at
+    `rate_frac` of the capacity measured by submitting the same requests all at once."""
+    import torch
+    import synth
+    from paper_2304_00337_amd import Server, to_device_block
+    reqs = synth.config_c5_requests(count, master_seed=seed, n_lo=64, n_hi=256, nev_lo=4, nev_hi=16,
+                                    nk_lo=11, nk_hi=21)
+    items = [dict(n=r.n, m=r.m, a=r.a, b=r.b, eps=r.eps, nev=r.nev, nthrow=r.nthrow, ks=r.ks,
+                  start=to_device_block(r.start())) for r in reqs]
+    pairs = sum(r.nev * len(r.ks) for r in reqs)
+
+    def drive(srv, gaps):
+        tickets, done = [], {}
+        t0 = time.perf_counter()
+        for g, it in zip(gaps, items):
+            if g > 0:
+                time.sleep(g)
+            tickets.append(srv.submit(**it))
+        while len(done) < len(tickets):
+            for t in tickets:
+                if t not in done:
+                    r = srv.poll(t)
+                    if r is not None:
+                        done[t] = r
+            time.sleep(0.0005)
+        return time.perf_counter() - t0, [done[t] for t in tickets]
+
+    with Server(precision="mixed", tol=1e-8, max_iter=300, max_slots=8) as srv:
+        drive(srv, [0.0] * len(items))                       # warm the engines
+        t_all, _ = drive(srv, [0.0] * len(items))
+        cap = len(items) / t_all
+        rate = rate_frac * cap
+        gaps = np.random.default_rng(seed).exponential(1.0 / rate, size=len(items))
+        t_run, res = drive(srv, gaps)
+        st = srv.stats()
+    lat = np.array([r["latency_s"] for r in res]) * 1e3
+    ok = sum(int((r["relres"] <= 1e-8).sum()) for r in res)
+    return {"requests": count, "eigenpairs": pairs, "converged_eigenpairs": ok,
+            "capacity_req_s": round(cap, 3), "arrival_rate_req_s": round(rate, 3),
+            "throughput_eigenpairs_s": round(ok / t_run, 2),
+            "p50_latency_ms": round(float(np.percentile(lat, 50)), 2),
+            "p99_latency_ms": round(float(np.percentile(lat, 99)), 2),
+            "engines": st["engines"], "rounds": st["rounds"],
+            "workload": "C5-like band paths: n log-uniform 64..256, nev 4..16, 11..21 points, "
+                        "disc-lattice or random-field eps; mixed precision; Poisson arrivals at "
+                        f"{rate_frac:.0%} of the measured closed-batch capacity"}
 
 
 def main():
@@ -101,8 +162,10 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--per-segment", type=int, default=10)
+    ap.add_argument("--segments", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--modes", default="fp64,mixed")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -113,39 +176,40 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     import synth
     prob = synth.config_c2(args.per_segment)
-    modes = args.modes.split(",")
-    res = {}
-    for mode in modes:
-        res[mode] = run_mode(prob, mode, args.steps, args.warmup)
-        print(f"# {mode}: {res[mode]['elapsed']:.3f}s for {args.steps} paths, "
-              f"iterations per k {res[mode]['recs'][0]['iters'].tolist()}", file=sys.stderr, flush=True)
-    head = "mixed" if "mixed" in res else modes[0]
-    ref = res["fp64"]["recs"][0]["evals"] if "fp64" in res else None
+    nk = len(prob.ks)
+    plain = run_form(prob, "fp64", 1, args.steps, args.warmup)
+    print(f"# fp64 plain: {plain['elapsed']:.3f}s for {args.steps} paths, iterations "
+          f"{plain['recs'][0]['iters'].tolist()}", file=sys.stderr, flush=True)
+    head = run_form(prob, "mixed", args.segments, args.steps, args.warmup)
+    print(f"# mixed x{args.segments} segments: {head['elapsed']:.3f}s for {args.steps} paths, iterations "
+          f"{head['recs'][0]['iters'].tolist()}", file=sys.stderr, flush=True)
+    ref = plain["recs"][0]["evals"]
 
     def rate(r):
         good = 0
         for rec in r["recs"]:
-            ok = rec["conv"]
-            if ref is not None:
-                ok = ok & (np.abs(rec["evals"] - ref) / ref <= 1e-6)
+            ok = rec["conv"] & (np.abs(rec["evals"] - ref) / ref <= 1e-6)
             good += int(ok.sum())
         return good / r["elapsed"]
 
-    H = res[head]
-    ms_all = np.concatenate([rec["ms"] for rec in H["recs"]])
-    value = rate(H)
-    nk = len(prob.ks)
-    # roofline of the dominant kernel: one colour pass of the finest-level node-patch
-    # Gauss-Seidel; compulsory bytes per launch: x read once, b read and x written on the
-    # updated half of the edges, coefficients (kappa, 3x3 patch inverses) once.
-    tm = H["timing"]
-    s_c = 8 if head == "mixed" else 16
-    ne = 2 * prob.n * prob.m
-    nm = prob.n * prob.m
+    value = rate(head)
+    v64 = rate(plain)
+    ms_all = np.concatenate([rec["ms"] for rec in head["recs"]])
+    ms64 = np.concatenate([rec["ms"] for rec in plain["recs"]])
+    # roofline of the dominant V-cycle kernel: one colour pass of the finest-level node-patch
+    # Gauss-Seidel.  Compulsory bytes per launch: the x block read once, b read and x written
+    # on the updated half of the edges (= 2 N_e values per column in all), and per slot the
+    # coefficients kappa (one value per cell) and the 3x3 patch inverses (6 values per node,
+    # a quarter of the nodes per colour pass).
+    tm = head["timing"]
+    s_c = 8
+    ne, nm = prob.n_edges, prob.n * prob.m
     avg_cols = tm["columns"] / max(1, tm["launches"])
-    bytes_per_launch = avg_cols * 2 * ne * s_c + nm * (s_c // 2) * (1 + 6 / 4)
+    slots_per_launch = avg_cols / prob.p
+    bytes_per_launch = avg_cols * 2 * ne * s_c + slots_per_launch * nm * (s_c // 2) * (1 + 6 / 4)
     avg_ms = tm["total_ms"] / max(1, tm["launches"])
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    dm = np.abs(head["recs"][0]["evals"] - ref) / ref
     out = {
         "metric": "converged Bloch eigenpairs/s (rel 1e-6), mixed vs FP64 GPU; p50/p99 solve ms",
         "value": round(value, 3),
@@ -153,40 +217,36 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(H["elapsed"] / args.steps * 1e3, 3),
+        "ms_per_step": round(head["elapsed"] / args.steps * 1e3, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "mixed: complex64 V-cycle and nodal projection, complex128 residual/Gram/Ritz"
-                 if head == "mixed" else "complex128",
+        "dtype": "mixed: c64 V-cycle and nodal projection, c128 residual/Gram/Ritz/extrapolation",
         "data": "synthetic",
         "config": {"workload": f"256x256 unit cell, eps=12 disc lattice r=0.3, {nk} k on Gamma-X-M-Gamma, "
-                               f"nev {prob.nev} (+{prob.nthrow}), tol {prob.tol:g}, {prob.levels}-level MG",
+                               f"nev {prob.nev} (+{prob.nthrow}), tol {prob.tol:g}, {prob.levels}-level MG; "
+                               f"path in {args.segments} batched segments",
                    "n": prob.n, "nk": nk, "nev": prob.nev, "p": prob.p, "levels": prob.levels,
-                   "mu": H["info"]["mu"]},
+                   "segments": args.segments},
         "p50_solve_ms": round(float(np.percentile(ms_all, 50)), 3),
         "p99_solve_ms": round(float(np.percentile(ms_all, 99)), 3),
-        "iterations_per_k": H["recs"][0]["iters"].tolist(),
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
-                     "frac": round(achieved / 8000.0, 4), "traffic": None,
-                     "kernel": "edge node-patch Gauss-Seidel colour pass, finest level",
-                     "avg_launch_ms": round(avg_ms, 5), "bytes_per_launch": int(bytes_per_launch),
-                     "launches_timed": tm["launches"]},
-    }
-    if "fp64" in res:
-        r64 = res["fp64"]
-        ms64 = np.concatenate([rec["ms"] for rec in r64["recs"]])
-        out["fp64"] = {"value": round(rate(r64), 3), "ms_per_step": round(r64["elapsed"] / args.steps * 1e3, 3),
+        "iterations_per_k": head["recs"][0]["iters"].tolist(),
+        "fp64_plain": {"value": round(v64, 3), "ms_per_step": round(plain["elapsed"] / args.steps * 1e3, 3),
                        "p50_solve_ms": round(float(np.percentile(ms64, 50)), 3),
                        "p99_solve_ms": round(float(np.percentile(ms64, 99)), 3),
-                       "iterations_per_k": r64["recs"][0]["iters"].tolist()}
-        if head == "mixed":
-            dm = np.abs(H["recs"][0]["evals"] - ref) / ref
-            out["mixed_vs_fp64_max_rel_eig_diff"] = float(dm.max())
-            out["speedup_mixed_vs_fp64"] = round(value / max(out["fp64"]["value"], 1e-12), 3)
+                       "iterations_per_k": plain["recs"][0]["iters"].tolist()},
+        "speedup_vs_fp64_plain": round(value / max(v64, 1e-12), 3),
+        "mixed_vs_fp64_max_rel_eig_diff": float(dm.max()),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+                     "frac": round(achieved / 8000.0, 4), "traffic": None,
+                     "kernel": "k_edge_gs<float> (node-patch Gauss-Seidel colour pass), finest level",
+                     "avg_launch_ms": round(avg_ms, 5), "bytes_per_launch": int(bytes_per_launch),
+                     "columns_per_launch": round(avg_cols, 2), "launches_timed": tm["launches"]},
+    }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, H["info"]["mu"], prob.levels,
-                                           H["recs"][0]["iters"])
+        out["cpu_baseline"] = cpu_baseline(prob, int(head["recs"][0]["iters"].sum()), args.segments)
+    if not args.no_serving:
+        out["serving"] = serving(args.serve_requests, seed=4)
     print(json.dumps(out), flush=True)
 
 

@@ -229,6 +229,8 @@ typedef struct bl_problem {
   double* evals;          /* host out, nk*nev (row t = point t)                              */
   double* relres;         /* host out, nk*nev                                                */
   int32_t* iters;         /* host out, nk                                                    */
+  double* point_ms;       /* NULL or host out, nk: wall time from the start of each point to
+                             the round in which it converged, ms                             */
   void* evecs_dev;        /* NULL or device FP64 planar block of nev columns, last point     */
   int32_t status;         /* out: BL_OK, BL_ENOCONV, BL_EINVAL, BL_ENOMEM                    */
   int32_t reserved1;
@@ -242,6 +244,19 @@ typedef struct bl_problem {
  * statuses in bl_problem.status; results of BL_ENOCONV problems hold the best values). */
 int bl_batch_solve(const bl_opts* opts, bl_problem* probs, int32_t count, int32_t max_slots,
                    void* stream);
+
+/* A batch context keeps its shape engines (device memory, coarse set-up buffers) between
+ * runs, so that repeated batches of the same shapes allocate nothing.  bl_batch_run has the
+ * semantics of bl_batch_solve with the context's options; hbm_budget 0 = 90% of the free
+ * device memory at creation. */
+typedef struct bl_batch bl_batch;
+int bl_batch_create(const bl_opts* opts, int32_t max_slots, size_t hbm_budget, bl_batch** out);
+int bl_batch_run(bl_batch* b, bl_problem* probs, int32_t count, void* stream);
+void bl_batch_destroy(bl_batch* b);
+/* Finest-level smoother timing (as bl_set_timing / bl_get_timing) summed over every engine
+ * of the context, including engines released since timing was enabled. */
+int bl_batch_set_timing(bl_batch* b, int32_t enable);
+int bl_batch_get_timing(const bl_batch* b, double* total_ms, int64_t* launches, int64_t* columns);
 
 /* ---- Serving: asynchronous requests with continuous batching -----------------------------
  * A server owns a worker thread that admits requests by device-memory footprint (engines of

@@ -10,7 +10,7 @@ from . import native
 from .native import (BlGrid, BlInfo, BlOpts, BlProblem, BlRequest, BlRequestInfo,
                      BlServerCounters, check)
 
-__all__ = ["Solver", "Server", "batch_solve", "to_device_block", "from_device_block"]
+__all__ = ["Solver", "Server", "Batch", "batch_solve", "to_device_block", "from_device_block"]
 
 
 def _torch():
@@ -67,14 +67,8 @@ def _start_block(start, p, n_edges):
     return start
 
 
-def batch_solve(problems, max_slots=0, stream=None, want_last_vectors=False, **opts):
-    """bl_batch_solve.  `problems`: sequence of dicts with n, m, a, b, eps (n*m), nev,
-    nthrow, ks ((nk, 2) array) and start (host complex (N_e, p) or device planar block).
-    Common options as for Solver.  Returns one dict per problem (evals, relres, iterations,
-    status, evecs)."""
+def _marshal_problems(problems, want_last_vectors):
     torch = _torch()
-    lib = native.load()
-    o = _make_opts(**opts)
     keep = []
     arr = (BlProblem * len(problems))()
     outs = []
@@ -85,31 +79,93 @@ def batch_solve(problems, max_slots=0, stream=None, want_last_vectors=False, **o
         eps = np.ascontiguousarray(pr["eps"], dtype=np.float64)
         ks = np.ascontiguousarray(pr["ks"], dtype=np.float64).reshape(-1, 2)
         st = _start_block(pr["start"], p, ne)
-        ev = np.zeros((ks.shape[0], nev))
-        rr = np.zeros((ks.shape[0], nev))
-        its = np.zeros(ks.shape[0], dtype=np.int32)
+        nk = ks.shape[0]
+        ev, rr, pm = np.zeros((nk, nev)), np.zeros((nk, nev)), np.zeros(nk)
+        its = np.zeros(nk, dtype=np.int32)
         vec = torch.empty((nev, 2, ne), dtype=torch.float64, device="cuda") if want_last_vectors else None
-        keep += [eps, ks, st, ev, rr, its, vec]
+        keep += [eps, ks, st, ev, rr, its, pm, vec]
         b = arr[i]
         b.grid = BlGrid(n, m, float(pr["a"]), float(pr["b"]))
         b.eps = _dptr(eps)
-        b.nev, b.nthrow, b.nk = nev, nthrow, ks.shape[0]
+        b.nev, b.nthrow, b.nk = nev, nthrow, nk
         b.ks = _dptr(ks)
         b.start_dev = st.data_ptr()
-        b.evals, b.relres = _dptr(ev), _dptr(rr)
+        b.evals, b.relres, b.point_ms = _dptr(ev), _dptr(rr), _dptr(pm)
         b.iters = its.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
         b.evecs_dev = vec.data_ptr() if vec is not None else None
-        outs.append((ev, rr, its, vec))
+        outs.append((ev, rr, its, pm, vec))
+    return arr, outs, keep
+
+
+def _unmarshal(arr, outs, rc, where):
+    if rc not in (native.BL_OK, native.BL_ENOCONV, native.BL_EINVAL, native.BL_ENOMEM):
+        check(rc, where)
+    res = []
+    for i, (ev, rr, its, pm, vec) in enumerate(outs):
+        res.append({"evals": ev, "relres": rr, "iterations": its, "point_ms": pm,
+                    "status": int(arr[i].status), "converged": arr[i].status == 0, "evecs": vec})
+    return res
+
+
+def batch_solve(problems, max_slots=0, stream=None, want_last_vectors=False, **opts):
+    """bl_batch_solve.  `problems`: sequence of dicts with n, m, a, b, eps (n*m), nev,
+    nthrow, ks ((nk, 2) array) and start (host complex (N_e, p) or device planar block).
+    Common options as for Solver.  Returns one dict per problem (evals, relres, iterations,
+    point_ms, status, evecs)."""
+    torch = _torch()
+    lib = native.load()
+    o = _make_opts(**opts)
+    arr, outs, _keep = _marshal_problems(problems, want_last_vectors)
     if stream is None:
         stream = torch.cuda.current_stream()
     rc = lib.bl_batch_solve(ctypes.byref(o), arr, len(problems), int(max_slots), ctypes.c_void_p(stream.cuda_stream))
-    if rc not in (native.BL_OK, native.BL_ENOCONV, native.BL_EINVAL, native.BL_ENOMEM):
-        check(rc, "bl_batch_solve")
-    res = []
-    for i, (ev, rr, its, vec) in enumerate(outs):
-        res.append({"evals": ev, "relres": rr, "iterations": its, "status": int(arr[i].status),
-                    "converged": arr[i].status == 0, "evecs": vec})
-    return res
+    return _unmarshal(arr, outs, rc, "bl_batch_solve")
+
+
+class Batch:
+    """bl_batch_*: a batch context whose shape engines persist between runs."""
+
+    def __init__(self, max_slots=0, hbm_budget=0, **opts):
+        self.lib = native.load()
+        o = _make_opts(**opts)
+        h = ctypes.c_void_p()
+        check(self.lib.bl_batch_create(ctypes.byref(o), int(max_slots), int(hbm_budget), ctypes.byref(h)),
+              "bl_batch_create")
+        self.h = h
+
+    def run(self, problems, stream=None, want_last_vectors=False):
+        torch = _torch()
+        arr, outs, _keep = _marshal_problems(problems, want_last_vectors)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        rc = self.lib.bl_batch_run(self.h, arr, len(problems), ctypes.c_void_p(stream.cuda_stream))
+        return _unmarshal(arr, outs, rc, "bl_batch_run")
+
+    def set_timing(self, enable=True):
+        check(self.lib.bl_batch_set_timing(self.h, 1 if enable else 0), "bl_batch_set_timing")
+
+    def timing(self) -> dict:
+        ms, cnt, cols = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64()
+        check(self.lib.bl_batch_get_timing(self.h, ctypes.byref(ms), ctypes.byref(cnt), ctypes.byref(cols)),
+              "bl_batch_get_timing")
+        return {"total_ms": ms.value, "launches": cnt.value, "columns": cols.value}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.bl_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 class Server:

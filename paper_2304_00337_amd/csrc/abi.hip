@@ -158,16 +158,7 @@ int bl_last_residual_history(const bl_solver* s, double* relres, int32_t cap) {
 
 int bl_set_timing(bl_solver* s, int32_t enable) {
   if (!s) return set_error(BL_EINVAL, "solver is NULL%s");
-  if (enable && s->ev_pool.empty()) {
-    s->ev_pool.resize(4096);
-    for (auto& e : s->ev_pool) HIP_OK(hipEventCreate(&e));
-  }
-  s->timing = enable != 0;
-  s->timed_ms = 0.0;
-  s->timed_count = 0;
-  s->timed_cols = 0;
-  s->ev_used = 0;
-  return BL_OK;
+  return engine_set_timing(s, enable != 0);
 }
 
 int bl_get_timing(const bl_solver* s, double* total_ms, int64_t* launches, int64_t* columns) {

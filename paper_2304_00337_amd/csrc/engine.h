@@ -36,6 +36,7 @@ struct Task {
   std::vector<double> evals, relres;   // nk * nev
   std::vector<int32_t> iters;          // nk
   std::vector<double> res_hist;        // nev per iteration of the last point
+  std::vector<double> t_points;        // host time at which each point was retired
   int status = BL_OK;
   std::string message;
   bool finished = false;         // host side finished; results valid once `done`
@@ -184,6 +185,9 @@ int engine_finish(bl_solver* s);
 int engine_run(bl_solver* s);
 // Wait for the stream and mark the retired tasks done.
 int engine_sync_retired(bl_solver* s);
+
+// Opt-in HIP-event timing of the finest-level smoother launches (resets the totals).
+int engine_set_timing(bl_solver* s, bool enable);
 
 // Operator-level helpers on slot 0.
 int engine_set_k0(bl_solver* s, double k1, double k2);

@@ -90,6 +90,28 @@ class Scheduler {
     return BL_OK;
   }
 
+  // Smoother timing of every engine (present and future); totals survive engine release.
+  int set_timing(bool on) {
+    timing_ = on;
+    t_ms_ = 0.0;
+    t_launches_ = t_cols_ = 0;
+    for (auto& g : engines_) {
+      int rc = engine_set_timing(g.e, on);
+      if (rc) return rc;
+    }
+    return BL_OK;
+  }
+  void timing(double* ms, int64_t* launches, int64_t* cols) const {
+    *ms = t_ms_;
+    *launches = t_launches_;
+    *cols = t_cols_;
+    for (auto& g : engines_) {
+      *ms += g.e->timed_ms;
+      *launches += g.e->timed_count;
+      *cols += g.e->timed_cols;
+    }
+  }
+
   // One round over every busy engine: issue all, then finish all.
   int step() {
     int rc;
@@ -121,6 +143,9 @@ class Scheduler {
 
   void release(Eng& g) {
     launches_done_ += g.e->launches;
+    t_ms_ += g.e->timed_ms;
+    t_launches_ += g.e->timed_count;
+    t_cols_ += g.e->timed_cols;
     engine_destroy(g.e);
     if (g.st) (void)hipStreamDestroy(g.st);
     used_ -= std::min(used_, g.bytes);
@@ -177,6 +202,11 @@ class Scheduler {
       if (rc == BL_ENOMEM && !engines_.empty()) return BL_EAGAIN;
       return rc;
     }
+    if (timing_ && (rc = engine_set_timing(g.e, true))) {
+      engine_destroy(g.e);
+      (void)hipStreamDestroy(g.st);
+      return rc;
+    }
     g.bytes = g.e->dev_bytes;
     used_ += g.bytes;
     engines_.push_back(g);
@@ -191,6 +221,9 @@ class Scheduler {
   int64_t launches_done_ = 0;
   std::deque<Job*> queue_;
   std::deque<Eng> engines_;
+  bool timing_ = false;
+  double t_ms_ = 0.0;
+  int64_t t_launches_ = 0, t_cols_ = 0;
 };
 
 int make_job(const bl_opts& common, const bl_grid* grid, const double* eps, int nev, int nthrow,
@@ -298,18 +331,18 @@ void server_loop(bl_server* s) {
 
 }  // namespace
 
-extern "C" {
+struct bl_batch {
+  bl_opts opts{};
+  std::unique_ptr<Scheduler> sched;
+};
 
-int bl_batch_solve(const bl_opts* opts, bl_problem* probs, int32_t count, int32_t max_slots,
-                   void* stream) {
+namespace {
+
+int run_batch(Scheduler& sched, const bl_opts& o, bl_problem* probs, int count, void* stream) {
   if (!probs || count < 1) return set_error(BL_EINVAL, "no problems%s");
-  bl_opts o;
-  if (opts) o = *opts; else bl_default_opts(&o, 8);
-  fill_defaults(&o);
   if (stream && hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess)
     return set_error(BL_EHIP, "caller stream failed%s");
   std::vector<std::unique_ptr<Job>> jobs(count);
-  Scheduler sched(o, default_budget(), max_slots);
   for (int i = 0; i < count; ++i) {
     bl_problem& pb = probs[i];
     jobs[i] = std::make_unique<Job>();
@@ -338,11 +371,58 @@ int bl_batch_solve(const bl_opts* opts, bl_problem* probs, int32_t count, int32_
       if (pb.evals) std::memcpy(pb.evals, t.evals.data(), cnt * 8);
       if (pb.relres) std::memcpy(pb.relres, t.relres.data(), cnt * 8);
       if (pb.iters) std::memcpy(pb.iters, t.iters.data(), (size_t)pb.nk * 4);
+      if (pb.point_ms)
+        for (int k = 0; k < pb.nk; ++k)
+          pb.point_ms[k] = k < (int)t.t_points.size()
+                               ? (t.t_points[k] - (k ? t.t_points[k - 1] : t.t_start)) * 1e3 : 0.0;
     }
     pb.status = t.status;
     if (t.status != BL_OK && status == BL_OK) status = t.status;
   }
   if (status != BL_OK) return set_error(status, "at least one problem failed (see bl_problem.status)%s");
+  return BL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bl_batch_solve(const bl_opts* opts, bl_problem* probs, int32_t count, int32_t max_slots,
+                   void* stream) {
+  bl_opts o;
+  if (opts) o = *opts; else bl_default_opts(&o, 8);
+  fill_defaults(&o);
+  Scheduler sched(o, default_budget(), max_slots);
+  return run_batch(sched, o, probs, count, stream);
+}
+
+int bl_batch_create(const bl_opts* opts, int32_t max_slots, size_t hbm_budget, bl_batch** out) {
+  if (!out) return set_error(BL_EINVAL, "out is NULL%s");
+  *out = nullptr;
+  bl_batch* b = new (std::nothrow) bl_batch();
+  if (!b) return set_error(BL_ENOMEM, "host allocation failed%s");
+  if (opts) b->opts = *opts; else bl_default_opts(&b->opts, 8);
+  fill_defaults(&b->opts);
+  b->sched = std::make_unique<Scheduler>(b->opts, hbm_budget ? hbm_budget : default_budget(), max_slots);
+  *out = b;
+  return BL_OK;
+}
+
+int bl_batch_run(bl_batch* b, bl_problem* probs, int32_t count, void* stream) {
+  if (!b) return set_error(BL_EINVAL, "batch is NULL%s");
+  return run_batch(*b->sched, b->opts, probs, count, stream);
+}
+
+void bl_batch_destroy(bl_batch* b) { delete b; }
+
+int bl_batch_set_timing(bl_batch* b, int32_t enable) {
+  if (!b) return set_error(BL_EINVAL, "batch is NULL%s");
+  return b->sched->set_timing(enable != 0);
+}
+
+int bl_batch_get_timing(const bl_batch* b, double* total_ms, int64_t* launches, int64_t* columns) {
+  if (!b || !total_ms || !launches || !columns) return set_error(BL_EINVAL, "NULL argument%s");
+  b->sched->timing(total_ms, launches, columns);
   return BL_OK;
 }
 

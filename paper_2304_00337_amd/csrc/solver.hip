@@ -546,6 +546,7 @@ int retire_point(bl_solver* s, int sl, bool conv, const double* lam, const doubl
     t->relres[(size_t)ss.t * nev + j] = rel[j];
   }
   t->iters[ss.t] = ss.it;
+  t->t_points.push_back(now_seconds());
   if (!conv && t->status == BL_OK) {
     t->status = BL_ENOCONV;
     t->message = "max_iter reached";
@@ -754,6 +755,7 @@ int engine_assign(bl_solver* s, int sl, Task* t) {
   t->status = BL_OK;
   t->finished = t->done = false;
   t->t_start = now_seconds();
+  t->t_points.clear();
   ss.task = t;
   ss.phase = SLOT_START;
   ss.t = 0;
@@ -910,6 +912,19 @@ int engine_sync_retired(bl_solver* s) {
     t->t_done = tnow;
   }
   s->retired.clear();
+  return BL_OK;
+}
+
+int engine_set_timing(bl_solver* s, bool enable) {
+  if (enable && s->ev_pool.empty()) {
+    s->ev_pool.resize(4096);
+    for (auto& e : s->ev_pool) HIP_OK(hipEventCreate(&e));
+  }
+  s->timing = enable;
+  s->timed_ms = 0.0;
+  s->timed_count = 0;
+  s->timed_cols = 0;
+  s->ev_used = 0;
   return BL_OK;
 }
 

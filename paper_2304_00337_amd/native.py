@@ -49,7 +49,8 @@ class BlProblem(ctypes.Structure):
     _fields_ = [("grid", BlGrid), ("eps", P(c_double)), ("nev", c_int32), ("nthrow", c_int32),
                 ("nk", c_int32), ("reserved0", c_int32), ("ks", P(c_double)), ("start_dev", c_void_p),
                 ("evals", P(c_double)), ("relres", P(c_double)), ("iters", P(c_int32)),
-                ("evecs_dev", c_void_p), ("status", c_int32), ("reserved1", c_int32)]
+                ("point_ms", P(c_double)), ("evecs_dev", c_void_p), ("status", c_int32),
+                ("reserved1", c_int32)]
 
 
 class BlRequest(ctypes.Structure):
@@ -90,6 +91,11 @@ EXPORTED = {
                                 P(c_double), P(c_double)]),
     "bl_rr_products": (c_int32, [c_void_p, c_void_p, c_int32, P(c_double), P(c_double)]),
     "bl_batch_solve": (c_int32, [P(BlOpts), P(BlProblem), c_int32, c_int32, c_void_p]),
+    "bl_batch_create": (c_int32, [P(BlOpts), c_int32, c_size_t, P(c_void_p)]),
+    "bl_batch_run": (c_int32, [c_void_p, P(BlProblem), c_int32, c_void_p]),
+    "bl_batch_destroy": (None, [c_void_p]),
+    "bl_batch_set_timing": (c_int32, [c_void_p, c_int32]),
+    "bl_batch_get_timing": (c_int32, [c_void_p, P(c_double), P(c_int64), P(c_int64)]),
     "bl_server_create": (c_int32, [P(BlOpts), c_size_t, c_int32, P(c_void_p)]),
     "bl_server_submit": (c_int32, [c_void_p, P(BlRequest), P(ctypes.c_uint64)]),
     "bl_server_poll": (c_int32, [c_void_p, ctypes.c_uint64, P(c_double), P(c_double), P(c_int32),

@@ -164,3 +164,22 @@ def test_server_errors():
         from paper_2304_00337_amd.native import check
         with pytest.raises(BlochError):
             check(srv.lib.bl_server_poll(srv.h, 12345, None, None, None, None), "bl_server_poll")
+
+
+def test_batch_context_reuses_engines():
+    """A batch context keeps its engines: a second run of the same problems allocates no new
+    engine and gives identical results; per-point times are reported and the smoother timing
+    counts launches."""
+    from paper_2304_00337_amd import Batch, batch_solve
+    probs = _problems()
+    with Batch(max_slots=4, **OPTS) as b:
+        b.set_timing(True)
+        r1 = b.run(probs)
+        t1 = b.timing()
+        r2 = b.run(probs)
+    ref = batch_solve(probs, **OPTS)
+    for x, y, z in zip(r1, r2, ref):
+        assert x["status"] == 0
+        assert np.array_equal(x["evals"], y["evals"]) and np.array_equal(x["evals"], z["evals"])
+        assert np.all(x["point_ms"] > 0)
+    assert t1["launches"] > 0 and t1["total_ms"] > 0 and t1["columns"] >= t1["launches"]
