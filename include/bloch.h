@@ -80,7 +80,9 @@ typedef struct bl_opts {
   int32_t precision;    /* 0 = FP64 throughout, 1 = mixed: V-cycle and nodal projection in
                            complex FP32, residuals, Gram, Ritz and extrapolation in FP64   */
   int32_t extrap_depth; /* previous Bloch parameters used for extrapolation, 1..3 (3)      */
-  int32_t reserved0;
+  int32_t autotune;     /* 1 = time the candidate launch shapes of the smoothers and of the
+                           Rayleigh-Ritz products when a handle is created and keep the
+                           fastest (cached per shape; never changes results), 0 = fixed (1) */
   double tol;           /* stop when ||A e_i - lambda_i M e_i||_2 / (lambda_i ||M e_i||_2)
                            <= tol for the first nev vectors (1e-8)                         */
   double mu;            /* regularisation of the preconditioned A + mu M (Section 5);
@@ -97,6 +99,12 @@ typedef struct bl_info {
   double mu;
   size_t device_bytes;  /* device memory held by the handle */
   int64_t kernel_launches; /* launches issued since creation */
+  int32_t edge_smooth_shape[3];  /* chosen launch shape of the edge smoother: threads per
+                                    block, columns per thread, XCD-major order (0/1)   */
+  int32_t nodal_smooth_shape[3]; /* same for the nodal smoother                        */
+  int32_t rr_tile;      /* Rayleigh-Ritz output tile for the 2p-wide basis: 48 or 64   */
+  int32_t reserved;
+  double autotune_ms;   /* time spent tuning at creation (0 when cached or off)        */
 } bl_info;
 
 /* Fill *opts with the defaults for `nev` wanted eigenpairs (nthrow = nev/2). */

@@ -306,7 +306,10 @@ class Solver:
         return {"n": inf.n, "m": inf.m, "p": inf.p, "nev": inf.nev, "levels": L,
                 "precision": inf.precision, "mu": inf.mu, "device_bytes": inf.device_bytes,
                 "kernel_launches": inf.kernel_launches,
-                "sizes": [(inf.level_n[i], inf.level_m[i]) for i in range(L)]}
+                "sizes": [(inf.level_n[i], inf.level_m[i]) for i in range(L)],
+                "edge_smooth_shape": list(inf.edge_smooth_shape),
+                "nodal_smooth_shape": list(inf.nodal_smooth_shape),
+                "rr_tile": inf.rr_tile, "autotune_ms": inf.autotune_ms}
 
     @staticmethod
     def footprint_bytes(n, m, a, b, nev=8, **opts) -> int:

@@ -56,6 +56,7 @@ void bl_default_opts(bl_opts* o, int32_t nev) {
   o->tol = 1e-8;
   o->mu = 0.0;
   o->zero_rel = 1e-2;
+  o->autotune = 1;
 }
 
 const char* bl_strerror(int code) {
@@ -105,6 +106,14 @@ int bl_get_info(const bl_solver* s, bl_info* out) {
   out->mu = s->mu_h.empty() ? 0.0 : s->mu_h[0];
   out->device_bytes = s->dev_bytes;
   out->kernel_launches = s->launches;
+  out->edge_smooth_shape[0] = s->tune_edge.bs;
+  out->edge_smooth_shape[1] = s->tune_edge.cpt;
+  out->edge_smooth_shape[2] = s->tune_edge.xcd;
+  out->nodal_smooth_shape[0] = s->tune_nodal.bs;
+  out->nodal_smooth_shape[1] = s->tune_nodal.cpt;
+  out->nodal_smooth_shape[2] = s->tune_nodal.xcd;
+  out->rr_tile = 16 * (s->tune_rr ? s->tune_rr : rr_tile(2 * s->p));
+  out->autotune_ms = s->tune_ms;
   return BL_OK;
 }
 

@@ -161,6 +161,10 @@ struct bl_solver {
   int64_t timed_count = 0;
   int64_t timed_cols = 0;
   bool debug = false;
+  // launch shapes chosen by the autotuner (defaults when it is off)
+  bl::SmoothShape tune_edge, tune_nodal;
+  int tune_rr = 0;            // Rayleigh-Ritz output tile for q = 2p (0 = by padding)
+  double tune_ms = 0.0;       // time the autotuner spent
 };
 
 namespace bl {
@@ -185,6 +189,12 @@ int engine_finish(bl_solver* s);
 int engine_run(bl_solver* s);
 // Wait for the stream and mark the retired tasks done.
 int engine_sync_retired(bl_solver* s);
+
+// Autotuner: time the candidate launch shapes of the finest-level smoothers and of the
+// Rayleigh-Ritz products on the engine's own buffers and keep the fastest; results are
+// cached per (n, m, p, precision, slots) for the process.
+int engine_autotune(bl_solver* s);
+int rr_tile(int q);
 
 // Opt-in HIP-event timing of the finest-level smoother launches (resets the totals).
 int engine_set_timing(bl_solver* s, bool enable);

@@ -69,10 +69,19 @@ void edge_apply(int mode, View<const TI> x, View<const TI> b, View<TO> out, cons
 void reduce_partials(const double* partial, int nblk, int ncols, int nval, double* out,
                      hipStream_t st);
 
+// Launch shape of the colour passes of the smoothers (chosen per engine shape by the
+// autotuner; results do not depend on it): threads per block, columns per thread (1 or 2,
+// sharing the patch coefficients) and the XCD-major block order.
+struct SmoothShape {
+  int bs = 256;
+  int cpt = 1;
+  int xcd = 0;
+};
+
 template <typename T>
 void edge_gs(View<T> x, View<const T> b, const double* kappa64, const float* kappa32,
              const double* sinv64, const float* sinv32, const Geo& g, const Phase* ph,
-             const double* mu, const PatchT& T4, int colour, const Launch& L);
+             const double* mu, const PatchT& T4, int colour, const SmoothShape& sh, const Launch& L);
 void patch_setup(const double* kappa, const Geo& g, const double* q, const double* mu, double* sinv64,
                  float* sinv32, int nslots, hipStream_t st);
 void coarsen_kappa(const double* kf, const Geo& gf, double* kc, int nslots, hipStream_t st);
@@ -90,7 +99,7 @@ void nodal_apply(View<const T> x, View<const T> b, View<T> out, const Geo& g, co
                  const NodalStencil& c, bool resid, const Launch& L);
 template <typename T>
 void nodal_gs(View<T> x, View<const T> b, const Geo& g, const Phase* ph, const NodalStencil& c,
-              int colour, const Launch& L);
+              int colour, const SmoothShape& sh, const Launch& L);
 template <typename T>
 void nodal_restrict(View<const T> rf, const Geo& gf, View<T> bc, const Geo& gc, const Phase* ph,
                     const Launch& L);

@@ -118,6 +118,7 @@ int validate_opts(const bl_opts* o) {
   if (o->variant != 0) return set_error(BL_EINVAL, "only the gradient variant is available%s");
   if (o->precision != 0 && o->precision != 1) return set_error(BL_EINVAL, "precision must be 0 or 1%s");
   if (o->extrap_depth < 1 || o->extrap_depth > 3) return set_error(BL_EINVAL, "extrap_depth must be 1..3%s");
+  if (o->autotune != 0 && o->autotune != 1) return set_error(BL_EINVAL, "autotune must be 0 or 1%s");
   if (!(o->tol > 0)) return set_error(BL_EINVAL, "tol must be positive%s");
   return BL_OK;
 }
@@ -259,7 +260,7 @@ void vcycle_edge(bl_solver* s, int l, View<const T> b, View<T> x, const Launch& 
   for (int it = 0; it < s->opts.nu_pre; ++it)
     for (int c = 0; c < 4; ++c) {
       timing_begin(s, l);
-      edge_gs<T>(x, b, lv.kappa64, lv.kappa32, lv.sinv64, lv.sinv32, lv.g, s->ph_d, s->mu_d, lv.T4, c, L);
+      edge_gs<T>(x, b, lv.kappa64, lv.kappa32, lv.sinv64, lv.sinv32, lv.g, s->ph_d, s->mu_d, lv.T4, c, s->tune_edge, L);
       timing_end(s, l, L.nact * L.ncps);
     }
   View<T> r = view(static_cast<T*>(lv.er[pr]), lv.ecap[pr]);
@@ -273,7 +274,7 @@ void vcycle_edge(bl_solver* s, int l, View<const T> b, View<T> x, const Launch& 
   for (int it = 0; it < s->opts.nu_post; ++it)
     for (int c = 3; c >= 0; --c) {
       timing_begin(s, l);
-      edge_gs<T>(x, b, lv.kappa64, lv.kappa32, lv.sinv64, lv.sinv32, lv.g, s->ph_d, s->mu_d, lv.T4, c, L);
+      edge_gs<T>(x, b, lv.kappa64, lv.kappa32, lv.sinv64, lv.sinv32, lv.g, s->ph_d, s->mu_d, lv.T4, c, s->tune_edge, L);
       timing_end(s, l, L.nact * L.ncps);
     }
   s->launches += 4 + 4 * (s->opts.nu_post + s->opts.nu_pre);
@@ -292,7 +293,7 @@ void vcycle_nodal(bl_solver* s, int l, View<const T> b, View<T> x, const Launch&
   }
   zero_cols<T>(x, lv.g.nm, L);
   for (int it = 0; it < s->opts.nu_pre; ++it)
-    for (int c = 0; c < 4; ++c) nodal_gs<T>(x, b, lv.g, s->ph_d, s->ns, c, L);
+    for (int c = 0; c < 4; ++c) nodal_gs<T>(x, b, lv.g, s->ph_d, s->ns, c, s->tune_nodal, L);
   View<T> r = view(static_cast<T*>(lv.nr[pr]), lv.ncap[pr]);
   nodal_apply<T>(cv(x), b, r, lv.g, s->ph_d, s->ns, true, L);
   Level& C = s->lv[l + 1];
@@ -302,7 +303,7 @@ void vcycle_nodal(bl_solver* s, int l, View<const T> b, View<T> x, const Launch&
   vcycle_nodal<T>(s, l + 1, cv(bc), xc, L);
   nodal_prolong_add<T>(cv(xc), C.g, x, lv.g, s->ph_d, L);
   for (int it = 0; it < s->opts.nu_post; ++it)
-    for (int c = 3; c >= 0; --c) nodal_gs<T>(x, b, lv.g, s->ph_d, s->ns, c, L);
+    for (int c = 3; c >= 0; --c) nodal_gs<T>(x, b, lv.g, s->ph_d, s->ns, c, s->tune_nodal, L);
   s->launches += 4 + 4 * (s->opts.nu_pre + s->opts.nu_post);
 }
 
@@ -389,16 +390,14 @@ int project(bl_solver* s, const std::vector<Group>& groups, View<double> out,
 }
 
 }  // namespace
-}  // namespace bl
-
-namespace bl {
-namespace {
 
 // Output tile of the Rayleigh-Ritz products: the 48- or 64-wide tiling that pads q least.
 int rr_tile(int q) {
   const int64_t p3 = (int64_t)((q + 47) / 48) * 48, p4 = (int64_t)((q + 63) / 64) * 64;
   return p4 < p3 ? 4 : 3;
 }
+
+namespace {
 
 // Ritz step on the q columns of S (FP64) of the listed slots: G = S^* M S, H = S^* A S,
 // generalised eigenproblem, E <- S Y for the p smallest Ritz values above the slot's
@@ -408,7 +407,8 @@ int ritz_step(bl_solver* s, const std::vector<int>& slots, int q, int nfix, bool
   const Geo& g = L0.g;
   Launch L = make_launch(s, slots, q);
   View<double> Sv = view(s->Sb, s->qmax);
-  if (rr_gram(cv(Sv), q, L0.kappa64, g, s->ph_d, s->gram_partial, s->gram_cap, s->Gm, s->Hm, rr_tile(q), L) != 0)
+  const int tile = (q == 2 * s->p && s->tune_rr) ? s->tune_rr : rr_tile(q);
+  if (rr_gram(cv(Sv), q, L0.kappa64, g, s->ph_d, s->gram_partial, s->gram_cap, s->Gm, s->Hm, tile, L) != 0)
     return set_error(BL_EINVAL, "Gram scratch too small%s");
   ritz_small(s->Gm, s->Hm, q, nfix, s->p, use_zthr ? s->zthr_d : nullptr, kDropRel, s->ritz_work,
              s->ritz_stride, s->Yd, s->lam_d, s->count_d, L);
@@ -695,6 +695,15 @@ int engine_create(const bl_grid* grid, const bl_opts* opts, int nslots, hipStrea
   identity_block(s->probe_e, s->nce, s->st);
   identity_block(s->probe_n, s->ncn, s->st);
   if ((rc = upload_slot_params(s))) return fail(rc);
+  HIP_OK(hipMemcpyAsync(s->mu_d, s->mu_h.data(), (size_t)S * 8, hipMemcpyHostToDevice, s->st));
+  if (!eps) {   // slots receive their permittivity with their first task; keep the rest finite
+    for (auto& L : s->lv) {
+      fill_zero<double>(L.kappa64, L.g.nm * S, s->st);
+      fill_zero<float>(L.kappa32, L.g.nm * S, s->st);
+      if (L.sinv64) fill_zero<double>(L.sinv64, L.g.nm * 6 * S, s->st);
+      if (L.sinv32) fill_zero<float>(L.sinv32, L.g.nm * 6 * S, s->st);
+    }
+  }
   if (eps) {
     std::vector<double> kap((size_t)gr.n * gr.m);
     double eps_min = eps[0];
@@ -707,6 +716,7 @@ int engine_create(const bl_grid* grid, const bl_opts* opts, int nslots, hipStrea
   }
   HIP_OK(hipStreamSynchronize(s->st));
   if ((rc = check_hip())) return fail(rc);
+  if (o.autotune && (rc = engine_autotune(s))) return fail(rc);
   *out = s;
   return BL_OK;
 }
@@ -966,11 +976,11 @@ int apply_t(bl_solver* s, int op, int level, int ncols, const void* xv, const vo
       if (!smoothed || !yv) return set_error(BL_EINVAL, "no smoother on this level / rhs missing%s");
       for (int c = 0; c < 4; ++c)
         edge_gs<T>(out, y, L.kappa64, L.kappa32, L.sinv64, L.sinv32, L.g, s->ph_d, s->mu_d, L.T4,
-                   op == BL_OP_EDGE_SMOOTH ? c : 3 - c, La);
+                   op == BL_OP_EDGE_SMOOTH ? c : 3 - c, s->tune_edge, La);
       break;
     case BL_OP_NODAL_SMOOTH:
       if (!smoothed || !yv) return set_error(BL_EINVAL, "no smoother on this level / rhs missing%s");
-      for (int c = 0; c < 4; ++c) nodal_gs<T>(out, y, L.g, s->ph_d, s->ns, c, La);
+      for (int c = 0; c < 4; ++c) nodal_gs<T>(out, y, L.g, s->ph_d, s->ns, c, s->tune_nodal, La);
       break;
     case BL_OP_EDGE_VCYCLE:
     case BL_OP_NODAL_VCYCLE: {

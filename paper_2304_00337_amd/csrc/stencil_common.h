@@ -78,6 +78,14 @@ __device__ __forceinline__ T* colp(View<T> v, SJ s, int64_t N) {
   return v.p + ((int64_t)s.slot * v.cps + v.off + s.j) * 2 * N;
 }
 
+// Block order that gives each of the 8 XCDs (which receive the blocks round-robin) one
+// contiguous range of logical blocks, so that the rows shared by neighbouring blocks stay in
+// one L2.  A bijection of [0, nb).
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int x = b & 7, i = b >> 3, q = nb >> 3, r = nb & 7;
+  return x * q + (x < r ? x : r) + i;
+}
+
 template <typename T>
 __device__ __forceinline__ T kap(const double* k64, const float* k32, int64_t i);
 template <>

@@ -12,6 +12,11 @@
 
 #include <cmath>
 
+// No contraction of multiplies and adds into FMAs: every launch-shape variant of a kernel
+// then performs exactly the written operations, so results do not depend on the shape the
+// autotuner picks.  The kernels are bandwidth-bound; the extra instructions cost nothing.
+#pragma clang fp contract(off)
+
 namespace bl {
 
 // ------------------------------------------------------------------------------------------
@@ -166,101 +171,116 @@ __device__ __forceinline__ const double* pick<double>(const double* a, const flo
 template <>
 __device__ __forceinline__ const float* pick<float>(const double*, const float* b) { return b; }
 
-template <typename T>
+template <typename T, int CPT>
 __global__ __launch_bounds__(256) void k_edge_gs(View<T> xv, View<const T> bv,
                                                  const double* __restrict__ k64,
                                                  const float* __restrict__ k32,
                                                  const double* __restrict__ si64,
                                                  const float* __restrict__ si32, Geo g,
                                                  const Phase* __restrict__ phs,
-                                                 const double* __restrict__ mus, PatchT T4, int colour, const int* __restrict__ slots,
-                                                 int ncps) {
-  const SJ sj = slot_col(slots, ncps);
+                                                 const double* __restrict__ mus, PatchT T4,
+                                                 int colour, const int* __restrict__ slots,
+                                                 int ncps, int xcd) {
+  const int ncg = (ncps + CPT - 1) / CPT;
+  const int si_ = (int)blockIdx.y / ncg;
+  const int slot = slots ? slots[si_] : si_;
+  const int j0 = ((int)blockIdx.y % ncg) * CPT;
   const int n = g.n, m = g.m, nh = n >> 1, mh = m >> 1;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int bx = xcd ? xcd_block((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+  const int64_t t = (int64_t)bx * blockDim.x + threadIdx.x;
   if (t >= (int64_t)nh * mh) return;
   const int p1 = 2 * (int)(t % nh) + (colour & 1);
   const int p2 = 2 * (int)(t / nh) + (colour >> 1);
   const int64_t nm = g.nm, N = g.ne;
-  const Ph<T> p = cast_phase<T>(phs[sj.slot]);
-  T* xc = colp(xv, sj, N);
-  const T* bc = colp(bv, sj, N);
-  k64 += (int64_t)sj.slot * nm;
-  k32 += (int64_t)sj.slot * nm;
-  const Cx<T> X00 = fetch<T, T>(xc, N, n, m, 0, p1, p2, p);
-  const Cx<T> X01 = fetch<T, T>(xc, N, n, m, 0, p1, p2 + 1, p);
-  const Cx<T> X0m = fetch<T, T>(xc, N, n, m, 0, p1, p2 - 1, p);
-  const Cx<T> Xm0 = fetch<T, T>(xc, N, n, m, 0, p1 - 1, p2, p);
-  const Cx<T> Xm1 = fetch<T, T>(xc, N, n, m, 0, p1 - 1, p2 + 1, p);
-  const Cx<T> Xmm = fetch<T, T>(xc, N, n, m, 0, p1 - 1, p2 - 1, p);
-  const Cx<T> Y00 = fetch<T, T>(xc, N, n, m, nm, p1, p2, p);
-  const Cx<T> Y10 = fetch<T, T>(xc, N, n, m, nm, p1 + 1, p2, p);
-  const Cx<T> Ym0 = fetch<T, T>(xc, N, n, m, nm, p1 - 1, p2, p);
-  const Cx<T> Y0m = fetch<T, T>(xc, N, n, m, nm, p1, p2 - 1, p);
-  const Cx<T> Y1m = fetch<T, T>(xc, N, n, m, nm, p1 + 1, p2 - 1, p);
-  const Cx<T> Ymm = fetch<T, T>(xc, N, n, m, nm, p1 - 1, p2 - 1, p);
-  const Cx<T> wne = X01 - X00 + Y00 - Y10;
-  const Cx<T> wnw = Xm1 - Xm0 + Ym0 - Y00;
-  const Cx<T> wsw = Xm0 - Xmm + Ymm - Y0m;
-  const Cx<T> wse = X00 - X0m + Y0m - Y1m;
+  const Ph<T> p = cast_phase<T>(phs[slot]);
+  k64 += (int64_t)slot * nm;
+  k32 += (int64_t)slot * nm;
   const int p1m = wrapi(p1 - 1, n), p2m = wrapi(p2 - 1, m);
   const T kne = kap<T>(k64, k32, (int64_t)p2 * n + p1);
   const T knw = kap<T>(k64, k32, (int64_t)p2 * n + p1m);
   const T ksw = kap<T>(k64, k32, (int64_t)p2m * n + p1m);
   const T kse = kap<T>(k64, k32, (int64_t)p2m * n + p1);
-  const T s = (T)g.s, mu = (T)mus[sj.slot];
+  const T* si = pick<T>(si64, si32) + 6 * ((int64_t)slot * nm + (int64_t)p2 * n + p1);
+  const T s00 = si[0], s01 = si[1], s02 = si[2], s11 = si[3], s12 = si[4], s22 = si[5];
+  const T s = (T)g.s, mu = (T)mus[slot];
   const T two3 = (T)(2.0 / 3.0), one6 = (T)(1.0 / 6.0);
   const T mmx = mu * (T)g.mx, mmy = mu * (T)g.my;
-  Cx<T> r[4];
-  r[0] = fetch<T, T>(bc, N, n, m, 0, p1, p2, p) -
-         ((s * ((kse * wse) - (kne * wne))) + mmx * ((two3 * X00) + one6 * (X01 + X0m)));
-  r[1] = fetch<T, T>(bc, N, n, m, 0, p1 - 1, p2, p) -
-         ((s * ((ksw * wsw) - (knw * wnw))) + mmx * ((two3 * Xm0) + one6 * (Xm1 + Xmm)));
-  r[2] = fetch<T, T>(bc, N, n, m, nm, p1, p2, p) -
-         ((s * ((kne * wne) - (knw * wnw))) + mmy * ((two3 * Y00) + one6 * (Y10 + Ym0)));
-  r[3] = fetch<T, T>(bc, N, n, m, nm, p1, p2 - 1, p) -
-         ((s * ((kse * wse) - (ksw * wsw))) + mmy * ((two3 * Y0m) + one6 * (Y1m + Ymm)));
-  // y = T^T r
-  Cx<T> y[4];
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    Cx<T> acc = {0, 0};
+  for (int cc = 0; cc < CPT; ++cc) {
+    const int j = j0 + cc;
+    if (j >= ncps) break;
+    const SJ sj{slot, j};
+    T* xc = colp(xv, sj, N);
+    const T* bc = colp(bv, sj, N);
+    const Cx<T> X00 = fetch<T, T>(xc, N, n, m, 0, p1, p2, p);
+    const Cx<T> X01 = fetch<T, T>(xc, N, n, m, 0, p1, p2 + 1, p);
+    const Cx<T> X0m = fetch<T, T>(xc, N, n, m, 0, p1, p2 - 1, p);
+    const Cx<T> Xm0 = fetch<T, T>(xc, N, n, m, 0, p1 - 1, p2, p);
+    const Cx<T> Xm1 = fetch<T, T>(xc, N, n, m, 0, p1 - 1, p2 + 1, p);
+    const Cx<T> Xmm = fetch<T, T>(xc, N, n, m, 0, p1 - 1, p2 - 1, p);
+    const Cx<T> Y00 = fetch<T, T>(xc, N, n, m, nm, p1, p2, p);
+    const Cx<T> Y10 = fetch<T, T>(xc, N, n, m, nm, p1 + 1, p2, p);
+    const Cx<T> Ym0 = fetch<T, T>(xc, N, n, m, nm, p1 - 1, p2, p);
+    const Cx<T> Y0m = fetch<T, T>(xc, N, n, m, nm, p1, p2 - 1, p);
+    const Cx<T> Y1m = fetch<T, T>(xc, N, n, m, nm, p1 + 1, p2 - 1, p);
+    const Cx<T> Ymm = fetch<T, T>(xc, N, n, m, nm, p1 - 1, p2 - 1, p);
+    const Cx<T> wne = X01 - X00 + Y00 - Y10;
+    const Cx<T> wnw = Xm1 - Xm0 + Ym0 - Y00;
+    const Cx<T> wsw = Xm0 - Xmm + Ymm - Y0m;
+    const Cx<T> wse = X00 - X0m + Y0m - Y1m;
+    Cx<T> r[4];
+    r[0] = fetch<T, T>(bc, N, n, m, 0, p1, p2, p) -
+           ((s * ((kse * wse) - (kne * wne))) + mmx * ((two3 * X00) + one6 * (X01 + X0m)));
+    r[1] = fetch<T, T>(bc, N, n, m, 0, p1 - 1, p2, p) -
+           ((s * ((ksw * wsw) - (knw * wnw))) + mmx * ((two3 * Xm0) + one6 * (Xm1 + Xmm)));
+    r[2] = fetch<T, T>(bc, N, n, m, nm, p1, p2, p) -
+           ((s * ((kne * wne) - (knw * wnw))) + mmy * ((two3 * Y00) + one6 * (Y10 + Ym0)));
+    r[3] = fetch<T, T>(bc, N, n, m, nm, p1, p2 - 1, p) -
+           ((s * ((kse * wse) - (ksw * wsw))) + mmy * ((two3 * Y0m) + one6 * (Y1m + Ymm)));
+    // y = T^T r
+    Cx<T> y[4];
 #pragma unroll
-    for (int l = 0; l < 4; ++l) acc = acc + ((T)T4.t[l * 4 + a] * r[l]);
-    y[a] = acc;
+    for (int a = 0; a < 4; ++a) {
+      Cx<T> acc = {0, 0};
+#pragma unroll
+      for (int l = 0; l < 4; ++l) acc = acc + ((T)T4.t[l * 4 + a] * r[l]);
+      y[a] = acc;
+    }
+    Cx<T> z[4];
+    z[0] = ((T)1 / mu) * y[0];
+    z[1] = (s00 * y[1]) + (s01 * y[2]) + (s02 * y[3]);
+    z[2] = (s01 * y[1]) + (s11 * y[2]) + (s12 * y[3]);
+    z[3] = (s02 * y[1]) + (s12 * y[2]) + (s22 * y[3]);
+    Cx<T> dl[4];
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      Cx<T> acc = {0, 0};
+#pragma unroll
+      for (int a = 0; a < 4; ++a) acc = acc + ((T)T4.t[l * 4 + a] * z[a]);
+      dl[l] = acc;
+    }
+    add_ext<T, T>(xc, N, n, m, 0, p1, p2, dl[0], p);
+    add_ext<T, T>(xc, N, n, m, 0, p1 - 1, p2, dl[1], p);
+    add_ext<T, T>(xc, N, n, m, nm, p1, p2, dl[2], p);
+    add_ext<T, T>(xc, N, n, m, nm, p1, p2 - 1, dl[3], p);
   }
-  const T* si = pick<T>(si64, si32) + 6 * ((int64_t)sj.slot * nm + (int64_t)p2 * n + p1);
-  const T s00 = si[0], s01 = si[1], s02 = si[2], s11 = si[3], s12 = si[4], s22 = si[5];
-  Cx<T> z[4];
-  z[0] = ((T)1 / mu) * y[0];
-  z[1] = (s00 * y[1]) + (s01 * y[2]) + (s02 * y[3]);
-  z[2] = (s01 * y[1]) + (s11 * y[2]) + (s12 * y[3]);
-  z[3] = (s02 * y[1]) + (s12 * y[2]) + (s22 * y[3]);
-  Cx<T> dl[4];
-#pragma unroll
-  for (int l = 0; l < 4; ++l) {
-    Cx<T> acc = {0, 0};
-#pragma unroll
-    for (int a = 0; a < 4; ++a) acc = acc + ((T)T4.t[l * 4 + a] * z[a]);
-    dl[l] = acc;
-  }
-  add_ext<T, T>(xc, N, n, m, 0, p1, p2, dl[0], p);
-  add_ext<T, T>(xc, N, n, m, 0, p1 - 1, p2, dl[1], p);
-  add_ext<T, T>(xc, N, n, m, nm, p1, p2, dl[2], p);
-  add_ext<T, T>(xc, N, n, m, nm, p1, p2 - 1, dl[3], p);
 }
 
 template <typename T>
 void edge_gs(View<T> x, View<const T> b, const double* kappa64, const float* kappa32,
              const double* sinv64, const float* sinv32, const Geo& g, const Phase* ph,
-             const double* mu, const PatchT& T4, int colour, const Launch& L) {
+             const double* mu, const PatchT& T4, int colour, const SmoothShape& sh, const Launch& L) {
   const int64_t cnt = (int64_t)(g.n / 2) * (g.m / 2);
-  dim3 grid((unsigned)((cnt + 255) / 256), (unsigned)(L.nact * L.ncps));
+  const int bs = sh.bs > 0 ? sh.bs : 256, cpt = sh.cpt == 2 ? 2 : 1;
+  dim3 grid((unsigned)((cnt + bs - 1) / bs), (unsigned)(L.nact * ((L.ncps + cpt - 1) / cpt)));
   if (grid.y == 0) return;
-  k_edge_gs<T><<<grid, 256, 0, L.st>>>(x, b, kappa64, kappa32, sinv64, sinv32, g, ph, mu, T4, colour, L.slots, L.ncps);
+  if (cpt == 2)
+    k_edge_gs<T, 2><<<grid, bs, 0, L.st>>>(x, b, kappa64, kappa32, sinv64, sinv32, g, ph, mu, T4, colour, L.slots, L.ncps, sh.xcd);
+  else
+    k_edge_gs<T, 1><<<grid, bs, 0, L.st>>>(x, b, kappa64, kappa32, sinv64, sinv32, g, ph, mu, T4, colour, L.slots, L.ncps, sh.xcd);
 }
-template void edge_gs<double>(View<double>, View<const double>, const double*, const float*, const double*, const float*, const Geo&, const Phase*, const double*, const PatchT&, int, const Launch&);
-template void edge_gs<float>(View<float>, View<const float>, const double*, const float*, const double*, const float*, const Geo&, const Phase*, const double*, const PatchT&, int, const Launch&);
+template void edge_gs<double>(View<double>, View<const double>, const double*, const float*, const double*, const float*, const Geo&, const Phase*, const double*, const PatchT&, int, const SmoothShape&, const Launch&);
+template void edge_gs<float>(View<float>, View<const float>, const double*, const float*, const double*, const float*, const Geo&, const Phase*, const double*, const PatchT&, int, const SmoothShape&, const Launch&);
 
 // Per-node inverse of the 3x3 block S = (Q'^T D^{-1/2} A_loc D^{-1/2} Q') + mu I of the
 // stabilised patch system, Q' = columns 2..4 of the orthogonal Q (passed row-major in q).
@@ -493,37 +513,50 @@ template void nodal_apply<float>(View<const float>, View<const float>, View<floa
 
 // Point Gauss-Seidel for P on the nodes of one colour (same-colour nodes are not
 // neighbours of the 9-point stencil).
-template <typename T>
+template <typename T, int CPT>
 __global__ __launch_bounds__(256) void k_nodal_gs(View<T> xv, View<const T> bv, Geo g,
                                                   const Phase* __restrict__ phs, NodalStencil s,
-                                                  int colour, const int* __restrict__ slots, int ncps) {
-  const SJ sj = slot_col(slots, ncps);
+                                                  int colour, const int* __restrict__ slots, int ncps,
+                                                  int xcd) {
+  const int ncg = (ncps + CPT - 1) / CPT;
+  const int si_ = (int)blockIdx.y / ncg;
+  const int slot = slots ? slots[si_] : si_;
+  const int j0 = ((int)blockIdx.y % ncg) * CPT;
   const int nh = g.n >> 1, mh = g.m >> 1;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int bx = xcd ? xcd_block((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+  const int64_t t = (int64_t)bx * blockDim.x + threadIdx.x;
   if (t >= (int64_t)nh * mh) return;
   const int p1 = 2 * (int)(t % nh) + (colour & 1);
   const int p2 = 2 * (int)(t / nh) + (colour >> 1);
-  const Ph<T> p = cast_phase<T>(phs[sj.slot]);
+  const Ph<T> p = cast_phase<T>(phs[slot]);
   const int64_t N = g.nm;
-  T* xc = colp(xv, sj, N);
-  const T* bc = colp(bv, sj, N);
   const int64_t i = (int64_t)p2 * g.n + p1;
-  const Cx<T> r = Cx<T>{bc[i], bc[N + i]} - nodal_stencil<T>(xc, N, g.n, g.m, p1, p2, s, p);
   const T inv = (T)1 / (T)s.c0;
-  xc[i] += inv * r.re;
-  xc[N + i] += inv * r.im;
+#pragma unroll
+  for (int cc = 0; cc < CPT; ++cc) {
+    const int j = j0 + cc;
+    if (j >= ncps) break;
+    const SJ sj{slot, j};
+    T* xc = colp(xv, sj, N);
+    const T* bc = colp(bv, sj, N);
+    const Cx<T> r = Cx<T>{bc[i], bc[N + i]} - nodal_stencil<T>(xc, N, g.n, g.m, p1, p2, s, p);
+    xc[i] += inv * r.re;
+    xc[N + i] += inv * r.im;
+  }
 }
 
 template <typename T>
 void nodal_gs(View<T> x, View<const T> b, const Geo& g, const Phase* ph, const NodalStencil& c,
-              int colour, const Launch& L) {
+              int colour, const SmoothShape& sh, const Launch& L) {
   const int64_t cnt = (int64_t)(g.n / 2) * (g.m / 2);
-  dim3 grid((unsigned)((cnt + 255) / 256), (unsigned)(L.nact * L.ncps));
+  const int bs = sh.bs > 0 ? sh.bs : 256, cpt = sh.cpt == 2 ? 2 : 1;
+  dim3 grid((unsigned)((cnt + bs - 1) / bs), (unsigned)(L.nact * ((L.ncps + cpt - 1) / cpt)));
   if (grid.y == 0) return;
-  k_nodal_gs<T><<<grid, 256, 0, L.st>>>(x, b, g, ph, c, colour, L.slots, L.ncps);
+  if (cpt == 2) k_nodal_gs<T, 2><<<grid, bs, 0, L.st>>>(x, b, g, ph, c, colour, L.slots, L.ncps, sh.xcd);
+  else k_nodal_gs<T, 1><<<grid, bs, 0, L.st>>>(x, b, g, ph, c, colour, L.slots, L.ncps, sh.xcd);
 }
-template void nodal_gs<double>(View<double>, View<const double>, const Geo&, const Phase*, const NodalStencil&, int, const Launch&);
-template void nodal_gs<float>(View<float>, View<const float>, const Geo&, const Phase*, const NodalStencil&, int, const Launch&);
+template void nodal_gs<double>(View<double>, View<const double>, const Geo&, const Phase*, const NodalStencil&, int, const SmoothShape&, const Launch&);
+template void nodal_gs<float>(View<float>, View<const float>, const Geo&, const Phase*, const NodalStencil&, int, const SmoothShape&, const Launch&);
 
 // Nodal transfers: bilinear interpolation of the coarse Q1 function (embedding) and its
 // adjoint (full weighting with Bloch phases).

@@ -1,0 +1,154 @@
+// Autotuner of the engine's launch shapes.  For one engine shape (n, m, p, precision, slot
+// count) it times, on the engine's own buffers and stream, every candidate shape of
+//  * the finest-level edge smoother colour pass and the nodal smoother colour pass:
+//    threads per block {64, 128, 256} x columns per thread {1, 2} x block order
+//    {plain, XCD-major};
+//  * the Rayleigh-Ritz products for the iteration's basis width q = 2p: 48- or 64-wide
+//    output tiles;
+// and keeps the fastest.  None of the candidates changes the arithmetic of any result
+// (same operations per entry, same order), so tuning never changes the numbers.  Choices
+// are cached for the process.
+#include "engine.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <tuple>
+
+namespace bl {
+
+namespace {
+
+struct Choice {
+  SmoothShape edge, nodal;
+  int rr = 0;
+};
+
+std::mutex g_mu;
+std::map<std::tuple<int, int, int, int, int>, Choice> g_cache;
+
+const SmoothShape kCands[] = {
+    {64, 1, 0}, {128, 1, 0}, {256, 1, 0}, {64, 2, 0}, {128, 2, 0}, {256, 2, 0},
+    {64, 1, 1}, {128, 1, 1}, {256, 1, 1}, {64, 2, 1}, {128, 2, 1}, {256, 2, 1},
+};
+
+template <typename F>
+float time_it(hipStream_t st, hipEvent_t e0, hipEvent_t e1, int reps, F&& run) {
+  run();   // warm-up
+  float best = 1e30f;
+  for (int r = 0; r < reps; ++r) {
+    (void)hipEventRecord(e0, st);
+    run();
+    (void)hipEventRecord(e1, st);
+    float ms = 0.f;
+    if (hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < best) best = ms;
+  }
+  return best;
+}
+
+template <typename T>
+Choice tune_t(bl_solver* s, hipEvent_t e0, hipEvent_t e1) {
+  const int pr = s->opts.precision ? 1 : 0;
+  Level& L0 = s->lv[0];
+  Choice c;
+  if (s->lv.size() < 2) return c;   // no smoothed level
+  const Launch Le{nullptr, s->nslots, s->p, s->st};
+  const Launch Ln{nullptr, s->nslots, 2 * s->p, s->st};
+  View<T> xe = view(static_cast<T*>(L0.ex[pr]), L0.ecap[pr]);
+  View<const T> be = cview(static_cast<const T*>(L0.eb[pr]), L0.ecap[pr]);
+  View<T> xn = view(static_cast<T*>(L0.nx[pr]), L0.ncap[pr]);
+  View<const T> bn = cview(static_cast<const T*>(L0.nb[pr]), L0.ncap[pr]);
+  float best_e = 1e30f, best_n = 1e30f;
+  for (const SmoothShape& sh : kCands) {
+    const float te = time_it(s->st, e0, e1, 3, [&] {
+      for (int col = 0; col < 4; ++col)
+        edge_gs<T>(xe, be, L0.kappa64, L0.kappa32, L0.sinv64, L0.sinv32, L0.g, s->ph_d, s->mu_d, L0.T4, col, sh, Le);
+    });
+    if (te < best_e) { best_e = te; c.edge = sh; }
+    const float tn = time_it(s->st, e0, e1, 3, [&] {
+      for (int col = 0; col < 4; ++col) nodal_gs<T>(xn, bn, L0.g, s->ph_d, s->ns, col, sh, Ln);
+    });
+    if (tn < best_n) { best_n = tn; c.nodal = sh; }
+  }
+  const int q = 2 * s->p;
+  float best_r = 1e30f;
+  for (int tile : {3, 4}) {
+    const float tr = time_it(s->st, e0, e1, 2, [&] {
+      (void)rr_gram(cview(s->Sb, s->qmax), q, L0.kappa64, L0.g, s->ph_d, s->gram_partial, s->gram_cap, s->Gm, s->Hm,
+                    tile, Le);
+    });
+    if (tr < best_r) { best_r = tr; c.rr = tile; }
+  }
+  return c;
+}
+
+}  // namespace
+
+int engine_autotune(bl_solver* s) {
+  // measurement and test hook: BL_SMOOTH_SHAPE="threads,columns,xcd" and BL_RR_TILE=48|64
+  // fix the shapes instead of timing them
+  const char* fs = std::getenv("BL_SMOOTH_SHAPE");
+  const char* ft = std::getenv("BL_RR_TILE");
+  if (fs || ft) {
+    int bs = 256, cpt = 1, xcd = 0;
+    if (fs && std::sscanf(fs, "%d,%d,%d", &bs, &cpt, &xcd) == 3 && (bs == 64 || bs == 128 || bs == 256) &&
+        (cpt == 1 || cpt == 2) && (xcd == 0 || xcd == 1)) {
+      s->tune_edge = s->tune_nodal = SmoothShape{bs, cpt, xcd};
+    }
+    if (ft) s->tune_rr = std::atoi(ft) == 64 ? 4 : 3;
+    return BL_OK;
+  }
+  const auto key = std::make_tuple(s->grid.n, s->grid.m, s->p, s->opts.precision, s->nslots);
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_cache.find(key);
+    if (it != g_cache.end()) {
+      s->tune_edge = it->second.edge;
+      s->tune_nodal = it->second.nodal;
+      s->tune_rr = it->second.rr;
+      return BL_OK;
+    }
+  }
+  const double t0 = now_seconds();
+  // benign contents for the timed buffers (the values do not affect the launch shapes'
+  // cost, but uninitialised memory could hold non-finite patterns)
+  const int pr = s->opts.precision ? 1 : 0;
+  Level& L0 = s->lv[0];
+  const int S = s->nslots;
+  if (pr) {
+    fill_zero<float>(static_cast<float*>(L0.ex[1]), (int64_t)S * L0.ecap[1] * 2 * L0.g.ne, s->st);
+    fill_zero<float>(static_cast<float*>(L0.eb[1]), (int64_t)S * L0.ecap[1] * 2 * L0.g.ne, s->st);
+    fill_zero<float>(static_cast<float*>(L0.nx[1]), (int64_t)S * L0.ncap[1] * 2 * L0.g.nm, s->st);
+    fill_zero<float>(static_cast<float*>(L0.nb[1]), (int64_t)S * L0.ncap[1] * 2 * L0.g.nm, s->st);
+  } else {
+    fill_zero<double>(static_cast<double*>(L0.ex[0]), (int64_t)S * L0.ecap[0] * 2 * L0.g.ne, s->st);
+    fill_zero<double>(static_cast<double*>(L0.eb[0]), (int64_t)S * L0.ecap[0] * 2 * L0.g.ne, s->st);
+    fill_zero<double>(static_cast<double*>(L0.nx[0]), (int64_t)S * L0.ncap[0] * 2 * L0.g.nm, s->st);
+    fill_zero<double>(static_cast<double*>(L0.nb[0]), (int64_t)S * L0.ncap[0] * 2 * L0.g.nm, s->st);
+  }
+  fill_zero<double>(s->Sb, (int64_t)S * s->qmax * 2 * L0.g.ne, s->st);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return set_error(BL_EHIP, "event creation failed%s");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return set_error(BL_EHIP, "event creation failed%s");
+  }
+  const Choice c = pr ? tune_t<float>(s, e0, e1) : tune_t<double>(s, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  hipError_t e = hipStreamSynchronize(s->st);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) return set_error(BL_EHIP, "autotuning failed: %s", hipGetErrorString(e));
+  s->tune_edge = c.edge;
+  s->tune_nodal = c.nodal;
+  s->tune_rr = c.rr;
+  s->tune_ms = (now_seconds() - t0) * 1e3;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_cache[key] = c;
+  return BL_OK;
+}
+
+}  // namespace bl

@@ -148,3 +148,32 @@ def test_errors_are_reported():
     assert not r["converged"] and r["iterations"] == 1
     with pytest.raises(BlochError):
         s.solve_k(float("nan"), 0.0, start=synth.start_block(2 * n * n, 6, 0))
+
+
+def test_autotuned_launch_shapes_do_not_change_results():
+    """The autotuner only picks launch shapes (threads per block, columns per thread, block
+    order, output tiles): every candidate shape reproduces the default one bit for bit."""
+    import os
+    prob = synth.config_c1()
+    E0 = synth.start_block(prob.n_edges, 12, 3)
+    base = _solver(prob, "mixed", levels=3, nthrow=4, max_iter=300, autotune=0)
+    assert base.info()["edge_smooth_shape"] == [256, 1, 0]
+    ref = base.solve_k(*prob.ks[0], start=E0)
+    tuned = _solver(prob, "mixed", levels=3, nthrow=4, max_iter=300, autotune=1)
+    it = tuned.info()
+    assert it["edge_smooth_shape"][0] in (64, 128, 256) and it["rr_tile"] in (48, 64)
+    got = [tuned.solve_k(*prob.ks[0], start=E0)]
+    try:
+        for shape in ("64,1,0", "128,2,1", "256,2,0", "64,2,1"):
+            for tile in ("48", "64"):
+                os.environ["BL_SMOOTH_SHAPE"] = shape
+                os.environ["BL_RR_TILE"] = tile
+                s = _solver(prob, "mixed", levels=3, nthrow=4, max_iter=300, autotune=1)
+                assert s.info()["edge_smooth_shape"] == [int(v) for v in shape.split(",")]
+                assert s.info()["rr_tile"] == int(tile)
+                got.append(s.solve_k(*prob.ks[0], start=E0))
+    finally:
+        os.environ.pop("BL_SMOOTH_SHAPE", None)
+        os.environ.pop("BL_RR_TILE", None)
+    for r in got:
+        assert np.array_equal(r["evals"], ref["evals"]) and r["iterations"] == ref["iterations"]
