@@ -261,6 +261,9 @@ typedef struct bl_batch bl_batch;
 int bl_batch_create(const bl_opts* opts, int32_t max_slots, size_t hbm_budget, bl_batch** out);
 int bl_batch_run(bl_batch* b, bl_problem* probs, int32_t count, void* stream);
 void bl_batch_destroy(bl_batch* b);
+/* Facts about the context's live engines (one per shape and slot group): fills *out for
+ * engine `index` when it exists and returns the number of live engines (>= 0). */
+int bl_batch_engine_info(const bl_batch* b, int32_t index, bl_info* out);
 /* Finest-level smoother timing (as bl_set_timing / bl_get_timing) summed over every engine
  * of the context, including engines released since timing was enabled. */
 int bl_batch_set_timing(bl_batch* b, int32_t enable);

@@ -67,6 +67,17 @@ def _start_block(start, p, n_edges):
     return start
 
 
+def _info_dict(inf) -> dict:
+    L = inf.levels
+    return {"n": inf.n, "m": inf.m, "p": inf.p, "nev": inf.nev, "levels": L,
+            "precision": inf.precision, "mu": inf.mu, "device_bytes": inf.device_bytes,
+            "kernel_launches": inf.kernel_launches,
+            "sizes": [(inf.level_n[i], inf.level_m[i]) for i in range(L)],
+            "edge_smooth_shape": list(inf.edge_smooth_shape),
+            "nodal_smooth_shape": list(inf.nodal_smooth_shape),
+            "rr_tile": inf.rr_tile, "autotune_ms": inf.autotune_ms}
+
+
 def _marshal_problems(problems, want_last_vectors):
     torch = _torch()
     keep = []
@@ -140,6 +151,17 @@ class Batch:
             stream = torch.cuda.current_stream()
         rc = self.lib.bl_batch_run(self.h, arr, len(problems), ctypes.c_void_p(stream.cuda_stream))
         return _unmarshal(arr, outs, rc, "bl_batch_run")
+
+    def engines(self) -> list:
+        """bl_info of every live engine of the context."""
+        out, i = [], 0
+        while True:
+            inf = BlInfo()
+            cnt = check(self.lib.bl_batch_engine_info(self.h, i, ctypes.byref(inf)), "bl_batch_engine_info")
+            if i >= cnt:
+                return out
+            out.append(_info_dict(inf))
+            i += 1
 
     def set_timing(self, enable=True):
         check(self.lib.bl_batch_set_timing(self.h, 1 if enable else 0), "bl_batch_set_timing")
@@ -302,14 +324,7 @@ class Solver:
     def info(self) -> dict:
         inf = BlInfo()
         check(self.lib.bl_get_info(self.h, ctypes.byref(inf)), "bl_get_info")
-        L = inf.levels
-        return {"n": inf.n, "m": inf.m, "p": inf.p, "nev": inf.nev, "levels": L,
-                "precision": inf.precision, "mu": inf.mu, "device_bytes": inf.device_bytes,
-                "kernel_launches": inf.kernel_launches,
-                "sizes": [(inf.level_n[i], inf.level_m[i]) for i in range(L)],
-                "edge_smooth_shape": list(inf.edge_smooth_shape),
-                "nodal_smooth_shape": list(inf.nodal_smooth_shape),
-                "rr_tile": inf.rr_tile, "autotune_ms": inf.autotune_ms}
+        return _info_dict(inf)
 
     @staticmethod
     def footprint_bytes(n, m, a, b, nev=8, **opts) -> int:

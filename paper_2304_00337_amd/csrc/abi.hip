@@ -92,6 +92,13 @@ void bl_destroy(bl_solver* s) { engine_destroy(s); }
 
 int bl_get_info(const bl_solver* s, bl_info* out) {
   if (!s || !out) return set_error(BL_EINVAL, "NULL argument%s");
+  bl::fill_info(s, out);
+  return BL_OK;
+}
+
+}  // extern "C"
+
+void bl::fill_info(const bl_solver* s, bl_info* out) {
   std::memset(out, 0, sizeof(*out));
   out->n = s->grid.n;
   out->m = s->grid.m;
@@ -114,8 +121,9 @@ int bl_get_info(const bl_solver* s, bl_info* out) {
   out->nodal_smooth_shape[2] = s->tune_nodal.xcd;
   out->rr_tile = 16 * (s->tune_rr ? s->tune_rr : rr_tile(2 * s->p));
   out->autotune_ms = s->tune_ms;
-  return BL_OK;
 }
+
+extern "C" {
 
 int bl_solve_k(bl_solver* s, double k1, double k2, const void* start_dev, double* evals,
                double* relres, int32_t* iters, void* evecs_dev) {

@@ -192,12 +192,15 @@ int engine_sync_retired(bl_solver* s);
 
 // Autotuner: time the candidate launch shapes of the finest-level smoothers and of the
 // Rayleigh-Ritz products on the engine's own buffers and keep the fastest; results are
-// cached per (n, m, p, precision, slots) for the process.
+// cached per (n, m, p, precision) for the process, seeded from the shipped table.
 int engine_autotune(bl_solver* s);
 int rr_tile(int q);
 
 // Opt-in HIP-event timing of the finest-level smoother launches (resets the totals).
 int engine_set_timing(bl_solver* s, bool enable);
+
+// bl_info of an engine (bl_get_info, bl_batch_engine_info).
+void fill_info(const bl_solver* s, bl_info* out);
 
 // Operator-level helpers on slot 0.
 int engine_set_k0(bl_solver* s, double k1, double k2);

@@ -112,6 +112,9 @@ class Scheduler {
     }
   }
 
+  int engine_count() const { return (int)engines_.size(); }
+  const bl_solver* engine_at(int i) const { return engines_[i].e; }
+
   // One round over every busy engine: issue all, then finish all.
   int step() {
     int rc;
@@ -414,6 +417,14 @@ int bl_batch_run(bl_batch* b, bl_problem* probs, int32_t count, void* stream) {
 }
 
 void bl_batch_destroy(bl_batch* b) { delete b; }
+
+int bl_batch_engine_info(const bl_batch* b, int32_t index, bl_info* out) {
+  if (!b || !out) return set_error(BL_EINVAL, "NULL argument%s");
+  if (index < 0) return set_error(BL_EINVAL, "negative index%s");
+  if (index >= b->sched->engine_count()) return b->sched->engine_count();
+  fill_info(b->sched->engine_at(index), out);
+  return b->sched->engine_count();
+}
 
 int bl_batch_set_timing(bl_batch* b, int32_t enable) {
   if (!b) return set_error(BL_EINVAL, "batch is NULL%s");

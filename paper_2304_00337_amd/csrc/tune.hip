@@ -7,15 +7,19 @@
 //    output tiles;
 // and keeps the fastest.  None of the candidates changes the arithmetic of any result
 // (same operations per entry, same order), so tuning never changes the numbers.  Choices
-// are cached for the process.
+// are cached for the process, keyed by (n, m, p, precision); a table of earlier choices
+// shipped with the library (tuning.txt, written by tune_table.py) seeds the cache, so that
+// runs are reproducible and pay no tuning time.
 #include "engine.h"
 
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
 #include <cstdlib>
 #include <map>
 #include <mutex>
+#include <string>
 #include <tuple>
 
 namespace bl {
@@ -28,7 +32,43 @@ struct Choice {
 };
 
 std::mutex g_mu;
-std::map<std::tuple<int, int, int, int, int>, Choice> g_cache;
+std::map<std::tuple<int, int, int, int>, Choice> g_cache;
+bool g_table_read = false;
+
+// Shapes chosen by earlier tuning runs, shipped next to the library as "tuning.txt": one line
+// per engine shape "n m p precision  edge_bs edge_cpt edge_xcd  nodal_bs nodal_cpt nodal_xcd
+// rr_tile"; '#' starts a comment.  Read once, into the cache; BL_TUNE_TABLE overrides the
+// path, an empty value disables the table.
+void read_table() {
+  g_table_read = true;
+  std::string path;
+  if (const char* e = std::getenv("BL_TUNE_TABLE")) {
+    path = e;
+  } else {
+    Dl_info info;
+    if (dladdr(reinterpret_cast<void*>(&read_table), &info) && info.dli_fname) {
+      path = info.dli_fname;
+      const size_t slash = path.find_last_of('/');
+      path = (slash == std::string::npos ? std::string(".") : path.substr(0, slash)) + "/tuning.txt";
+    }
+  }
+  if (path.empty()) return;
+  FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return;
+  char line[256];
+  while (std::fgets(line, sizeof(line), f)) {
+    if (line[0] == '#') continue;
+    int n, m, p, pr, eb, ec, ex, nb, nc, nx, rr;
+    if (std::sscanf(line, "%d %d %d %d %d %d %d %d %d %d %d", &n, &m, &p, &pr, &eb, &ec, &ex, &nb, &nc, &nx, &rr) != 11)
+      continue;
+    Choice c;
+    c.edge = SmoothShape{eb, ec, ex};
+    c.nodal = SmoothShape{nb, nc, nx};
+    c.rr = rr == 64 ? 4 : 3;
+    g_cache[std::make_tuple(n, m, p, pr)] = c;
+  }
+  std::fclose(f);
+}
 
 const SmoothShape kCands[] = {
     {64, 1, 0}, {128, 1, 0}, {256, 1, 0}, {64, 2, 0}, {128, 2, 0}, {256, 2, 0},
@@ -101,9 +141,10 @@ int engine_autotune(bl_solver* s) {
     if (ft) s->tune_rr = std::atoi(ft) == 64 ? 4 : 3;
     return BL_OK;
   }
-  const auto key = std::make_tuple(s->grid.n, s->grid.m, s->p, s->opts.precision, s->nslots);
+  const auto key = std::make_tuple(s->grid.n, s->grid.m, s->p, s->opts.precision);
   {
     std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_table_read && !std::getenv("BL_TUNE_IGNORE_TABLE")) read_table();
     auto it = g_cache.find(key);
     if (it != g_cache.end()) {
       s->tune_edge = it->second.edge;

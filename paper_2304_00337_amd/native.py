@@ -96,6 +96,7 @@ EXPORTED = {
     "bl_batch_create": (c_int32, [P(BlOpts), c_int32, c_size_t, P(c_void_p)]),
     "bl_batch_run": (c_int32, [c_void_p, P(BlProblem), c_int32, c_void_p]),
     "bl_batch_destroy": (None, [c_void_p]),
+    "bl_batch_engine_info": (c_int32, [c_void_p, c_int32, P(BlInfo)]),
     "bl_batch_set_timing": (c_int32, [c_void_p, c_int32]),
     "bl_batch_get_timing": (c_int32, [c_void_p, P(c_double), P(c_int64), P(c_int64)]),
     "bl_server_create": (c_int32, [P(BlOpts), c_size_t, c_int32, P(c_void_p)]),
@@ -119,6 +120,12 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2304_00337_amd.build` "
                            "(there is no fallback implementation)")
+    # PyTorch provides the device memory and streams and ships its own HIP runtime; load it
+    # first so that the library binds to the same runtime instance
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in EXPORTED.items():
         fn = getattr(lib, name)
