@@ -32,26 +32,32 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 
-def segments(prob, S):
-    """The path cut into S contiguous pieces; piece 0 starts from the problem's seeded
-    block, piece i > 0 from the block seeded 100 + i."""
+def segments(prob, S, per_segment):
+    """The path cut into S contiguous pieces (S = 0: its three legs Gamma-X, X-M, M-Gamma,
+    cut at the corners); piece 0 starts from the problem's seeded block, piece i > 0 from
+    the block seeded 100 + i."""
     import synth
     from paper_2304_00337_amd import to_device_block
     ks = np.asarray(prob.ks)
+    if S == 0:
+        cuts = [0, per_segment, 2 * per_segment, len(ks)]
+        pieces = [np.arange(cuts[i], cuts[i + 1]) for i in range(3)]
+    else:
+        pieces = np.array_split(np.arange(len(ks)), S)
     out = []
-    for i, ix in enumerate(np.array_split(np.arange(len(ks)), S)):
+    for i, ix in enumerate(pieces):
         st = prob.start() if i == 0 else synth.start_block(prob.n_edges, prob.p, 100 + i)
         out.append(dict(n=prob.n, m=prob.m, a=prob.a, b=prob.b, eps=prob.eps, nev=prob.nev,
                         nthrow=prob.nthrow, ks=ks[ix], start=to_device_block(st)))
     return out
 
 
-def run_form(prob, precision, S, steps, warmup):
+def run_form(prob, precision, S, steps, warmup, per_segment):
     import torch
     from paper_2304_00337_amd import Batch
-    probs = segments(prob, S)
+    probs = segments(prob, S, per_segment)
     recs = []
-    with Batch(max_slots=S, precision=precision, levels=prob.levels, tol=prob.tol, max_iter=300) as b:
+    with Batch(max_slots=len(probs), precision=precision, levels=prob.levels, tol=prob.tol, max_iter=300) as b:
         for _ in range(warmup):
             b.run(probs)
         torch.cuda.synchronize()
@@ -71,7 +77,7 @@ def run_form(prob, precision, S, steps, warmup):
         tm = b.timing()
         shapes = [{"edge_smooth_shape": e["edge_smooth_shape"],
                    "nodal_smooth_shape": e["nodal_smooth_shape"], "rr_tile": e["rr_tile"]} for e in b.engines()]
-    return {"elapsed": elapsed, "recs": recs, "timing": tm, "S": S, "shapes": shapes}
+    return {"elapsed": elapsed, "recs": recs, "timing": tm, "S": len(probs), "shapes": shapes}
 
 
 def cpu_baseline(prob, iters_total, cold_starts, sample_iters=3):
@@ -182,7 +188,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--per-segment", type=int, default=10)
-    ap.add_argument("--segments", type=int, default=4)
+    ap.add_argument("--segments", type=int, default=0,
+                    help="pieces of the path solved as one batch; 0 = its three legs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=16)
@@ -212,11 +219,11 @@ def main():
         del src, dst
     plain = None
     if not args.headline_only:
-        plain = run_form(prob, "fp64", 1, args.steps, args.warmup)
+        plain = run_form(prob, "fp64", 1, args.steps, args.warmup, args.per_segment)
         print(f"# fp64 plain: {plain['elapsed']:.3f}s for {args.steps} paths, iterations "
               f"{plain['recs'][0]['iters'].tolist()}", file=sys.stderr, flush=True)
-    head = run_form(prob, "mixed", args.segments, args.steps, args.warmup)
-    print(f"# mixed x{args.segments} segments: {head['elapsed']:.3f}s for {args.steps} paths, iterations "
+    head = run_form(prob, "mixed", args.segments, args.steps, args.warmup, args.per_segment)
+    print(f"# mixed x{head['S']} segments: {head['elapsed']:.3f}s for {args.steps} paths, iterations "
           f"{head['recs'][0]['iters'].tolist()}", file=sys.stderr, flush=True)
     ref = (plain or head)["recs"][0]["evals"]
 
@@ -262,9 +269,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"256x256 unit cell, eps=12 disc lattice r=0.3, {nk} k on Gamma-X-M-Gamma, "
                                f"nev {prob.nev} (+{prob.nthrow}), tol {prob.tol:g}, {prob.levels}-level MG; "
-                               f"path in {args.segments} batched segments",
+                               f"path in {head['S']} batched segments"
+                               + (" (its legs)" if args.segments == 0 else ""),
                    "n": prob.n, "nk": nk, "nev": prob.nev, "p": prob.p, "levels": prob.levels,
-                   "segments": args.segments},
+                   "segments": head["S"]},
         "p50_solve_ms": round(float(np.percentile(ms_all, 50)), 3),
         "p99_solve_ms": round(float(np.percentile(ms_all, 99)), 3),
         "iterations_per_k": head["recs"][0]["iters"].tolist(),
@@ -284,7 +292,7 @@ def main():
         "launch_shapes": {"headline": head["shapes"], "fp64_plain": plain["shapes"] if plain else None},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, int(head["recs"][0]["iters"].sum()), args.segments)
+        out["cpu_baseline"] = cpu_baseline(prob, int(head["recs"][0]["iters"].sum()), head["S"])
     if not args.no_serving:
         out["serving"] = serving(args.serve_requests, seed=4)
     print(json.dumps(out), flush=True)

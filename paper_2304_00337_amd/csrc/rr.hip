@@ -49,6 +49,9 @@ __global__ __launch_bounds__(256) void k_rr_gram(View<const double> Sv, int q,
   for (int a = 0; a < RT; ++a)
 #pragma unroll
     for (int b = 0; b < RT; ++b) { gr[a][b] = 0; gi[a][b] = 0; hr[a][b] = 0; hi[a][b] = 0; }
+  // diagonal tiles (all of them when q fits one tile) stage one column range: the curls of
+  // the i- and j-ranges coincide and are formed once
+  const bool diag = ti0 == tj0;
   for (int64_t r0 = rs; r0 < re; r0 += CH) {
     // consecutive threads take consecutive nodes of one column (coalesced reads)
     for (int e = tid; e < CH * TB; e += 256) {
@@ -64,9 +67,11 @@ __global__ __launch_bounds__(256) void k_rr_gram(View<const double> Sv, int q,
         xi[r][c] = col[N + d];
         xr[CH + r][c] = col[nm + d];
         xi[CH + r][c] = col[N + nm + d];
-        const Cx<double> w = cell_curl<double, double>(col, N, n, m, nm, j1, j2, p);
-        ar_[r][c] = wsc * w.re;
-        ai_[r][c] = wsc * w.im;
+        if (!diag) {
+          const Cx<double> w = cell_curl<double, double>(col, N, n, m, nm, j1, j2, p);
+          ar_[r][c] = wsc * w.re;
+          ai_[r][c] = wsc * w.im;
+        }
       } else {
         xr[r][c] = 0; xi[r][c] = 0; xr[CH + r][c] = 0; xi[CH + r][c] = 0;
         ar_[r][c] = 0; ai_[r][c] = 0;
@@ -110,8 +115,13 @@ __global__ __launch_bounds__(256) void k_rr_gram(View<const double> Sv, int q,
 #pragma unroll 4
     for (int rr = 0; rr < CH; ++rr) {
       double u_r[RT], u_i[RT], v_r[RT], v_i[RT];
+      if (diag) {
 #pragma unroll
-      for (int a = 0; a < RT; ++a) { u_r[a] = ar_[rr][ty * RT + a]; u_i[a] = ai_[rr][ty * RT + a]; }
+        for (int a = 0; a < RT; ++a) { u_r[a] = br_[rr][ty * RT + a]; u_i[a] = bi_[rr][ty * RT + a]; }
+      } else {
+#pragma unroll
+        for (int a = 0; a < RT; ++a) { u_r[a] = ar_[rr][ty * RT + a]; u_i[a] = ai_[rr][ty * RT + a]; }
+      }
 #pragma unroll
       for (int b = 0; b < RT; ++b) { v_r[b] = br_[rr][tx * RT + b]; v_i[b] = bi_[rr][tx * RT + b]; }
 #pragma unroll
