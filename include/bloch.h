@@ -83,6 +83,10 @@ typedef struct bl_opts {
   int32_t autotune;     /* 1 = time the candidate launch shapes of the smoothers and of the
                            Rayleigh-Ritz products when a handle is created and keep the
                            fastest (cached per shape; never changes results), 0 = fixed (1) */
+  int32_t coarse_fuse;  /* 1 = run the coarse levels of every V-cycle (those whose vectors
+                           fit one workgroup's LDS) in one launch per column; bit-identical
+                           to the per-level launches, 0 = per-level launches (1)           */
+  int32_t reserved1;
   double tol;           /* stop when ||A e_i - lambda_i M e_i||_2 / (lambda_i ||M e_i||_2)
                            <= tol for the first nev vectors (1e-8)                         */
   double mu;            /* regularisation of the preconditioned A + mu M (Section 5);
@@ -103,6 +107,8 @@ typedef struct bl_info {
                                     block, columns per thread, XCD-major order (0/1)   */
   int32_t nodal_smooth_shape[3]; /* same for the nodal smoother                        */
   int32_t rr_tile;      /* Rayleigh-Ritz output tile for the 2p-wide basis: 48 or 64   */
+  int32_t fused_edge_level;   /* first level of the edge V-cycle run fused, -1 = none    */
+  int32_t fused_nodal_level;  /* same for the nodal V-cycle (cycle precision)            */
   int32_t reserved;
   double autotune_ms;   /* time spent tuning at creation (0 when cached or off)        */
 } bl_info;

@@ -75,7 +75,8 @@ def _info_dict(inf) -> dict:
             "sizes": [(inf.level_n[i], inf.level_m[i]) for i in range(L)],
             "edge_smooth_shape": list(inf.edge_smooth_shape),
             "nodal_smooth_shape": list(inf.nodal_smooth_shape),
-            "rr_tile": inf.rr_tile, "autotune_ms": inf.autotune_ms}
+            "rr_tile": inf.rr_tile, "autotune_ms": inf.autotune_ms,
+            "fused_edge_level": inf.fused_edge_level, "fused_nodal_level": inf.fused_nodal_level}
 
 
 def _marshal_problems(problems, want_last_vectors):

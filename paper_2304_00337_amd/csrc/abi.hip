@@ -57,6 +57,7 @@ void bl_default_opts(bl_opts* o, int32_t nev) {
   o->mu = 0.0;
   o->zero_rel = 1e-2;
   o->autotune = 1;
+  o->coarse_fuse = 1;
 }
 
 const char* bl_strerror(int code) {
@@ -121,6 +122,8 @@ void bl::fill_info(const bl_solver* s, bl_info* out) {
   out->nodal_smooth_shape[2] = s->tune_nodal.xcd;
   out->rr_tile = 16 * (s->tune_rr ? s->tune_rr : rr_tile(2 * s->p));
   out->autotune_ms = s->tune_ms;
+  out->fused_edge_level = s->fuse_edge[s->opts.precision ? 1 : 0];
+  out->fused_nodal_level = s->fuse_nodal[s->opts.precision ? 1 : 0];
 }
 
 extern "C" {

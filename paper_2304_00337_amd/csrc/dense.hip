@@ -10,6 +10,10 @@
 #include <cstdio>
 #include <cstdlib>
 
+// The coarse solve is repeated inside the fused coarse cycles (coarse.hip) with the same
+// operations; no contraction on either side keeps the two bit-identical.
+#pragma clang fp contract(off)
+
 namespace bl {
 
 struct c2 {

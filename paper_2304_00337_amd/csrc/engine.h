@@ -161,6 +161,9 @@ struct bl_solver {
   int64_t timed_count = 0;
   int64_t timed_cols = 0;
   bool debug = false;
+  // first fused coarse level of the edge / nodal V-cycles per precision (-1: none)
+  int fuse_edge[2] = {-1, -1};
+  int fuse_nodal[2] = {-1, -1};
   // launch shapes chosen by the autotuner (defaults when it is off)
   bl::SmoothShape tune_edge, tune_nodal;
   int tune_rr = 0;            // Rayleigh-Ritz output tile for q = 2p (0 = by padding)

@@ -122,6 +122,35 @@ template <typename T>
 void fill_zero(T* p, int64_t count, hipStream_t st);
 template <typename T>
 void zero_cols(View<T> x, int64_t len, const Launch& L);
+// Fused coarse levels of a V-cycle: from the first fused level down to the coarsest, one
+// workgroup per column runs the whole rest of the cycle in LDS (coarse.hip).  Level 0 of the
+// description is the first fused level; the last one is solved with the dense inverse.
+constexpr int kMaxFused = 6;
+struct CoarseLevel {
+  Geo g;
+  PatchT T4;
+  const double* k64;    // kappa, slot-major (nm per slot)
+  const float* k32;
+  const double* si64;   // patch inverses, slot-major (6 nm per slot); null on the coarsest
+  const float* si32;
+};
+struct CoarseCycle {
+  int nlev;             // fused levels including the coarsest
+  int nu_pre, nu_post;
+  int64_t nc;           // unknowns of the coarsest level (edges or nodes)
+  const void* inv;      // its inverse in the cycle's precision, slot-major (nc x nc complex)
+  NodalStencil ns;      // nodal cycles
+  CoarseLevel L[kMaxFused];
+};
+// LDS bytes of a fused cycle with elements of `elem` bytes, and the device's limit.
+size_t fused_lds_bytes(const CoarseCycle& C, bool edge, size_t elem);
+size_t fused_lds_limit();
+template <typename T>
+void edge_vcycle_fused(View<const T> b, View<T> x, const CoarseCycle& C, const Phase* ph, const double* mu,
+                       const Launch& L);
+template <typename T>
+void nodal_vcycle_fused(View<const T> b, View<T> x, const CoarseCycle& C, const Phase* ph, const Launch& L);
+
 // Coarsest-level direct solvers.  Probe columns: n shared unit vectors (identity_block);
 // per slot s the probe results (n columns) at cols + s * n * 2n and the matrices (row-major
 // interleaved complex) at mat + s * n * n * 2.

@@ -119,6 +119,7 @@ int validate_opts(const bl_opts* o) {
   if (o->precision != 0 && o->precision != 1) return set_error(BL_EINVAL, "precision must be 0 or 1%s");
   if (o->extrap_depth < 1 || o->extrap_depth > 3) return set_error(BL_EINVAL, "extrap_depth must be 1..3%s");
   if (o->autotune != 0 && o->autotune != 1) return set_error(BL_EINVAL, "autotune must be 0 or 1%s");
+  if (o->coarse_fuse != 0 && o->coarse_fuse != 1) return set_error(BL_EINVAL, "coarse_fuse must be 0 or 1%s");
   if (!(o->tol > 0)) return set_error(BL_EINVAL, "tol must be positive%s");
   return BL_OK;
 }
@@ -245,6 +246,38 @@ void timing_collect(bl_solver* s) {
   s->ev_used = 0;
 }
 
+// ---- fused coarse levels --------------------------------------------------------------------
+CoarseCycle coarse_cycle(const bl_solver* s, int first, const void* inv, int64_t nc) {
+  CoarseCycle C{};
+  C.nlev = (int)s->lv.size() - first;
+  C.nu_pre = s->opts.nu_pre;
+  C.nu_post = s->opts.nu_post;
+  C.nc = nc;
+  C.inv = inv;
+  C.ns = s->ns;
+  for (int i = 0; i < C.nlev; ++i) {
+    const Level& L = s->lv[first + i];
+    C.L[i] = CoarseLevel{L.g, L.T4, L.kappa64, L.kappa32, L.sinv64, L.sinv32};
+  }
+  return C;
+}
+
+// First level from which the rest of a V-cycle fits one workgroup's LDS (at least two
+// levels, at most 64 x 64 nodes on the first, at most kMaxFused levels), or -1.
+int plan_fusion(const bl_solver* s, bool edge, size_t elem) {
+  if (!s->opts.coarse_fuse) return -1;
+  const int nl = (int)s->lv.size();
+  const size_t cap = std::min<size_t>(fused_lds_limit(), 144 * 1024);
+  int best = -1;
+  for (int f = nl - 2; f >= 0 && nl - f <= kMaxFused; --f) {
+    if (s->lv[f].g.nm > 4096) break;
+    const CoarseCycle C = coarse_cycle(s, f, nullptr, edge ? s->nce : s->ncn);
+    if (fused_lds_bytes(C, edge, elem) > cap) break;
+    best = f;
+  }
+  return best;
+}
+
 // ---- edge V-cycle for K = A + mu M with zero initial guess: x = V(b) ---------------------
 template <typename T>
 void vcycle_edge(bl_solver* s, int l, View<const T> b, View<T> x, const Launch& L) {
@@ -253,6 +286,11 @@ void vcycle_edge(bl_solver* s, int l, View<const T> b, View<T> x, const Launch& 
   const int nl = (int)s->lv.size();
   if (l == nl - 1) {
     dense_apply<T>(kc_inv<T>(s), s->nce, b, x, L);
+    s->launches += 1;
+    return;
+  }
+  if (l == s->fuse_edge[pr]) {
+    edge_vcycle_fused<T>(b, x, coarse_cycle(s, l, kc_inv<T>(s), s->nce), s->ph_d, s->mu_d, L);
     s->launches += 1;
     return;
   }
@@ -288,6 +326,11 @@ void vcycle_nodal(bl_solver* s, int l, View<const T> b, View<T> x, const Launch&
   const int nl = (int)s->lv.size();
   if (l == nl - 1) {
     dense_apply<T>(pc_inv<T>(s), s->ncn, b, x, L);
+    s->launches += 1;
+    return;
+  }
+  if (l == s->fuse_nodal[pr]) {
+    nodal_vcycle_fused<T>(b, x, coarse_cycle(s, l, pc_inv<T>(s), s->ncn), s->ph_d, L);
     s->launches += 1;
     return;
   }
@@ -716,6 +759,10 @@ int engine_create(const bl_grid* grid, const bl_opts* opts, int nslots, hipStrea
   }
   HIP_OK(hipStreamSynchronize(s->st));
   if ((rc = check_hip())) return fail(rc);
+  for (int pr = 0; pr < 2; ++pr) {
+    s->fuse_edge[pr] = plan_fusion(s, true, pr ? 4 : 8);
+    s->fuse_nodal[pr] = plan_fusion(s, false, pr ? 4 : 8);
+  }
   if (o.autotune && (rc = engine_autotune(s))) return fail(rc);
   *out = s;
   return BL_OK;

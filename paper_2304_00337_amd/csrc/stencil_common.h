@@ -6,6 +6,10 @@
 
 #include "internal.h"
 
+// No contraction into FMAs in these helpers either: they are inlined into the per-level
+// kernels and the fused coarse cycles alike, which must round identically.
+#pragma clang fp contract(off)
+
 namespace bl {
 
 template <typename T>

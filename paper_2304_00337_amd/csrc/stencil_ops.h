@@ -1,0 +1,191 @@
+// Per-point bodies of the stencil kernels (Sections 3-5), shared by the per-level kernels of
+// stencils.hip and the fused coarse-level V-cycles of coarse.hip, so that both perform the
+// same operations in the same order (and, with contraction off, round identically).
+// Vectors are planar (re at [0, N), im at [N, 2N)) and read in Bloch-extended coordinates.
+#pragma once
+
+#include "stencil_common.h"
+
+#pragma clang fp contract(off)
+
+namespace bl {
+
+// (A x)_d and (M x)_d at edge d; kapf(i) gives kappa of cell i in T.
+template <typename TI, typename T, typename KF>
+__device__ __forceinline__ void edge_AM(const TI* xc, int64_t N, int n, int m, int64_t nm, int64_t d,
+                                        const KF& kapf, T s, T mx, T my, const Ph<T>& p, Cx<T>& Au,
+                                        Cx<T>& Mu) {
+  const T two3 = (T)(2.0 / 3.0), one6 = (T)(1.0 / 6.0);
+  if (d < nm) {
+    const int j1 = (int)(d % n), j2 = (int)(d / n);
+    const Cx<T> wlo = cell_curl<TI, T>(xc, N, n, m, nm, j1, j2 - 1, p);
+    const Cx<T> whi = cell_curl<TI, T>(xc, N, n, m, nm, j1, j2, p);
+    const T klo = kapf((int64_t)wrapi(j2 - 1, m) * n + j1);
+    const T khi = kapf((int64_t)j2 * n + j1);
+    Au = s * ((klo * wlo) - (khi * whi));
+    const Cx<T> u0 = {(T)xc[d], (T)xc[N + d]};
+    Mu = mx * ((two3 * u0) + one6 * (fetch<TI, T>(xc, N, n, m, 0, j1, j2 + 1, p) +
+                                     fetch<TI, T>(xc, N, n, m, 0, j1, j2 - 1, p)));
+  } else {
+    const int64_t e = d - nm;
+    const int j1 = (int)(e % n), j2 = (int)(e / n);
+    const Cx<T> wr = cell_curl<TI, T>(xc, N, n, m, nm, j1, j2, p);
+    const Cx<T> wl = cell_curl<TI, T>(xc, N, n, m, nm, j1 - 1, j2, p);
+    const T kr = kapf((int64_t)j2 * n + j1);
+    const T kl = kapf((int64_t)j2 * n + wrapi(j1 - 1, n));
+    Au = s * ((kr * wr) - (kl * wl));
+    const Cx<T> u0 = {(T)xc[d], (T)xc[N + d]};
+    Mu = my * ((two3 * u0) + one6 * (fetch<TI, T>(xc, N, n, m, nm, j1 + 1, j2, p) +
+                                     fetch<TI, T>(xc, N, n, m, nm, j1 - 1, j2, p)));
+  }
+}
+
+// Stabilised node-patch update at node (p1, p2) (Section 5): residual of K = A + mu M on the
+// four patch edges, delta = T diag(1/mu, S^{-1}) T^T r, x += delta.  k* are the kappas of the
+// four cells around the node, si the node's 3x3 inverse (s00, s01, s02, s11, s12, s22).
+template <typename T>
+__device__ __forceinline__ void edge_patch_gs(T* xc, const T* bc, int64_t N, int n, int m, int64_t nm,
+                                              int p1, int p2, T kne, T knw, T ksw, T kse, const T* si,
+                                              const PatchT& T4, T s, T mu, T mmx, T mmy,
+                                              const Ph<T>& p) {
+  const T two3 = (T)(2.0 / 3.0), one6 = (T)(1.0 / 6.0);
+  const T s00 = si[0], s01 = si[1], s02 = si[2], s11 = si[3], s12 = si[4], s22 = si[5];
+  const Cx<T> X00 = fetch<T, T>(xc, N, n, m, 0, p1, p2, p);
+  const Cx<T> X01 = fetch<T, T>(xc, N, n, m, 0, p1, p2 + 1, p);
+  const Cx<T> X0m = fetch<T, T>(xc, N, n, m, 0, p1, p2 - 1, p);
+  const Cx<T> Xm0 = fetch<T, T>(xc, N, n, m, 0, p1 - 1, p2, p);
+  const Cx<T> Xm1 = fetch<T, T>(xc, N, n, m, 0, p1 - 1, p2 + 1, p);
+  const Cx<T> Xmm = fetch<T, T>(xc, N, n, m, 0, p1 - 1, p2 - 1, p);
+  const Cx<T> Y00 = fetch<T, T>(xc, N, n, m, nm, p1, p2, p);
+  const Cx<T> Y10 = fetch<T, T>(xc, N, n, m, nm, p1 + 1, p2, p);
+  const Cx<T> Ym0 = fetch<T, T>(xc, N, n, m, nm, p1 - 1, p2, p);
+  const Cx<T> Y0m = fetch<T, T>(xc, N, n, m, nm, p1, p2 - 1, p);
+  const Cx<T> Y1m = fetch<T, T>(xc, N, n, m, nm, p1 + 1, p2 - 1, p);
+  const Cx<T> Ymm = fetch<T, T>(xc, N, n, m, nm, p1 - 1, p2 - 1, p);
+  const Cx<T> wne = X01 - X00 + Y00 - Y10;
+  const Cx<T> wnw = Xm1 - Xm0 + Ym0 - Y00;
+  const Cx<T> wsw = Xm0 - Xmm + Ymm - Y0m;
+  const Cx<T> wse = X00 - X0m + Y0m - Y1m;
+  Cx<T> r[4];
+  r[0] = fetch<T, T>(bc, N, n, m, 0, p1, p2, p) -
+         ((s * ((kse * wse) - (kne * wne))) + mmx * ((two3 * X00) + one6 * (X01 + X0m)));
+  r[1] = fetch<T, T>(bc, N, n, m, 0, p1 - 1, p2, p) -
+         ((s * ((ksw * wsw) - (knw * wnw))) + mmx * ((two3 * Xm0) + one6 * (Xm1 + Xmm)));
+  r[2] = fetch<T, T>(bc, N, n, m, nm, p1, p2, p) -
+         ((s * ((kne * wne) - (knw * wnw))) + mmy * ((two3 * Y00) + one6 * (Y10 + Ym0)));
+  r[3] = fetch<T, T>(bc, N, n, m, nm, p1, p2 - 1, p) -
+         ((s * ((kse * wse) - (ksw * wsw))) + mmy * ((two3 * Y0m) + one6 * (Y1m + Ymm)));
+  // y = T^T r
+  Cx<T> y[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    Cx<T> acc = {0, 0};
+#pragma unroll
+    for (int l = 0; l < 4; ++l) acc = acc + ((T)T4.t[l * 4 + a] * r[l]);
+    y[a] = acc;
+  }
+  Cx<T> z[4];
+  z[0] = ((T)1 / mu) * y[0];
+  z[1] = (s00 * y[1]) + (s01 * y[2]) + (s02 * y[3]);
+  z[2] = (s01 * y[1]) + (s11 * y[2]) + (s12 * y[3]);
+  z[3] = (s02 * y[1]) + (s12 * y[2]) + (s22 * y[3]);
+  Cx<T> dl[4];
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    Cx<T> acc = {0, 0};
+#pragma unroll
+    for (int a = 0; a < 4; ++a) acc = acc + ((T)T4.t[l * 4 + a] * z[a]);
+    dl[l] = acc;
+  }
+  add_ext<T, T>(xc, N, n, m, 0, p1, p2, dl[0], p);
+  add_ext<T, T>(xc, N, n, m, 0, p1 - 1, p2, dl[1], p);
+  add_ext<T, T>(xc, N, n, m, nm, p1, p2, dl[2], p);
+  add_ext<T, T>(xc, N, n, m, nm, p1, p2 - 1, dl[3], p);
+}
+
+// Coarse edge d of (Pr^* r): the adjoint of the edge embedding (1/2 collinear, 1/4 parallel).
+template <typename T>
+__device__ __forceinline__ Cx<T> edge_restrict_at(const T* r, const Geo& gf, const Geo& gc, int64_t d,
+                                                  const Ph<T>& p) {
+  const int nf = gf.n, mf = gf.m;
+  const int64_t Nf = gf.ne, nmf = gf.nm;
+  const T h = (T)0.5, q = (T)0.25;
+  if (d < gc.nm) {
+    const int J1 = (int)(d % gc.n), J2 = (int)(d / gc.n);
+    const int f1 = 2 * J1, f2 = 2 * J2;
+    return h * (fetch<T, T>(r, Nf, nf, mf, 0, f1, f2, p) + fetch<T, T>(r, Nf, nf, mf, 0, f1 + 1, f2, p)) +
+           q * (fetch<T, T>(r, Nf, nf, mf, 0, f1, f2 + 1, p) + fetch<T, T>(r, Nf, nf, mf, 0, f1 + 1, f2 + 1, p) +
+                fetch<T, T>(r, Nf, nf, mf, 0, f1, f2 - 1, p) + fetch<T, T>(r, Nf, nf, mf, 0, f1 + 1, f2 - 1, p));
+  }
+  const int64_t e = d - gc.nm;
+  const int J1 = (int)(e % gc.n), J2 = (int)(e / gc.n);
+  const int f1 = 2 * J1, f2 = 2 * J2;
+  return h * (fetch<T, T>(r, Nf, nf, mf, nmf, f1, f2, p) + fetch<T, T>(r, Nf, nf, mf, nmf, f1, f2 + 1, p)) +
+         q * (fetch<T, T>(r, Nf, nf, mf, nmf, f1 + 1, f2, p) + fetch<T, T>(r, Nf, nf, mf, nmf, f1 + 1, f2 + 1, p) +
+              fetch<T, T>(r, Nf, nf, mf, nmf, f1 - 1, f2, p) + fetch<T, T>(r, Nf, nf, mf, nmf, f1 - 1, f2 + 1, p));
+}
+
+// Fine edge d of (Pr x_c): the embedding of the coarse Nedelec function.
+template <typename T>
+__device__ __forceinline__ Cx<T> edge_prolong_at(const T* c, const Geo& gc, const Geo& gf, int64_t d,
+                                                 const Ph<T>& p) {
+  const int nc = gc.n, mc = gc.m;
+  const int64_t Nc = gc.ne, nmc = gc.nm;
+  if (d < gf.nm) {
+    const int f1 = (int)(d % gf.n), f2 = (int)(d / gf.n);
+    const int J1 = f1 >> 1;
+    if ((f2 & 1) == 0) return (T)0.5 * fetch<T, T>(c, Nc, nc, mc, 0, J1, f2 >> 1, p);
+    return (T)0.25 * (fetch<T, T>(c, Nc, nc, mc, 0, J1, f2 >> 1, p) + fetch<T, T>(c, Nc, nc, mc, 0, J1, (f2 >> 1) + 1, p));
+  }
+  const int64_t e = d - gf.nm;
+  const int f1 = (int)(e % gf.n), f2 = (int)(e / gf.n);
+  const int J2 = f2 >> 1;
+  if ((f1 & 1) == 0) return (T)0.5 * fetch<T, T>(c, Nc, nc, mc, nmc, f1 >> 1, J2, p);
+  return (T)0.25 * (fetch<T, T>(c, Nc, nc, mc, nmc, f1 >> 1, J2, p) + fetch<T, T>(c, Nc, nc, mc, nmc, (f1 >> 1) + 1, J2, p));
+}
+
+// 9-point P = L^* M L at node (p1, p2); the coefficients depend only on h2/h1.
+template <typename T>
+__device__ __forceinline__ Cx<T> nodal_stencil(const T* c, int64_t N, int n, int m, int p1, int p2,
+                                               const NodalStencil& s, const Ph<T>& p) {
+  const Cx<T> u = {c[(int64_t)p2 * n + p1], c[N + (int64_t)p2 * n + p1]};
+  const Cx<T> ex = fetch<T, T>(c, N, n, m, 0, p1 + 1, p2, p) + fetch<T, T>(c, N, n, m, 0, p1 - 1, p2, p);
+  const Cx<T> ey = fetch<T, T>(c, N, n, m, 0, p1, p2 + 1, p) + fetch<T, T>(c, N, n, m, 0, p1, p2 - 1, p);
+  const Cx<T> ed = fetch<T, T>(c, N, n, m, 0, p1 + 1, p2 + 1, p) + fetch<T, T>(c, N, n, m, 0, p1 - 1, p2 + 1, p) +
+                   fetch<T, T>(c, N, n, m, 0, p1 + 1, p2 - 1, p) + fetch<T, T>(c, N, n, m, 0, p1 - 1, p2 - 1, p);
+  return ((T)s.c0 * u) + ((T)s.cx * ex) + ((T)s.cy * ey) + ((T)s.cd * ed);
+}
+
+// Coarse node d of the full-weighting restriction (adjoint of bilinear interpolation).
+template <typename T>
+__device__ __forceinline__ Cx<T> nodal_restrict_at(const T* r, const Geo& gf, const Geo& gc, int64_t d,
+                                                   const Ph<T>& p) {
+  const int J1 = (int)(d % gc.n), J2 = (int)(d / gc.n);
+  Cx<T> v = {0, 0};
+#pragma unroll
+  for (int d2 = -1; d2 <= 1; ++d2)
+#pragma unroll
+    for (int d1 = -1; d1 <= 1; ++d1) {
+      const T w = (T)((d1 == 0 ? 1.0 : 0.5) * (d2 == 0 ? 1.0 : 0.5));
+      v = v + (w * fetch<T, T>(r, gf.nm, gf.n, gf.m, 0, 2 * J1 + d1, 2 * J2 + d2, p));
+    }
+  return v;
+}
+
+// Fine node d of the bilinear interpolation of the coarse nodal function.
+template <typename T>
+__device__ __forceinline__ Cx<T> nodal_prolong_at(const T* c, const Geo& gc, const Geo& gf, int64_t d,
+                                                  const Ph<T>& p) {
+  const int f1 = (int)(d % gf.n), f2 = (int)(d / gf.n);
+  const int J1 = f1 >> 1, J2 = f2 >> 1;
+  const bool o1 = f1 & 1, o2 = f2 & 1;
+  const Cx<T> c00 = fetch<T, T>(c, gc.nm, gc.n, gc.m, 0, J1, J2, p);
+  if (!o1 && !o2) return c00;
+  if (o1 && !o2) return (T)0.5 * (c00 + fetch<T, T>(c, gc.nm, gc.n, gc.m, 0, J1 + 1, J2, p));
+  if (!o1 && o2) return (T)0.5 * (c00 + fetch<T, T>(c, gc.nm, gc.n, gc.m, 0, J1, J2 + 1, p));
+  return (T)0.25 * (c00 + fetch<T, T>(c, gc.nm, gc.n, gc.m, 0, J1 + 1, J2, p) +
+                    fetch<T, T>(c, gc.nm, gc.n, gc.m, 0, J1, J2 + 1, p) +
+                    fetch<T, T>(c, gc.nm, gc.n, gc.m, 0, J1 + 1, J2 + 1, p));
+}
+
+}  // namespace bl

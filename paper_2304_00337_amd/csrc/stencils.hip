@@ -8,13 +8,14 @@
 // so every stencil is the plain translation-invariant one and the phases enter only
 // through the reads (and writes) that cross the cell boundary.  The local patch matrices
 // are therefore real and independent of k.
-#include "stencil_common.h"
+#include "stencil_ops.h"
 
 #include <cmath>
 
 // No contraction of multiplies and adds into FMAs: every launch-shape variant of a kernel
-// then performs exactly the written operations, so results do not depend on the shape the
-// autotuner picks.  The kernels are bandwidth-bound; the extra instructions cost nothing.
+// (and the fused coarse-level cycles) then performs exactly the written operations, so
+// results do not depend on the shape the autotuner picks.  The kernels are bandwidth-bound;
+// the extra instructions cost nothing.
 #pragma clang fp contract(off)
 
 namespace bl {
@@ -42,30 +43,8 @@ __global__ __launch_bounds__(256) void k_edge_apply(View<const TI> xv, View<cons
   T rr = 0, mm = 0;
   if (d < N) {
     Cx<T> Au, Mu;
-    const T s = (T)g.s;
-    const T two3 = (T)(2.0 / 3.0), one6 = (T)(1.0 / 6.0);
-    if (d < nm) {
-      const int j1 = (int)(d % n), j2 = (int)(d / n);
-      const Cx<T> wlo = cell_curl<TI, T>(xc, N, n, m, nm, j1, j2 - 1, p);
-      const Cx<T> whi = cell_curl<TI, T>(xc, N, n, m, nm, j1, j2, p);
-      const T klo = kap<T>(k64, k32, (int64_t)wrapi(j2 - 1, m) * n + j1);
-      const T khi = kap<T>(k64, k32, (int64_t)j2 * n + j1);
-      Au = s * ((klo * wlo) - (khi * whi));
-      const Cx<T> u0 = {(T)xc[d], (T)xc[N + d]};
-      Mu = (T)g.mx * ((two3 * u0) + one6 * (fetch<TI, T>(xc, N, n, m, 0, j1, j2 + 1, p) +
-                                            fetch<TI, T>(xc, N, n, m, 0, j1, j2 - 1, p)));
-    } else {
-      const int64_t e = d - nm;
-      const int j1 = (int)(e % n), j2 = (int)(e / n);
-      const Cx<T> wr = cell_curl<TI, T>(xc, N, n, m, nm, j1, j2, p);
-      const Cx<T> wl = cell_curl<TI, T>(xc, N, n, m, nm, j1 - 1, j2, p);
-      const T kr = kap<T>(k64, k32, (int64_t)j2 * n + j1);
-      const T kl = kap<T>(k64, k32, (int64_t)j2 * n + wrapi(j1 - 1, n));
-      Au = s * ((kr * wr) - (kl * wl));
-      const Cx<T> u0 = {(T)xc[d], (T)xc[N + d]};
-      Mu = (T)g.my * ((two3 * u0) + one6 * (fetch<TI, T>(xc, N, n, m, nm, j1 + 1, j2, p) +
-                                            fetch<TI, T>(xc, N, n, m, nm, j1 - 1, j2, p)));
-    }
+    edge_AM<TI, T>(xc, N, n, m, nm, d, [&](int64_t i) { return kap<T>(k64, k32, i); }, (T)g.s, (T)g.mx,
+                   (T)g.my, p, Au, Mu);
     Cx<T> r;
     if (MODE == EM_A) {
       r = Au;
@@ -201,68 +180,15 @@ __global__ __launch_bounds__(256) void k_edge_gs(View<T> xv, View<const T> bv,
   const T ksw = kap<T>(k64, k32, (int64_t)p2m * n + p1m);
   const T kse = kap<T>(k64, k32, (int64_t)p2m * n + p1);
   const T* si = pick<T>(si64, si32) + 6 * ((int64_t)slot * nm + (int64_t)p2 * n + p1);
-  const T s00 = si[0], s01 = si[1], s02 = si[2], s11 = si[3], s12 = si[4], s22 = si[5];
   const T s = (T)g.s, mu = (T)mus[slot];
-  const T two3 = (T)(2.0 / 3.0), one6 = (T)(1.0 / 6.0);
   const T mmx = mu * (T)g.mx, mmy = mu * (T)g.my;
 #pragma unroll
   for (int cc = 0; cc < CPT; ++cc) {
     const int j = j0 + cc;
     if (j >= ncps) break;
     const SJ sj{slot, j};
-    T* xc = colp(xv, sj, N);
-    const T* bc = colp(bv, sj, N);
-    const Cx<T> X00 = fetch<T, T>(xc, N, n, m, 0, p1, p2, p);
-    const Cx<T> X01 = fetch<T, T>(xc, N, n, m, 0, p1, p2 + 1, p);
-    const Cx<T> X0m = fetch<T, T>(xc, N, n, m, 0, p1, p2 - 1, p);
-    const Cx<T> Xm0 = fetch<T, T>(xc, N, n, m, 0, p1 - 1, p2, p);
-    const Cx<T> Xm1 = fetch<T, T>(xc, N, n, m, 0, p1 - 1, p2 + 1, p);
-    const Cx<T> Xmm = fetch<T, T>(xc, N, n, m, 0, p1 - 1, p2 - 1, p);
-    const Cx<T> Y00 = fetch<T, T>(xc, N, n, m, nm, p1, p2, p);
-    const Cx<T> Y10 = fetch<T, T>(xc, N, n, m, nm, p1 + 1, p2, p);
-    const Cx<T> Ym0 = fetch<T, T>(xc, N, n, m, nm, p1 - 1, p2, p);
-    const Cx<T> Y0m = fetch<T, T>(xc, N, n, m, nm, p1, p2 - 1, p);
-    const Cx<T> Y1m = fetch<T, T>(xc, N, n, m, nm, p1 + 1, p2 - 1, p);
-    const Cx<T> Ymm = fetch<T, T>(xc, N, n, m, nm, p1 - 1, p2 - 1, p);
-    const Cx<T> wne = X01 - X00 + Y00 - Y10;
-    const Cx<T> wnw = Xm1 - Xm0 + Ym0 - Y00;
-    const Cx<T> wsw = Xm0 - Xmm + Ymm - Y0m;
-    const Cx<T> wse = X00 - X0m + Y0m - Y1m;
-    Cx<T> r[4];
-    r[0] = fetch<T, T>(bc, N, n, m, 0, p1, p2, p) -
-           ((s * ((kse * wse) - (kne * wne))) + mmx * ((two3 * X00) + one6 * (X01 + X0m)));
-    r[1] = fetch<T, T>(bc, N, n, m, 0, p1 - 1, p2, p) -
-           ((s * ((ksw * wsw) - (knw * wnw))) + mmx * ((two3 * Xm0) + one6 * (Xm1 + Xmm)));
-    r[2] = fetch<T, T>(bc, N, n, m, nm, p1, p2, p) -
-           ((s * ((kne * wne) - (knw * wnw))) + mmy * ((two3 * Y00) + one6 * (Y10 + Ym0)));
-    r[3] = fetch<T, T>(bc, N, n, m, nm, p1, p2 - 1, p) -
-           ((s * ((kse * wse) - (ksw * wsw))) + mmy * ((two3 * Y0m) + one6 * (Y1m + Ymm)));
-    // y = T^T r
-    Cx<T> y[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      Cx<T> acc = {0, 0};
-#pragma unroll
-      for (int l = 0; l < 4; ++l) acc = acc + ((T)T4.t[l * 4 + a] * r[l]);
-      y[a] = acc;
-    }
-    Cx<T> z[4];
-    z[0] = ((T)1 / mu) * y[0];
-    z[1] = (s00 * y[1]) + (s01 * y[2]) + (s02 * y[3]);
-    z[2] = (s01 * y[1]) + (s11 * y[2]) + (s12 * y[3]);
-    z[3] = (s02 * y[1]) + (s12 * y[2]) + (s22 * y[3]);
-    Cx<T> dl[4];
-#pragma unroll
-    for (int l = 0; l < 4; ++l) {
-      Cx<T> acc = {0, 0};
-#pragma unroll
-      for (int a = 0; a < 4; ++a) acc = acc + ((T)T4.t[l * 4 + a] * z[a]);
-      dl[l] = acc;
-    }
-    add_ext<T, T>(xc, N, n, m, 0, p1, p2, dl[0], p);
-    add_ext<T, T>(xc, N, n, m, 0, p1 - 1, p2, dl[1], p);
-    add_ext<T, T>(xc, N, n, m, nm, p1, p2, dl[2], p);
-    add_ext<T, T>(xc, N, n, m, nm, p1, p2 - 1, dl[3], p);
+    edge_patch_gs<T>(colp(xv, sj, N), colp(bv, sj, N), N, n, m, nm, p1, p2, kne, knw, ksw, kse, si, T4, s,
+                     mu, mmx, mmy, p);
   }
 }
 
@@ -387,25 +313,7 @@ __global__ __launch_bounds__(256) void k_edge_restrict(View<const T> rv, Geo gf,
   const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (d >= gc.ne) return;
   const Ph<T> p = cast_phase<T>(phs[sj.slot]);
-  const T* r = colp(rv, sj, gf.ne);
-  const int nf = gf.n, mf = gf.m;
-  const int64_t Nf = gf.ne, nmf = gf.nm;
-  const T h = (T)0.5, q = (T)0.25;
-  Cx<T> v;
-  if (d < gc.nm) {
-    const int J1 = (int)(d % gc.n), J2 = (int)(d / gc.n);
-    const int f1 = 2 * J1, f2 = 2 * J2;
-    v = h * (fetch<T, T>(r, Nf, nf, mf, 0, f1, f2, p) + fetch<T, T>(r, Nf, nf, mf, 0, f1 + 1, f2, p)) +
-        q * (fetch<T, T>(r, Nf, nf, mf, 0, f1, f2 + 1, p) + fetch<T, T>(r, Nf, nf, mf, 0, f1 + 1, f2 + 1, p) +
-             fetch<T, T>(r, Nf, nf, mf, 0, f1, f2 - 1, p) + fetch<T, T>(r, Nf, nf, mf, 0, f1 + 1, f2 - 1, p));
-  } else {
-    const int64_t e = d - gc.nm;
-    const int J1 = (int)(e % gc.n), J2 = (int)(e / gc.n);
-    const int f1 = 2 * J1, f2 = 2 * J2;
-    v = h * (fetch<T, T>(r, Nf, nf, mf, nmf, f1, f2, p) + fetch<T, T>(r, Nf, nf, mf, nmf, f1, f2 + 1, p)) +
-        q * (fetch<T, T>(r, Nf, nf, mf, nmf, f1 + 1, f2, p) + fetch<T, T>(r, Nf, nf, mf, nmf, f1 + 1, f2 + 1, p) +
-             fetch<T, T>(r, Nf, nf, mf, nmf, f1 - 1, f2, p) + fetch<T, T>(r, Nf, nf, mf, nmf, f1 - 1, f2 + 1, p));
-  }
+  const Cx<T> v = edge_restrict_at<T>(colp(rv, sj, gf.ne), gf, gc, d, p);
   T* o = colp(bv, sj, gc.ne);
   o[d] = v.re;
   o[gc.ne + d] = v.im;
@@ -419,28 +327,7 @@ __global__ __launch_bounds__(256) void k_edge_prolong_add(View<const T> cv, Geo 
   const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (d >= gf.ne) return;
   const Ph<T> p = cast_phase<T>(phs[sj.slot]);
-  const T* c = colp(cv, sj, gc.ne);
-  const int nc = gc.n, mc = gc.m;
-  const int64_t Nc = gc.ne, nmc = gc.nm;
-  Cx<T> v;
-  if (d < gf.nm) {
-    const int f1 = (int)(d % gf.n), f2 = (int)(d / gf.n);
-    const int J1 = f1 >> 1;
-    if ((f2 & 1) == 0) {
-      v = (T)0.5 * fetch<T, T>(c, Nc, nc, mc, 0, J1, f2 >> 1, p);
-    } else {
-      v = (T)0.25 * (fetch<T, T>(c, Nc, nc, mc, 0, J1, f2 >> 1, p) + fetch<T, T>(c, Nc, nc, mc, 0, J1, (f2 >> 1) + 1, p));
-    }
-  } else {
-    const int64_t e = d - gf.nm;
-    const int f1 = (int)(e % gf.n), f2 = (int)(e / gf.n);
-    const int J2 = f2 >> 1;
-    if ((f1 & 1) == 0) {
-      v = (T)0.5 * fetch<T, T>(c, Nc, nc, mc, nmc, f1 >> 1, J2, p);
-    } else {
-      v = (T)0.25 * (fetch<T, T>(c, Nc, nc, mc, nmc, f1 >> 1, J2, p) + fetch<T, T>(c, Nc, nc, mc, nmc, (f1 >> 1) + 1, J2, p));
-    }
-  }
+  const Cx<T> v = edge_prolong_at<T>(colp(cv, sj, gc.ne), gc, gf, d, p);
   T* o = colp(fv, sj, gf.ne);
   o[d] += v.re;
   o[gf.ne + d] += v.im;
@@ -468,17 +355,6 @@ template void edge_prolong_add<float>(View<const float>, const Geo&, View<float>
 // ------------------------------------------------------------------------------------------
 // Nodal operators.  P = L^* M L is the 9-point Bloch Q1 Laplacian; its coefficients depend
 // only on h2/h1, which bisection keeps, so every level uses the same stencil.
-template <typename T>
-__device__ __forceinline__ Cx<T> nodal_stencil(const T* c, int64_t N, int n, int m, int p1, int p2,
-                                               const NodalStencil& s, const Ph<T>& p) {
-  const Cx<T> u = {c[(int64_t)p2 * n + p1], c[N + (int64_t)p2 * n + p1]};
-  const Cx<T> ex = fetch<T, T>(c, N, n, m, 0, p1 + 1, p2, p) + fetch<T, T>(c, N, n, m, 0, p1 - 1, p2, p);
-  const Cx<T> ey = fetch<T, T>(c, N, n, m, 0, p1, p2 + 1, p) + fetch<T, T>(c, N, n, m, 0, p1, p2 - 1, p);
-  const Cx<T> ed = fetch<T, T>(c, N, n, m, 0, p1 + 1, p2 + 1, p) + fetch<T, T>(c, N, n, m, 0, p1 - 1, p2 + 1, p) +
-                   fetch<T, T>(c, N, n, m, 0, p1 + 1, p2 - 1, p) + fetch<T, T>(c, N, n, m, 0, p1 - 1, p2 - 1, p);
-  return ((T)s.c0 * u) + ((T)s.cx * ex) + ((T)s.cy * ey) + ((T)s.cd * ed);
-}
-
 template <typename T, bool RESID>
 __global__ __launch_bounds__(256) void k_nodal_apply(View<const T> xv, View<const T> bv, View<T> ov,
                                                      Geo g, const Phase* __restrict__ phs,
@@ -568,16 +444,7 @@ __global__ __launch_bounds__(256) void k_nodal_restrict(View<const T> rv, Geo gf
   const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (d >= gc.nm) return;
   const Ph<T> p = cast_phase<T>(phs[sj.slot]);
-  const T* r = colp(rv, sj, gf.nm);
-  const int J1 = (int)(d % gc.n), J2 = (int)(d / gc.n);
-  Cx<T> v = {0, 0};
-#pragma unroll
-  for (int d2 = -1; d2 <= 1; ++d2)
-#pragma unroll
-    for (int d1 = -1; d1 <= 1; ++d1) {
-      const T w = (T)((d1 == 0 ? 1.0 : 0.5) * (d2 == 0 ? 1.0 : 0.5));
-      v = v + (w * fetch<T, T>(r, gf.nm, gf.n, gf.m, 0, 2 * J1 + d1, 2 * J2 + d2, p));
-    }
+  const Cx<T> v = nodal_restrict_at<T>(colp(rv, sj, gf.nm), gf, gc, d, p);
   T* o = colp(bv, sj, gc.nm);
   o[d] = v.re;
   o[gc.nm + d] = v.im;
@@ -591,23 +458,7 @@ __global__ __launch_bounds__(256) void k_nodal_prolong_add(View<const T> cv, Geo
   const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (d >= gf.nm) return;
   const Ph<T> p = cast_phase<T>(phs[sj.slot]);
-  const T* c = colp(cv, sj, gc.nm);
-  const int f1 = (int)(d % gf.n), f2 = (int)(d / gf.n);
-  const int J1 = f1 >> 1, J2 = f2 >> 1;
-  const bool o1 = f1 & 1, o2 = f2 & 1;
-  Cx<T> v;
-  const Cx<T> c00 = fetch<T, T>(c, gc.nm, gc.n, gc.m, 0, J1, J2, p);
-  if (!o1 && !o2) {
-    v = c00;
-  } else if (o1 && !o2) {
-    v = (T)0.5 * (c00 + fetch<T, T>(c, gc.nm, gc.n, gc.m, 0, J1 + 1, J2, p));
-  } else if (!o1 && o2) {
-    v = (T)0.5 * (c00 + fetch<T, T>(c, gc.nm, gc.n, gc.m, 0, J1, J2 + 1, p));
-  } else {
-    v = (T)0.25 * (c00 + fetch<T, T>(c, gc.nm, gc.n, gc.m, 0, J1 + 1, J2, p) +
-                   fetch<T, T>(c, gc.nm, gc.n, gc.m, 0, J1, J2 + 1, p) +
-                   fetch<T, T>(c, gc.nm, gc.n, gc.m, 0, J1 + 1, J2 + 1, p));
-  }
+  const Cx<T> v = nodal_prolong_at<T>(colp(cv, sj, gc.nm), gc, gf, d, p);
   T* o = colp(fv, sj, gf.nm);
   o[d] += v.re;
   o[gf.nm + d] += v.im;

@@ -35,6 +35,7 @@ class BlOpts(ctypes.Structure):
                 ("levels", c_int32), ("coarsest_min", c_int32), ("nu_pre", c_int32),
                 ("nu_post", c_int32), ("nodal_cycles", c_int32), ("variant", c_int32),
                 ("precision", c_int32), ("extrap_depth", c_int32), ("autotune", c_int32),
+                ("coarse_fuse", c_int32), ("reserved1", c_int32),
                 ("tol", c_double), ("mu", c_double), ("zero_rel", c_double)]
 
 
@@ -43,7 +44,8 @@ class BlInfo(ctypes.Structure):
                 ("levels", c_int32), ("precision", c_int32), ("level_n", c_int32 * 16),
                 ("level_m", c_int32 * 16), ("mu", c_double), ("device_bytes", c_size_t),
                 ("kernel_launches", c_int64), ("edge_smooth_shape", c_int32 * 3),
-                ("nodal_smooth_shape", c_int32 * 3), ("rr_tile", c_int32), ("reserved", c_int32),
+                ("nodal_smooth_shape", c_int32 * 3), ("rr_tile", c_int32),
+                ("fused_edge_level", c_int32), ("fused_nodal_level", c_int32), ("reserved", c_int32),
                 ("autotune_ms", c_double)]
 
 

@@ -208,3 +208,37 @@ def test_rayleigh_ritz_products(case):
         G, Hm = s.rr_products(to_device_block(S))
         _close(G, S.conj().T @ (d.M @ S), 1e-13)
         _close(Hm, S.conj().T @ (d.A @ S), 1e-13)
+
+
+@pytest.mark.parametrize("n,levels", [(20, 0), (64, 0), (128, 5)])
+@pytest.mark.parametrize("fp32", [False, True])
+def test_fused_coarse_cycles_equal_per_level_cycles(n, levels, fp32):
+    """The coarse levels of a V-cycle run fused in one workgroup per column when they fit
+    LDS; the fused cycle performs the per-level cycle's operations in the same order, so
+    both give the same bits, for the edge and the nodal cycle and through a whole solve."""
+    import torch  # noqa: F401
+    from paper_2304_00337_amd import Solver
+    rng = np.random.default_rng(n)
+    m = n if n != 20 else 12
+    eps = rng.uniform(1.0, 12.0, n * m)
+    k = (0.7, -1.3)
+    kw = dict(nev=4, nthrow=2, mu=MU, levels=levels, coarsest_min=3, max_iter=40,
+              precision="mixed" if fp32 else "fp64")
+    s0 = Solver(n, m, 1.0, 1.0, eps, coarse_fuse=0, **kw)
+    s1 = Solver(n, m, 1.0, 1.0, eps, coarse_fuse=1, **kw)
+    i0, i1 = s0.info(), s1.info()
+    assert i0["fused_edge_level"] == -1 and i0["fused_nodal_level"] == -1
+    assert i1["fused_edge_level"] >= 0 and i1["fused_nodal_level"] >= 0
+    assert i1["sizes"] == i0["sizes"]
+    for s in (s0, s1):
+        s.set_k(*k)
+    B = _rand(rng, 2 * n * m, 5)
+    Bn = _rand(rng, n * m, 5)
+    for op, X, rows in (("EDGE_VCYCLE", B, 2 * n * m), ("NODAL_VCYCLE", Bn, n * m)):
+        a = _gpu(s0, op, X, out_rows=rows, fp32=fp32)
+        b = _gpu(s1, op, X, out_rows=rows, fp32=fp32)
+        assert np.array_equal(a, b), op
+    E0 = synth.start_block(2 * n * m, 6, 1)
+    r0 = s0.solve_k(*k, start=E0, allow_noconv=True)
+    r1 = s1.solve_k(*k, start=E0, allow_noconv=True)
+    assert np.array_equal(r0["evals"], r1["evals"]) and r0["iterations"] == r1["iterations"]
