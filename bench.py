@@ -174,7 +174,7 @@ def recorded_traffic(avg_cols):
         with open(os.path.join(ROOT, "profiles", "edge_gs_traffic.json")) as f:
             rec = json.load(f)
         src = "".join(open(os.path.join(ROOT, "paper_2304_00337_amd", "csrc", name)).read()
-                      for name in ("stencils.hip", "stencil_common.h"))
+                      for name in ("stencils.hip", "stencil_common.h", "stencil_ops.h"))
     except (OSError, ValueError):
         return None
     if hashlib.sha256(src.encode()).hexdigest() != rec.get("source_sha256"):

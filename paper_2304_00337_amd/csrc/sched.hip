@@ -1,10 +1,16 @@
 // Batched solves and the serving loop of bloch.h (bl_batch_solve, bl_server_*).
 //
-// Problems are grouped by shape (grid, block width p); each group runs on an engine whose
-// slots share every kernel launch of a round.  Engines live on streams of their own, so
-// the rounds of different shapes overlap on the device, and are created under an HBM
-// budget: admission takes a queued problem when an engine of its shape has a free slot, or
-// when a new engine fits the budget (idle engines of other shapes are released for it).
+// Problems are grouped by shape (grid, block width p); each group runs on engines whose
+// slots share every kernel launch of a round.  Engines live on streams of their own and
+// advance independently (an engine's next round is queued as soon as its previous one has
+// drained), so the rounds of different engines overlap on the device: while one engine
+// runs its latency-bound steps (the small Ritz problem, reductions, host decisions) the
+// others fill the compute units.  A shape whose single problem already fills the device
+// with its finest-level launches is therefore spread over up to kStreams engines rather
+// than packed into one; small shapes are packed (their launches need the slots to fill the
+// device).  Engines are created under an HBM budget: admission takes a queued problem when
+// an engine of its shape has a free slot, or when a new engine fits the budget (idle
+// engines of other shapes are released for it).
 // Slots that finish a problem take the next queued one of their shape at the next round
 // (continuous batching); a problem's eigenvector history stays on the device across its
 // Bloch parameters.
@@ -44,7 +50,15 @@ struct Eng {
   Key key{};
   hipStream_t st = nullptr;
   size_t bytes = 0;
+  bool pending = false;   // a round has been issued and not yet finished
 };
+
+// Engines of one shape that run side by side on streams of their own; the device's default
+// of four hardware queues per process leaves one for the caller's stream.
+constexpr int kStreams = 3;
+// Finest-level unknowns x block width above which one problem fills the device (the
+// finest smoother pass then has >= 1000 workgroups for that problem alone).
+constexpr int64_t kFillWork = (int64_t)1 << 20;
 
 class Scheduler {
  public:
@@ -54,7 +68,7 @@ class Scheduler {
   }
 
   void enqueue(Job* j) { queue_.push_back(j); }
-  bool idle() const { return queue_.empty() && busy_engines() == 0 && pending_retired() == 0; }
+  bool idle() const { return queue_.empty() && busy_engines() == 0 && pending_retired() == 0 && !in_flight(); }
   size_t queued() const { return queue_.size(); }
   size_t engines() const { return engines_.size(); }
   size_t bytes_used() const { return used_; }
@@ -115,20 +129,37 @@ class Scheduler {
   int engine_count() const { return (int)engines_.size(); }
   const bl_solver* engine_at(int i) const { return engines_[i].e; }
 
-  // One round over every busy engine: issue all, then finish all.
+  // Advance the engines: every busy engine without a round in flight issues one; then wait
+  // until at least one engine's stream has drained and finish the rounds of all that have
+  // (finishing queues that engine's preconditioner and Ritz step, and the next call issues
+  // its next round right behind them).  Engines therefore run out of step with each other.
   int step() {
     int rc;
-    std::vector<Eng*> act;
+    bool any = false;
+    for (auto& g : engines_) {
+      if (g.pending || !engine_busy(g.e)) continue;
+      if ((rc = engine_issue(g.e))) return rc;
+      g.pending = any = true;
+    }
+    bool waiting = false;
+    for (auto& g : engines_) waiting = waiting || g.pending;
+    while (waiting) {
+      bool done = false;
+      for (auto& g : engines_) {
+        if (!g.pending) continue;
+        const hipError_t q = hipStreamQuery(g.st);
+        if (q == hipErrorNotReady) continue;
+        g.pending = false;
+        done = true;
+        if ((rc = engine_finish(g.e))) return rc;   // reports a failed stream as a device error
+      }
+      if (done) break;
+      std::this_thread::yield();
+    }
     for (auto& g : engines_)
-      if (engine_busy(g.e)) act.push_back(&g);
-    for (Eng* g : act)
-      if ((rc = engine_issue(g->e))) return rc;
-    for (Eng* g : act)
-      if ((rc = engine_finish(g->e))) return rc;
-    for (auto& g : engines_)
-      if (!engine_busy(g.e) && !g.e->retired.empty())
+      if (!g.pending && !engine_busy(g.e) && !g.e->retired.empty())
         if ((rc = engine_sync_retired(g.e))) return rc;
-    if (!act.empty()) ++rounds_;
+    if (any) ++rounds_;
     return BL_OK;
   }
 
@@ -137,6 +168,11 @@ class Scheduler {
     int b = 0;
     for (auto& g : engines_) b += engine_busy(g.e) > 0;
     return b;
+  }
+  bool in_flight() const {
+    for (auto& g : engines_)
+      if (g.pending) return true;
+    return false;
   }
   int pending_retired() const {
     int r = 0;
@@ -170,9 +206,15 @@ class Scheduler {
       return engine_assign(g.e, sl, &j->task);
     }
     // a new engine: as many slots as the queue holds for this shape, within max_slots and
-    // the budget
-    int want = 0;
+    // the budget; a shape that fills the device with one problem shares the queue out over
+    // the engines still to be created for it (at most kStreams in all)
+    int want = 0, have = 0;
     for (Job* q : queue_) want += q->key == j->key;
+    for (auto& g : engines_) have += g.key == j->key;
+    if ((int64_t)j->key.n * j->key.m * j->key.p >= kFillWork) {
+      const int spread = std::max(1, kStreams - have);
+      want = (want + spread - 1) / spread;
+    }
     want = std::max(1, std::min(want, max_slots_ > 0 ? max_slots_ : kMaxSlots));
     bl_grid gr{j->key.n, j->key.m, j->key.a, j->key.b};
     bl_opts o = engine_opts(j->key);
@@ -185,7 +227,7 @@ class Scheduler {
     if (!fits(1)) {
       // release idle engines, least recently created first
       for (auto it = engines_.begin(); it != engines_.end() && !fits(1);) {
-        if (engine_busy(it->e) == 0 && it->e->retired.empty()) {
+        if (!it->pending && engine_busy(it->e) == 0 && it->e->retired.empty()) {
           release(*it);
           it = engines_.erase(it);
         } else {
