@@ -86,7 +86,9 @@ typedef struct bl_opts {
   int32_t coarse_fuse;  /* 1 = run the coarse levels of every V-cycle (those whose vectors
                            fit one workgroup's LDS) in one launch per column; bit-identical
                            to the per-level launches, 0 = per-level launches (1)           */
-  int32_t reserved1;
+  int32_t tiled_sweeps; /* 1 = each smoothing sweep of a level above the fused ones is one
+                           launch over LDS tiles with halos (all four colours); bit-identical
+                           to one launch per colour, 0 = one launch per colour (1)          */
   double tol;           /* stop when ||A e_i - lambda_i M e_i||_2 / (lambda_i ||M e_i||_2)
                            <= tol for the first nev vectors (1e-8)                         */
   double mu;            /* regularisation of the preconditioned A + mu M (Section 5);
@@ -196,14 +198,18 @@ int bl_set_k(bl_solver* s, double k1, double k2);
 int bl_apply(bl_solver* s, int32_t op, int32_t level, int32_t prec, int32_t ncols,
              const void* x, const void* y, void* out);
 
-/* Measurement: with timing enabled, every launch of the finest-level edge smoother (one
- * colour pass of the node-patch block Gauss-Seidel, the V-cycle's dominant kernel) is
- * bracketed by HIP events on the handle's stream; bl_get_timing returns the summed
- * duration in ms, the number of timed launches and the summed column count of those
- * launches since timing was (re)enabled.  Enabling allocates 4096 events (BL_EHIP on
- * failure); at most 2048 launches are timed between two residual evaluations. */
+/* Measurement: with timing enabled, every launch of the finest-level edge smoother (a tiled
+ * sweep of all four colours, or one colour pass with tiled_sweeps = 0: the V-cycle's
+ * dominant kernel) is bracketed by HIP events on the handle's stream; bl_get_timing returns
+ * the summed duration in ms, the number of timed launches, the summed column count of those
+ * launches and their summed algorithmic HBM bytes (per column: a sweep reads the right-hand
+ * side and, unless it starts from zero, the iterate, and writes the iterate; a colour pass
+ * reads the iterate and half the right-hand side and writes half the iterate; per slot the
+ * cell coefficients and the patch inverses once) since timing was (re)enabled.  Enabling
+ * allocates 4096 events (BL_EHIP on failure); at most 2048 launches are timed between two
+ * residual evaluations. */
 int bl_set_timing(bl_solver* s, int32_t enable);
-int bl_get_timing(const bl_solver* s, double* total_ms, int64_t* launches, int64_t* columns);
+int bl_get_timing(const bl_solver* s, double* total_ms, int64_t* launches, int64_t* columns, double* alg_bytes);
 
 /* Dense FP64 helpers of the Ritz step (Section 4), exposed for tests.
  * bl_gram: out (host q x r, row-major complex interleaved re,im) = X^* W for device
@@ -273,7 +279,8 @@ int bl_batch_engine_info(const bl_batch* b, int32_t index, bl_info* out);
 /* Finest-level smoother timing (as bl_set_timing / bl_get_timing) summed over every engine
  * of the context, including engines released since timing was enabled. */
 int bl_batch_set_timing(bl_batch* b, int32_t enable);
-int bl_batch_get_timing(const bl_batch* b, double* total_ms, int64_t* launches, int64_t* columns);
+int bl_batch_get_timing(const bl_batch* b, double* total_ms, int64_t* launches, int64_t* columns,
+                        double* alg_bytes);
 
 /* ---- Serving: asynchronous requests with continuous batching -----------------------------
  * A server owns a worker thread that admits requests by device-memory footprint (engines of

@@ -168,10 +168,10 @@ class Batch:
         check(self.lib.bl_batch_set_timing(self.h, 1 if enable else 0), "bl_batch_set_timing")
 
     def timing(self) -> dict:
-        ms, cnt, cols = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64()
-        check(self.lib.bl_batch_get_timing(self.h, ctypes.byref(ms), ctypes.byref(cnt), ctypes.byref(cols)),
-              "bl_batch_get_timing")
-        return {"total_ms": ms.value, "launches": cnt.value, "columns": cols.value}
+        ms, cnt, cols, nb = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
+        check(self.lib.bl_batch_get_timing(self.h, ctypes.byref(ms), ctypes.byref(cnt), ctypes.byref(cols),
+                                           ctypes.byref(nb)), "bl_batch_get_timing")
+        return {"total_ms": ms.value, "launches": cnt.value, "columns": cols.value, "alg_bytes": nb.value}
 
     def close(self):
         if getattr(self, "h", None):
@@ -394,12 +394,10 @@ class Solver:
         check(self.lib.bl_set_timing(self.h, 1 if enable else 0), "bl_set_timing")
 
     def timing(self) -> dict:
-        ms = ctypes.c_double()
-        cnt = ctypes.c_int64()
-        cols = ctypes.c_int64()
-        check(self.lib.bl_get_timing(self.h, ctypes.byref(ms), ctypes.byref(cnt), ctypes.byref(cols)),
-              "bl_get_timing")
-        return {"total_ms": ms.value, "launches": cnt.value, "columns": cols.value}
+        ms, cnt, cols, nb = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
+        check(self.lib.bl_get_timing(self.h, ctypes.byref(ms), ctypes.byref(cnt), ctypes.byref(cols),
+                                     ctypes.byref(nb)), "bl_get_timing")
+        return {"total_ms": ms.value, "launches": cnt.value, "columns": cols.value, "alg_bytes": nb.value}
 
     # -- operator level ----------------------------------------------------------------------
     def set_k(self, k1, k2):

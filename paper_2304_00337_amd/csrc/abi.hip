@@ -58,6 +58,7 @@ void bl_default_opts(bl_opts* o, int32_t nev) {
   o->zero_rel = 1e-2;
   o->autotune = 1;
   o->coarse_fuse = 1;
+  o->tiled_sweeps = 1;
 }
 
 const char* bl_strerror(int code) {
@@ -181,11 +182,12 @@ int bl_set_timing(bl_solver* s, int32_t enable) {
   return engine_set_timing(s, enable != 0);
 }
 
-int bl_get_timing(const bl_solver* s, double* total_ms, int64_t* launches, int64_t* columns) {
-  if (!s || !total_ms || !launches || !columns) return set_error(BL_EINVAL, "NULL argument%s");
+int bl_get_timing(const bl_solver* s, double* total_ms, int64_t* launches, int64_t* columns, double* alg_bytes) {
+  if (!s || !total_ms || !launches || !columns || !alg_bytes) return set_error(BL_EINVAL, "NULL argument%s");
   *total_ms = s->timed_ms;
   *launches = s->timed_count;
   *columns = s->timed_cols;
+  *alg_bytes = s->timed_bytes;
   return BL_OK;
 }
 

@@ -160,6 +160,7 @@ struct bl_solver {
   double timed_ms = 0.0;
   int64_t timed_count = 0;
   int64_t timed_cols = 0;
+  double timed_bytes = 0.0;   // algorithmic HBM bytes of the timed launches
   bool debug = false;
   // first fused coarse level of the edge / nodal V-cycles per precision (-1: none)
   int fuse_edge[2] = {-1, -1};

@@ -82,6 +82,17 @@ template <typename T>
 void edge_gs(View<T> x, View<const T> b, const double* kappa64, const float* kappa32,
              const double* sinv64, const float* sinv32, const Geo& g, const Phase* ph,
              const double* mu, const PatchT& T4, int colour, const SmoothShape& sh, const Launch& L);
+// One whole smoothing sweep (four colours; reverse colour order when backward) as one launch
+// over LDS tiles with halos, bit-identical to the four colour launches.  Reads the iterate
+// from xin and writes it to xout, which must be different buffers; zero_start: the iterate is
+// zero on entry (xin is then not read).  sweep.hip.
+template <typename T>
+void edge_sweep(View<const T> xin, View<T> xout, View<const T> b, const double* kappa64, const float* kappa32,
+                const double* sinv64, const float* sinv32, const Geo& g, const Phase* ph, const double* mu,
+                const PatchT& T4, bool backward, bool zero_start, const Launch& L);
+template <typename T>
+void nodal_sweep(View<const T> xin, View<T> xout, View<const T> b, const Geo& g, const Phase* ph,
+                 const NodalStencil& c, bool backward, bool zero_start, const Launch& L);
 void patch_setup(const double* kappa, const Geo& g, const double* q, const double* mu, double* sinv64,
                  float* sinv32, int nslots, hipStream_t st);
 void coarsen_kappa(const double* kf, const Geo& gf, double* kc, int nslots, hipStream_t st);
@@ -93,6 +104,10 @@ void edge_restrict(View<const T> rf, const Geo& gf, View<T> bc, const Geo& gc, c
 template <typename T>
 void edge_prolong_add(View<const T> xc, const Geo& gc, View<T> xf, const Geo& gf,
                       const Phase* ph, const Launch& L);
+// out = base + Pr xc (base may be out itself)
+template <typename T>
+void edge_prolong_to(View<const T> xc, const Geo& gc, View<const T> base, View<T> out, const Geo& gf,
+                     const Phase* ph, const Launch& L);
 
 template <typename T>
 void nodal_apply(View<const T> x, View<const T> b, View<T> out, const Geo& g, const Phase* ph,
@@ -106,6 +121,9 @@ void nodal_restrict(View<const T> rf, const Geo& gf, View<T> bc, const Geo& gc, 
 template <typename T>
 void nodal_prolong_add(View<const T> xc, const Geo& gc, View<T> xf, const Geo& gf,
                        const Phase* ph, const Launch& L);
+template <typename T>
+void nodal_prolong_to(View<const T> xc, const Geo& gc, View<const T> base, View<T> out, const Geo& gf,
+                      const Phase* ph, const Launch& L);
 template <typename TI, typename TO>
 void lhm(View<const TI> u, View<TO> out, const Geo& g, const Phase* ph, const Launch& L);
 template <typename TI, typename TP, typename TO>

@@ -109,20 +109,23 @@ class Scheduler {
     timing_ = on;
     t_ms_ = 0.0;
     t_launches_ = t_cols_ = 0;
+    t_bytes_ = 0.0;
     for (auto& g : engines_) {
       int rc = engine_set_timing(g.e, on);
       if (rc) return rc;
     }
     return BL_OK;
   }
-  void timing(double* ms, int64_t* launches, int64_t* cols) const {
+  void timing(double* ms, int64_t* launches, int64_t* cols, double* bytes) const {
     *ms = t_ms_;
     *launches = t_launches_;
     *cols = t_cols_;
+    *bytes = t_bytes_;
     for (auto& g : engines_) {
       *ms += g.e->timed_ms;
       *launches += g.e->timed_count;
       *cols += g.e->timed_cols;
+      *bytes += g.e->timed_bytes;
     }
   }
 
@@ -185,6 +188,7 @@ class Scheduler {
     t_ms_ += g.e->timed_ms;
     t_launches_ += g.e->timed_count;
     t_cols_ += g.e->timed_cols;
+    t_bytes_ += g.e->timed_bytes;
     engine_destroy(g.e);
     if (g.st) (void)hipStreamDestroy(g.st);
     used_ -= std::min(used_, g.bytes);
@@ -269,6 +273,7 @@ class Scheduler {
   bool timing_ = false;
   double t_ms_ = 0.0;
   int64_t t_launches_ = 0, t_cols_ = 0;
+  double t_bytes_ = 0.0;
 };
 
 int make_job(const bl_opts& common, const bl_grid* grid, const double* eps, int nev, int nthrow,
@@ -473,9 +478,10 @@ int bl_batch_set_timing(bl_batch* b, int32_t enable) {
   return b->sched->set_timing(enable != 0);
 }
 
-int bl_batch_get_timing(const bl_batch* b, double* total_ms, int64_t* launches, int64_t* columns) {
-  if (!b || !total_ms || !launches || !columns) return set_error(BL_EINVAL, "NULL argument%s");
-  b->sched->timing(total_ms, launches, columns);
+int bl_batch_get_timing(const bl_batch* b, double* total_ms, int64_t* launches, int64_t* columns,
+                        double* alg_bytes) {
+  if (!b || !total_ms || !launches || !columns || !alg_bytes) return set_error(BL_EINVAL, "NULL argument%s");
+  b->sched->timing(total_ms, launches, columns, alg_bytes);
   return BL_OK;
 }
 

@@ -120,6 +120,7 @@ int validate_opts(const bl_opts* o) {
   if (o->extrap_depth < 1 || o->extrap_depth > 3) return set_error(BL_EINVAL, "extrap_depth must be 1..3%s");
   if (o->autotune != 0 && o->autotune != 1) return set_error(BL_EINVAL, "autotune must be 0 or 1%s");
   if (o->coarse_fuse != 0 && o->coarse_fuse != 1) return set_error(BL_EINVAL, "coarse_fuse must be 0 or 1%s");
+  if (o->tiled_sweeps != 0 && o->tiled_sweeps != 1) return set_error(BL_EINVAL, "tiled_sweeps must be 0 or 1%s");
   if (!(o->tol > 0)) return set_error(BL_EINVAL, "tol must be positive%s");
   return BL_OK;
 }
@@ -226,12 +227,22 @@ void timing_begin(bl_solver* s, int l) {
   if (s->ev_used + 2 > (int)s->ev_pool.size()) return;
   (void)hipEventRecord(s->ev_pool[s->ev_used], s->st);
 }
-void timing_end(bl_solver* s, int l, int ncols) {
+void timing_end(bl_solver* s, int l, int ncols, double bytes) {
   if (!s->timing || l != 0) return;
   if (s->ev_used + 2 > (int)s->ev_pool.size()) return;
   (void)hipEventRecord(s->ev_pool[s->ev_used + 1], s->st);
   s->ev_used += 2;
   s->timed_cols += ncols;
+  s->timed_bytes += bytes;
+}
+// Algorithmic HBM bytes of one smoother launch over `ncols` columns of `nact` slots: a tiled
+// sweep reads b (and x unless it starts from zero) and writes x once; a colour pass reads x
+// and half of b and writes half of x.  Per slot: the cell coefficients and the patch
+// inverses (6 per node) once per sweep, a quarter of the inverses per colour pass.
+double smooth_bytes(const Geo& g, size_t elem, bool sweep, bool zero_start, int ncols, int nact) {
+  const double vec = 2.0 * (double)g.ne * (double)elem;
+  if (sweep) return ncols * vec * (zero_start ? 2.0 : 3.0) + nact * (double)g.nm * elem * 7.0;
+  return ncols * vec * 2.0 + nact * (double)g.nm * elem * (1.0 + 6.0 / 4.0);
 }
 void timing_collect(bl_solver* s) {
   if (!s->timing) return;
@@ -294,28 +305,68 @@ void vcycle_edge(bl_solver* s, int l, View<const T> b, View<T> x, const Launch& 
     s->launches += 1;
     return;
   }
-  zero_cols<T>(x, lv.g.ne, L);
-  for (int it = 0; it < s->opts.nu_pre; ++it)
+  // Tiled sweeps never update in place: they alternate between x and the level's residual
+  // block r (free outside the residual/restriction step), arranged so that the last sweep
+  // of each smoothing phase writes x; the prolongation then writes x + Pr xc into the first
+  // post-sweep's input.
+  const bool tiled = s->opts.tiled_sweeps != 0;
+  const int ncols = L.nact * L.ncps;
+  const int npre = s->opts.nu_pre, npost = s->opts.nu_post;
+  View<T> r = view(static_cast<T*>(lv.er[pr]), lv.ecap[pr]);
+  int nl_launch = 0;
+  if (!tiled || npre == 0) {
+    zero_cols<T>(x, lv.g.ne, L);
+    nl_launch += 1;
+  }
+  for (int it = 0; it < npre; ++it) {
+    if (tiled) {
+      View<T> src = ((npre - it) % 2 == 0) ? x : r;   // the previous sweep's output
+      View<T> dst = ((npre - 1 - it) % 2 == 0) ? x : r;
+      timing_begin(s, l);
+      edge_sweep<T>(cv(src), dst, b, lv.kappa64, lv.kappa32, lv.sinv64, lv.sinv32, lv.g, s->ph_d, s->mu_d, lv.T4,
+                    false, it == 0, L);
+      timing_end(s, l, ncols, smooth_bytes(lv.g, sizeof(T), true, it == 0, ncols, L.nact));
+      nl_launch += 1;
+      continue;
+    }
     for (int c = 0; c < 4; ++c) {
       timing_begin(s, l);
       edge_gs<T>(x, b, lv.kappa64, lv.kappa32, lv.sinv64, lv.sinv32, lv.g, s->ph_d, s->mu_d, lv.T4, c, s->tune_edge, L);
-      timing_end(s, l, L.nact * L.ncps);
+      timing_end(s, l, ncols, smooth_bytes(lv.g, sizeof(T), false, false, ncols, L.nact));
     }
-  View<T> r = view(static_cast<T*>(lv.er[pr]), lv.ecap[pr]);
+    nl_launch += 4;
+  }
   edge_apply<T, T>(EM_RESID_K, cv(x), b, r, lv.kappa64, lv.kappa32, nullptr, 0, lv.g, s->ph_d, s->mu_d, L, nullptr, nullptr);
   Level& C = s->lv[l + 1];
   View<T> bc = view(static_cast<T*>(C.eb[pr]), C.ecap[pr]);
   View<T> xc = view(static_cast<T*>(C.ex[pr]), C.ecap[pr]);
   edge_restrict<T>(cv(r), lv.g, bc, C.g, s->ph_d, L);
   vcycle_edge<T>(s, l + 1, cv(bc), xc, L);
+  if (tiled && npost > 0) {
+    View<T> cur = (npost % 2 == 1) ? r : x;
+    edge_prolong_to<T>(cv(xc), C.g, cv(x), cur, lv.g, s->ph_d, L);
+    for (int it = 0; it < npost; ++it) {
+      View<T> dst = (cur.p == x.p && cur.off == x.off && cur.cps == x.cps) ? r : x;
+      timing_begin(s, l);
+      edge_sweep<T>(cv(cur), dst, b, lv.kappa64, lv.kappa32, lv.sinv64, lv.sinv32, lv.g, s->ph_d, s->mu_d, lv.T4,
+                    true, false, L);
+      timing_end(s, l, ncols, smooth_bytes(lv.g, sizeof(T), true, false, ncols, L.nact));
+      cur = dst;
+      nl_launch += 1;
+    }
+    s->launches += 3 + nl_launch;
+    return;
+  }
   edge_prolong_add<T>(cv(xc), C.g, x, lv.g, s->ph_d, L);
-  for (int it = 0; it < s->opts.nu_post; ++it)
+  for (int it = 0; it < npost; ++it) {
     for (int c = 3; c >= 0; --c) {
       timing_begin(s, l);
       edge_gs<T>(x, b, lv.kappa64, lv.kappa32, lv.sinv64, lv.sinv32, lv.g, s->ph_d, s->mu_d, lv.T4, c, s->tune_edge, L);
-      timing_end(s, l, L.nact * L.ncps);
+      timing_end(s, l, ncols, smooth_bytes(lv.g, sizeof(T), false, false, ncols, L.nact));
     }
-  s->launches += 4 + 4 * (s->opts.nu_post + s->opts.nu_pre);
+    nl_launch += 4;
+  }
+  s->launches += 3 + nl_launch;
 }
 
 // ---- nodal V-cycle for P = L^* M L ----------------------------------------------------------
@@ -334,20 +385,49 @@ void vcycle_nodal(bl_solver* s, int l, View<const T> b, View<T> x, const Launch&
     s->launches += 1;
     return;
   }
-  zero_cols<T>(x, lv.g.nm, L);
-  for (int it = 0; it < s->opts.nu_pre; ++it)
-    for (int c = 0; c < 4; ++c) nodal_gs<T>(x, b, lv.g, s->ph_d, s->ns, c, s->tune_nodal, L);
+  // tiled sweeps alternate between x and the residual block r, as in the edge cycle
+  const bool tiled = s->opts.tiled_sweeps != 0;
+  const int npre = s->opts.nu_pre, npost = s->opts.nu_post;
   View<T> r = view(static_cast<T*>(lv.nr[pr]), lv.ncap[pr]);
+  int nl_launch = 0;
+  if (!tiled || npre == 0) {
+    zero_cols<T>(x, lv.g.nm, L);
+    nl_launch += 1;
+  }
+  for (int it = 0; it < npre; ++it) {
+    if (tiled) {
+      View<T> src = ((npre - it) % 2 == 0) ? x : r;
+      View<T> dst = ((npre - 1 - it) % 2 == 0) ? x : r;
+      nodal_sweep<T>(cv(src), dst, b, lv.g, s->ph_d, s->ns, false, it == 0, L);
+      nl_launch += 1;
+    } else {
+      for (int c = 0; c < 4; ++c) nodal_gs<T>(x, b, lv.g, s->ph_d, s->ns, c, s->tune_nodal, L);
+      nl_launch += 4;
+    }
+  }
   nodal_apply<T>(cv(x), b, r, lv.g, s->ph_d, s->ns, true, L);
   Level& C = s->lv[l + 1];
   View<T> bc = view(static_cast<T*>(C.nb[pr]), C.ncap[pr]);
   View<T> xc = view(static_cast<T*>(C.nx[pr]), C.ncap[pr]);
   nodal_restrict<T>(cv(r), lv.g, bc, C.g, s->ph_d, L);
   vcycle_nodal<T>(s, l + 1, cv(bc), xc, L);
-  nodal_prolong_add<T>(cv(xc), C.g, x, lv.g, s->ph_d, L);
-  for (int it = 0; it < s->opts.nu_post; ++it)
-    for (int c = 3; c >= 0; --c) nodal_gs<T>(x, b, lv.g, s->ph_d, s->ns, c, s->tune_nodal, L);
-  s->launches += 4 + 4 * (s->opts.nu_pre + s->opts.nu_post);
+  if (tiled && npost > 0) {
+    View<T> cur = (npost % 2 == 1) ? r : x;
+    nodal_prolong_to<T>(cv(xc), C.g, cv(x), cur, lv.g, s->ph_d, L);
+    for (int it = 0; it < npost; ++it) {
+      View<T> dst = (cur.p == x.p && cur.off == x.off && cur.cps == x.cps) ? r : x;
+      nodal_sweep<T>(cv(cur), dst, b, lv.g, s->ph_d, s->ns, true, false, L);
+      cur = dst;
+      nl_launch += 1;
+    }
+  } else {
+    nodal_prolong_add<T>(cv(xc), C.g, x, lv.g, s->ph_d, L);
+    for (int it = 0; it < npost; ++it) {
+      for (int c = 3; c >= 0; --c) nodal_gs<T>(x, b, lv.g, s->ph_d, s->ns, c, s->tune_nodal, L);
+      nl_launch += 4;
+    }
+  }
+  s->launches += 3 + nl_launch;
 }
 
 // phi ~ P^{-1} b by `cycles` V-cycles; b and phi must not be level-0 work blocks of the
@@ -981,6 +1061,7 @@ int engine_set_timing(bl_solver* s, bool enable) {
   s->timed_ms = 0.0;
   s->timed_count = 0;
   s->timed_cols = 0;
+  s->timed_bytes = 0.0;
   s->ev_used = 0;
   return BL_OK;
 }

@@ -40,28 +40,47 @@ __device__ __forceinline__ void edge_AM(const TI* xc, int64_t N, int n, int m, i
   }
 }
 
+// Edge values around a patch node (p1, p2), given in canonical indices, read and updated in
+// Bloch-extended coordinates: get(c, d1, d2) is component c (0 = x-edges, 1 = y-edges) at
+// (p1 + d1, p2 + d2) times the phase of the crossing, add(c, d1, d2, v) adds v (given in
+// extended coordinates) to the stored value.  This accessor reads a whole column in memory;
+// the tiled sweeps have one over an LDS copy of a tile (same operations, same rounding).
+template <typename T>
+struct ColumnEdges {
+  T* xc;
+  int64_t N, nm;
+  int n, m, p1, p2;
+  Ph<T> p;
+  __device__ __forceinline__ Cx<T> get(int c, int d1, int d2) const {
+    return fetch<T, T>(xc, N, n, m, c ? nm : 0, p1 + d1, p2 + d2, p);
+  }
+  __device__ __forceinline__ void add(int c, int d1, int d2, Cx<T> v) const {
+    add_ext<T, T>(xc, N, n, m, c ? nm : 0, p1 + d1, p2 + d2, v, p);
+  }
+};
+
 // Stabilised node-patch update at node (p1, p2) (Section 5): residual of K = A + mu M on the
 // four patch edges, delta = T diag(1/mu, S^{-1}) T^T r, x += delta.  k* are the kappas of the
-// four cells around the node, si the node's 3x3 inverse (s00, s01, s02, s11, s12, s22).
-template <typename T>
-__device__ __forceinline__ void edge_patch_gs(T* xc, const T* bc, int64_t N, int n, int m, int64_t nm,
-                                              int p1, int p2, T kne, T knw, T ksw, T kse, const T* si,
-                                              const PatchT& T4, T s, T mu, T mmx, T mmy,
-                                              const Ph<T>& p) {
+// four cells around the node, si the node's 3x3 inverse (s00, s01, s02, s11, s12, s22), bc the
+// right-hand side column (read in memory), X the accessor of the iterate.
+template <typename T, typename XA>
+__device__ __forceinline__ void patch_update(const XA& X, const T* bc, int64_t N, int n, int m, int64_t nm,
+                                             int p1, int p2, T kne, T knw, T ksw, T kse, const T* si,
+                                             const PatchT& T4, T s, T mu, T mmx, T mmy, const Ph<T>& p) {
   const T two3 = (T)(2.0 / 3.0), one6 = (T)(1.0 / 6.0);
   const T s00 = si[0], s01 = si[1], s02 = si[2], s11 = si[3], s12 = si[4], s22 = si[5];
-  const Cx<T> X00 = fetch<T, T>(xc, N, n, m, 0, p1, p2, p);
-  const Cx<T> X01 = fetch<T, T>(xc, N, n, m, 0, p1, p2 + 1, p);
-  const Cx<T> X0m = fetch<T, T>(xc, N, n, m, 0, p1, p2 - 1, p);
-  const Cx<T> Xm0 = fetch<T, T>(xc, N, n, m, 0, p1 - 1, p2, p);
-  const Cx<T> Xm1 = fetch<T, T>(xc, N, n, m, 0, p1 - 1, p2 + 1, p);
-  const Cx<T> Xmm = fetch<T, T>(xc, N, n, m, 0, p1 - 1, p2 - 1, p);
-  const Cx<T> Y00 = fetch<T, T>(xc, N, n, m, nm, p1, p2, p);
-  const Cx<T> Y10 = fetch<T, T>(xc, N, n, m, nm, p1 + 1, p2, p);
-  const Cx<T> Ym0 = fetch<T, T>(xc, N, n, m, nm, p1 - 1, p2, p);
-  const Cx<T> Y0m = fetch<T, T>(xc, N, n, m, nm, p1, p2 - 1, p);
-  const Cx<T> Y1m = fetch<T, T>(xc, N, n, m, nm, p1 + 1, p2 - 1, p);
-  const Cx<T> Ymm = fetch<T, T>(xc, N, n, m, nm, p1 - 1, p2 - 1, p);
+  const Cx<T> X00 = X.get(0, 0, 0);
+  const Cx<T> X01 = X.get(0, 0, 1);
+  const Cx<T> X0m = X.get(0, 0, -1);
+  const Cx<T> Xm0 = X.get(0, -1, 0);
+  const Cx<T> Xm1 = X.get(0, -1, 1);
+  const Cx<T> Xmm = X.get(0, -1, -1);
+  const Cx<T> Y00 = X.get(1, 0, 0);
+  const Cx<T> Y10 = X.get(1, 1, 0);
+  const Cx<T> Ym0 = X.get(1, -1, 0);
+  const Cx<T> Y0m = X.get(1, 0, -1);
+  const Cx<T> Y1m = X.get(1, 1, -1);
+  const Cx<T> Ymm = X.get(1, -1, -1);
   const Cx<T> wne = X01 - X00 + Y00 - Y10;
   const Cx<T> wnw = Xm1 - Xm0 + Ym0 - Y00;
   const Cx<T> wsw = Xm0 - Xmm + Ymm - Y0m;
@@ -97,10 +116,20 @@ __device__ __forceinline__ void edge_patch_gs(T* xc, const T* bc, int64_t N, int
     for (int a = 0; a < 4; ++a) acc = acc + ((T)T4.t[l * 4 + a] * z[a]);
     dl[l] = acc;
   }
-  add_ext<T, T>(xc, N, n, m, 0, p1, p2, dl[0], p);
-  add_ext<T, T>(xc, N, n, m, 0, p1 - 1, p2, dl[1], p);
-  add_ext<T, T>(xc, N, n, m, nm, p1, p2, dl[2], p);
-  add_ext<T, T>(xc, N, n, m, nm, p1, p2 - 1, dl[3], p);
+  X.add(0, 0, 0, dl[0]);
+  X.add(0, -1, 0, dl[1]);
+  X.add(1, 0, 0, dl[2]);
+  X.add(1, 0, -1, dl[3]);
+}
+
+// The patch update on a column in memory.
+template <typename T>
+__device__ __forceinline__ void edge_patch_gs(T* xc, const T* bc, int64_t N, int n, int m, int64_t nm,
+                                              int p1, int p2, T kne, T knw, T ksw, T kse, const T* si,
+                                              const PatchT& T4, T s, T mu, T mmx, T mmy,
+                                              const Ph<T>& p) {
+  const ColumnEdges<T> X{xc, N, nm, n, m, p1, p2, p};
+  patch_update<T>(X, bc, N, n, m, nm, p1, p2, kne, knw, ksw, kse, si, T4, s, mu, mmx, mmy, p);
 }
 
 // Coarse edge d of (Pr^* r): the adjoint of the edge embedding (1/2 collinear, 1/4 parallel).
@@ -144,16 +173,31 @@ __device__ __forceinline__ Cx<T> edge_prolong_at(const T* c, const Geo& gc, cons
   return (T)0.25 * (fetch<T, T>(c, Nc, nc, mc, nmc, f1 >> 1, J2, p) + fetch<T, T>(c, Nc, nc, mc, nmc, (f1 >> 1) + 1, J2, p));
 }
 
-// 9-point P = L^* M L at node (p1, p2); the coefficients depend only on h2/h1.
+// Nodal values around node (p1, p2) in Bloch-extended coordinates (as ColumnEdges, one
+// component): get(d1, d2) is the value at (p1 + d1, p2 + d2) times the crossing's phase.
+template <typename T>
+struct ColumnNodes {
+  const T* c;
+  int64_t N;
+  int n, m, p1, p2;
+  Ph<T> p;
+  __device__ __forceinline__ Cx<T> get(int d1, int d2) const { return fetch<T, T>(c, N, n, m, 0, p1 + d1, p2 + d2, p); }
+};
+
+// 9-point P = L^* M L at the accessor's node; the coefficients depend only on h2/h1.
+template <typename T, typename XA>
+__device__ __forceinline__ Cx<T> nodal_stencil_at(const XA& X, const NodalStencil& s) {
+  const Cx<T> u = X.get(0, 0);
+  const Cx<T> ex = X.get(1, 0) + X.get(-1, 0);
+  const Cx<T> ey = X.get(0, 1) + X.get(0, -1);
+  const Cx<T> ed = X.get(1, 1) + X.get(-1, 1) + X.get(1, -1) + X.get(-1, -1);
+  return ((T)s.c0 * u) + ((T)s.cx * ex) + ((T)s.cy * ey) + ((T)s.cd * ed);
+}
+
 template <typename T>
 __device__ __forceinline__ Cx<T> nodal_stencil(const T* c, int64_t N, int n, int m, int p1, int p2,
                                                const NodalStencil& s, const Ph<T>& p) {
-  const Cx<T> u = {c[(int64_t)p2 * n + p1], c[N + (int64_t)p2 * n + p1]};
-  const Cx<T> ex = fetch<T, T>(c, N, n, m, 0, p1 + 1, p2, p) + fetch<T, T>(c, N, n, m, 0, p1 - 1, p2, p);
-  const Cx<T> ey = fetch<T, T>(c, N, n, m, 0, p1, p2 + 1, p) + fetch<T, T>(c, N, n, m, 0, p1, p2 - 1, p);
-  const Cx<T> ed = fetch<T, T>(c, N, n, m, 0, p1 + 1, p2 + 1, p) + fetch<T, T>(c, N, n, m, 0, p1 - 1, p2 + 1, p) +
-                   fetch<T, T>(c, N, n, m, 0, p1 + 1, p2 - 1, p) + fetch<T, T>(c, N, n, m, 0, p1 - 1, p2 - 1, p);
-  return ((T)s.c0 * u) + ((T)s.cx * ex) + ((T)s.cy * ey) + ((T)s.cd * ed);
+  return nodal_stencil_at<T>(ColumnNodes<T>{c, N, n, m, p1, p2, p}, s);
 }
 
 // Coarse node d of the full-weighting restriction (adjoint of bilinear interpolation).

@@ -320,17 +320,18 @@ __global__ __launch_bounds__(256) void k_edge_restrict(View<const T> rv, Geo gf,
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_edge_prolong_add(View<const T> cv, Geo gc, View<T> fv, Geo gf,
-                                                          const Phase* __restrict__ phs,
+__global__ __launch_bounds__(256) void k_edge_prolong_add(View<const T> cv, Geo gc, View<const T> basev, View<T> fv,
+                                                          Geo gf, const Phase* __restrict__ phs,
                                                           const int* __restrict__ slots, int ncps) {
   const SJ sj = slot_col(slots, ncps);
   const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (d >= gf.ne) return;
   const Ph<T> p = cast_phase<T>(phs[sj.slot]);
   const Cx<T> v = edge_prolong_at<T>(colp(cv, sj, gc.ne), gc, gf, d, p);
+  const T* x0 = colp(basev, sj, gf.ne);   // may be the output itself (same element)
   T* o = colp(fv, sj, gf.ne);
-  o[d] += v.re;
-  o[gf.ne + d] += v.im;
+  o[d] = x0[d] + v.re;
+  o[gf.ne + d] = x0[gf.ne + d] + v.im;
 }
 
 template <typename T>
@@ -343,14 +344,21 @@ void edge_restrict(View<const T> rf, const Geo& gf, View<T> bc, const Geo& gc, c
 template <typename T>
 void edge_prolong_add(View<const T> xc, const Geo& gc, View<T> xf, const Geo& gf,
                       const Phase* ph, const Launch& L) {
+  edge_prolong_to<T>(xc, gc, View<const T>{xf.p, xf.cps, xf.off}, xf, gf, ph, L);
+}
+template <typename T>
+void edge_prolong_to(View<const T> xc, const Geo& gc, View<const T> base, View<T> out, const Geo& gf,
+                     const Phase* ph, const Launch& L) {
   dim3 grid((unsigned)((gf.ne + 255) / 256), (unsigned)(L.nact * L.ncps));
   if (grid.y == 0) return;
-  k_edge_prolong_add<T><<<grid, 256, 0, L.st>>>(xc, gc, xf, gf, ph, L.slots, L.ncps);
+  k_edge_prolong_add<T><<<grid, 256, 0, L.st>>>(xc, gc, base, out, gf, ph, L.slots, L.ncps);
 }
 template void edge_restrict<double>(View<const double>, const Geo&, View<double>, const Geo&, const Phase*, const Launch&);
 template void edge_restrict<float>(View<const float>, const Geo&, View<float>, const Geo&, const Phase*, const Launch&);
 template void edge_prolong_add<double>(View<const double>, const Geo&, View<double>, const Geo&, const Phase*, const Launch&);
 template void edge_prolong_add<float>(View<const float>, const Geo&, View<float>, const Geo&, const Phase*, const Launch&);
+template void edge_prolong_to<double>(View<const double>, const Geo&, View<const double>, View<double>, const Geo&, const Phase*, const Launch&);
+template void edge_prolong_to<float>(View<const float>, const Geo&, View<const float>, View<float>, const Geo&, const Phase*, const Launch&);
 
 // ------------------------------------------------------------------------------------------
 // Nodal operators.  P = L^* M L is the 9-point Bloch Q1 Laplacian; its coefficients depend
@@ -451,17 +459,18 @@ __global__ __launch_bounds__(256) void k_nodal_restrict(View<const T> rv, Geo gf
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_nodal_prolong_add(View<const T> cv, Geo gc, View<T> fv, Geo gf,
-                                                           const Phase* __restrict__ phs,
+__global__ __launch_bounds__(256) void k_nodal_prolong_add(View<const T> cv, Geo gc, View<const T> basev, View<T> fv,
+                                                           Geo gf, const Phase* __restrict__ phs,
                                                            const int* __restrict__ slots, int ncps) {
   const SJ sj = slot_col(slots, ncps);
   const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (d >= gf.nm) return;
   const Ph<T> p = cast_phase<T>(phs[sj.slot]);
   const Cx<T> v = nodal_prolong_at<T>(colp(cv, sj, gc.nm), gc, gf, d, p);
+  const T* x0 = colp(basev, sj, gf.nm);   // may be the output itself (same element)
   T* o = colp(fv, sj, gf.nm);
-  o[d] += v.re;
-  o[gf.nm + d] += v.im;
+  o[d] = x0[d] + v.re;
+  o[gf.nm + d] = x0[gf.nm + d] + v.im;
 }
 
 template <typename T>
@@ -474,14 +483,21 @@ void nodal_restrict(View<const T> rf, const Geo& gf, View<T> bc, const Geo& gc, 
 template <typename T>
 void nodal_prolong_add(View<const T> xc, const Geo& gc, View<T> xf, const Geo& gf,
                        const Phase* ph, const Launch& L) {
+  nodal_prolong_to<T>(xc, gc, View<const T>{xf.p, xf.cps, xf.off}, xf, gf, ph, L);
+}
+template <typename T>
+void nodal_prolong_to(View<const T> xc, const Geo& gc, View<const T> base, View<T> out, const Geo& gf,
+                      const Phase* ph, const Launch& L) {
   dim3 grid((unsigned)((gf.nm + 255) / 256), (unsigned)(L.nact * L.ncps));
   if (grid.y == 0) return;
-  k_nodal_prolong_add<T><<<grid, 256, 0, L.st>>>(xc, gc, xf, gf, ph, L.slots, L.ncps);
+  k_nodal_prolong_add<T><<<grid, 256, 0, L.st>>>(xc, gc, base, out, gf, ph, L.slots, L.ncps);
 }
 template void nodal_restrict<double>(View<const double>, const Geo&, View<double>, const Geo&, const Phase*, const Launch&);
 template void nodal_restrict<float>(View<const float>, const Geo&, View<float>, const Geo&, const Phase*, const Launch&);
 template void nodal_prolong_add<double>(View<const double>, const Geo&, View<double>, const Geo&, const Phase*, const Launch&);
 template void nodal_prolong_add<float>(View<const float>, const Geo&, View<float>, const Geo&, const Phase*, const Launch&);
+template void nodal_prolong_to<double>(View<const double>, const Geo&, View<const double>, View<double>, const Geo&, const Phase*, const Launch&);
+template void nodal_prolong_to<float>(View<const float>, const Geo&, View<const float>, View<float>, const Geo&, const Phase*, const Launch&);
 
 // out (nodal) = L^* M u (edge).  (L^* v)(p) = v_x(p1-1,p2) - v_x(p1,p2) + v_y(p1,p2-1) - v_y(p1,p2)
 // in extended coordinates, with v = M u evaluated on the fly.  Arithmetic in FP64 (the

@@ -35,7 +35,7 @@ class BlOpts(ctypes.Structure):
                 ("levels", c_int32), ("coarsest_min", c_int32), ("nu_pre", c_int32),
                 ("nu_post", c_int32), ("nodal_cycles", c_int32), ("variant", c_int32),
                 ("precision", c_int32), ("extrap_depth", c_int32), ("autotune", c_int32),
-                ("coarse_fuse", c_int32), ("reserved1", c_int32),
+                ("coarse_fuse", c_int32), ("tiled_sweeps", c_int32),
                 ("tol", c_double), ("mu", c_double), ("zero_rel", c_double)]
 
 
@@ -87,7 +87,7 @@ EXPORTED = {
     "bl_last_residual_history": (c_int32, [c_void_p, P(c_double), c_int32]),
     "bl_set_k": (c_int32, [c_void_p, c_double, c_double]),
     "bl_set_timing": (c_int32, [c_void_p, c_int32]),
-    "bl_get_timing": (c_int32, [c_void_p, P(c_double), P(c_int64), P(c_int64)]),
+    "bl_get_timing": (c_int32, [c_void_p, P(c_double), P(c_int64), P(c_int64), P(c_double)]),
     "bl_apply": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p, c_void_p,
                            c_void_p]),
     "bl_gram": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_int32, c_int64, P(c_double)]),
@@ -100,7 +100,7 @@ EXPORTED = {
     "bl_batch_destroy": (None, [c_void_p]),
     "bl_batch_engine_info": (c_int32, [c_void_p, c_int32, P(BlInfo)]),
     "bl_batch_set_timing": (c_int32, [c_void_p, c_int32]),
-    "bl_batch_get_timing": (c_int32, [c_void_p, P(c_double), P(c_int64), P(c_int64)]),
+    "bl_batch_get_timing": (c_int32, [c_void_p, P(c_double), P(c_int64), P(c_int64), P(c_double)]),
     "bl_server_create": (c_int32, [P(BlOpts), c_size_t, c_int32, P(c_void_p)]),
     "bl_server_submit": (c_int32, [c_void_p, P(BlRequest), P(ctypes.c_uint64)]),
     "bl_server_poll": (c_int32, [c_void_p, ctypes.c_uint64, P(c_double), P(c_double), P(c_int32),

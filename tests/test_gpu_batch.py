@@ -185,3 +185,4 @@ def test_batch_context_reuses_engines():
         assert np.array_equal(x["evals"], y["evals"]) and np.array_equal(x["evals"], z["evals"])
         assert np.all(x["point_ms"] > 0)
     assert t1["launches"] > 0 and t1["total_ms"] > 0 and t1["columns"] >= t1["launches"]
+    assert t1["alg_bytes"] > 0

@@ -210,35 +210,65 @@ def test_rayleigh_ritz_products(case):
         _close(Hm, S.conj().T @ (d.A @ S), 1e-13)
 
 
-@pytest.mark.parametrize("n,levels", [(20, 0), (64, 0), (128, 5)])
+@pytest.mark.parametrize("n,levels", [(20, 0), (64, 0), (128, 5), (80, 3)])
 @pytest.mark.parametrize("fp32", [False, True])
-def test_fused_coarse_cycles_equal_per_level_cycles(n, levels, fp32):
+def test_fused_and_tiled_cycles_equal_per_level_cycles(n, levels, fp32):
     """The coarse levels of a V-cycle run fused in one workgroup per column when they fit
-    LDS; the fused cycle performs the per-level cycle's operations in the same order, so
-    both give the same bits, for the edge and the nodal cycle and through a whole solve."""
+    LDS, and each smoothing sweep of the other levels runs as one launch over LDS tiles with
+    halos; both perform the per-level, per-colour operations in the same order, so every
+    combination gives the same bits, for the edge and the nodal cycle and through a whole
+    solve (80 x 48: tiles with ragged edges)."""
     import torch  # noqa: F401
     from paper_2304_00337_amd import Solver
     rng = np.random.default_rng(n)
-    m = n if n != 20 else 12
+    m = {20: 12, 80: 48}.get(n, n)
     eps = rng.uniform(1.0, 12.0, n * m)
     k = (0.7, -1.3)
     kw = dict(nev=4, nthrow=2, mu=MU, levels=levels, coarsest_min=3, max_iter=40,
               precision="mixed" if fp32 else "fp64")
-    s0 = Solver(n, m, 1.0, 1.0, eps, coarse_fuse=0, **kw)
-    s1 = Solver(n, m, 1.0, 1.0, eps, coarse_fuse=1, **kw)
-    i0, i1 = s0.info(), s1.info()
-    assert i0["fused_edge_level"] == -1 and i0["fused_nodal_level"] == -1
-    assert i1["fused_edge_level"] >= 0 and i1["fused_nodal_level"] >= 0
-    assert i1["sizes"] == i0["sizes"]
-    for s in (s0, s1):
+    variants = [(0, 0), (1, 0), (0, 1), (1, 1)]
+    sv = [Solver(n, m, 1.0, 1.0, eps, coarse_fuse=f, tiled_sweeps=t, **kw) for f, t in variants]
+    infos = [s.info() for s in sv]
+    assert infos[0]["fused_edge_level"] == -1 and infos[0]["fused_nodal_level"] == -1
+    assert infos[1]["fused_edge_level"] >= 0 and infos[1]["fused_nodal_level"] >= 0
+    assert all(i["sizes"] == infos[0]["sizes"] for i in infos)
+    for s in sv:
         s.set_k(*k)
     B = _rand(rng, 2 * n * m, 5)
     Bn = _rand(rng, n * m, 5)
-    for op, X, rows in (("EDGE_VCYCLE", B, 2 * n * m), ("NODAL_VCYCLE", Bn, n * m)):
-        a = _gpu(s0, op, X, out_rows=rows, fp32=fp32)
-        b = _gpu(s1, op, X, out_rows=rows, fp32=fp32)
-        assert np.array_equal(a, b), op
     E0 = synth.start_block(2 * n * m, 6, 1)
-    r0 = s0.solve_k(*k, start=E0, allow_noconv=True)
-    r1 = s1.solve_k(*k, start=E0, allow_noconv=True)
-    assert np.array_equal(r0["evals"], r1["evals"]) and r0["iterations"] == r1["iterations"]
+    ref = None
+    for s, var in zip(sv, variants):
+        got = [_gpu(s, "EDGE_VCYCLE", B, out_rows=2 * n * m, fp32=fp32),
+               _gpu(s, "NODAL_VCYCLE", Bn, out_rows=n * m, fp32=fp32)]
+        r = s.solve_k(*k, start=E0, allow_noconv=True)
+        if ref is None:
+            ref = (got, r)
+            continue
+        assert np.array_equal(got[0], ref[0][0]), ("edge V-cycle", var)
+        assert np.array_equal(got[1], ref[0][1]), ("nodal V-cycle", var)
+        assert np.array_equal(r["evals"], ref[1]["evals"]) and r["iterations"] == ref[1]["iterations"], var
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+def test_tiled_sweeps_with_many_workgroups(fp32):
+    """A 256 x 256 grid with 24 columns launches more tile workgroups than the device holds
+    at once, so tiles run in several waves: the tiled V-cycles must still equal the
+    per-colour ones bit for bit (the sweeps read and write different buffers)."""
+    import torch  # noqa: F401
+    from paper_2304_00337_amd import Solver
+    n = 256
+    eps = synth.eps_disc_lattice(n, n, 1.0, 1.0, 12.0, 0.3)
+    rng = np.random.default_rng(11)
+    kw = dict(nev=16, nthrow=8, mu=MU, levels=6, precision="mixed" if fp32 else "fp64")
+    B = _rand(rng, 2 * n * n, 24)
+    Bn = _rand(rng, n * n, 24)
+    outs = []
+    for tiled in (0, 1):
+        s = Solver(n, n, 1.0, 1.0, eps, tiled_sweeps=tiled, **kw)
+        s.set_k(0.9, 0.4)
+        outs.append([_gpu(s, "EDGE_VCYCLE", B, out_rows=2 * n * n, fp32=fp32) for _ in range(2)] +
+                    [_gpu(s, "NODAL_VCYCLE", Bn, out_rows=n * n, fp32=fp32) for _ in range(2)])
+        s.close()
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
