@@ -52,12 +52,16 @@ def segments(prob, S, per_segment):
     return out
 
 
-def run_form(prob, precision, S, steps, warmup, per_segment):
+def run_form(prob, precision, S, steps, warmup, per_segment, max_slots=None, engine_streams=0):
+    """Solve the path cut into S pieces (one batch) `steps` times after `warmup` untimed
+    runs; engine_streams = 0 keeps the library's default (engines of one shape side by side
+    on three streams), 1 runs the pieces one engine at a time."""
     import torch
     from paper_2304_00337_amd import Batch
     probs = segments(prob, S, per_segment)
     recs = []
-    with Batch(max_slots=len(probs), precision=precision, levels=prob.levels, tol=prob.tol, max_iter=300) as b:
+    with Batch(max_slots=max_slots or len(probs), precision=precision, levels=prob.levels, tol=prob.tol,
+               max_iter=300, engine_streams=engine_streams) as b:
         for _ in range(warmup):
             b.run(probs)
         torch.cuda.synchronize()
@@ -174,7 +178,7 @@ def recorded_traffic(avg_cols):
         with open(os.path.join(ROOT, "profiles", "edge_gs_traffic.json")) as f:
             rec = json.load(f)
         src = "".join(open(os.path.join(ROOT, "paper_2304_00337_amd", "csrc", name)).read()
-                      for name in ("stencils.hip", "stencil_common.h", "stencil_ops.h"))
+                      for name in ("stencils.hip", "stencil_common.h", "stencil_ops.h", "sweep.hip"))
     except (OSError, ValueError):
         return None
     if hashlib.sha256(src.encode()).hexdigest() != rec.get("source_sha256"):
@@ -196,6 +200,9 @@ def main():
     ap.add_argument("--headline-only", action="store_true",
                     help="time only the batched mixed form (profiling runs); eigenvalues are then "
                          "checked against its own first step")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="run only the roofline measurement: the three legs of the headline one "
+                         "after another on one single-slot engine (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="start with one plain device copy of 512 MiB, whose counters calibrate "
                          "hardware byte counters")
@@ -217,6 +224,36 @@ def main():
         torch.cuda.synchronize()
         print("# calibration copy: 536870912 bytes read, 536870912 bytes written", file=sys.stderr, flush=True)
         del src, dst
+    # roofline of the dominant kernel, measured in isolation: the headline's legs with the
+    # headline's launch configuration (single-slot engines, 24 columns per launch), run one
+    # after another, so that no other stream's kernels share the device during a launch
+    iso = run_form(prob, "mixed", 0, 1, 0 if args.roofline_only else 1, args.per_segment, max_slots=1,
+                   engine_streams=1)
+    print(f"# roofline leg (legs one engine at a time): {iso['elapsed']:.3f}s, "
+          f"{iso['timing']['launches']} timed launches", file=sys.stderr, flush=True)
+    # roofline of the dominant V-cycle kernel: one tiled sweep (all four colours) of the
+    # finest-level node-patch Gauss-Seidel.  Compulsory bytes per launch, summed by the
+    # library over the timed launches: per column b read, x read (not when the sweep starts
+    # from zero) and x written once; per slot the coefficients kappa (one value per cell) and
+    # the 3x3 patch inverses (6 values per node) once.
+    tm = iso["timing"]
+    avg_cols = tm["columns"] / max(1, tm["launches"])
+    bytes_per_launch = tm["alg_bytes"] / max(1, tm["launches"])
+    avg_ms = tm["total_ms"] / max(1, tm["launches"])
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    tb = recorded_traffic(avg_cols)
+    traffic = None if tb is None else round(tb / 1e6, 1)   # MB per launch
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+            "frac": round(achieved / 8000.0, 4), "traffic": traffic,
+            "kernel": "k_edge_sweep<float> (tiled four-colour node-patch Gauss-Seidel sweep), finest level",
+            "avg_launch_ms": round(avg_ms, 5), "bytes_per_launch": int(bytes_per_launch),
+            "columns_per_launch": round(avg_cols, 2), "launches_timed": tm["launches"],
+            "traffic_unit": "MB per launch (calibrated FETCH_SIZE + WRITE_SIZE)",
+            "measured": "the headline's legs one engine at a time (same launches, no concurrent "
+                        "streams), HIP events on the engine's stream"}
+    if args.roofline_only:
+        print(json.dumps({"roofline": roof}), flush=True)
+        return
     plain = None
     if not args.headline_only:
         plain = run_form(prob, "fp64", 1, args.steps, args.warmup, args.per_segment)
@@ -238,18 +275,10 @@ def main():
     v64 = rate(plain) if plain else float("nan")
     ms_all = np.concatenate([rec["ms"] for rec in head["recs"]])
     ms64 = np.concatenate([rec["ms"] for rec in plain["recs"]]) if plain else np.array([np.nan])
-    # roofline of the dominant V-cycle kernel: one tiled sweep (all four colours) of the
-    # finest-level node-patch Gauss-Seidel.  Compulsory bytes per launch, summed by the
-    # library over the timed launches: per column b read, x read (not when the sweep starts
-    # from zero) and x written once; per slot the coefficients kappa (one value per cell) and
-    # the 3x3 patch inverses (6 values per node) once.
-    tm = head["timing"]
-    avg_cols = tm["columns"] / max(1, tm["launches"])
-    bytes_per_launch = tm["alg_bytes"] / max(1, tm["launches"])
-    avg_ms = tm["total_ms"] / max(1, tm["launches"])
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    tb = recorded_traffic(avg_cols)
-    traffic = None if tb is None else round(tb / 1e6, 1)   # MB per launch
+    # the same kernel inside the timed headline, sharing the device with the other streams
+    tc = head["timing"]
+    avg_ms_c = tc["total_ms"] / max(1, tc["launches"])
+    achieved_c = tc["alg_bytes"] / max(1, tc["launches"]) / (avg_ms_c * 1e-3) / 1e9
     dm = np.abs(head["recs"][0]["evals"] - ref) / ref
     out = {
         "metric": "converged Bloch eigenpairs/s (rel 1e-6), mixed vs FP64 GPU; p50/p99 solve ms",
@@ -280,12 +309,8 @@ def main():
             "iterations_per_k": plain["recs"][0]["iters"].tolist()},
         "speedup_vs_fp64_plain": round(value / max(v64, 1e-12), 3),
         "mixed_vs_fp64_max_rel_eig_diff": float(dm.max()),
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
-                     "frac": round(achieved / 8000.0, 4), "traffic": traffic,
-                     "kernel": "k_edge_sweep<float> (tiled four-colour node-patch Gauss-Seidel sweep), finest level",
-                     "avg_launch_ms": round(avg_ms, 5), "bytes_per_launch": int(bytes_per_launch),
-                     "columns_per_launch": round(avg_cols, 2), "launches_timed": tm["launches"],
-                     "traffic_unit": "MB per launch (calibrated FETCH_SIZE + WRITE_SIZE)"},
+        "roofline": dict(roof, in_headline={"avg_launch_ms": round(avg_ms_c, 5), "achieved": round(achieved_c, 1),
+                                            "note": "durations while two other engine streams share the device"}),
         "launch_shapes": {"headline": head["shapes"], "fp64_plain": plain["shapes"] if plain else None},
     }
     if not args.no_cpu_baseline:

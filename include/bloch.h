@@ -96,6 +96,12 @@ typedef struct bl_opts {
                            cell at k = 0, p = nev + nthrow                                 */
   double zero_rel;      /* extrapolation skips Ritz values below zero_rel times the
                            smallest eigenvalue of the previous parameter (1e-2)            */
+  int32_t engine_streams; /* batches and servers: at most this many engines of one shape
+                             exist at a time, each on a stream of its own (further problems
+                             of the shape wait for a free slot); a shape of which one problem
+                             fills the device is spread over them rather than packed into
+                             one (1..16, default 3)                                        */
+  int32_t reserved2;
 } bl_opts;
 
 /* Read-only facts about a solver handle. */

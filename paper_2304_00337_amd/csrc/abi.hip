@@ -56,6 +56,7 @@ void bl_default_opts(bl_opts* o, int32_t nev) {
   o->tol = 1e-8;
   o->mu = 0.0;
   o->zero_rel = 1e-2;
+  o->engine_streams = 3;
   o->autotune = 1;
   o->coarse_fuse = 1;
   o->tiled_sweeps = 1;

@@ -68,8 +68,8 @@ __device__ void edge_colour(const CoarseCycle& C, int l, int slot, T* x, const T
     const T knw = kap<T>(k64, k32, (int64_t)p2 * n + p1m);
     const T ksw = kap<T>(k64, k32, (int64_t)p2m * n + p1m);
     const T kse = kap<T>(k64, k32, (int64_t)p2m * n + p1);
-    const T* si = pickp<T>(lv.si64, lv.si32) + 6 * ((int64_t)slot * nm + (int64_t)p2 * n + p1);
-    edge_patch_gs<T>(x, b, g.ne, n, m, nm, p1, p2, kne, knw, ksw, kse, si, lv.T4, s, mu, mmx, mmy, p);
+    const T* si = pickp<T>(lv.si64, lv.si32) + kPatchW * ((int64_t)slot * nm + (int64_t)p2 * n + p1);
+    edge_patch_gs<T>(x, b, g.ne, n, m, nm, p1, p2, kne, knw, ksw, kse, si, s, mmx, mmy, p);
   }
 }
 

@@ -29,6 +29,11 @@ struct PatchT {
   double t[16];
 };
 
+// Per node, the smoother keeps the stabilised patch inverse W = T diag(1/mu, S^{-1}) T^T as
+// its 10 upper-triangle entries (w00 w01 w02 w03 w11 w12 w13 w22 w23 w33), formed in FP64
+// from the factors when the coefficients are loaded.
+constexpr int kPatchW = 10;
+
 // 9-point coefficients of P = L^* M L (centre, x-neighbours, y-neighbours, diagonals).
 struct NodalStencil {
   double c0, cx, cy, cd;
@@ -93,8 +98,8 @@ void edge_sweep(View<const T> xin, View<T> xout, View<const T> b, const double* 
 template <typename T>
 void nodal_sweep(View<const T> xin, View<T> xout, View<const T> b, const Geo& g, const Phase* ph,
                  const NodalStencil& c, bool backward, bool zero_start, const Launch& L);
-void patch_setup(const double* kappa, const Geo& g, const double* q, const double* mu, double* sinv64,
-                 float* sinv32, int nslots, hipStream_t st);
+void patch_setup(const double* kappa, const Geo& g, const double* q, const PatchT& T4, const double* mu,
+                 double* sinv64, float* sinv32, int nslots, hipStream_t st);
 void coarsen_kappa(const double* kf, const Geo& gf, double* kc, int nslots, hipStream_t st);
 void to_float(const double* in, float* out, int64_t count, hipStream_t st);
 

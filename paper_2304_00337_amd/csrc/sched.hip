@@ -6,7 +6,7 @@
 // drained), so the rounds of different engines overlap on the device: while one engine
 // runs its latency-bound steps (the small Ritz problem, reductions, host decisions) the
 // others fill the compute units.  A shape whose single problem already fills the device
-// with its finest-level launches is therefore spread over up to kStreams engines rather
+// with its finest-level launches is therefore spread over up to engine_streams engines rather
 // than packed into one; small shapes are packed (their launches need the slots to fill the
 // device).  Engines are created under an HBM budget: admission takes a queued problem when
 // an engine of its shape has a free slot, or when a new engine fits the budget (idle
@@ -53,9 +53,6 @@ struct Eng {
   bool pending = false;   // a round has been issued and not yet finished
 };
 
-// Engines of one shape that run side by side on streams of their own; the device's default
-// of four hardware queues per process leaves one for the caller's stream.
-constexpr int kStreams = 3;
 // Finest-level unknowns x block width above which one problem fills the device (the
 // finest smoother pass then has >= 1000 workgroups for that problem alone).
 constexpr int64_t kFillWork = (int64_t)1 << 20;
@@ -210,13 +207,16 @@ class Scheduler {
       return engine_assign(g.e, sl, &j->task);
     }
     // a new engine: as many slots as the queue holds for this shape, within max_slots and
-    // the budget; a shape that fills the device with one problem shares the queue out over
-    // the engines still to be created for it (at most kStreams in all)
+    // the budget.  At most opts.engine_streams engines per shape (the default of 3 leaves one
+    // of the device's four hardware queues per process to the caller); beyond that the job
+    // waits for a slot.  A shape that fills the device with one problem shares the queue out
+    // over the engines still to be created for it.
     int want = 0, have = 0;
     for (Job* q : queue_) want += q->key == j->key;
     for (auto& g : engines_) have += g.key == j->key;
+    if (have >= opts_.engine_streams) return BL_EAGAIN;
     if ((int64_t)j->key.n * j->key.m * j->key.p >= kFillWork) {
-      const int spread = std::max(1, kStreams - have);
+      const int spread = std::max(1, opts_.engine_streams - have);
       want = (want + spread - 1) / spread;
     }
     want = std::max(1, std::min(want, max_slots_ > 0 ? max_slots_ : kMaxSlots));

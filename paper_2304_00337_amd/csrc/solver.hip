@@ -107,6 +107,7 @@ void fill_defaults(bl_opts* o) {
   if (o->extrap_depth <= 0) o->extrap_depth = 3;
   if (!(o->tol > 0)) o->tol = 1e-8;
   if (!(o->zero_rel > 0)) o->zero_rel = 1e-2;
+  if (o->engine_streams == 0) o->engine_streams = 3;
 }
 
 int validate_opts(const bl_opts* o) {
@@ -121,6 +122,7 @@ int validate_opts(const bl_opts* o) {
   if (o->autotune != 0 && o->autotune != 1) return set_error(BL_EINVAL, "autotune must be 0 or 1%s");
   if (o->coarse_fuse != 0 && o->coarse_fuse != 1) return set_error(BL_EINVAL, "coarse_fuse must be 0 or 1%s");
   if (o->tiled_sweeps != 0 && o->tiled_sweeps != 1) return set_error(BL_EINVAL, "tiled_sweeps must be 0 or 1%s");
+  if (o->engine_streams < 1 || o->engine_streams > 16) return set_error(BL_EINVAL, "engine_streams must be 1..16%s");
   if (!(o->tol > 0)) return set_error(BL_EINVAL, "tol must be positive%s");
   return BL_OK;
 }
@@ -616,7 +618,8 @@ int load_eps(bl_solver* s, int sl, const std::vector<double>& kappa, double eps_
     else coarsen_kappa(s->lv[l - 1].kappa64 + (int64_t)sl * s->lv[l - 1].g.nm, s->lv[l - 1].g, k64, 1, s->st);
     to_float(k64, L.kappa32 + (int64_t)sl * L.g.nm, L.g.nm, s->st);
     if (l + 1 < s->lv.size())
-      patch_setup(k64, L.g, L.Q, s->mu_d + sl, L.sinv64 + (int64_t)sl * L.g.nm * 6, L.sinv32 + (int64_t)sl * L.g.nm * 6, 1, s->st);
+      patch_setup(k64, L.g, L.Q, L.T4, s->mu_d + sl, L.sinv64 + (int64_t)sl * L.g.nm * kPatchW,
+                  L.sinv32 + (int64_t)sl * L.g.nm * kPatchW, 1, s->st);
     s->launches += 3;
   }
   // the host sources (the task's kappa, mu_h[sl]) stay unchanged until the copies have run:
@@ -773,8 +776,8 @@ int engine_create(const bl_grid* grid, const bl_opts* opts, int nslots, hipStrea
       const double dd[4] = {dx, dx, dy, dy};
       for (int i = 0; i < 4; ++i)
         for (int j = 0; j < 4; ++j) L.T4.t[i * 4 + j] = L.Q[i * 4 + j] / std::sqrt(dd[i]);
-      if ((rc = dalloc_t(s, &L.sinv64, L.g.nm * 6 * S))) return fail(rc);
-      if ((rc = dalloc_t(s, &L.sinv32, L.g.nm * 6 * S))) return fail(rc);
+      if ((rc = dalloc_t(s, &L.sinv64, L.g.nm * kPatchW * S))) return fail(rc);
+      if ((rc = dalloc_t(s, &L.sinv32, L.g.nm * kPatchW * S))) return fail(rc);
     }
   }
   const Geo& g0 = s->lv[0].g;
@@ -823,8 +826,8 @@ int engine_create(const bl_grid* grid, const bl_opts* opts, int nslots, hipStrea
     for (auto& L : s->lv) {
       fill_zero<double>(L.kappa64, L.g.nm * S, s->st);
       fill_zero<float>(L.kappa32, L.g.nm * S, s->st);
-      if (L.sinv64) fill_zero<double>(L.sinv64, L.g.nm * 6 * S, s->st);
-      if (L.sinv32) fill_zero<float>(L.sinv32, L.g.nm * 6 * S, s->st);
+      if (L.sinv64) fill_zero<double>(L.sinv64, L.g.nm * kPatchW * S, s->st);
+      if (L.sinv32) fill_zero<float>(L.sinv32, L.g.nm * kPatchW * S, s->st);
     }
   }
   if (eps) {

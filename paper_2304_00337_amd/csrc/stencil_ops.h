@@ -45,9 +45,9 @@ __device__ __forceinline__ void edge_AM(const TI* xc, int64_t N, int n, int m, i
 // (p1 + d1, p2 + d2) times the phase of the crossing, add(c, d1, d2, v) adds v (given in
 // extended coordinates) to the stored value.  This accessor reads a whole column in memory;
 // the tiled sweeps have one over an LDS copy of a tile (same operations, same rounding).
-template <typename T>
+template <typename T, typename TS = T>
 struct ColumnEdges {
-  T* xc;
+  TS* xc;
   int64_t N, nm;
   int n, m, p1, p2;
   Ph<T> p;
@@ -59,16 +59,42 @@ struct ColumnEdges {
   }
 };
 
-// Stabilised node-patch update at node (p1, p2) (Section 5): residual of K = A + mu M on the
-// four patch edges, delta = T diag(1/mu, S^{-1}) T^T r, x += delta.  k* are the kappas of the
-// four cells around the node, si the node's 3x3 inverse (s00, s01, s02, s11, s12, s22), bc the
-// right-hand side column (read in memory), X the accessor of the iterate.
-template <typename T, typename XA>
-__device__ __forceinline__ void patch_update(const XA& X, const T* bc, int64_t N, int n, int m, int64_t nm,
-                                             int p1, int p2, T kne, T knw, T ksw, T kse, const T* si,
-                                             const PatchT& T4, T s, T mu, T mmx, T mmy, const Ph<T>& p) {
+// Explicit fused multiply-adds (contraction is otherwise off), so that every kernel sharing
+// these bodies rounds the same way.
+template <typename T>
+__device__ __forceinline__ T fmat(T a, T b, T c);
+template <>
+__device__ __forceinline__ float fmat<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <>
+__device__ __forceinline__ double fmat<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
+template <typename T>
+__device__ __forceinline__ Cx<T> cfma(T w, Cx<T> r, Cx<T> acc) {
+  return {fmat<T>(w, r.re, acc.re), fmat<T>(w, r.im, acc.im)};
+}
+template <typename T>
+__device__ __forceinline__ Cx<T> cfma(T w, Cx<T> r, T c, Cx<T> u) {   // w r + c u
+  return {fmat<T>(w, r.re, c * u.re), fmat<T>(w, r.im, c * u.im)};
+}
+
+// Residual of K = A + mu M on one patch edge: b - (s (k_a w_a - k_b w_b) + mm (2/3 u0 +
+// 1/6 (u1 + u2))), for the edge's two cells (curls w_a, w_b) and its two parallel neighbours.
+template <typename T>
+__device__ __forceinline__ Cx<T> patch_resid(Cx<T> b, T ka, Cx<T> wa, T kb, Cx<T> wb, T s, T mm, Cx<T> u0, Cx<T> u1,
+                                             Cx<T> u2) {
   const T two3 = (T)(2.0 / 3.0), one6 = (T)(1.0 / 6.0);
-  const T s00 = si[0], s01 = si[1], s02 = si[2], s11 = si[3], s12 = si[4], s22 = si[5];
+  const Cx<T> c = cfma<T>(ka, wa, (T)-1, kb * wb);                 // ka wa - kb wb
+  const Cx<T> mass = cfma<T>(one6, u1 + u2, two3, u0);             // 2/3 u0 + 1/6 (u1 + u2)
+  return b - cfma<T>(s, c, mm, mass);
+}
+
+// Stabilised node-patch update at node (p1, p2) (Section 5): residual r of K = A + mu M on
+// the four patch edges, delta = W r with the node's patch inverse W = T diag(1/mu, S^{-1})
+// T^T (10 upper-triangle entries at w), x += delta.  k* are the kappas of the four cells
+// around the node, X the accessor of the iterate and B that of the right-hand side (both
+// around the patch node).
+template <typename T, typename XA, typename BA>
+__device__ __forceinline__ void patch_update(const XA& X, const BA& B, T kne, T knw, T ksw, T kse, const T* w,
+                                             T s, T mmx, T mmy) {
   const Cx<T> X00 = X.get(0, 0, 0);
   const Cx<T> X01 = X.get(0, 0, 1);
   const Cx<T> X0m = X.get(0, 0, -1);
@@ -85,51 +111,26 @@ __device__ __forceinline__ void patch_update(const XA& X, const T* bc, int64_t N
   const Cx<T> wnw = Xm1 - Xm0 + Ym0 - Y00;
   const Cx<T> wsw = Xm0 - Xmm + Ymm - Y0m;
   const Cx<T> wse = X00 - X0m + Y0m - Y1m;
-  Cx<T> r[4];
-  r[0] = fetch<T, T>(bc, N, n, m, 0, p1, p2, p) -
-         ((s * ((kse * wse) - (kne * wne))) + mmx * ((two3 * X00) + one6 * (X01 + X0m)));
-  r[1] = fetch<T, T>(bc, N, n, m, 0, p1 - 1, p2, p) -
-         ((s * ((ksw * wsw) - (knw * wnw))) + mmx * ((two3 * Xm0) + one6 * (Xm1 + Xmm)));
-  r[2] = fetch<T, T>(bc, N, n, m, nm, p1, p2, p) -
-         ((s * ((kne * wne) - (knw * wnw))) + mmy * ((two3 * Y00) + one6 * (Y10 + Ym0)));
-  r[3] = fetch<T, T>(bc, N, n, m, nm, p1, p2 - 1, p) -
-         ((s * ((kse * wse) - (ksw * wsw))) + mmy * ((two3 * Y0m) + one6 * (Y1m + Ymm)));
-  // y = T^T r
-  Cx<T> y[4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    Cx<T> acc = {0, 0};
-#pragma unroll
-    for (int l = 0; l < 4; ++l) acc = acc + ((T)T4.t[l * 4 + a] * r[l]);
-    y[a] = acc;
-  }
-  Cx<T> z[4];
-  z[0] = ((T)1 / mu) * y[0];
-  z[1] = (s00 * y[1]) + (s01 * y[2]) + (s02 * y[3]);
-  z[2] = (s01 * y[1]) + (s11 * y[2]) + (s12 * y[3]);
-  z[3] = (s02 * y[1]) + (s12 * y[2]) + (s22 * y[3]);
-  Cx<T> dl[4];
-#pragma unroll
-  for (int l = 0; l < 4; ++l) {
-    Cx<T> acc = {0, 0};
-#pragma unroll
-    for (int a = 0; a < 4; ++a) acc = acc + ((T)T4.t[l * 4 + a] * z[a]);
-    dl[l] = acc;
-  }
-  X.add(0, 0, 0, dl[0]);
-  X.add(0, -1, 0, dl[1]);
-  X.add(1, 0, 0, dl[2]);
-  X.add(1, 0, -1, dl[3]);
+  const Cx<T> r0 = patch_resid<T>(B.get(0, 0, 0), kse, wse, kne, wne, s, mmx, X00, X01, X0m);
+  const Cx<T> r1 = patch_resid<T>(B.get(0, -1, 0), ksw, wsw, knw, wnw, s, mmx, Xm0, Xm1, Xmm);
+  const Cx<T> r2 = patch_resid<T>(B.get(1, 0, 0), kne, wne, knw, wnw, s, mmy, Y00, Y10, Ym0);
+  const Cx<T> r3 = patch_resid<T>(B.get(1, 0, -1), kse, wse, ksw, wsw, s, mmy, Y0m, Y1m, Ymm);
+  const T w00 = w[0], w01 = w[1], w02 = w[2], w03 = w[3], w11 = w[4], w12 = w[5], w13 = w[6], w22 = w[7],
+          w23 = w[8], w33 = w[9];
+  X.add(0, 0, 0, cfma<T>(w03, r3, cfma<T>(w02, r2, cfma<T>(w01, r1, w00 * r0))));
+  X.add(0, -1, 0, cfma<T>(w13, r3, cfma<T>(w12, r2, cfma<T>(w11, r1, w01 * r0))));
+  X.add(1, 0, 0, cfma<T>(w23, r3, cfma<T>(w22, r2, cfma<T>(w12, r1, w02 * r0))));
+  X.add(1, 0, -1, cfma<T>(w33, r3, cfma<T>(w23, r2, cfma<T>(w13, r1, w03 * r0))));
 }
 
 // The patch update on a column in memory.
 template <typename T>
-__device__ __forceinline__ void edge_patch_gs(T* xc, const T* bc, int64_t N, int n, int m, int64_t nm,
-                                              int p1, int p2, T kne, T knw, T ksw, T kse, const T* si,
-                                              const PatchT& T4, T s, T mu, T mmx, T mmy,
+__device__ __forceinline__ void edge_patch_gs(T* xc, const T* bc, int64_t N, int n, int m, int64_t nm, int p1,
+                                              int p2, T kne, T knw, T ksw, T kse, const T* w, T s, T mmx, T mmy,
                                               const Ph<T>& p) {
   const ColumnEdges<T> X{xc, N, nm, n, m, p1, p2, p};
-  patch_update<T>(X, bc, N, n, m, nm, p1, p2, kne, knw, ksw, kse, si, T4, s, mu, mmx, mmy, p);
+  const ColumnEdges<T, const T> B{bc, N, nm, n, m, p1, p2, p};
+  patch_update<T>(X, B, kne, knw, ksw, kse, w, s, mmx, mmy);
 }
 
 // Coarse edge d of (Pr^* r): the adjoint of the edge embedding (1/2 collinear, 1/4 parallel).

@@ -179,7 +179,7 @@ __global__ __launch_bounds__(256) void k_edge_gs(View<T> xv, View<const T> bv,
   const T knw = kap<T>(k64, k32, (int64_t)p2 * n + p1m);
   const T ksw = kap<T>(k64, k32, (int64_t)p2m * n + p1m);
   const T kse = kap<T>(k64, k32, (int64_t)p2m * n + p1);
-  const T* si = pick<T>(si64, si32) + 6 * ((int64_t)slot * nm + (int64_t)p2 * n + p1);
+  const T* si = pick<T>(si64, si32) + kPatchW * ((int64_t)slot * nm + (int64_t)p2 * n + p1);
   const T s = (T)g.s, mu = (T)mus[slot];
   const T mmx = mu * (T)g.mx, mmy = mu * (T)g.my;
 #pragma unroll
@@ -187,8 +187,7 @@ __global__ __launch_bounds__(256) void k_edge_gs(View<T> xv, View<const T> bv,
     const int j = j0 + cc;
     if (j >= ncps) break;
     const SJ sj{slot, j};
-    edge_patch_gs<T>(colp(xv, sj, N), colp(bv, sj, N), N, n, m, nm, p1, p2, kne, knw, ksw, kse, si, T4, s,
-                     mu, mmx, mmy, p);
+    edge_patch_gs<T>(colp(xv, sj, N), colp(bv, sj, N), N, n, m, nm, p1, p2, kne, knw, ksw, kse, si, s, mmx, mmy, p);
   }
 }
 
@@ -217,8 +216,9 @@ template void edge_gs<float>(View<float>, View<const float>, const double*, cons
 struct Q16 {
   double q[16];
 };
-__global__ void k_patch_setup(const double* __restrict__ kappa, Geo g, Q16 Q, const double* __restrict__ mus,
-                              double* __restrict__ s64, float* __restrict__ s32, int nslots) {
+__global__ void k_patch_setup(const double* __restrict__ kappa, Geo g, Q16 Q, PatchT T4,
+                              const double* __restrict__ mus, double* __restrict__ s64, float* __restrict__ s32,
+                              int nslots) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= g.nm * nslots) return;
   const int64_t slot = gid / g.nm, node = gid % g.nm;
@@ -257,19 +257,26 @@ __global__ void k_patch_setup(const double* __restrict__ kappa, Geo g, Q16 Q, co
   const double i11 = (S[0][0] * S[2][2] - S[0][2] * S[2][0]) * id;
   const double i12 = (S[0][2] * S[1][0] - S[0][0] * S[1][2]) * id;
   const double i22 = (S[0][0] * S[1][1] - S[0][1] * S[1][0]) * id;
-  const double out[6] = {i00, i01, i02, i11, i12, i22};
-  for (int i = 0; i < 6; ++i) {
-    s64[gid * 6 + i] = out[i];
-    s32[gid * 6 + i] = (float)out[i];
-  }
+  // W = T diag(1/mu, S^{-1}) T^T (symmetric), upper triangle row by row
+  const double D[4][4] = {{1.0 / mu, 0, 0, 0}, {0, i00, i01, i02}, {0, i01, i11, i12}, {0, i02, i12, i22}};
+  int o = 0;
+  for (int l = 0; l < 4; ++l)
+    for (int k = l; k < 4; ++k) {
+      double w = 0;
+      for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) w += T4.t[l * 4 + a] * D[a][b] * T4.t[k * 4 + b];
+      s64[gid * kPatchW + o] = w;
+      s32[gid * kPatchW + o] = (float)w;
+      ++o;
+    }
 }
 
-void patch_setup(const double* kappa, const Geo& g, const double* q, const double* mu, double* sinv64,
-                 float* sinv32, int nslots, hipStream_t st) {
+void patch_setup(const double* kappa, const Geo& g, const double* q, const PatchT& T4, const double* mu,
+                 double* sinv64, float* sinv32, int nslots, hipStream_t st) {
   Q16 Q;
   for (int i = 0; i < 16; ++i) Q.q[i] = q[i];
   const int64_t cnt = g.nm * nslots;
-  k_patch_setup<<<(unsigned)((cnt + 255) / 256), 256, 0, st>>>(kappa, g, Q, mu, sinv64, sinv32, nslots);
+  k_patch_setup<<<(unsigned)((cnt + 255) / 256), 256, 0, st>>>(kappa, g, Q, T4, mu, sinv64, sinv32, nslots);
 }
 
 // kappa on the next coarser level: mean over the 2x2 children (Galerkin coarse operator

@@ -10,8 +10,13 @@
 // side, so after four passes the tile itself holds exactly what the per-colour launches
 // produce.  The halo widths are the smallest for which this holds for both colour orders
 // (checked by propagating the set of exact values through the passes).  Patches are
-// computed by the same per-point code as the per-colour kernels, through an accessor that
-// reads the LDS copy with the same Bloch-phase arithmetic, so the results agree bit for bit.
+// computed by the same per-point code as the per-colour kernels, through accessors that
+// read the LDS copy with the same Bloch-phase arithmetic, so the results agree bit for bit.
+//
+// LDS layout: the box is split by node parity into four sub-grids, so that the patches of
+// one colour, which are two nodes apart, sit at consecutive addresses (no bank conflicts)
+// and every neighbour of a patch is at a compile-time offset from it.  Only workgroups whose
+// box crosses the periodic seam run the phase checks of the Bloch extension.
 //
 // The sweep reads the iterate from one buffer and writes it to another: a tile's halo is the
 // neighbours' state before the sweep, which an in-place update could already have replaced.
@@ -44,52 +49,100 @@ __device__ __forceinline__ const double* pick_si<double>(const double* a, const 
 template <>
 __device__ __forceinline__ const float* pick_si<float>(const double*, const float* b) { return b; }
 
-// Phase of an extended index as fetch() applies it: j < 0 one period back, j >= n one ahead.
-template <typename T>
-__device__ __forceinline__ Cx<T> phased(Cx<T> v, int j1, int j2, int n, int m, const Ph<T>& p) {
-  if (j1 >= n) v = cmul(v, p.ar, p.ai);
-  else if (j1 < 0) v = cmul(v, p.ar, -p.ai);
-  if (j2 >= m) v = cmul(v, p.br, p.bi);
-  else if (j2 < 0) v = cmul(v, p.br, -p.bi);
-  return v;
-}
-
-// Edge values of the box in LDS (planes: x-edge re, x-edge im, y-edge re, y-edge im; index
-// by * BX + bx), seen from the patch at box position (bx, by) = canonical node (p1, p2).
-// Same reads and phase products as ColumnEdges on the column in memory.
-template <typename T, int BX>
-struct TileEdges {
-  T* re0;
-  T* im0;
-  T* re1;
-  T* im1;
-  int bx, by, n, m, p1, p2;
-  Ph<T> p;
-  __device__ __forceinline__ Cx<T> get(int c, int d1, int d2) const {
-    const int i = (by + d2) * BX + bx + d1;
-    const Cx<T> v = c ? Cx<T>{re1[i], im1[i]} : Cx<T>{re0[i], im0[i]};
-    return phased<T>(v, p1 + d1, p2 + d2, n, m, p);
-  }
-  __device__ __forceinline__ void add(int c, int d1, int d2, Cx<T> v) const {
-    const int i = (by + d2) * BX + bx + d1;
-    if (p1 + d1 < 0) v = cmul(v, p.ar, p.ai);
-    if (p2 + d2 < 0) v = cmul(v, p.br, p.bi);
-    T* re = c ? re1 : re0;
-    T* im = c ? im1 : im0;
-    re[i] = re[i] + v.re;
-    im[i] = im[i] + v.im;
+// Parity-split box: position (bx, by) of a BX x BY box is entry (by/2) HX + bx/2 of
+// sub-grid (bx mod 2) + 2 (by mod 2).
+template <int BX, int BY>
+struct Split {
+  static constexpr int HX = (BX + 1) / 2, HY = (BY + 1) / 2, SUB = HX * HY, N = 4 * SUB;
+  __device__ static __forceinline__ int at(int bx, int by) {
+    return ((bx & 1) + 2 * (by & 1)) * SUB + (by >> 1) * HX + (bx >> 1);
   }
 };
 
-template <typename T, int BX>
+// Which neighbours of a node lie across the periodic seam: for a node at canonical (p1, p2)
+// the neighbour at offset d1 = -1 crosses when p1 = 0, d1 = +1 when p1 = n - 1 (y alike).
+// Only the directions in which the box crosses the seam (CX, CY) are checked.
+template <bool CX, bool CY>
+struct Seam {
+  bool lx, hx, ly, hy;
+  __device__ __forceinline__ Seam(int p1, int p2, int n, int m)
+      : lx(CX && p1 == 0), hx(CX && p1 == n - 1), ly(CY && p2 == 0), hy(CY && p2 == m - 1) {}
+  __device__ __forceinline__ bool cross_x(int d1) const { return CX && ((d1 < 0 && lx) || (d1 > 0 && hx)); }
+  __device__ __forceinline__ bool cross_y(int d2) const { return CY && ((d2 < 0 && ly) || (d2 > 0 && hy)); }
+};
+
+template <typename T>
+__device__ __forceinline__ Cx<T> pick(bool c, Cx<T> a, Cx<T> b) {
+  return {c ? a.re : b.re, c ? a.im : b.im};
+}
+
+// The value at offset (d1, d2) as fetch() returns it: times alpha (one period ahead) or
+// conj(alpha) (one period back) across the x seam, then beta likewise across the y seam.
+// The products are formed unconditionally and selected per lane, so that workgroups on the
+// seam run the same instructions in every lane.
+template <bool CX, bool CY, typename T>
+__device__ __forceinline__ Cx<T> phased(Cx<T> v, int d1, int d2, const Seam<CX, CY>& sm, const Ph<T>& p) {
+  if (CX && d1 != 0) v = pick(sm.cross_x(d1), cmul(v, p.ar, d1 > 0 ? p.ai : -p.ai), v);
+  if (CY && d2 != 0) v = pick(sm.cross_y(d2), cmul(v, p.br, d2 > 0 ? p.bi : -p.bi), v);
+  return v;
+}
+
+// Iterate around the patch node at box position (2i + PX, 2j + PY) = canonical (p1, p2), in
+// the LDS planes (x-edge re, x-edge im, y-edge re, y-edge im, Split::N values each).
+template <typename T, int BX, int BY, int PX, int PY, bool CX, bool CY>
+struct TileEdges {
+  using S = Split<BX, BY>;
+  T* pl;
+  int i, j;
+  Seam<CX, CY> sm;
+  Ph<T> p;
+  __device__ __forceinline__ int idx(int d1, int d2) const {
+    const int sx = (PX + d1) & 1, sy = (PY + d2) & 1;
+    return (sx + 2 * sy) * S::SUB + (j + ((PY + d2) >> 1)) * S::HX + i + ((PX + d1) >> 1);
+  }
+  __device__ __forceinline__ Cx<T> get(int c, int d1, int d2) const {
+    const T* q = pl + c * 2 * S::N + idx(d1, d2);
+    return phased<CX, CY, T>(Cx<T>{q[0], q[S::N]}, d1, d2, sm, p);
+  }
+  // as add_ext(): a value written one period back is stored times alpha (beta)
+  __device__ __forceinline__ void add(int c, int d1, int d2, Cx<T> v) const {
+    if (CX && d1 < 0) v = pick(sm.lx, cmul(v, p.ar, p.ai), v);
+    if (CY && d2 < 0) v = pick(sm.ly, cmul(v, p.br, p.bi), v);
+    T* q = pl + c * 2 * S::N + idx(d1, d2);
+    q[0] = q[0] + v.re;
+    q[S::N] = q[S::N] + v.im;
+  }
+};
+
+// Right-hand side around the patch node, read in memory (as fetch()).
+template <typename T, bool CX, bool CY>
+struct TileRhs {
+  const T* bc;
+  int64_t N, nm;
+  int n, m, p1, p2;
+  Seam<CX, CY> sm;
+  Ph<T> p;
+  __device__ __forceinline__ Cx<T> get(int c, int d1, int d2) const {
+    int j1 = p1 + d1, j2 = p2 + d2;
+    if (CX && d1 != 0) j1 = sm.cross_x(d1) ? (d1 < 0 ? n - 1 : 0) : j1;
+    if (CY && d2 != 0) j2 = sm.cross_y(d2) ? (d2 < 0 ? m - 1 : 0) : j2;
+    const int64_t k = (c ? nm : 0) + (int64_t)j2 * n + j1;
+    return phased<CX, CY, T>(Cx<T>{bc[k], bc[N + k]}, d1, d2, sm, p);
+  }
+};
+
+// Nodal values around the node at box position (2i + PX, 2j + PY), two LDS planes.
+template <typename T, int BX, int BY, int PX, int PY, bool CX, bool CY>
 struct TileNodes {
-  const T* re;
-  const T* im;
-  int bx, by, n, m, p1, p2;
+  using S = Split<BX, BY>;
+  const T* pl;
+  int i, j;
+  Seam<CX, CY> sm;
   Ph<T> p;
   __device__ __forceinline__ Cx<T> get(int d1, int d2) const {
-    const int i = (by + d2) * BX + bx + d1;
-    return phased<T>(Cx<T>{re[i], im[i]}, p1 + d1, p2 + d2, n, m, p);
+    const int sx = (PX + d1) & 1, sy = (PY + d2) & 1;
+    const T* q = pl + (sx + 2 * sy) * S::SUB + (j + ((PY + d2) >> 1)) * S::HX + i + ((PX + d1) >> 1);
+    return phased<CX, CY, T>(Cx<T>{q[0], q[S::N]}, d1, d2, sm, p);
   }
 };
 
@@ -105,134 +158,190 @@ __device__ __forceinline__ TileRef tile_ref(const int* slots, int ncps, int tile
   return {slots ? slots[si] : si, (int)blockIdx.y % ncps, (t % tiles_x) * TX, (t / tiles_x) * TY};
 }
 
-template <typename T, int TX, int TY>
-__global__ __launch_bounds__(kThreads) void k_edge_sweep(View<const T> xin, View<T> xout, View<const T> bv,
-                                                         const double* __restrict__ k64,
-                                                         const float* __restrict__ k32,
-                                                         const double* __restrict__ si64,
-                                                         const float* __restrict__ si32, Geo g,
-                                                         const Phase* __restrict__ phs,
-                                                         const double* __restrict__ mus, PatchT T4, int backward,
-                                                         int zero_start, const int* __restrict__ slots, int ncps,
-                                                         int tiles_x) {
-  constexpr int BX = TX + kLo + kHiE, BY = TY + kLo + kHiE, BN = BX * BY;
-  __shared__ T lds[4 * BN];
-  T* const re0 = lds;
-  T* const im0 = lds + BN;
-  T* const re1 = lds + 2 * BN;
-  T* const im1 = lds + 3 * BN;
-  const TileRef tr = tile_ref(slots, ncps, tiles_x, TX, TY);
-  const int n = g.n, m = g.m, tid = threadIdx.x;
-  const int64_t N = g.ne, nm = g.nm;
-  const SJ sj{tr.slot, tr.j};
-  const T* xc = zero_start ? nullptr : colp(xin, sj, N);
-  T* xo = colp(xout, sj, N);
-  const T* bc = colp(bv, sj, N);
-  const Ph<T> p = cast_phase<T>(phs[tr.slot]);
-  for (int e = tid; e < BN; e += kThreads) {
-    if (zero_start) {
-      re0[e] = im0[e] = re1[e] = im1[e] = (T)0;
-    } else {
-      const int c1 = wrapm(tr.t0x - kLo + e % BX, n), c2 = wrapm(tr.t0y - kLo + e / BX, m);
-      const int64_t i = (int64_t)c2 * n + c1;
-      re0[e] = xc[i];
-      im0[e] = xc[N + i];
-      re1[e] = xc[nm + i];
-      im1[e] = xc[N + nm + i];
-    }
-  }
-  __syncthreads();
-  k64 += (int64_t)tr.slot * nm;
-  k32 += (int64_t)tr.slot * nm;
-  const T* sib = pick_si<T>(si64, si32) + 6 * (int64_t)tr.slot * nm;
-  const T s = (T)g.s, mu = (T)mus[tr.slot];
-  const T mmx = mu * (T)g.mx, mmy = mu * (T)g.my;
-  for (int q = 0; q < 4; ++q) {
-    const int colour = backward ? 3 - q : q;
-    // patch nodes: box positions 1 .. B-2 whose canonical parity is the colour's (the box
-    // origin t0 - kLo is even and n, m are even, so the parity is that of the position)
-    const int b0x = (colour & 1) ? 1 : 2, b0y = (colour >> 1) ? 1 : 2;
-    const int cx = (BX - 2 - b0x) / 2 + 1, cy = (BY - 2 - b0y) / 2 + 1;
-    for (int t = tid; t < cx * cy; t += kThreads) {
-      const int bx = b0x + 2 * (t % cx), by = b0y + 2 * (t / cx);
-      const int p1 = wrapm(tr.t0x - kLo + bx, n), p2 = wrapm(tr.t0y - kLo + by, m);
-      const int p1m = wrapi(p1 - 1, n), p2m = wrapi(p2 - 1, m);
-      const T kne = kap<T>(k64, k32, (int64_t)p2 * n + p1);
-      const T knw = kap<T>(k64, k32, (int64_t)p2 * n + p1m);
-      const T ksw = kap<T>(k64, k32, (int64_t)p2m * n + p1m);
-      const T kse = kap<T>(k64, k32, (int64_t)p2m * n + p1);
-      const T* si = sib + 6 * ((int64_t)p2 * n + p1);
-      const TileEdges<T, BX> X{re0, im0, re1, im1, bx, by, n, m, p1, p2, p};
-      patch_update<T>(X, bc, N, n, m, nm, p1, p2, kne, knw, ksw, kse, si, T4, s, mu, mmx, mmy, p);
-    }
-    __syncthreads();
-  }
-  for (int e = tid; e < TX * TY; e += kThreads) {
-    const int ix = e % TX, iy = e / TX;
-    const int c1 = tr.t0x + ix, c2 = tr.t0y + iy;
-    if (c1 >= n || c2 >= m) continue;
-    const int bi = (iy + kLo) * BX + ix + kLo;
-    const int64_t i = (int64_t)c2 * n + c1;
-    xo[i] = re0[bi];
-    xo[N + i] = im0[bi];
-    xo[nm + i] = re1[bi];
-    xo[N + nm + i] = im1[bi];
+struct EdgeArgs {
+  const double* k64;
+  const float* k32;
+  const double* si64;
+  const float* si32;
+  PatchT T4;
+  double s, mx, my;
+};
+
+// One colour pass of the edge smoother on the box (patch nodes at box positions 1 .. B-2 of
+// the colour's parity; the box origin t0 - kLo is even and n, m are even, so the parity of a
+// position is that of its canonical node).
+template <typename T, int BX, int BY, int COLOUR, bool CX, bool CY>
+__device__ __forceinline__ void edge_pass(T* pl, const T* bc, const EdgeArgs& a, int slot, int ox, int oy, int n,
+                                          int m, int64_t N, int64_t nm, T mu, const Ph<T>& p) {
+  constexpr int PX = COLOUR & 1, PY = COLOUR >> 1;
+  constexpr int B0X = PX ? 1 : 2, B0Y = PY ? 1 : 2;
+  constexpr int CNX = (BX - 2 - B0X) / 2 + 1, CNY = (BY - 2 - B0Y) / 2 + 1;
+  const double* k64 = a.k64 + (int64_t)slot * nm;
+  const float* k32 = a.k32 + (int64_t)slot * nm;
+  const T* sib = pick_si<T>(a.si64, a.si32) + kPatchW * (int64_t)slot * nm;
+  const T s = (T)a.s;
+  const T mmx = mu * (T)a.mx, mmy = mu * (T)a.my;
+  for (int t = threadIdx.x; t < CNX * CNY; t += kThreads) {
+    const int i = (B0X >> 1) + t % CNX, j = (B0Y >> 1) + t / CNX;
+    const int bx = 2 * i + PX, by = 2 * j + PY;
+    const int p1 = CX ? wrapm(ox + bx, n) : ox + bx;
+    const int p2 = CY ? wrapm(oy + by, m) : oy + by;
+    const T* si = sib + kPatchW * ((int64_t)p2 * n + p1);
+    const Seam<CX, CY> sm(p1, p2, n, m);
+    const TileEdges<T, BX, BY, PX, PY, CX, CY> X{pl, i, j, sm, p};
+    const int p1m = wrapi(p1 - 1, n), p2m = wrapi(p2 - 1, m);
+    const T kne = kap<T>(k64, k32, (int64_t)p2 * n + p1);
+    const T knw = kap<T>(k64, k32, (int64_t)p2 * n + p1m);
+    const T ksw = kap<T>(k64, k32, (int64_t)p2m * n + p1m);
+    const T kse = kap<T>(k64, k32, (int64_t)p2m * n + p1);
+    const TileRhs<T, CX, CY> B{bc, N, nm, n, m, p1, p2, sm, p};
+    patch_update<T>(X, B, kne, knw, ksw, kse, si, s, mmx, mmy);
   }
 }
 
-template <typename T, int TX, int TY>
-__global__ __launch_bounds__(kThreads) void k_nodal_sweep(View<const T> xin, View<T> xout, View<const T> bv, Geo g,
-                                                          const Phase* __restrict__ phs, NodalStencil st,
-                                                          int backward, int zero_start,
-                                                          const int* __restrict__ slots, int ncps, int tiles_x) {
-  constexpr int BX = TX + kLo + kHiN, BY = TY + kLo + kHiN, BN = BX * BY;
-  __shared__ T lds[2 * BN];
-  T* const re = lds;
-  T* const im = lds + BN;
+template <typename T, int BX, int BY, bool BWD, bool CX, bool CY>
+__device__ __forceinline__ void edge_passes(T* pl, const T* bc, const EdgeArgs& a, int slot, int ox, int oy, int n,
+                                            int m, int64_t N, int64_t nm, T mu, const Ph<T>& p) {
+  edge_pass<T, BX, BY, BWD ? 3 : 0, CX, CY>(pl, bc, a, slot, ox, oy, n, m, N, nm, mu, p);
+  __syncthreads();
+  edge_pass<T, BX, BY, BWD ? 2 : 1, CX, CY>(pl, bc, a, slot, ox, oy, n, m, N, nm, mu, p);
+  __syncthreads();
+  edge_pass<T, BX, BY, BWD ? 1 : 2, CX, CY>(pl, bc, a, slot, ox, oy, n, m, N, nm, mu, p);
+  __syncthreads();
+  edge_pass<T, BX, BY, BWD ? 0 : 3, CX, CY>(pl, bc, a, slot, ox, oy, n, m, N, nm, mu, p);
+  __syncthreads();
+}
+
+template <typename T, int TX, int TY, bool BWD>
+__global__ __launch_bounds__(kThreads) void k_edge_sweep(View<const T> xin, View<T> xout, View<const T> bv, EdgeArgs a,
+                                                         Geo g, const Phase* __restrict__ phs,
+                                                         const double* __restrict__ mus, int zero_start,
+                                                         const int* __restrict__ slots, int ncps, int tiles_x) {
+  constexpr int BX = TX + kLo + kHiE, BY = TY + kLo + kHiE;
+  using S = Split<BX, BY>;
+  __shared__ T pl[4 * S::N];
   const TileRef tr = tile_ref(slots, ncps, tiles_x, TX, TY);
   const int n = g.n, m = g.m, tid = threadIdx.x;
-  const int64_t N = g.nm;
+  const int64_t N = g.ne, nm = g.nm;
+  const int ox = tr.t0x - kLo, oy = tr.t0y - kLo;   // canonical node of box position 0 (unwrapped)
+  const bool cx = !(ox >= 0 && ox + BX <= n), cy = !(oy >= 0 && oy + BY <= m);
   const SJ sj{tr.slot, tr.j};
-  const T* xc = zero_start ? nullptr : colp(xin, sj, N);
   T* xo = colp(xout, sj, N);
   const T* bc = colp(bv, sj, N);
   const Ph<T> p = cast_phase<T>(phs[tr.slot]);
-  for (int e = tid; e < BN; e += kThreads) {
-    if (zero_start) {
-      re[e] = im[e] = (T)0;
-    } else {
-      const int c1 = wrapm(tr.t0x - kLo + e % BX, n), c2 = wrapm(tr.t0y - kLo + e / BX, m);
+  if (zero_start) {
+    for (int e = tid; e < 4 * S::N; e += kThreads) pl[e] = (T)0;
+  } else {
+    const T* xc = colp(xin, sj, N);
+    for (int e = tid; e < BX * BY; e += kThreads) {
+      const int bx = e % BX, by = e / BX;
+      const int c1 = cx ? wrapm(ox + bx, n) : ox + bx, c2 = cy ? wrapm(oy + by, m) : oy + by;
       const int64_t i = (int64_t)c2 * n + c1;
-      re[e] = xc[i];
-      im[e] = xc[N + i];
+      const int k = S::at(bx, by);
+      pl[k] = xc[i];
+      pl[S::N + k] = xc[N + i];
+      pl[2 * S::N + k] = xc[nm + i];
+      pl[3 * S::N + k] = xc[N + nm + i];
     }
   }
   __syncthreads();
-  const T inv = (T)1 / (T)st.c0;
-  for (int q = 0; q < 4; ++q) {
-    const int colour = backward ? 3 - q : q;
-    const int b0x = (colour & 1) ? 1 : 2, b0y = (colour >> 1) ? 1 : 2;
-    const int cx = (BX - 2 - b0x) / 2 + 1, cy = (BY - 2 - b0y) / 2 + 1;
-    for (int t = tid; t < cx * cy; t += kThreads) {
-      const int bx = b0x + 2 * (t % cx), by = b0y + 2 * (t / cx);
-      const int p1 = wrapm(tr.t0x - kLo + bx, n), p2 = wrapm(tr.t0y - kLo + by, m);
-      const int64_t i = (int64_t)p2 * n + p1;
-      const TileNodes<T, BX> X{re, im, bx, by, n, m, p1, p2, p};
-      const Cx<T> r = Cx<T>{bc[i], bc[N + i]} - nodal_stencil_at<T>(X, st);
-      const int bi = by * BX + bx;
-      re[bi] += inv * r.re;
-      im[bi] += inv * r.im;
-    }
-    __syncthreads();
-  }
+  const T mu = (T)mus[tr.slot];
+  if (!cx && !cy) edge_passes<T, BX, BY, BWD, false, false>(pl, bc, a, tr.slot, ox, oy, n, m, N, nm, mu, p);
+  else if (!cy) edge_passes<T, BX, BY, BWD, true, false>(pl, bc, a, tr.slot, ox, oy, n, m, N, nm, mu, p);
+  else if (!cx) edge_passes<T, BX, BY, BWD, false, true>(pl, bc, a, tr.slot, ox, oy, n, m, N, nm, mu, p);
+  else edge_passes<T, BX, BY, BWD, true, true>(pl, bc, a, tr.slot, ox, oy, n, m, N, nm, mu, p);
   for (int e = tid; e < TX * TY; e += kThreads) {
     const int ix = e % TX, iy = e / TX;
     const int c1 = tr.t0x + ix, c2 = tr.t0y + iy;
     if (c1 >= n || c2 >= m) continue;
-    const int bi = (iy + kLo) * BX + ix + kLo;
+    const int k = S::at(ix + kLo, iy + kLo);
     const int64_t i = (int64_t)c2 * n + c1;
-    xo[i] = re[bi];
-    xo[N + i] = im[bi];
+    xo[i] = pl[k];
+    xo[N + i] = pl[S::N + k];
+    xo[nm + i] = pl[2 * S::N + k];
+    xo[N + nm + i] = pl[3 * S::N + k];
+  }
+}
+
+// One colour pass of the nodal point Gauss-Seidel on the box.
+template <typename T, int BX, int BY, int COLOUR, bool CX, bool CY>
+__device__ __forceinline__ void nodal_pass(T* pl, const T* bc, const NodalStencil& st, int ox, int oy, int n, int m,
+                                           int64_t N, const Ph<T>& p) {
+  using S = Split<BX, BY>;
+  constexpr int PX = COLOUR & 1, PY = COLOUR >> 1;
+  constexpr int B0X = PX ? 1 : 2, B0Y = PY ? 1 : 2;
+  constexpr int CNX = (BX - 2 - B0X) / 2 + 1, CNY = (BY - 2 - B0Y) / 2 + 1;
+  const T inv = (T)1 / (T)st.c0;
+  for (int t = threadIdx.x; t < CNX * CNY; t += kThreads) {
+    const int i = (B0X >> 1) + t % CNX, j = (B0Y >> 1) + t / CNX;
+    const int bx = 2 * i + PX, by = 2 * j + PY;
+    const int p1 = CX ? wrapm(ox + bx, n) : ox + bx;
+    const int p2 = CY ? wrapm(oy + by, m) : oy + by;
+    const int64_t k = (int64_t)p2 * n + p1;
+    const TileNodes<T, BX, BY, PX, PY, CX, CY> X{pl, i, j, Seam<CX, CY>(p1, p2, n, m), p};
+    const Cx<T> r = Cx<T>{bc[k], bc[N + k]} - nodal_stencil_at<T>(X, st);
+    T* q = pl + (PX + 2 * PY) * S::SUB + j * S::HX + i;
+    q[0] += inv * r.re;
+    q[S::N] += inv * r.im;
+  }
+}
+
+template <typename T, int BX, int BY, bool BWD, bool CX, bool CY>
+__device__ __forceinline__ void nodal_passes(T* pl, const T* bc, const NodalStencil& st, int ox, int oy, int n, int m,
+                                             int64_t N, const Ph<T>& p) {
+  nodal_pass<T, BX, BY, BWD ? 3 : 0, CX, CY>(pl, bc, st, ox, oy, n, m, N, p);
+  __syncthreads();
+  nodal_pass<T, BX, BY, BWD ? 2 : 1, CX, CY>(pl, bc, st, ox, oy, n, m, N, p);
+  __syncthreads();
+  nodal_pass<T, BX, BY, BWD ? 1 : 2, CX, CY>(pl, bc, st, ox, oy, n, m, N, p);
+  __syncthreads();
+  nodal_pass<T, BX, BY, BWD ? 0 : 3, CX, CY>(pl, bc, st, ox, oy, n, m, N, p);
+  __syncthreads();
+}
+
+template <typename T, int TX, int TY, bool BWD>
+__global__ __launch_bounds__(kThreads) void k_nodal_sweep(View<const T> xin, View<T> xout, View<const T> bv, Geo g,
+                                                          const Phase* __restrict__ phs, NodalStencil st,
+                                                          int zero_start, const int* __restrict__ slots, int ncps,
+                                                          int tiles_x) {
+  constexpr int BX = TX + kLo + kHiN, BY = TY + kLo + kHiN;
+  using S = Split<BX, BY>;
+  __shared__ T pl[2 * S::N];
+  const TileRef tr = tile_ref(slots, ncps, tiles_x, TX, TY);
+  const int n = g.n, m = g.m, tid = threadIdx.x;
+  const int64_t N = g.nm;
+  const int ox = tr.t0x - kLo, oy = tr.t0y - kLo;
+  const bool cx = !(ox >= 0 && ox + BX <= n), cy = !(oy >= 0 && oy + BY <= m);
+  const SJ sj{tr.slot, tr.j};
+  T* xo = colp(xout, sj, N);
+  const T* bc = colp(bv, sj, N);
+  const Ph<T> p = cast_phase<T>(phs[tr.slot]);
+  if (zero_start) {
+    for (int e = tid; e < 2 * S::N; e += kThreads) pl[e] = (T)0;
+  } else {
+    const T* xc = colp(xin, sj, N);
+    for (int e = tid; e < BX * BY; e += kThreads) {
+      const int bx = e % BX, by = e / BX;
+      const int c1 = cx ? wrapm(ox + bx, n) : ox + bx, c2 = cy ? wrapm(oy + by, m) : oy + by;
+      const int64_t i = (int64_t)c2 * n + c1;
+      const int k = S::at(bx, by);
+      pl[k] = xc[i];
+      pl[S::N + k] = xc[N + i];
+    }
+  }
+  __syncthreads();
+  if (!cx && !cy) nodal_passes<T, BX, BY, BWD, false, false>(pl, bc, st, ox, oy, n, m, N, p);
+  else if (!cy) nodal_passes<T, BX, BY, BWD, true, false>(pl, bc, st, ox, oy, n, m, N, p);
+  else if (!cx) nodal_passes<T, BX, BY, BWD, false, true>(pl, bc, st, ox, oy, n, m, N, p);
+  else nodal_passes<T, BX, BY, BWD, true, true>(pl, bc, st, ox, oy, n, m, N, p);
+  for (int e = tid; e < TX * TY; e += kThreads) {
+    const int ix = e % TX, iy = e / TX;
+    const int c1 = tr.t0x + ix, c2 = tr.t0y + iy;
+    if (c1 >= n || c2 >= m) continue;
+    const int k = S::at(ix + kLo, iy + kLo);
+    const int64_t i = (int64_t)c2 * n + c1;
+    xo[i] = pl[k];
+    xo[N + i] = pl[S::N + k];
   }
 }
 
@@ -247,8 +356,13 @@ void edge_sweep(View<const T> xin, View<T> xout, View<const T> b, const double* 
   const int tx = (g.n + kTX - 1) / kTX, ty = (g.m + kTY - 1) / kTY;
   dim3 grid((unsigned)(tx * ty), (unsigned)(L.nact * L.ncps));
   if (grid.y == 0) return;
-  k_edge_sweep<T, kTX, kTY><<<grid, kThreads, 0, L.st>>>(xin, xout, b, kappa64, kappa32, sinv64, sinv32, g, ph, mu, T4,
-                                                         backward ? 1 : 0, zero_start ? 1 : 0, L.slots, L.ncps, tx);
+  const EdgeArgs a{kappa64, kappa32, sinv64, sinv32, T4, g.s, g.mx, g.my};
+  if (backward)
+    k_edge_sweep<T, kTX, kTY, true><<<grid, kThreads, 0, L.st>>>(xin, xout, b, a, g, ph, mu, zero_start ? 1 : 0,
+                                                                 L.slots, L.ncps, tx);
+  else
+    k_edge_sweep<T, kTX, kTY, false><<<grid, kThreads, 0, L.st>>>(xin, xout, b, a, g, ph, mu, zero_start ? 1 : 0,
+                                                                  L.slots, L.ncps, tx);
 }
 
 template <typename T>
@@ -257,8 +371,12 @@ void nodal_sweep(View<const T> xin, View<T> xout, View<const T> b, const Geo& g,
   const int tx = (g.n + kTX - 1) / kTX, ty = (g.m + kTY - 1) / kTY;
   dim3 grid((unsigned)(tx * ty), (unsigned)(L.nact * L.ncps));
   if (grid.y == 0) return;
-  k_nodal_sweep<T, kTX, kTY><<<grid, kThreads, 0, L.st>>>(xin, xout, b, g, ph, c, backward ? 1 : 0, zero_start ? 1 : 0,
-                                                          L.slots, L.ncps, tx);
+  if (backward)
+    k_nodal_sweep<T, kTX, kTY, true><<<grid, kThreads, 0, L.st>>>(xin, xout, b, g, ph, c, zero_start ? 1 : 0,
+                                                                  L.slots, L.ncps, tx);
+  else
+    k_nodal_sweep<T, kTX, kTY, false><<<grid, kThreads, 0, L.st>>>(xin, xout, b, g, ph, c, zero_start ? 1 : 0,
+                                                                   L.slots, L.ncps, tx);
 }
 
 template void edge_sweep<double>(View<const double>, View<double>, View<const double>, const double*, const float*, const double*, const float*, const Geo&, const Phase*, const double*, const PatchT&, bool, bool, const Launch&);

@@ -36,7 +36,8 @@ class BlOpts(ctypes.Structure):
                 ("nu_post", c_int32), ("nodal_cycles", c_int32), ("variant", c_int32),
                 ("precision", c_int32), ("extrap_depth", c_int32), ("autotune", c_int32),
                 ("coarse_fuse", c_int32), ("tiled_sweeps", c_int32),
-                ("tol", c_double), ("mu", c_double), ("zero_rel", c_double)]
+                ("tol", c_double), ("mu", c_double), ("zero_rel", c_double),
+                ("engine_streams", c_int32), ("reserved2", c_int32)]
 
 
 class BlInfo(ctypes.Structure):
