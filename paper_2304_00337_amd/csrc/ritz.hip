@@ -182,9 +182,11 @@ __device__ __forceinline__ int sturm_count(const double* d, const double* e2, in
 
 }  // namespace
 
-size_t ritz_small_work_doubles(int q) { return (size_t)10 * q * q + 8 * (size_t)q + 64; }  // 4 matrices + diagnostics
+// 4 matrices of q rows and stride q | 1 (at most 8 q (q + 1) doubles), then diagnostics at
+// 10 q^2 + 8 q
+size_t ritz_small_work_doubles(int q) { return (size_t)10 * q * q + 8 * (size_t)q + 64; }
 
-// LDS layout (when it fits): A (q*q c2) | B (q*q c2) | Z (q*q c2) | T (q*q c2).
+// LDS layout (when it fits): index arrays | A | B | Z | T, each q rows of stride q | 1.
 template <bool IN_LDS>
 __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2* __restrict__ H, int q,
                                              int nfix, int want, const double* __restrict__ zthr,
@@ -216,10 +218,13 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
   int* pinv = perm + q;
   c2* gw = reinterpret_cast<c2*>(work);
   // compile-time choice, so that LDS pointers keep their address space (no flat accesses)
+  // row strides are odd (q | 1 for q-wide matrices, r | 1 once the rank is known), so that
+  // the rows read side by side by neighbouring lanes fall in different LDS banks
+  const int lq = q | 1;
   c2* A = IN_LDS ? smem + index_block_c2(q) : gw;
-  c2* B = A + q * q;
-  c2* Z = B + q * q;
-  c2* T = Z + q * q;
+  c2* B = A + q * lq;
+  c2* Z = B + q * lq;
+  c2* T = Z + q * lq;
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
   double* stamp = work + 10 * q * q + 8 * q + 1;
   if (tid == 0) { stamp[0] = (double)wall_clock64(); stamp[7] = (double)clock64(); }
@@ -236,7 +241,7 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
     const int i = e / q, j = e % q;
     const c2 g = G[e], gt = G[j * q + i];
     const double s = dsc[i] * dsc[j];
-    A[e] = {0.5 * (g.r + gt.r) * s, 0.5 * (g.i - gt.i) * s};
+    A[i * lq + j] = {0.5 * (g.r + gt.r) * s, 0.5 * (g.i - gt.i) * s};
   }
   __syncthreads();
   int r = 0;
@@ -248,13 +253,13 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
     double v;
     int idx;
     if (k < nfix) {
-      v = A[k * q + k].r;
+      v = A[k * lq + k].r;
       idx = k;
     } else {
       v = -1.0;
       idx = q;
       for (int j = k + lane; j < q; j += 64) {
-        const double dv = A[j * q + j].r;
+        const double dv = A[j * lq + j].r;
         if (dv > v) { v = dv; idx = j; }
       }
       for (int o = 32; o > 0; o >>= 1) {
@@ -268,20 +273,20 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
     if (v < 1e-4 && tid == 0) second_s = 1;
     if (idx != k) {
       for (int c = tid; c < q; c += nt) {
-        const c2 t = A[k * q + c];
-        A[k * q + c] = A[idx * q + c];
-        A[idx * q + c] = t;
+        const c2 t = A[k * lq + c];
+        A[k * lq + c] = A[idx * lq + c];
+        A[idx * lq + c] = t;
         if (c < k) {
-          const c2 u = B[k * q + c];
-          B[k * q + c] = B[idx * q + c];
-          B[idx * q + c] = u;
+          const c2 u = B[k * lq + c];
+          B[k * lq + c] = B[idx * lq + c];
+          B[idx * lq + c] = u;
         }
       }
       __syncthreads();
       for (int c = tid; c < q; c += nt) {
-        const c2 t = A[c * q + k];
-        A[c * q + k] = A[c * q + idx];
-        A[c * q + idx] = t;
+        const c2 t = A[c * lq + k];
+        A[c * lq + k] = A[c * lq + idx];
+        A[c * lq + idx] = t;
       }
       if (tid == 0) {
         const int t = perm[k];
@@ -292,16 +297,16 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
     }
     // factor column k into B and the full trailing square of A in one pass (column k of A
     // is only read here)
-    const double d = A[k * q + k].r;
+    const double d = A[k * lq + k].r;
     const double piv = sqrt(d), invd = 1.0 / d;
     if (tx == 0)
       for (int i = k + ty; i < q; i += 16)
-        B[i * q + k] = (i == k) ? c2{piv, 0.0} : c2{A[i * q + k].r / piv, A[i * q + k].i / piv};
+        B[i * lq + k] = (i == k) ? c2{piv, 0.0} : c2{A[i * lq + k].r / piv, A[i * lq + k].i / piv};
     for (int i = k + 1 + ty; i < q; i += 16) {
-      const c2 aik = A[i * q + k];
+      const c2 aik = A[i * lq + k];
       for (int j = k + 1 + tx; j < q; j += 16) {
-        const c2 t = cmulc(A[j * q + k], aik);
-        A[i * q + j] = {A[i * q + j].r - t.r * invd, A[i * q + j].i - t.i * invd};
+        const c2 t = cmulc(A[j * lq + k], aik);
+        A[i * lq + j] = {A[i * lq + j].r - t.r * invd, A[i * lq + j].i - t.i * invd};
       }
     }
     __syncthreads();
@@ -310,10 +315,11 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
   if (tid == 0) rank_s = r;
   __syncthreads();
   r = rank_s;
+  const int lr = r | 1;
   if (tid == 0) stamp[1] = (double)wall_clock64();
 
   // ---- 2. Z = D P [L^{-*}; 0] -------------------------------------------------------------
-  lower_inv(B, q, A, q, r);
+  lower_inv(B, lq, A, lq, r);
   for (int i = tid; i < q; i += nt) pinv[perm[i]] = i;
   __syncthreads();
   for (int e = tid; e < q * r; e += nt) {
@@ -321,49 +327,49 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
     const int pi = pinv[i];
     c2 z = {0.0, 0.0};
     if (pi < r && pi <= c) {
-      const c2 l = A[c * q + pi];
+      const c2 l = A[c * lq + pi];
       z = {dsc[i] * l.r, -dsc[i] * l.i};
     }
-    Z[i * r + c] = z;
+    Z[i * lr + c] = z;
   }
   __syncthreads();
   if (second_s) {   // G2 = Z^* G Z = L2 L2^*, Z <- Z L2^{-*}
-    mm_nn(G, q, Z, r, T, r, q, r, q);
+    mm_nn(G, q, Z, lr, T, lr, q, r, q);
     __syncthreads();
-    mm_cn(Z, r, T, r, A, r, r, r, q);
+    mm_cn(Z, lr, T, lr, A, lr, r, r, q);
     __syncthreads();
-    chol(A, B, r, r);
-    lower_inv(B, r, A, r, r);
+    chol(A, B, r, lr);
+    lower_inv(B, lr, A, lr, r);
     for (int e = tid; e < q * r; e += nt) {
       const int i = e / r, c = e % r;
       c2 s = {0, 0};
       for (int l = 0; l <= c; ++l) {
-        const c2 t = cmulc(A[c * r + l], Z[i * r + l]);
+        const c2 t = cmulc(A[c * lr + l], Z[i * lr + l]);
         s.r += t.r;
         s.i += t.i;
       }
-      T[i * r + c] = s;
+      T[i * lr + c] = s;
     }
     __syncthreads();
-    for (int e = tid; e < q * r; e += nt) Z[e] = T[e];
+    for (int e = tid; e < q * lr; e += nt) Z[e] = T[e];
     __syncthreads();
   }
   if (tid == 0) stamp[2] = (double)wall_clock64();
 
   // ---- 3. H' = Z^* H Z (A, stride r), Hermitian part, then tridiagonalisation ----------------
-  mm_nn(H, q, Z, r, T, r, q, r, q);
+  mm_nn(H, q, Z, lr, T, lr, q, r, q);
   __syncthreads();
-  mm_cn(Z, r, T, r, A, r, r, r, q);
+  mm_cn(Z, lr, T, lr, A, lr, r, r, q);
   __syncthreads();
   for (int e = tid; e < r * r; e += nt) {
     const int a = e / r, b = e % r;
     if (a < b) {
-      const c2 x = A[a * r + b], y = A[b * r + a];
+      const c2 x = A[a * lr + b], y = A[b * lr + a];
       const c2 h = {0.5 * (x.r + y.r), 0.5 * (x.i - y.i)};
-      A[a * r + b] = h;
-      A[b * r + a] = {h.r, -h.i};
+      A[a * lr + b] = h;
+      A[b * lr + a] = {h.r, -h.i};
     } else if (a == b) {
-      A[e].i = 0.0;
+      A[a * lr + a].i = 0.0;
     }
   }
   __syncthreads();
@@ -378,16 +384,16 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
     const int m = r - k - 1;
     double part = 0;
     for (int j = lane; j < m; j += 64) {
-      const c2 x = A[(k + 1 + j) * r + k];
+      const c2 x = A[(k + 1 + j) * lr + k];
       part += x.r * x.r + x.i * x.i;
     }
     const double xn2 = wave_sum(part);
-    const c2 x0 = A[(k + 1) * r + k];
+    const c2 x0 = A[(k + 1) * lr + k];
     const double ax0 = sqrt(x0.r * x0.r + x0.i * x0.i);
     const double sig = xn2 - ax0 * ax0;
     if (sig <= 1e-30 * xn2 || xn2 == 0.0) {   // already reduced in this column
-      if (tid == 0) { tau[k] = 0.0; dd[k] = A[k * r + k].r; }
-      for (int j = tid; j < r; j += nt) B[k * r + j] = {0.0, 0.0};
+      if (tid == 0) { tau[k] = 0.0; dd[k] = A[k * lr + k].r; }
+      for (int j = tid; j < r; j += nt) B[k * lr + j] = {0.0, 0.0};
       __syncthreads();
       continue;
     }
@@ -398,19 +404,19 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
     for (int j = tid; j < r; j += nt) {
       c2 vj = {0.0, 0.0};
       if (j == k + 1) vj = {x0.r - beta.r, x0.i - beta.i};
-      else if (j > k + 1) vj = A[j * r + k];
-      B[k * r + j] = vj;
+      else if (j > k + 1) vj = A[j * lr + k];
+      B[k * lr + j] = vj;
     }
-    if (tid == 0) { tau[k] = tk; dd[k] = A[k * r + k].r; }
+    if (tid == 0) { tau[k] = tk; dd[k] = A[k * lr + k].r; }
     __syncthreads();
-    const c2* v = B + k * r;
+    const c2* v = B + k * lr;
     {   // p = tau A22 v, four lanes per row
       const int sub = tid & 3;
       for (int rb = 0; rb < m; rb += nt / 4) {
         const int i = rb + tid / 4;
         c2 s = {0, 0};
         if (i < m) {
-          const c2* row = A + (k + 1 + i) * r + k + 1;
+          const c2* row = A + (k + 1 + i) * lr + k + 1;
           for (int l = sub; l < m; l += 4) {
             const c2 t = cmul(row[l], v[k + 1 + l]);
             s.r += t.r;
@@ -435,19 +441,19 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
         const c2 vj = v[k + 1 + j];
         const c2 wj = {pv[j].r - Kh * vj.r, pv[j].i - Kh * vj.i};
         const c2 t1 = cmulc(wj, vi), t2 = cmulc(vj, wi);   // v_i conj(w_j), w_i conj(v_j)
-        c2& a = A[(k + 1 + i) * r + k + 1 + j];
+        c2& a = A[(k + 1 + i) * lr + k + 1 + j];
         a = {a.r - t1.r - t2.r, a.i - t1.i - t2.i};
       }
     }
-    if (tid == 0) A[(k + 1) * r + k] = beta;   // column k: outside the updated block
+    if (tid == 0) A[(k + 1) * lr + k] = beta;   // column k: outside the updated block
     __syncthreads();
   }
   // real tridiagonal: T' = Phi^* T Phi with Phi = diag(phase), off-diagonals |T_{k+1,k}|
   if (tid == 0) {
-    for (int k = (r >= 2 ? r - 2 : 0); k < r; ++k) dd[k] = A[k * r + k].r;
+    for (int k = (r >= 2 ? r - 2 : 0); k < r; ++k) dd[k] = A[k * lr + k].r;
     phase[0] = {1.0, 0.0};
     for (int k = 0; k + 1 < r; ++k) {
-      const c2 b = A[(k + 1) * r + k];
+      const c2 b = A[(k + 1) * lr + k];
       const double ab = sqrt(b.r * b.r + b.i * b.i);
       ee[k] = ab;
       ee2[k] = ab * ab;
@@ -584,12 +590,12 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
   if (tid == 0) stamp[5] = (double)wall_clock64();
 
   // ---- 5. back-transformation: y = H_0 ... H_{r-3} Phi x, then Y = Z y ----------------------
-  // complex vectors of length r, column-major in the A region: yv[c * r + i]
+  // complex vectors of length r, column-major in the A region: yv[c * lr + i]
   c2* yv = A;
   for (int e = tid; e < ns * r; e += nt) {
     const int c = e / r, i = e % r;
     const double xv = xs[(size_t)c * r + i];
-    yv[e] = {phase[i].r * xv, phase[i].i * xv};
+    yv[c * lr + i] = {phase[i].r * xv, phase[i].i * xv};
   }
   __syncthreads();
   {
@@ -599,11 +605,11 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
     for (int cb = 0; cb < ns; cb += nt / GS) {
       const int c = cb + tid / GS;
       if (c < ns) {
-        c2* y = yv + (size_t)c * r;
+        c2* y = yv + (size_t)c * lr;
         for (int k = r - 3; k >= 0; --k) {
           const double tk = tau[k];
           if (tk == 0.0) continue;
-          const c2* v = B + k * r;
+          const c2* v = B + k * lr;
           const int i0 = k + 1 + ((sub - (k + 1)) % GS + GS) % GS;
           c2 s = {0, 0};
           for (int i = i0; i < r; i += GS) {
@@ -637,9 +643,9 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
       for (int l = 0; l < r; ++l) {
         c2 za[3], yb[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) za[a] = (i0 + a < q) ? Z[(i0 + a) * r + l] : c2{0, 0};
+        for (int a = 0; a < 3; ++a) za[a] = (i0 + a < q) ? Z[(i0 + a) * lr + l] : c2{0, 0};
 #pragma unroll
-        for (int b = 0; b < 3; ++b) yb[b] = (j0 + b < ns) ? yv[(j0 + b) * r + l] : c2{0, 0};
+        for (int b = 0; b < 3; ++b) yb[b] = (j0 + b < ns) ? yv[(j0 + b) * lr + l] : c2{0, 0};
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -683,7 +689,7 @@ void ritz_small(const double* G, const double* H, int q, int nfix, int want, con
   }
   if (L.nact <= 0) return;
   const size_t idx = (size_t)index_block_c2(q) * sizeof(c2);
-  const size_t need = idx + (size_t)4 * q * q * sizeof(c2);
+  const size_t need = idx + (size_t)4 * q * (q | 1) * sizeof(c2);
   const int in_lds = need <= (size_t)g_cap ? 1 : 0;
   if (in_lds)
     k_ritz<true><<<L.nact, RT, need, L.st>>>(reinterpret_cast<const c2*>(G), reinterpret_cast<const c2*>(H), q,
