@@ -10,14 +10,17 @@
 //  3. H' = Z^* H Z (r x r) is reduced to real symmetric tridiagonal form by Householder
 //     reflections and a diagonal unitary scaling;
 //  4. the wanted eigenvalues (the `want` smallest above zero_thr) by Sturm-count
-//     multisection, eight lanes per eigenvalue; eigenvectors by inverse iteration with the
-//     tridiagonal LU, re-orthogonalised inside clusters of close eigenvalues;
+//     multisection, eight lanes per eigenvalue; eigenvectors of isolated eigenvalues from
+//     the twisted factorisation, of clusters of close eigenvalues by inverse iteration with
+//     the tridiagonal LU, re-orthogonalised inside the cluster;
 //  5. back-transformation through the scaling and the reflections (eight lanes per vector,
 //     each lane owning a fixed residue class of the rows), Y = Z y.
 //
-// The sequential parts (pivot steps, reflector steps) keep few barriers per step: pivot
-// searches and vector reductions are wave-level shuffle reductions, and every wave
-// computes the small reductions it needs itself instead of waiting for one thread.
+// The sequential parts (pivot steps, reflector steps) keep few barriers per step: the
+// Cholesky pivots without moving data (one barrier per step), pivot searches and vector
+// reductions are wave-level shuffle reductions, every wave computes the small reductions it
+// needs itself instead of waiting for one thread, and the recurrences use a Newton-refined
+// hardware reciprocal instead of division.
 #include "internal.h"
 
 #include <cmath>
@@ -37,13 +40,66 @@ __device__ __forceinline__ c2 cmulc(c2 a, c2 b) { return {a.r * b.r + a.i * b.i,
 constexpr int RT = 256;   // threads per workgroup
 constexpr int GS = 8;     // lanes per eigenvalue / eigenvector group
 
-// size of the per-index arrays (one complex, six doubles, two ints per basis index) in
+// size of the per-index arrays (one complex, eight doubles, four ints per basis index) in
 // complex units, rounded up
-__host__ __device__ inline int index_block_c2(int q) { return (q * (16 + 48 + 8) + 15) / 16; }
+__host__ __device__ inline int index_block_c2(int q) { return (q * (16 + 64 + 16) + 15) / 16; }
+
+// 1 / x from the hardware reciprocal and two Newton steps (full FP64 accuracy, without the
+// long division sequence on the Sturm and factorisation recurrences)
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return r;
+}
+
+// Cross-lane exchanges through DPP (data-parallel primitives: operand swizzles of the vector
+// ALU, a few cycles) instead of LDS permutes (a round trip through the LDS crossbar each).
+// Patterns within rows of 16 lanes: partner lane^1 and lane^2 (quad permutations), then the
+// mirror within 8 lanes and within 16 lanes, which after the first two stages reach the
+// other quad / the other half-row.  All lanes of the wave must be active.
+constexpr int kDppXor1 = 0xB1;         // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;         // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141;  // lane i <-> 7 - i within 8 lanes
+constexpr int kDppMirror = 0x140;      // lane i <-> 15 - i within 16 lanes
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int x) {
+  return __builtin_amdgcn_mov_dpp(x, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+  const long long b = __builtin_bit_cast(long long, x);
+  const int lo = dpp_i<CTRL>((int)(b & 0xffffffffLL)), hi = dpp_i<CTRL>((int)(b >> 32));
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double readlane_d(double x, int l) {
+  const long long b = __builtin_bit_cast(long long, x);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+// sum over groups of 4 / 8 / 16 aligned lanes, the same value in every lane of the group
+// (each stage adds two equal-order pairs, so partners agree bit for bit)
+__device__ __forceinline__ double sum4(double a) {
+  a += dpp_d<kDppXor1>(a);
+  return a + dpp_d<kDppXor2>(a);
+}
+__device__ __forceinline__ double sum8(double a) { a = sum4(a); return a + dpp_d<kDppHalfMirror>(a); }
+__device__ __forceinline__ double sum16(double a) { a = sum8(a); return a + dpp_d<kDppMirror>(a); }
 
 __device__ __forceinline__ double wave_sum(double a) {
-  for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
-  return a;
+  a = sum16(a);
+  return (readlane_d(a, 0) + readlane_d(a, 16)) + (readlane_d(a, 32) + readlane_d(a, 48));
+}
+
+// (v, idx, pos) of the partner lane replaces this lane's when larger, ties to the smaller
+// index (a strict order, so both partners keep the same triple)
+template <int CTRL>
+__device__ __forceinline__ void pick_max(double& v, int& idx, int& pos) {
+  const double ov = dpp_d<CTRL>(v);
+  const int oi = dpp_i<CTRL>(idx), op = dpp_i<CTRL>(pos);
+  if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; pos = op; }
 }
 
 // C (M x N, stride ldc) = X (M x K, stride ldx) * Y (K x N, stride ldy); 3 x 3 register
@@ -128,10 +184,8 @@ __device__ __forceinline__ void lower_inv(const c2* L, int ld, c2* Linv, int ldv
           s.r += t.r;
           s.i += t.i;
         }
-      s.r += __shfl_xor(s.r, 1, 64);
-      s.i += __shfl_xor(s.i, 1, 64);
-      s.r += __shfl_xor(s.r, 2, 64);
-      s.i += __shfl_xor(s.i, 2, 64);
+      s.r = sum4(s.r);
+      s.i = sum4(s.i);
       if (sub == 0 && c < r) {
         c2 v = {0, 0};
         if (c == i) v = {1.0, 0.0};
@@ -174,7 +228,7 @@ __device__ __forceinline__ int sturm_count(const double* d, const double* e2, in
 #pragma unroll 8
   for (int i = 1; i < r; ++i) {
     if (fabs(qv) < tiny) qv = qv < 0 ? -tiny : tiny;
-    qv = d[i] - x - e2[i - 1] / qv;
+    qv = d[i] - x - e2[i - 1] * rcp_nr(qv);
     if (qv < 0) ++c;
   }
   return c;
@@ -229,88 +283,249 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
   double* stamp = work + 10 * q * q + 8 * q + 1;
   if (tid == 0) { stamp[0] = (double)wall_clock64(); stamp[7] = (double)clock64(); }
 
-  // ---- 1. scaled G and pivoted Cholesky (factor columns into B, rows in pivot order) -------
+  // ---- 1. scaled G and pivoted Cholesky -----------------------------------------------------
+  // Implicit pivoting: A keeps the original index order; the remaining indices are a compact
+  // list and the current diagonal a separate array, both double-buffered by step parity, so
+  // that a step needs one barrier (pivot search and update read this step's buffers, the
+  // update writes the next step's).  L_{i,k} of the original index i goes to B[i][k]; the
+  // rows are put in pivot order afterwards.
+  double* dg = reinterpret_cast<double*>(pinv + q);   // [2][q]
+  int* rem = reinterpret_cast<int*>(dg + 2 * q);      // [2][q]
   for (int i = tid; i < q; i += nt) {
     const double gd = G[i * q + i].r;
     dsc[i] = gd > 0 ? 1.0 / sqrt(gd) : 0.0;
-    perm[i] = i;
+    rem[i] = i;
   }
   if (tid == 0) second_s = 0;
   __syncthreads();
-  for (int e = tid; e < q * q; e += nt) {
-    const int i = e / q, j = e % q;
-    const c2 g = G[e], gt = G[j * q + i];
-    const double s = dsc[i] * dsc[j];
-    A[i * lq + j] = {0.5 * (g.r + gt.r) * s, 0.5 * (g.i - gt.i) * s};
-  }
-  __syncthreads();
   int r = 0;
-  const int ty = tid >> 4, tx = tid & 15;   // 16 x 16 layout for the trailing updates
-  for (int k = 0; k < q; ++k) {
-    // pivot: largest remaining diagonal (the first nfix stay in order); every wave finds
-    // it itself (same lanes, same order, identical result).  Below nfix only A[k][k] is
-    // read, which this step's update does not write.
-    double v;
-    int idx;
-    if (k < nfix) {
-      v = A[k * lq + k].r;
-      idx = k;
-    } else {
-      v = -1.0;
-      idx = q;
-      for (int j = k + lane; j < q; j += 64) {
-        const double dv = A[j * lq + j].r;
-        if (dv > v) { v = dv; idx = j; }
+  const int ty = tid >> 4, tx = tid & 15;   // 16 x 16 thread grid
+  if (q <= 3 * 16) {
+    // The matrix in registers: thread (ty, tx) holds the entries (ty + 16 a, tx + 16 b),
+    // a, b < 3.  A step broadcasts the pivot column through LDS (colbuf, by step parity)
+    // and updates every held entry; entries of already pivoted indices are updated too but
+    // never read again, and their diagonal is published as -1, below every candidate, so
+    // that the search runs over all indices (dead: bit mask of the pivoted indices).  Two
+    // barriers per step.
+    c2* colbuf = T;   // [2][q], T is free until the factor is gathered
+    c2 ar[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const int i = ty + 16 * a, j = tx + 16 * b;
+        ar[a][b] = {0.0, 0.0};
+        if (i < q && j < q) {
+          const c2 g = G[i * q + j], gt = G[j * q + i];
+          const double sc = dsc[i] * dsc[j];
+          ar[a][b] = {0.5 * (g.r + gt.r) * sc, 0.5 * (g.i - gt.i) * sc};
+          if (i == j) dg[i] = ar[a][b].r;
+        }
       }
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ov = __shfl_xor(v, o, 64);
-        const int oi = __shfl_xor(idx, o, 64);
-        if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+    __syncthreads();
+    unsigned long long dead = 0;
+    for (int k = 0; k < q; ++k) {
+      const double* dcur = dg + (k & 1) * q;
+      double* dnext = dg + ((k + 1) & 1) * q;
+      c2* col = colbuf + (k & 1) * q;
+      double v;
+      int idx;
+      if (k < nfix) {
+        idx = k;
+        v = dcur[k];
+      } else {
+        v = lane < q ? dcur[lane] : -1.0;
+        idx = lane;
+        int pos = 0;   // unused here
+        pick_max<kDppXor1>(v, idx, pos);
+        pick_max<kDppXor2>(v, idx, pos);
+        pick_max<kDppHalfMirror>(v, idx, pos);
+        pick_max<kDppMirror>(v, idx, pos);
+        double bv = readlane_d(v, 0);
+        int bi = __builtin_amdgcn_readlane(idx, 0);
+        for (int rw = 16; rw < 64; rw += 16) {
+          const double ov = readlane_d(v, rw);
+          const int oi = __builtin_amdgcn_readlane(idx, rw);
+          if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+        }
+        v = bv;
+        idx = bi;
       }
-      __syncthreads();   // all waves have read the diagonal before it changes
-    }
-    if (!(v > drop_rel)) break;
-    if (v < 1e-4 && tid == 0) second_s = 1;
-    if (idx != k) {
-      for (int c = tid; c < q; c += nt) {
-        const c2 t = A[k * lq + c];
-        A[k * lq + c] = A[idx * lq + c];
-        A[idx * lq + c] = t;
-        if (c < k) {
-          const c2 u = B[k * lq + c];
-          B[k * lq + c] = B[idx * lq + c];
-          B[idx * lq + c] = u;
+      if (!(v > drop_rel)) break;
+      dead |= 1ull << idx;
+      if (tid == 0) {
+        if (v < 1e-4) second_s = 1;
+        perm[k] = idx;
+      }
+      const double piv = sqrt(v), rpiv = 1.0 / piv, invd = 1.0 / v;
+      // the pivot column to LDS, and column k of the factor (original rows) to B
+      if (tx == (idx & 15)) {
+        const int bsel = idx >> 4;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const int i = ty + 16 * a;
+          if (i >= q) continue;
+          c2 c = ar[a][0];
+#pragma unroll
+          for (int b = 1; b < 3; ++b) {   // component-wise selects keep ar in registers
+            c.r = (bsel == b) ? ar[a][b].r : c.r;
+            c.i = (bsel == b) ? ar[a][b].i : c.i;
+          }
+          col[i] = c;
+          B[i * lq + k] = (i == idx) ? c2{piv, 0.0} : c2{c.r * rpiv, c.i * rpiv};
         }
       }
       __syncthreads();
-      for (int c = tid; c < q; c += nt) {
-        const c2 t = A[c * lq + k];
-        A[c * lq + k] = A[c * lq + idx];
-        A[c * lq + idx] = t;
+      c2 ci[3], cj[3];
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        ci[u] = (ty + 16 * u < q) ? col[ty + 16 * u] : c2{0.0, 0.0};
+        cj[u] = (tx + 16 * u < q) ? col[tx + 16 * u] : c2{0.0, 0.0};
       }
-      if (tid == 0) {
-        const int t = perm[k];
-        perm[k] = perm[idx];
-        perm[idx] = t;
-      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+          const c2 t = cmulc(cj[b], ci[a]);   // A_i,idx conj(A_j,idx)
+          ar[a][b] = {ar[a][b].r - t.r * invd, ar[a][b].i - t.i * invd};
+        }
+      if (ty == tx)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const int i = ty + 16 * a;
+          if (i < q) dnext[i] = ((dead >> i) & 1ull) ? -1.0 : ar[a][a].r;
+        }
       __syncthreads();
+      r = k + 1;
     }
-    // factor column k into B and the full trailing square of A in one pass (column k of A
-    // is only read here)
-    const double d = A[k * lq + k].r;
-    const double piv = sqrt(d), invd = 1.0 / d;
-    if (tx == 0)
-      for (int i = k + ty; i < q; i += 16)
-        B[i * lq + k] = (i == k) ? c2{piv, 0.0} : c2{A[i * lq + k].r / piv, A[i * lq + k].i / piv};
-    for (int i = k + 1 + ty; i < q; i += 16) {
-      const c2 aik = A[i * lq + k];
-      for (int j = k + 1 + tx; j < q; j += 16) {
-        const c2 t = cmulc(A[j * lq + k], aik);
-        A[i * lq + j] = {A[i * lq + j].r - t.r * invd, A[i * lq + j].i - t.i * invd};
-      }
+    // the dropped indices follow the kept ones in index order
+    if (tid == 0) {
+      int t = r;
+      for (int i = 0; i < q; ++i)
+        if (!((dead >> i) & 1ull)) perm[t++] = i;
+    }
+  } else {
+    for (int e = tid; e < q * q; e += nt) {
+      const int i = e / q, j = e % q;
+      const c2 g = G[e], gt = G[j * q + i];
+      const double s = dsc[i] * dsc[j];
+      const c2 a = {0.5 * (g.r + gt.r) * s, 0.5 * (g.i - gt.i) * s};
+      A[i * lq + j] = a;
+      if (i == j) dg[i] = a.r;
     }
     __syncthreads();
-    r = k + 1;
+    for (int k = 0; k < q; ++k) {
+      const double* dcur = dg + (k & 1) * q;
+      double* dnext = dg + ((k + 1) & 1) * q;
+      const int* rcur = rem + (k & 1) * q;
+      int* rnext = rem + ((k + 1) & 1) * q;
+      const int nr = q - k;
+      // pivot: largest remaining diagonal, ties to the smaller index (the first nfix stay in
+      // order: they lead the list); every wave finds it itself (same lanes, same order)
+      double v;
+      int idx, pos;
+      if (k < nfix) {
+        pos = 0;
+        idx = rcur[0];
+        v = dcur[idx];
+      } else {
+        v = -1.0;
+        idx = q;
+        pos = q;
+        for (int t = lane; t < nr; t += 64) {
+          const int i = rcur[t];
+          const double dv = dcur[i];
+          if (dv > v || (dv == v && i < idx)) { v = dv; idx = i; pos = t; }
+        }
+        pick_max<kDppXor1>(v, idx, pos);
+        pick_max<kDppXor2>(v, idx, pos);
+        pick_max<kDppHalfMirror>(v, idx, pos);
+        pick_max<kDppMirror>(v, idx, pos);
+        // the four rows' winners, in row order (uniform values)
+        double bv = readlane_d(v, 0);
+        int bi = __builtin_amdgcn_readlane(idx, 0), bp = __builtin_amdgcn_readlane(pos, 0);
+        for (int rw = 16; rw < 64; rw += 16) {
+          const double ov = readlane_d(v, rw);
+          const int oi = __builtin_amdgcn_readlane(idx, rw), op = __builtin_amdgcn_readlane(pos, rw);
+          if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; bp = op; }
+        }
+        v = bv;
+        idx = bi;
+        pos = bp;
+      }
+      if (!(v > drop_rel)) break;
+      if (tid == 0) {
+        if (v < 1e-4) second_s = 1;
+        perm[k] = idx;
+      }
+      const double piv = sqrt(v), invd = 1.0 / v;
+      // factor column k (original rows) and the next step's list
+      for (int t = tid; t < nr; t += nt) {
+        const int i = rcur[t];
+        const c2 a = A[i * lq + idx];
+        B[i * lq + k] = (i == idx) ? c2{piv, 0.0} : c2{a.r / piv, a.i / piv};
+        if (t != pos) rnext[t < pos ? t : t - 1] = i;
+      }
+      // trailing update of the remaining indices but idx (column idx is only read here)
+      if (nr <= 48) {
+        // register block of up to 3 x 3 entries: every load before any store, so that the
+        // loads are not held behind stores the compiler cannot tell apart
+        int ib[3], jb[3];
+        c2 ai[3], aj[3], cur[3][3];
+  #pragma unroll
+        for (int u = 0; u < 3; ++u) {
+          const int a = ty + 16 * u, b = tx + 16 * u;
+          ib[u] = (a < nr && a != pos) ? rcur[a] : -1;
+          jb[u] = (b < nr && b != pos) ? rcur[b] : -1;
+        }
+  #pragma unroll
+        for (int u = 0; u < 3; ++u) {
+          if (ib[u] >= 0) ai[u] = A[ib[u] * lq + idx];
+          if (jb[u] >= 0) aj[u] = A[jb[u] * lq + idx];
+        }
+  #pragma unroll
+        for (int v = 0; v < 3; ++v)
+  #pragma unroll
+          for (int u = 0; u < 3; ++u)
+            if (ib[v] >= 0 && jb[u] >= 0) cur[v][u] = A[ib[v] * lq + jb[u]];
+  #pragma unroll
+        for (int v = 0; v < 3; ++v)
+  #pragma unroll
+          for (int u = 0; u < 3; ++u)
+            if (ib[v] >= 0 && jb[u] >= 0) {
+              const c2 t = cmulc(aj[u], ai[v]);
+              const c2 nv = {cur[v][u].r - t.r * invd, cur[v][u].i - t.i * invd};
+              A[ib[v] * lq + jb[u]] = nv;
+              if (ib[v] == jb[u]) dnext[ib[v]] = nv.r;
+            }
+      } else {
+        for (int a = ty; a < nr; a += 16) {
+          if (a == pos) continue;
+          const int i = rcur[a];
+          const c2 aik = A[i * lq + idx];
+          for (int b = tx; b < nr; b += 16) {
+            if (b == pos) continue;
+            const int j = rcur[b];
+            const c2 t = cmulc(A[j * lq + idx], aik);
+            const c2 nv = {A[i * lq + j].r - t.r * invd, A[i * lq + j].i - t.i * invd};
+            A[i * lq + j] = nv;
+            if (a == b) dnext[i] = nv.r;
+          }
+        }
+      }
+      __syncthreads();
+      r = k + 1;
+    }
+
+  }
+  // pivot order of the dropped indices (after the kept ones; the register path has set
+  // them), and the factor's rows in pivot order into T (rows of A are free from here on)
+  if (q > 3 * 16)
+    for (int t = tid; t < q - r; t += nt) perm[r + t] = rem[(r & 1) * q + t];
+  __syncthreads();
+  for (int e = tid; e < r * r; e += nt) {
+    const int ip = e / r, k = e % r;
+    if (k <= ip) T[ip * lq + k] = B[perm[ip] * lq + k];
   }
   if (tid == 0) rank_s = r;
   __syncthreads();
@@ -319,7 +534,7 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
   if (tid == 0) stamp[1] = (double)wall_clock64();
 
   // ---- 2. Z = D P [L^{-*}; 0] -------------------------------------------------------------
-  lower_inv(B, lq, A, lq, r);
+  lower_inv(T, lq, A, lq, r);
   for (int i = tid; i < q; i += nt) pinv[perm[i]] = i;
   __syncthreads();
   for (int e = tid; e < q * r; e += nt) {
@@ -379,74 +594,228 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
   // block becomes H_k A22 H_k via p = tau A22 v, w = p - (tau/2)(v^* p) v,
   // A22 <- A22 - v w^* - w v^*.  T holds p.  Every wave forms the column norm and v^* p
   // itself (same lanes, same order: identical values in all waves).
-  c2* pv = T;
-  for (int k = 0; k + 2 < r; ++k) {
-    const int m = r - k - 1;
-    double part = 0;
-    for (int j = lane; j < m; j += 64) {
-      const c2 x = A[(k + 1 + j) * lr + k];
-      part += x.r * x.r + x.i * x.i;
-    }
-    const double xn2 = wave_sum(part);
-    const c2 x0 = A[(k + 1) * lr + k];
-    const double ax0 = sqrt(x0.r * x0.r + x0.i * x0.i);
-    const double sig = xn2 - ax0 * ax0;
-    if (sig <= 1e-30 * xn2 || xn2 == 0.0) {   // already reduced in this column
-      if (tid == 0) { tau[k] = 0.0; dd[k] = A[k * lr + k].r; }
-      for (int j = tid; j < r; j += nt) B[k * lr + j] = {0.0, 0.0};
+  if (r <= 3 * 16) {
+    // The matrix in registers as in the Cholesky (thread (ty, tx) holds (ty + 16 a, tx + 16 b)).
+    // Per step: column k through LDS (colv, by step parity), the reflector from it in every
+    // wave, p = tau A22 v as per-thread partial sums combined across the 16 threads of a
+    // row with DPP, p through LDS (pv) for v^* p and the column side of w, then the rank-2
+    // update of the held entries.  Two barriers per step.  The subdiagonal (beta) and the
+    // diagonal go to A's LDS copy, where the extraction below reads them.
+    c2* colv = T;             // [2][r]
+    c2* pv = T + 2 * r;       // [r]
+    c2 ar[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const int i = ty + 16 * a, j = tx + 16 * b;
+        ar[a][b] = (i < r && j < r) ? A[i * lr + j] : c2{0.0, 0.0};
+      }
+    __syncthreads();   // A's copy is written below
+    for (int k = 0; k + 2 < r; ++k) {
+      c2* col = colv + (k & 1) * r;
+      if (tx == (k & 15)) {
+        const int bsel = k >> 4;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const int i = ty + 16 * a;
+          if (i >= r) continue;
+          c2 c = ar[a][0];
+#pragma unroll
+          for (int b = 1; b < 3; ++b) {
+            c.r = (bsel == b) ? ar[a][b].r : c.r;
+            c.i = (bsel == b) ? ar[a][b].i : c.i;
+          }
+          col[i] = c;
+          if (i == k) dd[k] = c.r;
+        }
+      }
       __syncthreads();
-      continue;
+      double part = 0;
+      if (lane > k && lane < r) {
+        const c2 x = col[lane];
+        part = x.r * x.r + x.i * x.i;
+      }
+      const double xn2 = wave_sum(part);
+      const c2 x0 = col[k + 1];
+      const double ax0 = sqrt(x0.r * x0.r + x0.i * x0.i);
+      const double sig = xn2 - ax0 * ax0;
+      if (sig <= 1e-30 * xn2 || xn2 == 0.0) {   // already reduced in this column
+        if (tid == 0) {
+          tau[k] = 0.0;
+          A[(k + 1) * lr + k] = x0;
+        }
+        for (int j = tid; j < r; j += nt) B[k * lr + j] = {0.0, 0.0};
+        continue;
+      }
+      const double xn = sqrt(xn2);
+      const c2 ph0 = ax0 > 0 ? c2{x0.r / ax0, x0.i / ax0} : c2{1.0, 0.0};
+      const c2 beta = {-ph0.r * xn, -ph0.i * xn};
+      const double tk = 1.0 / (xn2 + xn * ax0);      // 2 / (v^* v)
+      // v_j: x0 - beta at k + 1, x_j below, 0 above
+      auto vat = [&](int j) -> c2 {
+        if (j == k + 1) return c2{x0.r - beta.r, x0.i - beta.i};
+        return j > k + 1 && j < r ? col[j] : c2{0.0, 0.0};
+      };
+      if (tid < r) B[k * lr + tid] = vat(tid);
+      if (tid == 0) {
+        tau[k] = tk;
+        A[(k + 1) * lr + k] = beta;
+      }
+      c2 vi[3], vj[3];
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        vi[u] = vat(ty + 16 * u);
+        vj[u] = vat(tx + 16 * u);
+      }
+      // p_i = tau sum_j A_ij v_j for the held rows (partials over the held columns, summed
+      // across the row's 16 threads)
+      c2 pi[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        c2 sacc = {0.0, 0.0};
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+          const c2 t = cmul(ar[a][b], vj[b]);
+          sacc.r += t.r;
+          sacc.i += t.i;
+        }
+        pi[a] = {tk * sum16(sacc.r), tk * sum16(sacc.i)};
+        const int i = ty + 16 * a;
+        if (tx == 0 && i > k && i < r) pv[i] = pi[a];
+      }
+      __syncthreads();
+      double kp = 0;
+      if (lane > k && lane < r) kp = cmulc(vat(lane), pv[lane]).r;
+      const double Kh = 0.5 * tk * wave_sum(kp);
+      c2 wi[3], wj[3];
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        wi[u] = {pi[u].r - Kh * vi[u].r, pi[u].i - Kh * vi[u].i};
+        const int j = tx + 16 * u;
+        const c2 pj = (j > k && j < r) ? pv[j] : c2{0.0, 0.0};
+        wj[u] = {pj.r - Kh * vj[u].r, pj.i - Kh * vj[u].i};
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+          if (ty + 16 * a > k && tx + 16 * b > k) {
+            const c2 t1 = cmulc(wj[b], vi[a]), t2 = cmulc(vj[b], wi[a]);   // v_i conj(w_j), w_i conj(v_j)
+            ar[a][b] = {ar[a][b].r - t1.r - t2.r, ar[a][b].i - t1.i - t2.i};
+          }
     }
-    const double xn = sqrt(xn2);
-    const c2 ph0 = ax0 > 0 ? c2{x0.r / ax0, x0.i / ax0} : c2{1.0, 0.0};
-    const c2 beta = {-ph0.r * xn, -ph0.i * xn};
-    const double tk = 1.0 / (xn2 + xn * ax0);      // 2 / (v^* v)
-    for (int j = tid; j < r; j += nt) {
-      c2 vj = {0.0, 0.0};
-      if (j == k + 1) vj = {x0.r - beta.r, x0.i - beta.i};
-      else if (j > k + 1) vj = A[j * lr + k];
-      B[k * lr + j] = vj;
-    }
-    if (tid == 0) { tau[k] = tk; dd[k] = A[k * lr + k].r; }
+    // the last 2 x 2 block (diagonal and subdiagonal) to A's copy
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const int i = ty + 16 * a, j = tx + 16 * b;
+        if (i < r && j < r && i >= r - 2 && j >= r - 2 && j <= i) A[i * lr + j] = ar[a][b];
+      }
     __syncthreads();
-    const c2* v = B + k * lr;
-    {   // p = tau A22 v, four lanes per row
-      const int sub = tid & 3;
-      for (int rb = 0; rb < m; rb += nt / 4) {
-        const int i = rb + tid / 4;
-        c2 s = {0, 0};
-        if (i < m) {
-          const c2* row = A + (k + 1 + i) * lr + k + 1;
-          for (int l = sub; l < m; l += 4) {
-            const c2 t = cmul(row[l], v[k + 1 + l]);
-            s.r += t.r;
-            s.i += t.i;
+  } else {
+    c2* pv = T;
+    for (int k = 0; k + 2 < r; ++k) {
+      const int m = r - k - 1;
+      double part = 0;
+      for (int j = lane; j < m; j += 64) {
+        const c2 x = A[(k + 1 + j) * lr + k];
+        part += x.r * x.r + x.i * x.i;
+      }
+      const double xn2 = wave_sum(part);
+      const c2 x0 = A[(k + 1) * lr + k];
+      const double ax0 = sqrt(x0.r * x0.r + x0.i * x0.i);
+      const double sig = xn2 - ax0 * ax0;
+      if (sig <= 1e-30 * xn2 || xn2 == 0.0) {   // already reduced in this column
+        if (tid == 0) { tau[k] = 0.0; dd[k] = A[k * lr + k].r; }
+        for (int j = tid; j < r; j += nt) B[k * lr + j] = {0.0, 0.0};
+        __syncthreads();
+        continue;
+      }
+      const double xn = sqrt(xn2);
+      const c2 ph0 = ax0 > 0 ? c2{x0.r / ax0, x0.i / ax0} : c2{1.0, 0.0};
+      const c2 beta = {-ph0.r * xn, -ph0.i * xn};
+      const double tk = 1.0 / (xn2 + xn * ax0);      // 2 / (v^* v)
+      for (int j = tid; j < r; j += nt) {
+        c2 vj = {0.0, 0.0};
+        if (j == k + 1) vj = {x0.r - beta.r, x0.i - beta.i};
+        else if (j > k + 1) vj = A[j * lr + k];
+        B[k * lr + j] = vj;
+      }
+      if (tid == 0) { tau[k] = tk; dd[k] = A[k * lr + k].r; }
+      __syncthreads();
+      const c2* v = B + k * lr;
+      {   // p = tau A22 v, four lanes per row
+        const int sub = tid & 3;
+        for (int rb = 0; rb < m; rb += nt / 4) {
+          const int i = rb + tid / 4;
+          c2 s = {0, 0};
+          if (i < m) {
+            const c2* row = A + (k + 1 + i) * lr + k + 1;
+            for (int l = sub; l < m; l += 4) {
+              const c2 t = cmul(row[l], v[k + 1 + l]);
+              s.r += t.r;
+              s.i += t.i;
+            }
+          }
+          s.r = sum4(s.r);
+          s.i = sum4(s.i);
+          if (sub == 0 && i < m) pv[i] = {tk * s.r, tk * s.i};
+        }
+      }
+      __syncthreads();
+      double kp = 0;
+      for (int i = lane; i < m; i += 64) kp += cmulc(v[k + 1 + i], pv[i]).r;
+      const double Kh = 0.5 * tk * wave_sum(kp);
+      if (m <= 48) {
+        // register block of up to 3 x 3 entries, all loads before the stores (as in the
+        // Cholesky update)
+        c2 vi[3], wi[3], vj[3], wj[3], cur[3][3];
+  #pragma unroll
+        for (int u = 0; u < 3; ++u) {
+          const int i = ty + 16 * u, j = tx + 16 * u;
+          if (i < m) {
+            vi[u] = v[k + 1 + i];
+            const c2 pi = pv[i];
+            wi[u] = {pi.r - Kh * vi[u].r, pi.i - Kh * vi[u].i};
+          }
+          if (j < m) {
+            vj[u] = v[k + 1 + j];
+            const c2 pj = pv[j];
+            wj[u] = {pj.r - Kh * vj[u].r, pj.i - Kh * vj[u].i};
           }
         }
-        s.r += __shfl_xor(s.r, 1, 64);
-        s.i += __shfl_xor(s.i, 1, 64);
-        s.r += __shfl_xor(s.r, 2, 64);
-        s.i += __shfl_xor(s.i, 2, 64);
-        if (sub == 0 && i < m) pv[i] = {tk * s.r, tk * s.i};
+  #pragma unroll
+        for (int a = 0; a < 3; ++a)
+  #pragma unroll
+          for (int b = 0; b < 3; ++b)
+            if (ty + 16 * a < m && tx + 16 * b < m) cur[a][b] = A[(k + 1 + ty + 16 * a) * lr + k + 1 + tx + 16 * b];
+  #pragma unroll
+        for (int a = 0; a < 3; ++a)
+  #pragma unroll
+          for (int b = 0; b < 3; ++b)
+            if (ty + 16 * a < m && tx + 16 * b < m) {
+              const c2 t1 = cmulc(wj[b], vi[a]), t2 = cmulc(vj[b], wi[a]);   // v_i conj(w_j), w_i conj(v_j)
+              A[(k + 1 + ty + 16 * a) * lr + k + 1 + tx + 16 * b] = {cur[a][b].r - t1.r - t2.r,
+                                                                      cur[a][b].i - t1.i - t2.i};
+            }
+      } else {
+        for (int i = ty; i < m; i += 16) {
+          const c2 vi = v[k + 1 + i];
+          const c2 wi = {pv[i].r - Kh * vi.r, pv[i].i - Kh * vi.i};
+          for (int j = tx; j < m; j += 16) {
+            const c2 vj = v[k + 1 + j];
+            const c2 wj = {pv[j].r - Kh * vj.r, pv[j].i - Kh * vj.i};
+            const c2 t1 = cmulc(wj, vi), t2 = cmulc(vj, wi);   // v_i conj(w_j), w_i conj(v_j)
+            c2& a = A[(k + 1 + i) * lr + k + 1 + j];
+            a = {a.r - t1.r - t2.r, a.i - t1.i - t2.i};
+          }
+        }
       }
+      if (tid == 0) A[(k + 1) * lr + k] = beta;   // column k: outside the updated block
+      __syncthreads();
     }
-    __syncthreads();
-    double kp = 0;
-    for (int i = lane; i < m; i += 64) kp += cmulc(v[k + 1 + i], pv[i]).r;
-    const double Kh = 0.5 * tk * wave_sum(kp);
-    for (int i = ty; i < m; i += 16) {
-      const c2 vi = v[k + 1 + i];
-      const c2 wi = {pv[i].r - Kh * vi.r, pv[i].i - Kh * vi.i};
-      for (int j = tx; j < m; j += 16) {
-        const c2 vj = v[k + 1 + j];
-        const c2 wj = {pv[j].r - Kh * vj.r, pv[j].i - Kh * vj.i};
-        const c2 t1 = cmulc(wj, vi), t2 = cmulc(vj, wi);   // v_i conj(w_j), w_i conj(v_j)
-        c2& a = A[(k + 1 + i) * lr + k + 1 + j];
-        a = {a.r - t1.r - t2.r, a.i - t1.i - t2.i};
-      }
-    }
-    if (tid == 0) A[(k + 1) * lr + k] = beta;   // column k: outside the updated block
-    __syncthreads();
   }
   // real tridiagonal: T' = Phi^* T Phi with Phi = diag(phase), off-diagonals |T_{k+1,k}|
   if (tid == 0) {
@@ -489,10 +858,13 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
           const int c = inside ? sturm_count(dd, ee2, r, x, tiny) : -1;
           double nlo = (inside && c <= target) ? x : lo;
           double nhi = (inside && c > target) ? x : hi;
-          for (int o = 1; o < GS; o <<= 1) {
-            nlo = fmax(nlo, __shfl_xor(nlo, o, 64));
-            nhi = fmin(nhi, __shfl_xor(nhi, o, 64));
-          }
+          // combine the group of eight (GS) lanes: max of the lower, min of the upper ends
+          nlo = fmax(nlo, dpp_d<kDppXor1>(nlo));
+          nhi = fmin(nhi, dpp_d<kDppXor1>(nhi));
+          nlo = fmax(nlo, dpp_d<kDppXor2>(nlo));
+          nhi = fmin(nhi, dpp_d<kDppXor2>(nhi));
+          nlo = fmax(nlo, dpp_d<kDppHalfMirror>(nlo));
+          nhi = fmin(nhi, dpp_d<kDppHalfMirror>(nhi));
           if (nlo == lo && nhi == hi) break;   // no representable interior point left
           lo = nlo;
           hi = nhi;
@@ -503,9 +875,10 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
   }
   __syncthreads();
   if (tid == 0) stamp[9] = (double)wall_clock64();
-  // Inverse iteration on T' - lambda I with partial pivoting; eigenvalues closer than
-  // 1e-6 tn form a cluster, whose vectors are computed one after the other by one thread
-  // and Gram-Schmidt-orthogonalised against the cluster's earlier vectors.  Real vectors
+  // Eigenvectors: an isolated eigenvalue's from the twisted factorisation; eigenvalues closer
+  // than 1e-6 tn form a cluster, whose vectors come from inverse iteration on T' - lambda I
+  // with partial pivoting, one after the other by one thread, Gram-Schmidt-orthogonalised
+  // against the cluster's earlier vectors.  Real vectors
   // of length r are kept in T (as doubles): vec j at xs + j*r.  Per cluster head j the LU
   // of T' - lambda I (3 arrays of length r) lies in the free A region, continued in T's tail
   // (at most want*r + 3*want*r <= 4 q^2 doubles, the size of A and T together).
@@ -520,6 +893,47 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
     double* u1 = u + r;        // U: diagonal and first super-diagonal; the second
     double* lm = u1 + r;       // super-diagonal is e_{i+1} after a row swap, else 0.
                                // Multipliers; a row swap is encoded as -(mult) - 4.
+    if (jend == j + 1) {
+      // an isolated eigenvalue: its vector from the twisted factorisation of T' - lambda I
+      // (one forward LDL^T and one backward UDU^T pass; the twist index k minimises
+      // |gamma_k| = |D+_k + D-_k - (d_k - lambda)|, and z_k = 1 is propagated both ways)
+      double* x = xs + (size_t)j * r;
+      const double shift = lam[j];
+      double dp = dd[0] - shift;
+      for (int i = 0; i + 1 < r; ++i) {
+        if (fabs(dp) < tiny) dp = dp < 0 ? -tiny : tiny;
+        u[i] = dp;                           // D+_i
+        const double l = ee[i] * rcp_nr(dp);
+        u1[i] = l;                           // L+_i
+        dp = dd[i + 1] - shift - l * ee[i];
+      }
+      if (fabs(dp) < tiny) dp = dp < 0 ? -tiny : tiny;
+      u[r - 1] = dp;
+      double dm = dd[r - 1] - shift;
+      double best = fabs(u[r - 1]);
+      int kt = r - 1;
+      for (int i = r - 2; i >= 0; --i) {
+        if (fabs(dm) < tiny) dm = dm < 0 ? -tiny : tiny;
+        const double uu = ee[i] * rcp_nr(dm);
+        lm[i] = uu;                          // U-_i
+        dm = dd[i] - shift - uu * ee[i];     // D-_i
+        const double gam = fabs(u[i] + dm - (dd[i] - shift));
+        if (gam < best) { best = gam; kt = i; }
+      }
+      x[kt] = 1.0;
+      double nrm = 1.0;
+      for (int i = kt - 1; i >= 0; --i) {
+        x[i] = -u1[i] * x[i + 1];
+        nrm += x[i] * x[i];
+      }
+      for (int i = kt + 1; i < r; ++i) {
+        x[i] = -lm[i - 1] * x[i - 1];
+        nrm += x[i] * x[i];
+      }
+      const double inv = 1.0 / sqrt(nrm);
+      for (int i = 0; i < r; ++i) x[i] *= inv;
+      continue;
+    }
     for (int c = j; c < jend; ++c) {
       double* x = xs + (size_t)c * r;
       const double shift = lam[c];
@@ -617,10 +1031,8 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
             s.r += t.r;
             s.i += t.i;
           }
-          for (int o = 1; o < GS; o <<= 1) {
-            s.r += __shfl_xor(s.r, o, 64);
-            s.i += __shfl_xor(s.i, o, 64);
-          }
+          s.r = sum8(s.r);   // the vector's eight lanes (GS)
+          s.i = sum8(s.i);
           for (int i = i0; i < r; i += GS) {
             const c2 t = cmul(v[i], s);
             y[i] = {y[i].r - tk * t.r, y[i].i - tk * t.i};
