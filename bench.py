@@ -170,12 +170,12 @@ def serving(count, seed, rate_frac=0.7):
 
 def recorded_traffic(avg_cols):
     """HBM bytes per launch of the finest-level edge smoother from the recorded counter runs
-    (profiles/edge_gs_traffic.json: FETCH_SIZE and WRITE_SIZE per dispatch, calibrated on a
+    (profiles/edge_sweep_traffic.json: FETCH_SIZE and WRITE_SIZE per dispatch, calibrated on a
     plain copy), scaled to this run's columns per launch; None when the stencil sources have
     changed since the counters were taken."""
     import hashlib
     try:
-        with open(os.path.join(ROOT, "profiles", "edge_gs_traffic.json")) as f:
+        with open(os.path.join(ROOT, "profiles", "edge_sweep_traffic.json")) as f:
             rec = json.load(f)
         src = "".join(open(os.path.join(ROOT, "paper_2304_00337_amd", "csrc", name)).read()
                       for name in ("stencils.hip", "stencil_common.h", "stencil_ops.h", "sweep.hip"))
