@@ -59,7 +59,7 @@ void bl_default_opts(bl_opts* o, int32_t nev) {
   o->engine_streams = 3;
   o->autotune = 1;
   o->coarse_fuse = 1;
-  o->tiled_sweeps = 1;
+  o->tiled_sweeps = 2;
 }
 
 const char* bl_strerror(int code) {

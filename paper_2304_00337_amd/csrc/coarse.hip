@@ -8,11 +8,18 @@
 // for bit.
 #include "stencil_ops.h"
 
+#include <cstdlib>
+
 #pragma clang fp contract(off)
 
 namespace bl {
 
 namespace {
+
+// Threads per fused workgroup.  Only one workgroup per column runs, so the cycle is latency
+// bound: more threads shorten every pass (a 64 x 64 nodal colour pass is one node per thread
+// at 1024), at the price of slightly dearer barriers.
+constexpr int kFusedMaxThreads = 1024;
 
 template <typename T>
 __device__ __forceinline__ const T* pickp(const double* a, const float* b);
@@ -74,7 +81,7 @@ __device__ void edge_colour(const CoarseCycle& C, int l, int slot, T* x, const T
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_edge_vcycle_fused(View<const T> bv, View<T> xv, CoarseCycle C,
+__global__ __launch_bounds__(kFusedMaxThreads) void k_edge_vcycle_fused(View<const T> bv, View<T> xv, CoarseCycle C,
                                                            const Phase* __restrict__ phs,
                                                            const double* __restrict__ mus,
                                                            const int* __restrict__ slots, int ncps) {
@@ -168,7 +175,7 @@ __device__ void nodal_colour(const Geo& g, T* x, const T* b, int colour, const N
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_nodal_vcycle_fused(View<const T> bv, View<T> xv, CoarseCycle C,
+__global__ __launch_bounds__(kFusedMaxThreads) void k_nodal_vcycle_fused(View<const T> bv, View<T> xv, CoarseCycle C,
                                                             const Phase* __restrict__ phs,
                                                             const int* __restrict__ slots, int ncps) {
   extern __shared__ unsigned char lds_raw[];
@@ -268,6 +275,23 @@ size_t fused_lds_bytes(const CoarseCycle& C, bool edge, size_t elem) {
 
 size_t fused_lds_limit() { return (size_t)lds_cap(); }
 
+namespace {
+// Enough threads for one patch node (edge) or node (nodal) of a colour on the first fused
+// level each, between 256 and kFusedMaxThreads.  Results do not depend on it.
+int fused_threads(const CoarseCycle& C) {
+  static const int forced = [] {
+    const char* e = std::getenv("BL_FUSED_THREADS");
+    const int v = e ? std::atoi(e) : 0;
+    return v >= 64 && v <= kFusedMaxThreads && v % 64 == 0 ? v : 0;
+  }();
+  if (forced) return forced;
+  const int64_t per_colour = C.L[0].g.nm / 4;
+  int nt = 256;
+  while (nt < kFusedMaxThreads && nt < per_colour) nt *= 2;
+  return nt;
+}
+}  // namespace
+
 template <typename T>
 void edge_vcycle_fused(View<const T> b, View<T> x, const CoarseCycle& C, const Phase* ph, const double* mu,
                        const Launch& L) {
@@ -275,7 +299,7 @@ void edge_vcycle_fused(View<const T> b, View<T> x, const CoarseCycle& C, const P
   if (nb <= 0) return;
   const size_t lds = fused_lds_bytes(C, true, sizeof(T));
   (void)lds_cap();
-  k_edge_vcycle_fused<T><<<nb, 256, lds, L.st>>>(b, x, C, ph, mu, L.slots, L.ncps);
+  k_edge_vcycle_fused<T><<<nb, fused_threads(C), lds, L.st>>>(b, x, C, ph, mu, L.slots, L.ncps);
 }
 template <typename T>
 void nodal_vcycle_fused(View<const T> b, View<T> x, const CoarseCycle& C, const Phase* ph, const Launch& L) {
@@ -283,7 +307,7 @@ void nodal_vcycle_fused(View<const T> b, View<T> x, const CoarseCycle& C, const 
   if (nb <= 0) return;
   const size_t lds = fused_lds_bytes(C, false, sizeof(T));
   (void)lds_cap();
-  k_nodal_vcycle_fused<T><<<nb, 256, lds, L.st>>>(b, x, C, ph, L.slots, L.ncps);
+  k_nodal_vcycle_fused<T><<<nb, fused_threads(C), lds, L.st>>>(b, x, C, ph, L.slots, L.ncps);
 }
 template void edge_vcycle_fused<double>(View<const double>, View<double>, const CoarseCycle&, const Phase*, const double*, const Launch&);
 template void edge_vcycle_fused<float>(View<const float>, View<float>, const CoarseCycle&, const Phase*, const double*, const Launch&);

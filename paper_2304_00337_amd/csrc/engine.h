@@ -169,6 +169,7 @@ struct bl_solver {
   bl::SmoothShape tune_edge, tune_nodal;
   int tune_rr = 0;            // Rayleigh-Ritz output tile for q = 2p (0 = by padding)
   double tune_ms = 0.0;       // time the autotuner spent
+  int tune_sweep[2] = {0, 0}; // tile shapes of the edge and nodal sweeps (see edge_sweep)
 };
 
 namespace bl {

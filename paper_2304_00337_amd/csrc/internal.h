@@ -87,17 +87,32 @@ template <typename T>
 void edge_gs(View<T> x, View<const T> b, const double* kappa64, const float* kappa32,
              const double* sinv64, const float* sinv32, const Geo& g, const Phase* ph,
              const double* mu, const PatchT& T4, int colour, const SmoothShape& sh, const Launch& L);
+// Level transfers folded into a tiled sweep.  bc set (forward sweeps): the sweep also forms
+// the residual b - K x of its result and writes its restriction to the coarse right-hand
+// side bc (level geometry gc).  xc set: the sweep starts from xin + Pr xc (the coarse
+// correction prolongated on the fly).  base set: the sweep writes base + result (xout may be
+// base itself).  Each result equals that of the separate kernels bit for bit.
+template <typename T>
+struct SweepFuse {
+  View<T> bc{nullptr, 0, 0};
+  View<const T> xc{nullptr, 0, 0};
+  View<const T> base{nullptr, 0, 0};
+  Geo gc{};
+};
+
 // One whole smoothing sweep (four colours; reverse colour order when backward) as one launch
-// over LDS tiles with halos, bit-identical to the four colour launches.  Reads the iterate
+// over LDS tiles with halos, bit-identical to the four colour launches; `tile` selects the
+// tile shape (0: 32 x 32, 1: 64 x 32 nodes; FP64 edge sweeps 32 x 32).  Reads the iterate
 // from xin and writes it to xout, which must be different buffers; zero_start: the iterate is
 // zero on entry (xin is then not read).  sweep.hip.
 template <typename T>
 void edge_sweep(View<const T> xin, View<T> xout, View<const T> b, const double* kappa64, const float* kappa32,
                 const double* sinv64, const float* sinv32, const Geo& g, const Phase* ph, const double* mu,
-                const PatchT& T4, bool backward, bool zero_start, const Launch& L);
+                const PatchT& T4, bool backward, bool zero_start, int tile, const Launch& L);
 template <typename T>
 void nodal_sweep(View<const T> xin, View<T> xout, View<const T> b, const Geo& g, const Phase* ph,
-                 const NodalStencil& c, bool backward, bool zero_start, const Launch& L);
+                 const NodalStencil& c, bool backward, bool zero_start, int tile, const Launch& L,
+                 const SweepFuse<T>& fz = SweepFuse<T>{});
 void patch_setup(const double* kappa, const Geo& g, const double* q, const PatchT& T4, const double* mu,
                  double* sinv64, float* sinv32, int nslots, hipStream_t st);
 void coarsen_kappa(const double* kf, const Geo& gf, double* kc, int nslots, hipStream_t st);

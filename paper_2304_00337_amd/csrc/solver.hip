@@ -121,7 +121,7 @@ int validate_opts(const bl_opts* o) {
   if (o->extrap_depth < 1 || o->extrap_depth > 3) return set_error(BL_EINVAL, "extrap_depth must be 1..3%s");
   if (o->autotune != 0 && o->autotune != 1) return set_error(BL_EINVAL, "autotune must be 0 or 1%s");
   if (o->coarse_fuse != 0 && o->coarse_fuse != 1) return set_error(BL_EINVAL, "coarse_fuse must be 0 or 1%s");
-  if (o->tiled_sweeps != 0 && o->tiled_sweeps != 1) return set_error(BL_EINVAL, "tiled_sweeps must be 0 or 1%s");
+  if (o->tiled_sweeps < 0 || o->tiled_sweeps > 2) return set_error(BL_EINVAL, "tiled_sweeps must be 0, 1 or 2%s");
   if (o->engine_streams < 1 || o->engine_streams > 16) return set_error(BL_EINVAL, "engine_streams must be 1..16%s");
   if (!(o->tol > 0)) return set_error(BL_EINVAL, "tol must be positive%s");
   return BL_OK;
@@ -326,7 +326,7 @@ void vcycle_edge(bl_solver* s, int l, View<const T> b, View<T> x, const Launch& 
       View<T> dst = ((npre - 1 - it) % 2 == 0) ? x : r;
       timing_begin(s, l);
       edge_sweep<T>(cv(src), dst, b, lv.kappa64, lv.kappa32, lv.sinv64, lv.sinv32, lv.g, s->ph_d, s->mu_d, lv.T4,
-                    false, it == 0, L);
+                    false, it == 0, s->tune_sweep[0], L);
       timing_end(s, l, ncols, smooth_bytes(lv.g, sizeof(T), true, it == 0, ncols, L.nact));
       nl_launch += 1;
       continue;
@@ -351,7 +351,7 @@ void vcycle_edge(bl_solver* s, int l, View<const T> b, View<T> x, const Launch& 
       View<T> dst = (cur.p == x.p && cur.off == x.off && cur.cps == x.cps) ? r : x;
       timing_begin(s, l);
       edge_sweep<T>(cv(cur), dst, b, lv.kappa64, lv.kappa32, lv.sinv64, lv.sinv32, lv.g, s->ph_d, s->mu_d, lv.T4,
-                    true, false, L);
+                    true, false, s->tune_sweep[0], L);
       timing_end(s, l, ncols, smooth_bytes(lv.g, sizeof(T), true, false, ncols, L.nact));
       cur = dst;
       nl_launch += 1;
@@ -372,25 +372,65 @@ void vcycle_edge(bl_solver* s, int l, View<const T> b, View<T> x, const Launch& 
 }
 
 // ---- nodal V-cycle for P = L^* M L ----------------------------------------------------------
+// x = V(b); with add_to, a cycle that can fold the update into its last sweep writes
+// *add_to + V(b) to *add_to instead (x is then not written) and returns true.
 template <typename T>
-void vcycle_nodal(bl_solver* s, int l, View<const T> b, View<T> x, const Launch& L) {
+bool vcycle_nodal(bl_solver* s, int l, View<const T> b, View<T> x, const Launch& L, const View<T>* add_to = nullptr) {
   const int pr = PrecOf<T>::v;
   Level& lv = s->lv[l];
   const int nl = (int)s->lv.size();
   if (l == nl - 1) {
     dense_apply<T>(pc_inv<T>(s), s->ncn, b, x, L);
     s->launches += 1;
-    return;
+    return false;
   }
   if (l == s->fuse_nodal[pr]) {
     nodal_vcycle_fused<T>(b, x, coarse_cycle(s, l, pc_inv<T>(s), s->ncn), s->ph_d, L);
     s->launches += 1;
-    return;
+    return false;
   }
   // tiled sweeps alternate between x and the residual block r, as in the edge cycle
   const bool tiled = s->opts.tiled_sweeps != 0;
   const int npre = s->opts.nu_pre, npost = s->opts.nu_post;
   View<T> r = view(static_cast<T*>(lv.nr[pr]), lv.ncap[pr]);
+  if (s->opts.tiled_sweeps == 2 && npre > 0 && npost > 0) {
+    // Transfers folded into the sweeps: the last pre-sweep also restricts its residual to the
+    // coarse right-hand side, the first post-sweep starts from its input plus the prolongated
+    // coarse correction.  No residual block is stored: x and r only alternate as sweep
+    // buffers, the pre-smoothed iterate landing in E so that the last post-sweep writes x.
+    Level& C = s->lv[l + 1];
+    View<T> bc = view(static_cast<T*>(C.nb[pr]), C.ncap[pr]);
+    View<T> xc = view(static_cast<T*>(C.nx[pr]), C.ncap[pr]);
+    const View<T> E = (npost % 2 == 1) ? r : x, F = (npost % 2 == 1) ? x : r;
+    View<T> prev = E;
+    for (int it = 0; it < npre; ++it) {
+      const View<T> dst = ((npre - 1 - it) % 2 == 0) ? E : F;
+      SweepFuse<T> fz;
+      if (it == npre - 1) {
+        fz.bc = bc;
+        fz.gc = C.g;
+      }
+      nodal_sweep<T>(cv(prev), dst, b, lv.g, s->ph_d, s->ns, false, it == 0, s->tune_sweep[1], L, fz);
+      prev = dst;
+    }
+    vcycle_nodal<T>(s, l + 1, cv(bc), xc, L);
+    for (int it = 0; it < npost; ++it) {
+      View<T> dst = ((npost - 1 - it) % 2 == 0) ? x : r;
+      SweepFuse<T> fz;
+      if (it == 0) {
+        fz.xc = cv(xc);
+        fz.gc = C.g;
+      }
+      if (it == npost - 1 && add_to) {
+        dst = *add_to;
+        fz.base = cv(*add_to);
+      }
+      nodal_sweep<T>(cv(prev), dst, b, lv.g, s->ph_d, s->ns, true, false, s->tune_sweep[1], L, fz);
+      prev = dst;
+    }
+    s->launches += npre + npost;
+    return add_to != nullptr;
+  }
   int nl_launch = 0;
   if (!tiled || npre == 0) {
     zero_cols<T>(x, lv.g.nm, L);
@@ -400,7 +440,7 @@ void vcycle_nodal(bl_solver* s, int l, View<const T> b, View<T> x, const Launch&
     if (tiled) {
       View<T> src = ((npre - it) % 2 == 0) ? x : r;
       View<T> dst = ((npre - 1 - it) % 2 == 0) ? x : r;
-      nodal_sweep<T>(cv(src), dst, b, lv.g, s->ph_d, s->ns, false, it == 0, L);
+      nodal_sweep<T>(cv(src), dst, b, lv.g, s->ph_d, s->ns, false, it == 0, s->tune_sweep[1], L);
       nl_launch += 1;
     } else {
       for (int c = 0; c < 4; ++c) nodal_gs<T>(x, b, lv.g, s->ph_d, s->ns, c, s->tune_nodal, L);
@@ -418,7 +458,7 @@ void vcycle_nodal(bl_solver* s, int l, View<const T> b, View<T> x, const Launch&
     nodal_prolong_to<T>(cv(xc), C.g, cv(x), cur, lv.g, s->ph_d, L);
     for (int it = 0; it < npost; ++it) {
       View<T> dst = (cur.p == x.p && cur.off == x.off && cur.cps == x.cps) ? r : x;
-      nodal_sweep<T>(cv(cur), dst, b, lv.g, s->ph_d, s->ns, true, false, L);
+      nodal_sweep<T>(cv(cur), dst, b, lv.g, s->ph_d, s->ns, true, false, s->tune_sweep[1], L);
       cur = dst;
       nl_launch += 1;
     }
@@ -430,6 +470,7 @@ void vcycle_nodal(bl_solver* s, int l, View<const T> b, View<T> x, const Launch&
     }
   }
   s->launches += 3 + nl_launch;
+  return false;
 }
 
 // phi ~ P^{-1} b by `cycles` V-cycles; b and phi must not be level-0 work blocks of the
@@ -443,9 +484,11 @@ void nodal_solve(bl_solver* s, View<const T> b, View<T> phi, const Launch& L, in
   const Geo& g = s->lv[0].g;
   for (int c = 1; c < cycles; ++c) {
     nodal_apply<T>(cv(phi), b, res, g, s->ph_d, s->ns, true, L);
-    vcycle_nodal<T>(s, 0, cv(res), cor, L);
-    axpy<T>(phi, cv(cor), g.nm, L);
-    s->launches += 3;
+    s->launches += 1;
+    if (!vcycle_nodal<T>(s, 0, cv(res), cor, L, &phi)) {
+      axpy<T>(phi, cv(cor), g.nm, L);
+      s->launches += 1;
+    }
   }
 }
 

@@ -201,27 +201,32 @@ __device__ __forceinline__ Cx<T> nodal_stencil(const T* c, int64_t N, int n, int
   return nodal_stencil_at<T>(ColumnNodes<T>{c, N, n, m, p1, p2, p}, s);
 }
 
-// Coarse node d of the full-weighting restriction (adjoint of bilinear interpolation).
-template <typename T>
-__device__ __forceinline__ Cx<T> nodal_restrict_at(const T* r, const Geo& gf, const Geo& gc, int64_t d,
-                                                   const Ph<T>& p) {
-  const int J1 = (int)(d % gc.n), J2 = (int)(d / gc.n);
+// Full-weighting restriction (adjoint of bilinear interpolation) at a coarse node, from the
+// fine values around its fine node 2J given by an accessor R (R.get(d1, d2) as fetch()).
+template <typename T, typename RA>
+__device__ __forceinline__ Cx<T> nodal_restrict_acc(const RA& R) {
   Cx<T> v = {0, 0};
 #pragma unroll
   for (int d2 = -1; d2 <= 1; ++d2)
 #pragma unroll
     for (int d1 = -1; d1 <= 1; ++d1) {
       const T w = (T)((d1 == 0 ? 1.0 : 0.5) * (d2 == 0 ? 1.0 : 0.5));
-      v = v + (w * fetch<T, T>(r, gf.nm, gf.n, gf.m, 0, 2 * J1 + d1, 2 * J2 + d2, p));
+      v = v + (w * R.get(d1, d2));
     }
   return v;
 }
 
-// Fine node d of the bilinear interpolation of the coarse nodal function.
+// Coarse node d of the full-weighting restriction of the fine column r.
 template <typename T>
-__device__ __forceinline__ Cx<T> nodal_prolong_at(const T* c, const Geo& gc, const Geo& gf, int64_t d,
-                                                  const Ph<T>& p) {
-  const int f1 = (int)(d % gf.n), f2 = (int)(d / gf.n);
+__device__ __forceinline__ Cx<T> nodal_restrict_at(const T* r, const Geo& gf, const Geo& gc, int64_t d,
+                                                   const Ph<T>& p) {
+  const int J1 = (int)(d % gc.n), J2 = (int)(d / gc.n);
+  return nodal_restrict_acc<T>(ColumnNodes<T>{r, gf.nm, gf.n, gf.m, 2 * J1, 2 * J2, p});
+}
+
+// Fine node (f1, f2) of the bilinear interpolation of the coarse nodal function.
+template <typename T>
+__device__ __forceinline__ Cx<T> nodal_prolong_xy(const T* c, const Geo& gc, int f1, int f2, const Ph<T>& p) {
   const int J1 = f1 >> 1, J2 = f2 >> 1;
   const bool o1 = f1 & 1, o2 = f2 & 1;
   const Cx<T> c00 = fetch<T, T>(c, gc.nm, gc.n, gc.m, 0, J1, J2, p);
@@ -231,6 +236,13 @@ __device__ __forceinline__ Cx<T> nodal_prolong_at(const T* c, const Geo& gc, con
   return (T)0.25 * (c00 + fetch<T, T>(c, gc.nm, gc.n, gc.m, 0, J1 + 1, J2, p) +
                     fetch<T, T>(c, gc.nm, gc.n, gc.m, 0, J1, J2 + 1, p) +
                     fetch<T, T>(c, gc.nm, gc.n, gc.m, 0, J1 + 1, J2 + 1, p));
+}
+
+// Fine node d of the bilinear interpolation of the coarse nodal function.
+template <typename T>
+__device__ __forceinline__ Cx<T> nodal_prolong_at(const T* c, const Geo& gc, const Geo& gf, int64_t d,
+                                                  const Ph<T>& p) {
+  return nodal_prolong_xy<T>(c, gc, (int)(d % gf.n), (int)(d / gf.n), p);
 }
 
 }  // namespace bl

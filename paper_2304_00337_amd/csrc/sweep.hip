@@ -299,18 +299,89 @@ __device__ __forceinline__ void nodal_passes(T* pl, const T* bc, const NodalSten
   __syncthreads();
 }
 
-template <typename T, int TX, int TY, bool BWD>
+// Residual b - P x on the box positions of parity (PX, PY) inside the residual window
+// [LO - 1, LO + TX - 1] x [LO - 1, LO + TY - 1] (the fine nodes that the restriction to the
+// tile's coarse nodes reads), as the residual kernel computes it, into rl (row-major window,
+// re plane then im plane).
+template <typename T, int BX, int BY, int PX, int PY, bool CX, bool CY, int LO, int TX, int TY>
+__device__ __forceinline__ void nodal_resid_pass(const T* pl, T* rl, const T* bc, const NodalStencil& st, int ox,
+                                                 int oy, int n, int m, int64_t N, const Ph<T>& p) {
+  constexpr int R0 = LO - 1, RW = TX + 1, RH = TY + 1;
+  constexpr int I0 = (R0 - PX + 1) / 2, I1 = (LO + TX - 1 - PX) / 2;
+  constexpr int J0 = (R0 - PY + 1) / 2, J1 = (LO + TY - 1 - PY) / 2;
+  constexpr int CNX = I1 - I0 + 1, CNY = J1 - J0 + 1;
+  for (int t = threadIdx.x; t < CNX * CNY; t += kThreads) {
+    const int i = I0 + t % CNX, j = J0 + t / CNX;
+    const int bx = 2 * i + PX, by = 2 * j + PY;
+    const int p1 = CX ? wrapm(ox + bx, n) : ox + bx;
+    const int p2 = CY ? wrapm(oy + by, m) : oy + by;
+    const int64_t k = (int64_t)p2 * n + p1;
+    const TileNodes<T, BX, BY, PX, PY, CX, CY> X{pl, i, j, Seam<CX, CY>(p1, p2, n, m), p};
+    const Cx<T> r = Cx<T>{bc[k], bc[N + k]} - nodal_stencil_at<T>(X, st);
+    const int q = (by - R0) * RW + (bx - R0);
+    rl[q] = r.re;
+    rl[RW * RH + q] = r.im;
+  }
+}
+
+// Residual window values around window position (x, y) (as fetch()).
+template <typename T, int RW, int RH, bool CX, bool CY>
+struct WindowNodes {
+  const T* rl;
+  int x, y;
+  Seam<CX, CY> sm;
+  Ph<T> p;
+  __device__ __forceinline__ Cx<T> get(int d1, int d2) const {
+    const int q = (y + d2) * RW + x + d1;
+    return phased<CX, CY, T>(Cx<T>{rl[q], rl[RW * RH + q]}, d1, d2, sm, p);
+  }
+};
+
+// Residual of the swept tile and its restriction to the tile's coarse nodes.
+template <typename T, int BX, int BY, bool CX, bool CY, int LO, int TX, int TY>
+__device__ __forceinline__ void nodal_restrict_tile(const T* pl, T* rl, const T* bc, T* bco, const NodalStencil& st,
+                                                    int ox, int oy, int t0x, int t0y, int n, int m, int64_t N,
+                                                    const Geo& gc, const Ph<T>& p) {
+  nodal_resid_pass<T, BX, BY, 0, 0, CX, CY, LO, TX, TY>(pl, rl, bc, st, ox, oy, n, m, N, p);
+  nodal_resid_pass<T, BX, BY, 1, 0, CX, CY, LO, TX, TY>(pl, rl, bc, st, ox, oy, n, m, N, p);
+  nodal_resid_pass<T, BX, BY, 0, 1, CX, CY, LO, TX, TY>(pl, rl, bc, st, ox, oy, n, m, N, p);
+  nodal_resid_pass<T, BX, BY, 1, 1, CX, CY, LO, TX, TY>(pl, rl, bc, st, ox, oy, n, m, N, p);
+  __syncthreads();
+  constexpr int HX = TX / 2, HY = TY / 2;
+  for (int t = threadIdx.x; t < HX * HY; t += kThreads) {
+    const int jx = t % HX, jy = t / HX;
+    const int f1 = t0x + 2 * jx, f2 = t0y + 2 * jy;
+    if (f1 >= n || f2 >= m) continue;
+    const WindowNodes<T, TX + 1, TY + 1, CX, CY> R{rl, 2 * jx + 1, 2 * jy + 1, Seam<CX, CY>(f1, f2, n, m), p};
+    const Cx<T> v = nodal_restrict_acc<T>(R);
+    const int64_t J = (int64_t)(f2 >> 1) * gc.n + (f1 >> 1);
+    bco[J] = v.re;
+    bco[gc.nm + J] = v.im;
+  }
+}
+
+// MODE bits of a sweep with level transfers folded in: kRestrict (forward sweeps) also forms
+// the residual of the result and restricts it to the coarse right-hand side; kProlong starts
+// from xin + Pr xc; kBase writes base + result.
+constexpr int kRestrict = 1, kProlong = 2, kBase = 4;
+constexpr int kLoR = 6;   // low halo when the residual window is needed (even)
+
+template <typename T, int TX, int TY, bool BWD, int MODE>
 __global__ __launch_bounds__(kThreads) void k_nodal_sweep(View<const T> xin, View<T> xout, View<const T> bv, Geo g,
                                                           const Phase* __restrict__ phs, NodalStencil st,
                                                           int zero_start, const int* __restrict__ slots, int ncps,
-                                                          int tiles_x) {
-  constexpr int BX = TX + kLo + kHiN, BY = TY + kLo + kHiN;
+                                                          int tiles_x, SweepFuse<T> fz) {
+  static_assert(!((MODE & kRestrict) && BWD), "the residual window halo is sized for forward sweeps");
+  constexpr bool RES = (MODE & kRestrict) != 0, PRO = (MODE & kProlong) != 0, BAS = (MODE & kBase) != 0;
+  constexpr int LO = RES ? kLoR : kLo;
+  constexpr int BX = TX + LO + kHiN, BY = TY + LO + kHiN;
   using S = Split<BX, BY>;
   __shared__ T pl[2 * S::N];
+  __shared__ T rl[RES ? 2 * (TX + 1) * (TY + 1) : 1];
   const TileRef tr = tile_ref(slots, ncps, tiles_x, TX, TY);
   const int n = g.n, m = g.m, tid = threadIdx.x;
   const int64_t N = g.nm;
-  const int ox = tr.t0x - kLo, oy = tr.t0y - kLo;
+  const int ox = tr.t0x - LO, oy = tr.t0y - LO;
   const bool cx = !(ox >= 0 && ox + BX <= n), cy = !(oy >= 0 && oy + BY <= m);
   const SJ sj{tr.slot, tr.j};
   T* xo = colp(xout, sj, N);
@@ -320,13 +391,20 @@ __global__ __launch_bounds__(kThreads) void k_nodal_sweep(View<const T> xin, Vie
     for (int e = tid; e < 2 * S::N; e += kThreads) pl[e] = (T)0;
   } else {
     const T* xc = colp(xin, sj, N);
+    const T* cc = PRO ? colp(fz.xc, sj, fz.gc.nm) : nullptr;
     for (int e = tid; e < BX * BY; e += kThreads) {
       const int bx = e % BX, by = e / BX;
       const int c1 = cx ? wrapm(ox + bx, n) : ox + bx, c2 = cy ? wrapm(oy + by, m) : oy + by;
       const int64_t i = (int64_t)c2 * n + c1;
       const int k = S::at(bx, by);
-      pl[k] = xc[i];
-      pl[S::N + k] = xc[N + i];
+      if (PRO) {   // as the prolongation kernel: base + Pr xc
+        const Cx<T> v = nodal_prolong_xy<T>(cc, fz.gc, c1, c2, p);
+        pl[k] = xc[i] + v.re;
+        pl[S::N + k] = xc[N + i] + v.im;
+      } else {
+        pl[k] = xc[i];
+        pl[S::N + k] = xc[N + i];
+      }
     }
   }
   __syncthreads();
@@ -334,54 +412,117 @@ __global__ __launch_bounds__(kThreads) void k_nodal_sweep(View<const T> xin, Vie
   else if (!cy) nodal_passes<T, BX, BY, BWD, true, false>(pl, bc, st, ox, oy, n, m, N, p);
   else if (!cx) nodal_passes<T, BX, BY, BWD, false, true>(pl, bc, st, ox, oy, n, m, N, p);
   else nodal_passes<T, BX, BY, BWD, true, true>(pl, bc, st, ox, oy, n, m, N, p);
+  const T* bs = BAS ? colp(fz.base, sj, N) : nullptr;
   for (int e = tid; e < TX * TY; e += kThreads) {
     const int ix = e % TX, iy = e / TX;
     const int c1 = tr.t0x + ix, c2 = tr.t0y + iy;
     if (c1 >= n || c2 >= m) continue;
-    const int k = S::at(ix + kLo, iy + kLo);
+    const int k = S::at(ix + LO, iy + LO);
     const int64_t i = (int64_t)c2 * n + c1;
-    xo[i] = pl[k];
-    xo[N + i] = pl[S::N + k];
+    if (BAS) {   // as the update kernel: base + x
+      xo[i] = bs[i] + pl[k];
+      xo[N + i] = bs[N + i] + pl[S::N + k];
+    } else {
+      xo[i] = pl[k];
+      xo[N + i] = pl[S::N + k];
+    }
+  }
+  if (RES) {
+    T* bco = colp(fz.bc, sj, fz.gc.nm);
+    if (!cx && !cy)
+      nodal_restrict_tile<T, BX, BY, false, false, LO, TX, TY>(pl, rl, bc, bco, st, ox, oy, tr.t0x, tr.t0y, n, m, N,
+                                                              fz.gc, p);
+    else if (!cy)
+      nodal_restrict_tile<T, BX, BY, true, false, LO, TX, TY>(pl, rl, bc, bco, st, ox, oy, tr.t0x, tr.t0y, n, m, N,
+                                                             fz.gc, p);
+    else if (!cx)
+      nodal_restrict_tile<T, BX, BY, false, true, LO, TX, TY>(pl, rl, bc, bco, st, ox, oy, tr.t0x, tr.t0y, n, m, N,
+                                                             fz.gc, p);
+    else
+      nodal_restrict_tile<T, BX, BY, true, true, LO, TX, TY>(pl, rl, bc, bco, st, ox, oy, tr.t0x, tr.t0y, n, m, N,
+                                                            fz.gc, p);
   }
 }
 
-constexpr int kTX = 32, kTY = 32;
+// Tile shapes (nodes): 0: 32 x 32, 1: 64 x 32.  FP64 edge sweeps, and FP64 nodal sweeps with
+// the residual window, use 32 x 32 only (the larger boxes exceed the static LDS limit).
+template <typename T, int TX, int TY>
+void edge_launch(View<const T> xin, View<T> xout, View<const T> b, const EdgeArgs& a, const Geo& g, const Phase* ph,
+                 const double* mu, bool backward, bool zero_start, const Launch& L) {
+  const int tx = (g.n + TX - 1) / TX, ty = (g.m + TY - 1) / TY;
+  dim3 grid((unsigned)(tx * ty), (unsigned)(L.nact * L.ncps));
+  if (backward)
+    k_edge_sweep<T, TX, TY, true><<<grid, kThreads, 0, L.st>>>(xin, xout, b, a, g, ph, mu, zero_start ? 1 : 0,
+                                                               L.slots, L.ncps, tx);
+  else
+    k_edge_sweep<T, TX, TY, false><<<grid, kThreads, 0, L.st>>>(xin, xout, b, a, g, ph, mu, zero_start ? 1 : 0,
+                                                                L.slots, L.ncps, tx);
+}
+
+template <typename T, int TX, int TY, bool BWD, int MODE>
+void nodal_go(View<const T> xin, View<T> xout, View<const T> b, const Geo& g, const Phase* ph, const NodalStencil& c,
+              bool zero_start, const SweepFuse<T>& fz, const Launch& L) {
+  const int tx = (g.n + TX - 1) / TX, ty = (g.m + TY - 1) / TY;
+  dim3 grid((unsigned)(tx * ty), (unsigned)(L.nact * L.ncps));
+  k_nodal_sweep<T, TX, TY, BWD, MODE><<<grid, kThreads, 0, L.st>>>(xin, xout, b, g, ph, c, zero_start ? 1 : 0,
+                                                                   L.slots, L.ncps, tx, fz);
+}
+
+template <typename T, int TX, int TY>
+void nodal_launch(View<const T> xin, View<T> xout, View<const T> b, const Geo& g, const Phase* ph,
+                  const NodalStencil& c, bool backward, bool zero_start, const SweepFuse<T>& fz, const Launch& L) {
+  const int mode = (fz.bc.p ? kRestrict : 0) | (fz.xc.p ? kProlong : 0) | (fz.base.p ? kBase : 0);
+  if (!backward) {
+    if constexpr (sizeof(T) == 4 || TX * TY <= 1024) {   // (the FP64 64 x 32 window is routed to 32 x 32)
+      if (mode == kRestrict) {
+        nodal_go<T, TX, TY, false, kRestrict>(xin, xout, b, g, ph, c, zero_start, fz, L);
+        return;
+      }
+    }
+    nodal_go<T, TX, TY, false, 0>(xin, xout, b, g, ph, c, zero_start, fz, L);
+    return;
+  }
+  switch (mode) {
+    case kProlong: nodal_go<T, TX, TY, true, kProlong>(xin, xout, b, g, ph, c, zero_start, fz, L); break;
+    case kBase: nodal_go<T, TX, TY, true, kBase>(xin, xout, b, g, ph, c, zero_start, fz, L); break;
+    case kProlong | kBase:
+      nodal_go<T, TX, TY, true, kProlong | kBase>(xin, xout, b, g, ph, c, zero_start, fz, L);
+      break;
+    default: nodal_go<T, TX, TY, true, 0>(xin, xout, b, g, ph, c, zero_start, fz, L); break;
+  }
+}
 
 }  // namespace
 
 template <typename T>
 void edge_sweep(View<const T> xin, View<T> xout, View<const T> b, const double* kappa64, const float* kappa32,
                 const double* sinv64, const float* sinv32, const Geo& g, const Phase* ph, const double* mu,
-                const PatchT& T4, bool backward, bool zero_start, const Launch& L) {
-  const int tx = (g.n + kTX - 1) / kTX, ty = (g.m + kTY - 1) / kTY;
-  dim3 grid((unsigned)(tx * ty), (unsigned)(L.nact * L.ncps));
-  if (grid.y == 0) return;
+                const PatchT& T4, bool backward, bool zero_start, int tile, const Launch& L) {
+  if (L.nact * L.ncps == 0) return;
   const EdgeArgs a{kappa64, kappa32, sinv64, sinv32, T4, g.s, g.mx, g.my};
-  if (backward)
-    k_edge_sweep<T, kTX, kTY, true><<<grid, kThreads, 0, L.st>>>(xin, xout, b, a, g, ph, mu, zero_start ? 1 : 0,
-                                                                 L.slots, L.ncps, tx);
-  else
-    k_edge_sweep<T, kTX, kTY, false><<<grid, kThreads, 0, L.st>>>(xin, xout, b, a, g, ph, mu, zero_start ? 1 : 0,
-                                                                  L.slots, L.ncps, tx);
+  if constexpr (sizeof(T) == 4) {
+    if (tile == 1) {
+      edge_launch<T, 64, 32>(xin, xout, b, a, g, ph, mu, backward, zero_start, L);
+      return;
+    }
+  }
+  edge_launch<T, 32, 32>(xin, xout, b, a, g, ph, mu, backward, zero_start, L);
 }
 
 template <typename T>
 void nodal_sweep(View<const T> xin, View<T> xout, View<const T> b, const Geo& g, const Phase* ph,
-                 const NodalStencil& c, bool backward, bool zero_start, const Launch& L) {
-  const int tx = (g.n + kTX - 1) / kTX, ty = (g.m + kTY - 1) / kTY;
-  dim3 grid((unsigned)(tx * ty), (unsigned)(L.nact * L.ncps));
-  if (grid.y == 0) return;
-  if (backward)
-    k_nodal_sweep<T, kTX, kTY, true><<<grid, kThreads, 0, L.st>>>(xin, xout, b, g, ph, c, zero_start ? 1 : 0,
-                                                                  L.slots, L.ncps, tx);
+                 const NodalStencil& c, bool backward, bool zero_start, int tile, const Launch& L,
+                 const SweepFuse<T>& fz) {
+  if (L.nact * L.ncps == 0) return;
+  if (tile == 1 && (sizeof(T) == 4 || !fz.bc.p))
+    nodal_launch<T, 64, 32>(xin, xout, b, g, ph, c, backward, zero_start, fz, L);
   else
-    k_nodal_sweep<T, kTX, kTY, false><<<grid, kThreads, 0, L.st>>>(xin, xout, b, g, ph, c, zero_start ? 1 : 0,
-                                                                   L.slots, L.ncps, tx);
+    nodal_launch<T, 32, 32>(xin, xout, b, g, ph, c, backward, zero_start, fz, L);
 }
 
-template void edge_sweep<double>(View<const double>, View<double>, View<const double>, const double*, const float*, const double*, const float*, const Geo&, const Phase*, const double*, const PatchT&, bool, bool, const Launch&);
-template void edge_sweep<float>(View<const float>, View<float>, View<const float>, const double*, const float*, const double*, const float*, const Geo&, const Phase*, const double*, const PatchT&, bool, bool, const Launch&);
-template void nodal_sweep<double>(View<const double>, View<double>, View<const double>, const Geo&, const Phase*, const NodalStencil&, bool, bool, const Launch&);
-template void nodal_sweep<float>(View<const float>, View<float>, View<const float>, const Geo&, const Phase*, const NodalStencil&, bool, bool, const Launch&);
+template void edge_sweep<double>(View<const double>, View<double>, View<const double>, const double*, const float*, const double*, const float*, const Geo&, const Phase*, const double*, const PatchT&, bool, bool, int, const Launch&);
+template void edge_sweep<float>(View<const float>, View<float>, View<const float>, const double*, const float*, const double*, const float*, const Geo&, const Phase*, const double*, const PatchT&, bool, bool, int, const Launch&);
+template void nodal_sweep<double>(View<const double>, View<double>, View<const double>, const Geo&, const Phase*, const NodalStencil&, bool, bool, int, const Launch&, const SweepFuse<double>&);
+template void nodal_sweep<float>(View<const float>, View<float>, View<const float>, const Geo&, const Phase*, const NodalStencil&, bool, bool, int, const Launch&, const SweepFuse<float>&);
 
 }  // namespace bl

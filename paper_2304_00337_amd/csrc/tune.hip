@@ -128,8 +128,16 @@ Choice tune_t(bl_solver* s, hipEvent_t e0, hipEvent_t e1) {
 }  // namespace
 
 int engine_autotune(bl_solver* s) {
-  // measurement and test hook: BL_SMOOTH_SHAPE="threads,columns,xcd" and BL_RR_TILE=48|64
+  // measurement and test hooks: BL_SWEEP_TILE="edge,nodal" (0 = 32 x 32, 1 = 64 x 32 tiles),
+  // BL_SMOOTH_SHAPE="threads,columns,xcd" and BL_RR_TILE=48|64
   // fix the shapes instead of timing them
+  if (const char* e = std::getenv("BL_SWEEP_TILE")) {   // "edge,nodal" tile shape indices
+    int a = 0, b = 0;
+    if (std::sscanf(e, "%d,%d", &a, &b) == 2 && a >= 0 && a < 2 && b >= 0 && b < 2) {
+      s->tune_sweep[0] = a;
+      s->tune_sweep[1] = b;
+    }
+  }
   const char* fs = std::getenv("BL_SMOOTH_SHAPE");
   const char* ft = std::getenv("BL_RR_TILE");
   if (fs || ft) {

@@ -214,10 +214,11 @@ def test_rayleigh_ritz_products(case):
 @pytest.mark.parametrize("fp32", [False, True])
 def test_fused_and_tiled_cycles_equal_per_level_cycles(n, levels, fp32):
     """The coarse levels of a V-cycle run fused in one workgroup per column when they fit
-    LDS, and each smoothing sweep of the other levels runs as one launch over LDS tiles with
-    halos; both perform the per-level, per-colour operations in the same order, so every
-    combination gives the same bits, for the edge and the nodal cycle and through a whole
-    solve (80 x 48: tiles with ragged edges)."""
+    LDS, each smoothing sweep of the other levels runs as one launch over LDS tiles with
+    halos, and the transfers may ride in the sweeps; all perform the per-level, per-colour
+    operations in the same order, so every combination gives the same bits, for the edge
+    and the nodal cycle, the projection (two nodal cycles) and through a whole solve
+    (80 x 48: tiles with ragged edges)."""
     import torch  # noqa: F401
     from paper_2304_00337_amd import Solver
     rng = np.random.default_rng(n)
@@ -226,7 +227,7 @@ def test_fused_and_tiled_cycles_equal_per_level_cycles(n, levels, fp32):
     k = (0.7, -1.3)
     kw = dict(nev=4, nthrow=2, mu=MU, levels=levels, coarsest_min=3, max_iter=40,
               precision="mixed" if fp32 else "fp64")
-    variants = [(0, 0), (1, 0), (0, 1), (1, 1)]
+    variants = [(0, 0), (1, 0), (0, 1), (1, 1), (0, 2), (1, 2)]
     sv = [Solver(n, m, 1.0, 1.0, eps, coarse_fuse=f, tiled_sweeps=t, **kw) for f, t in variants]
     infos = [s.info() for s in sv]
     assert infos[0]["fused_edge_level"] == -1 and infos[0]["fused_nodal_level"] == -1
@@ -240,13 +241,15 @@ def test_fused_and_tiled_cycles_equal_per_level_cycles(n, levels, fp32):
     ref = None
     for s, var in zip(sv, variants):
         got = [_gpu(s, "EDGE_VCYCLE", B, out_rows=2 * n * m, fp32=fp32),
-               _gpu(s, "NODAL_VCYCLE", Bn, out_rows=n * m, fp32=fp32)]
+               _gpu(s, "NODAL_VCYCLE", Bn, out_rows=n * m, fp32=fp32),
+               _gpu(s, "PROJECT", B, out_rows=2 * n * m)]
         r = s.solve_k(*k, start=E0, allow_noconv=True)
         if ref is None:
             ref = (got, r)
             continue
         assert np.array_equal(got[0], ref[0][0]), ("edge V-cycle", var)
         assert np.array_equal(got[1], ref[0][1]), ("nodal V-cycle", var)
+        assert np.array_equal(got[2], ref[0][2]), ("projection (two nodal cycles)", var)
         assert np.array_equal(r["evals"], ref[1]["evals"]) and r["iterations"] == ref[1]["iterations"], var
 
 
@@ -264,11 +267,12 @@ def test_tiled_sweeps_with_many_workgroups(fp32):
     B = _rand(rng, 2 * n * n, 24)
     Bn = _rand(rng, n * n, 24)
     outs = []
-    for tiled in (0, 1):
+    for tiled in (0, 1, 2):
         s = Solver(n, n, 1.0, 1.0, eps, tiled_sweeps=tiled, **kw)
         s.set_k(0.9, 0.4)
         outs.append([_gpu(s, "EDGE_VCYCLE", B, out_rows=2 * n * n, fp32=fp32) for _ in range(2)] +
                     [_gpu(s, "NODAL_VCYCLE", Bn, out_rows=n * n, fp32=fp32) for _ in range(2)])
         s.close()
-    for a, b in zip(outs[0], outs[1]):
-        assert np.array_equal(a, b)
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
