@@ -88,11 +88,12 @@ typedef struct bl_opts {
                            to the per-level launches, 0 = per-level launches (1)           */
   int32_t tiled_sweeps; /* 1 = each smoothing sweep of a level above the fused ones is one
                            launch over LDS tiles with halos (all four colours); 2 = as 1, and
-                           the nodal cycles' residual, restriction, prolongation and update
-                           ride in the sweeps (the last pre-sweep writes the restricted
-                           residual, the first post-sweep reads the prolongated correction);
-                           all bit-identical to one launch per colour, 0 = one launch per
-                           colour (2)                                                       */
+                           the residual, restriction and prolongation of the nodal cycles
+                           and of the FP32 edge cycles ride in the sweeps (the last pre-sweep
+                           writes the restricted residual, the first post-sweep reads the
+                           prolongated correction; a nodal solve's update rides in its last
+                           sweep); all bit-identical to one launch per colour, 0 = one launch
+                           per colour (2)                                                   */
   double tol;           /* stop when ||A e_i - lambda_i M e_i||_2 / (lambda_i ||M e_i||_2)
                            <= tol for the first nev vectors (1e-8)                         */
   double mu;            /* regularisation of the preconditioned A + mu M (Section 5);

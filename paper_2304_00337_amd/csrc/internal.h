@@ -108,7 +108,11 @@ struct SweepFuse {
 template <typename T>
 void edge_sweep(View<const T> xin, View<T> xout, View<const T> b, const double* kappa64, const float* kappa32,
                 const double* sinv64, const float* sinv32, const Geo& g, const Phase* ph, const double* mu,
-                const PatchT& T4, bool backward, bool zero_start, int tile, const Launch& L);
+                const PatchT& T4, bool backward, bool zero_start, int tile, const Launch& L,
+                const SweepFuse<T>& fz = SweepFuse<T>{});
+// Whether edge sweeps of this element size can restrict (SweepFuse::bc): FP32 only (the
+// FP64 residual window exceeds the static LDS of a workgroup).
+bool edge_sweep_restricts(size_t elem);
 template <typename T>
 void nodal_sweep(View<const T> xin, View<T> xout, View<const T> b, const Geo& g, const Phase* ph,
                  const NodalStencil& c, bool backward, bool zero_start, int tile, const Launch& L,

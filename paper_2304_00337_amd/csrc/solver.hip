@@ -241,9 +241,12 @@ void timing_end(bl_solver* s, int l, int ncols, double bytes) {
 // sweep reads b (and x unless it starts from zero) and writes x once; a colour pass reads x
 // and half of b and writes half of x.  Per slot: the cell coefficients and the patch
 // inverses (6 per node) once per sweep, a quarter of the inverses per colour pass.
-double smooth_bytes(const Geo& g, size_t elem, bool sweep, bool zero_start, int ncols, int nact) {
+// extra: further vectors per column, in units of one fine edge vector (a folded restriction
+// writes and a folded prolongation reads a coarse vector, a quarter of one)
+double smooth_bytes(const Geo& g, size_t elem, bool sweep, bool zero_start, int ncols, int nact,
+                    double extra = 0.0) {
   const double vec = 2.0 * (double)g.ne * (double)elem;
-  if (sweep) return ncols * vec * (zero_start ? 2.0 : 3.0) + nact * (double)g.nm * elem * 7.0;
+  if (sweep) return ncols * vec * ((zero_start ? 2.0 : 3.0) + extra) + nact * (double)g.nm * elem * 7.0;
   return ncols * vec * 2.0 + nact * (double)g.nm * elem * (1.0 + 6.0 / 4.0);
 }
 void timing_collect(bl_solver* s) {
@@ -315,6 +318,44 @@ void vcycle_edge(bl_solver* s, int l, View<const T> b, View<T> x, const Launch& 
   const int ncols = L.nact * L.ncps;
   const int npre = s->opts.nu_pre, npost = s->opts.nu_post;
   View<T> r = view(static_cast<T*>(lv.er[pr]), lv.ecap[pr]);
+  if (s->opts.tiled_sweeps == 2 && npre > 0 && npost > 0 && edge_sweep_restricts(sizeof(T))) {
+    // transfers folded into the sweeps, as in the nodal cycle (x and r alternate as sweep
+    // buffers; the pre-smoothed iterate lands in E so that the last post-sweep writes x)
+    Level& C = s->lv[l + 1];
+    View<T> bc = view(static_cast<T*>(C.eb[pr]), C.ecap[pr]);
+    View<T> xc = view(static_cast<T*>(C.ex[pr]), C.ecap[pr]);
+    const View<T> E = (npost % 2 == 1) ? r : x, F = (npost % 2 == 1) ? x : r;
+    View<T> prev = E;
+    for (int it = 0; it < npre; ++it) {
+      const View<T> dst = ((npre - 1 - it) % 2 == 0) ? E : F;
+      SweepFuse<T> fz;
+      if (it == npre - 1) {
+        fz.bc = bc;
+        fz.gc = C.g;
+      }
+      timing_begin(s, l);
+      edge_sweep<T>(cv(prev), dst, b, lv.kappa64, lv.kappa32, lv.sinv64, lv.sinv32, lv.g, s->ph_d, s->mu_d, lv.T4,
+                    false, it == 0, s->tune_sweep[0], L, fz);
+      timing_end(s, l, ncols, smooth_bytes(lv.g, sizeof(T), true, it == 0, ncols, L.nact, fz.bc.p ? 0.25 : 0.0));
+      prev = dst;
+    }
+    vcycle_edge<T>(s, l + 1, cv(bc), xc, L);
+    for (int it = 0; it < npost; ++it) {
+      const View<T> dst = ((npost - 1 - it) % 2 == 0) ? x : r;
+      SweepFuse<T> fz;
+      if (it == 0) {
+        fz.xc = cv(xc);
+        fz.gc = C.g;
+      }
+      timing_begin(s, l);
+      edge_sweep<T>(cv(prev), dst, b, lv.kappa64, lv.kappa32, lv.sinv64, lv.sinv32, lv.g, s->ph_d, s->mu_d, lv.T4,
+                    true, false, s->tune_sweep[0], L, fz);
+      timing_end(s, l, ncols, smooth_bytes(lv.g, sizeof(T), true, false, ncols, L.nact, it == 0 ? 0.25 : 0.0));
+      prev = dst;
+    }
+    s->launches += npre + npost;
+    return;
+  }
   int nl_launch = 0;
   if (!tiled || npre == 0) {
     zero_cols<T>(x, lv.g.ne, L);

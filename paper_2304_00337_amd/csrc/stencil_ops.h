@@ -10,36 +10,6 @@
 
 namespace bl {
 
-// (A x)_d and (M x)_d at edge d; kapf(i) gives kappa of cell i in T.
-template <typename TI, typename T, typename KF>
-__device__ __forceinline__ void edge_AM(const TI* xc, int64_t N, int n, int m, int64_t nm, int64_t d,
-                                        const KF& kapf, T s, T mx, T my, const Ph<T>& p, Cx<T>& Au,
-                                        Cx<T>& Mu) {
-  const T two3 = (T)(2.0 / 3.0), one6 = (T)(1.0 / 6.0);
-  if (d < nm) {
-    const int j1 = (int)(d % n), j2 = (int)(d / n);
-    const Cx<T> wlo = cell_curl<TI, T>(xc, N, n, m, nm, j1, j2 - 1, p);
-    const Cx<T> whi = cell_curl<TI, T>(xc, N, n, m, nm, j1, j2, p);
-    const T klo = kapf((int64_t)wrapi(j2 - 1, m) * n + j1);
-    const T khi = kapf((int64_t)j2 * n + j1);
-    Au = s * ((klo * wlo) - (khi * whi));
-    const Cx<T> u0 = {(T)xc[d], (T)xc[N + d]};
-    Mu = mx * ((two3 * u0) + one6 * (fetch<TI, T>(xc, N, n, m, 0, j1, j2 + 1, p) +
-                                     fetch<TI, T>(xc, N, n, m, 0, j1, j2 - 1, p)));
-  } else {
-    const int64_t e = d - nm;
-    const int j1 = (int)(e % n), j2 = (int)(e / n);
-    const Cx<T> wr = cell_curl<TI, T>(xc, N, n, m, nm, j1, j2, p);
-    const Cx<T> wl = cell_curl<TI, T>(xc, N, n, m, nm, j1 - 1, j2, p);
-    const T kr = kapf((int64_t)j2 * n + j1);
-    const T kl = kapf((int64_t)j2 * n + wrapi(j1 - 1, n));
-    Au = s * ((kr * wr) - (kl * wl));
-    const Cx<T> u0 = {(T)xc[d], (T)xc[N + d]};
-    Mu = my * ((two3 * u0) + one6 * (fetch<TI, T>(xc, N, n, m, nm, j1 + 1, j2, p) +
-                                     fetch<TI, T>(xc, N, n, m, nm, j1 - 1, j2, p)));
-  }
-}
-
 // Edge values around a patch node (p1, p2), given in canonical indices, read and updated in
 // Bloch-extended coordinates: get(c, d1, d2) is component c (0 = x-edges, 1 = y-edges) at
 // (p1 + d1, p2 + d2) times the phase of the crossing, add(c, d1, d2, v) adds v (given in
@@ -58,6 +28,45 @@ struct ColumnEdges {
     add_ext<T, T>(xc, N, n, m, c ? nm : 0, p1 + d1, p2 + d2, v, p);
   }
 };
+
+// (A x) and (M x) at the edge of component c (0: x-edge, 1: y-edge) owned by the accessor's
+// node, from the curls of its two cells and its two parallel neighbours.  ka, kb: kappa of
+// the cells below and above an x-edge, right and left of a y-edge; mm: the edge's mass scale.
+template <typename T, typename XA>
+__device__ __forceinline__ void edge_AM_acc(const XA& X, int c, T ka, T kb, T s, T mm, Cx<T>& Au, Cx<T>& Mu) {
+  const T two3 = (T)(2.0 / 3.0), one6 = (T)(1.0 / 6.0);
+  if (c == 0) {
+    const Cx<T> wlo = X.get(0, 0, 0) - X.get(0, 0, -1) + X.get(1, 0, -1) - X.get(1, 1, -1);
+    const Cx<T> whi = X.get(0, 0, 1) - X.get(0, 0, 0) + X.get(1, 0, 0) - X.get(1, 1, 0);
+    Au = s * ((ka * wlo) - (kb * whi));
+    const Cx<T> u0 = X.get(0, 0, 0);
+    Mu = mm * ((two3 * u0) + one6 * (X.get(0, 0, 1) + X.get(0, 0, -1)));
+  } else {
+    const Cx<T> wr = X.get(0, 0, 1) - X.get(0, 0, 0) + X.get(1, 0, 0) - X.get(1, 1, 0);
+    const Cx<T> wl = X.get(0, -1, 1) - X.get(0, -1, 0) + X.get(1, -1, 0) - X.get(1, 0, 0);
+    Au = s * ((ka * wr) - (kb * wl));
+    const Cx<T> u0 = X.get(1, 0, 0);
+    Mu = mm * ((two3 * u0) + one6 * (X.get(1, 1, 0) + X.get(1, -1, 0)));
+  }
+}
+
+// (A x)_d and (M x)_d at edge d of a column in memory; kapf(i) gives kappa of cell i in T.
+template <typename TI, typename T, typename KF>
+__device__ __forceinline__ void edge_AM(const TI* xc, int64_t N, int n, int m, int64_t nm, int64_t d,
+                                        const KF& kapf, T s, T mx, T my, const Ph<T>& p, Cx<T>& Au,
+                                        Cx<T>& Mu) {
+  static_assert(sizeof(TI) == sizeof(T), "edge_AM reads the column in its compute type");
+  if (d < nm) {
+    const int j1 = (int)(d % n), j2 = (int)(d / n);
+    const ColumnEdges<T, const TI> X{xc, N, nm, n, m, j1, j2, p};
+    edge_AM_acc<T>(X, 0, kapf((int64_t)wrapi(j2 - 1, m) * n + j1), kapf((int64_t)j2 * n + j1), s, mx, Au, Mu);
+  } else {
+    const int64_t e = d - nm;
+    const int j1 = (int)(e % n), j2 = (int)(e / n);
+    const ColumnEdges<T, const TI> X{xc, N, nm, n, m, j1, j2, p};
+    edge_AM_acc<T>(X, 1, kapf((int64_t)j2 * n + j1), kapf((int64_t)j2 * n + wrapi(j1 - 1, n)), s, my, Au, Mu);
+  }
+}
 
 // Explicit fused multiply-adds (contraction is otherwise off), so that every kernel sharing
 // these bodies rounds the same way.
@@ -133,45 +142,54 @@ __device__ __forceinline__ void edge_patch_gs(T* xc, const T* bc, int64_t N, int
   patch_update<T>(X, B, kne, knw, ksw, kse, w, s, mmx, mmy);
 }
 
-// Coarse edge d of (Pr^* r): the adjoint of the edge embedding (1/2 collinear, 1/4 parallel).
+// Restriction (adjoint of the edge embedding: 1/2 collinear, 1/4 parallel) at the coarse
+// edge of component c owned by a coarse node, from the fine values around its fine node 2J
+// given by an accessor R (R.get(c, d1, d2) as fetch()).
+template <typename T, typename RA>
+__device__ __forceinline__ Cx<T> edge_restrict_acc(const RA& R, int c) {
+  const T h = (T)0.5, q = (T)0.25;
+  if (c == 0)
+    return h * (R.get(0, 0, 0) + R.get(0, 1, 0)) +
+           q * (R.get(0, 0, 1) + R.get(0, 1, 1) + R.get(0, 0, -1) + R.get(0, 1, -1));
+  return h * (R.get(1, 0, 0) + R.get(1, 0, 1)) +
+         q * (R.get(1, 1, 0) + R.get(1, 1, 1) + R.get(1, -1, 0) + R.get(1, -1, 1));
+}
+
+// Coarse edge d of (Pr^* r) for the fine column r.
 template <typename T>
 __device__ __forceinline__ Cx<T> edge_restrict_at(const T* r, const Geo& gf, const Geo& gc, int64_t d,
                                                   const Ph<T>& p) {
-  const int nf = gf.n, mf = gf.m;
-  const int64_t Nf = gf.ne, nmf = gf.nm;
-  const T h = (T)0.5, q = (T)0.25;
-  if (d < gc.nm) {
-    const int J1 = (int)(d % gc.n), J2 = (int)(d / gc.n);
-    const int f1 = 2 * J1, f2 = 2 * J2;
-    return h * (fetch<T, T>(r, Nf, nf, mf, 0, f1, f2, p) + fetch<T, T>(r, Nf, nf, mf, 0, f1 + 1, f2, p)) +
-           q * (fetch<T, T>(r, Nf, nf, mf, 0, f1, f2 + 1, p) + fetch<T, T>(r, Nf, nf, mf, 0, f1 + 1, f2 + 1, p) +
-                fetch<T, T>(r, Nf, nf, mf, 0, f1, f2 - 1, p) + fetch<T, T>(r, Nf, nf, mf, 0, f1 + 1, f2 - 1, p));
-  }
-  const int64_t e = d - gc.nm;
+  const int c = d < gc.nm ? 0 : 1;
+  const int64_t e = c ? d - gc.nm : d;
   const int J1 = (int)(e % gc.n), J2 = (int)(e / gc.n);
-  const int f1 = 2 * J1, f2 = 2 * J2;
-  return h * (fetch<T, T>(r, Nf, nf, mf, nmf, f1, f2, p) + fetch<T, T>(r, Nf, nf, mf, nmf, f1, f2 + 1, p)) +
-         q * (fetch<T, T>(r, Nf, nf, mf, nmf, f1 + 1, f2, p) + fetch<T, T>(r, Nf, nf, mf, nmf, f1 + 1, f2 + 1, p) +
-              fetch<T, T>(r, Nf, nf, mf, nmf, f1 - 1, f2, p) + fetch<T, T>(r, Nf, nf, mf, nmf, f1 - 1, f2 + 1, p));
+  const ColumnEdges<T, const T> R{r, gf.ne, gf.nm, gf.n, gf.m, 2 * J1, 2 * J2, p};
+  return edge_restrict_acc<T>(R, c);
 }
 
-// Fine edge d of (Pr x_c): the embedding of the coarse Nedelec function.
+// Fine edge of component c owned by fine node (f1, f2) of (Pr x_c): the embedding of the
+// coarse Nedelec function.
 template <typename T>
-__device__ __forceinline__ Cx<T> edge_prolong_at(const T* c, const Geo& gc, const Geo& gf, int64_t d,
+__device__ __forceinline__ Cx<T> edge_prolong_xy(const T* c, const Geo& gc, int comp, int f1, int f2,
                                                  const Ph<T>& p) {
   const int nc = gc.n, mc = gc.m;
   const int64_t Nc = gc.ne, nmc = gc.nm;
-  if (d < gf.nm) {
-    const int f1 = (int)(d % gf.n), f2 = (int)(d / gf.n);
+  if (comp == 0) {
     const int J1 = f1 >> 1;
     if ((f2 & 1) == 0) return (T)0.5 * fetch<T, T>(c, Nc, nc, mc, 0, J1, f2 >> 1, p);
     return (T)0.25 * (fetch<T, T>(c, Nc, nc, mc, 0, J1, f2 >> 1, p) + fetch<T, T>(c, Nc, nc, mc, 0, J1, (f2 >> 1) + 1, p));
   }
-  const int64_t e = d - gf.nm;
-  const int f1 = (int)(e % gf.n), f2 = (int)(e / gf.n);
   const int J2 = f2 >> 1;
   if ((f1 & 1) == 0) return (T)0.5 * fetch<T, T>(c, Nc, nc, mc, nmc, f1 >> 1, J2, p);
   return (T)0.25 * (fetch<T, T>(c, Nc, nc, mc, nmc, f1 >> 1, J2, p) + fetch<T, T>(c, Nc, nc, mc, nmc, (f1 >> 1) + 1, J2, p));
+}
+
+// Fine edge d of (Pr x_c).
+template <typename T>
+__device__ __forceinline__ Cx<T> edge_prolong_at(const T* c, const Geo& gc, const Geo& gf, int64_t d,
+                                                 const Ph<T>& p) {
+  const int comp = d < gf.nm ? 0 : 1;
+  const int64_t e = comp ? d - gf.nm : d;
+  return edge_prolong_xy<T>(c, gc, comp, (int)(e % gf.n), (int)(e / gf.n), p);
 }
 
 // Nodal values around node (p1, p2) in Bloch-extended coordinates (as ColumnEdges, one

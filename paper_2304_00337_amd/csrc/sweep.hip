@@ -37,6 +37,16 @@ constexpr int kHiE = 5;   // halo above / right, edge sweeps
 constexpr int kHiN = 4;   // halo above / right, nodal sweeps
 constexpr int kThreads = 256;
 
+// MODE bits of a sweep with level transfers folded in: kRestrict (forward sweeps) also forms
+// the residual of the result and restricts it to the coarse right-hand side; kProlong starts
+// from xin + Pr xc; kBase writes base + result.  The residual at the fine nodes that the
+// restriction reads (one node below/left of the tile to its last row/column) needs the swept
+// iterate two nodes below/left and one node above/right of the tile: the halos grow to kLoR
+// below (nodal and edge) and kHiER above (edge; the nodal forward sweep's kHiN suffices).
+constexpr int kRestrict = 1, kProlong = 2, kBase = 4;
+constexpr int kLoR = 6;
+constexpr int kHiER = 6;
+
 __device__ __forceinline__ int wrapm(int v, int n) {
   const int r = v % n;
   return r < 0 ? r + n : r;
@@ -212,18 +222,97 @@ __device__ __forceinline__ void edge_passes(T* pl, const T* bc, const EdgeArgs& 
   __syncthreads();
 }
 
-template <typename T, int TX, int TY, bool BWD>
+// Residual b - (A + mu M) x at both edges owned by the box positions of parity (PX, PY)
+// inside the residual window (as the residual kernel computes them), into rl (row-major
+// window; planes x re, x im, y re, y im).
+template <typename T, int BX, int BY, int PX, int PY, bool CX, bool CY, int LO, int TX, int TY>
+__device__ __forceinline__ void edge_resid_pass(T* pl, T* rl, const T* bc, const EdgeArgs& a, int slot, int ox,
+                                                int oy, int n, int m, int64_t N, int64_t nm, T mu, const Ph<T>& p) {
+  constexpr int R0 = LO - 1, RW = TX + 1, RH = TY + 1, RP = RW * RH;
+  constexpr int I0 = (R0 - PX + 1) / 2, I1 = (LO + TX - 1 - PX) / 2;
+  constexpr int J0 = (R0 - PY + 1) / 2, J1 = (LO + TY - 1 - PY) / 2;
+  constexpr int CNX = I1 - I0 + 1, CNY = J1 - J0 + 1;
+  const double* k64 = a.k64 + (int64_t)slot * nm;
+  const float* k32 = a.k32 + (int64_t)slot * nm;
+  const T s = (T)a.s, mx = (T)a.mx, my = (T)a.my;
+  for (int t = threadIdx.x; t < CNX * CNY; t += kThreads) {
+    const int i = I0 + t % CNX, j = J0 + t / CNX;
+    const int bx = 2 * i + PX, by = 2 * j + PY;
+    const int p1 = CX ? wrapm(ox + bx, n) : ox + bx;
+    const int p2 = CY ? wrapm(oy + by, m) : oy + by;
+    const int64_t k = (int64_t)p2 * n + p1;
+    const TileEdges<T, BX, BY, PX, PY, CX, CY> X{pl, i, j, Seam<CX, CY>(p1, p2, n, m), p};
+    const T kh = kap<T>(k64, k32, k);
+    const int q = (by - R0) * RW + (bx - R0);
+    Cx<T> Au, Mu;
+    edge_AM_acc<T>(X, 0, kap<T>(k64, k32, (int64_t)wrapi(p2 - 1, m) * n + p1), kh, s, mx, Au, Mu);
+    const Cx<T> rx = Cx<T>{bc[k], bc[N + k]} - (Au + (mu * Mu));
+    edge_AM_acc<T>(X, 1, kh, kap<T>(k64, k32, (int64_t)p2 * n + wrapi(p1 - 1, n)), s, my, Au, Mu);
+    const Cx<T> ry = Cx<T>{bc[nm + k], bc[N + nm + k]} - (Au + (mu * Mu));
+    rl[q] = rx.re;
+    rl[RP + q] = rx.im;
+    rl[2 * RP + q] = ry.re;
+    rl[3 * RP + q] = ry.im;
+  }
+}
+
+// Residual window values of component c around window position (x, y) (as fetch()).
+template <typename T, int RW, int RH, bool CX, bool CY>
+struct WindowEdges {
+  const T* rl;
+  int x, y;
+  Seam<CX, CY> sm;
+  Ph<T> p;
+  __device__ __forceinline__ Cx<T> get(int c, int d1, int d2) const {
+    const int q = c * 2 * RW * RH + (y + d2) * RW + x + d1;
+    return phased<CX, CY, T>(Cx<T>{rl[q], rl[RW * RH + q]}, d1, d2, sm, p);
+  }
+};
+
+// Residual of the swept tile and its restriction to the edges of the tile's coarse nodes.
+template <typename T, int BX, int BY, bool CX, bool CY, int LO, int TX, int TY>
+__device__ __forceinline__ void edge_restrict_tile(T* pl, T* rl, const T* bc, T* bco, const EdgeArgs& a,
+                                                   int slot, int ox, int oy, int t0x, int t0y, int n, int m,
+                                                   int64_t N, int64_t nm, T mu, const Geo& gc, const Ph<T>& p) {
+  edge_resid_pass<T, BX, BY, 0, 0, CX, CY, LO, TX, TY>(pl, rl, bc, a, slot, ox, oy, n, m, N, nm, mu, p);
+  edge_resid_pass<T, BX, BY, 1, 0, CX, CY, LO, TX, TY>(pl, rl, bc, a, slot, ox, oy, n, m, N, nm, mu, p);
+  edge_resid_pass<T, BX, BY, 0, 1, CX, CY, LO, TX, TY>(pl, rl, bc, a, slot, ox, oy, n, m, N, nm, mu, p);
+  edge_resid_pass<T, BX, BY, 1, 1, CX, CY, LO, TX, TY>(pl, rl, bc, a, slot, ox, oy, n, m, N, nm, mu, p);
+  __syncthreads();
+  constexpr int HX = TX / 2, HY = TY / 2;
+  for (int t = threadIdx.x; t < HX * HY; t += kThreads) {
+    const int jx = t % HX, jy = t / HX;
+    const int f1 = t0x + 2 * jx, f2 = t0y + 2 * jy;
+    if (f1 >= n || f2 >= m) continue;
+    const WindowEdges<T, TX + 1, TY + 1, CX, CY> R{rl, 2 * jx + 1, 2 * jy + 1, Seam<CX, CY>(f1, f2, n, m), p};
+    const int64_t J = (int64_t)(f2 >> 1) * gc.n + (f1 >> 1);
+    const Cx<T> vx = edge_restrict_acc<T>(R, 0);
+    const Cx<T> vy = edge_restrict_acc<T>(R, 1);
+    bco[J] = vx.re;
+    bco[gc.ne + J] = vx.im;
+    bco[gc.nm + J] = vy.re;
+    bco[gc.ne + gc.nm + J] = vy.im;
+  }
+}
+
+template <typename T, int TX, int TY, bool BWD, int MODE>
 __global__ __launch_bounds__(kThreads) void k_edge_sweep(View<const T> xin, View<T> xout, View<const T> bv, EdgeArgs a,
                                                          Geo g, const Phase* __restrict__ phs,
                                                          const double* __restrict__ mus, int zero_start,
-                                                         const int* __restrict__ slots, int ncps, int tiles_x) {
-  constexpr int BX = TX + kLo + kHiE, BY = TY + kLo + kHiE;
+                                                         const int* __restrict__ slots, int ncps, int tiles_x,
+                                                         SweepFuse<T> fz) {
+  static_assert(!((MODE & kRestrict) && BWD), "the residual window halo is sized for forward sweeps");
+  static_assert(!(MODE & kBase), "edge sweeps have no base update");
+  constexpr bool RES = (MODE & kRestrict) != 0, PRO = (MODE & kProlong) != 0;
+  constexpr int LO = RES ? kLoR : kLo;
+  constexpr int BX = TX + LO + (RES ? kHiER : kHiE), BY = TY + LO + (RES ? kHiER : kHiE);
   using S = Split<BX, BY>;
   __shared__ T pl[4 * S::N];
+  __shared__ T rl[RES ? 4 * (TX + 1) * (TY + 1) : 1];
   const TileRef tr = tile_ref(slots, ncps, tiles_x, TX, TY);
   const int n = g.n, m = g.m, tid = threadIdx.x;
   const int64_t N = g.ne, nm = g.nm;
-  const int ox = tr.t0x - kLo, oy = tr.t0y - kLo;   // canonical node of box position 0 (unwrapped)
+  const int ox = tr.t0x - LO, oy = tr.t0y - LO;   // canonical node of box position 0 (unwrapped)
   const bool cx = !(ox >= 0 && ox + BX <= n), cy = !(oy >= 0 && oy + BY <= m);
   const SJ sj{tr.slot, tr.j};
   T* xo = colp(xout, sj, N);
@@ -233,15 +322,25 @@ __global__ __launch_bounds__(kThreads) void k_edge_sweep(View<const T> xin, View
     for (int e = tid; e < 4 * S::N; e += kThreads) pl[e] = (T)0;
   } else {
     const T* xc = colp(xin, sj, N);
+    const T* cc = PRO ? colp(fz.xc, sj, fz.gc.ne) : nullptr;
     for (int e = tid; e < BX * BY; e += kThreads) {
       const int bx = e % BX, by = e / BX;
       const int c1 = cx ? wrapm(ox + bx, n) : ox + bx, c2 = cy ? wrapm(oy + by, m) : oy + by;
       const int64_t i = (int64_t)c2 * n + c1;
       const int k = S::at(bx, by);
-      pl[k] = xc[i];
-      pl[S::N + k] = xc[N + i];
-      pl[2 * S::N + k] = xc[nm + i];
-      pl[3 * S::N + k] = xc[N + nm + i];
+      if constexpr (PRO) {   // as the prolongation kernel: x + Pr xc
+        const Cx<T> vx = edge_prolong_xy<T>(cc, fz.gc, 0, c1, c2, p);
+        const Cx<T> vy = edge_prolong_xy<T>(cc, fz.gc, 1, c1, c2, p);
+        pl[k] = xc[i] + vx.re;
+        pl[S::N + k] = xc[N + i] + vx.im;
+        pl[2 * S::N + k] = xc[nm + i] + vy.re;
+        pl[3 * S::N + k] = xc[N + nm + i] + vy.im;
+      } else {
+        pl[k] = xc[i];
+        pl[S::N + k] = xc[N + i];
+        pl[2 * S::N + k] = xc[nm + i];
+        pl[3 * S::N + k] = xc[N + nm + i];
+      }
     }
   }
   __syncthreads();
@@ -254,12 +353,27 @@ __global__ __launch_bounds__(kThreads) void k_edge_sweep(View<const T> xin, View
     const int ix = e % TX, iy = e / TX;
     const int c1 = tr.t0x + ix, c2 = tr.t0y + iy;
     if (c1 >= n || c2 >= m) continue;
-    const int k = S::at(ix + kLo, iy + kLo);
+    const int k = S::at(ix + LO, iy + LO);
     const int64_t i = (int64_t)c2 * n + c1;
     xo[i] = pl[k];
     xo[N + i] = pl[S::N + k];
     xo[nm + i] = pl[2 * S::N + k];
     xo[N + nm + i] = pl[3 * S::N + k];
+  }
+  if constexpr (RES) {
+    T* bco = colp(fz.bc, sj, fz.gc.ne);
+    if (!cx && !cy)
+      edge_restrict_tile<T, BX, BY, false, false, LO, TX, TY>(pl, rl, bc, bco, a, tr.slot, ox, oy, tr.t0x, tr.t0y, n,
+                                                             m, N, nm, mu, fz.gc, p);
+    else if (!cy)
+      edge_restrict_tile<T, BX, BY, true, false, LO, TX, TY>(pl, rl, bc, bco, a, tr.slot, ox, oy, tr.t0x, tr.t0y, n,
+                                                            m, N, nm, mu, fz.gc, p);
+    else if (!cx)
+      edge_restrict_tile<T, BX, BY, false, true, LO, TX, TY>(pl, rl, bc, bco, a, tr.slot, ox, oy, tr.t0x, tr.t0y, n,
+                                                            m, N, nm, mu, fz.gc, p);
+    else
+      edge_restrict_tile<T, BX, BY, true, true, LO, TX, TY>(pl, rl, bc, bco, a, tr.slot, ox, oy, tr.t0x, tr.t0y, n,
+                                                           m, N, nm, mu, fz.gc, p);
   }
 }
 
@@ -360,12 +474,6 @@ __device__ __forceinline__ void nodal_restrict_tile(const T* pl, T* rl, const T*
   }
 }
 
-// MODE bits of a sweep with level transfers folded in: kRestrict (forward sweeps) also forms
-// the residual of the result and restricts it to the coarse right-hand side; kProlong starts
-// from xin + Pr xc; kBase writes base + result.
-constexpr int kRestrict = 1, kProlong = 2, kBase = 4;
-constexpr int kLoR = 6;   // low halo when the residual window is needed (even)
-
 template <typename T, int TX, int TY, bool BWD, int MODE>
 __global__ __launch_bounds__(kThreads) void k_nodal_sweep(View<const T> xin, View<T> xout, View<const T> bv, Geo g,
                                                           const Phase* __restrict__ phs, NodalStencil st,
@@ -397,7 +505,7 @@ __global__ __launch_bounds__(kThreads) void k_nodal_sweep(View<const T> xin, Vie
       const int c1 = cx ? wrapm(ox + bx, n) : ox + bx, c2 = cy ? wrapm(oy + by, m) : oy + by;
       const int64_t i = (int64_t)c2 * n + c1;
       const int k = S::at(bx, by);
-      if (PRO) {   // as the prolongation kernel: base + Pr xc
+      if constexpr (PRO) {   // as the prolongation kernel: base + Pr xc
         const Cx<T> v = nodal_prolong_xy<T>(cc, fz.gc, c1, c2, p);
         pl[k] = xc[i] + v.re;
         pl[S::N + k] = xc[N + i] + v.im;
@@ -419,7 +527,7 @@ __global__ __launch_bounds__(kThreads) void k_nodal_sweep(View<const T> xin, Vie
     if (c1 >= n || c2 >= m) continue;
     const int k = S::at(ix + LO, iy + LO);
     const int64_t i = (int64_t)c2 * n + c1;
-    if (BAS) {   // as the update kernel: base + x
+    if constexpr (BAS) {   // as the update kernel: base + x
       xo[i] = bs[i] + pl[k];
       xo[N + i] = bs[N + i] + pl[S::N + k];
     } else {
@@ -427,7 +535,7 @@ __global__ __launch_bounds__(kThreads) void k_nodal_sweep(View<const T> xin, Vie
       xo[N + i] = pl[S::N + k];
     }
   }
-  if (RES) {
+  if constexpr (RES) {
     T* bco = colp(fz.bc, sj, fz.gc.nm);
     if (!cx && !cy)
       nodal_restrict_tile<T, BX, BY, false, false, LO, TX, TY>(pl, rl, bc, bco, st, ox, oy, tr.t0x, tr.t0y, n, m, N,
@@ -446,17 +554,30 @@ __global__ __launch_bounds__(kThreads) void k_nodal_sweep(View<const T> xin, Vie
 
 // Tile shapes (nodes): 0: 32 x 32, 1: 64 x 32.  FP64 edge sweeps, and FP64 nodal sweeps with
 // the residual window, use 32 x 32 only (the larger boxes exceed the static LDS limit).
-template <typename T, int TX, int TY>
-void edge_launch(View<const T> xin, View<T> xout, View<const T> b, const EdgeArgs& a, const Geo& g, const Phase* ph,
-                 const double* mu, bool backward, bool zero_start, const Launch& L) {
+template <typename T, int TX, int TY, bool BWD, int MODE>
+void edge_go(View<const T> xin, View<T> xout, View<const T> b, const EdgeArgs& a, const Geo& g, const Phase* ph,
+             const double* mu, bool zero_start, const SweepFuse<T>& fz, const Launch& L) {
   const int tx = (g.n + TX - 1) / TX, ty = (g.m + TY - 1) / TY;
   dim3 grid((unsigned)(tx * ty), (unsigned)(L.nact * L.ncps));
-  if (backward)
-    k_edge_sweep<T, TX, TY, true><<<grid, kThreads, 0, L.st>>>(xin, xout, b, a, g, ph, mu, zero_start ? 1 : 0,
-                                                               L.slots, L.ncps, tx);
-  else
-    k_edge_sweep<T, TX, TY, false><<<grid, kThreads, 0, L.st>>>(xin, xout, b, a, g, ph, mu, zero_start ? 1 : 0,
-                                                                L.slots, L.ncps, tx);
+  k_edge_sweep<T, TX, TY, BWD, MODE><<<grid, kThreads, 0, L.st>>>(xin, xout, b, a, g, ph, mu, zero_start ? 1 : 0,
+                                                                  L.slots, L.ncps, tx, fz);
+}
+
+template <typename T, int TX, int TY>
+void edge_launch(View<const T> xin, View<T> xout, View<const T> b, const EdgeArgs& a, const Geo& g, const Phase* ph,
+                 const double* mu, bool backward, bool zero_start, const SweepFuse<T>& fz, const Launch& L) {
+  if (backward) {
+    if (fz.xc.p) edge_go<T, TX, TY, true, kProlong>(xin, xout, b, a, g, ph, mu, zero_start, fz, L);
+    else edge_go<T, TX, TY, true, 0>(xin, xout, b, a, g, ph, mu, zero_start, fz, L);
+    return;
+  }
+  if constexpr (sizeof(T) == 4 && TX * TY <= 1024) {   // the residual window fits LDS: FP32, 32 x 32
+    if (fz.bc.p) {
+      edge_go<T, TX, TY, false, kRestrict>(xin, xout, b, a, g, ph, mu, zero_start, fz, L);
+      return;
+    }
+  }
+  edge_go<T, TX, TY, false, 0>(xin, xout, b, a, g, ph, mu, zero_start, fz, L);
 }
 
 template <typename T, int TX, int TY, bool BWD, int MODE>
@@ -494,19 +615,21 @@ void nodal_launch(View<const T> xin, View<T> xout, View<const T> b, const Geo& g
 
 }  // namespace
 
+bool edge_sweep_restricts(size_t elem) { return elem == 4; }
+
 template <typename T>
 void edge_sweep(View<const T> xin, View<T> xout, View<const T> b, const double* kappa64, const float* kappa32,
                 const double* sinv64, const float* sinv32, const Geo& g, const Phase* ph, const double* mu,
-                const PatchT& T4, bool backward, bool zero_start, int tile, const Launch& L) {
+                const PatchT& T4, bool backward, bool zero_start, int tile, const Launch& L, const SweepFuse<T>& fz) {
   if (L.nact * L.ncps == 0) return;
   const EdgeArgs a{kappa64, kappa32, sinv64, sinv32, T4, g.s, g.mx, g.my};
   if constexpr (sizeof(T) == 4) {
-    if (tile == 1) {
-      edge_launch<T, 64, 32>(xin, xout, b, a, g, ph, mu, backward, zero_start, L);
+    if (tile == 1 && !fz.bc.p) {
+      edge_launch<T, 64, 32>(xin, xout, b, a, g, ph, mu, backward, zero_start, fz, L);
       return;
     }
   }
-  edge_launch<T, 32, 32>(xin, xout, b, a, g, ph, mu, backward, zero_start, L);
+  edge_launch<T, 32, 32>(xin, xout, b, a, g, ph, mu, backward, zero_start, fz, L);
 }
 
 template <typename T>
@@ -520,8 +643,8 @@ void nodal_sweep(View<const T> xin, View<T> xout, View<const T> b, const Geo& g,
     nodal_launch<T, 32, 32>(xin, xout, b, g, ph, c, backward, zero_start, fz, L);
 }
 
-template void edge_sweep<double>(View<const double>, View<double>, View<const double>, const double*, const float*, const double*, const float*, const Geo&, const Phase*, const double*, const PatchT&, bool, bool, int, const Launch&);
-template void edge_sweep<float>(View<const float>, View<float>, View<const float>, const double*, const float*, const double*, const float*, const Geo&, const Phase*, const double*, const PatchT&, bool, bool, int, const Launch&);
+template void edge_sweep<double>(View<const double>, View<double>, View<const double>, const double*, const float*, const double*, const float*, const Geo&, const Phase*, const double*, const PatchT&, bool, bool, int, const Launch&, const SweepFuse<double>&);
+template void edge_sweep<float>(View<const float>, View<float>, View<const float>, const double*, const float*, const double*, const float*, const Geo&, const Phase*, const double*, const PatchT&, bool, bool, int, const Launch&, const SweepFuse<float>&);
 template void nodal_sweep<double>(View<const double>, View<double>, View<const double>, const Geo&, const Phase*, const NodalStencil&, bool, bool, int, const Launch&, const SweepFuse<double>&);
 template void nodal_sweep<float>(View<const float>, View<float>, View<const float>, const Geo&, const Phase*, const NodalStencil&, bool, bool, int, const Launch&, const SweepFuse<float>&);
 
