@@ -217,11 +217,11 @@ int gram_blocks(int64_t len);
 // G_s = S_s^* M S_s and H_s = S_s^* A S_s (q x q, row-major interleaved complex, at
 // G/H + s * q * q * 2).  q <= 48 runs on the matrix cores; wider bases on the vector units
 // with 48- or 64-wide output tiles (`tile` 3 or 4).  Returns -1 (nothing launched) when
-// partial_cap (doubles) is below rr_partial_blocks(nm) * q * q * 4 * nact.
+// partial_cap (doubles) is below rr_partial_blocks(g) * q * q * 4 * nact.
 int rr_gram(View<const double> S, int q, const double* kappa, const Geo& g, const Phase* ph,
             double* partial, int64_t partial_cap, double* G, double* H, int tile, const Launch& L);
 int rr_blocks(int64_t nm);
-int rr_partial_blocks(int64_t nm);
+int rr_partial_blocks(const Geo& g);
 
 // Generalised Hermitian eigenproblem H y = theta G y per slot (q x q, row-major interleaved,
 // FP64, at G/H + s * q * q * 2), one workgroup per slot.  The first nfix basis vectors may

@@ -13,12 +13,16 @@
 // other slots of the launch.
 //
 // Bases of at most 48 columns (the iteration's [X, W] for p <= 24) take the matrix cores
-// instead: FP64 MFMA 16x16x4 products, one workgroup of eight waves per node range (four for
-// G, four for H; two waves per SIMD hide each other's loads).  Each lane forms, for one node
-// of a group of four and one column of each 16-column tile, the basis values and mass
-// products (G) or the scaled cell curls (H) directly in the operand layout of the
-// instruction (no LDS staging); the six upper tile pairs are accumulated in registers and
-// the waves' sums are combined in a fixed order before one partial per node range is written.
+// instead: FP64 MFMA 16x16x4 products.  One workgroup of eight waves (four for G, four for
+// H) owns a slice of 16 nodes of a band of rows and streams the rows through an LDS ring:
+// x-edge rows r-1, r, r+1 and the y-edge row r (with one halo node either side), stored as
+// fetch() returns them, with the next rows prefetched into registers while the current row
+// is computed (one barrier per row; every basis value is read from memory once per band).
+// Each lane forms, for one node of a group of four and one column of each 16-column tile,
+// the basis values and mass products (G) or the scaled cell curls (H) from LDS directly in
+// the operand layout of the instruction; the six upper tile pairs are accumulated in
+// registers and the waves' sums are combined in a fixed order before one partial per slice
+// and band is written.
 #include "stencil_common.h"
 
 // Contractions are explicit (fma in the accumulations, none elsewhere), so the 48- and
@@ -167,88 +171,12 @@ constexpr int MQ = 48;          // widest basis of the matrix-core path (3 tiles
 constexpr int MT = MQ / 16;     // column tiles
 constexpr int MP = MT * (MT + 1) / 2;   // tile pairs ti <= tj
 constexpr int MW = 4;           // waves per product (G or H) in a workgroup
+constexpr int SW = 4 * MW;      // nodes per row of a workgroup's slice (one group of 4 per wave)
+constexpr int CP = MQ + 4;      // LDS stride of a node's columns (complex; padded against bank conflicts)
+constexpr int XS = 4;           // x-edge row slots of the ring (rows r-1, r, r+1 in use, r+2 filling)
+constexpr int YW = SW + 2;      // y-edge row with one node either side
 
 #define BL_MFMA(a, b, c) __builtin_amdgcn_mfma_f64_16x16x4f64((a), (b), (c), 0, 0, 0)
-
-// Lane l of a wave takes node d (the group's node l / 16) and column 16 t + l % 16 of each
-// tile t.  Neighbour indices and the Bloch phases of the seam follow fetch().
-struct NodeRef {
-  int64_t d, up, dn, rt, lf;
-  bool ok, cu, cd, cr, cl;
-};
-__device__ __forceinline__ NodeRef node_ref(int64_t d, bool ok, int n, int m) {
-  NodeRef r;
-  r.ok = ok;
-  const int j1 = ok ? (int)(d % n) : 0, j2 = ok ? (int)(d / n) : 0;
-  r.d = ok ? d : 0;
-  r.cu = j2 == m - 1;
-  r.cd = j2 == 0;
-  r.cr = j1 == n - 1;
-  r.cl = j1 == 0;
-  r.up = r.cu ? r.d - (int64_t)(m - 1) * n : r.d + n;   // x-edge (j1, j2 + 1)
-  r.dn = r.cd ? r.d + (int64_t)(m - 1) * n : r.d - n;   // x-edge (j1, j2 - 1)
-  r.rt = r.cr ? r.d - (n - 1) : r.d + 1;                // y-edge (j1 + 1, j2)
-  r.lf = r.cl ? r.d + (n - 1) : r.d - 1;                // y-edge (j1 - 1, j2)
-  return r;
-}
-
-__device__ __forceinline__ Cx<double> sel(bool c, Cx<double> a, Cx<double> b) {
-  return {c ? a.re : b.re, c ? a.im : b.im};
-}
-
-// Operands of one 16-column tile for G = sum over edges of conj(u) (M u): the x- and y-edge
-// values (u) and their mass products (v), per component [0] x, [1] y.
-struct GTile {
-  double ur[2], ui[2], vr[2], vi[2];
-};
-__device__ __forceinline__ GTile g_tile(const double* __restrict__ S, int q, int64_t N, int64_t nm, const Geo& g,
-                                        const Ph<double>& p, const NodeRef& r, int t) {
-  GTile o = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
-  const int c = 16 * t + (int)(threadIdx.x & 15);
-  if (r.ok && c < q) {
-    const double two3 = 2.0 / 3.0, one6 = 1.0 / 6.0;
-    const double* col = S + (int64_t)c * 2 * N;
-    const Cx<double> x0 = {col[r.d], col[N + r.d]};
-    const Cx<double> xu = sel(r.cu, cmul(Cx<double>{col[r.up], col[N + r.up]}, p.br, p.bi),
-                              Cx<double>{col[r.up], col[N + r.up]});
-    const Cx<double> xd = sel(r.cd, cmul(Cx<double>{col[r.dn], col[N + r.dn]}, p.br, -p.bi),
-                              Cx<double>{col[r.dn], col[N + r.dn]});
-    const Cx<double> y0 = {col[nm + r.d], col[N + nm + r.d]};
-    const Cx<double> yr = sel(r.cr, cmul(Cx<double>{col[nm + r.rt], col[N + nm + r.rt]}, p.ar, p.ai),
-                              Cx<double>{col[nm + r.rt], col[N + nm + r.rt]});
-    const Cx<double> yl = sel(r.cl, cmul(Cx<double>{col[nm + r.lf], col[N + nm + r.lf]}, p.ar, -p.ai),
-                              Cx<double>{col[nm + r.lf], col[N + nm + r.lf]});
-    const Cx<double> mx = g.mx * ((two3 * x0) + one6 * (xu + xd));
-    const Cx<double> my = g.my * ((two3 * y0) + one6 * (yr + yl));
-    o.ur[0] = x0.re; o.ui[0] = x0.im; o.ur[1] = y0.re; o.ui[1] = y0.im;
-    o.vr[0] = mx.re; o.vi[0] = mx.im; o.vr[1] = my.re; o.vi[1] = my.im;
-  }
-  return o;
-}
-
-// Operands of one tile for H = sum over cells of (kappa s) conj(w) w: the cell curl scaled
-// by sqrt(kappa s).
-struct HTile {
-  double wr, wi;
-};
-__device__ __forceinline__ HTile h_tile(const double* __restrict__ S, int q, int64_t N, int64_t nm,
-                                        const Ph<double>& p, double wsc, const NodeRef& r, int t) {
-  HTile o = {0, 0};
-  const int c = 16 * t + (int)(threadIdx.x & 15);
-  if (r.ok && c < q) {
-    const double* col = S + (int64_t)c * 2 * N;
-    const Cx<double> x0 = {col[r.d], col[N + r.d]};
-    const Cx<double> xu = sel(r.cu, cmul(Cx<double>{col[r.up], col[N + r.up]}, p.br, p.bi),
-                              Cx<double>{col[r.up], col[N + r.up]});
-    const Cx<double> y0 = {col[nm + r.d], col[N + nm + r.d]};
-    const Cx<double> yr = sel(r.cr, cmul(Cx<double>{col[nm + r.rt], col[N + nm + r.rt]}, p.ar, p.ai),
-                              Cx<double>{col[nm + r.rt], col[N + nm + r.rt]});
-    const Cx<double> c0 = wsc * (xu - x0 + y0 - yr);
-    o.wr = c0.re;
-    o.wi = c0.im;
-  }
-  return o;
-}
 
 // G and H updates of tile pair (A, B), accumulator k
 #define BL_GPAIR(k, A, B)                                  \
@@ -266,59 +194,187 @@ __device__ __forceinline__ HTile h_tile(const double* __restrict__ S, int q, int
   ai[k] = BL_MFMA(A.wr, B.wi, ai[k]);                      \
   ai[k] = BL_MFMA(-A.wi, B.wr, ai[k]);
 
-// Workgroup of 2 MW waves per node range [rs, re): waves 0..MW-1 accumulate G, waves
-// MW..2MW-1 accumulate H, wave w of a product taking the 4-node groups w, w + MW, ...
-__global__ __launch_bounds__(128 * MW) void k_rr_mfma(View<const double> Sv, int q, const double* __restrict__ kappa,
-                                                      Geo g, const Phase* __restrict__ phs, int64_t rows_per_blk,
-                                                      double* __restrict__ partial, const int* __restrict__ slots) {
-  extern __shared__ double red[];   // per product: 2 MP d4 per lane (re, im), lane-major
+// Operands of one 16-column tile for G = sum over edges of conj(u) (M u): the x- and y-edge
+// values (u) and their mass products (v), per component [0] x, [1] y.
+struct GTile {
+  double ur[2], ui[2], vr[2], vi[2];
+};
+// Operands of one tile for H = sum over cells of (kappa s) conj(w) w: the cell curl scaled
+// by sqrt(kappa s).
+struct HTile {
+  double wr, wi;
+};
+
+// The workgroup's staging: x-edge rows in a ring of XS slots (row e in slot (e - r0 + 1) mod
+// XS), y-edge rows in two slots with the scaled curl weights of their cells; per node the
+// columns at stride CP (complex).  Values are stored as fetch() returns them for the row's
+// extended index (times beta one period up, conj(beta) one period back; the y halo times
+// alpha / conj(alpha)), zero for columns >= q and nodes past the grid.
+struct RRStage {
+  double2 x[XS][SW][CP];
+  double2 y[2][YW][CP];
+  double w[2][SW];
+};
+
+// Staged item e of a row pair: x-edge (node, column) of row xrow for e < SW MQ, then y-edge
+// (halo node, column) of row yrow, then the curl weight sqrt(kappa s) of the cells of row yrow
+// (in .x); its value as fetch() returns it (zero when not wanted or outside the basis / grid).
+__device__ __forceinline__ double2 rr_load(int e, const double* S, int q, int64_t N, int64_t nm, int n, int m,
+                                           const double* kap, double s, const Ph<double>& p, int c0, int xrow,
+                                           int yrow, bool want) {
+  constexpr int NX = SW * MQ, NY = YW * MQ;
+  if (!want) return double2{0.0, 0.0};
+  if (e < NX) {
+    const int col = e / SW, j1 = c0 + e % SW;
+    if (col >= q || j1 >= n) return double2{0.0, 0.0};
+    int r = xrow, sy = 0;
+    if (r < 0) { r += m; sy = -1; } else if (r >= m) { r -= m; sy = 1; }
+    const double* cp = S + (int64_t)col * 2 * N;
+    const int64_t d = (int64_t)r * n + j1;
+    Cx<double> v = {cp[d], cp[N + d]};
+    if (sy > 0) v = cmul(v, p.br, p.bi);
+    else if (sy < 0) v = cmul(v, p.br, -p.bi);
+    return double2{v.re, v.im};
+  }
+  e -= NX;
+  if (e < NY) {
+    const int col = e / YW;
+    int j1 = c0 - 1 + e % YW, sx = 0;
+    if (j1 < 0) { j1 += n; sx = -1; } else if (j1 == n) { j1 = 0; sx = 1; } else if (j1 > n) { return double2{0.0, 0.0}; }
+    if (col >= q) return double2{0.0, 0.0};
+    const double* cp = S + (int64_t)col * 2 * N;
+    const int64_t d = nm + (int64_t)yrow * n + j1;
+    Cx<double> v = {cp[d], cp[N + d]};
+    if (sx > 0) v = cmul(v, p.ar, p.ai);
+    else if (sx < 0) v = cmul(v, p.ar, -p.ai);
+    return double2{v.re, v.im};
+  }
+  e -= NY;
+  const int j1 = c0 + e;
+  return double2{j1 < n ? sqrt(kap[(int64_t)yrow * n + j1] * s) : 0.0, 0.0};
+}
+
+// store item e into the x slot / y slot
+__device__ __forceinline__ void rr_put(RRStage& st, int e, double2 v, int xslot, int yslot, bool with_x, bool with_y) {
+  constexpr int NX = SW * MQ, NY = YW * MQ;
+  if (e < NX) {
+    if (with_x) st.x[xslot][e % SW][e / SW] = v;
+  } else if (e < NX + NY) {
+    e -= NX;
+    if (with_y) st.y[yslot][e % YW][e / YW] = v;
+  } else if (with_y) {
+    st.w[yslot][e - NX - NY] = v.x;
+  }
+}
+
+constexpr int RR_ITEMS = SW * MQ + YW * MQ + SW;
+constexpr int RR_THREADS = 128 * MW;
+constexpr int RR_PER_THREAD = (RR_ITEMS + RR_THREADS - 1) / RR_THREADS;
+
+// One workgroup per slice of SW nodes x band of rows [r0, r1) of a slot: waves 0..MW-1 form
+// G, waves MW..2MW-1 form H, wave w of a product taking the nodes 4w .. 4w+3 of each row.
+// Rows stream through the LDS ring with a one-row prefetch in registers and one barrier per
+// row; the waves' sums are combined in a fixed order and the slice's full G and H written.
+__global__ __launch_bounds__(RR_THREADS) void k_rr_mfma(View<const double> Sv, int q, const double* __restrict__ kappa,
+                                                        Geo g, const Phase* __restrict__ phs, int slices, int band,
+                                                        double* __restrict__ partial, const int* __restrict__ slots) {
+  extern __shared__ double lds[];
+  RRStage& st = *reinterpret_cast<RRStage*>(lds);
   const int slot = slots ? slots[blockIdx.z] : (int)blockIdx.z;
   const int64_t N = g.ne, nm = g.nm;
   const int n = g.n, m = g.m;
   const double* S = Sv.p + ((int64_t)slot * Sv.cps + Sv.off) * 2 * N;
   const double* kap = kappa + (int64_t)slot * nm;
   const Ph<double> p = cast_phase<double>(phs[slot]);
+  const int c0 = (int)(blockIdx.x % slices) * SW;
+  const int r0 = (int)(blockIdx.x / slices) * band;
+  const int r1 = r0 + band < m ? r0 + band : m;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const bool is_h = wv >= MW;
   const int w = is_h ? wv - MW : wv;
-  const int64_t rs = (int64_t)blockIdx.x * rows_per_blk;
-  const int64_t re = rs + rows_per_blk < nm ? rs + rows_per_blk : nm;
-  const int64_t ngroups = (re - rs + 3) / 4;
+  const int tid = threadIdx.x;
+  auto xslot = [&](int e) { return (e - r0 + 1) & (XS - 1); };
+  // rows r0-1, r0, r0+1 (x) and r0 (y) straight into LDS
+  for (int e = tid; e < RR_ITEMS; e += RR_THREADS)
+    for (int k = 0; k < 3; ++k) {
+      const double2 v = rr_load(e, S, q, N, nm, n, m, kap, g.s, p, c0, r0 - 1 + k, r0, true);
+      rr_put(st, e, v, xslot(r0 - 1 + k), r0 & 1, true, k == 1);
+    }
+  // prefetch of rows r0+2 (x) and r0+1 (y)
+  double2 pf[RR_PER_THREAD];
+#pragma unroll
+  for (int u = 0; u < RR_PER_THREAD; ++u) {
+    const int e = tid + u * RR_THREADS;
+    pf[u] = rr_load(e < RR_ITEMS ? e : 0, S, q, N, nm, n, m, kap, g.s, p, c0, r0 + 2, r0 + 1,
+                    e < RR_ITEMS && r0 + 1 < r1);
+  }
   d4 ar[MP], ai[MP];
 #pragma unroll
   for (int k = 0; k < MP; ++k) ar[k] = ai[k] = d4{0, 0, 0, 0};
-  // tile pairs k = 0..5: (0,0) (0,1) (0,2) (1,1) (1,2) (2,2)
-  if (!is_h) {
-    for (int64_t grp = w; grp < ngroups; grp += MW) {
-      const int64_t d = rs + 4 * grp + (lane >> 4);
-      const NodeRef r = node_ref(d, d < re, n, m);
-      const GTile t0 = g_tile(S, q, N, nm, g, p, r, 0);
-      const GTile t1 = g_tile(S, q, N, nm, g, p, r, 1);
-      const GTile t2 = g_tile(S, q, N, nm, g, p, r, 2);
-      BL_GPAIR(0, t0, t0)
-      BL_GPAIR(1, t0, t1)
-      BL_GPAIR(2, t0, t2)
-      BL_GPAIR(3, t1, t1)
-      BL_GPAIR(4, t1, t2)
-      BL_GPAIR(5, t2, t2)
+  const double two3 = 2.0 / 3.0, one6 = 1.0 / 6.0;
+  const int jn = 4 * w + (lane >> 4);   // this lane's node in the slice
+  const int cl = lane & 15;             // and column in each tile
+  for (int r = r0; r < r1; ++r) {
+    __syncthreads();   // rows up to r + 1 staged; the slots written below are no longer read
+    if (r + 1 < r1) {
+#pragma unroll
+      for (int u = 0; u < RR_PER_THREAD; ++u) {
+        const int e = tid + u * RR_THREADS;
+        if (e < RR_ITEMS) rr_put(st, e, pf[u], xslot(r + 2), (r + 1) & 1, true, true);
+      }
+#pragma unroll
+      for (int u = 0; u < RR_PER_THREAD; ++u) {
+        const int e = tid + u * RR_THREADS;
+        pf[u] = rr_load(e < RR_ITEMS ? e : 0, S, q, N, nm, n, m, kap, g.s, p, c0, r + 3, r + 2,
+                        e < RR_ITEMS && r + 2 < r1);
+      }
     }
-  } else {
-    for (int64_t grp = w; grp < ngroups; grp += MW) {
-      const int64_t d = rs + 4 * grp + (lane >> 4);
-      const NodeRef r = node_ref(d, d < re, n, m);
-      const double wsc = r.ok ? sqrt(kap[r.d] * g.s) : 0.0;
-      const HTile t0 = h_tile(S, q, N, nm, p, wsc, r, 0);
-      const HTile t1 = h_tile(S, q, N, nm, p, wsc, r, 1);
-      const HTile t2 = h_tile(S, q, N, nm, p, wsc, r, 2);
-      BL_HPAIR(0, t0, t0)
-      BL_HPAIR(1, t0, t1)
-      BL_HPAIR(2, t0, t2)
-      BL_HPAIR(3, t1, t1)
-      BL_HPAIR(4, t1, t2)
-      BL_HPAIR(5, t2, t2)
+    const int sm = xslot(r - 1), s0 = xslot(r), sp = xslot(r + 1), sy = r & 1;
+    if (!is_h) {
+      const bool node_ok = c0 + jn < n;
+      GTile t[MT];
+#pragma unroll
+      for (int tt = 0; tt < MT; ++tt) {
+        const int c = 16 * tt + cl;
+        const double2 x0 = st.x[s0][jn][c], xu = st.x[sp][jn][c], xd = st.x[sm][jn][c];
+        const double2 y0 = st.y[sy][jn + 1][c], yr = st.y[sy][jn + 2][c], yl = st.y[sy][jn][c];
+        const Cx<double> mx = g.mx * ((two3 * Cx<double>{x0.x, x0.y}) + one6 * (Cx<double>{xu.x, xu.y} + Cx<double>{xd.x, xd.y}));
+        const Cx<double> my = g.my * ((two3 * Cx<double>{y0.x, y0.y}) + one6 * (Cx<double>{yr.x, yr.y} + Cx<double>{yl.x, yl.y}));
+        // u of nodes past the grid is zero (their y-edge slot may hold the wrapped halo value)
+        t[tt].ur[0] = x0.x; t[tt].ui[0] = x0.y;
+        t[tt].ur[1] = node_ok ? y0.x : 0.0; t[tt].ui[1] = node_ok ? y0.y : 0.0;
+        t[tt].vr[0] = mx.re; t[tt].vi[0] = mx.im; t[tt].vr[1] = my.re; t[tt].vi[1] = my.im;
+      }
+      BL_GPAIR(0, t[0], t[0])
+      BL_GPAIR(1, t[0], t[1])
+      BL_GPAIR(2, t[0], t[2])
+      BL_GPAIR(3, t[1], t[1])
+      BL_GPAIR(4, t[1], t[2])
+      BL_GPAIR(5, t[2], t[2])
+    } else {
+      HTile t[MT];
+      const double wsc = st.w[sy][jn];
+#pragma unroll
+      for (int tt = 0; tt < MT; ++tt) {
+        const int c = 16 * tt + cl;
+        const double2 x0 = st.x[s0][jn][c], xu = st.x[sp][jn][c];
+        const double2 y0 = st.y[sy][jn + 1][c], yr = st.y[sy][jn + 2][c];
+        const Cx<double> c0v = wsc * (Cx<double>{xu.x, xu.y} - Cx<double>{x0.x, x0.y} + Cx<double>{y0.x, y0.y} -
+                                      Cx<double>{yr.x, yr.y});
+        t[tt].wr = c0v.re;
+        t[tt].wi = c0v.im;
+      }
+      BL_HPAIR(0, t[0], t[0])
+      BL_HPAIR(1, t[0], t[1])
+      BL_HPAIR(2, t[0], t[2])
+      BL_HPAIR(3, t[1], t[1])
+      BL_HPAIR(4, t[1], t[2])
+      BL_HPAIR(5, t[2], t[2])
     }
   }
+  __syncthreads();   // the ring is reused for the combination
   // combine the waves of each product in order 0 .. MW-1
+  double* red = lds;
   double* mine = red + ((size_t)(is_h ? 1 : 0) * 64 + lane) * 8 * MP;
   for (int src = 0; src < MW; ++src) {
     if (w == src) {
@@ -338,9 +394,9 @@ __global__ __launch_bounds__(128 * MW) void k_rr_mfma(View<const double> Sv, int
     }
     __syncthreads();
   }
-  // write the range's full G and H (q x q, interleaved complex; lower tiles mirrored)
+  // write the slice's full G and H (q x q, interleaved complex; lower tiles mirrored)
   double* pg = partial + ((int64_t)blockIdx.z * gridDim.x + blockIdx.x) * (int64_t)q * q * 4;
-  for (int e = threadIdx.x; e < 2 * 64 * MP * 4; e += 128 * MW) {
+  for (int e = threadIdx.x; e < 2 * 64 * MP * 4; e += RR_THREADS) {
     const int prod = e / (64 * MP * 4), l = (e / (MP * 4)) % 64, k = (e / 4) % MP, v = e % 4;
     int ti = 0, tj = 0, kk = k;
     for (ti = 0; ti < MT; ++ti) {
@@ -394,18 +450,23 @@ __global__ __launch_bounds__(256) void k_rr_reduce(const double* __restrict__ pa
 
 }  // namespace
 
-// node ranges of the matrix-core path: up to one workgroup per compute unit, >= 64 nodes each
-int rr_mfma_blocks(int64_t nm) {
-  int64_t nb = (nm + 255) / 256;
-  if (nb > 256) nb = 256;
-  if (nb < 1) nb = 1;
-  int64_t rpb = (nm + nb - 1) / nb;
-  rpb = (rpb + 3) / 4 * 4;
-  return (int)((nm + rpb - 1) / rpb);
+// slices x bands of the matrix-core path: slices of SW nodes, bands of rows so that about
+// one workgroup per compute unit runs
+struct RRGrid {
+  int slices, band, blocks;
+};
+RRGrid rr_mfma_grid(const Geo& g) {
+  const int slices = (g.n + SW - 1) / SW;
+  int nbands = 256 / slices;
+  if (nbands < 1) nbands = 1;
+  if (nbands > g.m) nbands = g.m;
+  const int band = (g.m + nbands - 1) / nbands;
+  nbands = (g.m + band - 1) / band;
+  return {slices, band, slices * nbands};
 }
 
-int rr_partial_blocks(int64_t nm) {
-  const int a = rr_blocks(nm), b = rr_mfma_blocks(nm);
+int rr_partial_blocks(const Geo& g) {
+  const int a = rr_blocks(g.nm), b = rr_mfma_grid(g).blocks;
   return a > b ? a : b;
 }
 
@@ -422,18 +483,18 @@ int rr_gram(View<const double> S, int q, const double* kappa, const Geo& g, cons
             double* partial, int64_t partial_cap, double* G, double* H, int tile, const Launch& L) {
   if (L.nact <= 0) return 0;
   if (q <= MQ) {
-    const int nb = rr_mfma_blocks(g.nm);
+    const RRGrid grd = rr_mfma_grid(g);
+    const int nb = grd.blocks;
     if ((int64_t)nb * q * q * 4 * L.nact > partial_cap) return -1;
-    int64_t rpb = (g.nm + nb - 1) / nb;
-    rpb = (rpb + 3) / 4 * 4;
-    const size_t lds = (size_t)2 * 64 * 8 * MP * sizeof(double);
+    const size_t lds = sizeof(RRStage) > (size_t)2 * 64 * 8 * MP * sizeof(double) ? sizeof(RRStage)
+                                                                                 : (size_t)2 * 64 * 8 * MP * sizeof(double);
     static bool attr = false;
     if (!attr) {
       (void)hipFuncSetAttribute((const void*)k_rr_mfma, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       attr = true;
     }
-    k_rr_mfma<<<dim3((unsigned)nb, 1, (unsigned)L.nact), 128 * MW, lds, L.st>>>(S, q, kappa, g, ph, rpb, partial,
-                                                                                L.slots);
+    k_rr_mfma<<<dim3((unsigned)nb, 1, (unsigned)L.nact), RR_THREADS, lds, L.st>>>(S, q, kappa, g, ph, grd.slices,
+                                                                                  grd.band, partial, L.slots);
     const int64_t cnt = (int64_t)q * q * 4;
     k_rr_reduce<<<dim3((unsigned)((cnt + 63) / 64), (unsigned)L.nact), 256, 0, L.st>>>(partial, nb, q, G, H,
                                                                                       L.slots);

@@ -793,7 +793,7 @@ size_t engine_footprint(const bl_grid* grid, const bl_opts* o, int nslots) {
   Geo gc = make_geo(lv.back().first, lv.back().second, grid->a, grid->b);
   per += (size_t)gc.ne * gc.ne * 16 * 2 + (size_t)gc.nm * gc.nm * 16 * 2;   // inverses (FP64 + FP32)
   per += (size_t)gc.ne * gc.ne * 16;                                         // probe results
-  per += (size_t)rr_partial_blocks(g0.nm) * q * q * 32 + (size_t)10 * q * q * 16;
+  per += (size_t)rr_partial_blocks(g0) * q * q * 32 + (size_t)10 * q * q * 16;
   per += (size_t)p * ((g0.ne + 255) / 256) * 16;
   fixed += (size_t)gc.ne * gc.ne * 16 + (size_t)gc.nm * gc.nm * 16;           // probes
   return fixed + per * (size_t)std::max(1, nslots);
@@ -878,7 +878,7 @@ int engine_create(const bl_grid* grid, const bl_opts* opts, int nslots, hipStrea
   if ((rc = dalloc_t(s, &s->count_d, (size_t)S))) return fail(rc);
   if ((rc = dalloc_t(s, &s->partial, (size_t)p * S * ((g0.ne + 255) / 256) * 2))) return fail(rc);
   if ((rc = dalloc_t(s, &s->norms, (size_t)2 * p * S))) return fail(rc);
-  s->gram_cap = (int64_t)rr_partial_blocks(g0.nm) * q * q * 4 * S;
+  s->gram_cap = (int64_t)rr_partial_blocks(g0) * q * q * 4 * S;
   if ((rc = dalloc_t(s, &s->gram_partial, s->gram_cap))) return fail(rc);
   if ((rc = dalloc_t(s, &s->Gm, (size_t)q * q * 2 * S))) return fail(rc);
   if ((rc = dalloc_t(s, &s->Hm, (size_t)q * q * 2 * S))) return fail(rc);
