@@ -217,53 +217,66 @@ struct RRStage {
 };
 
 // Staged item e of a row pair: x-edge (node, column) of row xrow for e < SW MQ, then y-edge
-// (halo node, column) of row yrow, then the curl weight sqrt(kappa s) of the cells of row yrow
-// (in .x); its value as fetch() returns it (zero when not wanted or outside the basis / grid).
-__device__ __forceinline__ double2 rr_load(int e, const double* S, int q, int64_t N, int64_t nm, int n, int m,
-                                           const double* kap, double s, const Ph<double>& p, int c0, int xrow,
-                                           int yrow, bool want) {
+// (halo node, column) of row yrow, then the cell coefficient kappa of the cells of row yrow.
+// rr_fetch issues the loads only (from a valid address in every case, so that no value is
+// waited for before it is stored), with a code for what rr_put applies: bit 3 zero (not
+// wanted, or outside the basis / grid), bits 0-1 the Bloch factor (1: times the phase, 2:
+// times its conjugate), bit 2 the factor is alpha (y halo) instead of beta (x rows).
+struct RRRaw {
+  double a, b;
+  int code;
+};
+
+__device__ __forceinline__ RRRaw rr_fetch(int e, const double* S, int q, int64_t N, int64_t nm, int n, int m,
+                                          const double* kap, int c0, int xrow, int yrow, bool want) {
+  // branch-free: the three kinds' addresses are formed side by side and selected, and every
+  // lane issues its two loads, so that nothing waits for the values here
   constexpr int NX = SW * MQ, NY = YW * MQ;
-  if (!want) return double2{0.0, 0.0};
-  if (e < NX) {
-    const int col = e / SW, j1 = c0 + e % SW;
-    if (col >= q || j1 >= n) return double2{0.0, 0.0};
-    int r = xrow, sy = 0;
-    if (r < 0) { r += m; sy = -1; } else if (r >= m) { r -= m; sy = 1; }
-    const double* cp = S + (int64_t)col * 2 * N;
-    const int64_t d = (int64_t)r * n + j1;
-    Cx<double> v = {cp[d], cp[N + d]};
-    if (sy > 0) v = cmul(v, p.br, p.bi);
-    else if (sy < 0) v = cmul(v, p.br, -p.bi);
-    return double2{v.re, v.im};
-  }
-  e -= NX;
-  if (e < NY) {
-    const int col = e / YW;
-    int j1 = c0 - 1 + e % YW, sx = 0;
-    if (j1 < 0) { j1 += n; sx = -1; } else if (j1 == n) { j1 = 0; sx = 1; } else if (j1 > n) { return double2{0.0, 0.0}; }
-    if (col >= q) return double2{0.0, 0.0};
-    const double* cp = S + (int64_t)col * 2 * N;
-    const int64_t d = nm + (int64_t)yrow * n + j1;
-    Cx<double> v = {cp[d], cp[N + d]};
-    if (sx > 0) v = cmul(v, p.ar, p.ai);
-    else if (sx < 0) v = cmul(v, p.ar, -p.ai);
-    return double2{v.re, v.im};
-  }
-  e -= NY;
-  const int j1 = c0 + e;
-  return double2{j1 < n ? sqrt(kap[(int64_t)yrow * n + j1] * s) : 0.0, 0.0};
+  const bool isx = e < NX, isy = !isx && e < NX + NY, isw = !isx && !isy;
+  const int ey = e - NX, ew = e - NX - NY;
+  // x-edge rows: the row's wrap is the same for the whole workgroup
+  int r = xrow, cx = 0;
+  if (r < 0) { r += m; cx = 2; } else if (r >= m) { r -= m; cx = 1; }
+  const int colx = e / SW, jx = c0 + e % SW;
+  const bool okx = colx < q && jx < n;
+  // y-edge halo
+  const int coly = ey / YW;
+  int jy = c0 - 1 + ey % YW, cy = 4;
+  cy = jy < 0 ? (cy | 2) : (jy == n ? (cy | 1) : cy);
+  const bool oky = coly < q && jy <= n;
+  jy = jy < 0 ? jy + n : (jy == n ? 0 : jy);
+  // curl weight
+  const int jw = c0 + ew;
+  const bool okw = jw < n;
+  const bool ok = want && (isx ? okx : (isy ? oky : okw));
+  const int col = isx ? colx : coly;
+  const double* base = isw ? kap : S + (int64_t)((ok && col < q) ? col : 0) * 2 * N;
+  int64_t off = isx ? (int64_t)r * n + jx : (isy ? nm + (int64_t)yrow * n + jy : (int64_t)yrow * n + jw);
+  off = ok ? off : 0;
+  const int64_t str = isw ? 0 : N;
+  const int code = ok ? (isx ? cx : (isy ? cy : 0)) : 8;
+  return RRRaw{base[off], base[off + str], code};
 }
 
-// store item e into the x slot / y slot
-__device__ __forceinline__ void rr_put(RRStage& st, int e, double2 v, int xslot, int yslot, bool with_x, bool with_y) {
+// store item e (applying its code) into the x slot / y slot
+__device__ __forceinline__ void rr_put(RRStage& st, int e, const RRRaw& raw, const Ph<double>& p, double s, int xslot,
+                                       int yslot, bool with_x, bool with_y) {
   constexpr int NX = SW * MQ, NY = YW * MQ;
+  const bool zero = (raw.code & 8) != 0;
+  if (e >= NX + NY) {
+    if (with_y) st.w[yslot][e - NX - NY] = zero ? 0.0 : sqrt(raw.a * s);
+    return;
+  }
+  Cx<double> v = {raw.a, raw.b};
+  const double fr = (raw.code & 4) ? p.ar : p.br, fi = (raw.code & 4) ? p.ai : p.bi;
+  if (raw.code & 1) v = cmul(v, fr, fi);
+  else if (raw.code & 2) v = cmul(v, fr, -fi);
+  const double2 w = zero ? double2{0.0, 0.0} : double2{v.re, v.im};
   if (e < NX) {
-    if (with_x) st.x[xslot][e % SW][e / SW] = v;
-  } else if (e < NX + NY) {
+    if (with_x) st.x[xslot][e % SW][e / SW] = w;
+  } else {
     e -= NX;
-    if (with_y) st.y[yslot][e % YW][e / YW] = v;
-  } else if (with_y) {
-    st.w[yslot][e - NX - NY] = v.x;
+    if (with_y) st.y[yslot][e % YW][e / YW] = w;
   }
 }
 
@@ -294,19 +307,30 @@ __global__ __launch_bounds__(RR_THREADS) void k_rr_mfma(View<const double> Sv, i
   const int w = is_h ? wv - MW : wv;
   const int tid = threadIdx.x;
   auto xslot = [&](int e) { return (e - r0 + 1) & (XS - 1); };
-  // rows r0-1, r0, r0+1 (x) and r0 (y) straight into LDS
-  for (int e = tid; e < RR_ITEMS; e += RR_THREADS)
-    for (int k = 0; k < 3; ++k) {
-      const double2 v = rr_load(e, S, q, N, nm, n, m, kap, g.s, p, c0, r0 - 1 + k, r0, true);
-      rr_put(st, e, v, xslot(r0 - 1 + k), r0 & 1, true, k == 1);
-    }
+  // rows r0-1, r0, r0+1 (x) and r0 (y) straight into LDS (all loads issued first)
+  {
+    RRRaw ini[3][RR_PER_THREAD];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int u = 0; u < RR_PER_THREAD; ++u) {
+        const int e = tid + u * RR_THREADS;
+        ini[k][u] = rr_fetch(e < RR_ITEMS ? e : 0, S, q, N, nm, n, m, kap, c0, r0 - 1 + k, r0, e < RR_ITEMS);
+      }
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int u = 0; u < RR_PER_THREAD; ++u) {
+        const int e = tid + u * RR_THREADS;
+        if (e < RR_ITEMS) rr_put(st, e, ini[k][u], p, g.s, xslot(r0 - 1 + k), r0 & 1, true, k == 1);
+      }
+  }
   // prefetch of rows r0+2 (x) and r0+1 (y)
-  double2 pf[RR_PER_THREAD];
+  RRRaw pf[RR_PER_THREAD];
 #pragma unroll
   for (int u = 0; u < RR_PER_THREAD; ++u) {
     const int e = tid + u * RR_THREADS;
-    pf[u] = rr_load(e < RR_ITEMS ? e : 0, S, q, N, nm, n, m, kap, g.s, p, c0, r0 + 2, r0 + 1,
-                    e < RR_ITEMS && r0 + 1 < r1);
+    pf[u] = rr_fetch(e < RR_ITEMS ? e : 0, S, q, N, nm, n, m, kap, c0, r0 + 2, r0 + 1, e < RR_ITEMS && r0 + 1 < r1);
   }
   d4 ar[MP], ai[MP];
 #pragma unroll
@@ -320,13 +344,12 @@ __global__ __launch_bounds__(RR_THREADS) void k_rr_mfma(View<const double> Sv, i
 #pragma unroll
       for (int u = 0; u < RR_PER_THREAD; ++u) {
         const int e = tid + u * RR_THREADS;
-        if (e < RR_ITEMS) rr_put(st, e, pf[u], xslot(r + 2), (r + 1) & 1, true, true);
+        if (e < RR_ITEMS) rr_put(st, e, pf[u], p, g.s, xslot(r + 2), (r + 1) & 1, true, true);
       }
 #pragma unroll
       for (int u = 0; u < RR_PER_THREAD; ++u) {
         const int e = tid + u * RR_THREADS;
-        pf[u] = rr_load(e < RR_ITEMS ? e : 0, S, q, N, nm, n, m, kap, g.s, p, c0, r + 3, r + 2,
-                        e < RR_ITEMS && r + 2 < r1);
+        pf[u] = rr_fetch(e < RR_ITEMS ? e : 0, S, q, N, nm, n, m, kap, c0, r + 3, r + 2, e < RR_ITEMS && r + 2 < r1);
       }
     }
     const int sm = xslot(r - 1), s0 = xslot(r), sp = xslot(r + 1), sy = r & 1;
