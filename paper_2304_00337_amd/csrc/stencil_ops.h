@@ -166,21 +166,30 @@ __device__ __forceinline__ Cx<T> edge_restrict_at(const T* r, const Geo& gf, con
   return edge_restrict_acc<T>(R, c);
 }
 
+template <typename T>
+__device__ __forceinline__ Cx<T> pick_cx(bool c, Cx<T> a, Cx<T> b) {
+  return {c ? a.re : b.re, c ? a.im : b.im};
+}
+
 // Fine edge of component c owned by fine node (f1, f2) of (Pr x_c): the embedding of the
-// coarse Nedelec function.
+// coarse Nedelec function (1/2 of the coarse edge's value on its halves, 1/4 of the two
+// parallel coarse edges' values in between).  The transfers form every candidate and select
+// one, so that lanes of either parity run the same instructions.
 template <typename T>
 __device__ __forceinline__ Cx<T> edge_prolong_xy(const T* c, const Geo& gc, int comp, int f1, int f2,
                                                  const Ph<T>& p) {
   const int nc = gc.n, mc = gc.m;
   const int64_t Nc = gc.ne, nmc = gc.nm;
   if (comp == 0) {
-    const int J1 = f1 >> 1;
-    if ((f2 & 1) == 0) return (T)0.5 * fetch<T, T>(c, Nc, nc, mc, 0, J1, f2 >> 1, p);
-    return (T)0.25 * (fetch<T, T>(c, Nc, nc, mc, 0, J1, f2 >> 1, p) + fetch<T, T>(c, Nc, nc, mc, 0, J1, (f2 >> 1) + 1, p));
+    const int J1 = f1 >> 1, J2 = f2 >> 1;
+    const Cx<T> a = fetch<T, T>(c, Nc, nc, mc, 0, J1, J2, p);
+    const Cx<T> b = fetch<T, T>(c, Nc, nc, mc, 0, J1, J2 + 1, p);
+    return pick_cx<T>((f2 & 1) == 0, (T)0.5 * a, (T)0.25 * (a + b));
   }
-  const int J2 = f2 >> 1;
-  if ((f1 & 1) == 0) return (T)0.5 * fetch<T, T>(c, Nc, nc, mc, nmc, f1 >> 1, J2, p);
-  return (T)0.25 * (fetch<T, T>(c, Nc, nc, mc, nmc, f1 >> 1, J2, p) + fetch<T, T>(c, Nc, nc, mc, nmc, (f1 >> 1) + 1, J2, p));
+  const int J1 = f1 >> 1, J2 = f2 >> 1;
+  const Cx<T> a = fetch<T, T>(c, Nc, nc, mc, nmc, J1, J2, p);
+  const Cx<T> b = fetch<T, T>(c, Nc, nc, mc, nmc, J1 + 1, J2, p);
+  return pick_cx<T>((f1 & 1) == 0, (T)0.5 * a, (T)0.25 * (a + b));
 }
 
 // Fine edge d of (Pr x_c).
@@ -248,12 +257,13 @@ __device__ __forceinline__ Cx<T> nodal_prolong_xy(const T* c, const Geo& gc, int
   const int J1 = f1 >> 1, J2 = f2 >> 1;
   const bool o1 = f1 & 1, o2 = f2 & 1;
   const Cx<T> c00 = fetch<T, T>(c, gc.nm, gc.n, gc.m, 0, J1, J2, p);
-  if (!o1 && !o2) return c00;
-  if (o1 && !o2) return (T)0.5 * (c00 + fetch<T, T>(c, gc.nm, gc.n, gc.m, 0, J1 + 1, J2, p));
-  if (!o1 && o2) return (T)0.5 * (c00 + fetch<T, T>(c, gc.nm, gc.n, gc.m, 0, J1, J2 + 1, p));
-  return (T)0.25 * (c00 + fetch<T, T>(c, gc.nm, gc.n, gc.m, 0, J1 + 1, J2, p) +
-                    fetch<T, T>(c, gc.nm, gc.n, gc.m, 0, J1, J2 + 1, p) +
-                    fetch<T, T>(c, gc.nm, gc.n, gc.m, 0, J1 + 1, J2 + 1, p));
+  const Cx<T> c10 = fetch<T, T>(c, gc.nm, gc.n, gc.m, 0, J1 + 1, J2, p);
+  const Cx<T> c01 = fetch<T, T>(c, gc.nm, gc.n, gc.m, 0, J1, J2 + 1, p);
+  const Cx<T> c11 = fetch<T, T>(c, gc.nm, gc.n, gc.m, 0, J1 + 1, J2 + 1, p);
+  const Cx<T> vx = (T)0.5 * (c00 + c10);                   // odd f1, even f2
+  const Cx<T> vy = (T)0.5 * (c00 + c01);                   // even f1, odd f2
+  const Cx<T> vd = (T)0.25 * (c00 + c10 + c01 + c11);      // both odd
+  return pick_cx<T>(o1, pick_cx<T>(o2, vd, vx), pick_cx<T>(o2, vy, c00));
 }
 
 // Fine node d of the bilinear interpolation of the coarse nodal function.
