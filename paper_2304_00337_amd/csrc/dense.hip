@@ -250,8 +250,13 @@ int gram(View<const double> X, int q, View<const double> W, int r, int64_t len, 
 }
 
 // ------------------------------------------------------------------------------------------
-// out_s[:, j] = sum_l S_s[:, l] Y_s[l][j]; thread per row, 8 output columns per block row.
+// out_s[:, j] = sum_l S_s[:, l] Y_s[l][j]; thread per row, 8 output columns per workgroup.  The
+// column blocks of one row range are neighbouring workgroups (blockIdx.x = range * blocks +
+// column block), so they run together and read the basis rows through L2 once from memory.
+namespace {
+
 constexpr int CB = 8;
+
 __global__ __launch_bounds__(256) void k_block_combine(View<const double> Sv, int q,
                                                        const c2* __restrict__ Y, int want, int64_t len,
                                                        View<double> ov, const int* __restrict__ slots) {
@@ -260,13 +265,14 @@ __global__ __launch_bounds__(256) void k_block_combine(View<const double> Sv, in
   const double* S = Sv.p + ((int64_t)slot * Sv.cps + Sv.off) * 2 * len;
   double* out = ov.p + ((int64_t)slot * ov.cps + ov.off) * 2 * len;
   Y += (int64_t)slot * q * want;
-  const int j0 = blockIdx.y * CB;
+  const int ncb = (want + CB - 1) / CB;
+  const int j0 = (int)(blockIdx.x % ncb) * CB;
   for (int e = threadIdx.x; e < q * CB; e += blockDim.x) {
     const int l = e / CB, c = e % CB;
     ys[e] = (j0 + c < want) ? Y[l * want + j0 + c] : c2{0, 0};
   }
   __syncthreads();
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = (int64_t)(blockIdx.x / ncb) * blockDim.x + threadIdx.x;
   if (i >= len) return;
   double accr[CB], acci[CB];
 #pragma unroll
@@ -289,12 +295,15 @@ __global__ __launch_bounds__(256) void k_block_combine(View<const double> Sv, in
   }
 }
 
+}  // namespace
+
 void block_combine(View<const double> S, int q, const double* Y, int want, int64_t len,
                    View<double> out, const Launch& L) {
-  if (L.nact <= 0) return;
-  dim3 grid((unsigned)((len + 255) / 256), (unsigned)((want + CB - 1) / CB), (unsigned)L.nact);
-  k_block_combine<<<grid, 256, (size_t)q * CB * sizeof(c2), L.st>>>(S, q, reinterpret_cast<const c2*>(Y),
-                                                                    want, len, out, L.slots);
+  if (L.nact <= 0 || want <= 0) return;
+  const int ncb = (want + CB - 1) / CB;
+  dim3 grid((unsigned)(((len + 255) / 256) * ncb), 1, (unsigned)L.nact);
+  k_block_combine<<<grid, 256, (size_t)q * CB * sizeof(c2), L.st>>>(S, q, reinterpret_cast<const c2*>(Y), want, len,
+                                                                    out, L.slots);
 }
 
 }  // namespace bl

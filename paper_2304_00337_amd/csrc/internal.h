@@ -73,6 +73,8 @@ void edge_apply(int mode, View<const TI> x, View<const TI> b, View<TO> out, cons
                 const Phase* ph, const double* mu, const Launch& L, double* partial, int* nblk_out);
 void reduce_partials(const double* partial, int nblk, int ncols, int nval, double* out,
                      hipStream_t st);
+// blocks per column of the point kernels (edge_apply's partials per column)
+int apply_blocks(const Geo& g);
 
 // Launch shape of the colour passes of the smoothers (chosen per engine shape by the
 // autotuner; results do not depend on it): threads per block, columns per thread (1 or 2,

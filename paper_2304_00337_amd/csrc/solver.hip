@@ -876,7 +876,7 @@ int engine_create(const bl_grid* grid, const bl_opts* opts, int nslots, hipStrea
     if ((rc = dalloc_t(s, &s->hist[h], col * p * S))) return fail(rc);
   if ((rc = dalloc_t(s, &s->lam_d, (size_t)p * S))) return fail(rc);
   if ((rc = dalloc_t(s, &s->count_d, (size_t)S))) return fail(rc);
-  if ((rc = dalloc_t(s, &s->partial, (size_t)p * S * ((g0.ne + 255) / 256) * 2))) return fail(rc);
+  if ((rc = dalloc_t(s, &s->partial, (size_t)p * S * apply_blocks(g0) * 2))) return fail(rc);
   if ((rc = dalloc_t(s, &s->norms, (size_t)2 * p * S))) return fail(rc);
   s->gram_cap = (int64_t)rr_partial_blocks(g0) * q * q * 4 * S;
   if ((rc = dalloc_t(s, &s->gram_partial, s->gram_cap))) return fail(rc);

@@ -6,6 +6,8 @@
 
 #include "stencil_common.h"
 
+#include <type_traits>
+
 #pragma clang fp contract(off)
 
 namespace bl {
@@ -22,12 +24,52 @@ struct ColumnEdges {
   int n, m, p1, p2;
   Ph<T> p;
   __device__ __forceinline__ Cx<T> get(int c, int d1, int d2) const {
-    return fetch<T, T>(xc, N, n, m, c ? nm : 0, p1 + d1, p2 + d2, p);
+    return fetch<typename std::remove_const<TS>::type, T>(xc, N, n, m, c ? nm : 0, p1 + d1, p2 + d2, p);
   }
   __device__ __forceinline__ void add(int c, int d1, int d2, Cx<T> v) const {
     add_ext<T, T>(xc, N, n, m, c ? nm : 0, p1 + d1, p2 + d2, v, p);
   }
 };
+
+// The same reads for a node whose whole neighbourhood lies inside the grid (no seam): plain
+// indexing, no phase.  (Identical values to ColumnEdges there.)
+template <typename T, typename TS>
+struct DirectEdges {
+  const TS* xc;
+  int64_t N, nm, d;
+  int n;
+  __device__ __forceinline__ Cx<T> get(int c, int d1, int d2) const {
+    const int64_t i = (c ? nm : 0) + d + (int64_t)d2 * n + d1;
+    return {(T)xc[i], (T)xc[N + i]};
+  }
+};
+template <typename T, typename TS>
+struct DirectNodes {
+  const TS* xc;
+  int64_t N, d;
+  int n;
+  __device__ __forceinline__ Cx<T> get(int d1, int d2) const {
+    const int64_t i = d + (int64_t)d2 * n + d1;
+    return {(T)xc[i], (T)xc[N + i]};
+  }
+};
+
+// Workgroup tiles of the point kernels: kPtW x kPtH nodes (one per thread), row-major tiles;
+// `inner` (uniform in the workgroup) when every node of the tile and its 3 x 3 neighbourhood
+// lie inside the grid, so that the reads need no seam handling.
+constexpr int kPtW = 64, kPtH = 4;
+struct PointTile {
+  int p1, p2;
+  bool inner;
+};
+__device__ __forceinline__ PointTile point_tile(int n, int m) {
+  const int tiles_x = (n + kPtW - 1) / kPtW;
+  const int t = (int)blockIdx.x;
+  const int tx0 = (t % tiles_x) * kPtW, ty0 = (t / tiles_x) * kPtH;
+  return {tx0 + (int)(threadIdx.x % kPtW), ty0 + (int)(threadIdx.x / kPtW),
+          tx0 >= 1 && tx0 + kPtW <= n - 1 && ty0 >= 1 && ty0 + kPtH <= m - 1};
+}
+inline int point_tiles(int n, int m) { return ((n + kPtW - 1) / kPtW) * ((m + kPtH - 1) / kPtH); }
 
 // (A x) and (M x) at the edge of component c (0: x-edge, 1: y-edge) owned by the accessor's
 // node, from the curls of its two cells and its two parallel neighbours.  ka, kb: kappa of

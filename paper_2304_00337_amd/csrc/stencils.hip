@@ -22,7 +22,20 @@ namespace bl {
 
 // ------------------------------------------------------------------------------------------
 // Edge operators: A (curl-curl with kappa = 1/eps), M (mass), K = A + mu M and residuals.
-// Thread per (edge, column); T is the arithmetic type (double, or float with float data).
+// Thread per (node, column): the node's x-edge and y-edge; T is the arithmetic type (double,
+// or float with float data).  Tiles away from the seam read without the Bloch extension.
+template <typename T, int MODE, typename XA>
+__device__ __forceinline__ void edge_point(const XA& X, int c, T ka, T kb, T s, T mm, T mu, T lam, Cx<T> b,
+                                           Cx<T>& r, Cx<T>& Mu) {
+  Cx<T> Au;
+  edge_AM_acc<T>(X, c, ka, kb, s, mm, Au, Mu);
+  if (MODE == EM_A) r = Au;
+  else if (MODE == EM_M) r = Mu;
+  else if (MODE == EM_K) r = Au + (mu * Mu);
+  else if (MODE == EM_RESID_K) r = b - (Au + (mu * Mu));
+  else r = Au - (lam * Mu);
+}
+
 template <typename TI, typename TO, typename T, int MODE>
 __global__ __launch_bounds__(256) void k_edge_apply(View<const TI> xv, View<const TI> bv, View<TO> ov,
                                                     const double* __restrict__ k64,
@@ -33,41 +46,51 @@ __global__ __launch_bounds__(256) void k_edge_apply(View<const TI> xv, View<cons
                                                     const int* __restrict__ slots, int ncps,
                                                     double* __restrict__ partial) {
   const SJ sj = slot_col(slots, ncps);
-  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int n = g.n, m = g.m;
   const int64_t nm = g.nm, N = g.ne;
-  const Ph<T> p = cast_phase<T>(phs[sj.slot]);
-  const TI* xc = colp(xv, sj, N);
-  k64 += (int64_t)sj.slot * nm;
-  k32 += (int64_t)sj.slot * nm;
-  T rr = 0, mm = 0;
-  if (d < N) {
-    Cx<T> Au, Mu;
-    edge_AM<TI, T>(xc, N, n, m, nm, d, [&](int64_t i) { return kap<T>(k64, k32, i); }, (T)g.s, (T)g.mx,
-                   (T)g.my, p, Au, Mu);
-    Cx<T> r;
-    if (MODE == EM_A) {
-      r = Au;
-    } else if (MODE == EM_M) {
-      r = Mu;
-    } else if (MODE == EM_K) {
-      r = Au + ((T)mus[sj.slot] * Mu);
-    } else if (MODE == EM_RESID_K) {
+  const PointTile pt = point_tile(n, m);
+  T rr = 0, mmv = 0;
+  if (pt.p1 < n && pt.p2 < m) {
+    const Ph<T> p = cast_phase<T>(phs[sj.slot]);
+    const TI* xc = colp(xv, sj, N);
+    k64 += (int64_t)sj.slot * nm;
+    k32 += (int64_t)sj.slot * nm;
+    const int64_t d = (int64_t)pt.p2 * n + pt.p1;
+    const T kh = kap<T>(k64, k32, d);
+    const T kbelow = kap<T>(k64, k32, (int64_t)wrapi(pt.p2 - 1, m) * n + pt.p1);
+    const T kleft = kap<T>(k64, k32, (int64_t)pt.p2 * n + wrapi(pt.p1 - 1, n));
+    const T mu = (MODE == EM_K || MODE == EM_RESID_K) ? (T)mus[sj.slot] : (T)0;
+    const T lm = MODE == EM_EIGRES ? (T)lam[(int64_t)sj.slot * lam_cps + sj.j] : (T)0;
+    Cx<T> bx{0, 0}, by{0, 0};
+    if (MODE == EM_RESID_K) {
       const TI* bc = colp(bv, sj, N);
-      r = Cx<T>{(T)bc[d], (T)bc[N + d]} - (Au + ((T)mus[sj.slot] * Mu));
+      bx = Cx<T>{(T)bc[d], (T)bc[N + d]};
+      by = Cx<T>{(T)bc[nm + d], (T)bc[N + nm + d]};
+    }
+    Cx<T> rx, ry, mx, my;
+    if (pt.inner) {
+      const DirectEdges<T, TI> X{xc, N, nm, d, n};
+      edge_point<T, MODE>(X, 0, kbelow, kh, (T)g.s, (T)g.mx, mu, lm, bx, rx, mx);
+      edge_point<T, MODE>(X, 1, kh, kleft, (T)g.s, (T)g.my, mu, lm, by, ry, my);
     } else {
-      r = Au - ((T)lam[(int64_t)sj.slot * lam_cps + sj.j] * Mu);
-      rr = r.re * r.re + r.im * r.im;
-      mm = Mu.re * Mu.re + Mu.im * Mu.im;
+      const ColumnEdges<T, const TI> X{xc, N, nm, n, m, pt.p1, pt.p2, p};
+      edge_point<T, MODE>(X, 0, kbelow, kh, (T)g.s, (T)g.mx, mu, lm, bx, rx, mx);
+      edge_point<T, MODE>(X, 1, kh, kleft, (T)g.s, (T)g.my, mu, lm, by, ry, my);
     }
     TO* oc = colp(ov, sj, N);
-    oc[d] = (TO)r.re;
-    oc[N + d] = (TO)r.im;
+    oc[d] = (TO)rx.re;
+    oc[N + d] = (TO)rx.im;
+    oc[nm + d] = (TO)ry.re;
+    oc[N + nm + d] = (TO)ry.im;
+    if (MODE == EM_EIGRES) {
+      rr = (rx.re * rx.re + rx.im * rx.im) + (ry.re * ry.re + ry.im * ry.im);
+      mmv = (mx.re * mx.re + mx.im * mx.im) + (my.re * my.re + my.im * my.im);
+    }
   }
   if (MODE == EM_EIGRES) {
     // block reduction of the two squared norms, one partial per block
     __shared__ double sh[2][256 / 64];
-    double a = rr, c = mm;
+    double a = rr, c = mmv;
     for (int o = 32; o > 0; o >>= 1) {
       a += __shfl_down(a, o, 64);
       c += __shfl_down(c, o, 64);
@@ -85,16 +108,17 @@ __global__ __launch_bounds__(256) void k_edge_apply(View<const TI> xv, View<cons
   }
 }
 
+int apply_blocks(const Geo& g) { return point_tiles(g.n, g.m); }
+
 template <typename TI, typename TO>
 void edge_apply(int mode, View<const TI> x, View<const TI> b, View<TO> out, const double* kappa64,
                 const float* kappa32, const double* lam, int lam_cps, const Geo& g,
                 const Phase* ph, const double* mu, const Launch& L, double* partial, int* nblk_out) {
   using T = typename std::conditional<std::is_same<TI, double>::value, double, float>::type;
-  const int bs = 256;
-  dim3 grid((unsigned)((g.ne + bs - 1) / bs), (unsigned)(L.nact * L.ncps));
+  dim3 grid((unsigned)point_tiles(g.n, g.m), (unsigned)(L.nact * L.ncps));
   if (nblk_out) *nblk_out = (int)grid.x;
   if (grid.y == 0) return;
-#define BL_EA(MD) k_edge_apply<TI, TO, T, MD><<<grid, bs, 0, L.st>>>(x, b, out, kappa64, kappa32, lam, lam_cps, g, ph, mu, L.slots, L.ncps, partial)
+#define BL_EA(MD) k_edge_apply<TI, TO, T, MD><<<grid, kPtW * kPtH, 0, L.st>>>(x, b, out, kappa64, kappa32, lam, lam_cps, g, ph, mu, L.slots, L.ncps, partial)
   switch (mode) {
     case EM_A: BL_EA(EM_A); break;
     case EM_M: BL_EA(EM_M); break;
@@ -376,12 +400,17 @@ __global__ __launch_bounds__(256) void k_nodal_apply(View<const T> xv, View<cons
                                                      NodalStencil s, const int* __restrict__ slots,
                                                      int ncps) {
   const SJ sj = slot_col(slots, ncps);
-  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (d >= g.nm) return;
-  const Ph<T> p = cast_phase<T>(phs[sj.slot]);
-  const int64_t N = g.nm;
+  const PointTile pt = point_tile(g.n, g.m);
+  if (pt.p1 >= g.n || pt.p2 >= g.m) return;
+  const int64_t N = g.nm, d = (int64_t)pt.p2 * g.n + pt.p1;
   const T* xc = colp(xv, sj, N);
-  Cx<T> v = nodal_stencil<T>(xc, N, g.n, g.m, (int)(d % g.n), (int)(d / g.n), s, p);
+  Cx<T> v;
+  if (pt.inner) {
+    v = nodal_stencil_at<T>(DirectNodes<T, T>{xc, N, d, g.n}, s);
+  } else {
+    const Ph<T> p = cast_phase<T>(phs[sj.slot]);
+    v = nodal_stencil<T>(xc, N, g.n, g.m, pt.p1, pt.p2, s, p);
+  }
   if (RESID) {
     const T* bc = colp(bv, sj, N);
     v = Cx<T>{bc[d], bc[N + d]} - v;
@@ -394,10 +423,10 @@ __global__ __launch_bounds__(256) void k_nodal_apply(View<const T> xv, View<cons
 template <typename T>
 void nodal_apply(View<const T> x, View<const T> b, View<T> out, const Geo& g, const Phase* ph,
                  const NodalStencil& c, bool resid, const Launch& L) {
-  dim3 grid((unsigned)((g.nm + 255) / 256), (unsigned)(L.nact * L.ncps));
+  dim3 grid((unsigned)point_tiles(g.n, g.m), (unsigned)(L.nact * L.ncps));
   if (grid.y == 0) return;
-  if (resid) k_nodal_apply<T, true><<<grid, 256, 0, L.st>>>(x, b, out, g, ph, c, L.slots, L.ncps);
-  else k_nodal_apply<T, false><<<grid, 256, 0, L.st>>>(x, b, out, g, ph, c, L.slots, L.ncps);
+  if (resid) k_nodal_apply<T, true><<<grid, kPtW * kPtH, 0, L.st>>>(x, b, out, g, ph, c, L.slots, L.ncps);
+  else k_nodal_apply<T, false><<<grid, kPtW * kPtH, 0, L.st>>>(x, b, out, g, ph, c, L.slots, L.ncps);
 }
 template void nodal_apply<double>(View<const double>, View<const double>, View<double>, const Geo&, const Phase*, const NodalStencil&, bool, const Launch&);
 template void nodal_apply<float>(View<const float>, View<const float>, View<float>, const Geo&, const Phase*, const NodalStencil&, bool, const Launch&);
@@ -509,29 +538,36 @@ template void nodal_prolong_to<float>(View<const float>, const Geo&, View<const 
 // out (nodal) = L^* M u (edge).  (L^* v)(p) = v_x(p1-1,p2) - v_x(p1,p2) + v_y(p1,p2-1) - v_y(p1,p2)
 // in extended coordinates, with v = M u evaluated on the fly.  Arithmetic in FP64 (the
 // right-hand side of the projection keeps the outer precision).
+template <typename T, typename XA>
+__device__ __forceinline__ Cx<T> lhm_at(const XA& X, T mx, T my) {
+  const T two3 = 2.0 / 3.0, one6 = 1.0 / 6.0;
+  auto mx_at = [&](int d1) {
+    return mx * ((two3 * X.get(0, d1, 0)) + one6 * (X.get(0, d1, 1) + X.get(0, d1, -1)));
+  };
+  auto my_at = [&](int d2) {
+    return my * ((two3 * X.get(1, 0, d2)) + one6 * (X.get(1, 1, d2) + X.get(1, -1, d2)));
+  };
+  return mx_at(-1) - mx_at(0) + my_at(-1) - my_at(0);
+}
+
 template <typename TI, typename TO>
 __global__ __launch_bounds__(256) void k_lhm(View<const TI> uv, View<TO> ov, Geo g,
                                              const Phase* __restrict__ phs,
                                              const int* __restrict__ slots, int ncps) {
   using T = double;
   const SJ sj = slot_col(slots, ncps);
-  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (d >= g.nm) return;
-  const Ph<T> p = cast_phase<T>(phs[sj.slot]);
   const int n = g.n, m = g.m;
-  const int64_t N = g.ne, nm = g.nm;
+  const PointTile pt = point_tile(n, m);
+  if (pt.p1 >= n || pt.p2 >= m) return;
+  const int64_t N = g.ne, nm = g.nm, d = (int64_t)pt.p2 * n + pt.p1;
   const TI* c = colp(uv, sj, N);
-  const int p1 = (int)(d % n), p2 = (int)(d / n);
-  const T two3 = 2.0 / 3.0, one6 = 1.0 / 6.0;
-  auto mx_at = [&](int j1, int j2) {
-    return (T)g.mx * ((two3 * fetch<TI, T>(c, N, n, m, 0, j1, j2, p)) +
-                      one6 * (fetch<TI, T>(c, N, n, m, 0, j1, j2 + 1, p) + fetch<TI, T>(c, N, n, m, 0, j1, j2 - 1, p)));
-  };
-  auto my_at = [&](int j1, int j2) {
-    return (T)g.my * ((two3 * fetch<TI, T>(c, N, n, m, nm, j1, j2, p)) +
-                      one6 * (fetch<TI, T>(c, N, n, m, nm, j1 + 1, j2, p) + fetch<TI, T>(c, N, n, m, nm, j1 - 1, j2, p)));
-  };
-  const Cx<T> v = mx_at(p1 - 1, p2) - mx_at(p1, p2) + my_at(p1, p2 - 1) - my_at(p1, p2);
+  Cx<T> v;
+  if (pt.inner) {
+    v = lhm_at<T>(DirectEdges<T, TI>{c, N, nm, d, n}, (T)g.mx, (T)g.my);
+  } else {
+    const Ph<T> p = cast_phase<T>(phs[sj.slot]);
+    v = lhm_at<T>(ColumnEdges<T, const TI>{c, N, nm, n, m, pt.p1, pt.p2, p}, (T)g.mx, (T)g.my);
+  }
   TO* o = colp(ov, sj, nm);
   o[d] = (TO)v.re;
   o[nm + d] = (TO)v.im;
@@ -539,9 +575,9 @@ __global__ __launch_bounds__(256) void k_lhm(View<const TI> uv, View<TO> ov, Geo
 
 template <typename TI, typename TO>
 void lhm(View<const TI> u, View<TO> out, const Geo& g, const Phase* ph, const Launch& L) {
-  dim3 grid((unsigned)((g.nm + 255) / 256), (unsigned)(L.nact * L.ncps));
+  dim3 grid((unsigned)point_tiles(g.n, g.m), (unsigned)(L.nact * L.ncps));
   if (grid.y == 0) return;
-  k_lhm<TI, TO><<<grid, 256, 0, L.st>>>(u, out, g, ph, L.slots, L.ncps);
+  k_lhm<TI, TO><<<grid, kPtW * kPtH, 0, L.st>>>(u, out, g, ph, L.slots, L.ncps);
 }
 template void lhm<double, double>(View<const double>, View<double>, const Geo&, const Phase*, const Launch&);
 template void lhm<double, float>(View<const double>, View<float>, const Geo&, const Phase*, const Launch&);
