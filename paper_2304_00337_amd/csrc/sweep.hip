@@ -156,6 +156,73 @@ struct TileNodes {
   }
 };
 
+// Patches each colour pass has to update.  Walking the passes backwards from the region that
+// must be exact after the sweep (the tile, or the residual window's inputs), a pass needs the
+// patches of its colour that write into the region still required, and the values those
+// patches read must then be exact before it; every other patch of the box only feeds values
+// that never reach the tile.  The bounding rectangle of the needed patches (box positions,
+// inclusive) is formed at compile time for every box shape and colour order.
+struct PassRect {
+  int x0, x1, y0, y1;
+};
+struct SweepRects {
+  PassRect r[4];   // in sweep order
+  bool ok;         // no needed patch lies on the box's outermost ring (the halo suffices)
+};
+constexpr int kMaxBox = 80;
+constexpr SweepRects sweep_rects(bool edge, int BX, int BY, int LO, int TX, int TY, int EA, int EB, bool bwd) {
+  // need[c][by][bx]: component c (x-edge / y-edge; nodal values use c = 0) must be exact
+  bool need[2][kMaxBox][kMaxBox] = {};
+  for (int y = LO - EA; y < LO + TY + EB; ++y)
+    for (int x = LO - EA; x < LO + TX + EB; ++x) need[0][y][x] = need[1][y][x] = true;
+  // an edge patch at P reads x-edges at P + XR and y-edges at P + YR (patch_update) and writes
+  // the x-edges of P and P - (1, 0) and the y-edges of P and P - (0, 1); a nodal point reads
+  // its 3 x 3 neighbourhood and writes P
+  constexpr int XR[6][2] = {{0, 0}, {0, 1}, {0, -1}, {-1, 0}, {-1, 1}, {-1, -1}};
+  constexpr int YR[6][2] = {{0, 0}, {1, 0}, {-1, 0}, {0, -1}, {1, -1}, {-1, -1}};
+  SweepRects out{};
+  out.ok = BX <= kMaxBox && BY <= kMaxBox;
+  for (int k = 3; k >= 0; --k) {
+    const int colour = bwd ? 3 - k : k;
+    const int px = colour & 1, py = colour >> 1;
+    PassRect r{kMaxBox, -1, kMaxBox, -1};
+    bool hit[kMaxBox][kMaxBox] = {};
+    for (int y = 0; y < BY; ++y)
+      for (int x = 0; x < BX; ++x) {
+        if ((x & 1) != px || (y & 1) != py) continue;
+        hit[y][x] = edge ? (need[0][y][x] || (x > 0 && need[0][y][x - 1]) || need[1][y][x] ||
+                            (y > 0 && need[1][y - 1][x]))
+                         : need[0][y][x];
+        if (!hit[y][x]) continue;
+        if (x == 0 || y == 0 || x == BX - 1 || y == BY - 1) {   // not updatable: the halo is short
+          out.ok = false;
+          continue;
+        }
+        if (x < r.x0) r.x0 = x;
+        if (x > r.x1) r.x1 = x;
+        if (y < r.y0) r.y0 = y;
+        if (y > r.y1) r.y1 = y;
+      }
+    // the needed patches' reads must be exact before the pass (the other patches of the
+    // rectangle are updated too, but nothing needed reads what they write)
+    for (int y = 1; y < BY - 1; ++y)
+      for (int x = 1; x < BX - 1; ++x) {
+        if (!hit[y][x]) continue;
+        if (edge) {
+          for (int q = 0; q < 6; ++q) {
+            need[0][y + XR[q][1]][x + XR[q][0]] = true;
+            need[1][y + YR[q][1]][x + YR[q][0]] = true;
+          }
+        } else {
+          for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) need[0][y + dy][x + dx] = true;
+        }
+      }
+    out.r[k] = r;
+  }
+  return out;
+}
+
 // Column and tile of this workgroup: blockIdx.y = active slot x column, blockIdx.x = tile
 // (XCD-major order when there are at least 8 tiles, so that neighbouring tiles share an L2).
 struct TileRef {
@@ -180,12 +247,13 @@ struct EdgeArgs {
 // One colour pass of the edge smoother on the box (patch nodes at box positions 1 .. B-2 of
 // the colour's parity; the box origin t0 - kLo is even and n, m are even, so the parity of a
 // position is that of its canonical node).
-template <typename T, int BX, int BY, int COLOUR, bool CX, bool CY>
+template <typename T, int BX, int BY, int COLOUR, bool CX, bool CY, int X0, int X1, int Y0, int Y1>
 __device__ __forceinline__ void edge_pass(T* pl, const T* bc, const EdgeArgs& a, int slot, int ox, int oy, int n,
                                           int m, int64_t N, int64_t nm, T mu, const Ph<T>& p) {
   constexpr int PX = COLOUR & 1, PY = COLOUR >> 1;
-  constexpr int B0X = PX ? 1 : 2, B0Y = PY ? 1 : 2;
-  constexpr int CNX = (BX - 2 - B0X) / 2 + 1, CNY = (BY - 2 - B0Y) / 2 + 1;
+  static_assert((X0 & 1) == PX && (Y0 & 1) == PY && X0 >= 1 && Y0 >= 1 && X1 <= BX - 2 && Y1 <= BY - 2, "pass rectangle");
+  constexpr int B0X = X0, B0Y = Y0;
+  constexpr int CNX = (X1 - X0) / 2 + 1, CNY = (Y1 - Y0) / 2 + 1;
   const double* k64 = a.k64 + (int64_t)slot * nm;
   const float* k32 = a.k32 + (int64_t)slot * nm;
   const T* sib = pick_si<T>(a.si64, a.si32) + kPatchW * (int64_t)slot * nm;
@@ -209,17 +277,20 @@ __device__ __forceinline__ void edge_pass(T* pl, const T* bc, const EdgeArgs& a,
   }
 }
 
-template <typename T, int BX, int BY, bool BWD, bool CX, bool CY>
+template <typename T, int BX, int BY, bool BWD, bool CX, bool CY, int LO, int TX, int TY, int EA, int EB>
 __device__ __forceinline__ void edge_passes(T* pl, const T* bc, const EdgeArgs& a, int slot, int ox, int oy, int n,
                                             int m, int64_t N, int64_t nm, T mu, const Ph<T>& p) {
-  edge_pass<T, BX, BY, BWD ? 3 : 0, CX, CY>(pl, bc, a, slot, ox, oy, n, m, N, nm, mu, p);
+  constexpr SweepRects R = sweep_rects(true, BX, BY, LO, TX, TY, EA, EB, BWD);
+  static_assert(R.ok, "the halo does not cover the sweep's dependency cone");
+#define BL_EPASS(k, c)                                                                                             \
+  edge_pass<T, BX, BY, c, CX, CY, R.r[k].x0, R.r[k].x1, R.r[k].y0, R.r[k].y1>(pl, bc, a, slot, ox, oy, n, m, N, nm, mu, \
+                                                                            p);                                       \
   __syncthreads();
-  edge_pass<T, BX, BY, BWD ? 2 : 1, CX, CY>(pl, bc, a, slot, ox, oy, n, m, N, nm, mu, p);
-  __syncthreads();
-  edge_pass<T, BX, BY, BWD ? 1 : 2, CX, CY>(pl, bc, a, slot, ox, oy, n, m, N, nm, mu, p);
-  __syncthreads();
-  edge_pass<T, BX, BY, BWD ? 0 : 3, CX, CY>(pl, bc, a, slot, ox, oy, n, m, N, nm, mu, p);
-  __syncthreads();
+  BL_EPASS(0, BWD ? 3 : 0)
+  BL_EPASS(1, BWD ? 2 : 1)
+  BL_EPASS(2, BWD ? 1 : 2)
+  BL_EPASS(3, BWD ? 0 : 3)
+#undef BL_EPASS
 }
 
 // Residual b - (A + mu M) x at both edges owned by the box positions of parity (PX, PY)
@@ -345,10 +416,15 @@ __global__ __launch_bounds__(kThreads) void k_edge_sweep(View<const T> xin, View
   }
   __syncthreads();
   const T mu = (T)mus[tr.slot];
-  if (!cx && !cy) edge_passes<T, BX, BY, BWD, false, false>(pl, bc, a, tr.slot, ox, oy, n, m, N, nm, mu, p);
-  else if (!cy) edge_passes<T, BX, BY, BWD, true, false>(pl, bc, a, tr.slot, ox, oy, n, m, N, nm, mu, p);
-  else if (!cx) edge_passes<T, BX, BY, BWD, false, true>(pl, bc, a, tr.slot, ox, oy, n, m, N, nm, mu, p);
-  else edge_passes<T, BX, BY, BWD, true, true>(pl, bc, a, tr.slot, ox, oy, n, m, N, nm, mu, p);
+  constexpr int EA = RES ? 2 : 0, EB = RES ? 1 : 0;   // exact margin the residual window needs
+  if (!cx && !cy)
+    edge_passes<T, BX, BY, BWD, false, false, LO, TX, TY, EA, EB>(pl, bc, a, tr.slot, ox, oy, n, m, N, nm, mu, p);
+  else if (!cy)
+    edge_passes<T, BX, BY, BWD, true, false, LO, TX, TY, EA, EB>(pl, bc, a, tr.slot, ox, oy, n, m, N, nm, mu, p);
+  else if (!cx)
+    edge_passes<T, BX, BY, BWD, false, true, LO, TX, TY, EA, EB>(pl, bc, a, tr.slot, ox, oy, n, m, N, nm, mu, p);
+  else
+    edge_passes<T, BX, BY, BWD, true, true, LO, TX, TY, EA, EB>(pl, bc, a, tr.slot, ox, oy, n, m, N, nm, mu, p);
   for (int e = tid; e < TX * TY; e += kThreads) {
     const int ix = e % TX, iy = e / TX;
     const int c1 = tr.t0x + ix, c2 = tr.t0y + iy;
@@ -378,13 +454,14 @@ __global__ __launch_bounds__(kThreads) void k_edge_sweep(View<const T> xin, View
 }
 
 // One colour pass of the nodal point Gauss-Seidel on the box.
-template <typename T, int BX, int BY, int COLOUR, bool CX, bool CY>
+template <typename T, int BX, int BY, int COLOUR, bool CX, bool CY, int X0, int X1, int Y0, int Y1>
 __device__ __forceinline__ void nodal_pass(T* pl, const T* bc, const NodalStencil& st, int ox, int oy, int n, int m,
                                            int64_t N, const Ph<T>& p) {
   using S = Split<BX, BY>;
   constexpr int PX = COLOUR & 1, PY = COLOUR >> 1;
-  constexpr int B0X = PX ? 1 : 2, B0Y = PY ? 1 : 2;
-  constexpr int CNX = (BX - 2 - B0X) / 2 + 1, CNY = (BY - 2 - B0Y) / 2 + 1;
+  static_assert((X0 & 1) == PX && (Y0 & 1) == PY && X0 >= 1 && Y0 >= 1 && X1 <= BX - 2 && Y1 <= BY - 2, "pass rectangle");
+  constexpr int B0X = X0, B0Y = Y0;
+  constexpr int CNX = (X1 - X0) / 2 + 1, CNY = (Y1 - Y0) / 2 + 1;
   const T inv = (T)1 / (T)st.c0;
   for (int t = threadIdx.x; t < CNX * CNY; t += kThreads) {
     const int i = (B0X >> 1) + t % CNX, j = (B0Y >> 1) + t / CNX;
@@ -400,17 +477,19 @@ __device__ __forceinline__ void nodal_pass(T* pl, const T* bc, const NodalStenci
   }
 }
 
-template <typename T, int BX, int BY, bool BWD, bool CX, bool CY>
+template <typename T, int BX, int BY, bool BWD, bool CX, bool CY, int LO, int TX, int TY, int EA, int EB>
 __device__ __forceinline__ void nodal_passes(T* pl, const T* bc, const NodalStencil& st, int ox, int oy, int n, int m,
                                              int64_t N, const Ph<T>& p) {
-  nodal_pass<T, BX, BY, BWD ? 3 : 0, CX, CY>(pl, bc, st, ox, oy, n, m, N, p);
+  constexpr SweepRects R = sweep_rects(false, BX, BY, LO, TX, TY, EA, EB, BWD);
+  static_assert(R.ok, "the halo does not cover the sweep's dependency cone");
+#define BL_NPASS(k, c)                                                                                             \
+  nodal_pass<T, BX, BY, c, CX, CY, R.r[k].x0, R.r[k].x1, R.r[k].y0, R.r[k].y1>(pl, bc, st, ox, oy, n, m, N, p); \
   __syncthreads();
-  nodal_pass<T, BX, BY, BWD ? 2 : 1, CX, CY>(pl, bc, st, ox, oy, n, m, N, p);
-  __syncthreads();
-  nodal_pass<T, BX, BY, BWD ? 1 : 2, CX, CY>(pl, bc, st, ox, oy, n, m, N, p);
-  __syncthreads();
-  nodal_pass<T, BX, BY, BWD ? 0 : 3, CX, CY>(pl, bc, st, ox, oy, n, m, N, p);
-  __syncthreads();
+  BL_NPASS(0, BWD ? 3 : 0)
+  BL_NPASS(1, BWD ? 2 : 1)
+  BL_NPASS(2, BWD ? 1 : 2)
+  BL_NPASS(3, BWD ? 0 : 3)
+#undef BL_NPASS
 }
 
 // Residual b - P x on the box positions of parity (PX, PY) inside the residual window
@@ -516,10 +595,11 @@ __global__ __launch_bounds__(kThreads) void k_nodal_sweep(View<const T> xin, Vie
     }
   }
   __syncthreads();
-  if (!cx && !cy) nodal_passes<T, BX, BY, BWD, false, false>(pl, bc, st, ox, oy, n, m, N, p);
-  else if (!cy) nodal_passes<T, BX, BY, BWD, true, false>(pl, bc, st, ox, oy, n, m, N, p);
-  else if (!cx) nodal_passes<T, BX, BY, BWD, false, true>(pl, bc, st, ox, oy, n, m, N, p);
-  else nodal_passes<T, BX, BY, BWD, true, true>(pl, bc, st, ox, oy, n, m, N, p);
+  constexpr int EA = RES ? 2 : 0, EB = RES ? 1 : 0;   // exact margin the residual window needs
+  if (!cx && !cy) nodal_passes<T, BX, BY, BWD, false, false, LO, TX, TY, EA, EB>(pl, bc, st, ox, oy, n, m, N, p);
+  else if (!cy) nodal_passes<T, BX, BY, BWD, true, false, LO, TX, TY, EA, EB>(pl, bc, st, ox, oy, n, m, N, p);
+  else if (!cx) nodal_passes<T, BX, BY, BWD, false, true, LO, TX, TY, EA, EB>(pl, bc, st, ox, oy, n, m, N, p);
+  else nodal_passes<T, BX, BY, BWD, true, true, LO, TX, TY, EA, EB>(pl, bc, st, ox, oy, n, m, N, p);
   const T* bs = BAS ? colp(fz.base, sj, N) : nullptr;
   for (int e = tid; e < TX * TY; e += kThreads) {
     const int ix = e % TX, iy = e / TX;
