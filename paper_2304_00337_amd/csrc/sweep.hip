@@ -35,7 +35,10 @@ namespace {
 constexpr int kLo = 4;    // halo below / left of a tile, nodes (even: keeps colour parity)
 constexpr int kHiE = 5;   // halo above / right, edge sweeps
 constexpr int kHiN = 4;   // halo above / right, nodal sweeps
-constexpr int kThreads = 256;
+constexpr int kMaxThreads = 512;   // workgroups of 256 threads, or 512 where the launch has few tiles
+// (a colour pass of a 32 x 32 tile then takes one round instead of two: the coarser levels'
+// launches are too small to hide the rounds' latency behind other workgroups)
+__device__ __forceinline__ int nthreads() { return (int)blockDim.x; }
 
 // MODE bits of a sweep with level transfers folded in: kRestrict (forward sweeps) also forms
 // the residual of the result and restricts it to the coarse right-hand side; kProlong starts
@@ -259,7 +262,7 @@ __device__ __forceinline__ void edge_pass(T* pl, const T* bc, const EdgeArgs& a,
   const T* sib = pick_si<T>(a.si64, a.si32) + kPatchW * (int64_t)slot * nm;
   const T s = (T)a.s;
   const T mmx = mu * (T)a.mx, mmy = mu * (T)a.my;
-  for (int t = threadIdx.x; t < CNX * CNY; t += kThreads) {
+  for (int t = threadIdx.x; t < CNX * CNY; t += nthreads()) {
     const int i = (B0X >> 1) + t % CNX, j = (B0Y >> 1) + t / CNX;
     const int bx = 2 * i + PX, by = 2 * j + PY;
     const int p1 = CX ? wrapm(ox + bx, n) : ox + bx;
@@ -306,7 +309,7 @@ __device__ __forceinline__ void edge_resid_pass(T* pl, T* rl, const T* bc, const
   const double* k64 = a.k64 + (int64_t)slot * nm;
   const float* k32 = a.k32 + (int64_t)slot * nm;
   const T s = (T)a.s, mx = (T)a.mx, my = (T)a.my;
-  for (int t = threadIdx.x; t < CNX * CNY; t += kThreads) {
+  for (int t = threadIdx.x; t < CNX * CNY; t += nthreads()) {
     const int i = I0 + t % CNX, j = J0 + t / CNX;
     const int bx = 2 * i + PX, by = 2 * j + PY;
     const int p1 = CX ? wrapm(ox + bx, n) : ox + bx;
@@ -351,7 +354,7 @@ __device__ __forceinline__ void edge_restrict_tile(T* pl, T* rl, const T* bc, T*
   edge_resid_pass<T, BX, BY, 1, 1, CX, CY, LO, TX, TY>(pl, rl, bc, a, slot, ox, oy, n, m, N, nm, mu, p);
   __syncthreads();
   constexpr int HX = TX / 2, HY = TY / 2;
-  for (int t = threadIdx.x; t < HX * HY; t += kThreads) {
+  for (int t = threadIdx.x; t < HX * HY; t += nthreads()) {
     const int jx = t % HX, jy = t / HX;
     const int f1 = t0x + 2 * jx, f2 = t0y + 2 * jy;
     if (f1 >= n || f2 >= m) continue;
@@ -367,7 +370,7 @@ __device__ __forceinline__ void edge_restrict_tile(T* pl, T* rl, const T* bc, T*
 }
 
 template <typename T, int TX, int TY, bool BWD, int MODE>
-__global__ __launch_bounds__(kThreads) void k_edge_sweep(View<const T> xin, View<T> xout, View<const T> bv, EdgeArgs a,
+__global__ __launch_bounds__(kMaxThreads) void k_edge_sweep(View<const T> xin, View<T> xout, View<const T> bv, EdgeArgs a,
                                                          Geo g, const Phase* __restrict__ phs,
                                                          const double* __restrict__ mus, int zero_start,
                                                          const int* __restrict__ slots, int ncps, int tiles_x,
@@ -390,11 +393,11 @@ __global__ __launch_bounds__(kThreads) void k_edge_sweep(View<const T> xin, View
   const T* bc = colp(bv, sj, N);
   const Ph<T> p = cast_phase<T>(phs[tr.slot]);
   if (zero_start) {
-    for (int e = tid; e < 4 * S::N; e += kThreads) pl[e] = (T)0;
+    for (int e = tid; e < 4 * S::N; e += nthreads()) pl[e] = (T)0;
   } else {
     const T* xc = colp(xin, sj, N);
     const T* cc = PRO ? colp(fz.xc, sj, fz.gc.ne) : nullptr;
-    for (int e = tid; e < BX * BY; e += kThreads) {
+    for (int e = tid; e < BX * BY; e += nthreads()) {
       const int bx = e % BX, by = e / BX;
       const int c1 = cx ? wrapm(ox + bx, n) : ox + bx, c2 = cy ? wrapm(oy + by, m) : oy + by;
       const int64_t i = (int64_t)c2 * n + c1;
@@ -425,7 +428,7 @@ __global__ __launch_bounds__(kThreads) void k_edge_sweep(View<const T> xin, View
     edge_passes<T, BX, BY, BWD, false, true, LO, TX, TY, EA, EB>(pl, bc, a, tr.slot, ox, oy, n, m, N, nm, mu, p);
   else
     edge_passes<T, BX, BY, BWD, true, true, LO, TX, TY, EA, EB>(pl, bc, a, tr.slot, ox, oy, n, m, N, nm, mu, p);
-  for (int e = tid; e < TX * TY; e += kThreads) {
+  for (int e = tid; e < TX * TY; e += nthreads()) {
     const int ix = e % TX, iy = e / TX;
     const int c1 = tr.t0x + ix, c2 = tr.t0y + iy;
     if (c1 >= n || c2 >= m) continue;
@@ -463,7 +466,7 @@ __device__ __forceinline__ void nodal_pass(T* pl, const T* bc, const NodalStenci
   constexpr int B0X = X0, B0Y = Y0;
   constexpr int CNX = (X1 - X0) / 2 + 1, CNY = (Y1 - Y0) / 2 + 1;
   const T inv = (T)1 / (T)st.c0;
-  for (int t = threadIdx.x; t < CNX * CNY; t += kThreads) {
+  for (int t = threadIdx.x; t < CNX * CNY; t += nthreads()) {
     const int i = (B0X >> 1) + t % CNX, j = (B0Y >> 1) + t / CNX;
     const int bx = 2 * i + PX, by = 2 * j + PY;
     const int p1 = CX ? wrapm(ox + bx, n) : ox + bx;
@@ -503,7 +506,7 @@ __device__ __forceinline__ void nodal_resid_pass(const T* pl, T* rl, const T* bc
   constexpr int I0 = (R0 - PX + 1) / 2, I1 = (LO + TX - 1 - PX) / 2;
   constexpr int J0 = (R0 - PY + 1) / 2, J1 = (LO + TY - 1 - PY) / 2;
   constexpr int CNX = I1 - I0 + 1, CNY = J1 - J0 + 1;
-  for (int t = threadIdx.x; t < CNX * CNY; t += kThreads) {
+  for (int t = threadIdx.x; t < CNX * CNY; t += nthreads()) {
     const int i = I0 + t % CNX, j = J0 + t / CNX;
     const int bx = 2 * i + PX, by = 2 * j + PY;
     const int p1 = CX ? wrapm(ox + bx, n) : ox + bx;
@@ -541,7 +544,7 @@ __device__ __forceinline__ void nodal_restrict_tile(const T* pl, T* rl, const T*
   nodal_resid_pass<T, BX, BY, 1, 1, CX, CY, LO, TX, TY>(pl, rl, bc, st, ox, oy, n, m, N, p);
   __syncthreads();
   constexpr int HX = TX / 2, HY = TY / 2;
-  for (int t = threadIdx.x; t < HX * HY; t += kThreads) {
+  for (int t = threadIdx.x; t < HX * HY; t += nthreads()) {
     const int jx = t % HX, jy = t / HX;
     const int f1 = t0x + 2 * jx, f2 = t0y + 2 * jy;
     if (f1 >= n || f2 >= m) continue;
@@ -554,7 +557,7 @@ __device__ __forceinline__ void nodal_restrict_tile(const T* pl, T* rl, const T*
 }
 
 template <typename T, int TX, int TY, bool BWD, int MODE>
-__global__ __launch_bounds__(kThreads) void k_nodal_sweep(View<const T> xin, View<T> xout, View<const T> bv, Geo g,
+__global__ __launch_bounds__(kMaxThreads) void k_nodal_sweep(View<const T> xin, View<T> xout, View<const T> bv, Geo g,
                                                           const Phase* __restrict__ phs, NodalStencil st,
                                                           int zero_start, const int* __restrict__ slots, int ncps,
                                                           int tiles_x, SweepFuse<T> fz) {
@@ -575,11 +578,11 @@ __global__ __launch_bounds__(kThreads) void k_nodal_sweep(View<const T> xin, Vie
   const T* bc = colp(bv, sj, N);
   const Ph<T> p = cast_phase<T>(phs[tr.slot]);
   if (zero_start) {
-    for (int e = tid; e < 2 * S::N; e += kThreads) pl[e] = (T)0;
+    for (int e = tid; e < 2 * S::N; e += nthreads()) pl[e] = (T)0;
   } else {
     const T* xc = colp(xin, sj, N);
     const T* cc = PRO ? colp(fz.xc, sj, fz.gc.nm) : nullptr;
-    for (int e = tid; e < BX * BY; e += kThreads) {
+    for (int e = tid; e < BX * BY; e += nthreads()) {
       const int bx = e % BX, by = e / BX;
       const int c1 = cx ? wrapm(ox + bx, n) : ox + bx, c2 = cy ? wrapm(oy + by, m) : oy + by;
       const int64_t i = (int64_t)c2 * n + c1;
@@ -601,7 +604,7 @@ __global__ __launch_bounds__(kThreads) void k_nodal_sweep(View<const T> xin, Vie
   else if (!cx) nodal_passes<T, BX, BY, BWD, false, true, LO, TX, TY, EA, EB>(pl, bc, st, ox, oy, n, m, N, p);
   else nodal_passes<T, BX, BY, BWD, true, true, LO, TX, TY, EA, EB>(pl, bc, st, ox, oy, n, m, N, p);
   const T* bs = BAS ? colp(fz.base, sj, N) : nullptr;
-  for (int e = tid; e < TX * TY; e += kThreads) {
+  for (int e = tid; e < TX * TY; e += nthreads()) {
     const int ix = e % TX, iy = e / TX;
     const int c1 = tr.t0x + ix, c2 = tr.t0y + iy;
     if (c1 >= n || c2 >= m) continue;
@@ -634,12 +637,15 @@ __global__ __launch_bounds__(kThreads) void k_nodal_sweep(View<const T> xin, Vie
 
 // Tile shapes (nodes): 0: 32 x 32, 1: 64 x 32.  FP64 edge sweeps, and FP64 nodal sweeps with
 // the residual window, use 32 x 32 only (the larger boxes exceed the static LDS limit).
+// 512 threads when the launch has fewer than four tile workgroups per compute unit
+inline unsigned sweep_threads(const dim3& grid) { return (uint64_t)grid.x * grid.y < 1024 ? 512u : 256u; }
+
 template <typename T, int TX, int TY, bool BWD, int MODE>
 void edge_go(View<const T> xin, View<T> xout, View<const T> b, const EdgeArgs& a, const Geo& g, const Phase* ph,
              const double* mu, bool zero_start, const SweepFuse<T>& fz, const Launch& L) {
   const int tx = (g.n + TX - 1) / TX, ty = (g.m + TY - 1) / TY;
   dim3 grid((unsigned)(tx * ty), (unsigned)(L.nact * L.ncps));
-  k_edge_sweep<T, TX, TY, BWD, MODE><<<grid, kThreads, 0, L.st>>>(xin, xout, b, a, g, ph, mu, zero_start ? 1 : 0,
+  k_edge_sweep<T, TX, TY, BWD, MODE><<<grid, sweep_threads(grid), 0, L.st>>>(xin, xout, b, a, g, ph, mu, zero_start ? 1 : 0,
                                                                   L.slots, L.ncps, tx, fz);
 }
 
@@ -665,7 +671,7 @@ void nodal_go(View<const T> xin, View<T> xout, View<const T> b, const Geo& g, co
               bool zero_start, const SweepFuse<T>& fz, const Launch& L) {
   const int tx = (g.n + TX - 1) / TX, ty = (g.m + TY - 1) / TY;
   dim3 grid((unsigned)(tx * ty), (unsigned)(L.nact * L.ncps));
-  k_nodal_sweep<T, TX, TY, BWD, MODE><<<grid, kThreads, 0, L.st>>>(xin, xout, b, g, ph, c, zero_start ? 1 : 0,
+  k_nodal_sweep<T, TX, TY, BWD, MODE><<<grid, sweep_threads(grid), 0, L.st>>>(xin, xout, b, g, ph, c, zero_start ? 1 : 0,
                                                                    L.slots, L.ncps, tx, fz);
 }
 
