@@ -124,7 +124,8 @@ struct bl_solver {
   double* lam_d = nullptr;   // p per slot
   int* count_d = nullptr;    // per slot
   double* partial = nullptr;
-  double* norms = nullptr;
+  double* norms = nullptr;   // read-back block: norms, then lam_d and count_d
+  size_t readback_bytes = 0;
   double* gram_partial = nullptr;
   int64_t gram_cap = 0;
   double* Gm = nullptr;

@@ -444,30 +444,31 @@ __global__ __launch_bounds__(RR_THREADS) void k_rr_mfma(View<const double> Sv, i
 #undef BL_HPAIR
 #undef BL_MFMA
 
-// G_s, H_s = sums over the node ranges of launch entry z: 64 entries per block, the ranges
-// split into four consecutive quarters summed in range order, the quarters then added in
-// order (a fixed order, independent of timing).
+// G_s, H_s = sums over the node ranges of launch entry z: 16 entries per block, the ranges
+// split into sixteen consecutive groups summed in range order, the groups' sums then added
+// in order (a fixed order, independent of timing).
 __global__ __launch_bounds__(256) void k_rr_reduce(const double* __restrict__ partial, int nblk, int q,
                                                    double* __restrict__ G, double* __restrict__ H,
                                                    const int* __restrict__ slots) {
-  __shared__ double part[4][64];
+  __shared__ double part[16][17];
   const int z = blockIdx.y;
   const int64_t slot = slots ? slots[z] : z;
   const int64_t cnt = (int64_t)q * q * 4;
-  const int lo = threadIdx.x & 63, qt = threadIdx.x >> 6;
-  const int64_t e = (int64_t)blockIdx.x * 64 + lo;
+  const int lo = threadIdx.x & 15, gq = threadIdx.x >> 4;
+  const int64_t e = (int64_t)blockIdx.x * 16 + lo;
   const double* pz = partial + (int64_t)z * nblk * cnt;
-  const int b0 = (int)((int64_t)nblk * qt / 4), b1 = (int)((int64_t)nblk * (qt + 1) / 4);
+  const int b0 = (int)((int64_t)nblk * gq / 16), b1 = (int)((int64_t)nblk * (gq + 1) / 16);
   double sum = 0;
   if (e < cnt)
     for (int b = b0; b < b1; ++b) sum += pz[(int64_t)b * cnt + e];
-  part[qt][lo] = sum;
+  part[gq][lo] = sum;
   __syncthreads();
-  if (qt == 0 && e < cnt) {
-    const double s = ((part[0][lo] + part[1][lo]) + part[2][lo]) + part[3][lo];
+  if (gq == 0 && e < cnt) {
+    double t = part[0][lo];
+    for (int k = 1; k < 16; ++k) t += part[k][lo];
     const int64_t half = (int64_t)q * q * 2;
-    if (e < half) G[slot * half + e] = s;
-    else H[slot * half + e - half] = s;
+    if (e < half) G[slot * half + e] = t;
+    else H[slot * half + e - half] = t;
   }
 }
 
@@ -519,7 +520,7 @@ int rr_gram(View<const double> S, int q, const double* kappa, const Geo& g, cons
     k_rr_mfma<<<dim3((unsigned)nb, 1, (unsigned)L.nact), RR_THREADS, lds, L.st>>>(S, q, kappa, g, ph, grd.slices,
                                                                                   grd.band, partial, L.slots);
     const int64_t cnt = (int64_t)q * q * 4;
-    k_rr_reduce<<<dim3((unsigned)((cnt + 63) / 64), (unsigned)L.nact), 256, 0, L.st>>>(partial, nb, q, G, H,
+    k_rr_reduce<<<dim3((unsigned)((cnt + 15) / 16), (unsigned)L.nact), 256, 0, L.st>>>(partial, nb, q, G, H,
                                                                                       L.slots);
     return 0;
   }
@@ -533,7 +534,7 @@ int rr_gram(View<const double> S, int q, const double* kappa, const Geo& g, cons
   if (tile == 4) k_rr_gram<4><<<grid, 256, 0, L.st>>>(S, q, kappa, g, ph, rpb, partial, L.slots);
   else k_rr_gram<3><<<grid, 256, 0, L.st>>>(S, q, kappa, g, ph, rpb, partial, L.slots);
   const int64_t cnt = (int64_t)q * q * 4;
-  k_rr_reduce<<<dim3((unsigned)((cnt + 63) / 64), (unsigned)L.nact), 256, 0, L.st>>>(partial, nb, q, G, H, L.slots);
+  k_rr_reduce<<<dim3((unsigned)((cnt + 15) / 16), (unsigned)L.nact), 256, 0, L.st>>>(partial, nb, q, G, H, L.slots);
   return 0;
 }
 

@@ -874,10 +874,14 @@ int engine_create(const bl_grid* grid, const bl_opts* opts, int nslots, hipStrea
   if ((rc = dalloc_t(s, &s->Sb, col * q * S))) return fail(rc);
   for (int h = 0; h < 3; ++h)
     if ((rc = dalloc_t(s, &s->hist[h], col * p * S))) return fail(rc);
-  if ((rc = dalloc_t(s, &s->lam_d, (size_t)p * S))) return fail(rc);
-  if ((rc = dalloc_t(s, &s->count_d, (size_t)S))) return fail(rc);
+  // the round's read-back block: residual norms (2 p per slot), Ritz values (p per slot) and
+  // basis counts (per slot), contiguous so that one copy brings them to the host
+  const size_t rb = (size_t)3 * p * S + ((size_t)S + 1) / 2;
+  if ((rc = dalloc_t(s, &s->norms, rb))) return fail(rc);
+  s->lam_d = s->norms + (size_t)2 * p * S;
+  s->count_d = reinterpret_cast<int*>(s->norms + (size_t)3 * p * S);
+  s->readback_bytes = rb * 8;
   if ((rc = dalloc_t(s, &s->partial, (size_t)p * S * apply_blocks(g0) * 2))) return fail(rc);
-  if ((rc = dalloc_t(s, &s->norms, (size_t)2 * p * S))) return fail(rc);
   s->gram_cap = (int64_t)rr_partial_blocks(g0) * q * q * 4 * S;
   if ((rc = dalloc_t(s, &s->gram_partial, s->gram_cap))) return fail(rc);
   if ((rc = dalloc_t(s, &s->Gm, (size_t)q * q * 2 * S))) return fail(rc);
@@ -895,11 +899,11 @@ int engine_create(const bl_grid* grid, const bl_opts* opts, int nslots, hipStrea
   if ((rc = dalloc_t(s, &s->pc_inv32, (size_t)2 * s->ncn * s->ncn * S))) return fail(rc);
   if ((rc = dalloc_t(s, &s->lists_d, (size_t)kMaxLists * S))) return fail(rc);
   if (hipHostMalloc((void**)&s->lists_h, (size_t)kMaxLists * S * sizeof(int), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&s->norms_h, (size_t)2 * p * S * 8, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&s->lam_h, (size_t)p * S * 8, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&s->count_h, (size_t)S * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&s->norms_h, s->readback_bytes, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc(&s->param_h, (size_t)S * (sizeof(Phase) + 8), hipHostMallocDefault) != hipSuccess)
     return fail(set_error(BL_ENOMEM, "pinned host allocation failed%s"));
+  s->lam_h = s->norms_h + (size_t)2 * p * S;
+  s->count_h = reinterpret_cast<int*>(s->norms_h + (size_t)3 * p * S);
   const int ip = o.precision;
   if ((rc = ensure_level_buffers(s, ip, p, q))) return fail(rc);
   identity_block(s->probe_e, s->nce, s->st);
@@ -941,9 +945,7 @@ void engine_destroy(bl_solver* s) {
   else (void)hipDeviceSynchronize();
   for (void* p : s->allocs) (void)hipFree(p);
   if (s->lists_h) (void)hipHostFree(s->lists_h);
-  if (s->norms_h) (void)hipHostFree(s->norms_h);
-  if (s->lam_h) (void)hipHostFree(s->lam_h);
-  if (s->count_h) (void)hipHostFree(s->count_h);
+  if (s->norms_h) (void)hipHostFree(s->norms_h);   // lam_h and count_h point into it
   if (s->param_h) (void)hipHostFree(s->param_h);
   for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
   delete s;
@@ -1052,9 +1054,7 @@ int engine_issue(bl_solver* s) {
                                  L0.kappa64, L0.kappa32, s->lam_d, p, L0.g, s->ph_d, s->mu_d, L, s->partial, &nblk);
     reduce_partials(s->partial, nblk, (int)s->issued.size() * p, 2, s->norms, s->st);
     s->launches += 2;
-    HIP_OK(hipMemcpyAsync(s->norms_h, s->norms, s->issued.size() * p * 2 * 8, hipMemcpyDeviceToHost, s->st));
-    HIP_OK(hipMemcpyAsync(s->lam_h, s->lam_d, (size_t)s->nslots * p * 8, hipMemcpyDeviceToHost, s->st));
-    HIP_OK(hipMemcpyAsync(s->count_h, s->count_d, (size_t)s->nslots * sizeof(int), hipMemcpyDeviceToHost, s->st));
+    HIP_OK(hipMemcpyAsync(s->norms_h, s->norms, s->readback_bytes, hipMemcpyDeviceToHost, s->st));
   }
   return BL_OK;
 }
