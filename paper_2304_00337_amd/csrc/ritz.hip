@@ -549,7 +549,9 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
   }
   __syncthreads();
   if (second_s) {   // G2 = Z^* G Z = L2 L2^*, Z <- Z L2^{-*}
-    mm_nn(G, q, Z, lr, T, lr, q, r, q);
+    for (int e = tid; e < q * q; e += nt) B[(e / q) * lq + e % q] = G[e];   // G into the free B region
+    __syncthreads();
+    mm_nn(B, lq, Z, lr, T, lr, q, r, q);
     __syncthreads();
     mm_cn(Z, lr, T, lr, A, lr, r, r, q);
     __syncthreads();
@@ -572,7 +574,9 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
   if (tid == 0) stamp[2] = (double)wall_clock64();
 
   // ---- 3. H' = Z^* H Z (A, stride r), Hermitian part, then tridiagonalisation ----------------
-  mm_nn(H, q, Z, lr, T, lr, q, r, q);
+  for (int e = tid; e < q * q; e += nt) B[(e / q) * lq + e % q] = H[e];   // H into the free B region
+  __syncthreads();
+  mm_nn(B, lq, Z, lr, T, lr, q, r, q);
   __syncthreads();
   mm_cn(Z, lr, T, lr, A, lr, r, r, q);
   __syncthreads();
@@ -875,25 +879,29 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
   }
   __syncthreads();
   if (tid == 0) stamp[9] = (double)wall_clock64();
-  // Eigenvectors: an isolated eigenvalue's from the twisted factorisation; eigenvalues closer
-  // than 1e-6 tn form a cluster, whose vectors come from inverse iteration on T' - lambda I
-  // with partial pivoting, one after the other by one thread, Gram-Schmidt-orthogonalised
-  // against the cluster's earlier vectors.  Real vectors
-  // of length r are kept in T (as doubles): vec j at xs + j*r.  Per cluster head j the LU
-  // of T' - lambda I (3 arrays of length r) lies in the free A region, continued in T's tail
-  // (at most want*r + 3*want*r <= 4 q^2 doubles, the size of A and T together).
+  // Eigenvectors: an isolated eigenvalue's from the twisted factorisation (one thread each);
+  // eigenvalues closer than 1e-6 tn form a cluster, whose vectors come from inverse iteration
+  // on T' - lambda I with partial pivoting, one wave per cluster: every lane factorises and
+  // solves for one member, and after each of the three solves the members are Gram-Schmidt-
+  // orthogonalised in order (lanes over the rows, wave reductions).  Real vectors of length r
+  // are kept in T (as doubles): vec j at xs + j*r.  Per index j the LU of T' - lambda_j I
+  // (3 arrays of length r) lies in the free A region, continued in T's tail (at most want*r +
+  // 3*want*r <= 4 q^2 doubles, the size of A and T together).
   double* xs = reinterpret_cast<double*>(T);
   const int clus_in_a = (2 * q * q) / (3 * r > 0 ? 3 * r : 1);
+  auto lu_at = [&](int j) -> double* {
+    return j < clus_in_a ? reinterpret_cast<double*>(A) + (size_t)j * 3 * r
+                         : xs + (size_t)want * r + (size_t)(j - clus_in_a) * 3 * r;
+  };
+  auto in_cluster = [&](int j) {
+    return (j > 0 && lam[j] - lam[j - 1] <= 1e-6 * tn) || (j + 1 < ns && lam[j + 1] - lam[j] <= 1e-6 * tn);
+  };
   for (int j = tid; j < ns; j += nt) {
-    if (j > 0 && lam[j] - lam[j - 1] <= 1e-6 * tn) continue;   // not a cluster head
-    int jend = j + 1;
-    while (jend < ns && lam[jend] - lam[jend - 1] <= 1e-6 * tn) ++jend;
-    double* u = j < clus_in_a ? reinterpret_cast<double*>(A) + (size_t)j * 3 * r
-                              : xs + (size_t)want * r + (size_t)(j - clus_in_a) * 3 * r;
-    double* u1 = u + r;        // U: diagonal and first super-diagonal; the second
-    double* lm = u1 + r;       // super-diagonal is e_{i+1} after a row swap, else 0.
-                               // Multipliers; a row swap is encoded as -(mult) - 4.
-    if (jend == j + 1) {
+    if (in_cluster(j)) continue;
+    double* u = lu_at(j);
+    double* u1 = u + r;        // L+ / D+ of the twisted factorisation
+    double* lm = u1 + r;
+    {
       // an isolated eigenvalue: its vector from the twisted factorisation of T' - lambda I
       // (one forward LDL^T and one backward UDU^T pass; the twist index k minimises
       // |gamma_k| = |D+_k + D-_k - (d_k - lambda)|, and z_k = 1 is propagated both ways)
@@ -932,72 +940,107 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
       }
       const double inv = 1.0 / sqrt(nrm);
       for (int i = 0; i < r; ++i) x[i] *= inv;
-      continue;
     }
-    for (int c = j; c < jend; ++c) {
-      double* x = xs + (size_t)c * r;
-      const double shift = lam[c];
-      // Gaussian elimination with partial pivoting of the tridiagonal T' - shift I: the
-      // carried row has entries (a_i, b_i) in columns (i, i+1); the next row is
-      // (e_i, d_{i+1} - shift, e_{i+1}) in columns (i, i+1, i+2).
-      double a_i = dd[0] - shift, b_i = ee[0];
-      for (int i = 0; i < r - 1; ++i) {
-        const double sub = ee[i];
-        const double dnext = dd[i + 1] - shift, bnext = ee[i + 1];
-        if (fabs(sub) > fabs(a_i)) {              // swap rows i and i+1
-          const double mlt = a_i / sub;
-          u[i] = sub;
-          u1[i] = dnext;
-          lm[i] = -mlt - 4.0;                     // |mult| <= 1, so lm <= -3 marks a swap
-          a_i = b_i - mlt * dnext;
-          b_i = -mlt * bnext;
-        } else {
-          const double aa = fabs(a_i) > tiny ? a_i : (a_i < 0 ? -tiny : tiny);
-          const double mlt = sub / aa;
-          u[i] = aa;
-          u1[i] = b_i;
-          lm[i] = mlt;                            // |mult| <= 1
-          a_i = dnext - mlt * b_i;
-          b_i = bnext;
-        }
-      }
-      u[r - 1] = fabs(a_i) > tiny ? a_i : (a_i < 0 ? -tiny : tiny);
-      u1[r - 1] = 0.0;
-      lm[r - 1] = 0.0;
-      for (int i = 0; i < r; ++i) x[i] = 1.0 + 0.0625 * (double)((i * 7 + c * 3) % 11);
-      for (int rep = 0; rep < 3; ++rep) {
-        // forward: apply the row operations to x
-        for (int i = 0; i < r - 1; ++i) {
-          const double l = lm[i];
-          if (l <= -3.0) {   // swapped: new row i <- old row i+1; row i+1 <- old i - mult*old i+1
-            const double mlt = -(l + 4.0);
-            const double t = x[i];
-            x[i] = x[i + 1];
-            x[i + 1] = t - mlt * x[i];
-          } else {
-            x[i + 1] -= l * x[i];
+  }
+  {
+    const int wv = tid >> 6, nw = nt >> 6;
+    int ci = 0;
+    for (int j = 0; j < ns;) {
+      int jend = j + 1;
+      while (jend < ns && lam[jend] - lam[jend - 1] <= 1e-6 * tn) ++jend;
+      if (jend - j > 1 && (ci++ % nw) == wv) {
+        const int k = jend - j;
+        for (int c0 = 0; c0 < k; c0 += 64) {   // members, 64 at a time (lanes)
+          const int c = j + c0 + lane;
+          if (c0 + lane < k) {
+            double* u = lu_at(c);
+            double* u1 = u + r;    // U: diagonal and first super-diagonal; the second
+            double* lm = u1 + r;   // super-diagonal is e_{i+1} after a row swap, else 0.
+                                   // Multipliers; a row swap is encoded as -(mult) - 4.
+            const double shift = lam[c];
+            // Gaussian elimination with partial pivoting of the tridiagonal T' - shift I: the
+            // carried row has entries (a_i, b_i) in columns (i, i+1); the next row is
+            // (e_i, d_{i+1} - shift, e_{i+1}) in columns (i, i+1, i+2).
+            double a_i = dd[0] - shift, b_i = ee[0];
+            for (int i = 0; i < r - 1; ++i) {
+              const double sub = ee[i];
+              const double dnext = dd[i + 1] - shift, bnext = ee[i + 1];
+              if (fabs(sub) > fabs(a_i)) {              // swap rows i and i+1
+                const double mlt = a_i / sub;
+                u[i] = sub;
+                u1[i] = dnext;
+                lm[i] = -mlt - 4.0;                     // |mult| <= 1, so lm <= -3 marks a swap
+                a_i = b_i - mlt * dnext;
+                b_i = -mlt * bnext;
+              } else {
+                const double aa = fabs(a_i) > tiny ? a_i : (a_i < 0 ? -tiny : tiny);
+                const double mlt = sub / aa;
+                u[i] = aa;
+                u1[i] = b_i;
+                lm[i] = mlt;                            // |mult| <= 1
+                a_i = dnext - mlt * b_i;
+                b_i = bnext;
+              }
+            }
+            u[r - 1] = fabs(a_i) > tiny ? a_i : (a_i < 0 ? -tiny : tiny);
+            u1[r - 1] = 0.0;
+            lm[r - 1] = 0.0;
+            double* x = xs + (size_t)c * r;
+            for (int i = 0; i < r; ++i) x[i] = 1.0 + 0.0625 * (double)((i * 7 + c * 3) % 11);
           }
         }
-        // back substitution with U (diagonal u, super u1, super-super e_{i+1} on swaps)
-        for (int i = r - 1; i >= 0; --i) {
-          double s = x[i];
-          if (i + 1 < r) s -= u1[i] * x[i + 1];
-          if (i + 2 < r && lm[i] <= -3.0) s -= ee[i + 1] * x[i + 2];
-          x[i] = s / u[i];
+        for (int rep = 0; rep < 3; ++rep) {
+          for (int c0 = 0; c0 < k; c0 += 64) {
+            const int c = j + c0 + lane;
+            if (c0 + lane < k) {
+              const double* u = lu_at(c);
+              const double* u1 = u + r;
+              const double* lm = u1 + r;
+              double* x = xs + (size_t)c * r;
+              // forward: apply the row operations to x
+              for (int i = 0; i < r - 1; ++i) {
+                const double l = lm[i];
+                if (l <= -3.0) {   // swapped: new row i <- old row i+1; row i+1 <- old i - mult*old i+1
+                  const double mlt = -(l + 4.0);
+                  const double t = x[i];
+                  x[i] = x[i + 1];
+                  x[i + 1] = t - mlt * x[i];
+                } else {
+                  x[i + 1] -= l * x[i];
+                }
+              }
+              // back substitution with U (diagonal u, super u1, super-super e_{i+1} on swaps)
+              for (int i = r - 1; i >= 0; --i) {
+                double sacc = x[i];
+                if (i + 1 < r) sacc -= u1[i] * x[i + 1];
+                if (i + 2 < r && lm[i] <= -3.0) sacc -= ee[i + 1] * x[i + 2];
+                x[i] = sacc / u[i];
+              }
+            }
+          }
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          // orthogonalise each member against the earlier ones, normalise (lanes over rows)
+          for (int c = j; c < jend; ++c) {
+            double* x = xs + (size_t)c * r;
+            for (int pc = j; pc < c; ++pc) {
+              const double* y = xs + (size_t)pc * r;
+              double part = 0;
+              for (int i = lane; i < r; i += 64) part += y[i] * x[i];
+              const double dot = wave_sum(part);
+              for (int i = lane; i < r; i += 64) x[i] -= dot * y[i];
+            }
+            double part = 0;
+            for (int i = lane; i < r; i += 64) part += x[i] * x[i];
+            const double nrm = sqrt(wave_sum(part));
+            const double inv = nrm > 0 ? 1.0 / nrm : 0.0;
+            for (int i = lane; i < r; i += 64) x[i] *= inv;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+          }
         }
-        // orthogonalise against the cluster's earlier vectors, normalise
-        for (int pc = j; pc < c; ++pc) {
-          const double* y = xs + (size_t)pc * r;
-          double dot = 0;
-          for (int i = 0; i < r; ++i) dot += y[i] * x[i];
-          for (int i = 0; i < r; ++i) x[i] -= dot * y[i];
-        }
-        double nrm = 0;
-        for (int i = 0; i < r; ++i) nrm += x[i] * x[i];
-        nrm = sqrt(nrm);
-        const double inv = nrm > 0 ? 1.0 / nrm : 0.0;
-        for (int i = 0; i < r; ++i) x[i] *= inv;
       }
+      j = jend;
     }
   }
   __syncthreads();
