@@ -645,7 +645,9 @@ void edge_go(View<const T> xin, View<T> xout, View<const T> b, const EdgeArgs& a
              const double* mu, bool zero_start, const SweepFuse<T>& fz, const Launch& L) {
   const int tx = (g.n + TX - 1) / TX, ty = (g.m + TY - 1) / TY;
   dim3 grid((unsigned)(tx * ty), (unsigned)(L.nact * L.ncps));
-  k_edge_sweep<T, TX, TY, BWD, MODE><<<grid, sweep_threads(grid), 0, L.st>>>(xin, xout, b, a, g, ph, mu, zero_start ? 1 : 0,
+  // the restricting sweep's LDS (box and residual window) admits three workgroups per compute
+  // unit: 512 threads each keep the occupancy up
+  k_edge_sweep<T, TX, TY, BWD, MODE><<<grid, (MODE & kRestrict) ? 512u : sweep_threads(grid), 0, L.st>>>(xin, xout, b, a, g, ph, mu, zero_start ? 1 : 0,
                                                                   L.slots, L.ncps, tx, fz);
 }
 
