@@ -277,6 +277,7 @@ __global__ __launch_bounds__(256) void k_block_combine(View<const double> Sv, in
   double accr[CB], acci[CB];
 #pragma unroll
   for (int c = 0; c < CB; ++c) { accr[c] = 0; acci[c] = 0; }
+#pragma unroll 4
   for (int l = 0; l < q; ++l) {
     const double sr = S[(int64_t)l * 2 * len + i], si = S[(int64_t)l * 2 * len + len + i];
 #pragma unroll
