@@ -6,7 +6,9 @@
 //     columns, previous Ritz vectors, keep their order), stopped when the largest remaining
 //     pivot is below drop_rel: numerically dependent directions of S are dropped (rank r);
 //  2. Z = D P [L^{-*}; 0] (q x r) spans the kept directions M-orthonormally; if a kept pivot
-//     was small, a second Cholesky pass on Z^* G Z restores orthonormality to rounding;
+//     was small, G2 = Z^* G Z is formed and orthonormality restored to rounding: by one
+//     Newton-Schulz step Z <- Z (3I - G2)/2 when G2 is within 1e-3 of the identity (its error
+//     squares), else by a second Cholesky pass;
 //  3. H' = Z^* H Z (r x r) is reduced to real symmetric tridiagonal form by Householder
 //     reflections and a diagonal unitary scaling;
 //  4. the wanted eigenvalues (the `want` smallest above zero_thr) by Sturm-count
@@ -259,6 +261,7 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
   count += slot;
   const double zero_thr = zthr ? zthr[slot] : -INFINITY;
   __shared__ int rank_s, second_s;
+  __shared__ double red_s[16];
   // per-index arrays at the start of the dynamic LDS block, matrices after them (or in the
   // global work array when they do not fit)
   c2* phase = smem;
@@ -555,17 +558,40 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
     __syncthreads();
     mm_cn(Z, lr, T, lr, A, lr, r, r, q);
     __syncthreads();
-    chol(A, B, r, lr);
-    lower_inv(B, lr, A, lr, r);
-    for (int e = tid; e < q * r; e += nt) {
-      const int i = e / r, c = e % r;
-      c2 s = {0, 0};
-      for (int l = 0; l <= c; ++l) {
-        const c2 t = cmulc(A[c * lr + l], Z[i * lr + l]);
-        s.r += t.r;
-        s.i += t.i;
+    // distance of G2 from the identity (max entry); when it is small, one Newton-Schulz step
+    // Z <- Z (3I - G2) / 2 restores orthonormality to O(dev^2), else the Cholesky route
+    double dloc = 0;
+    for (int e = tid; e < r * r; e += nt) {
+      const int i = e / r, j = e % r;
+      const c2 a = A[i * lr + j];
+      dloc = fmax(dloc, fabs(a.r - (i == j ? 1.0 : 0.0)) + fabs(a.i));
+    }
+    for (int o = 32; o > 0; o >>= 1) dloc = fmax(dloc, __shfl_xor(dloc, o, 64));
+    if (lane == 0) red_s[tid >> 6] = dloc;
+    __syncthreads();
+    double dev = 0;
+    for (int w = 0; w < (nt >> 6); ++w) dev = fmax(dev, red_s[w]);
+    if (dev < 1e-3) {
+      for (int e = tid; e < r * r; e += nt) {
+        const int i = e / r, j = e % r;
+        const c2 a = A[i * lr + j];
+        A[i * lr + j] = (i == j) ? c2{1.5 - 0.5 * a.r, -0.5 * a.i} : c2{-0.5 * a.r, -0.5 * a.i};
       }
-      T[i * lr + c] = s;
+      __syncthreads();
+      mm_nn(Z, lr, A, lr, T, lr, q, r, r);
+    } else {
+      chol(A, B, r, lr);
+      lower_inv(B, lr, A, lr, r);
+      for (int e = tid; e < q * r; e += nt) {
+        const int i = e / r, c = e % r;
+        c2 s = {0, 0};
+        for (int l = 0; l <= c; ++l) {
+          const c2 t = cmulc(A[c * lr + l], Z[i * lr + l]);
+          s.r += t.r;
+          s.i += t.i;
+        }
+        T[i * lr + c] = s;
+      }
     }
     __syncthreads();
     for (int e = tid; e < q * lr; e += nt) Z[e] = T[e];
