@@ -987,28 +987,31 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
             // Gaussian elimination with partial pivoting of the tridiagonal T' - shift I: the
             // carried row has entries (a_i, b_i) in columns (i, i+1); the next row is
             // (e_i, d_{i+1} - shift, e_{i+1}) in columns (i, i+1, i+2).
+            // u keeps the reciprocals of U's diagonal (the back substitution multiplies)
             double a_i = dd[0] - shift, b_i = ee[0];
             for (int i = 0; i < r - 1; ++i) {
               const double sub = ee[i];
               const double dnext = dd[i + 1] - shift, bnext = ee[i + 1];
               if (fabs(sub) > fabs(a_i)) {              // swap rows i and i+1
-                const double mlt = a_i / sub;
-                u[i] = sub;
+                const double rs = rcp_nr(sub);
+                const double mlt = a_i * rs;
+                u[i] = rs;
                 u1[i] = dnext;
                 lm[i] = -mlt - 4.0;                     // |mult| <= 1, so lm <= -3 marks a swap
                 a_i = b_i - mlt * dnext;
                 b_i = -mlt * bnext;
               } else {
                 const double aa = fabs(a_i) > tiny ? a_i : (a_i < 0 ? -tiny : tiny);
-                const double mlt = sub / aa;
-                u[i] = aa;
+                const double ra = rcp_nr(aa);
+                const double mlt = sub * ra;
+                u[i] = ra;
                 u1[i] = b_i;
                 lm[i] = mlt;                            // |mult| <= 1
                 a_i = dnext - mlt * b_i;
                 b_i = bnext;
               }
             }
-            u[r - 1] = fabs(a_i) > tiny ? a_i : (a_i < 0 ? -tiny : tiny);
+            u[r - 1] = rcp_nr(fabs(a_i) > tiny ? a_i : (a_i < 0 ? -tiny : tiny));
             u1[r - 1] = 0.0;
             lm[r - 1] = 0.0;
             double* x = xs + (size_t)c * r;
@@ -1023,24 +1026,31 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
               const double* u1 = u + r;
               const double* lm = u1 + r;
               double* x = xs + (size_t)c * r;
-              // forward: apply the row operations to x
+              // forward: apply the row operations to x (the running entry carried in a register)
+              double xi = x[0];
               for (int i = 0; i < r - 1; ++i) {
-                const double l = lm[i];
+                const double l = lm[i], xn = x[i + 1];
                 if (l <= -3.0) {   // swapped: new row i <- old row i+1; row i+1 <- old i - mult*old i+1
                   const double mlt = -(l + 4.0);
-                  const double t = x[i];
-                  x[i] = x[i + 1];
-                  x[i + 1] = t - mlt * x[i];
+                  x[i] = xn;
+                  xi = xi - mlt * xn;
                 } else {
-                  x[i + 1] -= l * x[i];
+                  x[i] = xi;
+                  xi = xn - l * xi;
                 }
               }
-              // back substitution with U (diagonal u, super u1, super-super e_{i+1} on swaps)
+              x[r - 1] = xi;
+              // back substitution with U (reciprocal diagonal u, super u1, super-super e_{i+1}
+              // on swaps; the two entries below carried in registers)
+              double x1 = 0.0, x2 = 0.0;
               for (int i = r - 1; i >= 0; --i) {
                 double sacc = x[i];
-                if (i + 1 < r) sacc -= u1[i] * x[i + 1];
-                if (i + 2 < r && lm[i] <= -3.0) sacc -= ee[i + 1] * x[i + 2];
-                x[i] = sacc / u[i];
+                if (i + 1 < r) sacc -= u1[i] * x1;
+                if (i + 2 < r && lm[i] <= -3.0) sacc -= ee[i + 1] * x2;
+                const double xv = sacc * u[i];
+                x[i] = xv;
+                x2 = x1;
+                x1 = xv;
               }
             }
           }
