@@ -269,7 +269,8 @@ class Solver:
     """Handle for one grid and permittivity (bl_create).
 
     Keyword options map to bl_opts fields: nev, nthrow, max_iter, levels, coarsest_min,
-    nu_pre, nu_post, nodal_cycles, variant, precision ("fp64" | "mixed" or 0 | 1),
+    nu_pre, nu_post, nodal_cycles, variant ("gradient" | "lobpcg" or 0 | 1), precision ("fp64" |
+    "mixed" or 0 | 1),
     extrap_depth, tol, mu, zero_rel."""
 
     def __init__(self, n, m, a, b, eps, nev=8, stream=None, **opts):
@@ -281,6 +282,8 @@ class Solver:
         for k, v in opts.items():
             if k == "precision" and isinstance(v, str):
                 v = {"fp64": 0, "mixed": 1}[v]
+            if k == "variant" and isinstance(v, str):
+                v = {"gradient": 0, "lobpcg": 1}[v]
             if not hasattr(o, k):
                 raise TypeError(f"unknown option {k}")
             setattr(o, k, v)

@@ -46,6 +46,8 @@ template <typename T>
 __device__ void dense_solve(const T* inv, int64_t n, const T* b, T* x) {
   for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
     T sr = 0, si = 0;
+    // (unrolled: the loads of several terms are in flight; the summation order is unchanged)
+#pragma unroll 8
     for (int64_t l = 0; l < n; ++l) {
       const T ar = inv[2 * (l * n + i)], ai = -inv[2 * (l * n + i) + 1];
       const T br = b[l], bi = b[n + l];

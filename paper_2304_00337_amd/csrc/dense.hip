@@ -126,6 +126,8 @@ __global__ __launch_bounds__(256) void k_dense_apply(const T* __restrict__ inv, 
   inv += (int64_t)slot * n * n * 2;
   const T* bc = bv.p + ((int64_t)slot * bv.cps + bv.off + col) * 2 * n;
   T sr = 0, si_ = 0;
+  // (unrolled: the loads of several terms are in flight; the summation order is unchanged)
+#pragma unroll 8
   for (int64_t l = 0; l < n; ++l) {
     const T ar = inv[2 * (l * n + i)], ai = -inv[2 * (l * n + i) + 1];
     const T br = bc[l], bi = bc[n + l];

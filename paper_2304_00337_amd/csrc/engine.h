@@ -121,6 +121,8 @@ struct bl_solver {
   double* E = nullptr;       // p columns per slot
   double* Sb = nullptr;      // qmax columns per slot
   double* hist[3] = {nullptr, nullptr, nullptr};   // p columns per slot, most recent first
+  double* Eprev = nullptr;   // LOBPCG: the previous iteration's block (p columns per slot)
+  double* Dbuf = nullptr;    // LOBPCG: its direction E_prev - E (E^* M E_prev), p columns per slot
   double* lam_d = nullptr;   // p per slot
   int* count_d = nullptr;    // per slot
   double* partial = nullptr;

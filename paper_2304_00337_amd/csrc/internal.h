@@ -161,6 +161,9 @@ void lift(View<const TI> phi, View<TO> out, const Geo& g, const Phase* ph, const
 void gamma_deflate(View<double> u, const Geo& g, double* scratch, const Launch& L);
 template <typename T>
 void axpy(View<T> y, View<const T> x, int64_t len, const Launch& L);
+// out = a - b, or out = a when b.p is null (columns of length len)
+template <typename T>
+void sub_cols(View<const T> a, View<const T> b, View<T> out, int64_t len, const Launch& L);
 
 template <typename T>
 void fill_zero(T* p, int64_t count, hipStream_t st);

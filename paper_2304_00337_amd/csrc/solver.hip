@@ -116,7 +116,7 @@ int validate_opts(const bl_opts* o) {
   if (p > 80) return set_error(BL_EINVAL, "nev + nthrow must be <= 80%s");
   if (o->max_iter < 0 || o->nu_pre < 0 || o->nu_post < 0 || o->nodal_cycles < 1)
     return set_error(BL_EINVAL, "invalid iteration options%s");
-  if (o->variant != 0) return set_error(BL_EINVAL, "only the gradient variant is available%s");
+  if (o->variant != 0 && o->variant != 1) return set_error(BL_EINVAL, "variant must be 0 (gradient) or 1 (LOBPCG)%s");
   if (o->precision != 0 && o->precision != 1) return set_error(BL_EINVAL, "precision must be 0 or 1%s");
   if (o->extrap_depth < 1 || o->extrap_depth > 3) return set_error(BL_EINVAL, "extrap_depth must be 1..3%s");
   if (o->autotune != 0 && o->autotune != 1) return set_error(BL_EINVAL, "autotune must be 0 or 1%s");
@@ -874,6 +874,10 @@ int engine_create(const bl_grid* grid, const bl_opts* opts, int nslots, hipStrea
   if ((rc = dalloc_t(s, &s->Sb, col * q * S))) return fail(rc);
   for (int h = 0; h < 3; ++h)
     if ((rc = dalloc_t(s, &s->hist[h], col * p * S))) return fail(rc);
+  if (o.variant == 1) {
+    if ((rc = dalloc_t(s, &s->Eprev, col * p * S))) return fail(rc);
+    if ((rc = dalloc_t(s, &s->Dbuf, col * p * S))) return fail(rc);
+  }
   // the round's read-back block: residual norms (2 p per slot), Ritz values (p per slot) and
   // basis counts (per slot), contiguous so that one copy brings them to the host
   const size_t rb = (size_t)3 * p * S + ((size_t)S + 1) / 2;
@@ -1109,8 +1113,34 @@ int engine_finish(bl_solver* s) {
     Launch L = make_launch(s, cont, p);
     if (ip) vcycle_edge<float>(s, 0, cview(static_cast<const float*>(L0.eb[1]), L0.ecap[1]), view(static_cast<float*>(L0.ex[1]), L0.ecap[1]), L);
     else vcycle_edge<double>(s, 0, cview(static_cast<const double*>(L0.eb[0]), L0.ecap[0]), view(static_cast<double*>(L0.ex[0]), L0.ecap[0]), L);
-    if ((rc = project(s, {{s->E, p, 0, 0, p}, {L0.ex[ip], L0.ecap[ip], 0, ip, p}}, view(s->Sb, s->qmax), cont))) return rc;
-    if ((rc = ritz_step(s, cont, 2 * p, p, false))) return rc;
+    // LOBPCG (Section 4): from the second iteration of a point on, the basis also holds the
+    // previous block's direction D = E_prev - E (E^* M E_prev); the gradient variant, and the
+    // first iteration, use [E, C]
+    const bool lob = s->opts.variant == 1;
+    std::vector<int> three, two;
+    for (int sl : cont) (lob && s->slot[sl].it > 0 ? three : two).push_back(sl);
+    const View<const double> none{nullptr, 0, 0};
+    if (!three.empty()) {
+      Launch Lt = make_launch(s, three, p);
+      edge_apply<double, double>(EM_M, cview(s->Eprev, p), none, view(s->Dbuf, p), L0.kappa64, L0.kappa32, nullptr,
+                                 0, L0.g, s->ph_d, s->mu_d, Lt, nullptr, nullptr);
+      if (gram(cview(s->E, p), p, cview(s->Dbuf, p), p, L0.g.ne, s->gram_partial, s->gram_cap, s->Gm, Lt) != 0)
+        return set_error(BL_EINVAL, "Gram scratch too small%s");
+      block_combine(cview(s->E, p), p, s->Gm, p, L0.g.ne, view(s->Dbuf, p), Lt);
+      sub_cols<double>(cview(s->Eprev, p), cview(s->Dbuf, p), view(s->Dbuf, p), L0.g.ne, Lt);
+      s->launches += 5;
+      if ((rc = project(s, {{s->E, p, 0, 0, p}, {L0.ex[ip], L0.ecap[ip], 0, ip, p}, {s->Dbuf, p, 0, 0, p}},
+                        view(s->Sb, s->qmax), three)))
+        return rc;
+      sub_cols<double>(cview(s->E, p), none, view(s->Eprev, p), L0.g.ne, Lt);
+      if ((rc = ritz_step(s, three, 3 * p, p, false))) return rc;
+    }
+    if (!two.empty()) {
+      if ((rc = project(s, {{s->E, p, 0, 0, p}, {L0.ex[ip], L0.ecap[ip], 0, ip, p}}, view(s->Sb, s->qmax), two)))
+        return rc;
+      if (lob) sub_cols<double>(cview(s->E, p), none, view(s->Eprev, p), L0.g.ne, make_launch(s, two, p));
+      if ((rc = ritz_step(s, two, 2 * p, p, false))) return rc;
+    }
     for (int sl : cont) s->slot[sl].it += 1;
   }
   return BL_OK;

@@ -699,6 +699,24 @@ void axpy(View<T> y, View<const T> x, int64_t len, const Launch& L) {
 template void axpy<double>(View<double>, View<const double>, int64_t, const Launch&);
 template void axpy<float>(View<float>, View<const float>, int64_t, const Launch&);
 
+// out = a - b (b null: out = a) on the launch's columns of length len (complex, planar)
+template <typename T>
+__global__ void k_sub_cols(View<const T> av, View<const T> bv, View<T> ov, int64_t len, const int* __restrict__ slots,
+                           int ncps) {
+  const SJ sj = slot_col(slots, ncps);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2 * len) return;
+  const T a = colp(av, sj, len)[i];
+  colp(ov, sj, len)[i] = bv.p ? a - colp(bv, sj, len)[i] : a;
+}
+template <typename T>
+void sub_cols(View<const T> a, View<const T> b, View<T> out, int64_t len, const Launch& L) {
+  dim3 grid((unsigned)((2 * len + 255) / 256), (unsigned)(L.nact * L.ncps));
+  if (grid.y == 0) return;
+  k_sub_cols<T><<<grid, 256, 0, L.st>>>(a, b, out, len, L.slots, L.ncps);
+}
+template void sub_cols<double>(View<const double>, View<const double>, View<double>, int64_t, const Launch&);
+
 template <typename T>
 __global__ void k_fill_zero(T* __restrict__ p, int64_t count) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -104,6 +104,33 @@ def test_iteration_matches_oracle_iteration(k):
     assert abs(r["iterations"] - it_o) <= max(3, int(0.15 * it_o)), (r["iterations"], it_o)
 
 
+@pytest.mark.parametrize("k", [(0.7, -1.3), (math.pi, 0.0)])
+def test_lobpcg_matches_oracle_lobpcg(k):
+    """The LOBPCG variant (Section 4: the previous block joins the basis as the direction
+    E_prev - E (E^* M E_prev)) against the oracle's LOBPCG from the same start block:
+    eigenvalues, convergence and iteration count (which it cuts against the gradient
+    variant)."""
+    n = 32
+    eps = synth.eps_disc(n, n, 1.0, 1.0, 8.9, 0.3)
+    nev, nthrow, mu = 6, 4, 10.0
+    d = fem.Discretization(n, n, 1.0, 1.0, eps, *k)
+    H = Hierarchy(d, mu=mu, coarsest_min=4)
+    pr = Projector(d, H, 2)
+    E0 = synth.start_block(d.n_edges, nev + nthrow, 5)
+    lam0, Eo = initial_block(d, pr, E0, nev + nthrow)
+    lam_o, E_o, rel_o, it_o, conv_o = pinvit(d, H, pr, Eo, lam0, nev, 1e-9, 200, variant="lobpcg")
+    assert conv_o
+    from paper_2304_00337_amd import Solver
+    kw = dict(nev=nev, nthrow=nthrow, mu=mu, coarsest_min=4, tol=1e-9, max_iter=200)
+    r = Solver(n, n, 1.0, 1.0, eps, variant="lobpcg", **kw).solve_k(*k, start=E0)
+    g = Solver(n, n, 1.0, 1.0, eps, **kw).solve_k(*k, start=E0)
+    assert r["converged"] and g["converged"]
+    assert np.max(np.abs(r["evals"] - lam_o[:nev]) / lam_o[:nev]) < 1e-9
+    assert np.max(np.abs(r["evals"] - g["evals"]) / g["evals"]) < 1e-9
+    assert abs(r["iterations"] - it_o) <= max(3, int(0.15 * it_o)), (r["iterations"], it_o)
+    assert r["iterations"] < g["iterations"], (r["iterations"], g["iterations"])
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_short_path_matches_oracle_path(precision):
     n = 32
