@@ -52,7 +52,7 @@ def segments(prob, S, per_segment):
     return out
 
 
-def run_form(prob, precision, S, steps, warmup, per_segment, max_slots=None, engine_streams=0):
+def run_form(prob, precision, S, steps, warmup, per_segment, max_slots=None, engine_streams=0, variant=0):
     """Solve the path cut into S pieces (one batch) `steps` times after `warmup` untimed
     runs; engine_streams = 0 keeps the library's default (engines of one shape side by side
     on three streams), 1 runs the pieces one engine at a time."""
@@ -61,7 +61,7 @@ def run_form(prob, precision, S, steps, warmup, per_segment, max_slots=None, eng
     probs = segments(prob, S, per_segment)
     recs = []
     with Batch(max_slots=max_slots or len(probs), precision=precision, levels=prob.levels, tol=prob.tol,
-               max_iter=300, engine_streams=engine_streams) as b:
+               max_iter=300, engine_streams=engine_streams, variant=variant) as b:
         for _ in range(warmup):
             b.run(probs)
         torch.cuda.synchronize()
@@ -315,6 +315,15 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, int(head["recs"][0]["iters"].sum()), head["S"])
+    if not args.headline_only:
+        # the LOBPCG variant (Section 4) on the same path and launch configuration: fewer
+        # iterations; its 3p-wide Rayleigh-Ritz step runs on the vector path
+        lob = run_form(prob, "mixed", args.segments, 1, 1, args.per_segment, variant=1)
+        out["lobpcg"] = {"value": round(rate(lob), 3), "unit": "eigenpairs/s", "ms_per_path": round(1e3 * lob["elapsed"], 3),
+                         "iterations": int(lob["recs"][0]["iters"].sum()),
+                         "gradient_iterations": int(head["recs"][0]["iters"].sum())}
+        print(f"# lobpcg: {lob['elapsed']:.3f}s, iterations {lob['recs'][0]['iters'].tolist()}", file=sys.stderr,
+              flush=True)
     if not args.no_serving:
         out["serving"] = serving(args.serve_requests, seed=4)
     print(json.dumps(out), flush=True)

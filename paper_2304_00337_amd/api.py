@@ -52,6 +52,8 @@ def _make_opts(nev=8, **opts) -> BlOpts:
     for k, v in opts.items():
         if k == "precision" and isinstance(v, str):
             v = {"fp64": 0, "mixed": 1}[v]
+        if k == "variant" and isinstance(v, str):
+            v = {"gradient": 0, "lobpcg": 1}[v]
         if not hasattr(o, k):
             raise TypeError(f"unknown option {k}")
         setattr(o, k, v)
