@@ -168,6 +168,55 @@ def serving(count, seed, rate_frac=0.7):
                         f"{rate_frac:.0%} of the measured closed-batch capacity"}
 
 
+def _geometric_rate(res, upper=1e-2):
+    """Per-iteration convergence rate of a residual record: exp of the least-squares slope
+    of log(residual) from the first entry at or below `upper` to the end (NaN with fewer
+    than three entries)."""
+    r = np.asarray(res, dtype=np.float64)
+    below = np.nonzero(r <= upper)[0]
+    if below.size == 0 or r.size - below[0] < 3:
+        return float("nan")
+    j = np.arange(below[0], r.size, dtype=np.float64)
+    return float(np.exp(np.polyfit(j, np.log(r[below[0]:]), 1)[0]))
+
+
+def throwaway_study(n=128, nev=16, ts=(1, 2, 4, 8, 16), mu=0.5, seed=3):
+    """Section 7's experiment on the GPU path: permittivity 100 in the disc of radius 1/3,
+    the 16 smallest non-zero eigenvalues at k = (pi/2, pi/4) with t throw-away vectors
+    (plain FP64, tolerance 1e-9, the same seeded start block cut to p = 16 + t columns);
+    per t the iterations, the solve time and the observed rates of pairs 14, 15, 16 beside
+    the unpreconditioned block inverse iteration's lambda_i / lambda_{p+1}."""
+    import torch
+    import synth
+    from paper_2304_00337_amd import Solver, to_device_block
+    k = (0.5 * math.pi, 0.25 * math.pi)
+    eps = synth.paper_z1_eps(n)
+    E0 = synth.start_block(2 * n * n, nev + max(ts), seed)
+    kw = dict(mu=mu, tol=1e-9, max_iter=400, precision="fp64")
+    ref = Solver(n, n, 1.0, 1.0, eps, nev=nev + max(ts) + 1, nthrow=8, **kw).solve_k(
+        *k, start=to_device_block(synth.start_block(2 * n * n, nev + max(ts) + 9, seed + 1)), allow_noconv=True)
+    lam = ref["evals"]
+    rows = []
+    for t in ts:
+        p = nev + t
+        s = Solver(n, n, 1.0, 1.0, eps, nev=nev, nthrow=t, **kw)
+        start = to_device_block(np.ascontiguousarray(E0[:, :p]))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = s.solve_k(*k, start=start, allow_noconv=True)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0)
+        hist = s.residual_history()
+        rows.append({"t": t, "p": p, "iterations": out["iterations"], "converged": out["converged"],
+                     "solve_ms": round(ms, 3),
+                     "rates": {str(i): round(_geometric_rate(hist[:, i - 1]), 4) for i in (14, 15, 16)},
+                     "inverse_iteration_rates": {str(i): round(float(lam[i - 1] / lam[p]), 4)
+                                                 for i in (14, 15, 16)}})
+        print(f"# throw-away t={t}: {out['iterations']} iterations, {ms:.1f} ms", file=sys.stderr, flush=True)
+    return {"grid": n, "nev": nev, "k": [round(k[0], 6), round(k[1], 6)], "mu": mu, "precision": "fp64",
+            "eps": "100 in the disc of radius 1/3, 1 outside", "runs": rows}
+
+
 def recorded_traffic(avg_cols):
     """HBM bytes per launch of the finest-level edge smoother from the recorded counter runs
     (profiles/edge_sweep_traffic.json: FETCH_SIZE and WRITE_SIZE per dispatch, calibrated on a
@@ -324,6 +373,8 @@ def main():
                          "gradient_iterations": int(head["recs"][0]["iters"].sum())}
         print(f"# lobpcg: {lob['elapsed']:.3f}s, iterations {lob['recs'][0]['iters'].tolist()}", file=sys.stderr,
               flush=True)
+    if not args.headline_only:
+        out["throwaway"] = throwaway_study()
     if not args.no_serving:
         out["serving"] = serving(args.serve_requests, seed=4)
     print(json.dumps(out), flush=True)

@@ -16,6 +16,8 @@ Modules and the paper passages they follow:
   pinvit       -- Section 4 and Section 7: block preconditioned inverse iteration with the
                   null-space elimination, Ritz step and throw-away vectors
   extrapolation-- Section 6: Rayleigh-quotient extrapolation across Bloch parameters
+  throwaway    -- Section 7: observed convergence rates against the number of throw-away
+                  vectors, and the block inverse-iteration rate lambda_i / lambda_{p+1}
 
 Parity status of each function is stated in its docstring ("pinned by ..." or
 "parity unpinned").

@@ -1,0 +1,112 @@
+"""Pins of the throw-away study (Section 7) in the oracle: the rate estimator on exact
+geometric sequences, the Section 7 analysis on the textbook block inverse iteration, and
+the bound the analysis gives for the iteration with an exact preconditioner."""
+import math
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse.linalg as spla
+
+import synth
+from oracle import fem
+from oracle.dense import dense_eigs
+from oracle.multigrid import Hierarchy
+from oracle.pinvit import Projector
+from oracle.throwaway import inverse_iteration_rate, observed_rate, study
+
+K_STUDY = (0.5 * math.pi, 0.25 * math.pi)
+
+
+def test_observed_rate_recovers_geometric_sequences():
+    for rho in (0.12, 0.5, 0.93):
+        m = np.arange(800)
+        res = 3.0 * rho ** m
+        # a pre-asymptotic plateau above the window and a rounding floor below it
+        seq = np.concatenate([[5.0, 4.0, 3.5], res[res > 1e-13], [1e-14, 2e-14, 1e-14]])
+        got = observed_rate(seq, upper=1e-2, lower=1e-13)
+        assert abs(got - rho) < 1e-12 * max(1.0, 1.0 / (1 - rho)), (rho, got)
+    assert math.isnan(observed_rate([1.0, 0.5, 0.1]))          # never below the window top
+    assert math.isnan(observed_rate([1.0, 5e-3, 1e-3], lower=0.0, min_points=3))
+
+
+def test_block_inverse_iteration_rate_is_lambda_i_over_lambda_p1():
+    """Section 7's derivation on the textbook case: E <- A^{-1} E with orthonormalisation
+    (and a Rayleigh-Ritz rotation, which leaves the span alone) on a diagonal pencil; the
+    residual of Ritz pair i falls by lambda_i / lambda_{p+1} per step."""
+    rng = np.random.default_rng(11)
+    n, p = 160, 4
+    lam = np.concatenate([[1.0, 1.7, 2.5, 3.1, 4.0], 4.0 + np.sort(rng.uniform(0.5, 40.0, n - 5))])
+    A = np.diag(lam)
+    E = rng.standard_normal((n, p)) + 1j * rng.standard_normal((n, p))
+    hist = []
+    for _ in range(140):
+        E, _ = np.linalg.qr(np.linalg.solve(A, E))
+        th, U = np.linalg.eigh(E.conj().T @ A @ E)
+        X = E @ U
+        R = A @ X - X * th[None, :]
+        hist.append(np.linalg.norm(R, axis=0) / th)
+    hist = np.array(hist)
+    for i in range(1, p + 1):
+        want = inverse_iteration_rate(lam, i, p)
+        got = observed_rate(hist[:, i - 1], upper=1e-3, lower=1e-12)
+        assert abs(got - want) < 0.02 * want, (i, got, want)
+
+
+class _ExactSolves:
+    """The exact inverse of A + mu M as the preconditioner and the exact nodal solve for the
+    null-space elimination (stand-ins for the multigrid cycles)."""
+
+    def __init__(self, d, mu):
+        self.K = spla.splu((d.A + mu * d.M).tocsc())
+        P = (d.L.conj().T @ d.M @ d.L).tocsc()
+        self.P = spla.splu(P)
+
+    def edge_vcycle(self, b, level=0):
+        return self.K.solve(np.asarray(b, dtype=np.complex128))
+
+    def nodal_solve(self, b, cycles):
+        return self.P.solve(np.asarray(b, dtype=np.complex128))
+
+
+def test_exact_preconditioner_rates_within_the_inverse_iteration_bound():
+    """With B = (A + mu M)^{-1} the basis [E, B R] spans E and one shifted inverse-iteration
+    step of E, so by Courant-Fischer the iteration converges at least at the Section 7 rate
+    (lambda_i + mu) / (lambda_{p+1} + mu); more throw-away vectors lower that rate."""
+    n = 16
+    eps = synth.paper_z1_eps(n)
+    d = fem.Discretization(n, n, 1.0, 1.0, eps, *K_STUDY)
+    nev, ts = 4, (1, 4)
+    lam_ref, _, _ = dense_eigs(d, nev + max(ts) + 1)
+    mu = 0.05 * lam_ref[0]
+    ex = _ExactSolves(d, mu)
+    pr = Projector(d, ex, 1)
+    E0 = synth.start_block(d.n_edges, nev + max(ts), 2)
+    runs = study(d, ex, pr, E0, nev, ts, range(1, nev + 1), tol=1e-10, max_iter=200,
+                 upper=1e-1, lower=1e-10)
+    for r in runs:
+        assert r["converged"]
+        assert np.max(np.abs(r["lam"] - lam_ref[:nev]) / lam_ref[:nev]) < 1e-12
+        for i, rate in r["rates"].items():
+            bound = inverse_iteration_rate(lam_ref, i, r["p"], mu)
+            assert rate <= 1.02 * bound, (r["t"], i, rate, bound)
+    assert runs[1]["rates"][nev] < runs[0]["rates"][nev]
+    assert runs[1]["iterations"] <= runs[0]["iterations"]
+
+
+def test_throwaway_vectors_speed_up_the_multigrid_iteration():
+    """The Section 7 experiment in small: permittivity 100 in the disc of radius 1/3, the
+    multigrid preconditioner with a shift of the size of the wanted eigenvalues (mu = 0.5;
+    the high contrast puts them near 0.1 .. 1.5); the wanted pairs converge faster with more
+    throw-away vectors."""
+    n = 16
+    eps = synth.paper_z1_eps(n)
+    d = fem.Discretization(n, n, 1.0, 1.0, eps, *K_STUDY)
+    nev = 4
+    H = Hierarchy(d, mu=0.5, coarsest_min=4)
+    pr = Projector(d, H, 2)
+    E0 = synth.start_block(d.n_edges, nev + 8, 3)
+    runs = study(d, H, pr, E0, nev, (1, 8), range(nev - 1, nev + 1), tol=1e-9, max_iter=300)
+    assert all(r["converged"] for r in runs)
+    for i in (nev - 1, nev):
+        assert runs[1]["rates"][i] < runs[0]["rates"][i], (i, runs[0]["rates"], runs[1]["rates"])
+    assert runs[1]["iterations"] < runs[0]["iterations"]
