@@ -217,6 +217,32 @@ def throwaway_study(n=128, nev=16, ts=(1, 2, 4, 8, 16), mu=0.5, seed=3):
             "eps": "100 in the disc of radius 1/3, 1 outside", "runs": rows}
 
 
+def kgrid_raster(n=256, kappa=30, nev=16, nthrow=8, seed=9):
+    """Section 8's band-structure experiment on the Section 6 raster: permittivity 11.56 in
+    the disc of radius 0.18, the 16 smallest non-zero eigenpairs (plus 8 throw-away vectors)
+    at every point of the kappa x kappa Bloch grid, stopping when every wanted defect
+    ||A e - lambda M e||_2 is below 1e-2 (plain FP64, one handle, random first point)."""
+    import torch
+    import synth
+    from paper_2304_00337_amd import Solver, to_device_block
+    eps = synth.paper_z2_eps(n)
+    s = Solver(n, n, 1.0, 1.0, eps, nev=nev, nthrow=nthrow, tol=1e-2, tol_abs=1, max_iter=300, precision="fp64")
+    start = to_device_block(synth.start_block(2 * n * n, nev + nthrow, seed))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = s.solve_kgrid(kappa, start, allow_noconv=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    its = out["iterations"]
+    conv = out["relres"].max(axis=2) <= 1e-2
+    print(f"# k-grid raster {kappa}x{kappa}: {dt:.2f}s, median {np.median(its)} iterations", file=sys.stderr, flush=True)
+    return {"grid": n, "kappa": kappa, "nev": nev, "nthrow": nthrow, "precision": "fp64", "stop": "defect <= 1e-2",
+            "seconds": round(dt, 3), "value": round(nev * kappa * kappa / dt, 3), "unit": "eigenpairs/s",
+            "iterations_median": float(np.median(its)), "fraction_below_4": round(float(np.mean(its < 4)), 4),
+            "iterations_max": int(its.max()), "iterations_first_point": int(its[0, 0]),
+            "not_converged": int((~conv).sum())}
+
+
 def recorded_traffic(avg_cols):
     """HBM bytes per launch of the finest-level edge smoother from the recorded counter runs
     (profiles/edge_sweep_traffic.json: FETCH_SIZE and WRITE_SIZE per dispatch, calibrated on a
@@ -375,6 +401,7 @@ def main():
               flush=True)
     if not args.headline_only:
         out["throwaway"] = throwaway_study()
+        out["kgrid"] = kgrid_raster()
     if not args.no_serving:
         out["serving"] = serving(args.serve_requests, seed=4)
     print(json.dumps(out), flush=True)

@@ -106,7 +106,10 @@ typedef struct bl_opts {
                              of the shape wait for a free slot); a shape of which one problem
                              fills the device is spread over them rather than packed into
                              one (1..16, default 3)                                        */
-  int32_t reserved2;
+  int32_t tol_abs;      /* 1 = tol bounds the defects ||A e_i - lambda_i M e_i||_2 of the
+                           M-normalised vectors (the stopping measure of the band-structure
+                           experiment, Section 8), which relres then reports; 0 = relative
+                           residuals (0)                                                   */
 } bl_opts;
 
 /* Read-only facts about a solver handle. */
@@ -166,6 +169,28 @@ int bl_solve_k(bl_solver* s, double k1, double k2, const void* start_dev, double
  * keep their best approximations). */
 int bl_solve_path(bl_solver* s, const double* ks, int32_t nk, const void* start_dev,
                   double* evals, double* relres, int32_t* iters, void* evecs_last_dev);
+
+/* ---- Bloch-parameter grid (Section 6) ----------------------------------------------------
+ * The kappa x kappa grid k_ij = (pi/a (2 i/(kappa-1) - 1), pi/b (2 j/(kappa-1) - 1)),
+ * i, j = 0..kappa-1, solved in raster order: row j = 0..kappa-1, in a row i = 0..kappa-1.
+ * bl_raster_sources: the points whose eigenvector blocks give the start block of (i, j),
+ *   oldest first, as (i', j') pairs in src (host, room for 3 pairs): none for (0, 0); in the
+ *   first row the up to three points to the left; in columns 0..2 the up to three points
+ *   below; elsewhere the three points to the left (the paper states this rule for rows
+ *   j >= 3; rows 1 and 2 are read the same way).  Returns their number (0..3); BL_EINVAL for
+ *   kappa < 2, src NULL or (i, j) outside the grid.  Host code only (no device work).
+ * bl_solve_kgrid: solves every point, (0, 0) from start_dev (device FP64 planar block of p
+ *   columns, required), every other one from the Rayleigh-quotient extrapolation over its
+ *   sources (at most extrap_depth of them, the most recent first), each then iterated as in
+ *   bl_solve_k.  evals, relres: host kappa*kappa*nev (row j*kappa + i); iters: host
+ *   kappa*kappa.  Holds 15 more blocks of p columns on the device while it runs (BL_ENOMEM
+ *   when they cannot be allocated); the handle's history afterwards holds the blocks of the
+ *   last point's sources and the last point.  Returns BL_EINVAL (arguments), BL_EHIP, or
+ *   after finishing the grid the first non-OK point status (BL_ENOCONV points keep their
+ *   best approximations). */
+int bl_raster_sources(int32_t kappa, int32_t i, int32_t j, int32_t* src);
+int bl_solve_kgrid(bl_solver* s, int32_t kappa, const void* start_dev, double* evals,
+                   double* relres, int32_t* iters);
 
 /* Forget the extrapolation history. */
 int bl_reset_history(bl_solver* s);

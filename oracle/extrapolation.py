@@ -12,6 +12,13 @@ zero (left-over gradient content) and are skipped.
 The first parameter of a path starts from a seeded random block (the nested iteration of
 Section 6 is not used here).
 
+On the kappa x kappa grid of Bloch parameters (Section 6) the sources of each point follow
+the raster the paper describes: the first row left to right from its predecessors, the
+first three columns upward from the points below, and every other point from the three
+points to its left in its row.  The paper lists the horizontal rule for rows j >= 3 only;
+rows 1 and 2 beyond the third column are read the same way (the three points to the left
+exist there too).
+
 Pinned by: Courant-Fischer (extrapolated Ritz values are upper bounds of the true
 eigenvalues; with the exact eigenvectors of the same k in the span they are reproduced),
 and the end-to-end path results against dense solves (tests).
@@ -25,7 +32,7 @@ from .householder import m_householder, reference_columns
 from .multigrid import Hierarchy
 from .pinvit import Projector, initial_block, pinvit, ritz
 
-__all__ = ["extrapolate", "solve_path"]
+__all__ = ["extrapolate", "solve_path", "raster_k", "raster_sources", "solve_grid"]
 
 
 def extrapolate(disc, proj, history, p: int, zero_thr: float):
@@ -64,4 +71,54 @@ def solve_path(n, m, a, b, eps, ks, nev, nthrow, start, tol=1e-8, max_iter=200, 
         out.append(rec)
         if on_point is not None:
             on_point(t, rec, E)
+    return out
+
+
+def raster_k(kappa: int, i: int, j: int, a: float = 1.0, b: float = 1.0):
+    """Section 6: the Bloch parameter k_ij = (pi/a (2 i/(kappa-1) - 1), pi/b (2 j/(kappa-1) - 1))."""
+    return (np.pi / a * (2.0 * i / (kappa - 1) - 1.0), np.pi / b * (2.0 * j / (kappa - 1) - 1.0))
+
+
+def raster_sources(kappa: int, i: int, j: int):
+    """Section 6: the grid points (i', j') whose eigenvector blocks give the start block of
+    point (i, j), oldest first: none for (0, 0); along the first row the up to three points to
+    the left; in the first three columns the up to three points below; elsewhere the three
+    points to the left."""
+    if not (0 <= i < kappa and 0 <= j < kappa):
+        raise ValueError("point outside the grid")
+    if j == 0:
+        return [(s, 0) for s in range(max(0, i - 3), i)]
+    if i <= 2:
+        return [(i, s) for s in range(max(0, j - 3), j)]
+    return [(s, j) for s in range(i - 3, i)]
+
+
+def solve_grid(n, m, a, b, eps, kappa, nev, nthrow, start, tol=1e-8, max_iter=200, mu=None,
+               nodal_cycles=2, max_levels=0, coarsest_min=8, zero_rel=1e-2, absolute=False,
+               nu_pre=1, nu_post=1):
+    """Every point of the kappa x kappa grid in raster order (row j = 0 .. kappa-1, within a
+    row i = 0 .. kappa-1), (0, 0) from `start`, every other point extrapolated from the blocks
+    of raster_sources (most recent first) with the zero threshold zero_rel times the smallest
+    eigenvalue of the most recent source.  Returns a list of dicts in raster order."""
+    p = nev + nthrow
+    blocks = {}
+    out = []
+    for j in range(kappa):
+        for i in range(kappa):
+            k1, k2 = raster_k(kappa, i, j, a, b)
+            disc = Discretization(n, m, a, b, eps, k1, k2)
+            hier = Hierarchy(disc, mu=mu, max_levels=max_levels, coarsest_min=coarsest_min,
+                             nu_pre=nu_pre, nu_post=nu_post)
+            proj = Projector(disc, hier, nodal_cycles)
+            src = raster_sources(kappa, i, j)
+            if not src:
+                lam, E = initial_block(disc, proj, start, p)
+            else:
+                hist = [blocks[q][0] for q in reversed(src)]
+                lam, E = extrapolate(disc, proj, hist, p, zero_rel * blocks[src[-1]][1])
+            lam, E, rel, it, conv = pinvit(disc, hier, proj, E, lam, nev, tol, max_iter,
+                                           absolute=absolute)
+            blocks[(i, j)] = (E, float(lam[0]))
+            out.append({"ij": (i, j), "k": (k1, k2), "lam": lam[:nev].copy(),
+                        "relres": rel[:nev].copy(), "iterations": it, "converged": conv})
     return out

@@ -6,7 +6,7 @@ The computation lives in libbloch.so (HIP kernels for gfx950 behind the C ABI of
 include/bloch.h); this package is its Python binding.  PyTorch provides device memory
 and the stream.
 """
-from .api import Batch, Server, Solver, batch_solve, to_device_block, from_device_block  # noqa: F401
+from .api import Batch, Server, Solver, batch_solve, raster_sources, to_device_block, from_device_block  # noqa: F401
 from .native import OPS, load  # noqa: F401
 
-__all__ = ["Solver", "Server", "Batch", "batch_solve", "to_device_block", "from_device_block", "OPS", "load"]
+__all__ = ["Solver", "Server", "Batch", "batch_solve", "raster_sources", "to_device_block", "from_device_block", "OPS", "load"]

@@ -60,6 +60,15 @@ def _make_opts(nev=8, **opts) -> BlOpts:
     return o
 
 
+def raster_sources(kappa, i, j):
+    """Grid points (i', j') whose blocks give the start block of point (i, j) of the
+    kappa x kappa Bloch grid (Section 6), oldest first."""
+    lib = native.load()
+    buf = (ctypes.c_int32 * 6)()
+    c = check(lib.bl_raster_sources(int(kappa), int(i), int(j), buf), "bl_raster_sources")
+    return [(buf[2 * q], buf[2 * q + 1]) for q in range(c)]
+
+
 def _start_block(start, p, n_edges):
     torch = _torch()
     if isinstance(start, np.ndarray):
@@ -385,6 +394,22 @@ class Solver:
                                     its.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _ptr(vec))
         check(rc, "bl_solve_path", allow=(native.BL_ENOCONV,) if allow_noconv else ())
         return {"evals": ev, "relres": rr, "iterations": its, "converged": rc == 0, "evecs": vec}
+
+    def solve_kgrid(self, kappa, start, allow_noconv=False):
+        """Every point k_ij of the kappa x kappa Bloch grid in raster order (Section 6); arrays
+        are indexed [j, i]."""
+        start = self._start(start)
+        if start is None:
+            raise ValueError("the grid's first point needs a start block")
+        kappa = int(kappa)
+        ev = np.zeros((kappa, kappa, self.nev))
+        rr = np.zeros((kappa, kappa, self.nev))
+        its = np.zeros((kappa, kappa), dtype=np.int32)
+        rc = self.lib.bl_solve_kgrid(self.h, kappa, _ptr(start), ev.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     rr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     its.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        check(rc, "bl_solve_kgrid", allow=(native.BL_ENOCONV,) if allow_noconv else ())
+        return {"evals": ev, "relres": rr, "iterations": its, "converged": rc == 0}
 
     def reset_history(self):
         check(self.lib.bl_reset_history(self.h), "bl_reset_history")

@@ -35,6 +35,32 @@ int run_task(bl_solver* s, Task& t) {
   return BL_OK;
 }
 
+// Section 6 raster: sources of grid point (i, j), oldest first, as (i', j') pairs.
+int raster_sources(int kappa, int i, int j, int32_t* src) {
+  int c = 0;
+  auto put = [&](int a, int b) {
+    src[2 * c] = a;
+    src[2 * c + 1] = b;
+    ++c;
+  };
+  if (j == 0)
+    for (int q = std::max(0, i - 3); q < i; ++q) put(q, 0);
+  else if (i <= 2)
+    for (int q = std::max(0, j - 3); q < j; ++q) put(i, q);
+  else
+    for (int q = i - 3; q < i; ++q) put(q, j);
+  (void)kappa;
+  return c;
+}
+
+// Blocks kept while a grid is solved: the points of columns 0..2 in a ring of four rows (a
+// point of those columns is a source of the three rows above it), and every point in a ring
+// of three along its row (the horizontal sources).
+constexpr int kKeepBlocks = 15;
+int keep_column(int i, int j) { return i * 4 + (j & 3); }
+int keep_row(int i) { return 12 + i % 3; }
+int keep_of_source(int si, int sj, int j) { return sj == j ? keep_row(si) : keep_column(si, sj); }
+
 }  // namespace
 
 extern "C" {
@@ -162,6 +188,80 @@ int bl_solve_path(bl_solver* s, const double* ks, int32_t nk, const void* start_
   if (relres) std::memcpy(relres, t.relres.data(), cnt * 8);
   if (iters) std::memcpy(iters, t.iters.data(), (size_t)nk * 4);
   return rc;
+}
+
+int bl_raster_sources(int32_t kappa, int32_t i, int32_t j, int32_t* src) {
+  if (kappa < 2 || !src || i < 0 || j < 0 || i >= kappa || j >= kappa)
+    return set_error(BL_EINVAL, "kappa >= 2, src and a point of the grid required%s");
+  return raster_sources(kappa, i, j, src);
+}
+
+int bl_solve_kgrid(bl_solver* s, int32_t kappa, const void* start_dev, double* evals, double* relres,
+                   int32_t* iters) {
+  if (!s || kappa < 2 || kappa > 4096 || !start_dev || !evals || !relres || !iters)
+    return set_error(BL_EINVAL, "invalid grid arguments%s");
+  const int nev = s->opts.nev;
+  const size_t blk = (size_t)s->p * 2 * s->lv[0].g.ne;   // doubles per block (slot 0)
+  double* keep = nullptr;
+  if (hipMalloc((void**)&keep, kKeepBlocks * blk * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    return set_error(BL_ENOMEM, "no device memory for the grid's kept blocks%s");
+  }
+  double keep_lam1[kKeepBlocks] = {};
+  int first = BL_OK, rc = BL_OK;
+  const double pa = M_PI / s->grid.a, pb = M_PI / s->grid.b;
+  for (int j = 0; j < kappa && rc == BL_OK; ++j)
+    for (int i = 0; i < kappa; ++i) {
+      int32_t src[6];
+      const int c = raster_sources(kappa, i, j, src);
+      const int d = std::min(c, s->opts.extrap_depth);
+      SlotState& ss = s->slot[0];
+      for (int h = 0; h < d; ++h) {   // hist[0] = the most recent source
+        const int q = c - 1 - h;
+        const int id = keep_of_source(src[2 * q], src[2 * q + 1], j);
+        if (hipMemcpyAsync(s->hist[h], keep + id * blk, blk * sizeof(double), hipMemcpyDeviceToDevice, s->st) !=
+            hipSuccess) {
+          rc = set_error(BL_EHIP, "history copy failed%s");
+          break;
+        }
+      }
+      if (rc) break;
+      if (c > 0) {
+        ss.hist_count = d;
+        ss.hist_lam1 = keep_lam1[keep_of_source(src[2 * c - 2], src[2 * c - 1], j)];
+      }
+      Task t;
+      t.ks = {pa * (2.0 * i / (kappa - 1) - 1.0), pb * (2.0 * j / (kappa - 1) - 1.0)};
+      t.start_dev = c == 0 ? start_dev : nullptr;
+      t.nev = nev;
+      const int r = run_task(s, t);
+      if (r != BL_OK && r != BL_ENOCONV) {
+        rc = r;
+        break;
+      }
+      if (r != BL_OK && first == BL_OK) first = r;
+      const size_t row = (size_t)j * kappa + i;
+      std::memcpy(evals + row * nev, t.evals.data(), (size_t)nev * 8);
+      std::memcpy(relres + row * nev, t.relres.data(), (size_t)nev * 8);
+      iters[row] = t.iters[0];
+      // the solved block is the newest history entry now
+      const int ids[2] = {keep_row(i), i <= 2 ? keep_column(i, j) : -1};
+      for (int id : ids) {
+        if (id < 0) continue;
+        if (hipMemcpyAsync(keep + id * blk, s->hist[0], blk * sizeof(double), hipMemcpyDeviceToDevice, s->st) !=
+            hipSuccess) {
+          rc = set_error(BL_EHIP, "history copy failed%s");
+          break;
+        }
+        keep_lam1[id] = ss.hist_lam1;
+      }
+      if (rc) break;
+    }
+  const hipError_t se = hipStreamSynchronize(s->st);
+  (void)hipFree(keep);
+  if (rc) return rc;
+  if (se != hipSuccess) return set_error(BL_EHIP, "HIP error: %s", hipGetErrorString(se));
+  return first;
 }
 
 int bl_reset_history(bl_solver* s) {

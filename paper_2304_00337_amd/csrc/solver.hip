@@ -124,6 +124,7 @@ int validate_opts(const bl_opts* o) {
   if (o->tiled_sweeps < 0 || o->tiled_sweeps > 2) return set_error(BL_EINVAL, "tiled_sweeps must be 0, 1 or 2%s");
   if (o->engine_streams < 1 || o->engine_streams > 16) return set_error(BL_EINVAL, "engine_streams must be 1..16%s");
   if (!(o->tol > 0)) return set_error(BL_EINVAL, "tol must be positive%s");
+  if (o->tol_abs != 0 && o->tol_abs != 1) return set_error(BL_EINVAL, "tol_abs must be 0 or 1%s");
   return BL_OK;
 }
 
@@ -1093,7 +1094,7 @@ int engine_finish(bl_solver* s) {
     double rel[256];
     for (int j = 0; j < p; ++j) {
       const double den = std::fabs(lam[j]) * std::sqrt(nr[2 * j + 1]);
-      rel[j] = den > 0 ? std::sqrt(nr[2 * j]) / den : INFINITY;
+      rel[j] = s->opts.tol_abs ? std::sqrt(nr[2 * j]) : den > 0 ? std::sqrt(nr[2 * j]) / den : INFINITY;
     }
     bool conv = true;
     for (int j = 0; j < t->nev; ++j) {

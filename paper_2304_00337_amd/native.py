@@ -37,7 +37,7 @@ class BlOpts(ctypes.Structure):
                 ("precision", c_int32), ("extrap_depth", c_int32), ("autotune", c_int32),
                 ("coarse_fuse", c_int32), ("tiled_sweeps", c_int32),
                 ("tol", c_double), ("mu", c_double), ("zero_rel", c_double),
-                ("engine_streams", c_int32), ("reserved2", c_int32)]
+                ("engine_streams", c_int32), ("tol_abs", c_int32)]
 
 
 class BlInfo(ctypes.Structure):
@@ -85,6 +85,8 @@ EXPORTED = {
     "bl_solve_path": (c_int32, [c_void_p, P(c_double), c_int32, c_void_p, P(c_double),
                                 P(c_double), P(c_int32), c_void_p]),
     "bl_reset_history": (c_int32, [c_void_p]),
+    "bl_raster_sources": (c_int32, [c_int32, c_int32, c_int32, P(c_int32)]),
+    "bl_solve_kgrid": (c_int32, [c_void_p, c_int32, c_void_p, P(c_double), P(c_double), P(c_int32)]),
     "bl_last_residual_history": (c_int32, [c_void_p, P(c_double), c_int32]),
     "bl_set_k": (c_int32, [c_void_p, c_double, c_double]),
     "bl_set_timing": (c_int32, [c_void_p, c_int32]),

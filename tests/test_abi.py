@@ -82,3 +82,21 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for f in py._fields_:
             assert got[(cname, f[0])] == getattr(py, f[0]).offset, (cname, f[0])
+
+
+def test_raster_sources_match_the_oracle():
+    """Host logic of the Section 6 raster: the library's sources of every grid point equal
+    the oracle's, bit for bit; invalid arguments are rejected."""
+    from oracle.extrapolation import raster_sources as ref
+    from paper_2304_00337_amd import native
+    from paper_2304_00337_amd.api import raster_sources
+    for kappa in (2, 3, 4, 5, 7, 30):
+        for j in range(kappa):
+            for i in range(kappa):
+                assert raster_sources(kappa, i, j) == ref(kappa, i, j), (kappa, i, j)
+    lib = native.load()
+    buf = (ctypes.c_int32 * 6)()
+    assert lib.bl_raster_sources(1, 0, 0, buf) == native.BL_EINVAL
+    assert lib.bl_raster_sources(4, 4, 0, buf) == native.BL_EINVAL
+    assert lib.bl_raster_sources(4, 0, -1, buf) == native.BL_EINVAL
+    assert lib.bl_raster_sources(4, 1, 1, None) == native.BL_EINVAL

@@ -176,6 +176,41 @@ def test_throwaway_rates_match_oracle():
         assert ref[2]["rates"][i] < ref[1]["rates"][i] < ref[0]["rates"][i]
 
 
+def test_kgrid_raster_matches_oracle():
+    """The Section 6 raster through the C ABI (bl_solve_kgrid) on a 4 x 4 Bloch grid of the
+    32 x 32 mesh with the band-structure permittivity: per point the eigenvalues equal the
+    oracle's raster run to 1e-9 and its iteration counts agree; with the absolute defect as
+    stopping measure (tol_abs) the reported defects are below the tolerance and the
+    eigenvalues match the dense solve to it."""
+    from oracle.extrapolation import solve_grid
+    from paper_2304_00337_amd import Solver
+    n, kappa, nev, nthrow, mu = 32, 4, 6, 3, 5.0
+    eps = synth.paper_z2_eps(n)
+    start = synth.start_block(2 * n * n, nev + nthrow, 8)
+    ref = solve_grid(n, n, 1.0, 1.0, eps, kappa, nev, nthrow, start, tol=1e-9, mu=mu, coarsest_min=4)
+    s = Solver(n, n, 1.0, 1.0, eps, nev=nev, nthrow=nthrow, mu=mu, coarsest_min=4, tol=1e-9, max_iter=300)
+    out = s.solve_kgrid(kappa, start)
+    assert out["converged"]
+    its_o = []
+    for r in ref:
+        i, j = r["ij"]
+        assert r["converged"]
+        assert np.max(np.abs(out["evals"][j, i] - r["lam"]) / r["lam"]) < 1e-9, (i, j)
+        it = int(out["iterations"][j, i])
+        assert abs(it - r["iterations"]) <= max(3, int(0.2 * r["iterations"])), (i, j, it, r["iterations"])
+        its_o.append(r["iterations"])
+    assert abs(int(out["iterations"].sum()) - sum(its_o)) <= 0.1 * sum(its_o)
+    sa = Solver(n, n, 1.0, 1.0, eps, nev=nev, nthrow=nthrow, mu=mu, coarsest_min=4, tol=1e-3, tol_abs=1,
+                max_iter=300)
+    oa = sa.solve_kgrid(2, start)
+    assert oa["converged"] and np.all(oa["relres"] <= 1e-3)
+    for j in range(2):
+        for i in range(2):
+            d = fem.Discretization(n, n, 1.0, 1.0, eps, *((2 * i - 1) * math.pi, (2 * j - 1) * math.pi))
+            lam, _, _ = dense_eigs(d, nev)
+            assert np.max(np.abs(oa["evals"][j, i] - lam) / lam) < 1e-3
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_short_path_matches_oracle_path(precision):
     n = 32

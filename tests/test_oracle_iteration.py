@@ -19,7 +19,7 @@ import synth
 from oracle import fem
 from oracle.closed_form import discrete_nonzero
 from oracle.dense import dense_eigs, shift_invert_eigs
-from oracle.extrapolation import extrapolate, solve_path
+from oracle.extrapolation import extrapolate, raster_k, raster_sources, solve_grid, solve_path
 from oracle.householder import m_householder, reference_columns
 from oracle.multigrid import Hierarchy
 from oracle.pinvit import Projector, initial_block, pinvit
@@ -154,3 +154,61 @@ def test_shift_invert_reference_certifies_completeness():
     lam_s, _, reached = shift_invert_eigs(d, 5, sigma=0.75 * 1.1 * lam_d[4], extra=40)
     assert reached
     assert np.max(np.abs(lam_s[:5] - lam_d) / lam_d) < 1e-10
+
+
+def test_raster_sources_follow_section_6():
+    """The raster as Section 6 lists it: k10 from k00; k20 from k00, k10; k_i0 from the three
+    to its left; k01, k11, k21 from k00, k10, k20; k02 .. k22 from the two below; k0j .. k2j
+    from the three below (j >= 3); k_ij from the three to its left (i, j >= 3).  Every source
+    precedes its point in raster order and lies on one axis within distance 3."""
+    K = 9
+    assert raster_sources(K, 0, 0) == []
+    assert raster_sources(K, 1, 0) == [(0, 0)]
+    assert raster_sources(K, 2, 0) == [(0, 0), (1, 0)]
+    assert raster_sources(K, 6, 0) == [(3, 0), (4, 0), (5, 0)]
+    for i in range(3):
+        assert raster_sources(K, i, 1) == [(i, 0)]
+        assert raster_sources(K, i, 2) == [(i, 0), (i, 1)]
+        assert raster_sources(K, i, 5) == [(i, 2), (i, 3), (i, 4)]
+    assert raster_sources(K, 5, 4) == [(2, 4), (3, 4), (4, 4)]
+    assert raster_sources(K, 3, 3) == [(0, 3), (1, 3), (2, 3)]
+    for j in range(K):
+        for i in range(K):
+            src = raster_sources(K, i, j)
+            assert (len(src) == 0) == (i == 0 and j == 0) and len(src) <= 3
+            for (a, b) in src:
+                assert b * K + a < j * K + i
+                assert (a == i and 0 < j - b <= 3) or (b == j and 0 < i - a <= 3)
+    k = raster_k(K, 0, K - 1, 2.0, 0.5)
+    assert np.allclose(k, (-np.pi / 2.0, np.pi / 0.5))
+
+
+def test_grid_raster_matches_dense_and_warm_starts():
+    """The raster on the 16 x 16 mesh with the band-structure permittivity (11.56 in the disc
+    of radius 0.18).  kappa = 3: every point (Gamma at the centre included) converges to the
+    dense eigenvalues, and k_20 = k_00 + (2 pi, 0) carries the same pencil, so its start
+    extrapolated from k_00 and k_10 is already converged (Courant-Fischer reproduction).
+    kappa = 5: the extrapolated points need fewer iterations than the random start.  With
+    the absolute defect as stopping measure the reported defects are below the tolerance."""
+    n, nev, nthrow = 16, 4, 2
+    eps = synth.paper_z2_eps(n)
+    start = synth.start_block(2 * n * n, nev + nthrow, 7)
+    kw = dict(tol=1e-9, mu=5.0, coarsest_min=4)
+    res = solve_grid(n, n, 1.0, 1.0, eps, 3, nev, nthrow, start, **kw)
+    assert [r["ij"] for r in res] == [(i, j) for j in range(3) for i in range(3)]
+    for r in res:
+        assert r["converged"]
+        d = fem.Discretization(n, n, 1.0, 1.0, eps, *r["k"])
+        lam, _, _ = dense_eigs(d, nev)
+        assert np.max(np.abs(r["lam"] - lam) / lam) < 1e-8
+    assert res[2]["iterations"] == 0 and np.allclose(res[2]["lam"], res[0]["lam"], rtol=1e-9)
+    res5 = solve_grid(n, n, 1.0, 1.0, eps, 5, nev, nthrow, start, **kw)
+    assert all(r["converged"] for r in res5)
+    assert np.median([r["iterations"] for r in res5[1:]]) < res5[0]["iterations"]
+    ab = solve_grid(n, n, 1.0, 1.0, eps, 2, nev, nthrow, start, tol=1e-3, mu=5.0,
+                    coarsest_min=4, absolute=True)
+    for r in ab:
+        assert r["converged"] and np.all(r["relres"] <= 1e-3)
+        d = fem.Discretization(n, n, 1.0, 1.0, eps, *r["k"])
+        lam, _, _ = dense_eigs(d, nev)
+        assert np.max(np.abs(r["lam"] - lam) / lam) < 1e-3
