@@ -241,14 +241,14 @@ void timing_end(bl_solver* s, int l, int ncols, double bytes) {
 // Algorithmic HBM bytes of one smoother launch over `ncols` columns of `nact` slots: a tiled
 // sweep reads b (and x unless it starts from zero) and writes x once; a colour pass reads x
 // and half of b and writes half of x.  Per slot: the cell coefficients and the patch
-// inverses (6 per node) once per sweep, a quarter of the inverses per colour pass.
+// inverses (kPatchW per node) once per sweep, a quarter of the inverses per colour pass.
 // extra: further vectors per column, in units of one fine edge vector (a folded restriction
 // writes and a folded prolongation reads a coarse vector, a quarter of one)
 double smooth_bytes(const Geo& g, size_t elem, bool sweep, bool zero_start, int ncols, int nact,
                     double extra = 0.0) {
   const double vec = 2.0 * (double)g.ne * (double)elem;
-  if (sweep) return ncols * vec * ((zero_start ? 2.0 : 3.0) + extra) + nact * (double)g.nm * elem * 7.0;
-  return ncols * vec * 2.0 + nact * (double)g.nm * elem * (1.0 + 6.0 / 4.0);
+  if (sweep) return ncols * vec * ((zero_start ? 2.0 : 3.0) + extra) + nact * (double)g.nm * elem * (1.0 + kPatchW);
+  return ncols * vec * 2.0 + nact * (double)g.nm * elem * (1.0 + kPatchW / 4.0);
 }
 void timing_collect(bl_solver* s) {
   if (!s->timing) return;
