@@ -310,7 +310,7 @@ def main():
     # finest-level node-patch Gauss-Seidel.  Compulsory bytes per launch, summed by the
     # library over the timed launches: per column b read, x read (not when the sweep starts
     # from zero) and x written once; per slot the coefficients kappa (one value per cell) and
-    # the 3x3 patch inverses (6 values per node) once.
+    # the patch inverses W (10 values per node) once.
     tm = iso["timing"]
     avg_cols = tm["columns"] / max(1, tm["launches"])
     bytes_per_launch = tm["alg_bytes"] / max(1, tm["launches"])
