@@ -243,6 +243,36 @@ def kgrid_raster(n=256, kappa=30, nev=16, nthrow=8, seed=9):
             "not_converged": int((~conv).sum())}
 
 
+def nested_first_point(prob, seed=1):
+    """The path's first Bloch parameter cold-started two ways on one handle (mixed precision):
+    from the seeded random block, and from the nested iteration of Section 6 (dense coarsest
+    solve, then prolongation and iteration level by level to 1e-3); wall time of each and
+    the finest-level iterations."""
+    import torch
+    import synth
+    from paper_2304_00337_amd import Solver, to_device_block
+    s = Solver(prob.n, prob.m, prob.a, prob.b, prob.eps, nev=prob.nev, nthrow=prob.nthrow, tol=prob.tol,
+               max_iter=300, precision="mixed", levels=prob.levels)
+    k = prob.ks[0]
+    st = to_device_block(synth.start_block(prob.n_edges, prob.p, seed))
+    s.solve_k(*k, start=st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r0 = s.solve_k(*k, start=st)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    start, its = s.nested_start(*k, tol_levels=1e-3)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    r1 = s.solve_k(*k, start=start)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    return {"k": [float(k[0]), float(k[1])], "random_start": {"iterations": r0["iterations"], "ms": round(1e3 * (t1 - t0), 2)},
+            "nested": {"level_iterations": its.tolist(), "start_ms": round(1e3 * (t2 - t1), 2),
+                       "iterations": r1["iterations"], "solve_ms": round(1e3 * (t3 - t2), 2)},
+            "max_rel_eig_diff": float(np.max(np.abs(r0["evals"] - r1["evals"]) / r0["evals"]))}
+
+
 def recorded_traffic(avg_cols):
     """HBM bytes per launch of the finest-level edge smoother from the recorded counter runs
     (profiles/edge_sweep_traffic.json: FETCH_SIZE and WRITE_SIZE per dispatch, calibrated on a
@@ -402,6 +432,7 @@ def main():
     if not args.headline_only:
         out["throwaway"] = throwaway_study()
         out["kgrid"] = kgrid_raster()
+        out["nested_start"] = nested_first_point(prob)
     if not args.no_serving:
         out["serving"] = serving(args.serve_requests, seed=4)
     print(json.dumps(out), flush=True)

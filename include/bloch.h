@@ -192,6 +192,20 @@ int bl_raster_sources(int32_t kappa, int32_t i, int32_t j, int32_t* src);
 int bl_solve_kgrid(bl_solver* s, int32_t kappa, const void* start_dev, double* evals,
                    double* relres, int32_t* iters);
 
+/* Nested iteration for a first Bloch parameter (Section 6): the p smallest non-zero
+ * eigenpairs of the coarsest level's pencil by a direct (dense) solve, then level by level
+ * up the hierarchy: the block is prolongated to the next finer level and, below the finest
+ * level, iterated there (on a temporary handle for that level's mesh, with the same
+ * options, the handle's mu and relative tolerance tol_levels) before moving on.  out_dev
+ * (device FP64 planar block of p columns of length N_e) receives the block prolongated to
+ * the finest level: the start block of bl_solve_k / bl_solve_path / a batch problem.
+ * level_iters: NULL or host array of `levels` entries receiving the iterations per level
+ * (0 for the finest and the coarsest).  Errors: BL_EINVAL (arguments, or a coarsest level
+ * of more than 255 edges), BL_ENOCONV (fewer than p non-zero coarse eigenvalues), BL_ENOMEM,
+ * BL_EHIP.  Sets the handle's Bloch parameter for bl_apply to k. */
+int bl_nested_start(bl_solver* s, double k1, double k2, double tol_levels, void* out_dev,
+                    int32_t* level_iters);
+
 /* Forget the extrapolation history. */
 int bl_reset_history(bl_solver* s);
 

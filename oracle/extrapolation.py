@@ -27,12 +27,14 @@ from __future__ import annotations
 
 import numpy as np
 
-from .fem import Discretization
+from .dense import dense_eigs
+from .fem import Discretization, phases
 from .householder import m_householder, reference_columns
-from .multigrid import Hierarchy
+from .multigrid import Hierarchy, edge_prolongation, level_sizes
 from .pinvit import Projector, initial_block, pinvit, ritz
 
-__all__ = ["extrapolate", "solve_path", "raster_k", "raster_sources", "solve_grid"]
+__all__ = ["extrapolate", "solve_path", "raster_k", "raster_sources", "solve_grid", "level_kappas",
+           "nested_start"]
 
 
 def extrapolate(disc, proj, history, p: int, zero_thr: float):
@@ -122,3 +124,44 @@ def solve_grid(n, m, a, b, eps, kappa, nev, nthrow, start, tol=1e-8, max_iter=20
             out.append({"ij": (i, j), "k": (k1, k2), "lam": lam[:nev].copy(),
                         "relres": rel[:nev].copy(), "iterations": it, "converged": conv})
     return out
+
+
+def level_kappas(n: int, m: int, eps, sizes):
+    """kappa = 1/eps on every level of the hierarchy: each coarse cell takes the mean of its
+    2 x 2 children (the rediscretisation that equals the Galerkin coarse operators)."""
+    kap = [1.0 / np.asarray(eps, dtype=np.float64).reshape(m, n)]
+    for (cn, cm) in sizes[1:]:
+        f = kap[-1]
+        kap.append(0.25 * (f[0::2, 0::2] + f[0::2, 1::2] + f[1::2, 0::2] + f[1::2, 1::2]))
+    return [k.reshape(-1) for k in kap]
+
+
+def nested_start(n, m, a, b, eps, k1, k2, nev, nthrow, tol_levels=1e-3, max_iter=200, mu=None,
+                 nodal_cycles=2, max_levels=0, coarsest_min=8, nu_pre=1, nu_post=1):
+    """Section 6, first Bloch parameter: the p = nev + nthrow smallest non-zero eigenpairs of
+    the coarsest level by a dense generalized eigensolve; then for each finer level the block
+    is prolongated (the embedding of the coarse edge space) and, below the finest level,
+    iterated on that level to the relative residual tol_levels.  Returns the block
+    prolongated to the finest level and the iterations per level (finest first; 0 for the
+    finest and the coarsest)."""
+    p = nev + nthrow
+    sizes = level_sizes(n, m, max_levels, coarsest_min)
+    kap = level_kappas(n, m, eps, sizes)
+    L = len(sizes)
+    al, be = phases(k1, k2, a, b)
+    nc, mc = sizes[-1]
+    _, E, _ = dense_eigs(Discretization(nc, mc, a, b, 1.0 / kap[-1], k1, k2), p)
+    iters = [0] * L
+    for l in range(L - 2, -1, -1):
+        nf, mf = sizes[l]
+        E = edge_prolongation(nf, mf, a, b, al, be) @ E
+        if l == 0:
+            break
+        disc = Discretization(nf, mf, a, b, 1.0 / kap[l], k1, k2)
+        hier = Hierarchy(disc, mu=mu, max_levels=L - l, coarsest_min=coarsest_min,
+                         nu_pre=nu_pre, nu_post=nu_post)
+        proj = Projector(disc, hier, nodal_cycles)
+        lam, E = initial_block(disc, proj, E, p)
+        lam, E, _, it, _ = pinvit(disc, hier, proj, E, lam, nev, tol_levels, max_iter)
+        iters[l] = it
+    return E, iters

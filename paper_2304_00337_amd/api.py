@@ -395,6 +395,17 @@ class Solver:
         check(rc, "bl_solve_path", allow=(native.BL_ENOCONV,) if allow_noconv else ())
         return {"evals": ev, "relres": rr, "iterations": its, "converged": rc == 0, "evecs": vec}
 
+    def nested_start(self, k1, k2, tol_levels=1e-3):
+        """Start block for a first Bloch parameter by nested iteration (Section 6): returns the
+        device block and the iterations spent per level."""
+        torch = _torch()
+        out = torch.empty((self.p, 2, self.n_edges), dtype=torch.float64, device="cuda")
+        L = self.info()["levels"]
+        its = np.zeros(L, dtype=np.int32)
+        check(self.lib.bl_nested_start(self.h, float(k1), float(k2), float(tol_levels), _ptr(out),
+                                       its.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))), "bl_nested_start")
+        return out, its
+
     def solve_kgrid(self, kappa, start, allow_noconv=False):
         """Every point k_ij of the kappa x kappa Bloch grid in raster order (Section 6); arrays
         are indexed [j, i]."""

@@ -87,6 +87,7 @@ EXPORTED = {
     "bl_reset_history": (c_int32, [c_void_p]),
     "bl_raster_sources": (c_int32, [c_int32, c_int32, c_int32, P(c_int32)]),
     "bl_solve_kgrid": (c_int32, [c_void_p, c_int32, c_void_p, P(c_double), P(c_double), P(c_int32)]),
+    "bl_nested_start": (c_int32, [c_void_p, c_double, c_double, c_double, c_void_p, P(c_int32)]),
     "bl_last_residual_history": (c_int32, [c_void_p, P(c_double), c_int32]),
     "bl_set_k": (c_int32, [c_void_p, c_double, c_double]),
     "bl_set_timing": (c_int32, [c_void_p, c_int32]),

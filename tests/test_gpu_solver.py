@@ -176,6 +176,36 @@ def test_throwaway_rates_match_oracle():
         assert ref[2]["rates"][i] < ref[1]["rates"][i] < ref[0]["rates"][i]
 
 
+@pytest.mark.parametrize("k", [(0.7, -1.3), (0.0, 0.0)])
+def test_nested_start_matches_oracle(k):
+    """Nested iteration for a first Bloch parameter (Section 6) through the C ABI: the dense
+    coarsest solve, prolongation and per-level iterations give a start block from which the
+    finest solve reaches the dense eigenvalues in about as many iterations as the oracle's
+    nested start (and fewer than from a random block); per-level counts agree."""
+    from oracle.extrapolation import nested_start
+    from paper_2304_00337_amd import Solver
+    n, nev, nthrow, mu = 32, 6, 3, 10.0
+    eps = synth.eps_disc_lattice(n, n, 1.0, 1.0, 12.0, 0.3)
+    d = fem.Discretization(n, n, 1.0, 1.0, eps, *k)
+    E, its_o = nested_start(n, n, 1.0, 1.0, eps, *k, nev, nthrow, tol_levels=1e-3, mu=mu, coarsest_min=4)
+    H = Hierarchy(d, mu=mu, coarsest_min=4)
+    pr = Projector(d, H, 2)
+    lam0, E0 = initial_block(d, pr, E, nev + nthrow)
+    it_o = pinvit(d, H, pr, E0, lam0, nev, 1e-9, 200)[3]
+    s = Solver(n, n, 1.0, 1.0, eps, nev=nev, nthrow=nthrow, mu=mu, coarsest_min=4, tol=1e-9, max_iter=200)
+    start, its = s.nested_start(*k, tol_levels=1e-3)
+    assert len(its) == len(its_o)
+    for a, b in zip(its, its_o):
+        assert abs(int(a) - b) <= max(2, int(0.2 * b)), (list(its), its_o)
+    r = s.solve_k(*k, start=start)
+    ref, _, _ = dense_eigs(d, nev)
+    assert r["converged"] and np.max(np.abs(r["evals"] - ref) / ref) < 1e-9
+    assert abs(r["iterations"] - it_o) <= max(3, int(0.2 * it_o)), (r["iterations"], it_o)
+    rnd = Solver(n, n, 1.0, 1.0, eps, nev=nev, nthrow=nthrow, mu=mu, coarsest_min=4, tol=1e-9,
+                 max_iter=200).solve_k(*k, start=synth.start_block(d.n_edges, nev + nthrow, 5))
+    assert r["iterations"] < rnd["iterations"]
+
+
 def test_kgrid_raster_matches_oracle():
     """The Section 6 raster through the C ABI (bl_solve_kgrid) on a 4 x 4 Bloch grid of the
     32 x 32 mesh with the band-structure permittivity: per point the eigenvalues equal the

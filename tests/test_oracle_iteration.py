@@ -212,3 +212,35 @@ def test_grid_raster_matches_dense_and_warm_starts():
         d = fem.Discretization(n, n, 1.0, 1.0, eps, *r["k"])
         lam, _, _ = dense_eigs(d, nev)
         assert np.max(np.abs(r["lam"] - lam) / lam) < 1e-3
+
+
+def test_nested_start_follows_section_6():
+    """Nested iteration (Section 6): the coarsest block is the dense solution of the coarsest
+    pencil; the prolongation is the embedding, so the prolongated coarse eigenvectors keep
+    their Rayleigh quotients on the finer mesh's Galerkin hierarchy; the start block needs
+    fewer fine iterations than a random one and the iteration from it reaches the dense values."""
+    from oracle.extrapolation import level_kappas, nested_start
+    from oracle.multigrid import edge_prolongation, level_sizes
+    n = 16
+    eps = synth.eps_disc_lattice(n, n, 1.0, 1.0, 12.0, 0.3)
+    k = (0.7, -1.3)
+    sizes = level_sizes(n, n, 0, 4)
+    kap = level_kappas(n, n, eps, sizes)
+    dc = fem.Discretization(8, 8, 1.0, 1.0, 1.0 / kap[1], *k)
+    lam_c, E_c, _ = dense_eigs(fem.Discretization(4, 4, 1.0, 1.0, 1.0 / kap[2], *k), 5)
+    P = edge_prolongation(8, 8, 1.0, 1.0, dc.alpha, dc.beta)
+    F = P @ E_c
+    rq = np.real(np.einsum("ij,ij->j", F.conj(), dc.A @ F) / np.einsum("ij,ij->j", F.conj(), dc.M @ F))
+    assert np.allclose(rq, lam_c, rtol=1e-11)
+    E, its = nested_start(n, n, 1.0, 1.0, eps, *k, 4, 2, tol_levels=1e-3, mu=10.0, coarsest_min=4)
+    assert its[0] == 0 and its[-1] == 0 and its[1] > 0
+    d = fem.Discretization(n, n, 1.0, 1.0, eps, *k)
+    H = Hierarchy(d, mu=10.0, coarsest_min=4)
+    pr = Projector(d, H, 2)
+    lam0, E0 = initial_block(d, pr, E, 6)
+    lam, _, _, it, conv = pinvit(d, H, pr, E0, lam0, 4, 1e-9, 200)
+    lam1, E1 = initial_block(d, pr, synth.start_block(d.n_edges, 6, 5), 6)
+    it_random = pinvit(d, H, pr, E1, lam1, 4, 1e-9, 200)[3]
+    ref, _, _ = dense_eigs(d, 4)
+    assert conv and np.max(np.abs(lam[:4] - ref) / ref) < 1e-8
+    assert it < it_random
