@@ -28,7 +28,8 @@ import numpy as np
 import scipy.sparse as sp
 
 __all__ = ["phases", "is_gamma", "x_index", "y_index", "node_index", "cell_local_map",
-           "element_matrices", "assemble", "lifting", "nodal_laplacian", "Discretization"]
+           "element_matrices", "assemble", "lifting", "nodal_laplacian", "reduced_k",
+           "plane_wave", "plane_wave_eigenvalue", "Discretization"]
 
 
 def phases(k1: float, k2: float, a: float, b: float):
@@ -205,6 +206,46 @@ def nodal_laplacian(L, M):
     return (L.conj().T @ M @ L).tocsr()
 
 
+def reduced_k(k1: float, k2: float, a: float, b: float):
+    """The representative of k in the first Brillouin zone: k - 2 pi (p/a, r/b) with the
+    integers p, r nearest to k1 a / (2 pi) and k2 b / (2 pi) (ties to even).  Bloch phases
+    only depend on k modulo the reciprocal lattice; this representative is the one whose
+    nodal plane wave has the smallest energy."""
+    return (k1 - 2 * math.pi * round(k1 * a / (2 * math.pi)) / a,
+            k2 - 2 * math.pi * round(k2 * b / (2 * math.pi)) / b)
+
+
+def plane_wave(n: int, m: int, a: float, b: float, k1: float, k2: float) -> np.ndarray:
+    """Nodal vector w_j = exp(i (k1' j1 h1 + k2' j2 h2)) with k' = reduced_k(k) (all ones at
+    the Gamma point).  It satisfies the Bloch condition of the nodal space (Section 3: a
+    node beyond the right/top boundary carries the factor alpha/beta), and since
+    P = L^* M L is a constant-coefficient stencil it is an exact eigenvector of P
+    (checked in the tests against the assembled P).  Its eigenvalue tends to zero as
+    k -> 0, where P becomes singular."""
+    if is_gamma(k1, k2, a, b):
+        return np.ones(n * m, dtype=np.complex128)
+    r1, r2 = reduced_k(k1, k2, a, b)
+    j1, j2 = np.meshgrid(np.arange(n), np.arange(m), indexing="xy")
+    return np.exp(1j * (r1 * j1 * (a / n) + r2 * j2 * (b / m))).reshape(-1)
+
+
+def plane_wave_eigenvalue(n: int, m: int, a: float, b: float, k1: float, k2: float) -> float:
+    """P w = lambda_w w for w = plane_wave(...), in a cancellation-free closed form.
+
+    Derivation: the gradient of w on x-edge (j1, j2) is w_j (exp(i t1) - 1), t1 = k1' h1,
+    with |exp(i t1) - 1|^2 = 4 sin^2(t1/2); the mass matrix couples an x-edge to the x-edges
+    directly above and below with (h2/h1)(2/3, 1/6, 1/6), whose symbol is
+    (h2/h1)(1 - 2/3 sin^2(t2/2)); y-edges likewise with the roles swapped.  Zero at the
+    Gamma point."""
+    if is_gamma(k1, k2, a, b):
+        return 0.0
+    r1, r2 = reduced_k(k1, k2, a, b)
+    h1, h2 = a / n, b / m
+    s1 = math.sin(r1 * h1 / 2) ** 2
+    s2 = math.sin(r2 * h2 / 2) ** 2
+    return 4 * s1 * (h2 / h1) * (1 - 2.0 / 3.0 * s2) + 4 * s2 * (h1 / h2) * (1 - 2.0 / 3.0 * s1)
+
+
 class Discretization:
     """All Section-3 objects for one grid, permittivity and Bloch parameter."""
 
@@ -230,6 +271,11 @@ class Discretization:
     @property
     def n_nodes(self):
         return self.n * self.m
+
+    def plane_wave(self):
+        """The lowest eigenvector of P and its eigenvalue (plane_wave, plane_wave_eigenvalue)."""
+        args = (self.n, self.m, self.a, self.b, self.k1, self.k2)
+        return plane_wave(*args), plane_wave_eigenvalue(*args)
 
     def constant_fields(self):
         """The two constant edge fields x-hat (all x-edges 1) and y-hat: at k = 0 they are

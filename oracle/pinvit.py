@@ -27,20 +27,41 @@ __all__ = ["Projector", "ritz", "initial_block", "pinvit", "residuals"]
 class Projector:
     """Null-space elimination (Section 4): u <- u - L Phi with L^* M L Phi = L^* M u solved
     approximately by `cycles` nodal V-cycles; at k = 0 additionally the constant edge
-    fields (the explicitly known remainder of the kernel) are removed M-orthogonally."""
+    fields (the explicitly known remainder of the kernel) are removed M-orthogonally.
 
-    def __init__(self, disc, hier, cycles: int):
+    Plane-wave deflation (deflate=True, the default; a reading of Sections 4-5): P = L^* M L
+    has the exact eigenvector w = fem.plane_wave (lambda_w = fem.plane_wave_eigenvalue),
+    whose eigenvalue shrinks like |k|^2 h^2 next to the Gamma point, where P turns singular
+    (Section 3 notes the k = 0 kernel).  The nodal solve splits along it: the component of
+    Phi along w is solved exactly, c = (w^* b) / (w^* w lambda_w) (zero at Gamma, where
+    w^* b = 0), and the V-cycles act on the orthogonal complement (right-hand side and
+    result orthogonalised against w).  With exact nodal solves this is the same
+    projection; with V-cycles it removes the near-singular mode exactly, which a
+    single-precision nodal cycle cannot do (its residual loses that mode to rounding).
+    deflate=False is the unsplit form."""
+
+    def __init__(self, disc, hier, cycles: int, deflate: bool = True):
         self.disc, self.hier, self.cycles = disc, hier, cycles
         self.X = None
         if disc.gamma:
             X = disc.constant_fields()
             nrm = np.sqrt(np.real(np.einsum("ij,ij->j", X.conj(), disc.M @ X)))
             self.X = X / nrm
+        self.w = None
+        if deflate:
+            self.w, self.lam_w = disc.plane_wave()
 
     def __call__(self, U):
         d = self.disc
         b = d.L.conj().T @ (d.M @ U)
-        phi = self.hier.nodal_solve(b, self.cycles)
+        if self.w is None:
+            phi = self.hier.nodal_solve(b, self.cycles)
+        else:
+            w, ww = self.w, np.real(np.vdot(self.w, self.w))
+            s = (w.conj() @ b) / ww
+            c = s / self.lam_w if self.lam_w > 0 else np.zeros_like(s)
+            phi = self.hier.nodal_solve(b - np.outer(w, s), self.cycles)
+            phi = phi - np.outer(w, (w.conj() @ phi) / ww) + np.outer(w, c)
         U = U - d.L @ phi
         if self.X is not None:
             U = U - self.X @ (self.X.conj().T @ (d.M @ U))
