@@ -235,14 +235,24 @@ int bl_last_residual_history(const bl_solver* s, double* relres, int32_t cap);
  *                                P Phi = L^* M x (and the k = 0 deflation) (Section 4)
  *   BL_OP_COARSE_EDGE            out = K_c^{-1} x on the coarsest level
  *   BL_OP_COARSE_NODAL           out = P_c^{+} x on the coarsest level
- * x, y, out: device blocks (y only for the smoothers).  Errors: BL_EINVAL, BL_ESTATE
+ *   BL_OP_EIGRES                 out = A x_j - lambda_j M x_j (the iteration's residual,
+ *                                Section 4), lambda = y: ncols FP64 values on the device
+ *   BL_OP_EDGE_SWEEP             out <- one tiled sweep (colours 0..3, one launch) of the
+ *                                node-patch Gauss-Seidel for K out = y, starting from x
+ *                                (x and out must be different blocks)
+ *   BL_OP_EDGE_SWEEP_BACK        same with colours 3..0
+ *   BL_OP_NODAL_SWEEP            out <- one tiled point Gauss-Seidel sweep for P out = y
+ *                                from x (colours 0..3); BL_OP_NODAL_SWEEP_BACK: 3..0
+ * x, y, out: device blocks (y for the smoothers and sweeps).  Errors: BL_EINVAL, BL_ESTATE
  * (no k set), BL_EHIP. */
 enum {
   BL_OP_A = 0, BL_OP_M = 1, BL_OP_K = 2, BL_OP_LIFT = 3, BL_OP_LHM = 4, BL_OP_P = 5,
   BL_OP_EDGE_SMOOTH = 6, BL_OP_EDGE_SMOOTH_BACK = 7, BL_OP_NODAL_SMOOTH = 8,
   BL_OP_EDGE_VCYCLE = 9, BL_OP_NODAL_VCYCLE = 10, BL_OP_EDGE_PROLONG = 11,
   BL_OP_EDGE_RESTRICT = 12, BL_OP_NODAL_PROLONG = 13, BL_OP_NODAL_RESTRICT = 14,
-  BL_OP_PROJECT = 15, BL_OP_COARSE_EDGE = 16, BL_OP_COARSE_NODAL = 17
+  BL_OP_PROJECT = 15, BL_OP_COARSE_EDGE = 16, BL_OP_COARSE_NODAL = 17, BL_OP_EIGRES = 18,
+  BL_OP_EDGE_SWEEP = 19, BL_OP_EDGE_SWEEP_BACK = 20, BL_OP_NODAL_SWEEP = 21,
+  BL_OP_NODAL_SWEEP_BACK = 22
 };
 int bl_set_k(bl_solver* s, double k1, double k2);
 int bl_apply(bl_solver* s, int32_t op, int32_t level, int32_t prec, int32_t ncols,

@@ -104,6 +104,12 @@ struct bl_solver {
   int64_t nce = 0, ncn = 0;
   // per-slot parameters (host mirror and device copy)
   std::vector<bl::Phase> ph_h;
+  std::vector<bl::PlaneWave> pw_h;   // plane-wave deflation parameters per slot
+  bl::PlaneWave* pw_d = nullptr;
+  double* pw_tab = nullptr;          // per slot 2 (n + m) doubles
+  double* pw_part = nullptr;         // nslots * pw_cap columns * pw_blocks partials
+  double* pw_coef = nullptr;         // nslots * pw_cap columns * 6
+  int pw_cap = 0;
   std::vector<double> mu_h, zthr_h;
   bl::Phase* ph_d = nullptr;
   double* mu_d = nullptr;

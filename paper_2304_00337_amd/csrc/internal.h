@@ -24,6 +24,30 @@ struct Phase {
   double ar, ai, br, bi;
 };
 
+// Plane-wave deflation of the nodal solve (null-space elimination, Sections 4-5).  The nodal
+// vector w_j = exp(i (t1 j1 + t2 j2)), t = k' h with k' the first-zone representative of k, is
+// an exact eigenvector of P = L^* M L with eigenvalue lambda_w (-> 0 like |k|^2 h^2 at Gamma).
+// Per slot: t1, t2; ex = exp(i t1) - 1, ey = exp(i t2) - 1 (the gradient of w on an x- / y-edge
+// is w_j ex / w_j ey); inm = 1 / nm; ilw = 1 / (nm lambda_w), zero at Gamma.
+struct PlaneWave {
+  double t1, t2, exr, exi, eyr, eyi, inm, ilw;
+};
+// Arguments of the deflated projection's kernels.  tab: per slot (stride tabstride doubles)
+// the factors exp(i t1 j1), j1 < n, then exp(i t2 j2), j2 < m (interleaved complex).  part:
+// per launch column (index slot_in_launch * pcols + off + j) `nblk` block partials of two
+// doubles.  coef: per launch column six doubles: w^* b / nm, the exact coefficient
+// c = w^* b / (nm lambda_w), and gamma = c - w^* phi' / nm.
+struct PWDefl {
+  const double* tab;
+  const PlaneWave* par;
+  double* part;
+  double* coef;
+  int64_t tabstride;
+  int pcols;
+  int off;
+  int nblk;
+};
+
 // Real 4x4 transform T = D^{-1/2} Q of the stabilised node-patch solve (row-major).
 struct PatchT {
   double t[16];
@@ -62,6 +86,19 @@ template <typename T>
 inline View<T> view(T* p, int cps, int off = 0) { return View<T>{p, cps, off}; }
 template <typename T>
 inline View<const T> cview(const T* p, int cps, int off = 0) { return View<const T>{p, cps, off}; }
+
+// tab for slots 0..nslots-1 from par (after the parameters were uploaded).
+void pw_tables(const PlaneWave* par, double* tab, int64_t tabstride, int n, int m, int nslots, hipStream_t st);
+// mode 0: reduce the w^* b partials (count blocks) of every launch column into coef[0..3];
+// mode 1: reduce the w^* phi' partials into coef[4..5] = c - w^* phi' / nm.
+void pw_reduce(const PWDefl& d, int mode, int count, const Launch& L);
+// b -= w (w^* b / nm) on the launch's nodal columns (partial-free).
+template <typename T>
+void pw_rhs(View<T> b, const Geo& g, const PWDefl& d, const Launch& L);
+// partials of w^* phi on the launch's nodal columns; returns the block count.
+template <typename T>
+int pw_dot(View<const T> phi, const Geo& g, const PWDefl& d, const Launch& L);
+int pw_blocks(const Geo& g);
 
 // ---- launch wrappers (all asynchronous on L.st) --------------------------------------------
 // out = op(x); EM_RESID_K: out = b - (A + mu M) x; EM_EIGRES: out = A x - lam M x with lam of
@@ -150,11 +187,14 @@ void nodal_prolong_add(View<const T> xc, const Geo& gc, View<T> xf, const Geo& g
 template <typename T>
 void nodal_prolong_to(View<const T> xc, const Geo& gc, View<const T> base, View<T> out, const Geo& gf,
                       const Phase* ph, const Launch& L);
+// out = L^* M u; with pw, also the partials of w^* out (FP64, before rounding to TO).
 template <typename TI, typename TO>
-void lhm(View<const TI> u, View<TO> out, const Geo& g, const Phase* ph, const Launch& L);
+void lhm(View<const TI> u, View<TO> out, const Geo& g, const Phase* ph, const Launch& L,
+         const PWDefl* pw = nullptr);
+// out = u - L phi; with pw, also minus gamma L w (gamma = coef[4..5] of the column).
 template <typename TI, typename TP, typename TO>
 void lift_sub(View<const TI> u, View<const TP> phi, View<TO> out, const Geo& g, const Phase* ph,
-              const Launch& L);
+              const Launch& L, const PWDefl* pw = nullptr);
 template <typename TI, typename TO>
 void lift(View<const TI> phi, View<TO> out, const Geo& g, const Phase* ph, const Launch& L);
 // k = 0 deflation of the constant edge fields on the launch's columns of u.

@@ -196,6 +196,18 @@ int ensure_level_buffers(bl_solver* s, int prec, int ecols, int ncols) {
   return BL_OK;
 }
 
+// Partials and coefficients of the plane-wave deflation for projections of up to `cols`
+// columns per slot.
+int ensure_pw(bl_solver* s, int cols) {
+  if (cols <= s->pw_cap) return BL_OK;
+  const size_t nb = (size_t)pw_blocks(s->lv[0].g);
+  int rc;
+  if ((rc = dalloc_t(s, &s->pw_part, nb * 2 * cols * s->nslots))) return rc;
+  if ((rc = dalloc_t(s, &s->pw_coef, (size_t)6 * cols * s->nslots))) return rc;
+  s->pw_cap = cols;
+  return BL_OK;
+}
+
 template <typename T>
 const void* kc_inv(const bl_solver* s) { return PrecOf<T>::v ? (const void*)s->kc_inv32 : (const void*)s->kc_inv64; }
 template <typename T>
@@ -553,6 +565,7 @@ int project_groups(bl_solver* s, const std::vector<Group>& groups, View<double> 
   for (auto& g : groups) total += g.cols;
   int rc = ensure_level_buffers(s, pr, std::max(s->lv[0].ecap[pr], s->p), std::max(total, s->qmax));
   if (rc) return rc;
+  if ((rc = ensure_pw(s, total))) return rc;
   const Geo& g0 = s->lv[0].g;
   Launch L = make_launch(s, slots, 0);
   const int nc = s->lv[0].ncap[pr];
@@ -560,25 +573,37 @@ int project_groups(bl_solver* s, const std::vector<Group>& groups, View<double> 
   // which the level-0 V-cycle itself does not use (it works in nr and the coarser levels)
   TN* b0 = static_cast<TN*>(s->lv[0].nb[pr]);
   TN* phi = static_cast<TN*>(s->lv[0].nx[pr]);
+  const PWDefl pw{s->pw_tab, s->pw_d, s->pw_part, s->pw_coef, 2 * (int64_t)(g0.n + g0.m), total, 0, pw_blocks(g0)};
   int off = 0;
   for (auto& gr : groups) {
     Launch Lg = L;
     Lg.ncps = gr.cols;
-    if (gr.prec == 0) lhm<double, TN>(View<const double>{static_cast<const double*>(gr.ptr), gr.cps, gr.off}, view(b0, nc, off), g0, s->ph_d, Lg);
-    else lhm<float, TN>(View<const float>{static_cast<const float*>(gr.ptr), gr.cps, gr.off}, view(b0, nc, off), g0, s->ph_d, Lg);
+    PWDefl pg = pw;
+    pg.off = off;
+    if (gr.prec == 0) lhm<double, TN>(View<const double>{static_cast<const double*>(gr.ptr), gr.cps, gr.off}, view(b0, nc, off), g0, s->ph_d, Lg, &pg);
+    else lhm<float, TN>(View<const float>{static_cast<const float*>(gr.ptr), gr.cps, gr.off}, view(b0, nc, off), g0, s->ph_d, Lg, &pg);
     off += gr.cols;
     s->launches += 1;
   }
   Launch Lt = L;
   Lt.ncps = total;
+  // plane-wave deflation: b <- b - w (w^* b)/nm, the cycles on the complement, then the
+  // exact plane-wave coefficient added back through the lift
+  pw_reduce(pw, 0, apply_blocks(g0), Lt);   // k_lhm: one partial per point tile
+  pw_rhs<TN>(view(b0, nc), g0, pw, Lt);
   nodal_solve<TN>(s, cview(b0, nc), view(phi, nc), Lt, std::max(1, s->opts.nodal_cycles));
+  const int nd = pw_dot<TN>(cview(phi, nc), g0, pw, Lt);
+  pw_reduce(pw, 1, nd, Lt);
+  s->launches += 4;
   off = 0;
   for (auto& gr : groups) {
     Launch Lg = L;
     Lg.ncps = gr.cols;
+    PWDefl pg = pw;
+    pg.off = off;
     View<double> dst{out.p, out.cps, out.off + off};
-    if (gr.prec == 0) lift_sub<double, TN, double>(View<const double>{static_cast<const double*>(gr.ptr), gr.cps, gr.off}, cview(phi, nc, off), dst, g0, s->ph_d, Lg);
-    else lift_sub<float, TN, double>(View<const float>{static_cast<const float*>(gr.ptr), gr.cps, gr.off}, cview(phi, nc, off), dst, g0, s->ph_d, Lg);
+    if (gr.prec == 0) lift_sub<double, TN, double>(View<const double>{static_cast<const double*>(gr.ptr), gr.cps, gr.off}, cview(phi, nc, off), dst, g0, s->ph_d, Lg, &pg);
+    else lift_sub<float, TN, double>(View<const float>{static_cast<const float*>(gr.ptr), gr.cps, gr.off}, cview(phi, nc, off), dst, g0, s->ph_d, Lg, &pg);
     off += gr.cols;
     s->launches += 1;
   }
@@ -672,11 +697,40 @@ void setup_coarse(bl_solver* s, const std::vector<int>& slots) {
 int upload_slot_params(bl_solver* s) {
   char* h = static_cast<char*>(s->param_h);
   const size_t np = s->ph_h.size() * sizeof(Phase);
+  const size_t nz = s->zthr_h.size() * 8;
+  const size_t nw = s->pw_h.size() * sizeof(PlaneWave);
   std::memcpy(h, s->ph_h.data(), np);
-  std::memcpy(h + np, s->zthr_h.data(), s->zthr_h.size() * 8);
+  std::memcpy(h + np, s->zthr_h.data(), nz);
+  std::memcpy(h + np + nz, s->pw_h.data(), nw);
   HIP_OK(hipMemcpyAsync(s->ph_d, h, np, hipMemcpyHostToDevice, s->st));
-  HIP_OK(hipMemcpyAsync(s->zthr_d, h + np, s->zthr_h.size() * 8, hipMemcpyHostToDevice, s->st));
+  HIP_OK(hipMemcpyAsync(s->zthr_d, h + np, nz, hipMemcpyHostToDevice, s->st));
+  HIP_OK(hipMemcpyAsync(s->pw_d, h + np + nz, nw, hipMemcpyHostToDevice, s->st));
+  pw_tables(s->pw_d, s->pw_tab, 2 * (int64_t)(s->grid.n + s->grid.m), s->grid.n, s->grid.m, s->nslots, s->st);
+  s->launches += 1;
   return BL_OK;
+}
+
+// Plane-wave deflation parameters for k (PlaneWave): t = k' h with k' = k - 2 pi (p/a, r/b),
+// p, r the nearest integers (ties to even), and lambda_w of P in the cancellation-free form
+// 4 s1 (h2/h1)(1 - 2/3 s2) + 4 s2 (h1/h2)(1 - 2/3 s1), s_i = sin^2(t_i / 2).
+PlaneWave plane_wave_params(const Geo& g, double a, double b, double k1, double k2, bool gamma) {
+  PlaneWave q{};
+  q.inm = 1.0 / (double)g.nm;
+  if (gamma) return q;
+  const double tau = 2.0 * M_PI;
+  const double r1 = k1 - tau * std::nearbyint(k1 * a / tau) / a;
+  const double r2 = k2 - tau * std::nearbyint(k2 * b / tau) / b;
+  q.t1 = r1 * g.h1;
+  q.t2 = r2 * g.h2;
+  const double h1s = std::sin(0.5 * q.t1), h2s = std::sin(0.5 * q.t2);
+  const double s1 = h1s * h1s, s2 = h2s * h2s;
+  q.exr = -2.0 * s1;
+  q.exi = std::sin(q.t1);
+  q.eyr = -2.0 * s2;
+  q.eyi = std::sin(q.t2);
+  const double lw = 4.0 * s1 * g.mx * (1.0 - 2.0 / 3.0 * s2) + 4.0 * s2 * g.my * (1.0 - 2.0 / 3.0 * s1);
+  q.ilw = lw > 0 ? 1.0 / ((double)g.nm * lw) : 0.0;
+  return q;
 }
 
 // Phases of slot `sl` for (k1, k2); false for a non-finite parameter.
@@ -686,6 +740,7 @@ bool set_phase(bl_solver* s, int sl, double k1, double k2) {
   ss.gamma = is_gamma(k1, k2, s->grid.a, s->grid.b);
   if (ss.gamma) s->ph_h[sl] = {1.0, 0.0, 1.0, 0.0};
   else s->ph_h[sl] = {std::cos(k1 * s->grid.a), std::sin(k1 * s->grid.a), std::cos(k2 * s->grid.b), std::sin(k2 * s->grid.b)};
+  s->pw_h[sl] = plane_wave_params(s->lv[0].g, s->grid.a, s->grid.b, k1, k2, ss.gamma);
   return true;
 }
 
@@ -796,6 +851,7 @@ size_t engine_footprint(const bl_grid* grid, const bl_opts* o, int nslots) {
   per += (size_t)gc.ne * gc.ne * 16;                                         // probe results
   per += (size_t)rr_partial_blocks(g0) * q * q * 32 + (size_t)10 * q * q * 16;
   per += (size_t)p * ((g0.ne + 255) / 256) * 16;
+  per += (size_t)q * pw_blocks(g0) * 16 + (size_t)q * 48 + (size_t)(grid->n + grid->m) * 16 + sizeof(PlaneWave);
   fixed += (size_t)gc.ne * gc.ne * 16 + (size_t)gc.nm * gc.nm * 16;           // probes
   return fixed + per * (size_t)std::max(1, nslots);
 }
@@ -823,6 +879,7 @@ int engine_create(const bl_grid* grid, const bl_opts* opts, int nslots, hipStrea
   s->debug = std::getenv("BL_DEBUG") != nullptr;
   s->slot.resize(nslots);
   s->ph_h.assign(nslots, Phase{1.0, 0.0, 1.0, 0.0});
+  s->pw_h.assign(nslots, PlaneWave{});
   s->mu_h.assign(nslots, 1.0);
   s->zthr_h.assign(nslots, -INFINITY);
   auto fail = [&](int code) {
@@ -871,6 +928,10 @@ int engine_create(const bl_grid* grid, const bl_opts* opts, int nslots, hipStrea
   if ((rc = dalloc_t(s, &s->ph_d, S))) return fail(rc);
   if ((rc = dalloc_t(s, &s->mu_d, S))) return fail(rc);
   if ((rc = dalloc_t(s, &s->zthr_d, S))) return fail(rc);
+  for (auto& q : s->pw_h) q.inm = 1.0 / (double)g0.nm;
+  if ((rc = dalloc_t(s, &s->pw_d, S))) return fail(rc);
+  if ((rc = dalloc_t(s, &s->pw_tab, (size_t)2 * (gr.n + gr.m) * S))) return fail(rc);
+  if ((rc = ensure_pw(s, q))) return fail(rc);
   if ((rc = dalloc_t(s, &s->E, col * p * S))) return fail(rc);
   if ((rc = dalloc_t(s, &s->Sb, col * q * S))) return fail(rc);
   for (int h = 0; h < 3; ++h)
@@ -905,7 +966,7 @@ int engine_create(const bl_grid* grid, const bl_opts* opts, int nslots, hipStrea
   if ((rc = dalloc_t(s, &s->lists_d, (size_t)kMaxLists * S))) return fail(rc);
   if (hipHostMalloc((void**)&s->lists_h, (size_t)kMaxLists * S * sizeof(int), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&s->norms_h, s->readback_bytes, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc(&s->param_h, (size_t)S * (sizeof(Phase) + 8), hipHostMallocDefault) != hipSuccess)
+      hipHostMalloc(&s->param_h, (size_t)S * (sizeof(Phase) + 8 + sizeof(PlaneWave)), hipHostMallocDefault) != hipSuccess)
     return fail(set_error(BL_ENOMEM, "pinned host allocation failed%s"));
   s->lam_h = s->norms_h + (size_t)2 * p * S;
   s->count_h = reinterpret_cast<int*>(s->norms_h + (size_t)3 * p * S);
@@ -1269,6 +1330,27 @@ int apply_t(bl_solver* s, int op, int level, int ncols, const void* xv, const vo
       if (level != nl - 1) return set_error(BL_EINVAL, "coarse solve only on the coarsest level%s");
       dense_apply<T>(pc_inv<T>(s), s->ncn, x, out, La);
       break;
+    case BL_OP_EIGRES:
+      if (!yv) return set_error(BL_EINVAL, "eigenvalues (y) missing%s");
+      if ((size_t)ncols * 2 * apply_blocks(L.g) > (size_t)s->p * s->nslots * apply_blocks(s->lv[0].g) * 2)
+        return set_error(BL_EINVAL, "too many columns%s");
+      edge_apply<T, T>(EM_EIGRES, x, none, out, L.kappa64, L.kappa32, static_cast<const double*>(yv), ncols, L.g,
+                       s->ph_d, s->mu_d, La, s->partial, nullptr);
+      break;
+    case BL_OP_EDGE_SWEEP:
+    case BL_OP_EDGE_SWEEP_BACK:
+    case BL_OP_NODAL_SWEEP:
+    case BL_OP_NODAL_SWEEP_BACK: {
+      if (!smoothed || !yv) return set_error(BL_EINVAL, "no smoother on this level / rhs missing%s");
+      if (xv == outv) return set_error(BL_EINVAL, "a sweep reads x and writes out: different blocks required%s");
+      const bool back = op == BL_OP_EDGE_SWEEP_BACK || op == BL_OP_NODAL_SWEEP_BACK;
+      if (op == BL_OP_EDGE_SWEEP || op == BL_OP_EDGE_SWEEP_BACK)
+        edge_sweep<T>(x, out, y, L.kappa64, L.kappa32, L.sinv64, L.sinv32, L.g, s->ph_d, s->mu_d, L.T4, back, false,
+                      s->tune_sweep[0], La);
+      else
+        nodal_sweep<T>(x, out, y, L.g, s->ph_d, s->ns, back, false, s->tune_sweep[1], La);
+      break;
+    }
     default: return set_error(BL_EINVAL, "unknown operator%s");
   }
   return BL_OK;

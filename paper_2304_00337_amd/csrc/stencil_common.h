@@ -82,6 +82,33 @@ __device__ __forceinline__ T* colp(View<T> v, SJ s, int64_t N) {
   return v.p + ((int64_t)s.slot * v.cps + v.off + s.j) * 2 * N;
 }
 
+// Plane wave w_j = exp(i t1 j1) exp(i t2 j2) of a slot from its factor tables.
+__device__ __forceinline__ Cx<double> pw_value(const PWDefl& d, int slot, int n, int j1, int j2) {
+  const double* t = d.tab + (int64_t)slot * d.tabstride;
+  const double ar = t[2 * j1], ai = t[2 * j1 + 1];
+  const double br = t[2 * (n + j2)], bi = t[2 * (n + j2) + 1];
+  return {ar * br - ai * bi, ar * bi + ai * br};
+}
+
+// Sum of (a, b) over the workgroup (waves of 64, at most 1024 threads) in a fixed order;
+// thread 0 stores it at out[0..1].
+__device__ __forceinline__ void block_sum2(double a, double b, double* out) {
+  __shared__ double sh[2][16];
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_down(a, o, 64);
+    b += __shfl_down(b, o, 64);
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) { sh[0][wv] = a; sh[1][wv] = b; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double ta = 0, tb = 0;
+    for (int w = 0; w < (int)((blockDim.x + 63) >> 6); ++w) { ta += sh[0][w]; tb += sh[1][w]; }
+    out[0] = ta;
+    out[1] = tb;
+  }
+}
+
 // Block order that gives each of the 8 XCDs (which receive the blocks round-robin) one
 // contiguous range of logical blocks, so that the rows shared by neighbouring blocks stay in
 // one L2.  A bijection of [0, nb).

@@ -550,46 +550,61 @@ __device__ __forceinline__ Cx<T> lhm_at(const XA& X, T mx, T my) {
   return mx_at(-1) - mx_at(0) + my_at(-1) - my_at(0);
 }
 
-template <typename TI, typename TO>
+template <typename TI, typename TO, bool PW>
 __global__ __launch_bounds__(256) void k_lhm(View<const TI> uv, View<TO> ov, Geo g,
                                              const Phase* __restrict__ phs,
-                                             const int* __restrict__ slots, int ncps) {
+                                             const int* __restrict__ slots, int ncps, PWDefl pw) {
   using T = double;
   const SJ sj = slot_col(slots, ncps);
   const int n = g.n, m = g.m;
   const PointTile pt = point_tile(n, m);
-  if (pt.p1 >= n || pt.p2 >= m) return;
-  const int64_t N = g.ne, nm = g.nm, d = (int64_t)pt.p2 * n + pt.p1;
-  const TI* c = colp(uv, sj, N);
-  Cx<T> v;
-  if (pt.inner) {
-    v = lhm_at<T>(DirectEdges<T, TI>{c, N, nm, d, n}, (T)g.mx, (T)g.my);
-  } else {
-    const Ph<T> p = cast_phase<T>(phs[sj.slot]);
-    v = lhm_at<T>(ColumnEdges<T, const TI>{c, N, nm, n, m, pt.p1, pt.p2, p}, (T)g.mx, (T)g.my);
+  const bool live = pt.p1 < n && pt.p2 < m;
+  if (!PW && !live) return;
+  double sr = 0.0, si = 0.0;
+  if (live) {
+    const int64_t N = g.ne, nm = g.nm, d = (int64_t)pt.p2 * n + pt.p1;
+    const TI* c = colp(uv, sj, N);
+    Cx<T> v;
+    if (pt.inner) {
+      v = lhm_at<T>(DirectEdges<T, TI>{c, N, nm, d, n}, (T)g.mx, (T)g.my);
+    } else {
+      const Ph<T> p = cast_phase<T>(phs[sj.slot]);
+      v = lhm_at<T>(ColumnEdges<T, const TI>{c, N, nm, n, m, pt.p1, pt.p2, p}, (T)g.mx, (T)g.my);
+    }
+    TO* o = colp(ov, sj, nm);
+    o[d] = (TO)v.re;
+    o[nm + d] = (TO)v.im;
+    if (PW) {   // conj(w_j) v_j in FP64, before the rounding to TO
+      const Cx<double> w = pw_value(pw, sj.slot, n, pt.p1, pt.p2);
+      sr = w.re * v.re + w.im * v.im;
+      si = w.re * v.im - w.im * v.re;
+    }
   }
-  TO* o = colp(ov, sj, nm);
-  o[d] = (TO)v.re;
-  o[nm + d] = (TO)v.im;
+  if (PW) {
+    const int64_t col = (int64_t)(blockIdx.y / ncps) * pw.pcols + pw.off + sj.j;
+    block_sum2(sr, si, pw.part + (col * pw.nblk + blockIdx.x) * 2);
+  }
 }
 
 template <typename TI, typename TO>
-void lhm(View<const TI> u, View<TO> out, const Geo& g, const Phase* ph, const Launch& L) {
+void lhm(View<const TI> u, View<TO> out, const Geo& g, const Phase* ph, const Launch& L, const PWDefl* pw) {
   dim3 grid((unsigned)point_tiles(g.n, g.m), (unsigned)(L.nact * L.ncps));
   if (grid.y == 0) return;
-  k_lhm<TI, TO><<<grid, kPtW * kPtH, 0, L.st>>>(u, out, g, ph, L.slots, L.ncps);
+  if (pw) k_lhm<TI, TO, true><<<grid, kPtW * kPtH, 0, L.st>>>(u, out, g, ph, L.slots, L.ncps, *pw);
+  else k_lhm<TI, TO, false><<<grid, kPtW * kPtH, 0, L.st>>>(u, out, g, ph, L.slots, L.ncps, PWDefl{});
 }
-template void lhm<double, double>(View<const double>, View<double>, const Geo&, const Phase*, const Launch&);
-template void lhm<double, float>(View<const double>, View<float>, const Geo&, const Phase*, const Launch&);
-template void lhm<float, float>(View<const float>, View<float>, const Geo&, const Phase*, const Launch&);
-template void lhm<float, double>(View<const float>, View<double>, const Geo&, const Phase*, const Launch&);
+template void lhm<double, double>(View<const double>, View<double>, const Geo&, const Phase*, const Launch&, const PWDefl*);
+template void lhm<double, float>(View<const double>, View<float>, const Geo&, const Phase*, const Launch&, const PWDefl*);
+template void lhm<float, float>(View<const float>, View<float>, const Geo&, const Phase*, const Launch&, const PWDefl*);
+template void lhm<float, double>(View<const float>, View<double>, const Geo&, const Phase*, const Launch&, const PWDefl*);
 
 // out (edge) = u - L phi, (L phi)_x(j1,j2) = phi(j1+1,j2) - phi(j1,j2),
-// (L phi)_y(j1,j2) = phi(j1,j2+1) - phi(j1,j2) (extended reads).  FP64 arithmetic.
-template <typename TI, typename TP, typename TO, bool SUB>
+// (L phi)_y(j1,j2) = phi(j1,j2+1) - phi(j1,j2) (extended reads).  FP64 arithmetic.  PW: the
+// plane-wave part of the nodal solution is added as gamma L w, (L w)_x = w_j ex, (L w)_y = w_j ey.
+template <typename TI, typename TP, typename TO, bool SUB, bool PW>
 __global__ __launch_bounds__(256) void k_lift(View<const TI> uv, View<const TP> fv, View<TO> ov, Geo g,
                                               const Phase* __restrict__ phs,
-                                              const int* __restrict__ slots, int ncps) {
+                                              const int* __restrict__ slots, int ncps, PWDefl pw) {
   using T = double;
   const SJ sj = slot_col(slots, ncps);
   const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -599,13 +614,24 @@ __global__ __launch_bounds__(256) void k_lift(View<const TI> uv, View<const TP> 
   const int64_t N = g.ne, nm = g.nm;
   const TP* f = colp(fv, sj, nm);
   Cx<T> lp;
+  int j1, j2;
   if (d < nm) {
-    const int j1 = (int)(d % n), j2 = (int)(d / n);
+    j1 = (int)(d % n);
+    j2 = (int)(d / n);
     lp = fetch<TP, T>(f, nm, n, m, 0, j1 + 1, j2, p) - fetch<TP, T>(f, nm, n, m, 0, j1, j2, p);
   } else {
     const int64_t e = d - nm;
-    const int j1 = (int)(e % n), j2 = (int)(e / n);
+    j1 = (int)(e % n);
+    j2 = (int)(e / n);
     lp = fetch<TP, T>(f, nm, n, m, 0, j1, j2 + 1, p) - fetch<TP, T>(f, nm, n, m, 0, j1, j2, p);
+  }
+  if (PW) {
+    const PlaneWave& q = pw.par[sj.slot];
+    const Cx<double> w = pw_value(pw, sj.slot, n, j1, j2);
+    const Cx<double> lw = d < nm ? cmul(w, q.exr, q.exi) : cmul(w, q.eyr, q.eyi);
+    const int64_t col = (int64_t)(blockIdx.y / ncps) * pw.pcols + pw.off + sj.j;
+    const double* gm = pw.coef + col * 6 + 4;
+    lp = lp + cmul(lw, gm[0], gm[1]);
   }
   Cx<T> v = lp;
   if (SUB) {
@@ -619,22 +645,23 @@ __global__ __launch_bounds__(256) void k_lift(View<const TI> uv, View<const TP> 
 
 template <typename TI, typename TP, typename TO>
 void lift_sub(View<const TI> u, View<const TP> phi, View<TO> out, const Geo& g, const Phase* ph,
-              const Launch& L) {
+              const Launch& L, const PWDefl* pw) {
   dim3 grid((unsigned)((g.ne + 255) / 256), (unsigned)(L.nact * L.ncps));
   if (grid.y == 0) return;
-  k_lift<TI, TP, TO, true><<<grid, 256, 0, L.st>>>(u, phi, out, g, ph, L.slots, L.ncps);
+  if (pw) k_lift<TI, TP, TO, true, true><<<grid, 256, 0, L.st>>>(u, phi, out, g, ph, L.slots, L.ncps, *pw);
+  else k_lift<TI, TP, TO, true, false><<<grid, 256, 0, L.st>>>(u, phi, out, g, ph, L.slots, L.ncps, PWDefl{});
 }
 template <typename TI, typename TO>
 void lift(View<const TI> phi, View<TO> out, const Geo& g, const Phase* ph, const Launch& L) {
   dim3 grid((unsigned)((g.ne + 255) / 256), (unsigned)(L.nact * L.ncps));
   if (grid.y == 0) return;
-  k_lift<TO, TI, TO, false><<<grid, 256, 0, L.st>>>(View<const TO>{nullptr, 0, 0}, phi, out, g, ph, L.slots, L.ncps);
+  k_lift<TO, TI, TO, false, false><<<grid, 256, 0, L.st>>>(View<const TO>{nullptr, 0, 0}, phi, out, g, ph, L.slots, L.ncps, PWDefl{});
 }
-template void lift_sub<double, double, double>(View<const double>, View<const double>, View<double>, const Geo&, const Phase*, const Launch&);
-template void lift_sub<double, float, double>(View<const double>, View<const float>, View<double>, const Geo&, const Phase*, const Launch&);
-template void lift_sub<float, float, double>(View<const float>, View<const float>, View<double>, const Geo&, const Phase*, const Launch&);
-template void lift_sub<float, double, double>(View<const float>, View<const double>, View<double>, const Geo&, const Phase*, const Launch&);
-template void lift_sub<float, float, float>(View<const float>, View<const float>, View<float>, const Geo&, const Phase*, const Launch&);
+template void lift_sub<double, double, double>(View<const double>, View<const double>, View<double>, const Geo&, const Phase*, const Launch&, const PWDefl*);
+template void lift_sub<double, float, double>(View<const double>, View<const float>, View<double>, const Geo&, const Phase*, const Launch&, const PWDefl*);
+template void lift_sub<float, float, double>(View<const float>, View<const float>, View<double>, const Geo&, const Phase*, const Launch&, const PWDefl*);
+template void lift_sub<float, double, double>(View<const float>, View<const double>, View<double>, const Geo&, const Phase*, const Launch&, const PWDefl*);
+template void lift_sub<float, float, float>(View<const float>, View<const float>, View<float>, const Geo&, const Phase*, const Launch&, const PWDefl*);
 template void lift<double, double>(View<const double>, View<double>, const Geo&, const Phase*, const Launch&);
 template void lift<float, float>(View<const float>, View<float>, const Geo&, const Phase*, const Launch&);
 

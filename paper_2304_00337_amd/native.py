@@ -23,7 +23,8 @@ BL_OK, BL_EINVAL, BL_ENOMEM, BL_EHIP, BL_ENOCONV, BL_EAGAIN, BL_ESTATE = 0, -1, 
 OPS = {"A": 0, "M": 1, "K": 2, "LIFT": 3, "LHM": 4, "P": 5, "EDGE_SMOOTH": 6,
        "EDGE_SMOOTH_BACK": 7, "NODAL_SMOOTH": 8, "EDGE_VCYCLE": 9, "NODAL_VCYCLE": 10,
        "EDGE_PROLONG": 11, "EDGE_RESTRICT": 12, "NODAL_PROLONG": 13, "NODAL_RESTRICT": 14,
-       "PROJECT": 15, "COARSE_EDGE": 16, "COARSE_NODAL": 17}
+       "PROJECT": 15, "COARSE_EDGE": 16, "COARSE_NODAL": 17, "EIGRES": 18,
+       "EDGE_SWEEP": 19, "EDGE_SWEEP_BACK": 20, "NODAL_SWEEP": 21, "NODAL_SWEEP_BACK": 22}
 
 
 class BlGrid(ctypes.Structure):
