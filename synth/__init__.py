@@ -177,11 +177,13 @@ def config_c2(per_segment: int = 10) -> Problem:
 
 def config_c3(per_segment: int = 20) -> Problem:
     """1024 x 1024 grid, smoothed random two-phase field {1, 11.4}, 32 eigenpairs
-    (+16 throw-away) at 61 points along Gamma-X-M-Gamma."""
+    (+16 throw-away) at 61 points along Gamma-X-M-Gamma.  Relative residual tolerance 1e-6:
+    next to Gamma the FP64 residual of the acoustic band bottoms out near
+    u ||A|| / lambda_1 ~ 2e-7 at this mesh width, so 1e-8 cannot be reached by any FP64 run."""
     n = 1024
     eps = eps_random_field(n, n, 1.0, 1.0, seed=2, sigma=0.05, lo=1.0, hi=11.4)
     return Problem(n, n, 1.0, 1.0, eps, path_gxmg(per_segment), 32, 16, 2,
-                   tol=1e-8, levels=0, name="c3-randfield")
+                   tol=1e-6, levels=0, name="c3-randfield")
 
 
 def config_c4_problems(count: int = 64, master_seed: int = 3) -> list:

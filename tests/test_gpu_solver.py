@@ -136,10 +136,13 @@ def test_throwaway_rates_match_oracle():
     radius 1/3, the same start block and options on both sides.  Per t the residual records
     agree while the wanted pairs are above 1e-2, the observed rates of the last two wanted
     pairs over the window 1e-2 .. 1e-6 and the iteration counts agree with the oracle's, and
-    both rates fall as t grows.  The two records agree to 1e-12 in the first iterations; with
-    t = 1 their difference then grows about threefold per iteration (with t = 4 and 8 it stays
-    below 1e-7 to the end), so past ~20 iterations the t = 1 records differ by up to ~20%:
-    hence the bounds of 12% on the rates and 25% on the iteration counts."""
+    both rates fall as t grows.  With t = 4 and 8 the rates are well determined (the oracle's
+    own rates move by < 0.5% when its start block is perturbed at the rounding level,
+    tests/test_oracle_throwaway.py), so the GPU's must agree to 3%.  With t = 1 (p = nev + 1)
+    they are not: the same perturbations move the oracle's rates over 0.67 .. 0.72 and its
+    iteration count over 63 .. 70, and the GPU's Gram-based orthonormalisation perturbs every
+    iteration at that level; the t = 1 rates are held to that envelope widened by 10%
+    (0.60 .. 0.80) and its iterations to 25%."""
     from oracle.throwaway import observed_rate, study
     from paper_2304_00337_amd import Solver
     n, nev, ts, mu = 32, 8, (1, 4, 8), 0.5
@@ -159,8 +162,8 @@ def test_throwaway_rates_match_oracle():
         assert out["converged"] and r["converged"]
         assert hist.shape[0] == out["iterations"] + 1
         assert np.max(np.abs(out["evals"] - r["lam"]) / r["lam"]) < 1e-9
-        assert abs(out["iterations"] - r["iterations"]) <= max(3, int(0.25 * r["iterations"])), (
-            r["t"], out["iterations"], r["iterations"])
+        it_tol = max(3, int(0.25 * r["iterations"])) if r["t"] == 1 else max(3, int(0.15 * r["iterations"]))
+        assert abs(out["iterations"] - r["iterations"]) <= it_tol, (r["t"], out["iterations"], r["iterations"])
         h = r["history"]
         rows = min(len(h), len(hist))
         early = np.all(h[:rows, nev - 2:] >= 1e-2, axis=1)
@@ -169,7 +172,10 @@ def test_throwaway_rates_match_oracle():
         assert np.max(dev) < 2e-2, (r["t"], np.max(dev))
         rates = {i: observed_rate(hist[:, i - 1], 1e-2, 1e-6) for i in (nev - 1, nev)}
         for i, v in rates.items():
-            assert abs(v - r["rates"][i]) < 0.12 * r["rates"][i], (r["t"], i, v, r["rates"][i])
+            if r["t"] == 1:
+                assert 0.60 <= v <= 0.80, (r["t"], i, v, r["rates"][i])
+            else:
+                assert abs(v - r["rates"][i]) < 0.03 * r["rates"][i], (r["t"], i, v, r["rates"][i])
         gpu.append(rates)
     for i in (nev - 1, nev):
         assert gpu[2][i] < gpu[1][i] < gpu[0][i]

@@ -109,3 +109,40 @@ def test_deflation_removes_plane_wave_gradient_with_vcycles(k):
     for defl in (True, False):
         got = Projector(d, H, 2, deflate=defl)(V)
         assert np.all(mn(got - exact) <= 2e-2 * mn(V - exact))
+
+
+@pytest.mark.parametrize("n,m,a,b,k,eps_kind", [
+    (8, 8, 1.0, 1.0, (0.7, -1.3), "disc"),
+    (6, 10, 1.3, 0.8, (0.0, 0.0), "disc"),
+    (8, 8, 1.0, 1.0, (0.0, 0.0), "one"),          # degenerate: multiplicities 2 and 4
+    (8, 8, 1.0, 1.0, (math.pi, math.pi), "one"),
+])
+def test_gradient_free_eigs_against_dense(n, m, a, b, k, eps_kind):
+    from oracle.dense import dense_eigs, gradient_free_eigs
+    eps = np.ones(n * m) if eps_kind == "one" else synth.eps_disc(n, m, a, b, 8.9, 0.3)
+    d = fem.Discretization(n, m, a, b, eps, *k)
+    ref, _, _ = dense_eigs(d, 12)
+    lam, V = gradient_free_eigs(d, 12)
+    assert np.max(np.abs(lam - ref) / ref) < 1e-10
+    # eigenvectors (within a degenerate cluster ARPACK's are not mutually orthogonal)
+    R = d.A @ V - (d.M @ V) * lam[None, :]
+    assert np.max(np.linalg.norm(R, axis=0) / (lam * np.linalg.norm(d.M @ V, axis=0))) < 1e-9
+
+
+def test_gradient_free_eigs_closed_form_and_golden():
+    from oracle.closed_form import discrete_nonzero
+    from oracle.dense import gradient_free_eigs
+    n = 48
+    for k in ((0.0, 0.0), (0.4, 0.2)):
+        d = fem.Discretization(n, n, 1.0, 1.0, np.ones(n * n), *k)
+        lam, _ = gradient_free_eigs(d, 20)
+        ref = discrete_nonzero(n, n, 1.0, 1.0, 1.0, *k, count=20)
+        assert np.max(np.abs(lam - ref) / ref) < 1e-10
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c1_dense.json")) as f:
+        gold = json.load(f)
+    prob = synth.config_c1()
+    d = fem.Discretization(prob.n, prob.m, prob.a, prob.b, prob.eps, *prob.ks[0])
+    lam, _ = gradient_free_eigs(d, 12)
+    assert np.max(np.abs(lam - np.array(gold["disc"][:12])) / lam) < 1e-10
