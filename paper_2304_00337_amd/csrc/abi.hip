@@ -19,6 +19,16 @@ namespace {
     if (e_ != hipSuccess) return set_error(BL_EHIP, "HIP error: %s", hipGetErrorString(e_)); \
   } while (0)
 
+// Device buffer of one call, freed when the call returns (every path, errors included).
+struct DeviceScratch {
+  void* p = nullptr;
+  bool alloc(size_t bytes) { return hipMalloc(&p, bytes) == hipSuccess; }
+  double* d() const { return static_cast<double*>(p); }
+  ~DeviceScratch() {
+    if (p) (void)hipFree(p);
+  }
+};
+
 int check_hip() {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return set_error(BL_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
@@ -386,6 +396,7 @@ int bl_reset_history(bl_solver* s) {
 
 int bl_last_residual_history(const bl_solver* s, double* relres, int32_t cap) {
   if (!s || !relres) return set_error(BL_EINVAL, "NULL argument%s");
+  if (cap < 0) return set_error(BL_EINVAL, "cap must be >= 0%s");
   const int nev = s->opts.nev;
   const int rows = std::min(cap, s->last_res_rows);
   std::memcpy(relres, s->last_res_hist.data(), (size_t)rows * nev * 8);
@@ -420,17 +431,14 @@ int bl_apply(bl_solver* s, int32_t op, int32_t level, int32_t prec, int32_t ncol
 int bl_gram(bl_solver* s, const void* X, int32_t q, const void* W, int32_t r, int64_t len,
             double* out) {
   if (!s || !X || !W || !out || q < 1 || r < 1 || len < 1) return set_error(BL_EINVAL, "invalid gram arguments%s");
-  double *part = nullptr, *res = nullptr;
+  DeviceScratch part, res;
   const int64_t cap = (int64_t)gram_blocks(len) * q * r * 2;
-  HIP_OK(hipMalloc(&part, cap * 8));
-  HIP_OK(hipMalloc(&res, (size_t)q * r * 2 * 8));
+  if (!part.alloc(cap * 8) || !res.alloc((size_t)q * r * 2 * 8)) return set_error(BL_ENOMEM, "device allocation failed%s");
   const Launch L{nullptr, 1, 0, s->st};
   gram(View<const double>{static_cast<const double*>(X), q, 0}, q, View<const double>{static_cast<const double*>(W), r, 0}, r,
-       len, part, cap, res, L);
-  hipError_t e = hipMemcpyAsync(out, res, (size_t)q * r * 2 * 8, hipMemcpyDeviceToHost, s->st);
+       len, part.d(), cap, res.d(), L);
+  hipError_t e = hipMemcpyAsync(out, res.p, (size_t)q * r * 2 * 8, hipMemcpyDeviceToHost, s->st);
   if (e == hipSuccess) e = hipStreamSynchronize(s->st);
-  (void)hipFree(part);
-  (void)hipFree(res);
   if (e != hipSuccess) return set_error(BL_EHIP, "HIP error: %s", hipGetErrorString(e));
   return check_hip();
 }
@@ -444,33 +452,21 @@ int bl_ritz_small(bl_solver* s, const double* G, const double* H, int32_t q, int
                   double zero_thr, double* theta, double* Y) {
   if (!s || !G || !H || !theta || !Y || q < 1 || q > 255 || want < 1 || want > q)
     return set_error(BL_EINVAL, "invalid ritz arguments%s");
-  double *dG, *dH, *dW, *dY, *dT, *dZ;
-  int* dc;
   const size_t m2 = (size_t)q * q * 2 * 8;
-  HIP_OK(hipMalloc(&dG, m2));
-  HIP_OK(hipMalloc(&dH, m2));
-  HIP_OK(hipMalloc(&dW, ritz_small_work_doubles(q) * 8));
-  HIP_OK(hipMalloc(&dY, (size_t)q * want * 2 * 8));
-  HIP_OK(hipMalloc(&dT, (size_t)want * 8));
-  HIP_OK(hipMalloc(&dZ, 8));
-  HIP_OK(hipMalloc(&dc, sizeof(int)));
-  HIP_OK(hipMemcpyAsync(dG, G, m2, hipMemcpyHostToDevice, s->st));
-  HIP_OK(hipMemcpyAsync(dH, H, m2, hipMemcpyHostToDevice, s->st));
-  HIP_OK(hipMemcpyAsync(dZ, &zero_thr, 8, hipMemcpyHostToDevice, s->st));
+  DeviceScratch dG, dH, dW, dY, dT, dZ, dc;
+  if (!dG.alloc(m2) || !dH.alloc(m2) || !dW.alloc(ritz_small_work_doubles(q) * 8) ||
+      !dY.alloc((size_t)q * want * 2 * 8) || !dT.alloc((size_t)want * 8) || !dZ.alloc(8) || !dc.alloc(sizeof(int)))
+    return set_error(BL_ENOMEM, "device allocation failed%s");
+  HIP_OK(hipMemcpyAsync(dG.p, G, m2, hipMemcpyHostToDevice, s->st));
+  HIP_OK(hipMemcpyAsync(dH.p, H, m2, hipMemcpyHostToDevice, s->st));
+  HIP_OK(hipMemcpyAsync(dZ.p, &zero_thr, 8, hipMemcpyHostToDevice, s->st));
   const Launch L{nullptr, 1, 0, s->st};
-  ritz_small(dG, dH, q, 0, want, dZ, 1e-10, dW, 0, dY, dT, dc, L);
+  ritz_small(dG.d(), dH.d(), q, 0, want, dZ.d(), 1e-10, dW.d(), 0, dY.d(), dT.d(), static_cast<int*>(dc.p), L);
   int cnt = 0;
-  hipError_t e = hipMemcpyAsync(Y, dY, (size_t)q * want * 2 * 8, hipMemcpyDeviceToHost, s->st);
-  if (e == hipSuccess) e = hipMemcpyAsync(theta, dT, (size_t)want * 8, hipMemcpyDeviceToHost, s->st);
-  if (e == hipSuccess) e = hipMemcpyAsync(&cnt, dc, sizeof(int), hipMemcpyDeviceToHost, s->st);
+  hipError_t e = hipMemcpyAsync(Y, dY.p, (size_t)q * want * 2 * 8, hipMemcpyDeviceToHost, s->st);
+  if (e == hipSuccess) e = hipMemcpyAsync(theta, dT.p, (size_t)want * 8, hipMemcpyDeviceToHost, s->st);
+  if (e == hipSuccess) e = hipMemcpyAsync(&cnt, dc.p, sizeof(int), hipMemcpyDeviceToHost, s->st);
   if (e == hipSuccess) e = hipStreamSynchronize(s->st);
-  (void)hipFree(dG);
-  (void)hipFree(dH);
-  (void)hipFree(dW);
-  (void)hipFree(dY);
-  (void)hipFree(dT);
-  (void)hipFree(dZ);
-  (void)hipFree(dc);
   if (e != hipSuccess) return set_error(BL_EHIP, "HIP error: %s", hipGetErrorString(e));
   int rc = check_hip();
   return rc ? rc : cnt;
