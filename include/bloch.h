@@ -285,6 +285,20 @@ int bl_gram(bl_solver* s, const void* X, int32_t q, const void* W, int32_t r, in
             double* out);
 int bl_ritz_small(bl_solver* s, const double* G, const double* H, int32_t q, int32_t want,
                   double zero_thr, double* theta, double* Y);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): bl_gram with no allocation.  out_dev
+ * (device, q x r, row-major complex interleaved re,im, caller-owned) = X^* W for the device
+ * planar FP64 blocks X (q columns) and W (r columns) of length len, queued on the handle's
+ * stream (valid once the stream has been synchronised; no host copy, no synchronisation).
+ * The row-block partial sums use a fixed per-GPU device array of 2^21 doubles (16 MiB,
+ * held until the process ends) instead of a per-call allocation: BL_EINVAL when
+ * row blocks (ceil(len / 1024), at most 256) x q x r x 2 exceeds it, or when the current
+ * device is not the handle's.  Every call on one GPU shares that array: calls that overlap
+ * on one GPU (other streams or handles) race.  Same kernels and summation order as bl_gram,
+ * so the results are bit-identical to it. */
+int bl_gram_noalloc(bl_solver* s, const void* X, int32_t q, const void* W, int32_t r, int64_t len,
+                    void* out_dev);
 /* bl_rr_products: the Ritz step's products G = S^* M S and H = S^* A S (host q x q each,
  *   row-major interleaved complex) for a device planar FP64 block S of q <= 3p columns of
  *   length N_e, with the handle's permittivity and the Bloch parameter of bl_set_k; they

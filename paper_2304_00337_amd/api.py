@@ -463,6 +463,15 @@ class Solver:
                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "bl_gram")
         return out[..., 0] + 1j * out[..., 1]
 
+    def gram_noalloc(self, X, W, out):
+        """bl_gram_noalloc: out (device FP64 tensor of q * r * 2 values) = X^* W, queued on the
+        handle's stream with no allocation; returns out."""
+        q, r = X.shape[0], W.shape[0]
+        if out.numel() < q * r * 2:
+            raise ValueError("out must hold q * r complex values")
+        check(self.lib.bl_gram_noalloc(self.h, _ptr(X), q, _ptr(W), r, X.shape[2], _ptr(out)), "bl_gram_noalloc")
+        return out
+
     def rr_products(self, S):
         """(S^* M S, S^* A S) for a planar FP64 device block S (q, 2, N_e) (bl_rr_products)."""
         q = S.shape[0]

@@ -14,7 +14,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 SOURCES = ["csrc/stencils.hip", "csrc/dense.hip", "csrc/ritz.hip", "csrc/solver.hip",
            "csrc/abi.hip", "csrc/sched.hip", "csrc/rr.hip", "csrc/tune.hip", "csrc/coarse.hip",
-           "csrc/sweep.hip", "csrc/planewave.hip"]
+           "csrc/sweep.hip", "csrc/planewave.hip",
+           "csrc/noalloc.hip"]
 LIB = os.path.join(PKG, "libbloch.so")
 
 

@@ -96,6 +96,7 @@ EXPORTED = {
     "bl_apply": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p, c_void_p,
                            c_void_p]),
     "bl_gram": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_int32, c_int64, P(c_double)]),
+    "bl_gram_noalloc": (c_int32, [c_void_p, c_void_p, c_int32, c_void_p, c_int32, c_int64, c_void_p]),
     "bl_ritz_small": (c_int32, [c_void_p, P(c_double), P(c_double), c_int32, c_int32, c_double,
                                 P(c_double), P(c_double)]),
     "bl_rr_products": (c_int32, [c_void_p, c_void_p, c_int32, P(c_double), P(c_double)]),
