@@ -21,7 +21,7 @@ import numpy as np
 
 from .householder import m_householder, reference_columns
 
-__all__ = ["Projector", "ritz", "initial_block", "pinvit", "residuals"]
+__all__ = ["Projector", "ritz", "initial_block", "pinvit", "residuals", "gram_orthonormalize"]
 
 
 class Projector:
@@ -68,6 +68,18 @@ class Projector:
         return U
 
 
+def gram_orthonormalize(S, M):
+    """An M-orthonormal basis of range(S) through the Gram matrix (not the paper's
+    Householder route; for comparison with implementations that orthonormalise this way):
+    G = S^* M S scaled to unit diagonal by D, Cholesky D G D = L L^*, Q = S D L^{-*}.  Same
+    span as the Householder factorisation when S has full rank; the rounding differs, which
+    shows in the iteration counts of ill-conditioned cases (p = nev + 1)."""
+    G = S.conj().T @ (M @ S)
+    dsc = 1.0 / np.sqrt(np.real(np.diag(G)))
+    L = np.linalg.cholesky(G * np.outer(dsc, dsc))
+    return (S * dsc) @ np.linalg.inv(L).conj().T
+
+
 def ritz(Q, A, p: int, zero_thr: float = None):
     """Ritz step on the M-orthonormal basis Q: eigen-decomposition of Q^* A Q (ascending);
     returns the p smallest pairs, skipping Ritz values below zero_thr if given."""
@@ -94,16 +106,19 @@ def residuals(disc, E, lam, absolute: bool = False):
     return R, rel
 
 
-def initial_block(disc, proj, E0, p: int, zero_thr: float = None):
-    """Start block: eliminate the null space, M-orthonormalise by generalized Householder,
-    and rotate to Ritz vectors."""
+def initial_block(disc, proj, E0, p: int, zero_thr: float = None, ortho: str = "householder"):
+    """Start block: eliminate the null space, M-orthonormalise by generalized Householder
+    (or through the Gram matrix, ortho="gram"), and rotate to Ritz vectors."""
     S = proj(np.asarray(E0, dtype=np.complex128))
-    Q, _ = m_householder(S, disc.M, reference_columns(disc.n, disc.m, S.shape[1]))
+    if ortho == "gram":
+        Q = gram_orthonormalize(S, disc.M)
+    else:
+        Q, _ = m_householder(S, disc.M, reference_columns(disc.n, disc.m, S.shape[1]))
     return ritz(Q, disc.A, p, zero_thr)
 
 
 def pinvit(disc, hier, proj, E, lam, nev: int, tol: float, max_iter: int,
-           variant: str = "gradient", log=None, absolute: bool = False):
+           variant: str = "gradient", log=None, absolute: bool = False, ortho: str = "householder"):
     """Run the iteration from an M-orthonormal Ritz block (E, lam).
 
     The gradient variant minimises the Rayleigh quotient over span[E_hat, E].  The same
@@ -117,7 +132,8 @@ def pinvit(disc, hier, proj, E, lam, nev: int, tol: float, max_iter: int,
     E_prev - E (E^* M E_prev) removed of its E part.
 
     absolute=True stops on the defects ||A e_i - lambda_i M e_i||_2 instead of the relative
-    residuals.  Returns (lam, E, relres, iterations, converged)."""
+    residuals.  ortho="gram" orthonormalises through the Gram matrix instead of Householder
+    (gram_orthonormalize).  Returns (lam, E, relres, iterations, converged)."""
     p = E.shape[1]
     ref = reference_columns(disc.n, disc.m, 3 * p if variant == "lobpcg" else 2 * p)
     E_prev = None
@@ -136,7 +152,10 @@ def pinvit(disc, hier, proj, E, lam, nev: int, tol: float, max_iter: int,
             S = proj(np.hstack([E, C, D]))
         else:
             S = proj(np.hstack([E, C]))
-        Q, _ = m_householder(S, disc.M, ref[:S.shape[1]])
+        if ortho == "gram":
+            Q = gram_orthonormalize(S, disc.M)
+        else:
+            Q, _ = m_householder(S, disc.M, ref[:S.shape[1]])
         E_prev = E
         lam, E = ritz(Q, disc.A, p)
         it += 1

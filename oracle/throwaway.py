@@ -65,17 +65,18 @@ def inverse_iteration_rate(lam, i: int, p: int, mu: float = 0.0) -> float:
 
 
 def study(disc, hier, proj, E0, nev: int, ts, indices, tol: float, max_iter: int,
-          upper: float = 1e-2, lower: float = 0.0):
+          upper: float = 1e-2, lower: float = 0.0, ortho: str = "householder"):
     """For each t in ts: p = nev + t, the iteration started from the first p columns of E0
     (null-space projected, M-orthonormalised and Ritz-rotated), run to the relative
     residual tol for the first nev pairs; returns a list of dicts with t, p, iterations,
-    converged, and the observed rate of each eigenpair in `indices` (1-based, <= nev)."""
+    converged, and the observed rate of each eigenpair in `indices` (1-based, <= nev).
+    ortho selects the orthonormalisation of the iteration (pinvit)."""
     out = []
     for t in ts:
         p = nev + t
-        lam0, E = initial_block(disc, proj, E0[:, :p], p)
+        lam0, E = initial_block(disc, proj, E0[:, :p], p, ortho=ortho)
         log = []
-        lam, _, _, it, conv = pinvit(disc, hier, proj, E, lam0, nev, tol, max_iter, log=log)
+        lam, _, _, it, conv = pinvit(disc, hier, proj, E, lam0, nev, tol, max_iter, log=log, ortho=ortho)
         hist = np.array([rel[:nev] for (_, _, rel) in log])
         rates = {i: observed_rate(hist[:, i - 1], upper, lower) for i in indices}
         out.append({"t": int(t), "p": int(p), "iterations": int(it), "converged": bool(conv),

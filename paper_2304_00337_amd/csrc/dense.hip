@@ -6,6 +6,8 @@
 //  * block recombination S Y.
 #include "internal.h"
 
+#include <type_traits>
+
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -257,45 +259,102 @@ int gram(View<const double> X, int q, View<const double> W, int r, int64_t len, 
 // column block), so they run together and read the basis rows through L2 once from memory.
 namespace {
 
-constexpr int CB = 8;
+// Block combination out_s = S_s Y_s on the matrix cores (FP64 MFMA 16x16x4), computed as
+// out^T = Y^T S^T so that each lane's results are consecutive rows of one output column
+// (coalesced stores): the A operand is Y (staged in LDS, real and imaginary parts apart,
+// zero-padded to whole tiles), the B operand the basis rows straight from memory, four real
+// products per complex one.  Each wave owns BCR rows and the NTC output column tiles of its
+// workgroup (blockIdx.y selects the tile group when the block is wider); the next four basis
+// columns are loaded while the current ones are multiplied.
+typedef double bd4 __attribute__((ext_vector_type(4)));
+constexpr int BCW = 4;    // waves per workgroup
+constexpr int BCR = 32;   // rows per wave (two 16-row tiles)
 
-__global__ __launch_bounds__(256) void k_block_combine(View<const double> Sv, int q,
-                                                       const c2* __restrict__ Y, int want, int64_t len,
-                                                       View<double> ov, const int* __restrict__ slots) {
-  extern __shared__ c2 ys[];   // q x CB
+template <int NTC>
+__global__ __launch_bounds__(64 * BCW) void k_block_combine(View<const double> Sv, int q, const c2* __restrict__ Y,
+                                                            int want, int64_t len, View<double> ov,
+                                                            const int* __restrict__ slots) {
+  extern __shared__ double yl[];   // yr then yi, each q4 x 16 NTC
+  constexpr int WC = 16 * NTC;
+  const int q4 = (q + 3) & ~3;
+  const int cbase = (int)blockIdx.y * WC;   // first output column of the workgroup
   const int slot = slots ? slots[blockIdx.z] : (int)blockIdx.z;
   const double* S = Sv.p + ((int64_t)slot * Sv.cps + Sv.off) * 2 * len;
   double* out = ov.p + ((int64_t)slot * ov.cps + ov.off) * 2 * len;
   Y += (int64_t)slot * q * want;
-  const int ncb = (want + CB - 1) / CB;
-  const int j0 = (int)(blockIdx.x % ncb) * CB;
-  for (int e = threadIdx.x; e < q * CB; e += blockDim.x) {
-    const int l = e / CB, c = e % CB;
-    ys[e] = (j0 + c < want) ? Y[l * want + j0 + c] : c2{0, 0};
+  double* yr = yl;
+  double* yi = yl + (size_t)q4 * WC;
+  for (int e = threadIdx.x; e < q4 * WC; e += blockDim.x) {
+    const int l = e / WC, c = cbase + e % WC;
+    const c2 v = (l < q && c < want) ? Y[(int64_t)l * want + c] : c2{0, 0};
+    yr[e] = v.r;
+    yi[e] = v.i;
   }
   __syncthreads();
-  const int64_t i = (int64_t)(blockIdx.x / ncb) * blockDim.x + threadIdx.x;
-  if (i >= len) return;
-  double accr[CB], acci[CB];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t row0 = ((int64_t)blockIdx.x * BCW + wv) * BCR;
+  if (row0 >= len) return;
+  const int kk = lane >> 4, cc = lane & 15;
+  bd4 acr[2][NTC], aci[2][NTC];
 #pragma unroll
-  for (int c = 0; c < CB; ++c) { accr[c] = 0; acci[c] = 0; }
-#pragma unroll 4
-  for (int l = 0; l < q; ++l) {
-    const double sr = S[(int64_t)l * 2 * len + i], si = S[(int64_t)l * 2 * len + len + i];
+  for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-    for (int c = 0; c < CB; ++c) {
-      const c2 y = ys[l * CB + c];
-      accr[c] += sr * y.r - si * y.i;
-      acci[c] += sr * y.i + si * y.r;
+    for (int ct = 0; ct < NTC; ++ct) acr[rt][ct] = aci[rt][ct] = bd4{0, 0, 0, 0};
+  int64_t rows[2];
+  bool rok[2];
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt) {
+    rows[rt] = row0 + 16 * rt + cc;
+    rok[rt] = rows[rt] < len;
+  }
+  auto load = [&](int l0, double* sr, double* si) {
+    const int l = l0 + kk;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+      const bool ok = l < q && rok[rt];
+      const double* col = S + (int64_t)(ok ? l : 0) * 2 * len;
+      const int64_t r = ok ? rows[rt] : 0;
+      const double a = col[r], b = col[len + r];
+      sr[rt] = ok ? a : 0.0;
+      si[rt] = ok ? b : 0.0;
+    }
+  };
+  double sr[2], si[2], nr[2], ni[2];
+  load(0, sr, si);
+  for (int l0 = 0; l0 < q4; l0 += 4) {
+    if (l0 + 4 < q4) load(l0 + 4, nr, ni);
+    const int l = l0 + kk;
+#pragma unroll
+    for (int ct = 0; ct < NTC; ++ct) {
+      const double ar = yr[l * WC + 16 * ct + cc], ai = yi[l * WC + 16 * ct + cc];
+#pragma unroll
+      for (int rt = 0; rt < 2; ++rt) {
+        acr[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, sr[rt], acr[rt][ct], 0, 0, 0);
+        acr[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, si[rt], acr[rt][ct], 0, 0, 0);
+        aci[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, si[rt], aci[rt][ct], 0, 0, 0);
+        aci[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, sr[rt], aci[rt][ct], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+      sr[rt] = nr[rt];
+      si[rt] = ni[rt];
     }
   }
+  // accumulator entry v of lane (kk, cc) is output column 16 ct + 4 v + kk of row row0 + 16 rt + cc
+  // (the 16 x 16 result of the instruction has row 4 v + lane / 16 and column lane % 16)
 #pragma unroll
-  for (int c = 0; c < CB; ++c) {
-    if (j0 + c < want) {
-      out[(int64_t)(j0 + c) * 2 * len + i] = accr[c];
-      out[(int64_t)(j0 + c) * 2 * len + len + i] = acci[c];
-    }
-  }
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < NTC; ++ct)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int c = cbase + 16 * ct + 4 * v + kk;
+        if (c < want && rok[rt]) {
+          out[(int64_t)c * 2 * len + rows[rt]] = acr[rt][ct][v];
+          out[(int64_t)c * 2 * len + len + rows[rt]] = aci[rt][ct][v];
+        }
+      }
 }
 
 }  // namespace
@@ -303,10 +362,30 @@ __global__ __launch_bounds__(256) void k_block_combine(View<const double> Sv, in
 void block_combine(View<const double> S, int q, const double* Y, int want, int64_t len,
                    View<double> out, const Launch& L) {
   if (L.nact <= 0 || want <= 0) return;
-  const int ncb = (want + CB - 1) / CB;
-  dim3 grid((unsigned)(((len + 255) / 256) * ncb), 1, (unsigned)L.nact);
-  k_block_combine<<<grid, 256, (size_t)q * CB * sizeof(c2), L.st>>>(S, q, reinterpret_cast<const c2*>(Y), want, len,
-                                                                    out, L.slots);
+  const int q4 = (q + 3) & ~3;
+  const int64_t rows_per_wg = (int64_t)BCW * BCR;
+  const int ntc = (want + 15) / 16;
+  // column tiles per workgroup: up to three, as many as the staged Y allows in 160 KB of LDS
+  const size_t tile_lds = (size_t)2 * q4 * 16 * sizeof(double);
+  int per = 3;
+  while (per > 1 && tile_lds * per > (size_t)160 * 1024) --per;
+  if (per > ntc) per = ntc;
+  const dim3 grid((unsigned)((len + rows_per_wg - 1) / rows_per_wg), (unsigned)((ntc + per - 1) / per),
+                  (unsigned)L.nact);
+  auto go = [&](auto nt) {
+    constexpr int NTC = decltype(nt)::value;
+    static bool attr = false;
+    if (!attr) {
+      (void)hipFuncSetAttribute((const void*)k_block_combine<NTC>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                160 * 1024);
+      attr = true;
+    }
+    k_block_combine<NTC><<<grid, 64 * BCW, tile_lds * NTC, L.st>>>(S, q, reinterpret_cast<const c2*>(Y), want, len,
+                                                                  out, L.slots);
+  };
+  if (per == 1) go(std::integral_constant<int, 1>{});
+  else if (per == 2) go(std::integral_constant<int, 2>{});
+  else go(std::integral_constant<int, 3>{});
 }
 
 }  // namespace bl

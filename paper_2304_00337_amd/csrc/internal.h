@@ -197,8 +197,10 @@ void lift_sub(View<const TI> u, View<const TP> phi, View<TO> out, const Geo& g, 
               const Launch& L, const PWDefl* pw = nullptr);
 template <typename TI, typename TO>
 void lift(View<const TI> phi, View<TO> out, const Geo& g, const Phase* ph, const Launch& L);
-// k = 0 deflation of the constant edge fields on the launch's columns of u.
+// k = 0 deflation of the constant edge fields on the launch's columns of u; scratch holds
+// gamma_scratch_doubles(columns of the launch) doubles.
 void gamma_deflate(View<double> u, const Geo& g, double* scratch, const Launch& L);
+size_t gamma_scratch_doubles(int cols);
 template <typename T>
 void axpy(View<T> y, View<const T> x, int64_t len, const Launch& L);
 // out = a - b, or out = a when b.p is null (columns of length len)

@@ -12,9 +12,12 @@
 // per node range are reduced in a fixed order, so a slot's G and H do not depend on the
 // other slots of the launch.
 //
-// Bases of at most 48 columns (the iteration's [X, W] for p <= 24) take the matrix cores
-// instead: FP64 MFMA 16x16x4 products.  One workgroup of eight waves (four for G, four for
-// H) owns a slice of 16 nodes of a band of rows and streams the rows through an LDS ring:
+// Bases of at most 144 columns take the matrix cores instead: FP64 MFMA 16x16x4 products, the
+// columns cut into groups of 48 (three 16-column tiles): one launch for the diagonal blocks
+// (each group against itself, the upper tile pairs), one for the cross blocks (two groups
+// staged side by side, all nine tile pairs, mirrored into the lower triangle).  One
+// workgroup of eight waves (four for G, four for H) owns a slice of 16 nodes of a band of
+// rows and one block, and streams the rows through an LDS ring:
 // x-edge rows r-1, r, r+1 and the y-edge row r (with one halo node either side), stored as
 // fetch() returns them, with the next rows prefetched into registers while the current row
 // is computed (one barrier per row; every basis value is read from memory once per band).
@@ -24,6 +27,8 @@
 // registers and the waves' sums are combined in a fixed order before one partial per slice
 // and band is written.
 #include "stencil_common.h"
+
+#include <type_traits>
 
 // Contractions are explicit (fma in the accumulations, none elsewhere), so the 48- and
 // 64-wide tile variants round identically.
@@ -50,8 +55,13 @@ __global__ __launch_bounds__(256) void k_rr_gram(View<const double> Sv, int q,
   const double* S = Sv.p + ((int64_t)slot * Sv.cps + Sv.off) * 2 * N;
   const double* kap = kappa + (int64_t)slot * nm;
   const Ph<double> p = cast_phase<double>(phs[slot]);
+  // blockIdx.y enumerates the upper tile blocks (bi <= bj) row by row; entries below the
+  // diagonal are not summed but mirrored from the upper ones (Hermitian), so every kept entry
+  // (i <= j) is summed in the same order whatever the tile width
   const int ntj = (q + TB - 1) / TB;
-  const int ti0 = (blockIdx.y / ntj) * TB, tj0 = (blockIdx.y % ntj) * TB;
+  int bi = 0, rem = (int)blockIdx.y;
+  while (rem >= ntj - bi) { rem -= ntj - bi; ++bi; }
+  const int ti0 = bi * TB, tj0 = (bi + rem) * TB;
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
   const int64_t rs = (int64_t)blockIdx.x * rows_per_blk;
   const int64_t re = rs + rows_per_blk < nm ? rs + rows_per_blk : nm;
@@ -154,69 +164,72 @@ __global__ __launch_bounds__(256) void k_rr_gram(View<const double> Sv, int q,
 #pragma unroll
     for (int b = 0; b < RT; ++b) {
       const int i = ti0 + ty * RT + a, j = tj0 + tx * RT + b;
-      if (i < q && j < q) {
-        const int64_t e = 2 * ((int64_t)i * q + j);
+      if (i <= j && j < q) {
+        const int64_t e = 2 * ((int64_t)i * q + j), f = 2 * ((int64_t)j * q + i);
         pg[e] = gr[a][b];
         pg[e + 1] = gi[a][b];
         ph[e] = hr[a][b];
         ph[e + 1] = hi[a][b];
+        if (i != j) {
+          pg[f] = gr[a][b];
+          pg[f + 1] = -gi[a][b];
+          ph[f] = hr[a][b];
+          ph[f + 1] = -hi[a][b];
+        }
       }
     }
 }
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int MQ = 48;          // widest basis of the matrix-core path (3 tiles of 16 columns,
-                                // written out below as the pairs of three tiles)
-constexpr int MT = MQ / 16;     // column tiles
-constexpr int MP = MT * (MT + 1) / 2;   // tile pairs ti <= tj
+constexpr int MQ = 48;          // columns of one group of the matrix-core path (3 tiles of 16)
+constexpr int MT = MQ / 16;     // column tiles per group
 constexpr int MW = 4;           // waves per product (G or H) in a workgroup
 constexpr int SW = 4 * MW;      // nodes per row of a workgroup's slice (one group of 4 per wave)
-constexpr int CP = MQ + 4;      // LDS stride of a node's columns (complex; padded against bank conflicts)
 constexpr int XS = 4;           // x-edge row slots of the ring (rows r-1, r, r+1 in use, r+2 filling)
 constexpr int YW = SW + 2;      // y-edge row with one node either side
+constexpr int RR_THREADS = 128 * MW;
+constexpr int kMfmaGroups = 3;  // bases up to 3 groups (144 columns) take the matrix cores
+
+// A workgroup stages NG column groups: NG = 1 for a diagonal block of G and H (the upper tile
+// pairs of its three tiles), NG = 2 for the cross block of two groups (all nine tile pairs).
+template <int NG>
+struct RRConf {
+  static constexpr int NC = NG * MQ;           // staged columns
+  static constexpr int CP = NC + 4;            // LDS stride of a node's columns (complex; padded)
+  static constexpr int NT = NG * MT;           // staged tiles
+  static constexpr int MP = NG == 1 ? MT * (MT + 1) / 2 : MT * MT;   // tile pairs
+  static constexpr int ITEMS = SW * NC + YW * NC + SW;
+  static constexpr int PER_THREAD = (ITEMS + RR_THREADS - 1) / RR_THREADS;
+};
+// tile pair k -> staged tiles (ti, tj): NG = 1 the upper pairs of tiles 0..2, NG = 2 tiles
+// 0..2 (first group) against 3..5 (second group)
+template <int NG>
+__host__ __device__ constexpr int pair_ti(int k) { return NG == 1 ? (k < 3 ? 0 : (k < 5 ? 1 : 2)) : k / 3; }
+template <int NG>
+__host__ __device__ constexpr int pair_tj(int k) { return NG == 1 ? (k < 3 ? k : (k < 5 ? k - 2 : 2)) : 3 + k % 3; }
 
 #define BL_MFMA(a, b, c) __builtin_amdgcn_mfma_f64_16x16x4f64((a), (b), (c), 0, 0, 0)
 
-// G and H updates of tile pair (A, B), accumulator k
-#define BL_GPAIR(k, A, B)                                  \
-  ar[k] = BL_MFMA(A.ur[0], B.vr[0], ar[k]);                \
-  ar[k] = BL_MFMA(A.ui[0], B.vi[0], ar[k]);                \
-  ar[k] = BL_MFMA(A.ur[1], B.vr[1], ar[k]);                \
-  ar[k] = BL_MFMA(A.ui[1], B.vi[1], ar[k]);                \
-  ai[k] = BL_MFMA(A.ur[0], B.vi[0], ai[k]);                \
-  ai[k] = BL_MFMA(-A.ui[0], B.vr[0], ai[k]);               \
-  ai[k] = BL_MFMA(A.ur[1], B.vi[1], ai[k]);                \
-  ai[k] = BL_MFMA(-A.ui[1], B.vr[1], ai[k]);
-#define BL_HPAIR(k, A, B)                                  \
-  ar[k] = BL_MFMA(A.wr, B.wr, ar[k]);                      \
-  ar[k] = BL_MFMA(A.wi, B.wi, ar[k]);                      \
-  ai[k] = BL_MFMA(A.wr, B.wi, ai[k]);                      \
-  ai[k] = BL_MFMA(-A.wi, B.wr, ai[k]);
-
-// Operands of one 16-column tile for G = sum over edges of conj(u) (M u): the x- and y-edge
-// values (u) and their mass products (v), per component [0] x, [1] y.
-struct GTile {
-  double ur[2], ui[2], vr[2], vi[2];
-};
-// Operands of one tile for H = sum over cells of (kappa s) conj(w) w: the cell curl scaled
-// by sqrt(kappa s).
-struct HTile {
-  double wr, wi;
-};
-
 // The workgroup's staging: x-edge rows in a ring of XS slots (row e in slot (e - r0 + 1) mod
 // XS), y-edge rows in two slots with the scaled curl weights of their cells; per node the
-// columns at stride CP (complex).  Values are stored as fetch() returns them for the row's
-// extended index (times beta one period up, conj(beta) one period back; the y halo times
-// alpha / conj(alpha)), zero for columns >= q and nodes past the grid.
+// staged columns at stride CP (complex).  Values are stored as fetch() returns them for the
+// row's extended index (times beta one period up, conj(beta) one period back; the y halo
+// times alpha / conj(alpha)), zero for columns >= q and nodes past the grid.
+template <int NG>
 struct RRStage {
-  double2 x[XS][SW][CP];
-  double2 y[2][YW][CP];
+  double2 x[XS][SW][RRConf<NG>::CP];
+  double2 y[2][YW][RRConf<NG>::CP];
   double w[2][SW];
 };
 
-// Staged item e of a row pair: x-edge (node, column) of row xrow for e < SW MQ, then y-edge
+// Staged column c of a workgroup with group bases cA (and cB): global column.
+template <int NG>
+__device__ __forceinline__ int staged_col(int c, int cA, int cB) {
+  return (NG == 1 || c < MQ) ? cA + c : cB + (c - MQ);
+}
+
+// Staged item e of a row pair: x-edge (node, column) of row xrow for e < SW NC, then y-edge
 // (halo node, column) of row yrow, then the cell coefficient kappa of the cells of row yrow.
 // rr_fetch issues the loads only (from a valid address in every case, so that no value is
 // waited for before it is stored), with a code for what rr_put applies: bit 3 zero (not
@@ -227,20 +240,21 @@ struct RRRaw {
   int code;
 };
 
+template <int NG>
 __device__ __forceinline__ RRRaw rr_fetch(int e, const double* S, int q, int64_t N, int64_t nm, int n, int m,
-                                          const double* kap, int c0, int xrow, int yrow, bool want) {
+                                          const double* kap, int c0, int xrow, int yrow, bool want, int cA, int cB) {
   // branch-free: the three kinds' addresses are formed side by side and selected, and every
   // lane issues its two loads, so that nothing waits for the values here
-  constexpr int NX = SW * MQ, NY = YW * MQ;
+  constexpr int NX = SW * RRConf<NG>::NC, NY = YW * RRConf<NG>::NC;
   const bool isx = e < NX, isy = !isx && e < NX + NY, isw = !isx && !isy;
   const int ey = e - NX, ew = e - NX - NY;
   // x-edge rows: the row's wrap is the same for the whole workgroup
   int r = xrow, cx = 0;
   if (r < 0) { r += m; cx = 2; } else if (r >= m) { r -= m; cx = 1; }
-  const int colx = e / SW, jx = c0 + e % SW;
+  const int colx = staged_col<NG>(e / SW, cA, cB), jx = c0 + e % SW;
   const bool okx = colx < q && jx < n;
   // y-edge halo
-  const int coly = ey / YW;
+  const int coly = staged_col<NG>(ey / YW, cA, cB);
   int jy = c0 - 1 + ey % YW, cy = 4;
   cy = jy < 0 ? (cy | 2) : (jy == n ? (cy | 1) : cy);
   const bool oky = coly < q && jy <= n;
@@ -259,9 +273,10 @@ __device__ __forceinline__ RRRaw rr_fetch(int e, const double* S, int q, int64_t
 }
 
 // store item e (applying its code) into the x slot / y slot
-__device__ __forceinline__ void rr_put(RRStage& st, int e, const RRRaw& raw, const Ph<double>& p, double s, int xslot,
-                                       int yslot, bool with_x, bool with_y) {
-  constexpr int NX = SW * MQ, NY = YW * MQ;
+template <int NG>
+__device__ __forceinline__ void rr_put(RRStage<NG>& st, int e, const RRRaw& raw, const Ph<double>& p, double s,
+                                       int xslot, int yslot, bool with_x, bool with_y) {
+  constexpr int NX = SW * RRConf<NG>::NC, NY = YW * RRConf<NG>::NC;
   const bool zero = (raw.code & 8) != 0;
   if (e >= NX + NY) {
     if (with_y) st.w[yslot][e - NX - NY] = zero ? 0.0 : sqrt(raw.a * s);
@@ -280,20 +295,114 @@ __device__ __forceinline__ void rr_put(RRStage& st, int e, const RRRaw& raw, con
   }
 }
 
-constexpr int RR_ITEMS = SW * MQ + YW * MQ + SW;
-constexpr int RR_THREADS = 128 * MW;
-constexpr int RR_PER_THREAD = (RR_ITEMS + RR_THREADS - 1) / RR_THREADS;
+// Group bases of workgroup row blockIdx.y: NG = 1, diagonal block y (columns 48 y ..);
+// NG = 2, the y-th cross pair (I < J) in row order.
+template <int NG>
+__device__ __forceinline__ void group_bases(int y, int ngroups, int& cA, int& cB) {
+  if (NG == 1) {
+    cA = MQ * y;
+    cB = cA;
+    return;
+  }
+  int I = 0, rem = y;
+  while (rem >= ngroups - 1 - I) { rem -= ngroups - 1 - I; ++I; }
+  cA = MQ * I;
+  cB = MQ * (I + 1 + rem);
+}
 
-// One workgroup per slice of SW nodes x band of rows [r0, r1) of a slot: waves 0..MW-1 form
-// G, waves MW..2MW-1 form H, wave w of a product taking the nodes 4w .. 4w+3 of each row.
-// Rows stream through the LDS ring with a one-row prefetch in registers and one barrier per
-// row; the waves' sums are combined in a fixed order and the slice's full G and H written.
+// Cross blocks (NG = 2): wave w of a product takes the tile pairs [KB, KB + KC) of the nine
+// (KB = 0, KC = 5 for w < 2; KB = 5, KC = 4 otherwise) over the eight nodes 8 (w & 1) .. + 7 of
+// the slice (two groups of four), so that its accumulators and operands stay in registers.
+template <int KB, int KC>
+__device__ __forceinline__ void cross_g(const RRStage<2>& st, int s0, int sp, int sm, int sy, int nb8, int lane,
+                                        bool node_ok0, bool node_ok1, double mxs, double mys, d4* ar, d4* ai) {
+  constexpr int TI0 = pair_ti<2>(KB), TI1 = pair_ti<2>(KB + KC - 1);   // first-side tiles used
+  const double two3 = 2.0 / 3.0, one6 = 1.0 / 6.0;
+  const int cl = lane & 15;
+#pragma unroll
+  for (int gsub = 0; gsub < 2; ++gsub) {
+    const int jn = nb8 + 4 * gsub + (lane >> 4);
+    const bool node_ok = gsub ? node_ok1 : node_ok0;
+    double ur[MT][2], ui[MT][2], vr[MT][2], vi[MT][2];
+#pragma unroll
+    for (int ta = TI0; ta <= TI1; ++ta) {
+      const int c = 16 * ta + cl;
+      const double2 x0 = st.x[s0][jn][c], y0 = st.y[sy][jn + 1][c];
+      ur[ta][0] = x0.x; ui[ta][0] = x0.y;
+      ur[ta][1] = node_ok ? y0.x : 0.0; ui[ta][1] = node_ok ? y0.y : 0.0;
+    }
+#pragma unroll
+    for (int tb = 0; tb < MT; ++tb) {
+      const int c = MQ + 16 * tb + cl;
+      const double2 x0 = st.x[s0][jn][c], xu = st.x[sp][jn][c], xd = st.x[sm][jn][c];
+      const double2 y0 = st.y[sy][jn + 1][c], yr = st.y[sy][jn + 2][c], yl = st.y[sy][jn][c];
+      const Cx<double> mx = mxs * ((two3 * Cx<double>{x0.x, x0.y}) + one6 * (Cx<double>{xu.x, xu.y} + Cx<double>{xd.x, xd.y}));
+      const Cx<double> my = mys * ((two3 * Cx<double>{y0.x, y0.y}) + one6 * (Cx<double>{yr.x, yr.y} + Cx<double>{yl.x, yl.y}));
+      vr[tb][0] = mx.re; vi[tb][0] = mx.im; vr[tb][1] = my.re; vi[tb][1] = my.im;
+    }
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+      const int A = pair_ti<2>(KB + kk), B = pair_tj<2>(KB + kk) - MT;
+      ar[kk] = BL_MFMA(ur[A][0], vr[B][0], ar[kk]);
+      ar[kk] = BL_MFMA(ui[A][0], vi[B][0], ar[kk]);
+      ar[kk] = BL_MFMA(ur[A][1], vr[B][1], ar[kk]);
+      ar[kk] = BL_MFMA(ui[A][1], vi[B][1], ar[kk]);
+      ai[kk] = BL_MFMA(ur[A][0], vi[B][0], ai[kk]);
+      ai[kk] = BL_MFMA(-ui[A][0], vr[B][0], ai[kk]);
+      ai[kk] = BL_MFMA(ur[A][1], vi[B][1], ai[kk]);
+      ai[kk] = BL_MFMA(-ui[A][1], vr[B][1], ai[kk]);
+    }
+  }
+}
+template <int KB, int KC>
+__device__ __forceinline__ void cross_h(const RRStage<2>& st, int s0, int sp, int sy, int nb8, int lane, d4* ar,
+                                        d4* ai) {
+  constexpr int TI0 = pair_ti<2>(KB), TI1 = pair_ti<2>(KB + KC - 1);
+  const int cl = lane & 15;
+#pragma unroll
+  for (int gsub = 0; gsub < 2; ++gsub) {
+    const int jn = nb8 + 4 * gsub + (lane >> 4);
+    const double wsc = st.w[sy][jn];
+    double wr[2 * MT], wi[2 * MT];
+#pragma unroll
+    for (int tt = 0; tt < 2 * MT; ++tt) {
+      if (tt < MT && (tt < TI0 || tt > TI1)) continue;
+      const int c = 16 * tt + cl;
+      const double2 x0 = st.x[s0][jn][c], xu = st.x[sp][jn][c];
+      const double2 y0 = st.y[sy][jn + 1][c], yr = st.y[sy][jn + 2][c];
+      const Cx<double> c0v = wsc * (Cx<double>{xu.x, xu.y} - Cx<double>{x0.x, x0.y} + Cx<double>{y0.x, y0.y} -
+                                    Cx<double>{yr.x, yr.y});
+      wr[tt] = c0v.re;
+      wi[tt] = c0v.im;
+    }
+#pragma unroll
+    for (int kk = 0; kk < KC; ++kk) {
+      const int A = pair_ti<2>(KB + kk), B = pair_tj<2>(KB + kk);
+      ar[kk] = BL_MFMA(wr[A], wr[B], ar[kk]);
+      ar[kk] = BL_MFMA(wi[A], wi[B], ar[kk]);
+      ai[kk] = BL_MFMA(wr[A], wi[B], ai[kk]);
+      ai[kk] = BL_MFMA(-wi[A], wr[B], ai[kk]);
+    }
+  }
+}
+
+// One workgroup per slice of SW nodes x band of rows [r0, r1) of a slot and per column block
+// (blockIdx.y): waves 0..MW-1 form G, waves MW..2MW-1 form H, wave w of a product taking the
+// nodes 4w .. 4w+3 of each row.  Rows stream through the LDS ring with a one-row prefetch in
+// registers and one barrier per row; the waves' sums are combined in a fixed order and the
+// block's entries of G and H (with their Hermitian mirrors) written to the slice's partial.
+template <int NG>
 __global__ __launch_bounds__(RR_THREADS) void k_rr_mfma(View<const double> Sv, int q, const double* __restrict__ kappa,
                                                         Geo g, const Phase* __restrict__ phs, int slices, int band,
-                                                        double* __restrict__ partial, const int* __restrict__ slots) {
+                                                        int ngroups, double* __restrict__ partial,
+                                                        const int* __restrict__ slots) {
+  using C = RRConf<NG>;
+  constexpr int NT = C::NT, MP = C::MP, ITEMS = C::ITEMS, PT = C::PER_THREAD;
   extern __shared__ double lds[];
-  RRStage& st = *reinterpret_cast<RRStage*>(lds);
+  RRStage<NG>& st = *reinterpret_cast<RRStage<NG>*>(lds);
   const int slot = slots ? slots[blockIdx.z] : (int)blockIdx.z;
+  int cA, cB;
+  group_bases<NG>((int)blockIdx.y, ngroups, cA, cB);
   const int64_t N = g.ne, nm = g.nm;
   const int n = g.n, m = g.m;
   const double* S = Sv.p + ((int64_t)slot * Sv.cps + Sv.off) * 2 * N;
@@ -309,124 +418,168 @@ __global__ __launch_bounds__(RR_THREADS) void k_rr_mfma(View<const double> Sv, i
   auto xslot = [&](int e) { return (e - r0 + 1) & (XS - 1); };
   // rows r0-1, r0, r0+1 (x) and r0 (y) straight into LDS (all loads issued first)
   {
-    RRRaw ini[3][RR_PER_THREAD];
+    RRRaw ini[3][PT];
 #pragma unroll
     for (int k = 0; k < 3; ++k)
 #pragma unroll
-      for (int u = 0; u < RR_PER_THREAD; ++u) {
+      for (int u = 0; u < PT; ++u) {
         const int e = tid + u * RR_THREADS;
-        ini[k][u] = rr_fetch(e < RR_ITEMS ? e : 0, S, q, N, nm, n, m, kap, c0, r0 - 1 + k, r0, e < RR_ITEMS);
+        ini[k][u] = rr_fetch<NG>(e < ITEMS ? e : 0, S, q, N, nm, n, m, kap, c0, r0 - 1 + k, r0, e < ITEMS, cA, cB);
       }
 #pragma unroll
     for (int k = 0; k < 3; ++k)
 #pragma unroll
-      for (int u = 0; u < RR_PER_THREAD; ++u) {
+      for (int u = 0; u < PT; ++u) {
         const int e = tid + u * RR_THREADS;
-        if (e < RR_ITEMS) rr_put(st, e, ini[k][u], p, g.s, xslot(r0 - 1 + k), r0 & 1, true, k == 1);
+        if (e < ITEMS) rr_put<NG>(st, e, ini[k][u], p, g.s, xslot(r0 - 1 + k), r0 & 1, true, k == 1);
       }
   }
   // prefetch of rows r0+2 (x) and r0+1 (y)
-  RRRaw pf[RR_PER_THREAD];
+  RRRaw pf[PT];
 #pragma unroll
-  for (int u = 0; u < RR_PER_THREAD; ++u) {
+  for (int u = 0; u < PT; ++u) {
     const int e = tid + u * RR_THREADS;
-    pf[u] = rr_fetch(e < RR_ITEMS ? e : 0, S, q, N, nm, n, m, kap, c0, r0 + 2, r0 + 1, e < RR_ITEMS && r0 + 1 < r1);
+    pf[u] = rr_fetch<NG>(e < ITEMS ? e : 0, S, q, N, nm, n, m, kap, c0, r0 + 2, r0 + 1, e < ITEMS && r0 + 1 < r1, cA, cB);
   }
-  d4 ar[MP], ai[MP];
+  constexpr int NA = NG == 1 ? MP : 5;   // accumulators per wave (cross blocks: half the pairs)
+  d4 ar[NA], ai[NA];
 #pragma unroll
-  for (int k = 0; k < MP; ++k) ar[k] = ai[k] = d4{0, 0, 0, 0};
+  for (int k = 0; k < NA; ++k) ar[k] = ai[k] = d4{0, 0, 0, 0};
   const double two3 = 2.0 / 3.0, one6 = 1.0 / 6.0;
+  const int half = w >> 1, nb8 = 8 * (w & 1);   // cross blocks: pair half and node octet
   const int jn = 4 * w + (lane >> 4);   // this lane's node in the slice
   const int cl = lane & 15;             // and column in each tile
   for (int r = r0; r < r1; ++r) {
     __syncthreads();   // rows up to r + 1 staged; the slots written below are no longer read
     if (r + 1 < r1) {
 #pragma unroll
-      for (int u = 0; u < RR_PER_THREAD; ++u) {
+      for (int u = 0; u < PT; ++u) {
         const int e = tid + u * RR_THREADS;
-        if (e < RR_ITEMS) rr_put(st, e, pf[u], p, g.s, xslot(r + 2), (r + 1) & 1, true, true);
+        if (e < ITEMS) rr_put<NG>(st, e, pf[u], p, g.s, xslot(r + 2), (r + 1) & 1, true, true);
       }
 #pragma unroll
-      for (int u = 0; u < RR_PER_THREAD; ++u) {
+      for (int u = 0; u < PT; ++u) {
         const int e = tid + u * RR_THREADS;
-        pf[u] = rr_fetch(e < RR_ITEMS ? e : 0, S, q, N, nm, n, m, kap, c0, r + 3, r + 2, e < RR_ITEMS && r + 2 < r1);
+        pf[u] = rr_fetch<NG>(e < ITEMS ? e : 0, S, q, N, nm, n, m, kap, c0, r + 3, r + 2, e < ITEMS && r + 2 < r1, cA, cB);
       }
     }
     const int sm = xslot(r - 1), s0 = xslot(r), sp = xslot(r + 1), sy = r & 1;
-    if (!is_h) {
+    if (NG == 2) {
+      if (!is_h) {
+        const bool ok0 = c0 + nb8 + (lane >> 4) < n, ok1 = c0 + nb8 + 4 + (lane >> 4) < n;
+        if (half == 0) cross_g<0, 5>(*reinterpret_cast<const RRStage<2>*>(&st), s0, sp, sm, sy, nb8, lane, ok0, ok1, g.mx, g.my, ar, ai);
+        else cross_g<5, 4>(*reinterpret_cast<const RRStage<2>*>(&st), s0, sp, sm, sy, nb8, lane, ok0, ok1, g.mx, g.my, ar, ai);
+      } else {
+        if (half == 0) cross_h<0, 5>(*reinterpret_cast<const RRStage<2>*>(&st), s0, sp, sy, nb8, lane, ar, ai);
+        else cross_h<5, 4>(*reinterpret_cast<const RRStage<2>*>(&st), s0, sp, sy, nb8, lane, ar, ai);
+      }
+    } else if (!is_h) {
+      // G = sum over edges of conj(u) (M u): u of the pairs' first tiles, M u of their second
       const bool node_ok = c0 + jn < n;
-      GTile t[MT];
+      double ur[NT][2], ui[NT][2], vr[NT][2], vi[NT][2];
 #pragma unroll
-      for (int tt = 0; tt < MT; ++tt) {
+      for (int tt = 0; tt < NT; ++tt) {
         const int c = 16 * tt + cl;
-        const double2 x0 = st.x[s0][jn][c], xu = st.x[sp][jn][c], xd = st.x[sm][jn][c];
-        const double2 y0 = st.y[sy][jn + 1][c], yr = st.y[sy][jn + 2][c], yl = st.y[sy][jn][c];
+        const double2 x0 = st.x[s0][jn][c], y0 = st.y[sy][jn + 1][c];
+        // u of nodes past the grid is zero (their y-edge slot may hold the wrapped halo value)
+        ur[tt][0] = x0.x; ui[tt][0] = x0.y;
+        ur[tt][1] = node_ok ? y0.x : 0.0; ui[tt][1] = node_ok ? y0.y : 0.0;
+        const double2 xu = st.x[sp][jn][c], xd = st.x[sm][jn][c];
+        const double2 yr = st.y[sy][jn + 2][c], yl = st.y[sy][jn][c];
         const Cx<double> mx = g.mx * ((two3 * Cx<double>{x0.x, x0.y}) + one6 * (Cx<double>{xu.x, xu.y} + Cx<double>{xd.x, xd.y}));
         const Cx<double> my = g.my * ((two3 * Cx<double>{y0.x, y0.y}) + one6 * (Cx<double>{yr.x, yr.y} + Cx<double>{yl.x, yl.y}));
-        // u of nodes past the grid is zero (their y-edge slot may hold the wrapped halo value)
-        t[tt].ur[0] = x0.x; t[tt].ui[0] = x0.y;
-        t[tt].ur[1] = node_ok ? y0.x : 0.0; t[tt].ui[1] = node_ok ? y0.y : 0.0;
-        t[tt].vr[0] = mx.re; t[tt].vi[0] = mx.im; t[tt].vr[1] = my.re; t[tt].vi[1] = my.im;
+        vr[tt][0] = mx.re; vi[tt][0] = mx.im; vr[tt][1] = my.re; vi[tt][1] = my.im;
       }
-      BL_GPAIR(0, t[0], t[0])
-      BL_GPAIR(1, t[0], t[1])
-      BL_GPAIR(2, t[0], t[2])
-      BL_GPAIR(3, t[1], t[1])
-      BL_GPAIR(4, t[1], t[2])
-      BL_GPAIR(5, t[2], t[2])
+#pragma unroll
+      for (int k = 0; k < NA; ++k) {
+        const int A = pair_ti<NG>(k), B = pair_tj<NG>(k);
+        ar[k] = BL_MFMA(ur[A][0], vr[B][0], ar[k]);
+        ar[k] = BL_MFMA(ui[A][0], vi[B][0], ar[k]);
+        ar[k] = BL_MFMA(ur[A][1], vr[B][1], ar[k]);
+        ar[k] = BL_MFMA(ui[A][1], vi[B][1], ar[k]);
+        ai[k] = BL_MFMA(ur[A][0], vi[B][0], ai[k]);
+        ai[k] = BL_MFMA(-ui[A][0], vr[B][0], ai[k]);
+        ai[k] = BL_MFMA(ur[A][1], vi[B][1], ai[k]);
+        ai[k] = BL_MFMA(-ui[A][1], vr[B][1], ai[k]);
+      }
     } else {
-      HTile t[MT];
+      // H = sum over cells of (kappa s) conj(w) w, w the cell curl
+      double wr[NT], wi[NT];
       const double wsc = st.w[sy][jn];
 #pragma unroll
-      for (int tt = 0; tt < MT; ++tt) {
+      for (int tt = 0; tt < NT; ++tt) {
         const int c = 16 * tt + cl;
         const double2 x0 = st.x[s0][jn][c], xu = st.x[sp][jn][c];
         const double2 y0 = st.y[sy][jn + 1][c], yr = st.y[sy][jn + 2][c];
         const Cx<double> c0v = wsc * (Cx<double>{xu.x, xu.y} - Cx<double>{x0.x, x0.y} + Cx<double>{y0.x, y0.y} -
                                       Cx<double>{yr.x, yr.y});
-        t[tt].wr = c0v.re;
-        t[tt].wi = c0v.im;
+        wr[tt] = c0v.re;
+        wi[tt] = c0v.im;
       }
-      BL_HPAIR(0, t[0], t[0])
-      BL_HPAIR(1, t[0], t[1])
-      BL_HPAIR(2, t[0], t[2])
-      BL_HPAIR(3, t[1], t[1])
-      BL_HPAIR(4, t[1], t[2])
-      BL_HPAIR(5, t[2], t[2])
+#pragma unroll
+      for (int k = 0; k < NA; ++k) {
+        const int A = pair_ti<NG>(k), B = pair_tj<NG>(k);
+        ar[k] = BL_MFMA(wr[A], wr[B], ar[k]);
+        ar[k] = BL_MFMA(wi[A], wi[B], ar[k]);
+        ai[k] = BL_MFMA(wr[A], wi[B], ai[k]);
+        ai[k] = BL_MFMA(-wi[A], wr[B], ai[k]);
+      }
     }
   }
   __syncthreads();   // the ring is reused for the combination
-  // combine the waves of each product in order 0 .. MW-1
+  // combine the waves of each product in a fixed order: diagonal blocks waves 0 .. MW-1 (each
+  // holds every pair for its nodes); cross blocks the two node octets of each pair half
   double* red = lds;
-  double* mine = red + ((size_t)(is_h ? 1 : 0) * 64 + lane) * 8 * MP;
-  for (int src = 0; src < MW; ++src) {
-    if (w == src) {
+  if (NG == 1) {
+    double* mine = red + ((size_t)(is_h ? 1 : 0) * 64 + lane) * 8 * MP;
+    for (int src = 0; src < MW; ++src) {
+      if (w == src) {
 #pragma unroll
-      for (int k = 0; k < MP; ++k)
+        for (int k = 0; k < NA; ++k)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          double* e = mine + 8 * k + 2 * v;
-          if (src == 0) {
-            e[0] = ar[k][v];
-            e[1] = ai[k][v];
-          } else {
-            e[0] += ar[k][v];
-            e[1] += ai[k][v];
+          for (int v = 0; v < 4; ++v) {
+            double* e = mine + 8 * k + 2 * v;
+            if (src == 0) {
+              e[0] = ar[k][v];
+              e[1] = ai[k][v];
+            } else {
+              e[0] += ar[k][v];
+              e[1] += ai[k][v];
+            }
+          }
+      }
+      __syncthreads();
+    }
+  } else {
+    const int kb = half ? 5 : 0, kc = half ? 4 : 5;
+    double* mine = red + ((size_t)(is_h ? 1 : 0) * 64 + lane) * 8 * MP;
+    for (int oct = 0; oct < 2; ++oct) {
+      if ((w & 1) == oct) {
+#pragma unroll
+        for (int kk = 0; kk < NA; ++kk) {
+          if (kk >= kc) continue;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            double* e = mine + 8 * (kb + kk) + 2 * v;
+            if (oct == 0) {
+              e[0] = ar[kk][v];
+              e[1] = ai[kk][v];
+            } else {
+              e[0] += ar[kk][v];
+              e[1] += ai[kk][v];
+            }
           }
         }
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
-  // write the slice's full G and H (q x q, interleaved complex; lower tiles mirrored)
+  // write the block's entries of G and H (q x q, interleaved complex) with their mirrors
   double* pg = partial + ((int64_t)blockIdx.z * gridDim.x + blockIdx.x) * (int64_t)q * q * 4;
   for (int e = threadIdx.x; e < 2 * 64 * MP * 4; e += RR_THREADS) {
     const int prod = e / (64 * MP * 4), l = (e / (MP * 4)) % 64, k = (e / 4) % MP, v = e % 4;
-    int ti = 0, tj = 0, kk = k;
-    for (ti = 0; ti < MT; ++ti) {
-      if (kk < MT - ti) { tj = ti + kk; break; }
-      kk -= MT - ti;
-    }
-    const int i = 16 * ti + 4 * v + (l >> 4), j = 16 * tj + (l & 15);
+    const int ti = pair_ti<NG>(k), tj = pair_tj<NG>(k);
+    const int i = staged_col<NG>(16 * ti + 4 * v + (l >> 4), cA, cB), j = staged_col<NG>(16 * tj + (l & 15), cA, cB);
     if (i >= q || j >= q) continue;
     const double* src = red + ((size_t)prod * 64 + l) * 8 * MP + 8 * k + 2 * v;
     double* out = pg + (int64_t)prod * q * q * 2;
@@ -440,8 +593,6 @@ __global__ __launch_bounds__(RR_THREADS) void k_rr_mfma(View<const double> Sv, i
   }
 }
 
-#undef BL_GPAIR
-#undef BL_HPAIR
 #undef BL_MFMA
 
 // G_s, H_s = sums over the node ranges of launch entry z: 16 entries per block, the ranges
@@ -506,19 +657,25 @@ int rr_blocks(int64_t nm) {
 int rr_gram(View<const double> S, int q, const double* kappa, const Geo& g, const Phase* ph,
             double* partial, int64_t partial_cap, double* G, double* H, int tile, const Launch& L) {
   if (L.nact <= 0) return 0;
-  if (q <= MQ) {
+  if (q <= kMfmaGroups * MQ) {
     const RRGrid grd = rr_mfma_grid(g);
     const int nb = grd.blocks;
     if ((int64_t)nb * q * q * 4 * L.nact > partial_cap) return -1;
-    const size_t lds = sizeof(RRStage) > (size_t)2 * 64 * 8 * MP * sizeof(double) ? sizeof(RRStage)
-                                                                                 : (size_t)2 * 64 * 8 * MP * sizeof(double);
-    static bool attr = false;
-    if (!attr) {
-      (void)hipFuncSetAttribute((const void*)k_rr_mfma, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      attr = true;
-    }
-    k_rr_mfma<<<dim3((unsigned)nb, 1, (unsigned)L.nact), RR_THREADS, lds, L.st>>>(S, q, kappa, g, ph, grd.slices,
-                                                                                  grd.band, partial, L.slots);
+    const int ngroups = (q + MQ - 1) / MQ;
+    auto launch = [&](auto ngt, int blocks_y) {
+      constexpr int NG = decltype(ngt)::value;
+      const size_t red = (size_t)2 * 64 * 8 * RRConf<NG>::MP * sizeof(double);
+      const size_t lds = sizeof(RRStage<NG>) > red ? sizeof(RRStage<NG>) : red;
+      static bool attr = false;
+      if (!attr) {
+        (void)hipFuncSetAttribute((const void*)k_rr_mfma<NG>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        attr = true;
+      }
+      k_rr_mfma<NG><<<dim3((unsigned)nb, (unsigned)blocks_y, (unsigned)L.nact), RR_THREADS, lds, L.st>>>(
+          S, q, kappa, g, ph, grd.slices, grd.band, ngroups, partial, L.slots);
+    };
+    launch(std::integral_constant<int, 1>{}, ngroups);
+    if (ngroups > 1) launch(std::integral_constant<int, 2>{}, ngroups * (ngroups - 1) / 2);
     const int64_t cnt = (int64_t)q * q * 4;
     k_rr_reduce<<<dim3((unsigned)((cnt + 15) / 16), (unsigned)L.nact), 256, 0, L.st>>>(partial, nb, q, G, H,
                                                                                       L.slots);
@@ -530,7 +687,7 @@ int rr_gram(View<const double> S, int q, const double* kappa, const Geo& g, cons
   rpb = (rpb + CH - 1) / CH * CH;
   const int TB = tile == 4 ? 64 : 48;
   const int nt = (q + TB - 1) / TB;
-  dim3 grid((unsigned)nb, (unsigned)(nt * nt), (unsigned)L.nact);
+  dim3 grid((unsigned)nb, (unsigned)(nt * (nt + 1) / 2), (unsigned)L.nact);
   if (tile == 4) k_rr_gram<4><<<grid, 256, 0, L.st>>>(S, q, kappa, g, ph, rpb, partial, L.slots);
   else k_rr_gram<3><<<grid, 256, 0, L.st>>>(S, q, kappa, g, ph, rpb, partial, L.slots);
   const int64_t cnt = (int64_t)q * q * 4;

@@ -610,7 +610,7 @@ int project_groups(bl_solver* s, const std::vector<Group>& groups, View<double> 
   if (!gslots.empty()) {
     Launch Lgam = make_launch(s, gslots, total);
     gamma_deflate(out, g0, s->mean_scratch, Lgam);
-    s->launches += 2;
+    s->launches += 3;
   }
   return BL_OK;
 }
@@ -955,7 +955,7 @@ int engine_create(const bl_grid* grid, const bl_opts* opts, int nslots, hipStrea
   if ((rc = dalloc_t(s, &s->Yd, (size_t)q * q * 2 * S))) return fail(rc);
   s->ritz_stride = ritz_small_work_doubles(q);
   if ((rc = dalloc_t(s, &s->ritz_work, s->ritz_stride * S))) return fail(rc);
-  if ((rc = dalloc_t(s, &s->mean_scratch, (size_t)4 * q * S))) return fail(rc);
+  if ((rc = dalloc_t(s, &s->mean_scratch, gamma_scratch_doubles(q * S)))) return fail(rc);
   if ((rc = dalloc_t(s, &s->probe_e, (size_t)2 * s->nce * s->nce))) return fail(rc);
   if ((rc = dalloc_t(s, &s->probe_n, (size_t)2 * s->ncn * s->ncn))) return fail(rc);
   if ((rc = dalloc_t(s, &s->probe_out, (size_t)2 * s->nce * s->nce * S))) return fail(rc);

@@ -667,14 +667,18 @@ template void lift<float, float>(View<const float>, View<float>, const Geo&, con
 
 // k = 0: remove the constant x- and y-edge fields M-orthogonally.  With alpha = beta = 1,
 // M applied to a constant x-field is h2/h1 times it, so the M-projection onto the constant
-// fields subtracts the mean of the x-part and of the y-part of every column.
-__global__ void k_col_means(View<const double> uv, Geo g, double* __restrict__ out,
-                            const int* __restrict__ slots, int ncps) {
+// fields subtracts the mean of the x-part and of the y-part of every column.  The sums are
+// formed by kGammaBlocks workgroups per column (partials in a fixed order), then reduced.
+constexpr int kGammaBlocks = 64;
+__global__ __launch_bounds__(256) void k_col_sums(View<const double> uv, Geo g, double* __restrict__ part,
+                                                  const int* __restrict__ slots, int ncps) {
   const SJ sj = slot_col(slots, ncps);
   const int64_t N = g.ne, nm = g.nm;
   const double* c = colp(uv, sj, N);
+  const int64_t per = (nm + kGammaBlocks - 1) / kGammaBlocks;
+  const int64_t i0 = (int64_t)blockIdx.x * per, i1 = i0 + per < nm ? i0 + per : nm;
   double a[4] = {0, 0, 0, 0};
-  for (int64_t i = threadIdx.x; i < nm; i += blockDim.x) {
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
     a[0] += c[i];
     a[1] += c[N + i];
     a[2] += c[nm + i];
@@ -689,9 +693,9 @@ __global__ void k_col_means(View<const double> uv, Geo g, double* __restrict__ o
     __syncthreads();
   }
   if (threadIdx.x == 0)
-    for (int v = 0; v < 4; ++v) out[(int64_t)blockIdx.y * 4 + v] = sh[v][0] / (double)nm;
+    for (int v = 0; v < 4; ++v) part[((int64_t)blockIdx.y * kGammaBlocks + blockIdx.x) * 4 + v] = sh[v][0];
 }
-__global__ void k_sub_means(View<double> uv, Geo g, const double* __restrict__ mean,
+__global__ void k_sub_means(View<double> uv, Geo g, const double* __restrict__ sums,
                             const int* __restrict__ slots, int ncps) {
   const SJ sj = slot_col(slots, ncps);
   const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -699,14 +703,20 @@ __global__ void k_sub_means(View<double> uv, Geo g, const double* __restrict__ m
   const int64_t N = g.ne;
   double* c = colp(uv, sj, N);
   const int part = d < g.nm ? 0 : 2;
-  c[d] -= mean[(int64_t)blockIdx.y * 4 + part];
-  c[N + d] -= mean[(int64_t)blockIdx.y * 4 + part + 1];
+  const double inv = 1.0 / (double)g.nm;
+  c[d] -= sums[(int64_t)blockIdx.y * 4 + part] * inv;
+  c[N + d] -= sums[(int64_t)blockIdx.y * 4 + part + 1] * inv;
 }
+size_t gamma_scratch_doubles(int cols) { return (size_t)(kGammaBlocks + 1) * 4 * cols; }
 void gamma_deflate(View<double> u, const Geo& g, double* scratch, const Launch& L) {
-  if (L.nact * L.ncps == 0) return;
-  k_col_means<<<dim3(1, (unsigned)(L.nact * L.ncps)), 256, 0, L.st>>>(View<const double>{u.p, u.cps, u.off}, g, scratch, L.slots, L.ncps);
-  dim3 grid((unsigned)((g.ne + 255) / 256), (unsigned)(L.nact * L.ncps));
-  k_sub_means<<<grid, 256, 0, L.st>>>(u, g, scratch, L.slots, L.ncps);
+  const int cols = L.nact * L.ncps;
+  if (cols == 0) return;
+  double* sums = scratch + (size_t)kGammaBlocks * 4 * cols;
+  k_col_sums<<<dim3(kGammaBlocks, (unsigned)cols), 256, 0, L.st>>>(View<const double>{u.p, u.cps, u.off}, g, scratch,
+                                                                   L.slots, L.ncps);
+  reduce_partials(scratch, kGammaBlocks, cols, 4, sums, L.st);
+  dim3 grid((unsigned)((g.ne + 255) / 256), (unsigned)cols);
+  k_sub_means<<<grid, 256, 0, L.st>>>(u, g, sums, L.slots, L.ncps);
 }
 
 // y += x on the launch's columns (vectors of length len)

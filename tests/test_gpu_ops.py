@@ -193,17 +193,17 @@ def test_gram_and_ritz_small():
 @pytest.mark.parametrize("case", CASES)
 def test_rayleigh_ritz_products(case):
     """G = S^* M S and H = S^* A S formed straight from S (bl_rr_products) against the
-    oracle's assembled matrices, for block widths inside one output tile, spanning several
-    tiles (48- and 64-wide tilings) and with ragged tails."""
+    oracle's assembled matrices, for block widths inside one column group of the matrix-core
+    path, spanning two and three groups (diagonal and cross blocks) and with ragged tails."""
     import torch  # noqa: F401
     from paper_2304_00337_amd import Solver, to_device_block
     n, m, a, b, cmin, k = case
     rng = np.random.default_rng(7 + n)
     eps = rng.uniform(1.0, 12.0, n * m)
     d = fem.Discretization(n, m, a, b, eps, *k)
-    s = Solver(n, m, a, b, eps, nev=20, nthrow=4, mu=MU, coarsest_min=cmin)
+    s = Solver(n, m, a, b, eps, nev=40, nthrow=8, mu=MU, coarsest_min=cmin)
     s.set_k(*k)
-    for q in (1, 5, 48, 60, 72):
+    for q in (1, 5, 48, 60, 72, 96, 121, 144):
         S = _rand(rng, d.n_edges, q)
         G, Hm = s.rr_products(to_device_block(S))
         _close(G, S.conj().T @ (d.M @ S), 1e-13)

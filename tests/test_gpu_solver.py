@@ -134,15 +134,18 @@ def test_lobpcg_matches_oracle_lobpcg(k):
 def test_throwaway_rates_match_oracle():
     """The throw-away study (Section 7) through the C ABI: permittivity 100 in the disc of
     radius 1/3, the same start block and options on both sides.  Per t the residual records
-    agree while the wanted pairs are above 1e-2, the observed rates of the last two wanted
+    agree to 1e-5 while the wanted pairs are above 1e-2 (t = 1: the first ten iterations), the
+    observed rates of the last two wanted
     pairs over the window 1e-2 .. 1e-6 and the iteration counts agree with the oracle's, and
     both rates fall as t grows.  With t = 4 and 8 the rates are well determined (the oracle's
     own rates move by < 0.5% when its start block is perturbed at the rounding level,
     tests/test_oracle_throwaway.py), so the GPU's must agree to 3%.  With t = 1 (p = nev + 1)
     they are not: the same perturbations move the oracle's rates over 0.67 .. 0.72 and its
-    iteration count over 63 .. 70, and the GPU's Gram-based orthonormalisation perturbs every
-    iteration at that level; the t = 1 rates are held to that envelope widened by 10%
-    (0.60 .. 0.80) and its iterations to 25%."""
+    iteration count over 63 .. 70, and the route of the orthonormalisation matters: the
+    oracle run with the Gram (Cholesky) orthonormalisation the GPU uses instead of
+    Householder takes 73 .. 74 iterations at rates 0.72 .. 0.75.  The GPU's t = 1 count is
+    held to 25% of the Gram-route oracle's and its rates to the two routes' envelope widened
+    by 10%."""
     from oracle.throwaway import observed_rate, study
     from paper_2304_00337_amd import Solver
     n, nev, ts, mu = 32, 8, (1, 4, 8), 0.5
@@ -153,6 +156,8 @@ def test_throwaway_rates_match_oracle():
     E0 = synth.start_block(d.n_edges, nev + max(ts), 3)
     ref = study(d, H, Projector(d, H, 2), E0, nev, ts, (nev - 1, nev), tol=1e-9, max_iter=300,
                 lower=1e-6)
+    ref_gram = study(d, H, Projector(d, H, 2), E0, nev, (1,), (nev - 1, nev), tol=1e-9, max_iter=300,
+                     lower=1e-6, ortho="gram")[0]
     gpu = []
     for r in ref:
         s = Solver(n, n, 1.0, 1.0, eps, nev=nev, nthrow=r["t"], mu=mu, coarsest_min=4, tol=1e-9,
@@ -162,18 +167,30 @@ def test_throwaway_rates_match_oracle():
         assert out["converged"] and r["converged"]
         assert hist.shape[0] == out["iterations"] + 1
         assert np.max(np.abs(out["evals"] - r["lam"]) / r["lam"]) < 1e-9
-        it_tol = max(3, int(0.25 * r["iterations"])) if r["t"] == 1 else max(3, int(0.15 * r["iterations"]))
-        assert abs(out["iterations"] - r["iterations"]) <= it_tol, (r["t"], out["iterations"], r["iterations"])
+        if r["t"] == 1:
+            it_ref = ref_gram["iterations"]
+            assert abs(out["iterations"] - it_ref) <= max(3, int(0.25 * it_ref)), (out["iterations"], it_ref)
+        else:
+            assert abs(out["iterations"] - r["iterations"]) <= max(3, int(0.15 * r["iterations"])), (
+                r["t"], out["iterations"], r["iterations"])
+        # the residual records while the last wanted pairs are above 1e-2: with t >= 4 the
+        # oracle's own record moves by < 3e-8 under rounding-level perturbations there, with
+        # t = 1 its deviation grows about threefold per iteration (6e-3 by the 19th), so
+        # only the first ten rows are determined well enough to compare
         h = r["history"]
         rows = min(len(h), len(hist))
         early = np.all(h[:rows, nev - 2:] >= 1e-2, axis=1)
+        if r["t"] == 1:
+            early[10:] = False
         assert early.sum() >= 3
         dev = np.abs(hist[:rows][early] - h[:rows][early]) / h[:rows][early]
-        assert np.max(dev) < 2e-2, (r["t"], np.max(dev))
+        assert np.max(dev) < 1e-5, (r["t"], np.max(dev))
         rates = {i: observed_rate(hist[:, i - 1], 1e-2, 1e-6) for i in (nev - 1, nev)}
         for i, v in rates.items():
             if r["t"] == 1:
-                assert 0.60 <= v <= 0.80, (r["t"], i, v, r["rates"][i])
+                lo = 0.9 * min(r["rates"][i], ref_gram["rates"][i])
+                hi = 1.1 * max(r["rates"][i], ref_gram["rates"][i])
+                assert lo <= v <= hi, (i, v, r["rates"][i], ref_gram["rates"][i])
             else:
                 assert abs(v - r["rates"][i]) < 0.03 * r["rates"][i], (r["t"], i, v, r["rates"][i])
         gpu.append(rates)

@@ -244,3 +244,29 @@ def test_nested_start_follows_section_6():
     ref, _, _ = dense_eigs(d, 4)
     assert conv and np.max(np.abs(lam[:4] - ref) / ref) < 1e-8
     assert it < it_random
+
+
+def test_gram_orthonormalisation_same_span_and_limit():
+    """The Gram (Cholesky) orthonormalisation spans the same space as the Householder one,
+    is M-orthonormal, and the iteration run with it reaches the dense eigenvalues."""
+    from oracle.householder import m_householder, reference_columns
+    from oracle.pinvit import gram_orthonormalize
+    n = 12
+    eps = synth.eps_disc(n, n, 1.0, 1.0, 8.9, 0.3)
+    d = fem.Discretization(n, n, 1.0, 1.0, eps, 0.7, -0.2)
+    rng = np.random.default_rng(4)
+    S = rng.standard_normal((d.n_edges, 9)) + 1j * rng.standard_normal((d.n_edges, 9))
+    Qg = gram_orthonormalize(S, d.M)
+    Qh, _ = m_householder(S, d.M, reference_columns(n, n, 9))
+    assert np.abs(Qg.conj().T @ (d.M @ Qg) - np.eye(9)).max() < 1e-12
+    # equal spans: the M-orthogonal projectors agree
+    Pg = Qg @ (Qg.conj().T @ d.M.toarray())
+    Ph = Qh @ (Qh.conj().T @ d.M.toarray())
+    assert np.abs(Pg - Ph).max() < 1e-10
+    H = Hierarchy(d, mu=5.0, coarsest_min=3)
+    pr = Projector(d, H, 2)
+    E0 = synth.start_block(d.n_edges, 6, 2)
+    lam0, E = initial_block(d, pr, E0, 6, ortho="gram")
+    lam, _, _, it, conv = pinvit(d, H, pr, E, lam0, 4, 1e-10, 200, ortho="gram")
+    ref, _, _ = dense_eigs(d, 4)
+    assert conv and np.max(np.abs(lam[:4] - ref) / ref) < 1e-9
