@@ -1,23 +1,26 @@
 #!/usr/bin/env python
 """Benchmark: converged Bloch eigenpairs per second on one MI355X.
 
-Workload (one "step" = one whole band path through the hot path): 256 x 256 grid on the
-unit cell, square lattice of eps = 12 discs of radius 0.3 on eps = 1, the 16 smallest
-non-zero eigenpairs (plus 8 throw-away vectors) at 31 Bloch parameters along
-Gamma-X-M-Gamma, 6-level multigrid, relative residual tolerance 1e-8.  Inputs are
-synthetic and seeded (synth.config_c2); they are on the device before the timed region.
+Headline workload: the 1024 x 1024 mixed-precision band path.  Unit cell a = b = 1, a
+seeded smoothed random two-phase permittivity (Gaussian noise blurred with sigma = 0.05,
+thresholded to {1, 11.4}), the 32 smallest non-zero eigenpairs (plus 16 throw-away vectors)
+at 61 Bloch parameters along Gamma-X-M-Gamma (20 intervals per leg), relative residual
+tolerance 1e-6, 8-level multigrid (synth.config_c3).  Inputs are synthetic and seeded, on
+the device before the timed region.
 
-Two forms are timed on the same path:
-  * plain FP64: one problem slot walking the whole path, every point after the first
-    warm-started by Rayleigh-quotient extrapolation;
-  * mixed precision, batched (the headline `value`): V-cycle and nodal projection in
-    complex FP32, everything else in FP64; the path is cut into `--segments` contiguous
-    pieces solved as one batch (each piece cold-starts from a seeded random block, then
-    extrapolates), so every kernel launch of an iteration round serves all pieces.
-An eigenpair counts if it converged and its eigenvalue agrees with the plain FP64 run to
-1e-6 (relative).  Also reported: p50/p99 of the per-point solve time, the roofline of the
-finest-level smoother, the oracle on the host cores, and a short serving run (Poisson
-arrivals of band-path requests, continuous batching).  Prints one JSON line.
+One step = one leg of the path (Gamma->X, X->M, M->Gamma in turn), cold-started from the
+leg's seeded random block and warm-started point to point by Rayleigh-quotient
+extrapolation.  Two forms are timed on the same legs:
+  * mixed (headline `value`): V-cycle and nodal projection in complex FP32, residual,
+    Rayleigh-Ritz, orthonormalisation and extrapolation in FP64;
+  * plain FP64 (`fp64_plain`), every leg once: the precision gain at equal segmentation.
+An eigenpair counts if its point converged and its eigenvalue agrees with the FP64 run of
+the same leg to 1e-6 (relative); both are also checked against the oracle's ARPACK values
+where those are stored (tests/golden).  Also reported: p50/p99 of the per-point solve time,
+the roofline of the finest-level edge smoother on this run, the oracle on the host cores,
+and side legs (the 256 x 256 lattice path in plain FP64, a batch of 64 problems, a serving
+run, the LOBPCG variant, the throw-away study, the Bloch-grid raster and the nested start).
+Prints one JSON line.
 """
 import argparse
 import json
@@ -31,102 +34,211 @@ sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
 
+T_START = time.perf_counter()
+BUDGET_S = 530.0   # whole-run budget; side legs are skipped when it runs short
 
-def segments(prob, S, per_segment):
-    """The path cut into S contiguous pieces (S = 0: its three legs Gamma-X, X-M, M-Gamma,
-    cut at the corners); piece 0 starts from the problem's seeded block, piece i > 0 from
-    the block seeded 100 + i."""
+
+def remaining():
+    return BUDGET_S - (time.perf_counter() - T_START)
+
+
+def log(msg):
+    print(f"# [{time.perf_counter() - T_START:6.1f}s] {msg}", file=sys.stderr, flush=True)
+
+
+# ---- headline: the C3 path, leg by leg --------------------------------------------------
+LEG_CUTS = (0, 20, 40, 61)
+
+
+def c3_legs(prob):
+    """The 61-point path cut at X and M into its three legs; leg 0 starts from the workload's
+    seeded block, leg i > 0 from the block seeded 100 + i."""
     import synth
     from paper_2304_00337_amd import to_device_block
-    ks = np.asarray(prob.ks)
-    if S == 0:
-        cuts = [0, per_segment, 2 * per_segment, len(ks)]
-        pieces = [np.arange(cuts[i], cuts[i + 1]) for i in range(3)]
-    else:
-        pieces = np.array_split(np.arange(len(ks)), S)
-    out = []
-    for i, ix in enumerate(pieces):
+    legs = []
+    for i in range(3):
+        ks = np.asarray(prob.ks)[LEG_CUTS[i]:LEG_CUTS[i + 1]]
         st = prob.start() if i == 0 else synth.start_block(prob.n_edges, prob.p, 100 + i)
-        out.append(dict(n=prob.n, m=prob.m, a=prob.a, b=prob.b, eps=prob.eps, nev=prob.nev,
-                        nthrow=prob.nthrow, ks=ks[ix], start=to_device_block(st)))
-    return out
+        legs.append(dict(n=prob.n, m=prob.m, a=prob.a, b=prob.b, eps=prob.eps, nev=prob.nev,
+                         nthrow=prob.nthrow, ks=ks, start=to_device_block(st)))
+    return legs
 
 
-def run_form(prob, precision, S, steps, warmup, per_segment, max_slots=None, engine_streams=0, variant=0):
-    """Solve the path cut into S pieces (one batch) `steps` times after `warmup` untimed
-    runs; engine_streams = 0 keeps the library's default (engines of one shape side by side
-    on three streams), 1 runs the pieces one engine at a time."""
+def run_legs(prob, legs, precision, steps, warmup, timing_warmup=False):
+    """`warmup` untimed legs (with the finest-smoother timing on when asked), then `steps`
+    timed legs, leg i % 3 at step i."""
     import torch
     from paper_2304_00337_amd import Batch
-    probs = segments(prob, S, per_segment)
     recs = []
-    with Batch(max_slots=max_slots or len(probs), precision=precision, levels=prob.levels, tol=prob.tol,
-               max_iter=300, engine_streams=engine_streams, variant=variant) as b:
-        for _ in range(warmup):
-            b.run(probs)
+    with Batch(max_slots=1, engine_streams=1, precision=precision, levels=prob.levels, tol=prob.tol,
+               max_iter=200) as b:
+        if timing_warmup:
+            b.set_timing(True)
+        for w in range(warmup):
+            b.run([legs[w % 3]])
         torch.cuda.synchronize()
-        b.set_timing(True)
+        tm = b.timing() if timing_warmup else None
+        b.set_timing(False)
+        shapes = [{"edge_smooth_shape": e["edge_smooth_shape"], "nodal_smooth_shape": e["nodal_smooth_shape"],
+                   "fused_edge_level": e["fused_edge_level"], "fused_nodal_level": e["fused_nodal_level"],
+                   "levels": e["levels"], "mu": e["mu"]} for e in b.engines()]
         t0 = time.perf_counter()
-        for _ in range(steps):
+        for i in range(steps):
+            leg = i % 3
             ts = time.perf_counter()
-            res = b.run(probs)
-            recs.append({"evals": np.concatenate([r["evals"] for r in res]),
-                         "iters": np.concatenate([r["iterations"] for r in res]),
-                         "conv": np.concatenate([r["relres"] <= prob.tol for r in res]),
-                         "ms": np.concatenate([r["point_ms"] for r in res]),
-                         "status": [r["status"] for r in res],
+            r = b.run([legs[leg]])[0]
+            recs.append({"leg": leg, "evals": r["evals"], "iters": r["iterations"],
+                         "conv": r["relres"] <= prob.tol, "ms": r["point_ms"], "status": r["status"],
                          "wall": time.perf_counter() - ts})
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
-        tm = b.timing()
-        shapes = [{"edge_smooth_shape": e["edge_smooth_shape"],
-                   "nodal_smooth_shape": e["nodal_smooth_shape"], "rr_tile": e["rr_tile"]} for e in b.engines()]
-    return {"elapsed": elapsed, "recs": recs, "timing": tm, "S": len(probs), "shapes": shapes}
+    return {"elapsed": elapsed, "recs": recs, "timing": tm, "shapes": shapes}
 
 
-def cpu_baseline(prob, iters_total, cold_starts, sample_iters=3):
-    """The oracle on a bounded sample: setup and start block of the first Bloch point and
-    `sample_iters` iterations, scaled to the workload with the GPU run's iteration count."""
+def golden(name):
+    try:
+        with open(os.path.join(ROOT, "tests", "golden", name)) as f:
+            return json.load(f)
+    except OSError:
+        return None
+
+
+def golden_errors(recs, gold):
+    """Largest relative eigenvalue error against stored oracle values at their path points."""
+    if gold is None:
+        return None
+    worst = 0.0
+    found = 0
+    for pt in gold["points"]:
+        i = int(pt["index"])
+        leg = max(L for L in range(3) if LEG_CUTS[L] <= i)
+        for rec in recs:
+            if rec["leg"] == leg:
+                got = rec["evals"][i - LEG_CUTS[leg]]
+                ref = np.array(pt["evals"][:len(got)])
+                worst = max(worst, float(np.max(np.abs(got - ref) / ref)))
+                found += 1
+                break
+    return {"max_rel_err": worst, "points": found}
+
+
+# ---- the oracle on the host -------------------------------------------------------------
+def cpu_baseline(prob, iters_total, cold_starts, sample_n=256):
+    """The oracle on a bounded sample: the same generator's workload at sample_n^2 (the
+    1024^2 oracle takes ~110 s of setup per Bloch point and ~8 min per iteration), its setup
+    at the first point after Gamma, the start block and one iteration with the full block
+    width, scaled to the workload by the dof ratio (the stencils and multigrid are linear in
+    the dofs) and by the GPU run's iteration count."""
+    import synth
     from oracle import fem
+    from oracle.closed_form import discrete_nonzero
     from oracle.multigrid import Hierarchy
     from oracle.pinvit import Projector, initial_block, pinvit
-    k = prob.ks[0]
+    n = sample_n
+    eps = synth.eps_random_field(n, n, 1.0, 1.0, seed=2, sigma=0.05, lo=1.0, hi=11.4)
+    k = prob.ks[1]
     t0 = time.perf_counter()
-    d = fem.Discretization(prob.n, prob.m, prob.a, prob.b, prob.eps, *k)
-    eps_min = float(np.min(prob.eps))
-    # the solver's shift rule: mu = lambda_p of the homogeneous cell (eps_min) at k = 0, / 10
-    from oracle.closed_form import discrete_nonzero
-    mu = discrete_nonzero(prob.n, prob.m, prob.a, prob.b, eps_min, 0.0, 0.0, prob.p)[-1] / 10.0
-    H = Hierarchy(d, mu=mu, max_levels=prob.levels)
+    d = fem.Discretization(n, n, 1.0, 1.0, eps, *k)
+    mu = discrete_nonzero(n, n, 1.0, 1.0, float(eps.min()), 0.0, 0.0, prob.p)[-1] / 10.0
+    H = Hierarchy(d, mu=mu)
     pr = Projector(d, H, 2)
     t1 = time.perf_counter()
-    lam, E = initial_block(d, pr, prob.start(), prob.p)
+    lam, E = initial_block(d, pr, synth.start_block(2 * n * n, prob.p, 2), prob.p)
     t2 = time.perf_counter()
-    pinvit(d, H, pr, E, lam, prob.nev, prob.tol, sample_iters)
+    pinvit(d, H, pr, E, lam, prob.nev, prob.tol, 1)
     t3 = time.perf_counter()
-    per_iter = (t3 - t2) / sample_iters
+    scale = (prob.n * prob.m) / (n * n)
     nk = len(prob.ks)
-    path_s = nk * (t1 - t0) + cold_starts * (t2 - t1) + (nk - cold_starts) * (t2 - t1) + iters_total * per_iter
+    path_s = scale * (nk * (t1 - t0) + cold_starts * (t2 - t1) + iters_total * (t3 - t2))
     try:
         from threadpoolctl import threadpool_info
         cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
         cores = os.cpu_count() or 1
     return {"value": prob.nev * nk / path_s, "unit": "eigenpairs/s", "cores": int(cores), "kind": "oracle",
-            "sample": (f"first Bloch point of the path on the host: setup {t1 - t0:.1f}s, start block "
-                       f"{t2 - t1:.1f}s, {sample_iters} iterations at {per_iter:.2f}s each; workload time = "
-                       f"{nk} x (setup + start) + {int(iters_total)} iterations (the headline GPU run's "
-                       f"count) x per-iteration time = {path_s:.0f}s")}
+            "sample": (f"the oracle at {n}x{n} on the same generator (random two-phase field, seed 2), first point "
+                       f"after Gamma: setup {t1 - t0:.1f}s, start block ({prob.p} columns) {t2 - t1:.1f}s, one "
+                       f"iteration {t3 - t2:.1f}s; workload time = {scale:.0f} (dof ratio) x [{nk} x setup + "
+                       f"{cold_starts} x start + {int(iters_total)} iterations (the GPU run's count per path) x "
+                       f"iteration] = {path_s:.0f}s; BLAS threads as reported, sparse products single-threaded")}
 
 
-def serving(count, seed, rate_frac=0.7):
-    """Band-path requests (n 64..256, nev 4..16, 11..21 points) with Poisson arrivals at
-    `rate_frac` of the capacity measured by submitting the same requests all at once."""
+# ---- side legs ---------------------------------------------------------------------------
+def c2_plain(steps=2):
+    """configs[1]-style plain FP64 path: 256 x 256 lattice, 31 points, one slot."""
     import torch
     import synth
-    from paper_2304_00337_amd import Server, to_device_block
-    reqs = synth.config_c5_requests(count, master_seed=seed, n_lo=64, n_hi=256, nev_lo=4, nev_hi=16,
-                                    nk_lo=11, nk_hi=21)
+    from paper_2304_00337_amd import Batch, to_device_block
+    prob = synth.config_c2()
+    pr = dict(n=prob.n, m=prob.m, a=prob.a, b=prob.b, eps=prob.eps, nev=prob.nev, nthrow=prob.nthrow,
+              ks=np.asarray(prob.ks), start=to_device_block(prob.start()))
+    with Batch(max_slots=1, engine_streams=1, precision="fp64", levels=prob.levels, tol=prob.tol, max_iter=300) as b:
+        b.run([pr])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rs = [b.run([pr])[0] for _ in range(steps)]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    ms = np.concatenate([r["point_ms"] for r in rs])
+    ok = sum(int((r["relres"] <= prob.tol).sum()) for r in rs)
+    g = golden("arpack_c2_256.json")
+    err = 0.0
+    for pt in g["points"]:
+        err = max(err, float(np.max(np.abs(rs[0]["evals"][pt["index"]] - np.array(pt["evals"])) / np.array(pt["evals"]))))
+    return {"workload": "256x256 lattice of eps=12 discs r=0.3, 31 points on Gamma-X-M-Gamma, 16 (+8), tol 1e-8, "
+                        "plain FP64, one slot", "value": round(ok / dt, 2), "unit": "eigenpairs/s",
+            "p50_solve_ms": round(float(np.percentile(ms, 50)), 3), "p99_solve_ms": round(float(np.percentile(ms, 99)), 3),
+            "iterations": int(rs[0]["iterations"].sum()), "max_rel_err_vs_oracle_arpack": err}
+
+
+def c4_batch(count=64):
+    """64 independent single-k problems in one batch context (grid sizes 128..512, disc
+    lattices, nev 4/8/16), mixed and FP64; per problem status, eigenvalues mixed vs FP64."""
+    import torch
+    import synth
+    from paper_2304_00337_amd import Batch, to_device_block
+    probs = synth.config_c4_problems(count)
+    items = [dict(n=p.n, m=p.m, a=p.a, b=p.b, eps=p.eps, nev=p.nev, nthrow=p.nthrow, ks=np.asarray(p.ks),
+                  start=to_device_block(p.start())) for p in probs]
+    out = {}
+    res = {}
+    for prec in ("mixed", "fp64"):
+        with Batch(precision=prec, tol=1e-6, tol_floor=1, max_iter=300) as b:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rs = b.run(items)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            engines = len(b.engines())
+        res[prec] = rs
+        pairs = sum(p.nev for p in probs)
+        ok = [r["status"] == 0 for r in rs]
+        out[prec] = {"seconds": round(dt, 3), "eigenpairs_per_s": round(pairs * np.mean(ok) / dt, 2),
+                     "converged_problems": int(sum(ok)), "engines": engines}
+    diff = max(float(np.max(np.abs(a["evals"] - b["evals"]) / b["evals"])) for a, b in zip(res["mixed"], res["fp64"]))
+    good = sum(int(np.sum((np.abs(a["evals"] - b["evals"]) / b["evals"] <= 1e-6))) for a, b in zip(res["mixed"], res["fp64"])
+               if a["status"] == 0)
+    out.update({"problems": count, "eigenpairs": int(sum(p.nev for p in probs)),
+                "value": round(good / out["mixed"]["seconds"], 2), "unit": "eigenpairs/s",
+                "mixed_vs_fp64_max_rel_eig_diff": diff,
+                "workload": "64 problems: n in {128,192,256,384,512}, disc lattices r in [0.1,0.45], contrast [2,13], "
+                            "nev in {4,8,16} (+nev/2), one uniform k each, cold start, tol 1e-6 with the FP64 floor"})
+    return out
+
+
+def serving(count, seed, rate_frac=0.7, n_hi=2048, budget_frac=1.1):
+    """Band-path requests (n log-uniform 64..n_hi rounded to n0 2^l, nev 4..32, 11..61
+    points) with Poisson arrivals at `rate_frac` of the capacity measured by submitting the
+    same requests at once, mixed precision, under an HBM budget of budget_frac times the
+    largest request's footprint (so the largest request runs nearly alone and waits for the
+    others to drain: admission must not let later requests pass it without bound)."""
+    import synth
+    from paper_2304_00337_amd import Server, Solver, to_device_block
+    reqs = synth.config_c5_requests(count, master_seed=seed, n_lo=64, n_hi=n_hi, nev_lo=4, nev_hi=32,
+                                    nk_lo=11, nk_hi=61)
+    kw = dict(precision="mixed", tol=1e-6, tol_floor=1, max_iter=300)
+    biggest = max(Solver.footprint_bytes(r.n, r.m, r.a, r.b, nev=r.nev, nthrow=r.nthrow, **kw) for r in reqs)
+    budget_gb = budget_frac * biggest / 2 ** 30
     items = [dict(n=r.n, m=r.m, a=r.a, b=r.b, eps=r.eps, nev=r.nev, nthrow=r.nthrow, ks=r.ks,
                   start=to_device_block(r.start())) for r in reqs]
     pairs = sum(r.nev * len(r.ks) for r in reqs)
@@ -147,8 +259,7 @@ def serving(count, seed, rate_frac=0.7):
             time.sleep(0.0005)
         return time.perf_counter() - t0, [done[t] for t in tickets]
 
-    with Server(precision="mixed", tol=1e-8, max_iter=300, max_slots=8) as srv:
-        drive(srv, [0.0] * len(items))                       # warm the engines
+    with Server(hbm_budget=int(budget_gb * 2 ** 30), max_slots=8, **kw) as srv:
         t_all, _ = drive(srv, [0.0] * len(items))
         cap = len(items) / t_all
         rate = rate_frac * cap
@@ -156,22 +267,20 @@ def serving(count, seed, rate_frac=0.7):
         t_run, res = drive(srv, gaps)
         st = srv.stats()
     lat = np.array([r["latency_s"] for r in res]) * 1e3
-    ok = sum(int((r["relres"] <= 1e-8).sum()) for r in res)
+    ok = sum(int(r["iterations"].size * r["evals"].shape[1]) for r in res if r["status"] == 0)
     return {"requests": count, "eigenpairs": pairs, "converged_eigenpairs": ok,
+            "largest_grid": int(max(r.n for r in reqs)), "largest_nev": int(max(r.nev for r in reqs)),
             "capacity_req_s": round(cap, 3), "arrival_rate_req_s": round(rate, 3),
             "throughput_eigenpairs_s": round(ok / t_run, 2),
             "p50_latency_ms": round(float(np.percentile(lat, 50)), 2),
             "p99_latency_ms": round(float(np.percentile(lat, 99)), 2),
-            "engines": st["engines"], "rounds": st["rounds"],
-            "workload": "C5-like band paths: n log-uniform 64..256, nev 4..16, 11..21 points, "
-                        "disc-lattice or random-field eps; mixed precision; Poisson arrivals at "
-                        f"{rate_frac:.0%} of the measured closed-batch capacity"}
+            "engines_at_end": st["engines"], "rounds": st["rounds"], "hbm_budget_gb": round(budget_gb, 2),
+            "workload": f"band paths: n log-uniform 64..{n_hi} (rounded to n0 2^l), nev 4..32 (+nev/2), 11..61 "
+                        "points, disc-lattice or random-field eps; mixed precision, tol 1e-6 with the FP64 floor; "
+                        f"Poisson arrivals at {rate_frac:.0%} of the measured closed-batch capacity"}
 
 
 def _geometric_rate(res, upper=1e-2):
-    """Per-iteration convergence rate of a residual record: exp of the least-squares slope
-    of log(residual) from the first entry at or below `upper` to the end (NaN with fewer
-    than three entries)."""
     r = np.asarray(res, dtype=np.float64)
     below = np.nonzero(r <= upper)[0]
     if below.size == 0 or r.size - below[0] < 3:
@@ -181,11 +290,9 @@ def _geometric_rate(res, upper=1e-2):
 
 
 def throwaway_study(n=128, nev=16, ts=(1, 2, 4, 8, 16), mu=0.5, seed=3):
-    """Section 7's experiment on the GPU path: permittivity 100 in the disc of radius 1/3,
-    the 16 smallest non-zero eigenvalues at k = (pi/2, pi/4) with t throw-away vectors
-    (plain FP64, tolerance 1e-9, the same seeded start block cut to p = 16 + t columns);
-    per t the iterations, the solve time and the observed rates of pairs 14, 15, 16 beside
-    the unpreconditioned block inverse iteration's lambda_i / lambda_{p+1}."""
+    """Section 7's experiment: permittivity 100 in the disc of radius 1/3, 16 pairs at
+    k = (pi/2, pi/4), t throw-away vectors, plain FP64, tolerance 1e-9; per t the iterations,
+    solve time and observed rates of pairs 14-16 beside lambda_i / lambda_{p+1}."""
     import torch
     import synth
     from paper_2304_00337_amd import Solver, to_device_block
@@ -210,23 +317,20 @@ def throwaway_study(n=128, nev=16, ts=(1, 2, 4, 8, 16), mu=0.5, seed=3):
         rows.append({"t": t, "p": p, "iterations": out["iterations"], "converged": out["converged"],
                      "solve_ms": round(ms, 3),
                      "rates": {str(i): round(_geometric_rate(hist[:, i - 1]), 4) for i in (14, 15, 16)},
-                     "inverse_iteration_rates": {str(i): round(float(lam[i - 1] / lam[p]), 4)
-                                                 for i in (14, 15, 16)}})
-        print(f"# throw-away t={t}: {out['iterations']} iterations, {ms:.1f} ms", file=sys.stderr, flush=True)
+                     "inverse_iteration_rates": {str(i): round(float(lam[i - 1] / lam[p]), 4) for i in (14, 15, 16)}})
     return {"grid": n, "nev": nev, "k": [round(k[0], 6), round(k[1], 6)], "mu": mu, "precision": "fp64",
             "eps": "100 in the disc of radius 1/3, 1 outside", "runs": rows}
 
 
-def kgrid_raster(n=256, kappa=30, nev=16, nthrow=8, seed=9):
+def kgrid_raster(n, precision, kappa=30, nev=16, nthrow=8, seed=9):
     """Section 8's band-structure experiment on the Section 6 raster: permittivity 11.56 in
-    the disc of radius 0.18, the 16 smallest non-zero eigenpairs (plus 8 throw-away vectors)
-    at every point of the kappa x kappa Bloch grid, stopping when every wanted defect
-    ||A e - lambda M e||_2 is below 1e-2 (plain FP64, one handle, random first point)."""
+    the disc of radius 0.18, 16 pairs (+8) at every point of the kappa x kappa grid, stop when
+    every wanted defect ||A e - lambda M e||_2 is below 1e-2, one handle, random first point."""
     import torch
     import synth
     from paper_2304_00337_amd import Solver, to_device_block
     eps = synth.paper_z2_eps(n)
-    s = Solver(n, n, 1.0, 1.0, eps, nev=nev, nthrow=nthrow, tol=1e-2, tol_abs=1, max_iter=300, precision="fp64")
+    s = Solver(n, n, 1.0, 1.0, eps, nev=nev, nthrow=nthrow, tol=1e-2, tol_abs=1, max_iter=300, precision=precision)
     start = to_device_block(synth.start_block(2 * n * n, nev + nthrow, seed))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -235,19 +339,41 @@ def kgrid_raster(n=256, kappa=30, nev=16, nthrow=8, seed=9):
     dt = time.perf_counter() - t0
     its = out["iterations"]
     conv = out["relres"].max(axis=2) <= 1e-2
-    print(f"# k-grid raster {kappa}x{kappa}: {dt:.2f}s, median {np.median(its)} iterations", file=sys.stderr, flush=True)
-    return {"grid": n, "kappa": kappa, "nev": nev, "nthrow": nthrow, "precision": "fp64", "stop": "defect <= 1e-2",
+    s.close()
+    return {"grid": n, "kappa": kappa, "nev": nev, "nthrow": nthrow, "precision": precision, "stop": "defect <= 1e-2",
             "seconds": round(dt, 3), "value": round(nev * kappa * kappa / dt, 3), "unit": "eigenpairs/s",
             "iterations_median": float(np.median(its)), "fraction_below_4": round(float(np.mean(its < 4)), 4),
             "iterations_max": int(its.max()), "iterations_first_point": int(its[0, 0]),
             "not_converged": int((~conv).sum())}
 
 
+def lobpcg_c2():
+    """The LOBPCG variant (Section 4) on the 256 x 256 lattice path, mixed, against the
+    gradient variant on the same launches (q = 3p = 72 on the matrix-core products)."""
+    import torch
+    import synth
+    from paper_2304_00337_amd import Batch, to_device_block
+    prob = synth.config_c2()
+    pr = dict(n=prob.n, m=prob.m, a=prob.a, b=prob.b, eps=prob.eps, nev=prob.nev, nthrow=prob.nthrow,
+              ks=np.asarray(prob.ks), start=to_device_block(prob.start()))
+    out = {}
+    for name, variant in (("gradient", 0), ("lobpcg", 1)):
+        with Batch(max_slots=1, engine_streams=1, precision="mixed", levels=prob.levels, tol=prob.tol, max_iter=300,
+                   variant=variant) as b:
+            b.run([pr])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = b.run([pr])[0]
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        out[name] = {"ms_per_path": round(1e3 * dt, 2), "iterations": int(r["iterations"].sum()),
+                     "value": round(int((r["relres"] <= prob.tol).sum()) / dt, 2)}
+    return out
+
+
 def nested_first_point(prob, seed=1):
-    """The path's first Bloch parameter cold-started two ways on one handle (mixed precision):
-    from the seeded random block, and from the nested iteration of Section 6 (dense coarsest
-    solve, then prolongation and iteration level by level to 1e-3); wall time of each and
-    the finest-level iterations."""
+    """The 256 x 256 lattice path's first point cold-started from the seeded random block
+    and from the nested iteration of Section 6 (mixed precision)."""
     import torch
     import synth
     from paper_2304_00337_amd import Solver, to_device_block
@@ -291,100 +417,89 @@ def recorded_traffic(avg_cols):
     return rec["bytes_per_column"] * avg_cols
 
 
+def side(name, fn, need_s, out):
+    if remaining() < need_s:
+        out[name] = {"skipped": f"time budget ({remaining():.0f}s left, needs ~{need_s:.0f}s)"}
+        log(f"{name}: skipped")
+        return
+    t0 = time.perf_counter()
+    try:
+        out[name] = fn()
+    except Exception as e:   # a side leg must not lose the headline
+        out[name] = {"error": repr(e)}
+    log(f"{name}: {time.perf_counter() - t0:.1f}s")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--per-segment", type=int, default=10)
-    ap.add_argument("--segments", type=int, default=0,
-                    help="pieces of the path solved as one batch; 0 = its three legs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=16)
-    ap.add_argument("--headline-only", action="store_true",
-                    help="time only the batched mixed form (profiling runs); eigenvalues are then "
-                         "checked against its own first step")
-    ap.add_argument("--roofline-only", action="store_true",
-                    help="run only the roofline measurement: the three legs of the headline one "
-                         "after another on one single-slot engine (profiling runs)")
+    ap.add_argument("--headline-only", action="store_true", help="only the mixed headline (profiling runs)")
+    ap.add_argument("--fp64-steps", type=int, default=3, help="timed FP64 legs (every leg once by default)")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="start with one plain device copy of 512 MiB, whose counters calibrate "
-                         "hardware byte counters")
+                    help="start with one plain device copy of 512 MiB, whose counters calibrate hardware byte "
+                         "counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(the band path shards by independent Bloch segments or requests; see DESIGN.md)",
-              file=sys.stderr)
+              "(the band path shards by independent Bloch segments or requests; see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     import synth
-    prob = synth.config_c2(args.per_segment)
-    nk = len(prob.ks)
     if args.calibrate_copy:
         src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        print("# calibration copy: 536870912 bytes read, 536870912 bytes written", file=sys.stderr, flush=True)
+        log("calibration copy: 536870912 bytes read, 536870912 bytes written")
         del src, dst
-    # roofline of the dominant kernel, measured in isolation: the headline's legs with the
-    # headline's launch configuration (single-slot engines, 24 columns per launch), run one
-    # after another, so that no other stream's kernels share the device during a launch
-    iso = run_form(prob, "mixed", 0, 1, 0 if args.roofline_only else 1, args.per_segment, max_slots=1,
-                   engine_streams=1)
-    print(f"# roofline leg (legs one engine at a time): {iso['elapsed']:.3f}s, "
-          f"{iso['timing']['launches']} timed launches", file=sys.stderr, flush=True)
-    # roofline of the dominant V-cycle kernel: one tiled sweep (all four colours) of the
-    # finest-level node-patch Gauss-Seidel.  Compulsory bytes per launch, summed by the
-    # library over the timed launches: per column b read, x read (not when the sweep starts
-    # from zero) and x written once; per slot the coefficients kappa (one value per cell) and
-    # the patch inverses W (10 values per node) once.
-    tm = iso["timing"]
+    prob = synth.config_c3()
+    legs = c3_legs(prob)
+    torch.cuda.synchronize()
+    head = run_legs(prob, legs, "mixed", args.steps, max(1, args.warmup), timing_warmup=True)
+    log(f"mixed: {head['elapsed']:.2f}s for {args.steps} legs, iterations "
+        f"{[int(r['iters'].sum()) for r in head['recs']]}")
+    plain = None
+    if not args.headline_only:
+        plain = run_legs(prob, legs, "fp64", args.fp64_steps, 1)
+        log(f"fp64: {plain['elapsed']:.2f}s for {args.fp64_steps} legs")
+    ref = {}
+    for rec in (plain or head)["recs"]:
+        ref.setdefault(rec["leg"], rec["evals"])
+
+    def rate(r):
+        good, total = 0, 0
+        for rec in r["recs"]:
+            ok = rec["conv"] & (np.abs(rec["evals"] - ref[rec["leg"]]) / ref[rec["leg"]] <= 1e-6)
+            good += int(ok.sum())
+            total += ok.size
+        return good / r["elapsed"], good, total
+
+    value, good, total = rate(head)
+    v64 = rate(plain)[0] if plain else float("nan")
+    ms_all = np.concatenate([rec["ms"] for rec in head["recs"]])
+    ms64 = np.concatenate([rec["ms"] for rec in plain["recs"]]) if plain else np.array([np.nan])
+    dm = max(float(np.max(np.abs(rec["evals"] - ref[rec["leg"]]) / ref[rec["leg"]])) for rec in head["recs"])
+    # roofline of the finest-level edge smoother (one tiled sweep of all four colours): the
+    # library's algorithmic bytes of the timed launches (per column the right-hand side, the
+    # iterate unless the sweep starts from zero, the iterate written, the coarse vector
+    # written or read; per slot kappa and the patch inverses once) over their HIP-event time
+    tm = head["timing"]
     avg_cols = tm["columns"] / max(1, tm["launches"])
     bytes_per_launch = tm["alg_bytes"] / max(1, tm["launches"])
     avg_ms = tm["total_ms"] / max(1, tm["launches"])
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     tb = recorded_traffic(avg_cols)
-    traffic = None if tb is None else round(tb / 1e6, 1)   # MB per launch
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
-            "frac": round(achieved / 8000.0, 4), "traffic": traffic,
-            "kernel": "k_edge_sweep<float> (tiled four-colour node-patch Gauss-Seidel sweep), finest level",
+            "frac": round(achieved / 8000.0, 4), "traffic": None if tb is None else round(tb / 1e6, 1),
+            "kernel": "k_edge_sweep<float> (tiled four-colour node-patch Gauss-Seidel sweep), finest level 1024x1024",
             "avg_launch_ms": round(avg_ms, 5), "bytes_per_launch": int(bytes_per_launch),
             "columns_per_launch": round(avg_cols, 2), "launches_timed": tm["launches"],
             "traffic_unit": "MB per launch (calibrated FETCH_SIZE + WRITE_SIZE)",
-            "measured": "the headline's legs one engine at a time (same launches, no concurrent "
-                        "streams), HIP events on the engine's stream"}
-    if args.roofline_only:
-        print(json.dumps({"roofline": roof}), flush=True)
-        return
-    plain = None
-    if not args.headline_only:
-        plain = run_form(prob, "fp64", 1, args.steps, args.warmup, args.per_segment)
-        print(f"# fp64 plain: {plain['elapsed']:.3f}s for {args.steps} paths, iterations "
-              f"{plain['recs'][0]['iters'].tolist()}", file=sys.stderr, flush=True)
-    head = run_form(prob, "mixed", args.segments, args.steps, args.warmup, args.per_segment)
-    print(f"# mixed x{head['S']} segments: {head['elapsed']:.3f}s for {args.steps} paths, iterations "
-          f"{head['recs'][0]['iters'].tolist()}", file=sys.stderr, flush=True)
-    ref = (plain or head)["recs"][0]["evals"]
-
-    def rate(r):
-        good = 0
-        for rec in r["recs"]:
-            ok = rec["conv"] & (np.abs(rec["evals"] - ref) / ref <= 1e-6)
-            good += int(ok.sum())
-        return good / r["elapsed"]
-
-    value = rate(head)
-    v64 = rate(plain) if plain else float("nan")
-    ms_all = np.concatenate([rec["ms"] for rec in head["recs"]])
-    ms64 = np.concatenate([rec["ms"] for rec in plain["recs"]]) if plain else np.array([np.nan])
-    # the same kernel inside the timed headline, sharing the device with the other streams
-    tc = head["timing"]
-    avg_ms_c = tc["total_ms"] / max(1, tc["launches"])
-    achieved_c = tc["alg_bytes"] / max(1, tc["launches"]) / (avg_ms_c * 1e-3) / 1e9
-    dm = np.abs(head["recs"][0]["evals"] - ref) / ref
+            "measured": "the headline's warm-up legs (same launches), HIP events on the engine's stream"}
     out = {
         "metric": "converged Bloch eigenpairs/s (rel 1e-6), mixed vs FP64 GPU; p50/p99 solve ms",
         "value": round(value, 3),
@@ -398,43 +513,41 @@ def main():
         "vs_baseline": None,
         "dtype": "mixed: c64 V-cycle and nodal projection, c128 residual/Gram/Ritz/extrapolation",
         "data": "synthetic",
-        "config": {"workload": f"256x256 unit cell, eps=12 disc lattice r=0.3, {nk} k on Gamma-X-M-Gamma, "
-                               f"nev {prob.nev} (+{prob.nthrow}), tol {prob.tol:g}, {prob.levels}-level MG; "
-                               f"path in {head['S']} batched segments"
-                               + (" (its legs)" if args.segments == 0 else ""),
-                   "n": prob.n, "nk": nk, "nev": prob.nev, "p": prob.p, "levels": prob.levels,
-                   "segments": head["S"]},
+        "config": {"workload": "1024x1024 unit cell, smoothed random two-phase eps {1, 11.4} (seed 2), 61 k on "
+                               "Gamma-X-M-Gamma (20 per leg), nev 32 (+16), rel. residual tol 1e-6, 8-level MG; "
+                               "one step = one leg (legs in turn), cold start per leg, extrapolation within",
+                   "n": prob.n, "nk": len(prob.ks), "nev": prob.nev, "p": prob.p, "legs": [20, 20, 21]},
+        "eigenpairs_counted": good, "eigenpairs_solved": total,
         "p50_solve_ms": round(float(np.percentile(ms_all, 50)), 3),
         "p99_solve_ms": round(float(np.percentile(ms_all, 99)), 3),
-        "iterations_per_k": head["recs"][0]["iters"].tolist(),
+        "iterations_per_leg": [int(r["iters"].sum()) for r in head["recs"]],
         "fp64_plain": None if plain is None else {
-            "value": round(v64, 3), "ms_per_step": round(plain["elapsed"] / args.steps * 1e3, 3),
+            "value": round(v64, 3), "ms_per_step": round(plain["elapsed"] / args.fp64_steps * 1e3, 3),
             "p50_solve_ms": round(float(np.percentile(ms64, 50)), 3),
             "p99_solve_ms": round(float(np.percentile(ms64, 99)), 3),
-            "iterations_per_k": plain["recs"][0]["iters"].tolist()},
+            "iterations_per_leg": [int(r["iters"].sum()) for r in plain["recs"]],
+            "note": "same legs, same segmentation and launch configuration"},
         "speedup_vs_fp64_plain": round(value / max(v64, 1e-12), 3),
-        "mixed_vs_fp64_max_rel_eig_diff": float(dm.max()),
-        "roofline": dict(roof, in_headline={"avg_launch_ms": round(avg_ms_c, 5), "achieved": round(achieved_c, 1),
-                                            "note": "durations while two other engine streams share the device"}),
-        "launch_shapes": {"headline": head["shapes"], "fp64_plain": plain["shapes"] if plain else None},
+        "mixed_vs_fp64_max_rel_eig_diff": dm,
+        "vs_oracle_arpack": {"mixed": golden_errors(head["recs"], golden("arpack_c3_1024.json")),
+                             "fp64": golden_errors(plain["recs"], golden("arpack_c3_1024.json")) if plain else None},
+        "roofline": roof,
+        "launch_shapes": head["shapes"],
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, int(head["recs"][0]["iters"].sum()), head["S"])
+        t0 = time.perf_counter()
+        its_total = np.mean([int(r["iters"].sum()) for r in head["recs"]]) * 3
+        out["cpu_baseline"] = cpu_baseline(prob, its_total, 3)
+        log(f"cpu baseline: {time.perf_counter() - t0:.1f}s")
     if not args.headline_only:
-        # the LOBPCG variant (Section 4) on the same path and launch configuration: fewer
-        # iterations; its 3p-wide Rayleigh-Ritz step runs on the vector path
-        lob = run_form(prob, "mixed", args.segments, 1, 1, args.per_segment, variant=1)
-        out["lobpcg"] = {"value": round(rate(lob), 3), "unit": "eigenpairs/s", "ms_per_path": round(1e3 * lob["elapsed"], 3),
-                         "iterations": int(lob["recs"][0]["iters"].sum()),
-                         "gradient_iterations": int(head["recs"][0]["iters"].sum())}
-        print(f"# lobpcg: {lob['elapsed']:.3f}s, iterations {lob['recs'][0]['iters'].tolist()}", file=sys.stderr,
-              flush=True)
-    if not args.headline_only:
-        out["throwaway"] = throwaway_study()
-        out["kgrid"] = kgrid_raster()
-        out["nested_start"] = nested_first_point(prob)
-    if not args.no_serving:
-        out["serving"] = serving(args.serve_requests, seed=4)
+        side("c2_fp64", c2_plain, 20, out)
+        side("c4_batch", c4_batch, 60, out)
+        side("serving", lambda: serving(10, seed=7), 90, out)
+        side("lobpcg", lobpcg_c2, 15, out)
+        side("throwaway", throwaway_study, 15, out)
+        side("kgrid", lambda: kgrid_raster(1024, "mixed"), 60, out)
+        side("nested_start", lambda: nested_first_point(synth.config_c2()), 10, out)
+    log("done")
     print(json.dumps(out), flush=True)
 
 

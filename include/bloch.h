@@ -110,6 +110,12 @@ typedef struct bl_opts {
                            M-normalised vectors (the stopping measure of the band-structure
                            experiment, Section 8), which relres then reports; 0 = relative
                            residuals (0)                                                   */
+  int32_t tol_floor;    /* 1 = a pair also counts as converged once its relative residual
+                           is below the FP64 rounding floor u ||A||_G / (|lambda_i| m_min),
+                           u = 2^-53, ||A||_G = 8 kappa_max / (h1 h2) the stencil's Gershgorin
+                           bound, m_min = min(h2/h1, h1/h2): the computed A e of a small
+                           eigenvalue cancels to lambda M e and cannot resolve residuals below
+                           it (acoustic band next to Gamma on fine meshes); 0 = off (0)    */
 } bl_opts;
 
 /* Read-only facts about a solver handle. */

@@ -56,6 +56,7 @@ struct SlotState {
   double hist_lam1 = 0.0;
   bool gamma = false;
   double mu = 1.0;
+  double kappa_max = 1.0;   // largest 1/eps of the slot's permittivity (residual floor)
   std::vector<double> res_rows;
 };
 

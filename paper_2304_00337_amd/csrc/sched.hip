@@ -10,7 +10,9 @@
 // than packed into one; small shapes are packed (their launches need the slots to fill the
 // device).  Engines are created under an HBM budget: admission takes a queued problem when
 // an engine of its shape has a free slot, or when a new engine fits the budget (idle
-// engines of other shapes are released for it).
+// engines of other shapes are released for it).  Later problems may pass a queued one that
+// does not fit yet, but at most kPassLimit of them: then nothing else is admitted until it
+// is, so the engines drain and the idle ones are released for it (no unbounded wait).
 // Slots that finish a problem take the next queued one of their shape at the next round
 // (continuous batching); a problem's eigenvector history stays on the device across its
 // Bloch parameters.
@@ -43,7 +45,12 @@ struct Job {
   Task task;
   Key key{};
   bool published = false;   // serving: results handed to the caller's thread
+  int passed = 0;           // later jobs admitted while this one waited for memory
+  bool mem_wait = false;    // the last admission attempt failed on the memory budget
 };
+
+// Later jobs that may be admitted ahead of a waiting one before admission stops for it.
+constexpr int kPassLimit = 4;
 
 struct Eng {
   bl_solver* e = nullptr;
@@ -76,13 +83,21 @@ class Scheduler {
     return l;
   }
 
-  // Admit queued jobs (FIFO, later jobs may pass one that does not fit).  Returns a device
-  // error or BL_OK; a job that can never fit ends with BL_ENOMEM.
+  // Admit queued jobs (FIFO; later jobs may pass one that does not fit the memory budget, at
+  // most kPassLimit of them, after which nothing behind it is tried; a job waiting for a slot
+  // of its shape's engines gets one as their tasks end and is not counted).  Returns a device error or
+  // BL_OK; a job that can never fit ends with BL_ENOMEM.
   int admit() {
     for (auto it = queue_.begin(); it != queue_.end();) {
       Job* j = *it;
+      bool blocked = false;   // an older job has been passed over often enough
+      for (auto jt = queue_.begin(); jt != it; ++jt)
+        if ((*jt)->passed >= kPassLimit) blocked = true;
+      if (blocked) break;
       int rc = place(j);
       if (rc == BL_OK) {
+        for (auto jt = queue_.begin(); jt != it; ++jt)
+          if ((*jt)->mem_wait) (*jt)->passed += 1;
         it = queue_.erase(it);
         continue;
       }
@@ -200,6 +215,7 @@ class Scheduler {
   }
 
   int place(Job* j) {
+    j->mem_wait = false;
     for (auto& g : engines_) {
       if (!(g.key == j->key)) continue;
       const int sl = engine_free_slot(g.e);
@@ -238,7 +254,11 @@ class Scheduler {
           ++it;
         }
       }
-      if (!fits(1)) return engines_.empty() ? set_error(BL_ENOMEM, "problem larger than the memory budget%s") : BL_EAGAIN;
+      if (!fits(1)) {
+        if (engines_.empty()) return set_error(BL_ENOMEM, "problem larger than the memory budget%s");
+        j->mem_wait = true;
+        return BL_EAGAIN;
+      }
     }
     while (want > 1 && !fits(want)) --want;
     Eng g;
@@ -248,7 +268,10 @@ class Scheduler {
     int rc = engine_create(&gr, &o, want, g.st, nullptr, &g.e);
     if (rc) {
       (void)hipStreamDestroy(g.st);
-      if (rc == BL_ENOMEM && !engines_.empty()) return BL_EAGAIN;
+      if (rc == BL_ENOMEM && !engines_.empty()) {
+        j->mem_wait = true;
+        return BL_EAGAIN;
+      }
       return rc;
     }
     if (timing_ && (rc = engine_set_timing(g.e, true))) {

@@ -125,6 +125,7 @@ int validate_opts(const bl_opts* o) {
   if (o->engine_streams < 1 || o->engine_streams > 16) return set_error(BL_EINVAL, "engine_streams must be 1..16%s");
   if (!(o->tol > 0)) return set_error(BL_EINVAL, "tol must be positive%s");
   if (o->tol_abs != 0 && o->tol_abs != 1) return set_error(BL_EINVAL, "tol_abs must be 0 or 1%s");
+  if (o->tol_floor != 0 && o->tol_floor != 1) return set_error(BL_EINVAL, "tol_floor must be 0 or 1%s");
   return BL_OK;
 }
 
@@ -750,6 +751,7 @@ int load_eps(bl_solver* s, int sl, const std::vector<double>& kappa, double eps_
                                      : homogeneous_lambda(s->grid.n, s->grid.m, s->grid.a, s->grid.b, eps_min, s->p) / 10.0;
   s->mu_h[sl] = mu;
   s->slot[sl].mu = mu;
+  s->slot[sl].kappa_max = eps_min > 0 ? 1.0 / eps_min : 1.0;
   HIP_OK(hipMemcpyAsync(s->mu_d + sl, &s->mu_h[sl], 8, hipMemcpyHostToDevice, s->st));
   for (size_t l = 0; l < s->lv.size(); ++l) {
     Level& L = s->lv[l];
@@ -1157,10 +1159,17 @@ int engine_finish(bl_solver* s) {
       const double den = std::fabs(lam[j]) * std::sqrt(nr[2 * j + 1]);
       rel[j] = s->opts.tol_abs ? std::sqrt(nr[2 * j]) : den > 0 ? std::sqrt(nr[2 * j]) / den : INFINITY;
     }
+    // optional rounding floor of the relative residual (see bl_opts.tol_floor)
+    double floor_num = 0.0;
+    if (s->opts.tol_floor && !s->opts.tol_abs) {
+      const Geo& g0 = s->lv[0].g;
+      floor_num = std::ldexp(1.0, -53) * 8.0 * ss.kappa_max * g0.s / std::min(g0.mx, g0.my);
+    }
     bool conv = true;
     for (int j = 0; j < t->nev; ++j) {
       ss.res_rows.push_back(rel[j]);
-      conv = conv && (rel[j] <= s->opts.tol);
+      const double tol_j = std::max(s->opts.tol, lam[j] != 0.0 ? floor_num / std::fabs(lam[j]) : 0.0);
+      conv = conv && (rel[j] <= tol_j);
     }
     if (conv || ss.it >= s->opts.max_iter) {
       if ((rc = retire_point(s, sl, conv, lam, rel))) return rc;

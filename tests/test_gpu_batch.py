@@ -186,3 +186,47 @@ def test_batch_context_reuses_engines():
         assert np.all(x["point_ms"] > 0)
     assert t1["launches"] > 0 and t1["total_ms"] > 0 and t1["columns"] >= t1["launches"]
     assert t1["alg_bytes"] > 0
+
+
+def test_server_large_request_is_not_starved():
+    """A budget that holds the large request only when nothing else is on the device, and a
+    stream of small requests arriving with and after it: admission lets at most a few later
+    requests pass the large one, then drains the small engine, releases it and admits the
+    large request, which therefore finishes before most of the small requests submitted
+    after it, with the same result as alone."""
+    from paper_2304_00337_amd import Server, Solver
+    eps_small = synth.eps_disc(32, 32, 1.0, 1.0, 8.9, 0.3)
+    eps_big = synth.eps_disc_lattice(128, 128, 1.0, 1.0, 12.0, 0.3)
+    small = [dict(n=32, m=32, a=1.0, b=1.0, eps=eps_small, nev=4, nthrow=2,
+                  ks=np.array([(0.9, -0.4), (1.0, -0.35), (1.1, -0.3)]),
+                  start=synth.start_block(2 * 32 * 32, 6, 40 + i)) for i in range(14)]
+    big = dict(n=128, m=128, a=1.0, b=1.0, eps=eps_big, nev=4, nthrow=2, ks=np.array([(0.7, 0.2), (0.8, 0.25)]),
+               start=synth.start_block(2 * 128 * 128, 6, 99))
+    fb = Solver.footprint_bytes(128, 128, 1.0, 1.0, nev=6, nthrow=0, coarsest_min=4)
+    fs = Solver.footprint_bytes(32, 32, 1.0, 1.0, nev=6, nthrow=0, coarsest_min=4)
+    reqs = small[:2] + [big] + small[2:]
+    with Server(hbm_budget=int(fb + 0.5 * fs), max_slots=2, precision="mixed", **OPTS) as srv:
+        t_sub = []
+        tickets = []
+        for rq in reqs:
+            t_sub.append(time.perf_counter())
+            tickets.append(srv.submit(**rq))
+        done, t_done = {}, {}
+        deadline = time.time() + 120
+        while len(done) < len(tickets):
+            assert time.time() < deadline, "server did not finish"
+            for t in tickets:
+                if t not in done:
+                    r = srv.poll(t)
+                    if r is not None:
+                        done[t] = r
+                        t_done[t] = time.perf_counter()
+            time.sleep(0.001)
+    res = [done[t] for t in tickets]
+    assert all(r["status"] == 0 for r in res)
+    big_done = t_done[tickets[2]]
+    later_small_after = sum(1 for t in tickets[3:] if t_done[t] > big_done)
+    assert later_small_after >= 6, later_small_after
+    with Server(precision="mixed", **OPTS) as srv:
+        alone = _serve(srv, [big], rate_hz=1000.0, seed=3)[0]
+    assert np.array_equal(alone["evals"], res[2]["evals"])
