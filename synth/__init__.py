@@ -19,7 +19,7 @@ import numpy as np
 
 __all__ = [
     "cell_centres", "eps_disc", "eps_disc_lattice", "eps_random_field", "start_block",
-    "path_gxmg", "uniform_k", "Problem", "config_c1", "config_c2", "config_c3",
+    "path_gxmg", "uniform_k", "Problem", "config_c1", "config_c2", "config_c3", "config_c4_small",
     "config_c4_problems", "config_c5_requests", "paper_z2_eps", "paper_z1_eps",
 ]
 
@@ -202,6 +202,25 @@ def config_c4_problems(count: int = 64, master_seed: int = 3) -> list:
         seed = int(rng.integers(0, 2 ** 31 - 1))
         out.append(Problem(n, n, 1.0, 1.0, eps, np.array([k]), nev, nev // 2, seed,
                            tol=1e-8, name=f"c4-{i}", meta={"radius": r, "contrast": c}))
+    return out
+
+
+def config_c4_small() -> list:
+    """A reduced batch of the C4 kind for parity tests against the oracle: six single-k
+    problems, n in {64, 96, 128} and nev in {4, 8, 16} (each n with two nev), disc lattices
+    with seeded radius and contrast, k uniform in the Brillouin zone."""
+    ss = np.random.SeedSequence(31)
+    out = []
+    specs = [(64, 4), (96, 8), (128, 16), (64, 16), (96, 4), (128, 8)]
+    for i, (child, (n, nev)) in enumerate(zip(ss.spawn(len(specs)), specs)):
+        rng = np.random.default_rng(child)
+        r = float(rng.uniform(0.1, 0.45))
+        c = float(rng.uniform(2.0, 13.0))
+        k = uniform_k(rng)
+        eps = eps_disc_lattice(n, n, 1.0, 1.0, c, r)
+        seed = int(rng.integers(0, 2 ** 31 - 1))
+        out.append(Problem(n, n, 1.0, 1.0, eps, np.array([k]), nev, nev // 2, seed,
+                           tol=1e-8, name=f"c4small-{i}", meta={"radius": r, "contrast": c}))
     return out
 
 

@@ -4,12 +4,13 @@ Gamma-X-M-Gamma path with 10 intervals per leg (the first point after Gamma, X, 
 last point before Gamma); with --z2, of the band-structure experiment's cell (eps = 11.56 in
 the disc of radius 0.18, 16 pairs) at 256 x 256 on its kappa = 30 raster at the two points
 next to Gamma, (i, j) = (14, 14) and (15, 14); with --c3, of the 1024 x 1024 random
-two-phase workload (32 pairs) at its first point after Gamma and at X.  Source:
+two-phase workload (32 pairs) at its first point after Gamma and at X; with --c4small, of
+the six problems of synth.config_c4_small (n 64..128, nev 4..16).  Source:
 oracle.dense.gradient_free_eigs (ARPACK on the pencil restricted to the complement of the
 null space by exact sparse projections; the kernel cluster of dimension nm would defeat the
 plain shift-invert certificate).  Calls only oracle/ and the input generators.
 
-Run from the repository root:  python tests/golden/make_arpack.py [--z2 | --c3]
+Run from the repository root:  python tests/golden/make_arpack.py [--z2 | --c3 | --c4small]
 """
 import json
 import os
@@ -43,7 +44,19 @@ def run(prob, idx, count):
 
 def main():
     here = os.path.dirname(os.path.abspath(__file__))
-    if "--z2" in sys.argv:
+    if "--c4small" in sys.argv:
+        pts = []
+        for i, prob in enumerate(synth.config_c4_small()):
+            k1, k2 = (float(v) for v in prob.ks[0])
+            d = fem.Discretization(prob.n, prob.m, prob.a, prob.b, prob.eps, k1, k2)
+            lam, _ = gradient_free_eigs(d, prob.nev)
+            pts.append({"index": i, "n": prob.n, "nev": prob.nev, "k": [k1, k2], "evals": [float(x) for x in lam]})
+            print(f"problem {i} n={prob.n} nev={prob.nev} lam1={lam[0]:.10g}", flush=True)
+        out = {"workload": "synth.config_c4_small: six single-k disc-lattice problems, n 64..128, nev 4..16",
+               "source": "oracle.dense.gradient_free_eigs (ARPACK on the complement of the null space)",
+               "points": pts}
+        name = "arpack_c4small.json"
+    elif "--z2" in sys.argv:
         n = 256
         prob = synth.Problem(n, n, 1.0, 1.0, synth.paper_z2_eps(n),
                              np.array([raster_k(30, 14, 14), raster_k(30, 15, 14)]), 16, 8, 5)

@@ -230,3 +230,44 @@ def test_server_large_request_is_not_starved():
     with Server(precision="mixed", **OPTS) as srv:
         alone = _serve(srv, [big], rate_hz=1000.0, seed=3)[0]
     assert np.array_equal(alone["evals"], res[2]["evals"])
+
+
+def test_reduced_mixed_batch_against_oracle():
+    """A reduced batch of the 64-problem kind in one batch context: n in {64, 96, 128} and
+    nev in {4, 8, 16}, mixed precision, every problem converged and its eigenvalues within
+    1e-6 of the oracle's ARPACK values (tests/golden/arpack_c4small.json); the plain FP64
+    batch within 1e-9."""
+    import json
+    import os
+    from paper_2304_00337_amd import batch_solve
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "arpack_c4small.json")) as f:
+        gold = json.load(f)["points"]
+    probs = synth.config_c4_small()
+    items = [dict(n=p.n, m=p.m, a=p.a, b=p.b, eps=p.eps, nev=p.nev, nthrow=p.nthrow, ks=np.asarray(p.ks),
+                  start=p.start()) for p in probs]
+    for precision, tol in (("mixed", 1e-6), ("fp64", 1e-9)):
+        res = batch_solve(items, precision=precision, tol=1e-8, max_iter=300)
+        for p, r, g in zip(probs, res, gold):
+            assert r["status"] == 0, (precision, p.n, p.nev)
+            ref = np.array(g["evals"])
+            err = np.max(np.abs(r["evals"][0] - ref) / ref)
+            assert err <= tol, (precision, p.n, p.nev, err)
+
+
+def test_server_alone_equals_in_mix_large_request():
+    """A 512 x 512 request served among smaller ones gives the same result, to the last
+    bit, as when it is served alone."""
+    from paper_2304_00337_amd import Server
+    probs = _problems()
+    reqs = [dict(n=p["n"], m=p["m"], a=1.0, b=1.0, eps=p["eps"], nev=p["nev"], nthrow=p["nthrow"],
+                 ks=p["ks"], start=p["start"]) for p in probs]
+    big = dict(n=512, m=512, a=1.0, b=1.0, eps=synth.eps_random_field(512, 512, 1.0, 1.0, 21), nev=8, nthrow=4,
+               ks=np.array([(0.6, 0.3), (0.7, 0.35), (0.8, 0.4)]), start=synth.start_block(2 * 512 * 512, 12, 77))
+    mix = reqs[:2] + [big] + reqs[2:]
+    with Server(max_slots=4, precision="mixed", **OPTS) as srv:
+        got = _serve(srv, mix, rate_hz=200.0, seed=5)
+    assert all(r["status"] == 0 for r in got)
+    with Server(precision="mixed", **OPTS) as srv:
+        alone = _serve(srv, [big], rate_hz=1000.0, seed=6)[0]
+    assert np.array_equal(alone["evals"], got[2]["evals"])
+    assert np.array_equal(alone["iterations"], got[2]["iterations"])
