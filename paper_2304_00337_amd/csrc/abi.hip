@@ -3,6 +3,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 namespace bl {
@@ -468,6 +470,15 @@ int bl_ritz_small(bl_solver* s, const double* G, const double* H, int32_t q, int
   if (e == hipSuccess) e = hipMemcpyAsync(&cnt, dc.p, sizeof(int), hipMemcpyDeviceToHost, s->st);
   if (e == hipSuccess) e = hipStreamSynchronize(s->st);
   if (e != hipSuccess) return set_error(BL_EHIP, "HIP error: %s", hipGetErrorString(e));
+  if (std::getenv("BL_DEBUG")) {
+    // the kernel's phase stamps (wall clock, 100 MHz): Cholesky, Z, orthonormality repair,
+    // reduction and tridiagonalisation, eigenvalues, eigenvectors, back-transformation
+    double st[10] = {};
+    if (hipMemcpy(st, dW.d() + 10 * (size_t)q * q + 8 * q + 1, sizeof(st), hipMemcpyDeviceToHost) == hipSuccess)
+      std::fprintf(stderr, "bloch: ritz q=%d want=%d phases us: %.1f %.1f %.1f %.1f %.1f %.1f %.1f total %.1f\n", q,
+                   want, (st[1] - st[0]) / 100, (st[2] - st[1]) / 100, (st[3] - st[2]) / 100, (st[4] - st[3]) / 100,
+                   (st[9] - st[4]) / 100, (st[5] - st[9]) / 100, (st[6] - st[5]) / 100, (st[6] - st[0]) / 100);
+  }
   int rc = check_hip();
   return rc ? rc : cnt;
 }
