@@ -116,6 +116,14 @@ typedef struct bl_opts {
                            bound, m_min = min(h2/h1, h1/h2): the computed A e of a small
                            eigenvalue cancels to lambda M e and cannot resolve residuals below
                            it (acoustic band next to Gamma on fine meshes); 0 = off (0)    */
+  int32_t nested_start; /* 1 = a problem's first Bloch parameter without a start block starts
+                           from nested iteration (Section 6): the coarsest level's p smallest
+                           non-zero eigenpairs by a dense solve, then prolongation and block
+                           iteration to nested_tol on every level up to the finest, all in the
+                           engine's device buffers; needs a coarsest level of at most 255
+                           edges (checked at creation).  0 = the block in the slot (0)      */
+  double nested_tol;    /* relative residual to which the levels below the finest are
+                           iterated in the nested start; 0 selects 1e-3                    */
 } bl_opts;
 
 /* Read-only facts about a solver handle. */
@@ -159,7 +167,8 @@ int bl_get_info(const bl_solver* s, bl_info* out);
  * start_dev: device FP64 planar block of p = nev+nthrow columns of length N_e used as the
  *   starting block (it is null-space projected, M-orthonormalised and Ritz-rotated), or
  *   NULL to extrapolate from the eigenvector blocks of the previously solved parameters
- *   kept in the handle (Section 6); BL_ESTATE if NULL and no history exists.
+ *   kept in the handle (Section 6); if NULL and no history exists: the nested start when
+ *   opts.nested_start is set, else BL_ESTATE.
  * evals (host, nev), relres (host, nev): results; iters (host, 1): iterations used.
  * evecs_dev: NULL or device FP64 planar block of nev columns receiving M-orthonormal
  *   eigenvectors (each column's phase is arbitrary).
@@ -201,8 +210,9 @@ int bl_solve_kgrid(bl_solver* s, int32_t kappa, const void* start_dev, double* e
 /* Nested iteration for a first Bloch parameter (Section 6): the p smallest non-zero
  * eigenpairs of the coarsest level's pencil by a direct (dense) solve, then level by level
  * up the hierarchy: the block is prolongated to the next finer level and, below the finest
- * level, iterated there (on a temporary handle for that level's mesh, with the same
- * options, the handle's mu and relative tolerance tol_levels) before moving on.  out_dev
+ * level, iterated there (that level taken as the finest of its own hierarchy, with the
+ * handle's options and mu, to the relative residual tol_levels) before moving on, all in
+ * the handle's own device buffers (the same path as the nested_start option).  out_dev
  * (device FP64 planar block of p columns of length N_e) receives the block prolongated to
  * the finest level: the start block of bl_solve_k / bl_solve_path / a batch problem.
  * level_iters: NULL or host array of `levels` entries receiving the iterations per level
@@ -325,7 +335,8 @@ typedef struct bl_problem {
   int32_t nk;             /* Bloch parameters on the path, >= 1                              */
   int32_t reserved0;
   const double* ks;       /* host, 2*nk: k1, k2 per point, solved in order with extrapolation */
-  const void* start_dev;  /* device FP64 planar block of p columns of length N_e (required)  */
+  const void* start_dev;  /* device FP64 planar block of p columns of length N_e; NULL only
+                             with opts.nested_start (then the nested start)                 */
   double* evals;          /* host out, nk*nev (row t = point t)                              */
   double* relres;         /* host out, nk*nev                                                */
   int32_t* iters;         /* host out, nk                                                    */
@@ -376,7 +387,8 @@ typedef struct bl_request {
   const double* ks;       /* host, 2*nk (copied)                                             */
   const void* start_dev;  /* device FP64 planar block of p columns, written completely
                              before the call (the server reads it on a stream of its own);
-                             must stay valid and unchanged until the result is polled       */
+                             must stay valid and unchanged until the result is polled; NULL
+                             only with opts.nested_start (then the nested start)           */
 } bl_request;
 
 typedef struct bl_request_info {

@@ -101,7 +101,7 @@ def _marshal_problems(problems, want_last_vectors):
         p, ne = nev + nthrow, 2 * n * m
         eps = np.ascontiguousarray(pr["eps"], dtype=np.float64)
         ks = np.ascontiguousarray(pr["ks"], dtype=np.float64).reshape(-1, 2)
-        st = _start_block(pr["start"], p, ne)
+        st = _start_block(pr["start"], p, ne) if pr.get("start") is not None else None
         nk = ks.shape[0]
         ev, rr, pm = np.zeros((nk, nev)), np.zeros((nk, nev)), np.zeros(nk)
         its = np.zeros(nk, dtype=np.int32)
@@ -112,7 +112,7 @@ def _marshal_problems(problems, want_last_vectors):
         b.eps = _dptr(eps)
         b.nev, b.nthrow, b.nk = nev, nthrow, nk
         b.ks = _dptr(ks)
-        b.start_dev = st.data_ptr()
+        b.start_dev = st.data_ptr() if st is not None else None
         b.evals, b.relres, b.point_ms = _dptr(ev), _dptr(rr), _dptr(pm)
         b.iters = its.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
         b.evecs_dev = vec.data_ptr() if vec is not None else None
@@ -237,13 +237,13 @@ class Server:
         """Queue a request; returns its ticket.  The start block is kept alive until polled."""
         eps = np.ascontiguousarray(eps, dtype=np.float64)
         ks = np.ascontiguousarray(ks, dtype=np.float64).reshape(-1, 2)
-        st = _start_block(start, int(nev) + int(nthrow), 2 * int(n) * int(m))
+        st = _start_block(start, int(nev) + int(nthrow), 2 * int(n) * int(m)) if start is not None else None
         r = BlRequest()
         r.grid = BlGrid(int(n), int(m), float(a), float(b))
         r.eps = _dptr(eps)
         r.nev, r.nthrow, r.nk = int(nev), int(nthrow), ks.shape[0]
         r.ks = _dptr(ks)
-        r.start_dev = st.data_ptr()
+        r.start_dev = st.data_ptr() if st is not None else None
         _torch().cuda.current_stream().synchronize()   # the server reads it on its own stream
         t = ctypes.c_uint64()
         check(self.lib.bl_server_submit(self.h, ctypes.byref(r), ctypes.byref(t)), "bl_server_submit")

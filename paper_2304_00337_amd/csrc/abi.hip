@@ -277,117 +277,23 @@ int bl_solve_kgrid(bl_solver* s, int32_t kappa, const void* start_dev, double* e
 }
 
 int bl_nested_start(bl_solver* s, double k1, double k2, double tol_levels, void* out_dev, int32_t* level_iters) {
-  if (!s || !out_dev || !(tol_levels > 0)) return set_error(BL_EINVAL, "invalid nested-start arguments%s");
-  const int L = (int)s->lv.size(), lc = L - 1, p = s->p;
-  const Geo gc = s->lv[lc].g;
-  const int q = (int)gc.ne;
-  if (q > 255) return set_error(BL_EINVAL, "the coarsest mesh has more than 255 edges%s");
+  if (!s || !out_dev || !(tol_levels > 0) || !(tol_levels < 1)) return set_error(BL_EINVAL, "invalid nested-start arguments%s");
+  const int L = (int)s->lv.size();
   if (level_iters)
     for (int l = 0; l < L; ++l) level_iters[l] = 0;
   int rc = engine_set_k0(s, k1, k2);
   if (rc) return rc;
-  // kappa of every level on the host (the hierarchy's 2x2 means), for the per-level handles
-  std::vector<std::vector<double>> kap(L);
-  for (int l = 0; l < L; ++l) {
-    kap[l].resize((size_t)s->lv[l].g.nm);
-    HIP_OK(hipMemcpyAsync(kap[l].data(), s->lv[l].kappa64, kap[l].size() * 8, hipMemcpyDeviceToHost, s->st));
-  }
-  // coarsest level: the dense pencil (A_c, M_c) from the operators applied to the unit vectors
-  const size_t colc = (size_t)2 * q;
-  std::vector<double> X((size_t)q * colc, 0.0), AX(X.size()), MX(X.size());
-  for (int j = 0; j < q; ++j) X[(size_t)j * colc + j] = 1.0;
-  double *dX = nullptr, *dAX = nullptr, *dMX = nullptr;
-  auto release = [&]() {
-    (void)hipFree(dX);
-    (void)hipFree(dAX);
-    (void)hipFree(dMX);
-  };
-  if (hipMalloc((void**)&dX, X.size() * 8) != hipSuccess || hipMalloc((void**)&dAX, X.size() * 8) != hipSuccess ||
-      hipMalloc((void**)&dMX, X.size() * 8) != hipSuccess) {
-    release();
-    return set_error(BL_ENOMEM, "no device memory for the coarsest pencil%s");
-  }
-  rc = hipMemcpyAsync(dX, X.data(), X.size() * 8, hipMemcpyHostToDevice, s->st) == hipSuccess ? BL_OK : BL_EHIP;
-  if (!rc) rc = engine_apply(s, BL_OP_A, lc, 0, q, dX, nullptr, dAX);
-  if (!rc) rc = engine_apply(s, BL_OP_M, lc, 0, q, dX, nullptr, dMX);
-  if (!rc && (hipMemcpy(AX.data(), dAX, X.size() * 8, hipMemcpyDeviceToHost) != hipSuccess ||
-              hipMemcpy(MX.data(), dMX, X.size() * 8, hipMemcpyDeviceToHost) != hipSuccess))
-    rc = set_error(BL_EHIP, "pencil copy failed%s");
-  release();
+  const double saved = s->opts.nested_tol;
+  s->opts.nested_tol = tol_levels;
+  std::vector<int> its;
+  rc = engine_nested_start(s, 0, k1, k2, s->opts.nev, its);
+  s->opts.nested_tol = saved;
   if (rc) return rc;
-  std::vector<double> G((size_t)q * q * 2), H(G.size());
-  double hmax = 0.0;
-  for (int i = 0; i < q; ++i)
-    for (int j = 0; j < q; ++j) {
-      const size_t o = ((size_t)i * q + j) * 2;
-      G[o] = MX[(size_t)j * colc + i];
-      G[o + 1] = MX[(size_t)j * colc + q + i];
-      H[o] = AX[(size_t)j * colc + i];
-      H[o + 1] = AX[(size_t)j * colc + q + i];
-      if (i == j) hmax = std::max(hmax, H[o] / G[o]);
-    }
-  // the gradients (and at k = 0 the constant fields) are the exact zeros of the pencil
-  std::vector<double> theta(p), Y((size_t)q * p * 2);
-  const int found = bl_ritz_small(s, G.data(), H.data(), q, p, 1e-9 * hmax, theta.data(), Y.data());
-  if (found < 0) return found;
-  if (found < p) return set_error(BL_ENOCONV, "the coarsest mesh has fewer than p non-zero eigenvalues%s");
-  // the block on the current level (planar FP64, p columns)
-  std::vector<double> Eh((size_t)p * colc);
-  for (int j = 0; j < p; ++j)
-    for (int i = 0; i < q; ++i) {
-      Eh[(size_t)j * colc + i] = Y[((size_t)i * p + j) * 2];
-      Eh[(size_t)j * colc + q + i] = Y[((size_t)i * p + j) * 2 + 1];
-    }
-  double* cur = nullptr;
-  if (hipMalloc((void**)&cur, Eh.size() * 8) != hipSuccess) return set_error(BL_ENOMEM, "no device memory%s");
-  if (hipMemcpy(cur, Eh.data(), Eh.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
-    (void)hipFree(cur);
-    return set_error(BL_EHIP, "block copy failed%s");
-  }
-  // levels lc-1 .. 0: prolongate, and below the finest level iterate to tol_levels
-  for (int l = lc - 1; l >= 0 && !rc; --l) {
-    const Geo& gl = s->lv[l].g;
-    const size_t blk = (size_t)p * 2 * gl.ne;
-    bl_solver* h = s;
-    if (l > 0) {
-      bl_opts o = s->opts;
-      o.levels = L - l;
-      o.autotune = 0;
-      o.tol = tol_levels;
-      o.tol_abs = 0;
-      o.mu = s->mu_h[0];
-      std::vector<double> eps(kap[l].size());
-      for (size_t c = 0; c < eps.size(); ++c) eps[c] = 1.0 / kap[l][c];
-      const bl_grid gr{gl.n, gl.m, s->grid.a, s->grid.b};
-      rc = engine_create(&gr, &o, 1, s->st, eps.data(), &h);
-      if (rc) break;
-      rc = engine_set_k0(h, k1, k2);
-    }
-    double* next = nullptr;
-    if (!rc && l > 0 && hipMalloc((void**)&next, blk * 8) != hipSuccess)
-      rc = set_error(BL_ENOMEM, "no device memory%s");
-    if (!rc) rc = engine_apply(h, BL_OP_EDGE_PROLONG, 0, 0, p, cur, nullptr, l > 0 ? (void*)next : out_dev);
-    if (!rc && l > 0) {
-      Task t;
-      t.ks = {k1, k2};
-      t.start_dev = next;
-      t.nev = h->opts.nev;
-      const int r = run_task(h, t);
-      if (r != BL_OK && r != BL_ENOCONV) rc = r;
-      if (!rc) {
-        if (level_iters) level_iters[l] = t.iters[0];
-        // the iterated block (slot 0 of the handle's iterate) is the next level's input
-        if (hipMemcpyAsync(next, h->E, blk * 8, hipMemcpyDeviceToDevice, h->st) != hipSuccess ||
-            hipStreamSynchronize(h->st) != hipSuccess)
-          rc = set_error(BL_EHIP, "block copy failed%s");
-      }
-    }
-    if (h != s) engine_destroy(h);
-    (void)hipFree(cur);
-    cur = next;
-  }
-  (void)hipFree(cur);
-  return rc;
+  HIP_OK(hipMemcpyAsync(out_dev, s->E, (size_t)s->p * 2 * s->lv[0].g.ne * 8, hipMemcpyDeviceToDevice, s->st));
+  HIP_OK(hipStreamSynchronize(s->st));
+  if (level_iters)
+    for (int l = 0; l < L; ++l) level_iters[l] = its[l];
+  return check_hip();
 }
 
 int bl_reset_history(bl_solver* s) {

@@ -37,6 +37,7 @@ struct Task {
   std::vector<int32_t> iters;          // nk
   std::vector<double> res_hist;        // nev per iteration of the last point
   std::vector<double> t_points;        // host time at which each point was retired
+  std::vector<int> nested_its;         // nested start: iterations per level (finest first)
   int status = BL_OK;
   std::string message;
   bool finished = false;         // host side finished; results valid once `done`
@@ -57,6 +58,7 @@ struct SlotState {
   bool gamma = false;
   double mu = 1.0;
   double kappa_max = 1.0;   // largest 1/eps of the slot's permittivity (residual floor)
+  bool e_start = false;     // E holds the start block of the task's first point (nested start)
   std::vector<double> res_rows;
 };
 
@@ -143,6 +145,12 @@ struct bl_solver {
   double* ritz_work = nullptr;
   size_t ritz_stride = 0;
   double* mean_scratch = nullptr;
+  // nested start: the coarsest level's dense pencil and its Ritz step (one slot at a time)
+  double* nst_G = nullptr;
+  double* nst_H = nullptr;
+  double* nst_Y = nullptr;
+  double* nst_work = nullptr;
+  int nst_q = 0;
   void* nodal_extra[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
   int nodal_extra_cap[2] = {0, 0};
   // slot lists: pinned host staging and device copies, recycled after each synchronisation
@@ -222,5 +230,8 @@ int engine_set_k0(bl_solver* s, double k1, double k2);
 int engine_apply(bl_solver* s, int op, int level, int prec, int ncols, const void* x,
                  const void* y, void* out);
 int engine_rr_products(bl_solver* s, const void* S, int q, double* G, double* H);
+// Nested iteration (Section 6) for slot sl at (k1, k2), whose phases are set: the start block
+// in E on return, iterations per level in its.
+int engine_nested_start(bl_solver* s, int sl, double k1, double k2, int nev, std::vector<int>& its);
 
 }  // namespace bl

@@ -39,7 +39,9 @@ struct c2 {
 __device__ __forceinline__ c2 cmul(c2 a, c2 b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
 __device__ __forceinline__ c2 cmulc(c2 a, c2 b) { return {a.r * b.r + a.i * b.i, a.r * b.i - a.i * b.r}; }  // conj(a) b
 
-constexpr int RT = 256;   // threads per workgroup
+// threads per workgroup: a 16 x 16 grid for q <= 48 (the register paths hold 3 x 3 entries
+// per thread), a 32 x 32 grid above (register paths up to q = 96, four times the threads for
+// the rest)
 constexpr int GS = 8;     // lanes per eigenvalue / eigenvector group
 
 // size of the per-index arrays (one complex, eight doubles, four ints per basis index) in
@@ -89,6 +91,14 @@ __device__ __forceinline__ double sum4(double a) {
 }
 __device__ __forceinline__ double sum8(double a) { a = sum4(a); return a + dpp_d<kDppHalfMirror>(a); }
 __device__ __forceinline__ double sum16(double a) { a = sum8(a); return a + dpp_d<kDppMirror>(a); }
+// sum over the TG threads of a row of the TG x TG thread grid (16: one row of 16 lanes; 32:
+// two, the second pair of partial sums exchanged across the half-wave)
+template <int TG>
+__device__ __forceinline__ double row_sum(double a) {
+  a = sum16(a);
+  if constexpr (TG == 32) a += __shfl_xor(a, 16, 64);
+  return a;
+}
 
 __device__ __forceinline__ double wave_sum(double a) {
   a = sum16(a);
@@ -243,8 +253,8 @@ __device__ __forceinline__ int sturm_count(const double* d, const double* e2, in
 size_t ritz_small_work_doubles(int q) { return (size_t)10 * q * q + 8 * (size_t)q + 64; }
 
 // LDS layout (when it fits): index arrays | A | B | Z | T, each q rows of stride q | 1.
-template <bool IN_LDS>
-__global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2* __restrict__ H, int q,
+template <int MEM, int TG>
+__global__ __launch_bounds__(TG * TG) void k_ritz(const c2* __restrict__ G, const c2* __restrict__ H, int q,
                                              int nfix, int want, const double* __restrict__ zthr,
                                              double drop_rel, double* __restrict__ work,
                                              size_t work_stride, c2* __restrict__ Y,
@@ -277,9 +287,11 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
   // compile-time choice, so that LDS pointers keep their address space (no flat accesses)
   // row strides are odd (q | 1 for q-wide matrices, r | 1 once the rank is known), so that
   // the rows read side by side by neighbouring lanes fall in different LDS banks
+  // MEM 2: the four matrices in LDS; 1: A (the matrix being factorised, reduced or holding
+  // the vectors) in LDS, B, Z, T in the work array; 0: all four in the work array
   const int lq = q | 1;
-  c2* A = IN_LDS ? smem + index_block_c2(q) : gw;
-  c2* B = A + q * lq;
+  c2* A = MEM >= 1 ? smem + index_block_c2(q) : gw;
+  c2* B = (MEM == 2 ? A : gw) + q * lq;
   c2* Z = B + q * lq;
   c2* T = Z + q * lq;
   const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
@@ -302,9 +314,9 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
   if (tid == 0) second_s = 0;
   __syncthreads();
   int r = 0;
-  const int ty = tid >> 4, tx = tid & 15;   // 16 x 16 thread grid
-  if (q <= 3 * 16) {
-    // The matrix in registers: thread (ty, tx) holds the entries (ty + 16 a, tx + 16 b),
+  const int ty = tid / TG, tx = tid % TG;   // TG x TG thread grid
+  if (TG == 16 && q <= 3 * TG) {
+    // The matrix in registers: thread (ty, tx) holds the entries (ty + TG a, tx + TG b),
     // a, b < 3.  A step broadcasts the pivot column through LDS (colbuf, by step parity)
     // and updates every held entry; entries of already pivoted indices are updated too but
     // never read again, and their diagonal is published as -1, below every candidate, so
@@ -316,7 +328,7 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
     for (int a = 0; a < 3; ++a)
 #pragma unroll
       for (int b = 0; b < 3; ++b) {
-        const int i = ty + 16 * a, j = tx + 16 * b;
+        const int i = ty + TG * a, j = tx + TG * b;
         ar[a][b] = {0.0, 0.0};
         if (i < q && j < q) {
           const c2 g = G[i * q + j], gt = G[j * q + i];
@@ -326,7 +338,8 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
         }
       }
     __syncthreads();
-    unsigned long long dead = 0;
+    unsigned long long dead0 = 0, dead1 = 0;   // indices 0..63, 64..127
+    auto is_dead = [&](int i) { return ((i < 64 ? dead0 >> i : dead1 >> (i - 64)) & 1ull) != 0; };
     for (int k = 0; k < q; ++k) {
       const double* dcur = dg + (k & 1) * q;
       double* dnext = dg + ((k + 1) & 1) * q;
@@ -337,8 +350,12 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
         idx = k;
         v = dcur[k];
       } else {
-        v = lane < q ? dcur[lane] : -1.0;
-        idx = lane;
+        v = -1.0;
+        idx = q;
+        for (int t = lane; t < q; t += 64) {
+          const double dv = dcur[t];
+          if (dv > v || (dv == v && t < idx)) { v = dv; idx = t; }
+        }
         int pos = 0;   // unused here
         pick_max<kDppXor1>(v, idx, pos);
         pick_max<kDppXor2>(v, idx, pos);
@@ -355,18 +372,18 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
         idx = bi;
       }
       if (!(v > drop_rel)) break;
-      dead |= 1ull << idx;
+      if (idx < 64) dead0 |= 1ull << idx; else dead1 |= 1ull << (idx - 64);
       if (tid == 0) {
         if (v < 1e-4) second_s = 1;
         perm[k] = idx;
       }
       const double piv = sqrt(v), rpiv = 1.0 / piv, invd = 1.0 / v;
       // the pivot column to LDS, and column k of the factor (original rows) to B
-      if (tx == (idx & 15)) {
-        const int bsel = idx >> 4;
+      if (tx == idx % TG) {
+        const int bsel = idx / TG;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          const int i = ty + 16 * a;
+          const int i = ty + TG * a;
           if (i >= q) continue;
           c2 c = ar[a][0];
 #pragma unroll
@@ -382,8 +399,8 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
       c2 ci[3], cj[3];
 #pragma unroll
       for (int u = 0; u < 3; ++u) {
-        ci[u] = (ty + 16 * u < q) ? col[ty + 16 * u] : c2{0.0, 0.0};
-        cj[u] = (tx + 16 * u < q) ? col[tx + 16 * u] : c2{0.0, 0.0};
+        ci[u] = (ty + TG * u < q) ? col[ty + TG * u] : c2{0.0, 0.0};
+        cj[u] = (tx + TG * u < q) ? col[tx + TG * u] : c2{0.0, 0.0};
       }
 #pragma unroll
       for (int a = 0; a < 3; ++a)
@@ -395,8 +412,8 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
       if (ty == tx)
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          const int i = ty + 16 * a;
-          if (i < q) dnext[i] = ((dead >> i) & 1ull) ? -1.0 : ar[a][a].r;
+          const int i = ty + TG * a;
+          if (i < q) dnext[i] = is_dead(i) ? -1.0 : ar[a][a].r;
         }
       __syncthreads();
       r = k + 1;
@@ -405,7 +422,7 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
     if (tid == 0) {
       int t = r;
       for (int i = 0; i < q; ++i)
-        if (!((dead >> i) & 1ull)) perm[t++] = i;
+        if (!is_dead(i)) perm[t++] = i;
     }
   } else {
     for (int e = tid; e < q * q; e += nt) {
@@ -470,14 +487,14 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
         if (t != pos) rnext[t < pos ? t : t - 1] = i;
       }
       // trailing update of the remaining indices but idx (column idx is only read here)
-      if (nr <= 48) {
+      if (TG == 16 && nr <= 3 * TG) {
         // register block of up to 3 x 3 entries: every load before any store, so that the
         // loads are not held behind stores the compiler cannot tell apart
         int ib[3], jb[3];
         c2 ai[3], aj[3], cur[3][3];
   #pragma unroll
         for (int u = 0; u < 3; ++u) {
-          const int a = ty + 16 * u, b = tx + 16 * u;
+          const int a = ty + TG * u, b = tx + TG * u;
           ib[u] = (a < nr && a != pos) ? rcur[a] : -1;
           jb[u] = (b < nr && b != pos) ? rcur[b] : -1;
         }
@@ -502,11 +519,11 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
               if (ib[v] == jb[u]) dnext[ib[v]] = nv.r;
             }
       } else {
-        for (int a = ty; a < nr; a += 16) {
+        for (int a = ty; a < nr; a += TG) {
           if (a == pos) continue;
           const int i = rcur[a];
           const c2 aik = A[i * lq + idx];
-          for (int b = tx; b < nr; b += 16) {
+          for (int b = tx; b < nr; b += TG) {
             if (b == pos) continue;
             const int j = rcur[b];
             const c2 t = cmulc(A[j * lq + idx], aik);
@@ -523,7 +540,7 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
   }
   // pivot order of the dropped indices (after the kept ones; the register path has set
   // them), and the factor's rows in pivot order into T (rows of A are free from here on)
-  if (q > 3 * 16)
+  if (!(TG == 16 && q <= 3 * TG))
     for (int t = tid; t < q - r; t += nt) perm[r + t] = rem[(r & 1) * q + t];
   __syncthreads();
   for (int e = tid; e < r * r; e += nt) {
@@ -624,10 +641,10 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
   // block becomes H_k A22 H_k via p = tau A22 v, w = p - (tau/2)(v^* p) v,
   // A22 <- A22 - v w^* - w v^*.  T holds p.  Every wave forms the column norm and v^* p
   // itself (same lanes, same order: identical values in all waves).
-  if (r <= 3 * 16) {
-    // The matrix in registers as in the Cholesky (thread (ty, tx) holds (ty + 16 a, tx + 16 b)).
+  if (TG == 16 && r <= 3 * TG) {
+    // The matrix in registers as in the Cholesky (thread (ty, tx) holds (ty + TG a, tx + TG b)).
     // Per step: column k through LDS (colv, by step parity), the reflector from it in every
-    // wave, p = tau A22 v as per-thread partial sums combined across the 16 threads of a
+    // wave, p = tau A22 v as per-thread partial sums combined across the TG threads of a
     // row with DPP, p through LDS (pv) for v^* p and the column side of w, then the rank-2
     // update of the held entries.  Two barriers per step.  The subdiagonal (beta) and the
     // diagonal go to A's LDS copy, where the extraction below reads them.
@@ -638,17 +655,17 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
     for (int a = 0; a < 3; ++a)
 #pragma unroll
       for (int b = 0; b < 3; ++b) {
-        const int i = ty + 16 * a, j = tx + 16 * b;
+        const int i = ty + TG * a, j = tx + TG * b;
         ar[a][b] = (i < r && j < r) ? A[i * lr + j] : c2{0.0, 0.0};
       }
     __syncthreads();   // A's copy is written below
     for (int k = 0; k + 2 < r; ++k) {
       c2* col = colv + (k & 1) * r;
-      if (tx == (k & 15)) {
-        const int bsel = k >> 4;
+      if (tx == k % TG) {
+        const int bsel = k / TG;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          const int i = ty + 16 * a;
+          const int i = ty + TG * a;
           if (i >= r) continue;
           c2 c = ar[a][0];
 #pragma unroll
@@ -662,10 +679,11 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
       }
       __syncthreads();
       double part = 0;
-      if (lane > k && lane < r) {
-        const c2 x = col[lane];
-        part = x.r * x.r + x.i * x.i;
-      }
+      for (int l = lane; l < r; l += 64)
+        if (l > k) {
+          const c2 x = col[l];
+          part += x.r * x.r + x.i * x.i;
+        }
       const double xn2 = wave_sum(part);
       const c2 x0 = col[k + 1];
       const double ax0 = sqrt(x0.r * x0.r + x0.i * x0.i);
@@ -695,11 +713,11 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
       c2 vi[3], vj[3];
 #pragma unroll
       for (int u = 0; u < 3; ++u) {
-        vi[u] = vat(ty + 16 * u);
-        vj[u] = vat(tx + 16 * u);
+        vi[u] = vat(ty + TG * u);
+        vj[u] = vat(tx + TG * u);
       }
       // p_i = tau sum_j A_ij v_j for the held rows (partials over the held columns, summed
-      // across the row's 16 threads)
+      // across the row's TG threads)
       c2 pi[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
@@ -710,19 +728,20 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
           sacc.r += t.r;
           sacc.i += t.i;
         }
-        pi[a] = {tk * sum16(sacc.r), tk * sum16(sacc.i)};
-        const int i = ty + 16 * a;
+        pi[a] = {tk * row_sum<TG>(sacc.r), tk * row_sum<TG>(sacc.i)};
+        const int i = ty + TG * a;
         if (tx == 0 && i > k && i < r) pv[i] = pi[a];
       }
       __syncthreads();
       double kp = 0;
-      if (lane > k && lane < r) kp = cmulc(vat(lane), pv[lane]).r;
+      for (int l = lane; l < r; l += 64)
+        if (l > k) kp += cmulc(vat(l), pv[l]).r;
       const double Kh = 0.5 * tk * wave_sum(kp);
       c2 wi[3], wj[3];
 #pragma unroll
       for (int u = 0; u < 3; ++u) {
         wi[u] = {pi[u].r - Kh * vi[u].r, pi[u].i - Kh * vi[u].i};
-        const int j = tx + 16 * u;
+        const int j = tx + TG * u;
         const c2 pj = (j > k && j < r) ? pv[j] : c2{0.0, 0.0};
         wj[u] = {pj.r - Kh * vj[u].r, pj.i - Kh * vj[u].i};
       }
@@ -730,7 +749,7 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
       for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b)
-          if (ty + 16 * a > k && tx + 16 * b > k) {
+          if (ty + TG * a > k && tx + TG * b > k) {
             const c2 t1 = cmulc(wj[b], vi[a]), t2 = cmulc(vj[b], wi[a]);   // v_i conj(w_j), w_i conj(v_j)
             ar[a][b] = {ar[a][b].r - t1.r - t2.r, ar[a][b].i - t1.i - t2.i};
           }
@@ -740,12 +759,16 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
     for (int a = 0; a < 3; ++a)
 #pragma unroll
       for (int b = 0; b < 3; ++b) {
-        const int i = ty + 16 * a, j = tx + 16 * b;
+        const int i = ty + TG * a, j = tx + TG * b;
         if (i < r && j < r && i >= r - 2 && j >= r - 2 && j <= i) A[i * lr + j] = ar[a][b];
       }
     __syncthreads();
   } else {
-    c2* pv = T;
+    // with A in LDS and the other matrices in the work array (MEM 1), the reflector and p
+    // are also kept in LDS (after A) for the products; the reflector still goes to B for the
+    // back-transformation
+    c2* vst = MEM == 1 ? A + q * lq : nullptr;
+    c2* pv = MEM == 1 ? vst + q : T;
     for (int k = 0; k + 2 < r; ++k) {
       const int m = r - k - 1;
       double part = 0;
@@ -772,10 +795,11 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
         if (j == k + 1) vj = {x0.r - beta.r, x0.i - beta.i};
         else if (j > k + 1) vj = A[j * lr + k];
         B[k * lr + j] = vj;
+        if (MEM == 1) vst[j] = vj;
       }
       if (tid == 0) { tau[k] = tk; dd[k] = A[k * lr + k].r; }
       __syncthreads();
-      const c2* v = B + k * lr;
+      const c2* v = MEM == 1 ? vst : B + k * lr;
       {   // p = tau A22 v, four lanes per row
         const int sub = tid & 3;
         for (int rb = 0; rb < m; rb += nt / 4) {
@@ -798,13 +822,13 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
       double kp = 0;
       for (int i = lane; i < m; i += 64) kp += cmulc(v[k + 1 + i], pv[i]).r;
       const double Kh = 0.5 * tk * wave_sum(kp);
-      if (m <= 48) {
+      if (TG == 16 && m <= 3 * TG) {
         // register block of up to 3 x 3 entries, all loads before the stores (as in the
         // Cholesky update)
         c2 vi[3], wi[3], vj[3], wj[3], cur[3][3];
   #pragma unroll
         for (int u = 0; u < 3; ++u) {
-          const int i = ty + 16 * u, j = tx + 16 * u;
+          const int i = ty + TG * u, j = tx + TG * u;
           if (i < m) {
             vi[u] = v[k + 1 + i];
             const c2 pi = pv[i];
@@ -820,21 +844,21 @@ __global__ __launch_bounds__(RT) void k_ritz(const c2* __restrict__ G, const c2*
         for (int a = 0; a < 3; ++a)
   #pragma unroll
           for (int b = 0; b < 3; ++b)
-            if (ty + 16 * a < m && tx + 16 * b < m) cur[a][b] = A[(k + 1 + ty + 16 * a) * lr + k + 1 + tx + 16 * b];
+            if (ty + TG * a < m && tx + TG * b < m) cur[a][b] = A[(k + 1 + ty + TG * a) * lr + k + 1 + tx + TG * b];
   #pragma unroll
         for (int a = 0; a < 3; ++a)
   #pragma unroll
           for (int b = 0; b < 3; ++b)
-            if (ty + 16 * a < m && tx + 16 * b < m) {
+            if (ty + TG * a < m && tx + TG * b < m) {
               const c2 t1 = cmulc(wj[b], vi[a]), t2 = cmulc(vj[b], wi[a]);   // v_i conj(w_j), w_i conj(v_j)
-              A[(k + 1 + ty + 16 * a) * lr + k + 1 + tx + 16 * b] = {cur[a][b].r - t1.r - t2.r,
+              A[(k + 1 + ty + TG * a) * lr + k + 1 + tx + TG * b] = {cur[a][b].r - t1.r - t2.r,
                                                                       cur[a][b].i - t1.i - t2.i};
             }
       } else {
-        for (int i = ty; i < m; i += 16) {
+        for (int i = ty; i < m; i += TG) {
           const c2 vi = v[k + 1 + i];
           const c2 wi = {pv[i].r - Kh * vi.r, pv[i].i - Kh * vi.i};
-          for (int j = tx; j < m; j += 16) {
+          for (int j = tx; j < m; j += TG) {
             const c2 vj = v[k + 1 + j];
             const c2 wj = {pv[j].r - Kh * vj.r, pv[j].i - Kh * vj.i};
             const c2 t1 = cmulc(wj, vi), t2 = cmulc(vj, wi);   // v_i conj(w_j), w_i conj(v_j)
@@ -1172,8 +1196,12 @@ void ritz_small(const double* G, const double* H, int q, int nfix, int want, con
     (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&cap, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) cap = 65536;
     cap -= 1024;   // the kernel's static LDS (scalars) is below 1 KB
-    if (cap > 0 && (hipFuncSetAttribute((const void*)k_ritz<true>, hipFuncAttributeMaxDynamicSharedMemorySize, cap) != hipSuccess ||
-                    hipFuncSetAttribute((const void*)k_ritz<false>, hipFuncAttributeMaxDynamicSharedMemorySize, cap) != hipSuccess))
+    bool ok = cap > 0;
+    const void* fns[6] = {(const void*)k_ritz<0, 16>, (const void*)k_ritz<1, 16>, (const void*)k_ritz<2, 16>,
+                          (const void*)k_ritz<0, 32>, (const void*)k_ritz<1, 32>, (const void*)k_ritz<2, 32>};
+    for (const void* f : fns)
+      if (ok && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, cap) != hipSuccess) ok = false;
+    if (!ok)
       cap = 64 * 1024 - 1024;
     g_cap = cap > 0 ? cap : 0;
     if (std::getenv("BL_DEBUG")) std::fprintf(stderr, "bloch: ritz dynamic LDS cap %d bytes\n", g_cap);
@@ -1181,15 +1209,25 @@ void ritz_small(const double* G, const double* H, int q, int nfix, int want, con
   if (L.nact <= 0) return;
   const size_t idx = (size_t)index_block_c2(q) * sizeof(c2);
   const size_t need = idx + (size_t)4 * q * (q | 1) * sizeof(c2);
-  const int in_lds = need <= (size_t)g_cap ? 1 : 0;
-  if (in_lds)
-    k_ritz<true><<<L.nact, RT, need, L.st>>>(reinterpret_cast<const c2*>(G), reinterpret_cast<const c2*>(H), q,
-                                             nfix, want, zthr, drop_rel, work, work_stride,
-                                             reinterpret_cast<c2*>(Y), theta, count, L.slots);
-  else
-    k_ritz<false><<<L.nact, RT, idx, L.st>>>(reinterpret_cast<const c2*>(G), reinterpret_cast<const c2*>(H), q,
-                                             nfix, want, zthr, drop_rel, work, work_stride,
-                                             reinterpret_cast<c2*>(Y), theta, count, L.slots);
+  const size_t need1 = idx + ((size_t)q * (q | 1) + 2 * (size_t)q) * sizeof(c2);
+  const int mem = need <= (size_t)g_cap ? 2 : (need1 <= (size_t)g_cap ? 1 : 0);
+  const size_t lds = mem == 2 ? need : (mem == 1 ? need1 : idx);
+  const c2* g = reinterpret_cast<const c2*>(G);
+  const c2* h = reinterpret_cast<const c2*>(H);
+  c2* y = reinterpret_cast<c2*>(Y);
+#define BL_RITZ(M, TGV)                                                                                    \
+  k_ritz<M, TGV><<<L.nact, TGV * TGV, lds, L.st>>>(g, h, q, nfix, want, zthr, drop_rel, work, work_stride, y, \
+                                                   theta, count, L.slots)
+  if (q <= 48) {
+    if (mem == 2) BL_RITZ(2, 16);
+    else if (mem == 1) BL_RITZ(1, 16);
+    else BL_RITZ(0, 16);
+  } else {
+    if (mem == 2) BL_RITZ(2, 32);
+    else if (mem == 1) BL_RITZ(1, 32);
+    else BL_RITZ(0, 32);
+  }
+#undef BL_RITZ
 }
 
 }  // namespace bl

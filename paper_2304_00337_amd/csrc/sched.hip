@@ -301,7 +301,8 @@ class Scheduler {
 
 int make_job(const bl_opts& common, const bl_grid* grid, const double* eps, int nev, int nthrow,
              int nk, const double* ks, const void* start_dev, Job* j) {
-  if (!grid || !eps || !ks || nk < 1 || !start_dev) return set_error(BL_EINVAL, "invalid problem (grid, eps, ks and start block are required)%s");
+  if (!grid || !eps || !ks || nk < 1 || (!start_dev && !common.nested_start))
+    return set_error(BL_EINVAL, "invalid problem (grid, eps, ks and a start block, unless nested_start is set, are required)%s");
   bl_opts o = common;
   o.nev = nev;
   o.nthrow = nthrow;

@@ -126,6 +126,8 @@ int validate_opts(const bl_opts* o) {
   if (!(o->tol > 0)) return set_error(BL_EINVAL, "tol must be positive%s");
   if (o->tol_abs != 0 && o->tol_abs != 1) return set_error(BL_EINVAL, "tol_abs must be 0 or 1%s");
   if (o->tol_floor != 0 && o->tol_floor != 1) return set_error(BL_EINVAL, "tol_floor must be 0 or 1%s");
+  if (o->nested_start != 0 && o->nested_start != 1) return set_error(BL_EINVAL, "nested_start must be 0 or 1%s");
+  if (!(o->nested_tol >= 0) || o->nested_tol >= 1) return set_error(BL_EINVAL, "nested_tol must be in [0, 1)%s");
   return BL_OK;
 }
 
@@ -213,6 +215,11 @@ template <typename T>
 const void* kc_inv(const bl_solver* s) { return PrecOf<T>::v ? (const void*)s->kc_inv32 : (const void*)s->kc_inv64; }
 template <typename T>
 const void* pc_inv(const bl_solver* s) { return PrecOf<T>::v ? (const void*)s->pc_inv32 : (const void*)s->pc_inv64; }
+
+// Blocks of a coarser level inside the slot-major blocks E (p columns per slot) and S (qmax
+// per slot): with the column stride per slot scaled by N_0 / N_l (= 4^l) the level-l columns of
+// a slot start where its finest-level block starts and stay inside it.
+int level_scale(const bl_solver* s, int lev) { return (int)(s->lv[0].g.ne / s->lv[lev].g.ne); }
 
 // ---- slot lists -------------------------------------------------------------------------
 // Device list for a launch over `v`; null when v is 0, 1, ..., |v|-1 (the kernels then use
@@ -531,16 +538,16 @@ bool vcycle_nodal(bl_solver* s, int l, View<const T> b, View<T> x, const Launch&
 // phi ~ P^{-1} b by `cycles` V-cycles; b and phi must not be level-0 work blocks of the
 // nodal cycle (nr) or the multi-cycle work blocks.
 template <typename T>
-void nodal_solve(bl_solver* s, View<const T> b, View<T> phi, const Launch& L, int cycles) {
+void nodal_solve(bl_solver* s, View<const T> b, View<T> phi, const Launch& L, int cycles, int lev = 0) {
   const int pr = PrecOf<T>::v;
-  vcycle_nodal<T>(s, 0, b, phi, L);
+  vcycle_nodal<T>(s, lev, b, phi, L);
   View<T> res = view(static_cast<T*>(s->nodal_extra[pr][0]), s->nodal_extra_cap[pr]);
   View<T> cor = view(static_cast<T*>(s->nodal_extra[pr][1]), s->nodal_extra_cap[pr]);
-  const Geo& g = s->lv[0].g;
+  const Geo& g = s->lv[lev].g;
   for (int c = 1; c < cycles; ++c) {
     nodal_apply<T>(cv(phi), b, res, g, s->ph_d, s->ns, true, L);
     s->launches += 1;
-    if (!vcycle_nodal<T>(s, 0, cv(res), cor, L, &phi)) {
+    if (!vcycle_nodal<T>(s, lev, cv(res), cor, L, &phi)) {
       axpy<T>(phi, cv(cor), g.nm, L);
       s->launches += 1;
     }
@@ -560,20 +567,20 @@ struct Group {
 // constant edge fields are removed (the slots of Lg).  Nodal arithmetic in TN.
 template <typename TN>
 int project_groups(bl_solver* s, const std::vector<Group>& groups, View<double> out,
-                   const std::vector<int>& slots, const std::vector<int>& gslots) {
+                   const std::vector<int>& slots, const std::vector<int>& gslots, int lev) {
   const int pr = PrecOf<TN>::v;
   int total = 0;
   for (auto& g : groups) total += g.cols;
   int rc = ensure_level_buffers(s, pr, std::max(s->lv[0].ecap[pr], s->p), std::max(total, s->qmax));
   if (rc) return rc;
   if ((rc = ensure_pw(s, total))) return rc;
-  const Geo& g0 = s->lv[0].g;
+  const Geo& g0 = s->lv[lev].g;
   Launch L = make_launch(s, slots, 0);
-  const int nc = s->lv[0].ncap[pr];
-  // right-hand side and solution of the nodal solve: the level-0 nodal blocks nb and nx,
-  // which the level-0 V-cycle itself does not use (it works in nr and the coarser levels)
-  TN* b0 = static_cast<TN*>(s->lv[0].nb[pr]);
-  TN* phi = static_cast<TN*>(s->lv[0].nx[pr]);
+  const int nc = s->lv[lev].ncap[pr];
+  // right-hand side and solution of the nodal solve: the level's nodal blocks nb and nx,
+  // which the V-cycle from that level does not use (it works in nr and the coarser levels)
+  TN* b0 = static_cast<TN*>(s->lv[lev].nb[pr]);
+  TN* phi = static_cast<TN*>(s->lv[lev].nx[pr]);
   const PWDefl pw{s->pw_tab, s->pw_d, s->pw_part, s->pw_coef, 2 * (int64_t)(g0.n + g0.m), total, 0, pw_blocks(g0)};
   int off = 0;
   for (auto& gr : groups) {
@@ -592,7 +599,7 @@ int project_groups(bl_solver* s, const std::vector<Group>& groups, View<double> 
   // exact plane-wave coefficient added back through the lift
   pw_reduce(pw, 0, apply_blocks(g0), Lt);   // k_lhm: one partial per point tile
   pw_rhs<TN>(view(b0, nc), g0, pw, Lt);
-  nodal_solve<TN>(s, cview(b0, nc), view(phi, nc), Lt, std::max(1, s->opts.nodal_cycles));
+  nodal_solve<TN>(s, cview(b0, nc), view(phi, nc), Lt, std::max(1, s->opts.nodal_cycles), lev);
   const int nd = pw_dot<TN>(cview(phi, nc), g0, pw, Lt);
   pw_reduce(pw, 1, nd, Lt);
   s->launches += 4;
@@ -617,12 +624,12 @@ int project_groups(bl_solver* s, const std::vector<Group>& groups, View<double> 
 }
 
 int project(bl_solver* s, const std::vector<Group>& groups, View<double> out,
-            const std::vector<int>& slots) {
+            const std::vector<int>& slots, int lev = 0) {
   std::vector<int> gs;
   for (int sl : slots)
     if (s->slot[sl].gamma) gs.push_back(sl);
-  if (s->opts.precision) return project_groups<float>(s, groups, out, slots, gs);
-  return project_groups<double>(s, groups, out, slots, gs);
+  if (s->opts.precision) return project_groups<float>(s, groups, out, slots, gs, lev);
+  return project_groups<double>(s, groups, out, slots, gs, lev);
 }
 
 }  // namespace
@@ -638,17 +645,18 @@ namespace {
 // Ritz step on the q columns of S (FP64) of the listed slots: G = S^* M S, H = S^* A S,
 // generalised eigenproblem, E <- S Y for the p smallest Ritz values above the slot's
 // zero threshold (zthr_d, or none), Ritz values into lam_d.
-int ritz_step(bl_solver* s, const std::vector<int>& slots, int q, int nfix, bool use_zthr) {
-  const Level& L0 = s->lv[0];
+int ritz_step(bl_solver* s, const std::vector<int>& slots, int q, int nfix, bool use_zthr, int lev = 0) {
+  const Level& L0 = s->lv[lev];
   const Geo& g = L0.g;
+  const int sc = level_scale(s, lev);
   Launch L = make_launch(s, slots, q);
-  View<double> Sv = view(s->Sb, s->qmax);
+  View<double> Sv = view(s->Sb, s->qmax * sc);
   const int tile = (q == 2 * s->p && s->tune_rr) ? s->tune_rr : rr_tile(q);
   if (rr_gram(cv(Sv), q, L0.kappa64, g, s->ph_d, s->gram_partial, s->gram_cap, s->Gm, s->Hm, tile, L) != 0)
     return set_error(BL_EINVAL, "Gram scratch too small%s");
   ritz_small(s->Gm, s->Hm, q, nfix, s->p, use_zthr ? s->zthr_d : nullptr, kDropRel, s->ritz_work,
              s->ritz_stride, s->Yd, s->lam_d, s->count_d, L);
-  block_combine(cv(Sv), q, s->Yd, s->p, g.ne, view(s->E, s->p), L);
+  block_combine(cv(Sv), q, s->Yd, s->p, g.ne, view(s->E, s->p * sc), L);
   s->launches += 4;
   if (s->debug && !slots.empty()) {
     double sw[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -775,6 +783,152 @@ int check_hip() {
   return BL_OK;
 }
 
+// ---- nested iteration for a first Bloch parameter (Section 6) ------------------------------
+// The coarsest level's pencil (A_c, M_c) is probed with unit vectors and solved densely for
+// its p smallest non-zero eigenpairs (the gradients are its exact zeros and are skipped); the
+// block is then prolongated level by level and, on every level between, iterated to the
+// relative residual opts.nested_tol with the level as the finest one of its own hierarchy.
+// Everything stays on the device in the engine's own buffers: level-l blocks use the slot's
+// regions of E and S (level_scale), the V-cycle and nodal blocks of level l are the ones the
+// finest-level cycles use below it, and the dense pencil has buffers of its own.
+
+// Buffers of the coarsest pencil (one slot at a time), allocated on the first nested start.
+int ensure_nested(bl_solver* s) {
+  const int q = (int)s->nce;
+  if (s->nst_q >= q) return BL_OK;
+  int rc;
+  if ((rc = dalloc_t(s, &s->nst_G, (size_t)q * q * 2))) return rc;
+  if ((rc = dalloc_t(s, &s->nst_H, (size_t)q * q * 2))) return rc;
+  if ((rc = dalloc_t(s, &s->nst_Y, (size_t)q * s->p * 2))) return rc;
+  if ((rc = dalloc_t(s, &s->nst_work, ritz_small_work_doubles(q)))) return rc;
+  s->nst_q = q;
+  return BL_OK;
+}
+
+// Plane-wave parameters and tables of slot sl for the geometry of level lev (the projection
+// on that level deflates its own discrete plane wave).
+int plane_wave_level(bl_solver* s, int sl, int lev, double k1, double k2) {
+  const Geo& g = s->lv[lev].g;
+  s->pw_h[sl] = plane_wave_params(g, s->grid.a, s->grid.b, k1, k2, s->slot[sl].gamma);
+  char* h = static_cast<char*>(s->param_h);   // free: its last copies completed at a synchronisation
+  std::memcpy(h, &s->pw_h[sl], sizeof(PlaneWave));
+  HIP_OK(hipMemcpyAsync(s->pw_d + sl, h, sizeof(PlaneWave), hipMemcpyHostToDevice, s->st));
+  const int64_t stride = 2 * (int64_t)(s->grid.n + s->grid.m);
+  pw_tables(s->pw_d + sl, s->pw_tab + sl * stride, stride, g.n, g.m, 1, s->st);
+  HIP_OK(hipStreamSynchronize(s->st));
+  s->launches += 1;
+  return BL_OK;
+}
+
+// E (level lev + 1) -> E (level lev) of slot sl by the edge prolongation, through S.
+void prolong_block(bl_solver* s, int sl, int lev) {
+  const int p = s->p;
+  const Level& F = s->lv[lev];
+  const Level& C = s->lv[lev + 1];
+  Launch L = make_launch(s, {sl}, p);
+  const View<double> Sf = view(s->Sb, s->qmax * level_scale(s, lev));
+  zero_cols<double>(Sf, F.g.ne, L);
+  edge_prolong_add<double>(cview(s->E, p * level_scale(s, lev + 1)), C.g, Sf, F.g, s->ph_d, L);
+  sub_cols<double>(cv(Sf), View<const double>{nullptr, 0, 0}, view(s->E, p * level_scale(s, lev)), F.g.ne, L);
+  s->launches += 3;
+}
+
+// Block iteration of slot sl on level lev >= 1 from the block in E to the relative residual
+// tol over the first nev pairs (at most max_it iterations); the iterations go to *its.
+int iterate_level(bl_solver* s, int sl, int lev, int nev, double tol, int max_it, int* its) {
+  const int p = s->p, ip = s->opts.precision, sc = level_scale(s, lev);
+  Level& Lv = s->lv[lev];
+  const std::vector<int> one{sl};
+  const View<const double> none{nullptr, 0, 0};
+  int rc;
+  if ((rc = project(s, {{s->E, p * sc, 0, 0, p}}, view(s->Sb, s->qmax * sc), one, lev))) return rc;
+  if ((rc = ritz_step(s, one, p, 0, false, lev))) return rc;
+  for (int it = 0;; ++it) {
+    Launch L = make_launch(s, one, p);
+    int nblk = 0;
+    if (ip)
+      edge_apply<double, float>(EM_EIGRES, cview(s->E, p * sc), none, view(static_cast<float*>(Lv.eb[1]), Lv.ecap[1]),
+                                Lv.kappa64, Lv.kappa32, s->lam_d, p, Lv.g, s->ph_d, s->mu_d, L, s->partial, &nblk);
+    else
+      edge_apply<double, double>(EM_EIGRES, cview(s->E, p * sc), none, view(static_cast<double*>(Lv.eb[0]), Lv.ecap[0]),
+                                 Lv.kappa64, Lv.kappa32, s->lam_d, p, Lv.g, s->ph_d, s->mu_d, L, s->partial, &nblk);
+    reduce_partials(s->partial, nblk, p, 2, s->norms, s->st);
+    s->launches += 2;
+    HIP_OK(hipMemcpyAsync(s->norms_h, s->norms, s->readback_bytes, hipMemcpyDeviceToHost, s->st));
+    HIP_OK(hipStreamSynchronize(s->st));
+    s->lists_used = 0;
+    if ((rc = check_hip())) return rc;
+    if (it == 0 && s->count_h[sl] < p) return set_error(BL_ENOCONV, "nested start: the block lost rank%s");
+    const double* lam = s->lam_h + (size_t)sl * p;
+    bool conv = true;
+    for (int j = 0; j < nev; ++j) {
+      const double den = std::fabs(lam[j]) * std::sqrt(s->norms_h[2 * j + 1]);
+      conv = conv && den > 0 && std::sqrt(s->norms_h[2 * j]) <= tol * den;
+    }
+    if (conv || it >= max_it) {
+      *its = it;
+      return BL_OK;
+    }
+    if (ip) vcycle_edge<float>(s, lev, cview(static_cast<const float*>(Lv.eb[1]), Lv.ecap[1]), view(static_cast<float*>(Lv.ex[1]), Lv.ecap[1]), L);
+    else vcycle_edge<double>(s, lev, cview(static_cast<const double*>(Lv.eb[0]), Lv.ecap[0]), view(static_cast<double*>(Lv.ex[0]), Lv.ecap[0]), L);
+    if ((rc = project(s, {{s->E, p * sc, 0, 0, p}, {Lv.ex[ip], Lv.ecap[ip], 0, ip, p}}, view(s->Sb, s->qmax * sc), one, lev)))
+      return rc;
+    if ((rc = ritz_step(s, one, 2 * p, p, false, lev))) return rc;
+  }
+}
+
+// The start block of slot sl at (k1, k2) by nested iteration, left in E (finest level); the
+// iterations per level (finest first, 0 for the finest and the coarsest) go to its.  The
+// slot's phases must be set; on return its plane-wave parameters are those of the finest
+// level again.
+int nested_start_slot(bl_solver* s, int sl, double k1, double k2, int nev, std::vector<int>& its) {
+  const int nl = (int)s->lv.size(), lc = nl - 1, p = s->p;
+  its.assign(nl, 0);
+  if (nl < 2 || s->nce > 255) return set_error(BL_EINVAL, "nested start needs a coarsest level of at most 255 edges%s");
+  int rc;
+  if ((rc = ensure_nested(s))) return rc;
+  SlotState& ss = s->slot[sl];
+  const Level& C = s->lv[lc];
+  const int q = (int)s->nce;
+  // zero threshold of the dense pencil: far above the rounding of its zero eigenvalues
+  // (u times the stencil's Gershgorin bound 8 kappa_max (1/h1^2 + 1/h2^2)), far below the
+  // smallest non-zero one
+  s->zthr_h[sl] = 1e-8 * 8.0 * ss.kappa_max * (1.0 / (C.g.h1 * C.g.h1) + 1.0 / (C.g.h2 * C.g.h2));
+  if ((rc = upload_slot_params(s))) return rc;
+  setup_coarse(s, {sl});
+  // coarsest pencil: columns of A_c and M_c from the unit vectors (shared by every slot, so
+  // the output columns are addressed without a slot offset), to row-major matrices
+  Launch Lp = make_launch(s, {sl}, q);
+  const View<const double> unit{s->probe_e, 0, 0}, none{nullptr, 0, 0};
+  const Launch L1{nullptr, 1, 0, s->st};
+  edge_apply<double, double>(EM_A, unit, none, View<double>{s->probe_out, 0, 0}, C.kappa64, C.kappa32, nullptr, 0, C.g,
+                             s->ph_d, s->mu_d, Lp, nullptr, nullptr);
+  planar_to_matrix(s->probe_out, q, s->nst_H, L1);
+  edge_apply<double, double>(EM_M, unit, none, View<double>{s->probe_out, 0, 0}, C.kappa64, C.kappa32, nullptr, 0, C.g,
+                             s->ph_d, s->mu_d, Lp, nullptr, nullptr);
+  planar_to_matrix(s->probe_out, q, s->nst_G, L1);
+  ritz_small(s->nst_G, s->nst_H, q, 0, p, s->zthr_d + sl, kDropRel, s->nst_work, 0, s->nst_Y, s->lam_d + (size_t)sl * p,
+             s->count_d + sl, L1);
+  // E (coarsest level) = the unit vectors combined with the Ritz vectors
+  block_combine(unit, q, s->nst_Y, p, C.g.ne, View<double>{s->E + (size_t)sl * p * 2 * s->lv[0].g.ne, p * level_scale(s, lc), 0},
+                L1);
+  s->launches += 7;
+  HIP_OK(hipMemcpyAsync(s->norms_h, s->norms, s->readback_bytes, hipMemcpyDeviceToHost, s->st));
+  HIP_OK(hipStreamSynchronize(s->st));
+  s->lists_used = 0;
+  if ((rc = check_hip())) return rc;
+  if (s->count_h[sl] < p) return set_error(BL_ENOCONV, "the coarsest mesh has fewer than p non-zero eigenvalues%s");
+  const double tol = s->opts.nested_tol > 0 ? s->opts.nested_tol : 1e-3;
+  for (int l = lc - 1; l >= 0 && !rc; --l) {
+    prolong_block(s, sl, l);
+    if (l == 0) break;
+    if ((rc = plane_wave_level(s, sl, l, k1, k2))) break;
+    rc = iterate_level(s, sl, l, nev, tol, s->opts.max_iter, &its[l]);
+  }
+  const int rc2 = plane_wave_level(s, sl, 0, k1, k2);
+  return rc ? rc : rc2;
+}
+
 void end_task(bl_solver* s, int sl, int status, const char* msg) {
   SlotState& ss = s->slot[sl];
   Task* t = ss.task;
@@ -855,6 +1009,8 @@ size_t engine_footprint(const bl_grid* grid, const bl_opts* o, int nslots) {
   per += (size_t)p * ((g0.ne + 255) / 256) * 16;
   per += (size_t)q * pw_blocks(g0) * 16 + (size_t)q * 48 + (size_t)(grid->n + grid->m) * 16 + sizeof(PlaneWave);
   fixed += (size_t)gc.ne * gc.ne * 16 + (size_t)gc.nm * gc.nm * 16;           // probes
+  if (o->nested_start)   // the coarsest pencil of the nested start, its Ritz vectors and work
+    fixed += (size_t)gc.ne * gc.ne * 32 + (size_t)gc.ne * p * 16 + ritz_small_work_doubles((int)gc.ne) * 8;
   return fixed + per * (size_t)std::max(1, nslots);
 }
 
@@ -897,6 +1053,8 @@ int engine_create(const bl_grid* grid, const bl_opts* opts, int nslots, hipStrea
   s->nce = c.ne;
   s->ncn = c.nm;
   if (s->nce > kMaxCoarse) return fail(set_error(BL_EINVAL, "grid cannot be coarsened to a small enough level%s"));
+  if (o.nested_start && (s->nce > 255 || s->lv.size() < 2))
+    return fail(set_error(BL_EINVAL, "nested_start needs a hierarchy whose coarsest level has at most 255 edges%s"));
   {  // nodal stencil (same on every level: depends on h2/h1 only)
     const double r = s->lv[0].g.mx, q = s->lv[0].g.my;
     s->ns = {(4.0 / 3.0) * (r + q), -(2.0 / 3.0) * r + (1.0 / 3.0) * q, (1.0 / 3.0) * r - (2.0 / 3.0) * q, -(1.0 / 6.0) * (r + q)};
@@ -1042,7 +1200,8 @@ int engine_assign(bl_solver* s, int sl, Task* t) {
     if (rc) return rc;
     ss.hist_count = 0;
   }
-  if (!t->start_dev && ss.hist_count == 0) return set_error(BL_ESTATE, "no start block and no history to extrapolate from%s");
+  if (!t->start_dev && ss.hist_count == 0 && !s->opts.nested_start)
+    return set_error(BL_ESTATE, "no start block and no history to extrapolate from%s");
   t->evals.assign((size_t)nk * t->nev, 0.0);
   t->relres.assign((size_t)nk * t->nev, INFINITY);
   t->iters.assign(nk, 0);
@@ -1075,15 +1234,26 @@ int engine_issue(bl_solver* s) {
     starting.push_back(sl);
   }
   if (!starting.empty()) {
+    // a task's first point with neither a start block nor a history to extrapolate from:
+    // nested iteration (Section 6) when enabled; should the block lose rank on the way, the
+    // point starts from the block in E
+    for (int sl : starting) {
+      SlotState& ss = s->slot[sl];
+      ss.e_start = false;
+      if (ss.t != 0 || ss.task->start_dev || ss.hist_count > 0 || !s->opts.nested_start) continue;
+      const int rc = nested_start_slot(s, sl, ss.task->ks[0], ss.task->ks[1], ss.task->nev, ss.task->nested_its);
+      if (rc == BL_OK) ss.e_start = true;
+      else if (rc != BL_ENOCONV) return rc;
+    }
     // group by the width of the start basis: a start block (p) or 1..3 history blocks
     std::vector<int> by_q[4];
     for (int sl : starting) {
       SlotState& ss = s->slot[sl];
-      const bool from_start = ss.t == 0 && ss.task->start_dev;
+      const bool from_start = ss.t == 0 && (ss.task->start_dev || ss.e_start);
       const int depth = from_start ? 0 : std::min(ss.hist_count, s->opts.extrap_depth);
       s->zthr_h[sl] = from_start ? -INFINITY : s->opts.zero_rel * ss.hist_lam1;
       by_q[depth].push_back(sl);
-      if (from_start)
+      if (from_start && ss.task->start_dev)
         HIP_OK(hipMemcpyAsync(s->E + (size_t)sl * p * 2 * g0.ne, ss.task->start_dev, (size_t)p * 2 * g0.ne * 8,
                               hipMemcpyDeviceToDevice, s->st));
     }
@@ -1264,6 +1434,10 @@ int engine_set_k0(bl_solver* s, double k1, double k2) {
   HIP_OK(hipStreamSynchronize(s->st));
   s->lists_used = 0;
   return check_hip();
+}
+
+int engine_nested_start(bl_solver* s, int sl, double k1, double k2, int nev, std::vector<int>& its) {
+  return nested_start_slot(s, sl, k1, k2, nev, its);
 }
 
 namespace {

@@ -38,7 +38,8 @@ class BlOpts(ctypes.Structure):
                 ("precision", c_int32), ("extrap_depth", c_int32), ("autotune", c_int32),
                 ("coarse_fuse", c_int32), ("tiled_sweeps", c_int32),
                 ("tol", c_double), ("mu", c_double), ("zero_rel", c_double),
-                ("engine_streams", c_int32), ("tol_abs", c_int32), ("tol_floor", c_int32)]
+                ("engine_streams", c_int32), ("tol_abs", c_int32), ("tol_floor", c_int32),
+                ("nested_start", c_int32), ("nested_tol", c_double)]
 
 
 class BlInfo(ctypes.Structure):

@@ -63,6 +63,29 @@ def test_batch_matches_dense_and_alone(precision):
         assert np.array_equal(a["iterations"], r["iterations"])
 
 
+def test_batch_nested_start_for_problems_without_a_start_block():
+    """With nested_start, batched problems without a start block start from the nested
+    iteration on their own slot while the others iterate: every problem matches the dense
+    eigenvalues, the problems that have start blocks give what they give without the option,
+    and a nested problem gives in the batch what it gives alone."""
+    from paper_2304_00337_amd import batch_solve
+    probs = _problems()
+    for i in (0, 2, 4):
+        probs[i] = dict(probs[i], start=None)
+    mixed = batch_solve(probs, nested_start=1, **OPTS)
+    for pr, r in zip(probs, mixed):
+        assert r["status"] == 0, r
+        for t in range(len(pr["ks"])):
+            ref = _dense(pr, t)
+            assert np.max(np.abs(r["evals"][t] - ref) / ref) < 1e-9
+    plain = batch_solve([pr for pr in probs if pr["start"] is not None], **OPTS)
+    for r, q in zip([r for pr, r in zip(probs, mixed) if pr["start"] is not None], plain):
+        assert np.array_equal(r["evals"], q["evals"]) and np.array_equal(r["iterations"], q["iterations"])
+    alone = batch_solve([probs[2]], nested_start=1, **OPTS)[0]
+    assert np.array_equal(alone["evals"], mixed[2]["evals"])
+    assert np.array_equal(alone["iterations"], mixed[2]["iterations"])
+
+
 def test_batch_equals_single_handle_and_slot_limits():
     """A batched problem equals the same path on a one-problem handle (bl_solve_path), and
     engines with fewer slots than problems (slots re-used as problems finish) give the same

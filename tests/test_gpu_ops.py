@@ -190,6 +190,49 @@ def test_gram_and_ritz_small():
     _close(th3, ref[3:8], 1e-12)
 
 
+@pytest.mark.parametrize("q", [49, 72, 96, 120, 144])
+def test_ritz_small_wide(q):
+    """The Ritz step for bases wider than 48 columns (the 2p = 96 of 32 + 16 vectors, the 3p
+    of LOBPCG): generalized eigenvalues against scipy, Y G-orthonormal and H-diagonal, with a
+    well-conditioned G, with a nearly dependent column (dropped), and with a four-fold
+    eigenvalue (the cluster path)."""
+    import scipy.linalg as sla
+    d, H, s, rng = _setup(CASES[0])
+    want = min(q, 48)
+    Z = _rand(rng, 400, q)
+    G = Z.conj().T @ Z
+    A0 = _rand(rng, 400, 400)
+    A0 = A0 @ A0.conj().T
+    Hm = Z.conj().T @ A0 @ Z
+    ref = sla.eigh(Hm, G, eigvals_only=True)
+    th, Y = s.ritz_small(G, Hm, want)
+    assert len(th) == want
+    assert np.abs(th - ref[:want]).max() <= 1e-11 * np.abs(ref[:want]).max()
+    assert np.abs(Y.conj().T @ G @ Y - np.eye(want)).max() < 1e-9
+    assert np.abs(Y.conj().T @ Hm @ Y - np.diag(th)).max() < 1e-9 * np.abs(th).max()
+    # a nearly dependent column is dropped: the rest of the pencil's values remain
+    Z2 = Z.copy()
+    Z2[:, 5] = 2.0 * Z2[:, 9] + 1e-10 * Z2[:, 11]
+    G2 = Z2.conj().T @ Z2
+    H2 = Z2.conj().T @ A0 @ Z2
+    keep = [j for j in range(q) if j != 5]
+    ref2 = sla.eigh(H2[np.ix_(keep, keep)], G2[np.ix_(keep, keep)], eigvals_only=True)
+    th2, Y2 = s.ritz_small(G2, H2, want)
+    assert np.abs(th2 - ref2[:want]).max() <= 1e-7 * np.abs(ref2[:want]).max()
+    assert np.abs(Y2.conj().T @ G2 @ Y2 - np.eye(want)).max() < 1e-7
+    # a four-fold eigenvalue inside the wanted range
+    L = np.linalg.cholesky(G)
+    Q, _ = np.linalg.qr(_rand(rng, q, q))
+    lam = np.sort(rng.uniform(0.5, 40.0, q))
+    lam[10:14] = lam[10]
+    H3 = L @ (Q * lam) @ Q.conj().T @ L.conj().T
+    H3 = 0.5 * (H3 + H3.conj().T)
+    th3, Y3 = s.ritz_small(G, H3, want)
+    assert np.abs(th3 - lam[:want]).max() <= 1e-10 * lam.max()
+    assert np.abs(Y3.conj().T @ G @ Y3 - np.eye(want)).max() < 1e-9
+    assert np.abs(Y3.conj().T @ H3 @ Y3 - np.diag(th3)).max() < 1e-9 * lam.max()
+
+
 @pytest.mark.parametrize("case", CASES)
 def test_rayleigh_ritz_products(case):
     """G = S^* M S and H = S^* A S formed straight from S (bl_rr_products) against the

@@ -69,6 +69,25 @@ def test_c1_disc_against_dense(precision):
     _subspace_check(from_device_block(r["evecs"]), V, d.M, lam, 8)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_wide_block_against_arpack(precision):
+    """32 eigenpairs with 16 throw-away vectors, the block width of the 1024 x 1024 path (a
+    96-column Rayleigh-Ritz basis), on a 48 x 48 random two-phase field next to Gamma, against
+    the oracle's ARPACK solve: 1e-9 relative in FP64, 1e-6 in mixed precision."""
+    from oracle.dense import gradient_free_eigs
+    from paper_2304_00337_amd import Solver
+    n = 48
+    eps = synth.eps_random_field(n, n, 1.0, 1.0, seed=2, sigma=0.05, lo=1.0, hi=11.4)
+    k = (math.pi / 20, 0.0)
+    d = fem.Discretization(n, n, 1.0, 1.0, eps, *k)
+    ref = gradient_free_eigs(d, 32)[0]
+    s = Solver(n, n, 1.0, 1.0, eps, nev=32, nthrow=16, precision=precision, tol=1e-8, max_iter=300)
+    r = s.solve_k(*k, start=synth.start_block(d.n_edges, 48, 5))
+    assert r["converged"], r["iterations"]
+    rel = np.abs(r["evals"] - ref) / ref
+    assert rel.max() < (1e-9 if precision == "fp64" else 1e-6), rel.max()
+
+
 def test_c1_eps_one_closed_form():
     prob = synth.config_c1(eps_one=True)
     s = _solver(prob, "fp64", levels=3, max_iter=400)
@@ -227,6 +246,31 @@ def test_nested_start_matches_oracle(k):
     rnd = Solver(n, n, 1.0, 1.0, eps, nev=nev, nthrow=nthrow, mu=mu, coarsest_min=4, tol=1e-9,
                  max_iter=200).solve_k(*k, start=synth.start_block(d.n_edges, nev + nthrow, 5))
     assert r["iterations"] < rnd["iterations"]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_nested_start_option_in_the_engine(precision):
+    """The nested_start option: a path's first point without a start block starts from the
+    nested iteration inside the engine, and gives to the last bit what the same point gives
+    from the block bl_nested_start returns; every point of the path matches the dense
+    eigenvalues, and the first point needs fewer iterations than from a random block."""
+    from paper_2304_00337_amd import Solver
+    n, nev, nthrow, mu = 32, 6, 3, 10.0
+    eps = synth.eps_disc_lattice(n, n, 1.0, 1.0, 12.0, 0.3)
+    ks = np.array([(0.7, -1.3), (0.8, -1.2), (0.9, -1.1)])
+    kw = dict(nev=nev, nthrow=nthrow, mu=mu, coarsest_min=4, tol=1e-9, max_iter=200, precision=precision)
+    block, its = Solver(n, n, 1.0, 1.0, eps, **kw).nested_start(*ks[0], tol_levels=1e-3)
+    assert its[1:-1].min() > 0
+    a = Solver(n, n, 1.0, 1.0, eps, nested_start=1, nested_tol=1e-3, **kw).solve_path(ks)
+    b = Solver(n, n, 1.0, 1.0, eps, **kw).solve_path(ks, start=block)
+    assert np.array_equal(a["evals"], b["evals"]) and np.array_equal(a["iterations"], b["iterations"])
+    tol = 1e-9 if precision == "fp64" else 1e-6
+    for t in range(len(ks)):
+        d = fem.Discretization(n, n, 1.0, 1.0, eps, *ks[t])
+        ref = dense_eigs(d, nev)[0]
+        assert np.max(np.abs(a["evals"][t] - ref) / ref) < tol
+    rnd = Solver(n, n, 1.0, 1.0, eps, **kw).solve_k(*ks[0], start=synth.start_block(2 * n * n, nev + nthrow, 5))
+    assert a["iterations"][0] < rnd["iterations"]
 
 
 def test_kgrid_raster_matches_oracle():
