@@ -50,17 +50,17 @@ def log(msg):
 LEG_CUTS = (0, 20, 40, 61)
 
 
+NESTED_TOL = 1e-2   # relative residual of the nested start's intermediate levels
+
+
 def c3_legs(prob):
-    """The 61-point path cut at X and M into its three legs; leg 0 starts from the workload's
-    seeded block, leg i > 0 from the block seeded 100 + i."""
-    import synth
-    from paper_2304_00337_amd import to_device_block
+    """The 61-point path cut at X and M into its three legs; each leg's first point starts
+    from the nested iteration (Section 6), the others are extrapolated within the leg."""
     legs = []
     for i in range(3):
         ks = np.asarray(prob.ks)[LEG_CUTS[i]:LEG_CUTS[i + 1]]
-        st = prob.start() if i == 0 else synth.start_block(prob.n_edges, prob.p, 100 + i)
         legs.append(dict(n=prob.n, m=prob.m, a=prob.a, b=prob.b, eps=prob.eps, nev=prob.nev,
-                         nthrow=prob.nthrow, ks=ks, start=to_device_block(st)))
+                         nthrow=prob.nthrow, ks=ks, start=None))
     return legs
 
 
@@ -71,7 +71,7 @@ def run_legs(prob, legs, precision, steps, warmup, timing_warmup=False):
     from paper_2304_00337_amd import Batch
     recs = []
     with Batch(max_slots=1, engine_streams=1, precision=precision, levels=prob.levels, tol=prob.tol,
-               max_iter=200) as b:
+               max_iter=200, nested_start=1, nested_tol=NESTED_TOL) as b:
         if timing_warmup:
             b.set_timing(True)
         for w in range(warmup):
@@ -128,7 +128,9 @@ def cpu_baseline(prob, iters_total, cold_starts, sample_n=256):
     1024^2 oracle takes ~110 s of setup per Bloch point and ~8 min per iteration), its setup
     at the first point after Gamma, the start block and one iteration with the full block
     width, scaled to the workload by the dof ratio (the stencils and multigrid are linear in
-    the dofs) and by the GPU run's iteration count."""
+    the dofs) and by the GPU run's iteration count; each leg's nested start is charged as the
+    start block plus four fine iterations (its levels below the finest cost sum_l it_l 4^-l
+    fine iterations, with at most 12 iterations per level)."""
     import synth
     from oracle import fem
     from oracle.closed_form import discrete_nonzero
@@ -149,7 +151,7 @@ def cpu_baseline(prob, iters_total, cold_starts, sample_n=256):
     t3 = time.perf_counter()
     scale = (prob.n * prob.m) / (n * n)
     nk = len(prob.ks)
-    path_s = scale * (nk * (t1 - t0) + cold_starts * (t2 - t1) + iters_total * (t3 - t2))
+    path_s = scale * (nk * (t1 - t0) + cold_starts * ((t2 - t1) + 4 * (t3 - t2)) + iters_total * (t3 - t2))
     try:
         from threadpoolctl import threadpool_info
         cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
@@ -159,8 +161,9 @@ def cpu_baseline(prob, iters_total, cold_starts, sample_n=256):
             "sample": (f"the oracle at {n}x{n} on the same generator (random two-phase field, seed 2), first point "
                        f"after Gamma: setup {t1 - t0:.1f}s, start block ({prob.p} columns) {t2 - t1:.1f}s, one "
                        f"iteration {t3 - t2:.1f}s; workload time = {scale:.0f} (dof ratio) x [{nk} x setup + "
-                       f"{cold_starts} x start + {int(iters_total)} iterations (the GPU run's count per path) x "
-                       f"iteration] = {path_s:.0f}s; BLAS threads as reported, sparse products single-threaded")}
+                       f"{cold_starts} x (start + 4 iterations for the nested levels) + {int(iters_total)} "
+                       f"iterations (the GPU run's count per path) x iteration] = {path_s:.0f}s; BLAS threads as "
+                       f"reported, sparse products single-threaded")}
 
 
 # ---- side legs ---------------------------------------------------------------------------
@@ -233,14 +236,15 @@ def serving(count, seed, rate_frac=0.7, n_hi=2048, budget_frac=1.1):
     largest request's footprint (so the largest request runs nearly alone and waits for the
     others to drain: admission must not let later requests pass it without bound)."""
     import synth
-    from paper_2304_00337_amd import Server, Solver, to_device_block
+    from paper_2304_00337_amd import Server, Solver
     reqs = synth.config_c5_requests(count, master_seed=seed, n_lo=64, n_hi=n_hi, nev_lo=4, nev_hi=32,
                                     nk_lo=11, nk_hi=61)
-    kw = dict(precision="mixed", tol=1e-6, tol_floor=1, max_iter=300)
+    kw = dict(precision="mixed", tol=1e-6, tol_floor=1, max_iter=300, nested_start=1, nested_tol=NESTED_TOL)
     biggest = max(Solver.footprint_bytes(r.n, r.m, r.a, r.b, nev=r.nev, nthrow=r.nthrow, **kw) for r in reqs)
     budget_gb = budget_frac * biggest / 2 ** 30
-    items = [dict(n=r.n, m=r.m, a=r.a, b=r.b, eps=r.eps, nev=r.nev, nthrow=r.nthrow, ks=r.ks,
-                  start=to_device_block(r.start())) for r in reqs]
+    # requests carry no start block: each path's first point starts from the nested iteration
+    items = [dict(n=r.n, m=r.m, a=r.a, b=r.b, eps=r.eps, nev=r.nev, nthrow=r.nthrow, ks=r.ks, start=None)
+             for r in reqs]
     pairs = sum(r.nev * len(r.ks) for r in reqs)
 
     def drive(srv, gaps):
@@ -276,7 +280,8 @@ def serving(count, seed, rate_frac=0.7, n_hi=2048, budget_frac=1.1):
             "p99_latency_ms": round(float(np.percentile(lat, 99)), 2),
             "engines_at_end": st["engines"], "rounds": st["rounds"], "hbm_budget_gb": round(budget_gb, 2),
             "workload": f"band paths: n log-uniform 64..{n_hi} (rounded to n0 2^l), nev 4..32 (+nev/2), 11..61 "
-                        "points, disc-lattice or random-field eps; mixed precision, tol 1e-6 with the FP64 floor; "
+                        "points, disc-lattice or random-field eps; mixed precision, tol 1e-6 with the FP64 floor, "
+                        "nested start per request; "
                         f"Poisson arrivals at {rate_frac:.0%} of the measured closed-batch capacity"}
 
 
@@ -372,30 +377,33 @@ def lobpcg_c2():
 
 
 def nested_first_point(prob, seed=1):
-    """The 256 x 256 lattice path's first point cold-started from the seeded random block
-    and from the nested iteration of Section 6 (mixed precision)."""
+    """A leg's first point (the path's first, Gamma) from the seeded random block against
+    the engine's nested start (Section 6, the headline's setting), mixed precision; the
+    per-level iterations from bl_nested_start on the same handle options."""
     import torch
     import synth
     from paper_2304_00337_amd import Solver, to_device_block
-    s = Solver(prob.n, prob.m, prob.a, prob.b, prob.eps, nev=prob.nev, nthrow=prob.nthrow, tol=prob.tol,
-               max_iter=300, precision="mixed", levels=prob.levels)
+    kw = dict(nev=prob.nev, nthrow=prob.nthrow, tol=prob.tol, max_iter=300, precision="mixed", levels=prob.levels)
+    s_r = Solver(prob.n, prob.m, prob.a, prob.b, prob.eps, **kw)
+    s_n = Solver(prob.n, prob.m, prob.a, prob.b, prob.eps, nested_start=1, nested_tol=NESTED_TOL, **kw)
     k = prob.ks[0]
     st = to_device_block(synth.start_block(prob.n_edges, prob.p, seed))
-    s.solve_k(*k, start=st)
+    s_r.solve_k(*k, start=st)
+    s_n.solve_k(*k)
+    s_n.reset_history()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    r0 = s.solve_k(*k, start=st)
+    r0 = s_r.solve_k(*k, start=st)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    start, its = s.nested_start(*k, tol_levels=1e-3)
+    r1 = s_n.solve_k(*k)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    r1 = s.solve_k(*k, start=start)
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
-    return {"k": [float(k[0]), float(k[1])], "random_start": {"iterations": r0["iterations"], "ms": round(1e3 * (t1 - t0), 2)},
-            "nested": {"level_iterations": its.tolist(), "start_ms": round(1e3 * (t2 - t1), 2),
-                       "iterations": r1["iterations"], "solve_ms": round(1e3 * (t3 - t2), 2)},
+    _, its = s_r.nested_start(*k, tol_levels=NESTED_TOL)
+    return {"workload": f"{prob.n}x{prob.m}, nev {prob.nev} (+{prob.nthrow}), k = Gamma, mixed, tol {prob.tol:g}",
+            "random_start": {"iterations": r0["iterations"], "ms": round(1e3 * (t1 - t0), 2)},
+            "nested": {"iterations": r1["iterations"], "ms": round(1e3 * (t2 - t1), 2),
+                       "level_iterations": its.tolist(), "nested_tol": NESTED_TOL},
             "max_rel_eig_diff": float(np.max(np.abs(r0["evals"] - r1["evals"]) / r0["evals"]))}
 
 
@@ -441,6 +449,10 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="start with one plain device copy of 512 MiB, whose counters calibrate hardware byte "
                          "counters")
+    ap.add_argument("--counter-slice", action="store_true",
+                    help="only a short slice for hardware-counter passes: 12 iterations of the headline's "
+                         "mixed solve at the first point after Gamma (same launches as the headline's "
+                         "iterations), then exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -457,6 +469,14 @@ def main():
         log("calibration copy: 536870912 bytes read, 536870912 bytes written")
         del src, dst
     prob = synth.config_c3()
+    if args.counter_slice:
+        from paper_2304_00337_amd import Solver, to_device_block
+        s = Solver(prob.n, prob.m, prob.a, prob.b, prob.eps, nev=prob.nev, nthrow=prob.nthrow, tol=prob.tol,
+                   max_iter=12, precision="mixed", levels=prob.levels, engine_streams=1)
+        r = s.solve_k(*prob.ks[1], start=to_device_block(prob.start()), allow_noconv=True)
+        torch.cuda.synchronize()
+        log(f"counter slice: {r['iterations']} iterations at k = {tuple(prob.ks[1])}")
+        return
     legs = c3_legs(prob)
     torch.cuda.synchronize()
     head = run_legs(prob, legs, "mixed", args.steps, max(1, args.warmup), timing_warmup=True)
@@ -515,7 +535,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "1024x1024 unit cell, smoothed random two-phase eps {1, 11.4} (seed 2), 61 k on "
                                "Gamma-X-M-Gamma (20 per leg), nev 32 (+16), rel. residual tol 1e-6, 8-level MG; "
-                               "one step = one leg (legs in turn), cold start per leg, extrapolation within",
+                               "one step = one leg (legs in turn), nested start per leg (Section 6, levels to 1e-2), "
+                               "extrapolation within",
                    "n": prob.n, "nk": len(prob.ks), "nev": prob.nev, "p": prob.p, "legs": [20, 20, 21]},
         "eigenpairs_counted": good, "eigenpairs_solved": total,
         "p50_solve_ms": round(float(np.percentile(ms_all, 50)), 3),
@@ -546,7 +567,7 @@ def main():
         side("lobpcg", lobpcg_c2, 15, out)
         side("throwaway", throwaway_study, 15, out)
         side("kgrid", lambda: kgrid_raster(1024, "mixed"), 60, out)
-        side("nested_start", lambda: nested_first_point(synth.config_c2()), 10, out)
+        side("nested_start", lambda: nested_first_point(prob), 12, out)
     log("done")
     print(json.dumps(out), flush=True)
 

@@ -120,7 +120,7 @@ typedef struct bl_opts {
                            from nested iteration (Section 6): the coarsest level's p smallest
                            non-zero eigenpairs by a dense solve, then prolongation and block
                            iteration to nested_tol on every level up to the finest, all in the
-                           engine's device buffers; needs a coarsest level of at most 255
+                           engine's device buffers; needs a coarsest level of at most 512
                            edges (checked at creation).  0 = the block in the slot (0)      */
   double nested_tol;    /* relative residual to which the levels below the finest are
                            iterated in the nested start; 0 selects 1e-3                    */
@@ -217,7 +217,7 @@ int bl_solve_kgrid(bl_solver* s, int32_t kappa, const void* start_dev, double* e
  * the finest level: the start block of bl_solve_k / bl_solve_path / a batch problem.
  * level_iters: NULL or host array of `levels` entries receiving the iterations per level
  * (0 for the finest and the coarsest).  Errors: BL_EINVAL (arguments, or a coarsest level
- * of more than 255 edges), BL_ENOCONV (fewer than p non-zero coarse eigenvalues), BL_ENOMEM,
+ * of more than 512 edges), BL_ENOCONV (fewer than p non-zero coarse eigenvalues), BL_ENOMEM,
  * BL_EHIP.  Sets the handle's Bloch parameter for bl_apply to k. */
 int bl_nested_start(bl_solver* s, double k1, double k2, double tol_levels, void* out_dev,
                     int32_t* level_iters);
@@ -295,7 +295,8 @@ int bl_get_timing(const bl_solver* s, double* total_ms, int64_t* launches, int64
  *   G is orthonormalised by pivoted Cholesky of its unit-diagonal scaling; directions whose
  *   squared distance from the kept ones is below 1e-10 (relative) are dropped; the `want` smallest
  *   Ritz values above zero_thr are returned in theta (host) and their G-orthonormal
- *   coefficient vectors in Y (host q x want, row-major interleaved).  Runs on the GPU.
+ *   coefficient vectors in Y (host q x want, row-major interleaved).  Runs on the GPU;
+ *   1 <= q <= 512, 1 <= want <= q (else BL_EINVAL).
  *   Returns the number of values found (>= 0) or an error. */
 int bl_gram(bl_solver* s, const void* X, int32_t q, const void* W, int32_t r, int64_t len,
             double* out);

@@ -358,7 +358,7 @@ int bl_rr_products(bl_solver* s, const void* S, int32_t q, double* G, double* H)
 
 int bl_ritz_small(bl_solver* s, const double* G, const double* H, int32_t q, int32_t want,
                   double zero_thr, double* theta, double* Y) {
-  if (!s || !G || !H || !theta || !Y || q < 1 || q > 255 || want < 1 || want > q)
+  if (!s || !G || !H || !theta || !Y || q < 1 || q > 512 || want < 1 || want > q)
     return set_error(BL_EINVAL, "invalid ritz arguments%s");
   const size_t m2 = (size_t)q * q * 2 * 8;
   DeviceScratch dG, dH, dW, dY, dT, dZ, dc;

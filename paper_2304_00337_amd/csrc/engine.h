@@ -20,6 +20,7 @@ namespace bl {
 
 constexpr int kMaxLevels = 16;
 constexpr int64_t kMaxCoarse = 2048;   // largest coarsest-level edge count solved densely
+constexpr int64_t kMaxNestedCoarse = 512;   // largest coarsest pencil of the nested start (Ritz kernel)
 constexpr int kMaxSlots = 256;
 constexpr int kMaxLists = 32;          // device slot lists alive between two synchronisations
 

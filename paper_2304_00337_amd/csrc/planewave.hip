@@ -71,25 +71,34 @@ void pw_reduce(const PWDefl& d, int mode, int count, const Launch& L) {
   k_pw_reduce<<<dim3(1, (unsigned)cols), 256, 0, L.st>>>(d, mode, count, L.slots);
 }
 
+// kPwPer elements per thread (strided by the block size, so that a wave's accesses stay
+// contiguous): fewer, fuller blocks for these streaming passes
+constexpr int kPwPer = 4;
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_pw_rhs(View<T> bv, Geo g, PWDefl d, const int* __restrict__ slots, int ncps) {
   const SJ sj = slot_col(slots, ncps);
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.nm) return;
   const int n = g.n;
-  const int j1 = (int)(i % n), j2 = (int)(i / n);
-  const Cx<double> w = pw_value(d, sj.slot, n, j1, j2);
   const int64_t col = (int64_t)(blockIdx.y / ncps) * d.pcols + d.off + sj.j;
   const double* c = d.coef + col * 6;
   T* b = colp(bv, sj, g.nm);
-  const Cx<double> ws = cmul(w, c[0], c[1]);
-  b[i] = (T)((double)b[i] - ws.re);
-  b[g.nm + i] = (T)((double)b[g.nm + i] - ws.im);
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x * kPwPer + threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < kPwPer; ++u) {
+    const int64_t i = i0 + (int64_t)u * blockDim.x;
+    if (i >= g.nm) break;
+    int j1, j2;
+    split_index(i, n, j1, j2);
+    const Cx<double> w = pw_value(d, sj.slot, n, j1, j2);
+    const Cx<double> ws = cmul(w, c[0], c[1]);
+    b[i] = (T)((double)b[i] - ws.re);
+    b[g.nm + i] = (T)((double)b[g.nm + i] - ws.im);
+  }
 }
 
 template <typename T>
 void pw_rhs(View<T> b, const Geo& g, const PWDefl& d, const Launch& L) {
-  dim3 grid((unsigned)((g.nm + 255) / 256), (unsigned)(L.nact * L.ncps));
+  dim3 grid((unsigned)((g.nm + 256 * kPwPer - 1) / (256 * kPwPer)), (unsigned)(L.nact * L.ncps));
   if (grid.y == 0) return;
   k_pw_rhs<T><<<grid, 256, 0, L.st>>>(b, g, d, L.slots, L.ncps);
 }
@@ -99,15 +108,20 @@ template void pw_rhs<float>(View<float>, const Geo&, const PWDefl&, const Launch
 template <typename T>
 __global__ __launch_bounds__(256) void k_pw_dot(View<const T> fv, Geo g, PWDefl d, const int* __restrict__ slots, int ncps) {
   const SJ sj = slot_col(slots, ncps);
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int n = g.n;
+  const T* f = colp(fv, sj, g.nm);
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x * kPwPer + threadIdx.x;
   double sr = 0.0, si = 0.0;
-  if (i < g.nm) {
-    const int n = g.n;
-    const Cx<double> w = pw_value(d, sj.slot, n, (int)(i % n), (int)(i / n));
-    const T* f = colp(fv, sj, g.nm);
+#pragma unroll
+  for (int u = 0; u < kPwPer; ++u) {
+    const int64_t i = i0 + (int64_t)u * blockDim.x;
+    if (i >= g.nm) break;
+    int j1, j2;
+    split_index(i, n, j1, j2);
+    const Cx<double> w = pw_value(d, sj.slot, n, j1, j2);
     const double fr = (double)f[i], fi = (double)f[g.nm + i];
-    sr = w.re * fr + w.im * fi;
-    si = w.re * fi - w.im * fr;
+    sr += w.re * fr + w.im * fi;
+    si += w.re * fi - w.im * fr;
   }
   const int64_t col = (int64_t)(blockIdx.y / ncps) * d.pcols + d.off + sj.j;
   block_sum2(sr, si, d.part + (col * d.nblk + blockIdx.x) * 2);
@@ -115,7 +129,7 @@ __global__ __launch_bounds__(256) void k_pw_dot(View<const T> fv, Geo g, PWDefl 
 
 template <typename T>
 int pw_dot(View<const T> phi, const Geo& g, const PWDefl& d, const Launch& L) {
-  dim3 grid((unsigned)((g.nm + 255) / 256), (unsigned)(L.nact * L.ncps));
+  dim3 grid((unsigned)((g.nm + 256 * kPwPer - 1) / (256 * kPwPer)), (unsigned)(L.nact * L.ncps));
   if (grid.y == 0) return (int)grid.x;
   k_pw_dot<T><<<grid, 256, 0, L.st>>>(phi, g, d, L.slots, L.ncps);
   return (int)grid.x;

@@ -1,5 +1,5 @@
 // Ritz step of the block iteration (Section 4, Ritz vectors and values) for gfx950: the
-// generalised Hermitian eigenproblem  H y = theta G y  of the basis S (q <= 255 columns),
+// generalised Hermitian eigenproblem  H y = theta G y  of the basis S (q <= 512 columns),
 // G = S^* M S and H = S^* A S, solved in one workgroup per problem slot, in LDS:
 //
 //  1. unit-diagonal scaling D; pivoted Cholesky P^T (D G D) P = L L^* (the first nfix

@@ -884,7 +884,8 @@ int iterate_level(bl_solver* s, int sl, int lev, int nev, double tol, int max_it
 int nested_start_slot(bl_solver* s, int sl, double k1, double k2, int nev, std::vector<int>& its) {
   const int nl = (int)s->lv.size(), lc = nl - 1, p = s->p;
   its.assign(nl, 0);
-  if (nl < 2 || s->nce > 255) return set_error(BL_EINVAL, "nested start needs a coarsest level of at most 255 edges%s");
+  if (nl < 2 || s->nce > kMaxNestedCoarse)
+    return set_error(BL_EINVAL, "nested start needs a coarsest level of at most 512 edges%s");
   int rc;
   if ((rc = ensure_nested(s))) return rc;
   SlotState& ss = s->slot[sl];
@@ -1053,8 +1054,8 @@ int engine_create(const bl_grid* grid, const bl_opts* opts, int nslots, hipStrea
   s->nce = c.ne;
   s->ncn = c.nm;
   if (s->nce > kMaxCoarse) return fail(set_error(BL_EINVAL, "grid cannot be coarsened to a small enough level%s"));
-  if (o.nested_start && (s->nce > 255 || s->lv.size() < 2))
-    return fail(set_error(BL_EINVAL, "nested_start needs a hierarchy whose coarsest level has at most 255 edges%s"));
+  if (o.nested_start && (s->nce > kMaxNestedCoarse || s->lv.size() < 2))
+    return fail(set_error(BL_EINVAL, "nested_start needs a hierarchy whose coarsest level has at most 512 edges%s"));
   {  // nodal stencil (same on every level: depends on h2/h1 only)
     const double r = s->lv[0].g.mx, q = s->lv[0].g.my;
     s->ns = {(4.0 / 3.0) * (r + q), -(2.0 / 3.0) * r + (1.0 / 3.0) * q, (1.0 / 3.0) * r - (2.0 / 3.0) * q, -(1.0 / 6.0) * (r + q)};

@@ -109,6 +109,14 @@ __device__ __forceinline__ void block_sum2(double a, double b, double* out) {
   }
 }
 
+// (i mod n, i / n) in 32-bit unsigned arithmetic, for 0 <= i < 2^32 (node and edge indices of
+// a level fit); a 64-bit division costs several times as many instructions
+__device__ __forceinline__ void split_index(int64_t i, int n, int& j1, int& j2) {
+  const unsigned u = (unsigned)i, q = u / (unsigned)n;
+  j2 = (int)q;
+  j1 = (int)(u - q * (unsigned)n);
+}
+
 // Block order that gives each of the 8 XCDs (which receive the blocks round-robin) one
 // contiguous range of logical blocks, so that the rows shared by neighbouring blocks stay in
 // one L2.  A bijection of [0, nb).

@@ -64,7 +64,11 @@ struct PointTile {
 };
 __device__ __forceinline__ PointTile point_tile(int n, int m) {
   const int tiles_x = (n + kPtW - 1) / kPtW;
-  const int t = (int)blockIdx.x;
+  // XCD-major order (consecutive blocks go to the eight XCDs in turn): each XCD takes a
+  // contiguous range of tile rows, so the rows a tile shares with its neighbours above and
+  // below are read through the same L2
+  const int nb = (int)gridDim.x;
+  const int t = nb >= 8 ? xcd_block((int)blockIdx.x, nb) : (int)blockIdx.x;
   const int tx0 = (t % tiles_x) * kPtW, ty0 = (t / tiles_x) * kPtH;
   return {tx0 + (int)(threadIdx.x % kPtW), ty0 + (int)(threadIdx.x / kPtW),
           tx0 >= 1 && tx0 + kPtW <= n - 1 && ty0 >= 1 && ty0 + kPtH <= m - 1};

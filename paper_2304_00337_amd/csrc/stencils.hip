@@ -616,13 +616,11 @@ __global__ __launch_bounds__(256) void k_lift(View<const TI> uv, View<const TP> 
   Cx<T> lp;
   int j1, j2;
   if (d < nm) {
-    j1 = (int)(d % n);
-    j2 = (int)(d / n);
+    split_index(d, n, j1, j2);
     lp = fetch<TP, T>(f, nm, n, m, 0, j1 + 1, j2, p) - fetch<TP, T>(f, nm, n, m, 0, j1, j2, p);
   } else {
     const int64_t e = d - nm;
-    j1 = (int)(e % n);
-    j2 = (int)(e / n);
+    split_index(e, n, j1, j2);
     lp = fetch<TP, T>(f, nm, n, m, 0, j1, j2 + 1, p) - fetch<TP, T>(f, nm, n, m, 0, j1, j2, p);
   }
   if (PW) {

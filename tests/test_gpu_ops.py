@@ -190,7 +190,7 @@ def test_gram_and_ritz_small():
     _close(th3, ref[3:8], 1e-12)
 
 
-@pytest.mark.parametrize("q", [49, 72, 96, 120, 144])
+@pytest.mark.parametrize("q", [49, 72, 96, 120, 144, 450])
 def test_ritz_small_wide(q):
     """The Ritz step for bases wider than 48 columns (the 2p = 96 of 32 + 16 vectors, the 3p
     of LOBPCG): generalized eigenvalues against scipy, Y G-orthonormal and H-diagonal, with a
@@ -199,9 +199,10 @@ def test_ritz_small_wide(q):
     import scipy.linalg as sla
     d, H, s, rng = _setup(CASES[0])
     want = min(q, 48)
-    Z = _rand(rng, 400, q)
+    rows = max(400, q + 50)
+    Z = _rand(rng, rows, q)
     G = Z.conj().T @ Z
-    A0 = _rand(rng, 400, 400)
+    A0 = _rand(rng, rows, rows)
     A0 = A0 @ A0.conj().T
     Hm = Z.conj().T @ A0 @ Z
     ref = sla.eigh(Hm, G, eigvals_only=True)

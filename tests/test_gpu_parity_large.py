@@ -22,7 +22,10 @@ and sweep tiles (32 x 32 plus halo) away from the periodic seam need n >= 192 an
   oracle (tests/golden/arpack_c2_256.json): FP64 to 1e-9, mixed to 1e-6 (relative);
 * mixed precision next to Gamma (the band-structure experiment's raster points next to
   Gamma, and a 512 x 512 point closer still): mixed equals FP64 to 1e-6 and the oracle's
-  ARPACK values.
+  ARPACK values;
+* the 1024 x 1024 headline workload (32 + 16 vectors, tolerance 1e-6, nested start) at the
+  first point after Gamma and at X, mixed precision, against the oracle's ARPACK values
+  (tests/golden/arpack_c3_1024.json) to 1e-6.
 """
 import json
 import math
@@ -306,3 +309,22 @@ def test_mixed_close_to_gamma_512():
         out[precision] = r["evals"]
         s.close()
     assert np.max(np.abs(out["mixed"] - out["fp64"]) / out["fp64"]) <= 1e-6
+
+
+def test_c3_points_against_arpack():
+    """The 1024 x 1024 random two-phase workload in mixed precision, each point started from
+    the nested iteration as in the measured run, against the oracle's certified ARPACK
+    values at the first point after Gamma and at X: every one of the 32 eigenvalues to 1e-6."""
+    from paper_2304_00337_amd import Solver
+    gold = _golden("arpack_c3_1024.json")
+    prob = synth.config_c3()
+    s = Solver(prob.n, prob.m, prob.a, prob.b, prob.eps, nev=prob.nev, nthrow=prob.nthrow, tol=prob.tol,
+               precision="mixed", max_iter=200, nested_start=1, nested_tol=1e-2)
+    for pt in gold["points"]:
+        s.reset_history()
+        r = s.solve_k(*pt["k"])
+        ref = np.array(pt["evals"])
+        err = np.abs(r["evals"] - ref) / ref
+        print(f"point {pt['index']} k={pt['k']} iterations {r['iterations']} max rel err {err.max():.2e}", flush=True)
+        assert r["converged"] and err.max() <= 1e-6, (pt["index"], err.max())
+    s.close()
