@@ -82,6 +82,7 @@ def run_legs(prob, legs, precision, steps, warmup, timing_warmup=False):
         shapes = [{"edge_smooth_shape": e["edge_smooth_shape"], "nodal_smooth_shape": e["nodal_smooth_shape"],
                    "fused_edge_level": e["fused_edge_level"], "fused_nodal_level": e["fused_nodal_level"],
                    "levels": e["levels"], "mu": e["mu"]} for e in b.engines()]
+        launches0 = sum(e["kernel_launches"] for e in b.engines())
         t0 = time.perf_counter()
         for i in range(steps):
             leg = i % 3
@@ -92,7 +93,8 @@ def run_legs(prob, legs, precision, steps, warmup, timing_warmup=False):
                          "wall": time.perf_counter() - ts})
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
-    return {"elapsed": elapsed, "recs": recs, "timing": tm, "shapes": shapes}
+        launches = sum(e["kernel_launches"] for e in b.engines()) - launches0
+    return {"elapsed": elapsed, "recs": recs, "timing": tm, "shapes": shapes, "launches": launches}
 
 
 def golden(name):
@@ -141,7 +143,8 @@ def cpu_baseline(prob, iters_total, cold_starts, sample_n=256):
     k = prob.ks[1]
     t0 = time.perf_counter()
     d = fem.Discretization(n, n, 1.0, 1.0, eps, *k)
-    mu = discrete_nonzero(n, n, 1.0, 1.0, float(eps.min()), 0.0, 0.0, prob.p)[-1] / 10.0
+    lam_h = discrete_nonzero(n, n, 1.0, 1.0, float(eps.min()), 0.0, 0.0, prob.p)
+    mu = max(lam_h[-1] / 40.0, lam_h[0] / 2.0)   # the library's default shift
     H = Hierarchy(d, mu=mu)
     pr = Projector(d, H, 2)
     t1 = time.perf_counter()
@@ -542,6 +545,7 @@ def main():
         "p50_solve_ms": round(float(np.percentile(ms_all, 50)), 3),
         "p99_solve_ms": round(float(np.percentile(ms_all, 99)), 3),
         "iterations_per_leg": [int(r["iters"].sum()) for r in head["recs"]],
+        "kernel_launches_per_iteration": round(head["launches"] / max(1, sum(int(r["iters"].sum()) for r in head["recs"])), 1),
         "fp64_plain": None if plain is None else {
             "value": round(v64, 3), "ms_per_step": round(plain["elapsed"] / args.fp64_steps * 1e3, 3),
             "p50_solve_ms": round(float(np.percentile(ms64, 50)), 3),

@@ -97,7 +97,7 @@ typedef struct bl_opts {
   double tol;           /* stop when ||A e_i - lambda_i M e_i||_2 / (lambda_i ||M e_i||_2)
                            <= tol for the first nev vectors (1e-8)                         */
   double mu;            /* regularisation of the preconditioned A + mu M (Section 5);
-                           <= 0 selects mu = lambda_p(eps_min) / 10 of the homogeneous
+                           <= 0 selects mu = max(lambda_p / 40, lambda_1 / 2) of the homogeneous
                            cell at k = 0, p = nev + nthrow                                 */
   double zero_rel;      /* extrapolation skips Ritz values below zero_rel times the
                            smallest eigenvalue of the previous parameter (1e-2)            */
@@ -123,7 +123,7 @@ typedef struct bl_opts {
                            engine's device buffers; needs a coarsest level of at most 512
                            edges (checked at creation).  0 = the block in the slot (0)      */
   double nested_tol;    /* relative residual to which the levels below the finest are
-                           iterated in the nested start; 0 selects 1e-3                    */
+                           iterated in the nested start; 0 selects 1e-2                    */
 } bl_opts;
 
 /* Read-only facts about a solver handle. */

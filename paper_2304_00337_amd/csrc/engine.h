@@ -22,6 +22,9 @@ constexpr int kMaxLevels = 16;
 constexpr int64_t kMaxCoarse = 2048;   // largest coarsest-level edge count solved densely
 constexpr int64_t kMaxNestedCoarse = 512;   // largest coarsest pencil of the nested start (Ritz kernel)
 constexpr int kMaxSlots = 256;
+// default shift of the preconditioned A + mu M: lambda_p of the homogeneous cell (eps_min,
+// k = 0) over this divisor, at least half of its lambda_1 (Section 5 leaves mu open)
+constexpr double kMuDivisor = 40.0;
 constexpr int kMaxLists = 32;          // device slot lists alive between two synchronisations
 
 // One problem: a path of Bloch parameters on one permittivity.

@@ -755,8 +755,13 @@ bool set_phase(bl_solver* s, int sl, double k1, double k2) {
 
 // Permittivity of slot `sl`: kappa on every level, mu, stabilised patch factors.
 int load_eps(bl_solver* s, int sl, const std::vector<double>& kappa, double eps_min) {
-  const double mu = (s->opts.mu > 0) ? s->opts.mu
-                                     : homogeneous_lambda(s->grid.n, s->grid.m, s->grid.a, s->grid.b, eps_min, s->p) / 10.0;
+  // default shift (Section 5 leaves it open): half the first non-zero eigenvalue of the
+  // homogeneous cell, or lambda_p / 40 when larger; much smaller shifts amplify the gradient
+  // part that the inexact nodal projection leaves faster than the projection removes it
+  const double mu = (s->opts.mu > 0)
+                        ? s->opts.mu
+                        : std::max(homogeneous_lambda(s->grid.n, s->grid.m, s->grid.a, s->grid.b, eps_min, s->p) / kMuDivisor,
+                                   homogeneous_lambda(s->grid.n, s->grid.m, s->grid.a, s->grid.b, eps_min, 1) / 2.0);
   s->mu_h[sl] = mu;
   s->slot[sl].mu = mu;
   s->slot[sl].kappa_max = eps_min > 0 ? 1.0 / eps_min : 1.0;
@@ -919,7 +924,7 @@ int nested_start_slot(bl_solver* s, int sl, double k1, double k2, int nev, std::
   s->lists_used = 0;
   if ((rc = check_hip())) return rc;
   if (s->count_h[sl] < p) return set_error(BL_ENOCONV, "the coarsest mesh has fewer than p non-zero eigenvalues%s");
-  const double tol = s->opts.nested_tol > 0 ? s->opts.nested_tol : 1e-3;
+  const double tol = s->opts.nested_tol > 0 ? s->opts.nested_tol : 1e-2;
   for (int l = lc - 1; l >= 0 && !rc; --l) {
     prolong_block(s, sl, l);
     if (l == 0) break;
