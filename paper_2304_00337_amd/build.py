@@ -17,6 +17,9 @@ SOURCES = ["csrc/stencils.hip", "csrc/dense.hip", "csrc/ritz.hip", "csrc/solver.
            "csrc/sweep.hip", "csrc/planewave.hip",
            "csrc/noalloc.hip"]
 LIB = os.path.join(PKG, "libbloch.so")
+# per-source flags: the block combination keeps its MFMA accumulators in ordinary VGPRs (the
+# default heuristic moves them between register files on every step of its loop)
+EXTRA_FLAGS = {"csrc/dense.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def hipcc() -> str:
@@ -37,7 +40,7 @@ def build(verbose: bool = False) -> str:
     procs = []
     for src in SOURCES:
         obj = os.path.join(objdir, os.path.basename(src).replace(".hip", ".o"))
-        cmd = [hipcc(), *flags, "-c", os.path.join(PKG, src), "-o", obj]
+        cmd = [hipcc(), *flags, *EXTRA_FLAGS.get(src, []), "-c", os.path.join(PKG, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT), src))

@@ -261,14 +261,19 @@ namespace {
 
 // Block combination out_s = S_s Y_s on the matrix cores (FP64 MFMA 16x16x4), computed as
 // out^T = Y^T S^T so that each lane's results are consecutive rows of one output column
-// (coalesced stores): the A operand is Y (staged in LDS, real and imaginary parts apart,
-// zero-padded to whole tiles), the B operand the basis rows straight from memory, four real
-// products per complex one.  Each wave owns BCR rows and the NTC output column tiles of its
-// workgroup (blockIdx.y selects the tile group when the block is wider); the next four basis
-// columns are loaded while the current ones are multiplied.
+// (coalesced stores): the A operand is Y (staged in LDS once per workgroup, real and
+// imaginary parts apart, zero-padded to whole tiles), the B operand the basis rows straight
+// from memory.  A complex product takes three real ones (Gauss's three-multiplication form):
+//   P1 = Yr Sr,  P2 = Yi Si,  P3 = (Yr + Yi)(Sr + Si),  Re = P1 - P2,  Im = P3 - P1 - P2,
+// each summed over the basis columns in its own accumulator.  The workgroups are persistent:
+// each wave walks row tiles of BCR rows (tile t, t + stride, ...) for the NTC output column
+// tiles of its workgroup (blockIdx.y selects the tile group when the block is wider), one
+// stream of steps of four basis columns across its tiles, with the columns two steps ahead
+// (possibly of the next tile) loaded while the current ones are multiplied.  (The file is
+// compiled with MFMA results in ordinary VGPRs, so the accumulators stay put across the loop.)
 typedef double bd4 __attribute__((ext_vector_type(4)));
 constexpr int BCW = 4;    // waves per workgroup
-constexpr int BCR = 32;   // rows per wave (two 16-row tiles)
+constexpr int BCR = 32;   // rows per tile (two 16-row MFMA tiles)
 
 template <int NTC>
 __global__ __launch_bounds__(64 * BCW) void k_block_combine(View<const double> Sv, int q, const c2* __restrict__ Y,
@@ -284,77 +289,122 @@ __global__ __launch_bounds__(64 * BCW) void k_block_combine(View<const double> S
   Y += (int64_t)slot * q * want;
   double* yr = yl;
   double* yi = yl + (size_t)q4 * WC;
-  for (int e = threadIdx.x; e < q4 * WC; e += blockDim.x) {
-    const int l = e / WC, c = cbase + e % WC;
-    const c2 v = (l < q && c < want) ? Y[(int64_t)l * want + c] : c2{0, 0};
-    yr[e] = v.r;
-    yi[e] = v.i;
+  {
+    // all of a thread's loads first, then the stores
+    constexpr int PER = 8;
+    for (int e0 = threadIdx.x; e0 < q4 * WC; e0 += PER * (int)blockDim.x) {
+      c2 v[PER];
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int e = e0 + u * (int)blockDim.x, l = e / WC, c = cbase + e % WC;
+        v[u] = (e < q4 * WC && l < q && c < want) ? Y[(int64_t)l * want + c] : c2{0, 0};
+      }
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int e = e0 + u * (int)blockDim.x;
+        if (e < q4 * WC) {
+          yr[e] = v[u].r;
+          yi[e] = v[u].i;
+        }
+      }
+    }
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t row0 = ((int64_t)blockIdx.x * BCW + wv) * BCR;
-  if (row0 >= len) return;
+  const int64_t ntiles = (len + BCR - 1) / BCR;
+  const int64_t tstride = (int64_t)gridDim.x * BCW;
+  int64_t ct = (int64_t)blockIdx.x * BCW + wv;   // tile being multiplied
+  if (ct >= ntiles) return;
   const int kk = lane >> 4, cc = lane & 15;
-  bd4 acr[2][NTC], aci[2][NTC];
+  bd4 p1[2][NTC], p2[2][NTC], p3[2][NTC];
 #pragma unroll
   for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
-    for (int ct = 0; ct < NTC; ++ct) acr[rt][ct] = aci[rt][ct] = bd4{0, 0, 0, 0};
-  int64_t rows[2];
-  bool rok[2];
-#pragma unroll
-  for (int rt = 0; rt < 2; ++rt) {
-    rows[rt] = row0 + 16 * rt + cc;
-    rok[rt] = rows[rt] < len;
-  }
-  auto load = [&](int l0, double* sr, double* si) {
+    for (int c = 0; c < NTC; ++c) p1[rt][c] = p2[rt][c] = p3[rt][c] = bd4{0, 0, 0, 0};
+  // basis column l0 + kk of this lane's two rows of tile t (zero past the basis, the rows or
+  // the last tile)
+  auto load = [&](int64_t t, int l0, double* sr, double* si) {
     const int l = l0 + kk;
+    const int64_t off = (int64_t)(l < q ? l : q - 1) * 2 * len;
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt) {
-      const bool ok = l < q && rok[rt];
-      const double* col = S + (int64_t)(ok ? l : 0) * 2 * len;
-      const int64_t r = ok ? rows[rt] : 0;
-      const double a = col[r], b = col[len + r];
+      const int64_t row = t * BCR + 16 * rt + cc;
+      const bool ok = t < ntiles && l < q && row < len;
+      const double* rp = S + (ok ? row : 0) + (ok ? off : 0);
+      const double a = rp[0], b = rp[len];
       sr[rt] = ok ? a : 0.0;
       si[rt] = ok ? b : 0.0;
     }
   };
-  double sr[2], si[2], nr[2], ni[2];
-  load(0, sr, si);
-  for (int l0 = 0; l0 < q4; l0 += 4) {
-    if (l0 + 4 < q4) load(l0 + 4, nr, ni);
-    const int l = l0 + kk;
+  // prefetch position (tile pt, columns pl0 ..), two steps ahead of the multiplication
+  int64_t pt = ct;
+  int pl0 = 0;
+  auto advance = [&]() {
+    pl0 += 4;
+    if (pl0 >= q4) {
+      pl0 = 0;
+      pt += tstride;
+    }
+  };
+  double s0r[2], s0i[2], s1r[2], s1i[2], s2r[2], s2i[2];
+  load(pt, pl0, s0r, s0i);
+  advance();
+  load(pt, pl0, s1r, s1i);
+  advance();
+  int cl0 = 0;
+  for (;;) {
+    load(pt, pl0, s2r, s2i);
+    advance();
+    const int l = cl0 + kk;
+    double ss[2];
 #pragma unroll
-    for (int ct = 0; ct < NTC; ++ct) {
-      const double ar = yr[l * WC + 16 * ct + cc], ai = yi[l * WC + 16 * ct + cc];
+    for (int rt = 0; rt < 2; ++rt) ss[rt] = s0r[rt] + s0i[rt];
+#pragma unroll
+    for (int c = 0; c < NTC; ++c) {
+      const double yre = yr[l * WC + 16 * c + cc], yim = yi[l * WC + 16 * c + cc];
+      const double ys = yre + yim;
 #pragma unroll
       for (int rt = 0; rt < 2; ++rt) {
-        acr[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, sr[rt], acr[rt][ct], 0, 0, 0);
-        acr[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, si[rt], acr[rt][ct], 0, 0, 0);
-        aci[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, si[rt], aci[rt][ct], 0, 0, 0);
-        aci[rt][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, sr[rt], aci[rt][ct], 0, 0, 0);
+        p1[rt][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(yre, s0r[rt], p1[rt][c], 0, 0, 0);
+        p2[rt][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(yim, s0i[rt], p2[rt][c], 0, 0, 0);
+        p3[rt][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ys, ss[rt], p3[rt][c], 0, 0, 0);
       }
     }
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt) {
-      sr[rt] = nr[rt];
-      si[rt] = ni[rt];
+      s0r[rt] = s1r[rt];
+      s0i[rt] = s1i[rt];
+      s1r[rt] = s2r[rt];
+      s1i[rt] = s2i[rt];
     }
-  }
-  // accumulator entry v of lane (kk, cc) is output column 16 ct + 4 v + kk of row row0 + 16 rt + cc
-  // (the 16 x 16 result of the instruction has row 4 v + lane / 16 and column lane % 16)
+    cl0 += 4;
+    if (cl0 < q4) continue;
+    // tile ct done: accumulator entry v of lane (kk, cc) is output column 16 c + 4 v + kk of
+    // row 16 rt + cc of the tile (the 16 x 16 result of the instruction has row 4 v + lane / 16
+    // and column lane % 16)
 #pragma unroll
-  for (int rt = 0; rt < 2; ++rt)
+    for (int rt = 0; rt < 2; ++rt) {
+      const int64_t row = ct * BCR + 16 * rt + cc;
 #pragma unroll
-    for (int ct = 0; ct < NTC; ++ct)
+      for (int c = 0; c < NTC; ++c)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int c = cbase + 16 * ct + 4 * v + kk;
-        if (c < want && rok[rt]) {
-          out[(int64_t)c * 2 * len + rows[rt]] = acr[rt][ct][v];
-          out[(int64_t)c * 2 * len + len + rows[rt]] = aci[rt][ct][v];
+        for (int v = 0; v < 4; ++v) {
+          const int col = cbase + 16 * c + 4 * v + kk;
+          if (col < want && row < len) {
+            const double a = p1[rt][c][v], b = p2[rt][c][v];
+            out[(int64_t)col * 2 * len + row] = a - b;
+            out[(int64_t)col * 2 * len + len + row] = (p3[rt][c][v] - a) - b;
+          }
         }
-      }
+    }
+    ct += tstride;
+    if (ct >= ntiles) break;
+    cl0 = 0;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int c = 0; c < NTC; ++c) p1[rt][c] = p2[rt][c] = p3[rt][c] = bd4{0, 0, 0, 0};
+  }
 }
 
 }  // namespace
@@ -363,15 +413,28 @@ void block_combine(View<const double> S, int q, const double* Y, int want, int64
                    View<double> out, const Launch& L) {
   if (L.nact <= 0 || want <= 0) return;
   const int q4 = (q + 3) & ~3;
-  const int64_t rows_per_wg = (int64_t)BCW * BCR;
   const int ntc = (want + 15) / 16;
   // column tiles per workgroup: up to three, as many as the staged Y allows in 160 KB of LDS
   const size_t tile_lds = (size_t)2 * q4 * 16 * sizeof(double);
   int per = 3;
   while (per > 1 && tile_lds * per > (size_t)160 * 1024) --per;
   if (per > ntc) per = ntc;
-  const dim3 grid((unsigned)((len + rows_per_wg - 1) / rows_per_wg), (unsigned)((ntc + per - 1) / per),
-                  (unsigned)L.nact);
+  const int ny = (ntc + per - 1) / per;
+  // persistent workgroups: as many as stay resident together (by LDS, at most two per compute
+  // unit), spread over the column groups and slots of the launch
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+      cus = 256;
+  }
+  const int per_cu = tile_lds * per <= (size_t)80 * 1024 ? 2 : 1;
+  const int64_t tiles_wg = ((len + BCR - 1) / BCR + BCW - 1) / BCW;
+  int64_t nx = ((int64_t)cus * per_cu + (int64_t)ny * L.nact - 1) / ((int64_t)ny * L.nact);
+  if (nx < 1) nx = 1;
+  if (nx > tiles_wg) nx = tiles_wg;
+  const dim3 grid((unsigned)nx, (unsigned)ny, (unsigned)L.nact);
   auto go = [&](auto nt) {
     constexpr int NTC = decltype(nt)::value;
     static bool attr = false;

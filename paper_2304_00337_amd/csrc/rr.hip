@@ -220,7 +220,7 @@ template <int NG>
 struct RRStage {
   double2 x[XS][SW][RRConf<NG>::CP];
   double2 y[2][YW][RRConf<NG>::CP];
-  double w[2][SW];
+  double2 w[2][SW];   // scaled curl weight of the row's cells (first component)
 };
 
 // Staged column c of a workgroup with group bases cA (and cB): global column.
@@ -229,70 +229,85 @@ __device__ __forceinline__ int staged_col(int c, int cA, int cB) {
   return (NG == 1 || c < MQ) ? cA + c : cB + (c - MQ);
 }
 
-// Staged item e of a row pair: x-edge (node, column) of row xrow for e < SW NC, then y-edge
-// (halo node, column) of row yrow, then the cell coefficient kappa of the cells of row yrow.
-// rr_fetch issues the loads only (from a valid address in every case, so that no value is
-// waited for before it is stored), with a code for what rr_put applies: bit 3 zero (not
-// wanted, or outside the basis / grid), bits 0-1 the Bloch factor (1: times the phase, 2:
-// times its conjugate), bit 2 the factor is alpha (y halo) instead of beta (x rows).
+// Staged item e of a row pair: x-edge (node, column) of a row for e < SW NC, then y-edge
+// (halo node, column) of a row, then the cell coefficient kappa of the cells of that row.
+// What does not change from row to row is worked out once per thread (RRItem): the address
+// of the item's value in row 0, its LDS position within a row slot, its kind, the Bloch
+// factor of a y halo node (alpha or its conjugate past the slice's left / right end of the
+// period) and whether it lies inside the basis and the grid.  A row then costs a pointer
+// offset, two loads and, at the store, the Bloch factor of the row (x rows one period up or
+// back take beta or its conjugate) or of the halo node.
+struct RRItem {
+  const double* base;   // value of the item in row 0; the slot's first value when not in use
+  int info;             // LDS offset (bits 0-15), kind (16-17: 0 x, 1 y, 2 kappa, 3 none),
+                        // halo phase (18-19: 1 times alpha, 2 times conj(alpha)), in use (20)
+};
 struct RRRaw {
   double a, b;
-  int code;
 };
 
 template <int NG>
-__device__ __forceinline__ RRRaw rr_fetch(int e, const double* S, int q, int64_t N, int64_t nm, int n, int m,
-                                          const double* kap, int c0, int xrow, int yrow, bool want, int cA, int cB) {
-  // branch-free: the three kinds' addresses are formed side by side and selected, and every
-  // lane issues its two loads, so that nothing waits for the values here
-  constexpr int NX = SW * RRConf<NG>::NC, NY = YW * RRConf<NG>::NC;
-  const bool isx = e < NX, isy = !isx && e < NX + NY, isw = !isx && !isy;
-  const int ey = e - NX, ew = e - NX - NY;
-  // x-edge rows: the row's wrap is the same for the whole workgroup
-  int r = xrow, cx = 0;
-  if (r < 0) { r += m; cx = 2; } else if (r >= m) { r -= m; cx = 1; }
-  const int colx = staged_col<NG>(e / SW, cA, cB), jx = c0 + e % SW;
-  const bool okx = colx < q && jx < n;
-  // y-edge halo
-  const int coly = staged_col<NG>(ey / YW, cA, cB);
-  int jy = c0 - 1 + ey % YW, cy = 4;
-  cy = jy < 0 ? (cy | 2) : (jy == n ? (cy | 1) : cy);
-  const bool oky = coly < q && jy <= n;
-  jy = jy < 0 ? jy + n : (jy == n ? 0 : jy);
-  // curl weight
-  const int jw = c0 + ew;
-  const bool okw = jw < n;
-  const bool ok = want && (isx ? okx : (isy ? oky : okw));
-  const int col = isx ? colx : coly;
-  const double* base = isw ? kap : S + (int64_t)((ok && col < q) ? col : 0) * 2 * N;
-  int64_t off = isx ? (int64_t)r * n + jx : (isy ? nm + (int64_t)yrow * n + jy : (int64_t)yrow * n + jw);
-  off = ok ? off : 0;
-  const int64_t str = isw ? 0 : N;
-  const int code = ok ? (isx ? cx : (isy ? cy : 0)) : 8;
-  return RRRaw{base[off], base[off + str], code};
+__device__ __forceinline__ RRItem rr_plan(int e, const double* S, int q, int64_t N, int64_t nm, int n,
+                                          const double* kap, int c0, int cA, int cB) {
+  constexpr int NC = RRConf<NG>::NC, CP = RRConf<NG>::CP, NX = SW * NC, NY = YW * NC;
+  if (e >= RRConf<NG>::ITEMS) return RRItem{S, 3 << 16};
+  if (e < NX) {
+    const int col = staged_col<NG>(e / SW, cA, cB), j = c0 + e % SW;
+    const bool ok = col < q && j < n;
+    return RRItem{ok ? S + (int64_t)col * 2 * N + j : S, ((e % SW) * CP + e / SW) | (ok ? 1 << 20 : 0)};
+  }
+  if (e < NX + NY) {
+    const int ey = e - NX;
+    const int col = staged_col<NG>(ey / YW, cA, cB);
+    int j = c0 - 1 + ey % YW;
+    const int ph = j < 0 ? 2 : (j == n ? 1 : 0);
+    const bool ok = col < q && j <= n;
+    j = j < 0 ? j + n : (j == n ? 0 : j);
+    return RRItem{ok ? S + (int64_t)col * 2 * N + nm + j : S,
+                  ((ey % YW) * CP + ey / YW) | (1 << 16) | (ph << 18) | (ok ? 1 << 20 : 0)};
+  }
+  const int ew = e - NX - NY, j = c0 + ew;
+  const bool ok = j < n;
+  return RRItem{ok ? kap + j : kap, ew | (2 << 16) | (ok ? 1 << 20 : 0)};
 }
 
-// store item e (applying its code) into the x slot / y slot
+// Issue the item's loads for x row offset xoff / y row offset yoff (in values); an item not in
+// use (or a row not wanted) reads its base, a valid address.
+__device__ __forceinline__ RRRaw rr_load(const RRItem& it, int64_t xoff, int64_t yoff, bool want, int64_t N) {
+  const int kind = (it.info >> 16) & 3;
+  const bool use = want && (it.info & (1 << 20));
+  const int64_t off = use ? (kind == 0 ? xoff : yoff) : 0;
+  const double* ptr = it.base + off;
+  return RRRaw{ptr[0], ptr[kind == 2 ? 0 : N]};
+}
+
+// Store the item into its x slot / y slot / weight slot, with the Bloch factor of its row
+// (x: code xcode, uniform over the workgroup; 1 times beta, 2 times conj(beta)) or of its halo
+// node (y); zero when not in use.
 template <int NG>
-__device__ __forceinline__ void rr_put(RRStage<NG>& st, int e, const RRRaw& raw, const Ph<double>& p, double s,
-                                       int xslot, int yslot, bool with_x, bool with_y) {
-  constexpr int NX = SW * RRConf<NG>::NC, NY = YW * RRConf<NG>::NC;
-  const bool zero = (raw.code & 8) != 0;
-  if (e >= NX + NY) {
-    if (with_y) st.w[yslot][e - NX - NY] = zero ? 0.0 : sqrt(raw.a * s);
-    return;
-  }
+__device__ __forceinline__ void rr_store(RRStage<NG>& st, const RRItem& it, const RRRaw& raw, bool want, int xcode,
+                                         const Ph<double>& p, double s, int xslot, int yslot, bool with_y) {
+  const int kind = (it.info >> 16) & 3;
+  if (kind == 3 || (kind != 0 && !with_y)) return;
+  const bool use = want && (it.info & (1 << 20));
   Cx<double> v = {raw.a, raw.b};
-  const double fr = (raw.code & 4) ? p.ar : p.br, fi = (raw.code & 4) ? p.ai : p.bi;
-  if (raw.code & 1) v = cmul(v, fr, fi);
-  else if (raw.code & 2) v = cmul(v, fr, -fi);
-  const double2 w = zero ? double2{0.0, 0.0} : double2{v.re, v.im};
-  if (e < NX) {
-    if (with_x) st.x[xslot][e % SW][e / SW] = w;
+  if (kind == 0) {
+    if (xcode) v = cmul(v, p.br, xcode & 2 ? -p.bi : p.bi);
+  } else if (kind == 1) {
+    const int hcode = (it.info >> 18) & 3;
+    if (hcode) v = cmul(v, p.ar, hcode & 2 ? -p.ai : p.ai);
   } else {
-    e -= NX;
-    if (with_y) st.y[yslot][e % YW][e / YW] = w;
+    v = Cx<double>{sqrt(raw.a * s), 0.0};
   }
+  double2* dst = kind == 0 ? &st.x[xslot][0][0] : (kind == 1 ? &st.y[yslot][0][0] : &st.w[yslot][0]);
+  dst[it.info & 0xffff] = use ? double2{v.re, v.im} : double2{0.0, 0.0};
+}
+
+// x row xr (in [-1, m + 1]) of the extended grid: its stored row offset and Bloch code
+__device__ __forceinline__ void rr_xrow(int xr, int n, int m, int64_t& off, int& code) {
+  code = 0;
+  if (xr < 0) { xr += m; code = 2; } else if (xr >= m) { xr -= m; code = 1; }
+  off = (int64_t)xr * n;
 }
 
 // Group bases of workgroup row blockIdx.y: NG = 1, diagonal block y (columns 48 y ..);
@@ -362,7 +377,7 @@ __device__ __forceinline__ void cross_h(const RRStage<2>& st, int s0, int sp, in
 #pragma unroll
   for (int gsub = 0; gsub < 2; ++gsub) {
     const int jn = nb8 + 4 * gsub + (lane >> 4);
-    const double wsc = st.w[sy][jn];
+    const double wsc = st.w[sy][jn].x;
     double wr[2 * MT], wi[2 * MT];
 #pragma unroll
     for (int tt = 0; tt < 2 * MT; ++tt) {
@@ -397,7 +412,7 @@ __global__ __launch_bounds__(RR_THREADS) void k_rr_mfma(View<const double> Sv, i
                                                         int ngroups, double* __restrict__ partial,
                                                         const int* __restrict__ slots) {
   using C = RRConf<NG>;
-  constexpr int NT = C::NT, MP = C::MP, ITEMS = C::ITEMS, PT = C::PER_THREAD;
+  constexpr int NT = C::NT, MP = C::MP, PT = C::PER_THREAD;
   extern __shared__ double lds[];
   RRStage<NG>& st = *reinterpret_cast<RRStage<NG>*>(lds);
   const int slot = slots ? slots[blockIdx.z] : (int)blockIdx.z;
@@ -416,30 +431,34 @@ __global__ __launch_bounds__(RR_THREADS) void k_rr_mfma(View<const double> Sv, i
   const int w = is_h ? wv - MW : wv;
   const int tid = threadIdx.x;
   auto xslot = [&](int e) { return (e - r0 + 1) & (XS - 1); };
+  RRItem items[PT];
+#pragma unroll
+  for (int u = 0; u < PT; ++u) items[u] = rr_plan<NG>(tid + u * RR_THREADS, S, q, N, nm, n, kap, c0, cA, cB);
   // rows r0-1, r0, r0+1 (x) and r0 (y) straight into LDS (all loads issued first)
   {
     RRRaw ini[3][PT];
+    int xc[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      int64_t xo;
+      rr_xrow(r0 - 1 + k, n, m, xo, xc[k]);
+#pragma unroll
+      for (int u = 0; u < PT; ++u) ini[k][u] = rr_load(items[u], xo, (int64_t)r0 * n, true, N);
+    }
 #pragma unroll
     for (int k = 0; k < 3; ++k)
 #pragma unroll
-      for (int u = 0; u < PT; ++u) {
-        const int e = tid + u * RR_THREADS;
-        ini[k][u] = rr_fetch<NG>(e < ITEMS ? e : 0, S, q, N, nm, n, m, kap, c0, r0 - 1 + k, r0, e < ITEMS, cA, cB);
-      }
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-      for (int u = 0; u < PT; ++u) {
-        const int e = tid + u * RR_THREADS;
-        if (e < ITEMS) rr_put<NG>(st, e, ini[k][u], p, g.s, xslot(r0 - 1 + k), r0 & 1, true, k == 1);
-      }
+      for (int u = 0; u < PT; ++u)
+        rr_store<NG>(st, items[u], ini[k][u], true, xc[k], p, g.s, xslot(r0 - 1 + k), r0 & 1, k == 1);
   }
   // prefetch of rows r0+2 (x) and r0+1 (y)
   RRRaw pf[PT];
+  int pf_code;
+  {
+    int64_t xo;
+    rr_xrow(r0 + 2, n, m, xo, pf_code);
 #pragma unroll
-  for (int u = 0; u < PT; ++u) {
-    const int e = tid + u * RR_THREADS;
-    pf[u] = rr_fetch<NG>(e < ITEMS ? e : 0, S, q, N, nm, n, m, kap, c0, r0 + 2, r0 + 1, e < ITEMS && r0 + 1 < r1, cA, cB);
+    for (int u = 0; u < PT; ++u) pf[u] = rr_load(items[u], xo, (int64_t)(r0 + 1) * n, r0 + 1 < r1, N);
   }
   constexpr int NA = NG == 1 ? MP : 5;   // accumulators per wave (cross blocks: half the pairs)
   d4 ar[NA], ai[NA];
@@ -453,15 +472,13 @@ __global__ __launch_bounds__(RR_THREADS) void k_rr_mfma(View<const double> Sv, i
     __syncthreads();   // rows up to r + 1 staged; the slots written below are no longer read
     if (r + 1 < r1) {
 #pragma unroll
-      for (int u = 0; u < PT; ++u) {
-        const int e = tid + u * RR_THREADS;
-        if (e < ITEMS) rr_put<NG>(st, e, pf[u], p, g.s, xslot(r + 2), (r + 1) & 1, true, true);
-      }
+      for (int u = 0; u < PT; ++u)
+        rr_store<NG>(st, items[u], pf[u], true, pf_code, p, g.s, xslot(r + 2), (r + 1) & 1, true);
+      int64_t xo;
+      rr_xrow(r + 3, n, m, xo, pf_code);
+      const bool want = r + 2 < r1;
 #pragma unroll
-      for (int u = 0; u < PT; ++u) {
-        const int e = tid + u * RR_THREADS;
-        pf[u] = rr_fetch<NG>(e < ITEMS ? e : 0, S, q, N, nm, n, m, kap, c0, r + 3, r + 2, e < ITEMS && r + 2 < r1, cA, cB);
-      }
+      for (int u = 0; u < PT; ++u) pf[u] = rr_load(items[u], xo, (int64_t)(r + 2) * n, want, N);
     }
     const int sm = xslot(r - 1), s0 = xslot(r), sp = xslot(r + 1), sy = r & 1;
     if (NG == 2) {
@@ -505,7 +522,7 @@ __global__ __launch_bounds__(RR_THREADS) void k_rr_mfma(View<const double> Sv, i
     } else {
       // H = sum over cells of (kappa s) conj(w) w, w the cell curl
       double wr[NT], wi[NT];
-      const double wsc = st.w[sy][jn];
+      const double wsc = st.w[sy][jn].x;
 #pragma unroll
       for (int tt = 0; tt < NT; ++tt) {
         const int c = 16 * tt + cl;
