@@ -221,6 +221,13 @@ __device__ __forceinline__ Cx<T> pick_cx(bool c, Cx<T> a, Cx<T> b) {
 // coarse Nedelec function (1/2 of the coarse edge's value on its halves, 1/4 of the two
 // parallel coarse edges' values in between).  The transfers form every candidate and select
 // one, so that lanes of either parity run the same instructions.
+// A fine edge from the coarse edge a it lies on (even position across the edge direction:
+// half of it) or from the two coarse edges a, b it lies between (odd: a quarter of their sum).
+template <typename T>
+__device__ __forceinline__ Cx<T> edge_prolong_combine(const Cx<T>& a, const Cx<T>& b, bool odd) {
+  return pick_cx<T>(!odd, (T)0.5 * a, (T)0.25 * (a + b));
+}
+
 template <typename T>
 __device__ __forceinline__ Cx<T> edge_prolong_xy(const T* c, const Geo& gc, int comp, int f1, int f2,
                                                  const Ph<T>& p) {
@@ -230,12 +237,12 @@ __device__ __forceinline__ Cx<T> edge_prolong_xy(const T* c, const Geo& gc, int 
     const int J1 = f1 >> 1, J2 = f2 >> 1;
     const Cx<T> a = fetch<T, T>(c, Nc, nc, mc, 0, J1, J2, p);
     const Cx<T> b = fetch<T, T>(c, Nc, nc, mc, 0, J1, J2 + 1, p);
-    return pick_cx<T>((f2 & 1) == 0, (T)0.5 * a, (T)0.25 * (a + b));
+    return edge_prolong_combine<T>(a, b, (f2 & 1) != 0);
   }
   const int J1 = f1 >> 1, J2 = f2 >> 1;
   const Cx<T> a = fetch<T, T>(c, Nc, nc, mc, nmc, J1, J2, p);
   const Cx<T> b = fetch<T, T>(c, Nc, nc, mc, nmc, J1 + 1, J2, p);
-  return pick_cx<T>((f1 & 1) == 0, (T)0.5 * a, (T)0.25 * (a + b));
+  return edge_prolong_combine<T>(a, b, (f1 & 1) != 0);
 }
 
 // Fine edge d of (Pr x_c).
@@ -298,6 +305,18 @@ __device__ __forceinline__ Cx<T> nodal_restrict_at(const T* r, const Geo& gf, co
 }
 
 // Fine node (f1, f2) of the bilinear interpolation of the coarse nodal function.
+// Bilinear interpolation at a fine node from the four coarse values around it (coarse node
+// (J1, J2) = fine (f1 >> 1, f2 >> 1) and its neighbours one up in x, y and both); o1, o2 the
+// parities of f1, f2.
+template <typename T>
+__device__ __forceinline__ Cx<T> nodal_prolong_combine(const Cx<T>& c00, const Cx<T>& c10, const Cx<T>& c01,
+                                                       const Cx<T>& c11, bool o1, bool o2) {
+  const Cx<T> vx = (T)0.5 * (c00 + c10);                   // odd f1, even f2
+  const Cx<T> vy = (T)0.5 * (c00 + c01);                   // even f1, odd f2
+  const Cx<T> vd = (T)0.25 * (c00 + c10 + c01 + c11);      // both odd
+  return pick_cx<T>(o1, pick_cx<T>(o2, vd, vx), pick_cx<T>(o2, vy, c00));
+}
+
 template <typename T>
 __device__ __forceinline__ Cx<T> nodal_prolong_xy(const T* c, const Geo& gc, int f1, int f2, const Ph<T>& p) {
   const int J1 = f1 >> 1, J2 = f2 >> 1;
@@ -306,10 +325,7 @@ __device__ __forceinline__ Cx<T> nodal_prolong_xy(const T* c, const Geo& gc, int
   const Cx<T> c10 = fetch<T, T>(c, gc.nm, gc.n, gc.m, 0, J1 + 1, J2, p);
   const Cx<T> c01 = fetch<T, T>(c, gc.nm, gc.n, gc.m, 0, J1, J2 + 1, p);
   const Cx<T> c11 = fetch<T, T>(c, gc.nm, gc.n, gc.m, 0, J1 + 1, J2 + 1, p);
-  const Cx<T> vx = (T)0.5 * (c00 + c10);                   // odd f1, even f2
-  const Cx<T> vy = (T)0.5 * (c00 + c01);                   // even f1, odd f2
-  const Cx<T> vd = (T)0.25 * (c00 + c10 + c01 + c11);      // both odd
-  return pick_cx<T>(o1, pick_cx<T>(o2, vd, vx), pick_cx<T>(o2, vy, c00));
+  return nodal_prolong_combine<T>(c00, c10, c01, c11, o1, o2);
 }
 
 // Fine node d of the bilinear interpolation of the coarse nodal function.

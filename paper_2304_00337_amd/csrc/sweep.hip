@@ -381,8 +381,13 @@ __global__ __launch_bounds__(kMaxThreads) void k_edge_sweep(View<const T> xin, V
   constexpr int LO = RES ? kLoR : kLo;
   constexpr int BX = TX + LO + (RES ? kHiER : kHiE), BY = TY + LO + (RES ? kHiER : kHiE);
   using S = Split<BX, BY>;
+  // coarse edges under the box (prolongating sweeps of boxes inside the period, FP32): fine box
+  // position b lies over coarse box position b >> 1 and its neighbours one up
+  constexpr bool STAGE = PRO && sizeof(T) == 4;
+  constexpr int CBX = (BX - 1) / 2 + 2, CBY = (BY - 1) / 2 + 2, CB = CBX * CBY;
   __shared__ T pl[4 * S::N];
   __shared__ T rl[RES ? 4 * (TX + 1) * (TY + 1) : 1];
+  __shared__ T cl[STAGE ? 4 * CB : 1];   // x-edge re, im, y-edge re, im
   const TileRef tr = tile_ref(slots, ncps, tiles_x, TX, TY);
   const int n = g.n, m = g.m, tid = threadIdx.x;
   const int64_t N = g.ne, nm = g.nm;
@@ -397,23 +402,71 @@ __global__ __launch_bounds__(kMaxThreads) void k_edge_sweep(View<const T> xin, V
   } else {
     const T* xc = colp(xin, sj, N);
     const T* cc = PRO ? colp(fz.xc, sj, fz.gc.ne) : nullptr;
-    for (int e = tid; e < BX * BY; e += nthreads()) {
-      const int bx = e % BX, by = e / BX;
-      const int c1 = cx ? wrapm(ox + bx, n) : ox + bx, c2 = cy ? wrapm(oy + by, m) : oy + by;
-      const int64_t i = (int64_t)c2 * n + c1;
-      const int k = S::at(bx, by);
-      if constexpr (PRO) {   // as the prolongation kernel: x + Pr xc
-        const Cx<T> vx = edge_prolong_xy<T>(cc, fz.gc, 0, c1, c2, p);
-        const Cx<T> vy = edge_prolong_xy<T>(cc, fz.gc, 1, c1, c2, p);
-        pl[k] = xc[i] + vx.re;
-        pl[S::N + k] = xc[N + i] + vx.im;
-        pl[2 * S::N + k] = xc[nm + i] + vy.re;
-        pl[3 * S::N + k] = xc[N + nm + i] + vy.im;
-      } else {
-        pl[k] = xc[i];
-        pl[S::N + k] = xc[N + i];
-        pl[2 * S::N + k] = xc[nm + i];
-        pl[3 * S::N + k] = xc[N + nm + i];
+    if (STAGE && !cx && !cy) {
+      // as the prolongation kernel, x + Pr xc, with the coarse edges (as fetch() returns them
+      // at the box's coarse positions, ox and oy being even) staged once in LDS, and the
+      // iterate's loads issued four positions at a time
+      const Geo& gc = fz.gc;
+      const int J0 = ox >> 1, K0 = oy >> 1;
+      for (int e = tid; e < CB; e += nthreads()) {
+        const int a = e % CBX, b = e / CBX;
+        const Cx<T> vx = fetch<T, T>(cc, gc.ne, gc.n, gc.m, 0, J0 + a, K0 + b, p);
+        const Cx<T> vy = fetch<T, T>(cc, gc.ne, gc.n, gc.m, gc.nm, J0 + a, K0 + b, p);
+        cl[e] = vx.re;
+        cl[CB + e] = vx.im;
+        cl[2 * CB + e] = vy.re;
+        cl[3 * CB + e] = vy.im;
+      }
+      __syncthreads();
+      constexpr int LB = 4;
+      for (int e0 = tid; e0 < BX * BY; e0 += LB * nthreads()) {
+        T u[LB][4];
+#pragma unroll
+        for (int v = 0; v < LB; ++v) {
+          const int e = e0 + v * nthreads();
+          if (e >= BX * BY) continue;
+          const int64_t i = (int64_t)(oy + e / BX) * n + ox + e % BX;
+          u[v][0] = xc[i];
+          u[v][1] = xc[N + i];
+          u[v][2] = xc[nm + i];
+          u[v][3] = xc[N + nm + i];
+        }
+#pragma unroll
+        for (int v = 0; v < LB; ++v) {
+          const int e = e0 + v * nthreads();
+          if (e >= BX * BY) continue;
+          const int bx = e % BX, by = e / BX;
+          const int q = (by >> 1) * CBX + (bx >> 1);
+          const Cx<T> vx = edge_prolong_combine<T>(Cx<T>{cl[q], cl[CB + q]}, Cx<T>{cl[q + CBX], cl[CB + q + CBX]},
+                                                   (by & 1) != 0);
+          const Cx<T> vy = edge_prolong_combine<T>(Cx<T>{cl[2 * CB + q], cl[3 * CB + q]},
+                                                   Cx<T>{cl[2 * CB + q + 1], cl[3 * CB + q + 1]}, (bx & 1) != 0);
+          const int k = S::at(bx, by);
+          pl[k] = u[v][0] + vx.re;
+          pl[S::N + k] = u[v][1] + vx.im;
+          pl[2 * S::N + k] = u[v][2] + vy.re;
+          pl[3 * S::N + k] = u[v][3] + vy.im;
+        }
+      }
+    } else {
+      for (int e = tid; e < BX * BY; e += nthreads()) {
+        const int bx = e % BX, by = e / BX;
+        const int c1 = cx ? wrapm(ox + bx, n) : ox + bx, c2 = cy ? wrapm(oy + by, m) : oy + by;
+        const int64_t i = (int64_t)c2 * n + c1;
+        const int k = S::at(bx, by);
+        if constexpr (PRO) {   // as the prolongation kernel: x + Pr xc
+          const Cx<T> vx = edge_prolong_xy<T>(cc, fz.gc, 0, c1, c2, p);
+          const Cx<T> vy = edge_prolong_xy<T>(cc, fz.gc, 1, c1, c2, p);
+          pl[k] = xc[i] + vx.re;
+          pl[S::N + k] = xc[N + i] + vx.im;
+          pl[2 * S::N + k] = xc[nm + i] + vy.re;
+          pl[3 * S::N + k] = xc[N + nm + i] + vy.im;
+        } else {
+          pl[k] = xc[i];
+          pl[S::N + k] = xc[N + i];
+          pl[2 * S::N + k] = xc[nm + i];
+          pl[3 * S::N + k] = xc[N + nm + i];
+        }
       }
     }
   }
@@ -566,8 +619,12 @@ __global__ __launch_bounds__(kMaxThreads) void k_nodal_sweep(View<const T> xin, 
   constexpr int LO = RES ? kLoR : kLo;
   constexpr int BX = TX + LO + kHiN, BY = TY + LO + kHiN;
   using S = Split<BX, BY>;
+  // coarse nodes under the box (prolongating sweeps of boxes inside the period): fine box
+  // position b lies over coarse box position b >> 1 and its neighbours one up
+  constexpr int CBX = (BX - 1) / 2 + 2, CBY = (BY - 1) / 2 + 2, CB = CBX * CBY;
   __shared__ T pl[2 * S::N];
   __shared__ T rl[RES ? 2 * (TX + 1) * (TY + 1) : 1];
+  __shared__ T cl[PRO && (sizeof(T) == 4 || TX * TY <= 1024) ? 2 * CB : 1];
   const TileRef tr = tile_ref(slots, ncps, tiles_x, TX, TY);
   const int n = g.n, m = g.m, tid = threadIdx.x;
   const int64_t N = g.nm;
@@ -582,18 +639,58 @@ __global__ __launch_bounds__(kMaxThreads) void k_nodal_sweep(View<const T> xin, 
   } else {
     const T* xc = colp(xin, sj, N);
     const T* cc = PRO ? colp(fz.xc, sj, fz.gc.nm) : nullptr;
-    for (int e = tid; e < BX * BY; e += nthreads()) {
-      const int bx = e % BX, by = e / BX;
-      const int c1 = cx ? wrapm(ox + bx, n) : ox + bx, c2 = cy ? wrapm(oy + by, m) : oy + by;
-      const int64_t i = (int64_t)c2 * n + c1;
-      const int k = S::at(bx, by);
-      if constexpr (PRO) {   // as the prolongation kernel: base + Pr xc
-        const Cx<T> v = nodal_prolong_xy<T>(cc, fz.gc, c1, c2, p);
-        pl[k] = xc[i] + v.re;
-        pl[S::N + k] = xc[N + i] + v.im;
-      } else {
-        pl[k] = xc[i];
-        pl[S::N + k] = xc[N + i];
+    // (not for FP64 64 x 32 tiles, whose registers would then cost occupancy)
+    constexpr bool STAGE = PRO && (sizeof(T) == 4 || TX * TY <= 1024);
+    if (STAGE && !cx && !cy) {
+      // as the prolongation kernel, x + Pr xc, with the coarse values (as fetch() returns them
+      // at the box's coarse positions, ox and oy being even) staged once in LDS, and the
+      // iterate's loads issued four positions at a time
+      const int J0 = ox >> 1, K0 = oy >> 1;
+      for (int e = tid; e < CB; e += nthreads()) {
+        const Cx<T> v = fetch<T, T>(cc, fz.gc.nm, fz.gc.n, fz.gc.m, 0, J0 + e % CBX, K0 + e / CBX, p);
+        cl[e] = v.re;
+        cl[CB + e] = v.im;
+      }
+      __syncthreads();
+      constexpr int LB = 4;
+      for (int e0 = tid; e0 < BX * BY; e0 += LB * nthreads()) {
+        T ur[LB], ui[LB];
+#pragma unroll
+        for (int u = 0; u < LB; ++u) {
+          const int e = e0 + u * nthreads();
+          if (e >= BX * BY) continue;
+          const int64_t i = (int64_t)(oy + e / BX) * n + ox + e % BX;
+          ur[u] = xc[i];
+          ui[u] = xc[N + i];
+        }
+#pragma unroll
+        for (int u = 0; u < LB; ++u) {
+          const int e = e0 + u * nthreads();
+          if (e >= BX * BY) continue;
+          const int bx = e % BX, by = e / BX;
+          const int q = (by >> 1) * CBX + (bx >> 1);
+          const Cx<T> v = nodal_prolong_combine<T>(Cx<T>{cl[q], cl[CB + q]}, Cx<T>{cl[q + 1], cl[CB + q + 1]},
+                                                   Cx<T>{cl[q + CBX], cl[CB + q + CBX]},
+                                                   Cx<T>{cl[q + CBX + 1], cl[CB + q + CBX + 1]}, bx & 1, by & 1);
+          const int k = S::at(bx, by);
+          pl[k] = ur[u] + v.re;
+          pl[S::N + k] = ui[u] + v.im;
+        }
+      }
+    } else {
+      for (int e = tid; e < BX * BY; e += nthreads()) {
+        const int bx = e % BX, by = e / BX;
+        const int c1 = cx ? wrapm(ox + bx, n) : ox + bx, c2 = cy ? wrapm(oy + by, m) : oy + by;
+        const int64_t i = (int64_t)c2 * n + c1;
+        const int k = S::at(bx, by);
+        if constexpr (PRO) {   // as the prolongation kernel: base + Pr xc
+          const Cx<T> v = nodal_prolong_xy<T>(cc, fz.gc, c1, c2, p);
+          pl[k] = xc[i] + v.re;
+          pl[S::N + k] = xc[N + i] + v.im;
+        } else {
+          pl[k] = xc[i];
+          pl[S::N + k] = xc[N + i];
+        }
       }
     }
   }
@@ -604,16 +701,38 @@ __global__ __launch_bounds__(kMaxThreads) void k_nodal_sweep(View<const T> xin, 
   else if (!cx) nodal_passes<T, BX, BY, BWD, false, true, LO, TX, TY, EA, EB>(pl, bc, st, ox, oy, n, m, N, p);
   else nodal_passes<T, BX, BY, BWD, true, true, LO, TX, TY, EA, EB>(pl, bc, st, ox, oy, n, m, N, p);
   const T* bs = BAS ? colp(fz.base, sj, N) : nullptr;
-  for (int e = tid; e < TX * TY; e += nthreads()) {
-    const int ix = e % TX, iy = e / TX;
-    const int c1 = tr.t0x + ix, c2 = tr.t0y + iy;
-    if (c1 >= n || c2 >= m) continue;
-    const int k = S::at(ix + LO, iy + LO);
-    const int64_t i = (int64_t)c2 * n + c1;
-    if constexpr (BAS) {   // as the update kernel: base + x
-      xo[i] = bs[i] + pl[k];
-      xo[N + i] = bs[N + i] + pl[S::N + k];
-    } else {
+  if constexpr (BAS) {   // as the update kernel: base + x (the base loads four positions at a time)
+    constexpr int LB = 4;
+    for (int e0 = tid; e0 < TX * TY; e0 += LB * nthreads()) {
+      T br[LB], bi[LB];
+#pragma unroll
+      for (int u = 0; u < LB; ++u) {
+        const int e = e0 + u * nthreads();
+        const int c1 = tr.t0x + e % TX, c2 = tr.t0y + e / TX;
+        if (e >= TX * TY || c1 >= n || c2 >= m) continue;
+        const int64_t i = (int64_t)c2 * n + c1;
+        br[u] = bs[i];
+        bi[u] = bs[N + i];
+      }
+#pragma unroll
+      for (int u = 0; u < LB; ++u) {
+        const int e = e0 + u * nthreads();
+        const int ix = e % TX, iy = e / TX;
+        const int c1 = tr.t0x + ix, c2 = tr.t0y + iy;
+        if (e >= TX * TY || c1 >= n || c2 >= m) continue;
+        const int k = S::at(ix + LO, iy + LO);
+        const int64_t i = (int64_t)c2 * n + c1;
+        xo[i] = br[u] + pl[k];
+        xo[N + i] = bi[u] + pl[S::N + k];
+      }
+    }
+  } else {
+    for (int e = tid; e < TX * TY; e += nthreads()) {
+      const int ix = e % TX, iy = e / TX;
+      const int c1 = tr.t0x + ix, c2 = tr.t0y + iy;
+      if (c1 >= n || c2 >= m) continue;
+      const int k = S::at(ix + LO, iy + LO);
+      const int64_t i = (int64_t)c2 * n + c1;
       xo[i] = pl[k];
       xo[N + i] = pl[S::N + k];
     }
