@@ -75,6 +75,20 @@ __device__ __forceinline__ PointTile point_tile(int n, int m) {
 }
 inline int point_tiles(int n, int m) { return ((n + kPtW - 1) / kPtW) * ((m + kPtH - 1) / kPtH); }
 
+// Workgroups that walk kPtPer consecutive tiles (k = 0 .. kPtPer - 1) of their XCD-major block
+// in turn, paying the set-up (slot, phase and column pointers) once; tiles past the last are
+// empty (no live point).
+constexpr int kPtPer = 4;
+__device__ __forceinline__ PointTile point_tile_k(int n, int m, int k) {
+  const int tiles_x = (n + kPtW - 1) / kPtW;
+  const int nb = (int)gridDim.x;
+  const int t = (nb >= 8 ? xcd_block((int)blockIdx.x, nb) : (int)blockIdx.x) * kPtPer + k;
+  const int tx0 = (t % tiles_x) * kPtW, ty0 = (t / tiles_x) * kPtH;
+  return {tx0 + (int)(threadIdx.x % kPtW), ty0 + (int)(threadIdx.x / kPtW),
+          tx0 >= 1 && tx0 + kPtW <= n - 1 && ty0 >= 1 && ty0 + kPtH <= m - 1};
+}
+inline int point_blocks(int n, int m) { return (point_tiles(n, m) + kPtPer - 1) / kPtPer; }
+
 // (A x) and (M x) at the edge of component c (0: x-edge, 1: y-edge) owned by the accessor's
 // node, from the curls of its two cells and its two parallel neighbours.  ka, kb: kappa of
 // the cells below and above an x-edge, right and left of a y-edge; mm: the edge's mass scale.

@@ -48,22 +48,24 @@ __global__ __launch_bounds__(256) void k_edge_apply(View<const TI> xv, View<cons
   const SJ sj = slot_col(slots, ncps);
   const int n = g.n, m = g.m;
   const int64_t nm = g.nm, N = g.ne;
-  const PointTile pt = point_tile(n, m);
   T rr = 0, mmv = 0;
-  if (pt.p1 < n && pt.p2 < m) {
-    const Ph<T> p = cast_phase<T>(phs[sj.slot]);
-    const TI* xc = colp(xv, sj, N);
-    k64 += (int64_t)sj.slot * nm;
-    k32 += (int64_t)sj.slot * nm;
+  const Ph<T> p = cast_phase<T>(phs[sj.slot]);
+  const TI* xc = colp(xv, sj, N);
+  k64 += (int64_t)sj.slot * nm;
+  k32 += (int64_t)sj.slot * nm;
+  const T mu = (MODE == EM_K || MODE == EM_RESID_K) ? (T)mus[sj.slot] : (T)0;
+  const T lm = MODE == EM_EIGRES ? (T)lam[(int64_t)sj.slot * lam_cps + sj.j] : (T)0;
+  const TI* bc = MODE == EM_RESID_K ? colp(bv, sj, N) : nullptr;
+  TO* oc = colp(ov, sj, N);
+  for (int kt = 0; kt < kPtPer; ++kt) {
+    const PointTile pt = point_tile_k(n, m, kt);
+    if (pt.p1 >= n || pt.p2 >= m) continue;
     const int64_t d = (int64_t)pt.p2 * n + pt.p1;
     const T kh = kap<T>(k64, k32, d);
     const T kbelow = kap<T>(k64, k32, (int64_t)wrapi(pt.p2 - 1, m) * n + pt.p1);
     const T kleft = kap<T>(k64, k32, (int64_t)pt.p2 * n + wrapi(pt.p1 - 1, n));
-    const T mu = (MODE == EM_K || MODE == EM_RESID_K) ? (T)mus[sj.slot] : (T)0;
-    const T lm = MODE == EM_EIGRES ? (T)lam[(int64_t)sj.slot * lam_cps + sj.j] : (T)0;
     Cx<T> bx{0, 0}, by{0, 0};
     if (MODE == EM_RESID_K) {
-      const TI* bc = colp(bv, sj, N);
       bx = Cx<T>{(T)bc[d], (T)bc[N + d]};
       by = Cx<T>{(T)bc[nm + d], (T)bc[N + nm + d]};
     }
@@ -77,14 +79,13 @@ __global__ __launch_bounds__(256) void k_edge_apply(View<const TI> xv, View<cons
       edge_point<T, MODE>(X, 0, kbelow, kh, (T)g.s, (T)g.mx, mu, lm, bx, rx, mx);
       edge_point<T, MODE>(X, 1, kh, kleft, (T)g.s, (T)g.my, mu, lm, by, ry, my);
     }
-    TO* oc = colp(ov, sj, N);
     oc[d] = (TO)rx.re;
     oc[N + d] = (TO)rx.im;
     oc[nm + d] = (TO)ry.re;
     oc[N + nm + d] = (TO)ry.im;
     if (MODE == EM_EIGRES) {
-      rr = (rx.re * rx.re + rx.im * rx.im) + (ry.re * ry.re + ry.im * ry.im);
-      mmv = (mx.re * mx.re + mx.im * mx.im) + (my.re * my.re + my.im * my.im);
+      rr += (rx.re * rx.re + rx.im * rx.im) + (ry.re * ry.re + ry.im * ry.im);
+      mmv += (mx.re * mx.re + mx.im * mx.im) + (my.re * my.re + my.im * my.im);
     }
   }
   if (MODE == EM_EIGRES) {
@@ -108,14 +109,14 @@ __global__ __launch_bounds__(256) void k_edge_apply(View<const TI> xv, View<cons
   }
 }
 
-int apply_blocks(const Geo& g) { return point_tiles(g.n, g.m); }
+int apply_blocks(const Geo& g) { return point_blocks(g.n, g.m); }
 
 template <typename TI, typename TO>
 void edge_apply(int mode, View<const TI> x, View<const TI> b, View<TO> out, const double* kappa64,
                 const float* kappa32, const double* lam, int lam_cps, const Geo& g,
                 const Phase* ph, const double* mu, const Launch& L, double* partial, int* nblk_out) {
   using T = typename std::conditional<std::is_same<TI, double>::value, double, float>::type;
-  dim3 grid((unsigned)point_tiles(g.n, g.m), (unsigned)(L.nact * L.ncps));
+  dim3 grid((unsigned)point_blocks(g.n, g.m), (unsigned)(L.nact * L.ncps));
   if (nblk_out) *nblk_out = (int)grid.x;
   if (grid.y == 0) return;
 #define BL_EA(MD) k_edge_apply<TI, TO, T, MD><<<grid, kPtW * kPtH, 0, L.st>>>(x, b, out, kappa64, kappa32, lam, lam_cps, g, ph, mu, L.slots, L.ncps, partial)
@@ -400,30 +401,28 @@ __global__ __launch_bounds__(256) void k_nodal_apply(View<const T> xv, View<cons
                                                      NodalStencil s, const int* __restrict__ slots,
                                                      int ncps) {
   const SJ sj = slot_col(slots, ncps);
-  const PointTile pt = point_tile(g.n, g.m);
-  if (pt.p1 >= g.n || pt.p2 >= g.m) return;
-  const int64_t N = g.nm, d = (int64_t)pt.p2 * g.n + pt.p1;
+  const int64_t N = g.nm;
   const T* xc = colp(xv, sj, N);
-  Cx<T> v;
-  if (pt.inner) {
-    v = nodal_stencil_at<T>(DirectNodes<T, T>{xc, N, d, g.n}, s);
-  } else {
-    const Ph<T> p = cast_phase<T>(phs[sj.slot]);
-    v = nodal_stencil<T>(xc, N, g.n, g.m, pt.p1, pt.p2, s, p);
-  }
-  if (RESID) {
-    const T* bc = colp(bv, sj, N);
-    v = Cx<T>{bc[d], bc[N + d]} - v;
-  }
+  const T* bc = RESID ? colp(bv, sj, N) : nullptr;
   T* o = colp(ov, sj, N);
-  o[d] = v.re;
-  o[N + d] = v.im;
+  const Ph<T> p = cast_phase<T>(phs[sj.slot]);
+  for (int kt = 0; kt < kPtPer; ++kt) {
+    const PointTile pt = point_tile_k(g.n, g.m, kt);
+    if (pt.p1 >= g.n || pt.p2 >= g.m) continue;
+    const int64_t d = (int64_t)pt.p2 * g.n + pt.p1;
+    Cx<T> v;
+    if (pt.inner) v = nodal_stencil_at<T>(DirectNodes<T, T>{xc, N, d, g.n}, s);
+    else v = nodal_stencil<T>(xc, N, g.n, g.m, pt.p1, pt.p2, s, p);
+    if (RESID) v = Cx<T>{bc[d], bc[N + d]} - v;
+    o[d] = v.re;
+    o[N + d] = v.im;
+  }
 }
 
 template <typename T>
 void nodal_apply(View<const T> x, View<const T> b, View<T> out, const Geo& g, const Phase* ph,
                  const NodalStencil& c, bool resid, const Launch& L) {
-  dim3 grid((unsigned)point_tiles(g.n, g.m), (unsigned)(L.nact * L.ncps));
+  dim3 grid((unsigned)point_blocks(g.n, g.m), (unsigned)(L.nact * L.ncps));
   if (grid.y == 0) return;
   if (resid) k_nodal_apply<T, true><<<grid, kPtW * kPtH, 0, L.st>>>(x, b, out, g, ph, c, L.slots, L.ncps);
   else k_nodal_apply<T, false><<<grid, kPtW * kPtH, 0, L.st>>>(x, b, out, g, ph, c, L.slots, L.ncps);
@@ -557,27 +556,24 @@ __global__ __launch_bounds__(256) void k_lhm(View<const TI> uv, View<TO> ov, Geo
   using T = double;
   const SJ sj = slot_col(slots, ncps);
   const int n = g.n, m = g.m;
-  const PointTile pt = point_tile(n, m);
-  const bool live = pt.p1 < n && pt.p2 < m;
-  if (!PW && !live) return;
+  const int64_t N = g.ne, nm = g.nm;
+  const TI* c = colp(uv, sj, N);
+  TO* o = colp(ov, sj, nm);
+  const Ph<T> p = cast_phase<T>(phs[sj.slot]);
   double sr = 0.0, si = 0.0;
-  if (live) {
-    const int64_t N = g.ne, nm = g.nm, d = (int64_t)pt.p2 * n + pt.p1;
-    const TI* c = colp(uv, sj, N);
+  for (int kt = 0; kt < kPtPer; ++kt) {
+    const PointTile pt = point_tile_k(n, m, kt);
+    if (pt.p1 >= n || pt.p2 >= m) continue;
+    const int64_t d = (int64_t)pt.p2 * n + pt.p1;
     Cx<T> v;
-    if (pt.inner) {
-      v = lhm_at<T>(DirectEdges<T, TI>{c, N, nm, d, n}, (T)g.mx, (T)g.my);
-    } else {
-      const Ph<T> p = cast_phase<T>(phs[sj.slot]);
-      v = lhm_at<T>(ColumnEdges<T, const TI>{c, N, nm, n, m, pt.p1, pt.p2, p}, (T)g.mx, (T)g.my);
-    }
-    TO* o = colp(ov, sj, nm);
+    if (pt.inner) v = lhm_at<T>(DirectEdges<T, TI>{c, N, nm, d, n}, (T)g.mx, (T)g.my);
+    else v = lhm_at<T>(ColumnEdges<T, const TI>{c, N, nm, n, m, pt.p1, pt.p2, p}, (T)g.mx, (T)g.my);
     o[d] = (TO)v.re;
     o[nm + d] = (TO)v.im;
     if (PW) {   // conj(w_j) v_j in FP64, before the rounding to TO
       const Cx<double> w = pw_value(pw, sj.slot, n, pt.p1, pt.p2);
-      sr = w.re * v.re + w.im * v.im;
-      si = w.re * v.im - w.im * v.re;
+      sr += w.re * v.re + w.im * v.im;
+      si += w.re * v.im - w.im * v.re;
     }
   }
   if (PW) {
@@ -588,7 +584,7 @@ __global__ __launch_bounds__(256) void k_lhm(View<const TI> uv, View<TO> ov, Geo
 
 template <typename TI, typename TO>
 void lhm(View<const TI> u, View<TO> out, const Geo& g, const Phase* ph, const Launch& L, const PWDefl* pw) {
-  dim3 grid((unsigned)point_tiles(g.n, g.m), (unsigned)(L.nact * L.ncps));
+  dim3 grid((unsigned)point_blocks(g.n, g.m), (unsigned)(L.nact * L.ncps));
   if (grid.y == 0) return;
   if (pw) k_lhm<TI, TO, true><<<grid, kPtW * kPtH, 0, L.st>>>(u, out, g, ph, L.slots, L.ncps, *pw);
   else k_lhm<TI, TO, false><<<grid, kPtW * kPtH, 0, L.st>>>(u, out, g, ph, L.slots, L.ncps, PWDefl{});
@@ -601,57 +597,97 @@ template void lhm<float, double>(View<const float>, View<double>, const Geo&, co
 // out (edge) = u - L phi, (L phi)_x(j1,j2) = phi(j1+1,j2) - phi(j1,j2),
 // (L phi)_y(j1,j2) = phi(j1,j2+1) - phi(j1,j2) (extended reads).  FP64 arithmetic.  PW: the
 // plane-wave part of the nodal solution is added as gamma L w, (L w)_x = w_j ex, (L w)_y = w_j ey.
+// A thread takes kLiftPer edges (256 apart, so that every load stays coalesced): the
+// workgroup's set-up is paid once for all of them and every edge's loads are issued before the
+// first result is formed (the arithmetic per edge is fetch()'s, in the same order).
+constexpr int kLiftPer = 4;
+
 template <typename TI, typename TP, typename TO, bool SUB, bool PW>
 __global__ __launch_bounds__(256) void k_lift(View<const TI> uv, View<const TP> fv, View<TO> ov, Geo g,
                                               const Phase* __restrict__ phs,
                                               const int* __restrict__ slots, int ncps, PWDefl pw) {
   using T = double;
   const SJ sj = slot_col(slots, ncps);
-  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (d >= g.ne) return;
+  const int64_t d0 = (int64_t)blockIdx.x * (kLiftPer * 256) + threadIdx.x;
+  if (d0 >= g.ne) return;
   const Ph<T> p = cast_phase<T>(phs[sj.slot]);
   const int n = g.n, m = g.m;
   const int64_t N = g.ne, nm = g.nm;
   const TP* f = colp(fv, sj, nm);
-  Cx<T> lp;
-  int j1, j2;
-  if (d < nm) {
-    split_index(d, n, j1, j2);
-    lp = fetch<TP, T>(f, nm, n, m, 0, j1 + 1, j2, p) - fetch<TP, T>(f, nm, n, m, 0, j1, j2, p);
-  } else {
-    const int64_t e = d - nm;
-    split_index(e, n, j1, j2);
-    lp = fetch<TP, T>(f, nm, n, m, 0, j1, j2 + 1, p) - fetch<TP, T>(f, nm, n, m, 0, j1, j2, p);
-  }
-  if (PW) {
-    const PlaneWave& q = pw.par[sj.slot];
-    const Cx<double> w = pw_value(pw, sj.slot, n, j1, j2);
-    const Cx<double> lw = d < nm ? cmul(w, q.exr, q.exi) : cmul(w, q.eyr, q.eyi);
-    const int64_t col = (int64_t)(blockIdx.y / ncps) * pw.pcols + pw.off + sj.j;
-    const double* gm = pw.coef + col * 6 + 4;
-    lp = lp + cmul(lw, gm[0], gm[1]);
-  }
-  Cx<T> v = lp;
-  if (SUB) {
-    const TI* uc = colp(uv, sj, N);
-    v = Cx<T>{(T)uc[d], (T)uc[N + d]} - lp;
-  }
+  const TI* uc = SUB ? colp(uv, sj, N) : nullptr;
   TO* o = colp(ov, sj, N);
-  o[d] = (TO)v.re;
-  o[N + d] = (TO)v.im;
+  // loads: phi at the edge's far node (a, Bloch code sa) and its own node (b), u, the plane wave
+  TP ar[kLiftPer], ai[kLiftPer], br[kLiftPer], bi[kLiftPer];
+  TI ur[kLiftPer], ui[kLiftPer];
+  int sa[kLiftPer];
+  double w1r[kLiftPer], w1i[kLiftPer], w2r[kLiftPer], w2i[kLiftPer];
+  const double* tab = PW ? pw.tab + (int64_t)sj.slot * pw.tabstride : nullptr;
+#pragma unroll
+  for (int k = 0; k < kLiftPer; ++k) {
+    const int64_t d = d0 + k * 256;
+    if (d >= N) continue;
+    const bool xe = d < nm;
+    int j1, j2;
+    split_index(xe ? d : d - nm, n, j1, j2);
+    // far node (j1 + 1, j2) or (j1, j2 + 1), wrapped: code 1 one period ahead in x, 2 in y
+    int f1 = j1 + (xe ? 1 : 0), f2 = j2 + (xe ? 0 : 1), code = 0;
+    if (f1 >= n) { f1 -= n; code = 1; }
+    if (f2 >= m) { f2 -= m; code = 2; }
+    const int64_t ia = (int64_t)f2 * n + f1, ib = (int64_t)j2 * n + j1;
+    sa[k] = code;
+    ar[k] = f[ia];
+    ai[k] = f[nm + ia];
+    br[k] = f[ib];
+    bi[k] = f[nm + ib];
+    if (SUB) {
+      ur[k] = uc[d];
+      ui[k] = uc[N + d];
+    }
+    if (PW) {
+      w1r[k] = tab[2 * j1];
+      w1i[k] = tab[2 * j1 + 1];
+      w2r[k] = tab[2 * (n + j2)];
+      w2i[k] = tab[2 * (n + j2) + 1];
+    }
+  }
+  const double* gm = nullptr;
+  if (PW) {
+    const int64_t col = (int64_t)(blockIdx.y / ncps) * pw.pcols + pw.off + sj.j;
+    gm = pw.coef + col * 6 + 4;
+  }
+#pragma unroll
+  for (int k = 0; k < kLiftPer; ++k) {
+    const int64_t d = d0 + k * 256;
+    if (d >= N) continue;
+    const bool xe = d < nm;
+    Cx<T> a = {(T)ar[k], (T)ai[k]};
+    if (sa[k] == 1) a = cmul(a, p.ar, p.ai);
+    else if (sa[k] == 2) a = cmul(a, p.br, p.bi);
+    Cx<T> lp = a - Cx<T>{(T)br[k], (T)bi[k]};
+    if (PW) {
+      const PlaneWave& q = pw.par[sj.slot];
+      const Cx<double> w = {w1r[k] * w2r[k] - w1i[k] * w2i[k], w1r[k] * w2i[k] + w1i[k] * w2r[k]};
+      const Cx<double> lw = xe ? cmul(w, q.exr, q.exi) : cmul(w, q.eyr, q.eyi);
+      lp = lp + cmul(lw, gm[0], gm[1]);
+    }
+    Cx<T> v = lp;
+    if (SUB) v = Cx<T>{(T)ur[k], (T)ui[k]} - lp;
+    o[d] = (TO)v.re;
+    o[N + d] = (TO)v.im;
+  }
 }
 
 template <typename TI, typename TP, typename TO>
 void lift_sub(View<const TI> u, View<const TP> phi, View<TO> out, const Geo& g, const Phase* ph,
               const Launch& L, const PWDefl* pw) {
-  dim3 grid((unsigned)((g.ne + 255) / 256), (unsigned)(L.nact * L.ncps));
+  dim3 grid((unsigned)((g.ne + kLiftPer * 256 - 1) / (kLiftPer * 256)), (unsigned)(L.nact * L.ncps));
   if (grid.y == 0) return;
   if (pw) k_lift<TI, TP, TO, true, true><<<grid, 256, 0, L.st>>>(u, phi, out, g, ph, L.slots, L.ncps, *pw);
   else k_lift<TI, TP, TO, true, false><<<grid, 256, 0, L.st>>>(u, phi, out, g, ph, L.slots, L.ncps, PWDefl{});
 }
 template <typename TI, typename TO>
 void lift(View<const TI> phi, View<TO> out, const Geo& g, const Phase* ph, const Launch& L) {
-  dim3 grid((unsigned)((g.ne + 255) / 256), (unsigned)(L.nact * L.ncps));
+  dim3 grid((unsigned)((g.ne + kLiftPer * 256 - 1) / (kLiftPer * 256)), (unsigned)(L.nact * L.ncps));
   if (grid.y == 0) return;
   k_lift<TO, TI, TO, false, false><<<grid, 256, 0, L.st>>>(View<const TO>{nullptr, 0, 0}, phi, out, g, ph, L.slots, L.ncps, PWDefl{});
 }
