@@ -136,6 +136,7 @@ struct SweepFuse {
   View<T> bc{nullptr, 0, 0};
   View<const T> xc{nullptr, 0, 0};
   View<const T> base{nullptr, 0, 0};
+  View<T> res{nullptr, 0, 0};   // nodal backward sweeps: also write b - P xout here
   Geo gc{};
 };
 

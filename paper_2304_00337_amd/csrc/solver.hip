@@ -437,7 +437,9 @@ void vcycle_edge(bl_solver* s, int l, View<const T> b, View<T> x, const Launch& 
 // x = V(b); with add_to, a cycle that can fold the update into its last sweep writes
 // *add_to + V(b) to *add_to instead (x is then not written) and returns true.
 template <typename T>
-bool vcycle_nodal(bl_solver* s, int l, View<const T> b, View<T> x, const Launch& L, const View<T>* add_to = nullptr) {
+bool vcycle_nodal(bl_solver* s, int l, View<const T> b, View<T> x, const Launch& L, const View<T>* add_to = nullptr,
+                  const View<T>* res_out = nullptr, bool* res_done = nullptr) {
+  if (res_done) *res_done = false;
   const int pr = PrecOf<T>::v;
   Level& lv = s->lv[l];
   const int nl = (int)s->lv.size();
@@ -486,6 +488,10 @@ bool vcycle_nodal(bl_solver* s, int l, View<const T> b, View<T> x, const Launch&
       if (it == npost - 1 && add_to) {
         dst = *add_to;
         fz.base = cv(*add_to);
+      }
+      if (it == npost - 1 && res_out && !add_to) {   // the residual b - P x of the result
+        fz.res = *res_out;
+        if (res_done) *res_done = true;
       }
       nodal_sweep<T>(cv(prev), dst, b, lv.g, s->ph_d, s->ns, true, false, s->tune_sweep[1], L, fz);
       prev = dst;
@@ -540,13 +546,18 @@ bool vcycle_nodal(bl_solver* s, int l, View<const T> b, View<T> x, const Launch&
 template <typename T>
 void nodal_solve(bl_solver* s, View<const T> b, View<T> phi, const Launch& L, int cycles, int lev = 0) {
   const int pr = PrecOf<T>::v;
-  vcycle_nodal<T>(s, lev, b, phi, L);
   View<T> res = view(static_cast<T*>(s->nodal_extra[pr][0]), s->nodal_extra_cap[pr]);
   View<T> cor = view(static_cast<T*>(s->nodal_extra[pr][1]), s->nodal_extra_cap[pr]);
+  // the first cycle's last sweep also forms the residual the second cycle starts from
+  bool have_res = false;
+  vcycle_nodal<T>(s, lev, b, phi, L, nullptr, cycles > 1 ? &res : nullptr, &have_res);
   const Geo& g = s->lv[lev].g;
   for (int c = 1; c < cycles; ++c) {
-    nodal_apply<T>(cv(phi), b, res, g, s->ph_d, s->ns, true, L);
-    s->launches += 1;
+    if (!have_res) {
+      nodal_apply<T>(cv(phi), b, res, g, s->ph_d, s->ns, true, L);
+      s->launches += 1;
+    }
+    have_res = false;
     if (!vcycle_nodal<T>(s, lev, cv(res), cor, L, &phi)) {
       axpy<T>(phi, cv(cor), g.nm, L);
       s->launches += 1;

@@ -47,6 +47,10 @@ __device__ __forceinline__ int nthreads() { return (int)blockDim.x; }
 // iterate two nodes below/left and one node above/right of the tile: the halos grow to kLoR
 // below (nodal and edge) and kHiER above (edge; the nodal forward sweep's kHiN suffices).
 constexpr int kRestrict = 1, kProlong = 2, kBase = 4;
+// kResid (nodal backward sweeps): the sweep also writes the residual b - P x of its result at
+// the tile's nodes (as the residual kernel computes it), for which the iterate must be exact
+// one node around the tile.
+constexpr int kResid = 8;
 constexpr int kLoR = 6;
 constexpr int kHiER = 6;
 
@@ -573,6 +577,37 @@ __device__ __forceinline__ void nodal_resid_pass(const T* pl, T* rl, const T* bc
   }
 }
 
+// Residual b - P x at the tile's nodes (box positions LO .. LO + TX - 1, LO .. LO + TY - 1),
+// straight to memory, as the residual kernel computes it.
+template <typename T, int BX, int BY, int PAR, bool CX, bool CY, int LO, int TX, int TY>
+__device__ __forceinline__ void nodal_tile_resid_par(const T* pl, const T* bc, T* ro, const NodalStencil& st, int ox,
+                                                     int oy, int n, int m, int64_t N, const Ph<T>& p) {
+  constexpr int PX = PAR & 1, PY = PAR >> 1;
+  constexpr int I0 = (LO - PX + 1) / 2, I1 = (LO + TX - 1 - PX) / 2;
+  constexpr int J0 = (LO - PY + 1) / 2, J1 = (LO + TY - 1 - PY) / 2;
+  constexpr int CNX = I1 - I0 + 1, CNY = J1 - J0 + 1;
+  for (int t = threadIdx.x; t < CNX * CNY; t += nthreads()) {
+    const int i = I0 + t % CNX, j = J0 + t / CNX;
+    const int bx = 2 * i + PX, by = 2 * j + PY;
+    const int p1 = CX ? wrapm(ox + bx, n) : ox + bx;
+    const int p2 = CY ? wrapm(oy + by, m) : oy + by;
+    if (ox + bx >= n || oy + by >= m) continue;   // past the grid's last tile column / row
+    const int64_t k = (int64_t)p2 * n + p1;
+    const TileNodes<T, BX, BY, PX, PY, CX, CY> X{pl, i, j, Seam<CX, CY>(p1, p2, n, m), p};
+    const Cx<T> r = Cx<T>{bc[k], bc[N + k]} - nodal_stencil_at<T>(X, st);
+    ro[k] = r.re;
+    ro[N + k] = r.im;
+  }
+}
+template <typename T, int BX, int BY, bool CX, bool CY, int LO, int TX, int TY>
+__device__ __forceinline__ void nodal_tile_resid(const T* pl, const T* bc, T* ro, const NodalStencil& st, int ox,
+                                                 int oy, int n, int m, int64_t N, const Ph<T>& p) {
+  nodal_tile_resid_par<T, BX, BY, 0, CX, CY, LO, TX, TY>(pl, bc, ro, st, ox, oy, n, m, N, p);
+  nodal_tile_resid_par<T, BX, BY, 1, CX, CY, LO, TX, TY>(pl, bc, ro, st, ox, oy, n, m, N, p);
+  nodal_tile_resid_par<T, BX, BY, 2, CX, CY, LO, TX, TY>(pl, bc, ro, st, ox, oy, n, m, N, p);
+  nodal_tile_resid_par<T, BX, BY, 3, CX, CY, LO, TX, TY>(pl, bc, ro, st, ox, oy, n, m, N, p);
+}
+
 // Residual window values around window position (x, y) (as fetch()).
 template <typename T, int RW, int RH, bool CX, bool CY>
 struct WindowNodes {
@@ -615,9 +650,12 @@ __global__ __launch_bounds__(kMaxThreads) void k_nodal_sweep(View<const T> xin, 
                                                           int zero_start, const int* __restrict__ slots, int ncps,
                                                           int tiles_x, SweepFuse<T> fz) {
   static_assert(!((MODE & kRestrict) && BWD), "the residual window halo is sized for forward sweeps");
+  static_assert(!((MODE & kResid) && !BWD), "the tile residual rides on backward sweeps");
   constexpr bool RES = (MODE & kRestrict) != 0, PRO = (MODE & kProlong) != 0, BAS = (MODE & kBase) != 0;
+  constexpr bool TRES = (MODE & kResid) != 0;
   constexpr int LO = RES ? kLoR : kLo;
-  constexpr int BX = TX + LO + kHiN, BY = TY + LO + kHiN;
+  constexpr int HI = TRES ? kHiN + 1 : kHiN;   // (the tile residual: exact one node above / right too)
+  constexpr int BX = TX + LO + HI, BY = TY + LO + HI;
   using S = Split<BX, BY>;
   // coarse nodes under the box (prolongating sweeps of boxes inside the period): fine box
   // position b lies over coarse box position b >> 1 and its neighbours one up
@@ -695,7 +733,8 @@ __global__ __launch_bounds__(kMaxThreads) void k_nodal_sweep(View<const T> xin, 
     }
   }
   __syncthreads();
-  constexpr int EA = RES ? 2 : 0, EB = RES ? 1 : 0;   // exact margin the residual window needs
+  // exact margin the residual window (restriction) or the tile residual needs
+  constexpr int EA = RES ? 2 : (TRES ? 1 : 0), EB = (RES || TRES) ? 1 : 0;
   if (!cx && !cy) nodal_passes<T, BX, BY, BWD, false, false, LO, TX, TY, EA, EB>(pl, bc, st, ox, oy, n, m, N, p);
   else if (!cy) nodal_passes<T, BX, BY, BWD, true, false, LO, TX, TY, EA, EB>(pl, bc, st, ox, oy, n, m, N, p);
   else if (!cx) nodal_passes<T, BX, BY, BWD, false, true, LO, TX, TY, EA, EB>(pl, bc, st, ox, oy, n, m, N, p);
@@ -736,6 +775,13 @@ __global__ __launch_bounds__(kMaxThreads) void k_nodal_sweep(View<const T> xin, 
       xo[i] = pl[k];
       xo[N + i] = pl[S::N + k];
     }
+  }
+  if constexpr (TRES) {
+    T* ro = colp(fz.res, sj, N);
+    if (!cx && !cy) nodal_tile_resid<T, BX, BY, false, false, LO, TX, TY>(pl, bc, ro, st, ox, oy, n, m, N, p);
+    else if (!cy) nodal_tile_resid<T, BX, BY, true, false, LO, TX, TY>(pl, bc, ro, st, ox, oy, n, m, N, p);
+    else if (!cx) nodal_tile_resid<T, BX, BY, false, true, LO, TX, TY>(pl, bc, ro, st, ox, oy, n, m, N, p);
+    else nodal_tile_resid<T, BX, BY, true, true, LO, TX, TY>(pl, bc, ro, st, ox, oy, n, m, N, p);
   }
   if constexpr (RES) {
     T* bco = colp(fz.bc, sj, fz.gc.nm);
@@ -799,7 +845,8 @@ void nodal_go(View<const T> xin, View<T> xout, View<const T> b, const Geo& g, co
 template <typename T, int TX, int TY>
 void nodal_launch(View<const T> xin, View<T> xout, View<const T> b, const Geo& g, const Phase* ph,
                   const NodalStencil& c, bool backward, bool zero_start, const SweepFuse<T>& fz, const Launch& L) {
-  const int mode = (fz.bc.p ? kRestrict : 0) | (fz.xc.p ? kProlong : 0) | (fz.base.p ? kBase : 0);
+  const int mode = (fz.bc.p ? kRestrict : 0) | (fz.xc.p ? kProlong : 0) | (fz.base.p ? kBase : 0) |
+                   (fz.res.p ? kResid : 0);
   if (!backward) {
     if constexpr (sizeof(T) == 4 || TX * TY <= 1024) {   // (the FP64 64 x 32 window is routed to 32 x 32)
       if (mode == kRestrict) {
@@ -816,6 +863,10 @@ void nodal_launch(View<const T> xin, View<T> xout, View<const T> b, const Geo& g
     case kProlong | kBase:
       nodal_go<T, TX, TY, true, kProlong | kBase>(xin, xout, b, g, ph, c, zero_start, fz, L);
       break;
+    case kProlong | kResid:
+      nodal_go<T, TX, TY, true, kProlong | kResid>(xin, xout, b, g, ph, c, zero_start, fz, L);
+      break;
+    case kResid: nodal_go<T, TX, TY, true, kResid>(xin, xout, b, g, ph, c, zero_start, fz, L); break;
     default: nodal_go<T, TX, TY, true, 0>(xin, xout, b, g, ph, c, zero_start, fz, L); break;
   }
 }
