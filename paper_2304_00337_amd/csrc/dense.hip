@@ -422,13 +422,13 @@ void block_combine(View<const double> S, int q, const double* Y, int want, int64
   const int ny = (ntc + per - 1) / per;
   // persistent workgroups: as many as stay resident together (by LDS, at most two per compute
   // unit), spread over the column groups and slots of the launch
-  static int cus = 0;
-  if (!cus) {
-    int dev = 0;
+  static const int cus = [] {   // initialised once, thread-safely
+    int dev = 0, c = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-      cus = 256;
-  }
+        hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0)
+      c = 256;
+    return c;
+  }();
   const int per_cu = tile_lds * per <= (size_t)80 * 1024 ? 2 : 1;
   const int64_t tiles_wg = ((len + BCR - 1) / BCR + BCW - 1) / BCW;
   int64_t nx = ((int64_t)cus * per_cu + (int64_t)ny * L.nact - 1) / ((int64_t)ny * L.nact);
@@ -437,12 +437,12 @@ void block_combine(View<const double> S, int q, const double* Y, int want, int64
   const dim3 grid((unsigned)nx, (unsigned)ny, (unsigned)L.nact);
   auto go = [&](auto nt) {
     constexpr int NTC = decltype(nt)::value;
-    static bool attr = false;
-    if (!attr) {
+    static const bool attr = [&] {   // once per instantiation, thread-safely
       (void)hipFuncSetAttribute((const void*)k_block_combine<NTC>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 160 * 1024);
-      attr = true;
-    }
+      return true;
+    }();
+    (void)attr;
     k_block_combine<NTC><<<grid, 64 * BCW, tile_lds * NTC, L.st>>>(S, q, reinterpret_cast<const c2*>(Y), want, len,
                                                                   out, L.slots);
   };

@@ -683,11 +683,11 @@ int rr_gram(View<const double> S, int q, const double* kappa, const Geo& g, cons
       constexpr int NG = decltype(ngt)::value;
       const size_t red = (size_t)2 * 64 * 8 * RRConf<NG>::MP * sizeof(double);
       const size_t lds = sizeof(RRStage<NG>) > red ? sizeof(RRStage<NG>) : red;
-      static bool attr = false;
-      if (!attr) {
+      static const bool attr = [&] {   // once per instantiation, thread-safely
         (void)hipFuncSetAttribute((const void*)k_rr_mfma<NG>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        attr = true;
-      }
+        return true;
+      }();
+      (void)attr;
       k_rr_mfma<NG><<<dim3((unsigned)nb, (unsigned)blocks_y, (unsigned)L.nact), RR_THREADS, lds, L.st>>>(
           S, q, kappa, g, ph, grd.slices, grd.band, ngroups, partial, L.slots);
     };
