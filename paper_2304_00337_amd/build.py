@@ -17,9 +17,11 @@ SOURCES = ["csrc/stencils.hip", "csrc/dense.hip", "csrc/ritz.hip", "csrc/solver.
            "csrc/sweep.hip", "csrc/planewave.hip",
            "csrc/noalloc.hip"]
 LIB = os.path.join(PKG, "libbloch.so")
-# per-source flags: the block combination keeps its MFMA accumulators in ordinary VGPRs (the
-# default heuristic moves them between register files on every step of its loop)
-EXTRA_FLAGS = {"csrc/dense.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+# per-source flags: the block combination and the Ritz step's products keep their MFMA
+# accumulators in ordinary VGPRs (the default heuristic moves them between register files on
+# every step of their loops)
+EXTRA_FLAGS = {"csrc/dense.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+               "csrc/ritz.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def hipcc() -> str:

@@ -114,70 +114,51 @@ __device__ __forceinline__ void pick_max(double& v, int& idx, int& pos) {
   if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; pos = op; }
 }
 
-// C (M x N, stride ldc) = X (M x K, stride ldx) * Y (K x N, stride ldy); 3 x 3 register
-// blocks per thread.
-__device__ __forceinline__ void mm_nn(const c2* X, int ldx, const c2* Y, int ldy, c2* C, int ldc, int M, int N, int K) {
-  const int bm = (M + 2) / 3, bn = (N + 2) / 3;
-  for (int e = threadIdx.x; e < bm * bn; e += blockDim.x) {
-    const int i0 = (e / bn) * 3, j0 = (e % bn) * 3;
-    c2 acc[3][3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int b = 0; b < 3; ++b) acc[a][b] = {0, 0};
-    for (int l = 0; l < K; ++l) {
-      c2 xa[3], yb[3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) xa[a] = (i0 + a < M) ? X[(i0 + a) * ldx + l] : c2{0, 0};
-#pragma unroll
-      for (int b = 0; b < 3; ++b) yb[b] = (j0 + b < N) ? Y[l * ldy + j0 + b] : c2{0, 0};
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-          const c2 t = cmul(xa[a], yb[b]);
-          acc[a][b].r += t.r;
-          acc[a][b].i += t.i;
-        }
+// C (M x N, row-major, leading dimension ldc) = op(X) op(Y) on the matrix cores (FP64 MFMA
+// 16x16x4, four real products per complex one), every wave of the workgroup taking 16 x 16
+// output tiles in turn; op(X) = X (M x K, row-major) or, with CX, X^* for X stored K x M;
+// op(Y) = Y (K x N, row-major) or, with TY, the transpose of Y stored N x K.  Columns j >= NB
+// of op(Y) are taken as zero.  Operands may live in LDS or global memory; the next four-wide
+// step's operands are loaded while the current one is multiplied.  Call between barriers.
+typedef double rd4 __attribute__((ext_vector_type(4)));
+template <bool CX, bool TY>
+__device__ __forceinline__ void mm_mfma(const c2* X, int ldx, const c2* Y, int ldy, c2* C, int ldc, int M, int N,
+                                        int K, int NB) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (int)blockDim.x >> 6;
+  const int tm = (M + 15) / 16, tn = (N + 15) / 16;
+  const int r16 = lane & 15, k4 = lane >> 4;
+  for (int t = wv; t < tm * tn; t += nw) {
+    const int i0 = (t / tn) * 16, j0 = (t % tn) * 16;
+    const int ia = i0 + r16, jb = j0 + r16;   // the operand row of X and column of Y this lane supplies
+    auto lda = [&](int l) -> c2 {
+      if (ia >= M || l >= K) return c2{0.0, 0.0};
+      if (CX) {
+        const c2 v = X[(int64_t)l * ldx + ia];
+        return c2{v.r, -v.i};
+      }
+      return X[(int64_t)ia * ldx + l];
+    };
+    auto ldb = [&](int l) -> c2 {
+      if (jb >= NB || l >= K) return c2{0.0, 0.0};
+      return TY ? Y[(int64_t)jb * ldy + l] : Y[(int64_t)l * ldy + jb];
+    };
+    rd4 cr = {0.0, 0.0, 0.0, 0.0}, ci = {0.0, 0.0, 0.0, 0.0};
+    c2 a = lda(k4), b = ldb(k4);
+    for (int l0 = 0; l0 < K; l0 += 4) {
+      const c2 an = lda(l0 + 4 + k4), bn = ldb(l0 + 4 + k4);
+      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.r, b.r, cr, 0, 0, 0);
+      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.i, b.i, cr, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.r, b.i, ci, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.i, b.r, ci, 0, 0, 0);
+      a = an;
+      b = bn;
     }
+    // accumulator entry v of lane (k4, r16) is C[i0 + 4 v + k4][j0 + r16]
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int b = 0; b < 3; ++b)
-        if (i0 + a < M && j0 + b < N) C[(i0 + a) * ldc + j0 + b] = acc[a][b];
-  }
-}
-
-// C (M x N, stride ldc) = X^* Y, X (K x M, stride ldx), Y (K x N, stride ldy).
-__device__ __forceinline__ void mm_cn(const c2* X, int ldx, const c2* Y, int ldy, c2* C, int ldc, int M, int N, int K) {
-  const int bm = (M + 2) / 3, bn = (N + 2) / 3;
-  for (int e = threadIdx.x; e < bm * bn; e += blockDim.x) {
-    const int i0 = (e / bn) * 3, j0 = (e % bn) * 3;
-    c2 acc[3][3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int b = 0; b < 3; ++b) acc[a][b] = {0, 0};
-    for (int l = 0; l < K; ++l) {
-      c2 xa[3], yb[3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a) xa[a] = (i0 + a < M) ? X[l * ldx + i0 + a] : c2{0, 0};
-#pragma unroll
-      for (int b = 0; b < 3; ++b) yb[b] = (j0 + b < N) ? Y[l * ldy + j0 + b] : c2{0, 0};
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-          const c2 t = cmulc(xa[a], yb[b]);
-          acc[a][b].r += t.r;
-          acc[a][b].i += t.i;
-        }
+    for (int v = 0; v < 4; ++v) {
+      const int i = i0 + 4 * v + k4, j = j0 + r16;
+      if (i < M && j < N) C[(int64_t)i * ldc + j] = c2{cr[v], ci[v]};
     }
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int b = 0; b < 3; ++b)
-        if (i0 + a < M && j0 + b < N) C[(i0 + a) * ldc + j0 + b] = acc[a][b];
   }
 }
 
@@ -571,9 +552,9 @@ __global__ __launch_bounds__(TG * TG) void k_ritz(const c2* __restrict__ G, cons
   if (second_s) {   // G2 = Z^* G Z = L2 L2^*, Z <- Z L2^{-*}
     for (int e = tid; e < q * q; e += nt) B[(e / q) * lq + e % q] = G[e];   // G into the free B region
     __syncthreads();
-    mm_nn(B, lq, Z, lr, T, lr, q, r, q);
+    mm_mfma<false, false>(B, lq, Z, lr, T, lr, q, r, q, r);
     __syncthreads();
-    mm_cn(Z, lr, T, lr, A, lr, r, r, q);
+    mm_mfma<true, false>(Z, lr, T, lr, A, lr, r, r, q, r);
     __syncthreads();
     // distance of G2 from the identity (max entry); when it is small, one Newton-Schulz step
     // Z <- Z (3I - G2) / 2 restores orthonormality to O(dev^2), else the Cholesky route
@@ -595,7 +576,7 @@ __global__ __launch_bounds__(TG * TG) void k_ritz(const c2* __restrict__ G, cons
         A[i * lr + j] = (i == j) ? c2{1.5 - 0.5 * a.r, -0.5 * a.i} : c2{-0.5 * a.r, -0.5 * a.i};
       }
       __syncthreads();
-      mm_nn(Z, lr, A, lr, T, lr, q, r, r);
+      mm_mfma<false, false>(Z, lr, A, lr, T, lr, q, r, r, r);
     } else {
       chol(A, B, r, lr);
       lower_inv(B, lr, A, lr, r);
@@ -619,9 +600,9 @@ __global__ __launch_bounds__(TG * TG) void k_ritz(const c2* __restrict__ G, cons
   // ---- 3. H' = Z^* H Z (A, stride r), Hermitian part, then tridiagonalisation ----------------
   for (int e = tid; e < q * q; e += nt) B[(e / q) * lq + e % q] = H[e];   // H into the free B region
   __syncthreads();
-  mm_nn(B, lq, Z, lr, T, lr, q, r, q);
+  mm_mfma<false, false>(B, lq, Z, lr, T, lr, q, r, q, r);
   __syncthreads();
-  mm_cn(Z, lr, T, lr, A, lr, r, r, q);
+  mm_mfma<true, false>(Z, lr, T, lr, A, lr, r, r, q, r);
   __syncthreads();
   for (int e = tid; e < r * r; e += nt) {
     const int a = e / r, b = e % r;
@@ -1146,37 +1127,7 @@ __global__ __launch_bounds__(TG * TG) void k_ritz(const c2* __restrict__ G, cons
   }
   __syncthreads();
   // Y (q x want) = Z (q x r) y; columns ns..want-1 zero
-  {
-    const int bm = (q + 2) / 3, bn = (want + 2) / 3;
-    for (int e = tid; e < bm * bn; e += nt) {
-      const int i0 = (e / bn) * 3, j0 = (e % bn) * 3;
-      c2 acc[3][3];
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) acc[a][b] = {0, 0};
-      for (int l = 0; l < r; ++l) {
-        c2 za[3], yb[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) za[a] = (i0 + a < q) ? Z[(i0 + a) * lr + l] : c2{0, 0};
-#pragma unroll
-        for (int b = 0; b < 3; ++b) yb[b] = (j0 + b < ns) ? yv[(j0 + b) * lr + l] : c2{0, 0};
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-          for (int b = 0; b < 3; ++b) {
-            const c2 t = cmul(za[a], yb[b]);
-            acc[a][b].r += t.r;
-            acc[a][b].i += t.i;
-          }
-      }
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b)
-          if (i0 + a < q && j0 + b < want) Y[(i0 + a) * want + j0 + b] = acc[a][b];
-    }
-  }
+  mm_mfma<false, true>(Z, lr, yv, lr, Y, want, q, want, r, ns);
   for (int c = tid; c < want; c += nt) theta[c] = c < ns ? lam[c] : 0.0;
   if (tid == 0) {
     *count = ns;
