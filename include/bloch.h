@@ -124,6 +124,13 @@ typedef struct bl_opts {
                            edges (checked at creation).  0 = the block in the slot (0)      */
   double nested_tol;    /* relative residual to which the levels below the finest are
                            iterated in the nested start; 0 selects 1e-2                    */
+  double lock_rel;      /* soft locking of converged pairs (gradient variant): after a
+                           round, the leading pairs whose stopping measure is at most
+                           lock_rel * tol in every slot of the round get no preconditioned
+                           direction in the next basis [E, C] (their vectors stay in it, so
+                           the Ritz step still refines them, and a pair that drifts back
+                           above the bound is unlocked in the next round); the stopping test
+                           over all nev pairs is unchanged.  0 = off, at most 1 (0)         */
 } bl_opts;
 
 /* Read-only facts about a solver handle. */
@@ -141,6 +148,8 @@ typedef struct bl_info {
   int32_t fused_nodal_level;  /* same for the nodal V-cycle (cycle precision)            */
   int32_t reserved;
   double autotune_ms;   /* time spent tuning at creation (0 when cached or off)        */
+  int64_t locked_columns; /* soft-locked columns (bl_opts.lock_rel) summed over the
+                             iterations and slots since creation                        */
 } bl_info;
 
 /* Fill *opts with the defaults for `nev` wanted eigenpairs (nthrow = nev/2). */

@@ -87,7 +87,8 @@ def _info_dict(inf) -> dict:
             "edge_smooth_shape": list(inf.edge_smooth_shape),
             "nodal_smooth_shape": list(inf.nodal_smooth_shape),
             "rr_tile": inf.rr_tile, "autotune_ms": inf.autotune_ms,
-            "fused_edge_level": inf.fused_edge_level, "fused_nodal_level": inf.fused_nodal_level}
+            "fused_edge_level": inf.fused_edge_level, "fused_nodal_level": inf.fused_nodal_level,
+            "locked_columns": inf.locked_columns}
 
 
 def _marshal_problems(problems, want_last_vectors):
@@ -282,7 +283,7 @@ class Solver:
     Keyword options map to bl_opts fields: nev, nthrow, max_iter, levels, coarsest_min,
     nu_pre, nu_post, nodal_cycles, variant ("gradient" | "lobpcg" or 0 | 1), precision ("fp64" |
     "mixed" or 0 | 1),
-    extrap_depth, tol, mu, zero_rel."""
+    extrap_depth, tol, mu, zero_rel, lock_rel and the other bl_opts fields by name."""
 
     def __init__(self, n, m, a, b, eps, nev=8, stream=None, **opts):
         torch = _torch()

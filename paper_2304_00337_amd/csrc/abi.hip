@@ -162,6 +162,7 @@ void bl::fill_info(const bl_solver* s, bl_info* out) {
   out->nodal_smooth_shape[2] = s->tune_nodal.xcd;
   out->rr_tile = 16 * (s->tune_rr ? s->tune_rr : rr_tile(2 * s->p));
   out->autotune_ms = s->tune_ms;
+  out->locked_columns = s->locked_cols;
   out->fused_edge_level = s->fuse_edge[s->opts.precision ? 1 : 0];
   out->fused_nodal_level = s->fuse_nodal[s->opts.precision ? 1 : 0];
 }

@@ -63,6 +63,7 @@ struct SlotState {
   double mu = 1.0;
   double kappa_max = 1.0;   // largest 1/eps of the slot's permittivity (residual floor)
   bool e_start = false;     // E holds the start block of the task's first point (nested start)
+  int lock = 0;             // leading pairs within the soft-locking bound after the last round
   std::vector<double> res_rows;
 };
 
@@ -172,6 +173,7 @@ struct bl_solver {
   std::vector<void*> allocs;
   size_t dev_bytes = 0;
   int64_t launches = 0;
+  int64_t locked_cols = 0;   // soft-locked columns summed over slots and iterations
   int64_t rounds = 0;
   std::vector<double> last_res_hist;   // slot 0, last point
   int last_res_rows = 0;

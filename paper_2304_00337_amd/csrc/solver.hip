@@ -128,6 +128,7 @@ int validate_opts(const bl_opts* o) {
   if (o->tol_floor != 0 && o->tol_floor != 1) return set_error(BL_EINVAL, "tol_floor must be 0 or 1%s");
   if (o->nested_start != 0 && o->nested_start != 1) return set_error(BL_EINVAL, "nested_start must be 0 or 1%s");
   if (!(o->nested_tol >= 0) || o->nested_tol >= 1) return set_error(BL_EINVAL, "nested_tol must be in [0, 1)%s");
+  if (!(o->lock_rel >= 0) || o->lock_rel > 1) return set_error(BL_EINVAL, "lock_rel must be in [0, 1]%s");
   return BL_OK;
 }
 
@@ -1186,6 +1187,9 @@ void engine_destroy(bl_solver* s) {
   if (!s) return;
   if (s->st) (void)hipStreamSynchronize(s->st);
   else (void)hipDeviceSynchronize();
+  if (s->debug && s->rounds > 0)
+    std::fprintf(stderr, "bloch: %lld rounds, %.2f soft-locked columns per round\n", (long long)s->rounds,
+                 (double)s->locked_cols / (double)s->rounds);
   for (void* p : s->allocs) (void)hipFree(p);
   if (s->lists_h) (void)hipHostFree(s->lists_h);
   if (s->norms_h) (void)hipHostFree(s->norms_h);   // lam_h and count_h point into it
@@ -1353,28 +1357,40 @@ int engine_finish(bl_solver* s) {
       floor_num = std::ldexp(1.0, -53) * 8.0 * ss.kappa_max * g0.s / std::min(g0.mx, g0.my);
     }
     bool conv = true;
+    int lead = 0;   // leading pairs within the locking bound
     for (int j = 0; j < t->nev; ++j) {
       ss.res_rows.push_back(rel[j]);
       const double tol_j = std::max(s->opts.tol, lam[j] != 0.0 ? floor_num / std::fabs(lam[j]) : 0.0);
       conv = conv && (rel[j] <= tol_j);
+      if (lead == j && rel[j] <= s->opts.lock_rel * tol_j) ++lead;
     }
     if (conv || ss.it >= s->opts.max_iter) {
       if ((rc = retire_point(s, sl, conv, lam, rel))) return rc;
     } else {
       cont.push_back(sl);
+      ss.lock = lead;
     }
   }
   s->issued.clear();
   if (!cont.empty()) {
     const int ip = s->opts.precision;
+    const bool lob = s->opts.variant == 1;
     Level& L0 = s->lv[0];
     Launch L = make_launch(s, cont, p);
-    if (ip) vcycle_edge<float>(s, 0, cview(static_cast<const float*>(L0.eb[1]), L0.ecap[1]), view(static_cast<float*>(L0.ex[1]), L0.ecap[1]), L);
-    else vcycle_edge<double>(s, 0, cview(static_cast<const double*>(L0.eb[0]), L0.ecap[0]), view(static_cast<double*>(L0.ex[0]), L0.ecap[0]), L);
+    // soft locking (gradient variant): the first c columns, within the locking bound in every
+    // continuing slot, get no preconditioned direction; the V-cycle, the projection and the
+    // Ritz step run on the other p - c (c < nev: an unconverged slot has a pair above tol)
+    int c = p;
+    for (int sl : cont) c = std::min(c, s->slot[sl].lock);
+    if (lob || !(s->opts.lock_rel > 0)) c = 0;
+    s->locked_cols += (int64_t)c * (int64_t)cont.size();
+    Launch Lc = L;
+    Lc.ncps = p - c;
+    if (ip) vcycle_edge<float>(s, 0, cview(static_cast<const float*>(L0.eb[1]), L0.ecap[1], c), view(static_cast<float*>(L0.ex[1]), L0.ecap[1], c), Lc);
+    else vcycle_edge<double>(s, 0, cview(static_cast<const double*>(L0.eb[0]), L0.ecap[0], c), view(static_cast<double*>(L0.ex[0]), L0.ecap[0], c), Lc);
     // LOBPCG (Section 4): from the second iteration of a point on, the basis also holds the
     // previous block's direction D = E_prev - E (E^* M E_prev); the gradient variant, and the
     // first iteration, use [E, C]
-    const bool lob = s->opts.variant == 1;
     std::vector<int> three, two;
     for (int sl : cont) (lob && s->slot[sl].it > 0 ? three : two).push_back(sl);
     const View<const double> none{nullptr, 0, 0};
@@ -1394,10 +1410,10 @@ int engine_finish(bl_solver* s) {
       if ((rc = ritz_step(s, three, 3 * p, p, false))) return rc;
     }
     if (!two.empty()) {
-      if ((rc = project(s, {{s->E, p, 0, 0, p}, {L0.ex[ip], L0.ecap[ip], 0, ip, p}}, view(s->Sb, s->qmax), two)))
+      if ((rc = project(s, {{s->E, p, 0, 0, p}, {L0.ex[ip], L0.ecap[ip], c, ip, p - c}}, view(s->Sb, s->qmax), two)))
         return rc;
       if (lob) sub_cols<double>(cview(s->E, p), none, view(s->Eprev, p), L0.g.ne, make_launch(s, two, p));
-      if ((rc = ritz_step(s, two, 2 * p, p, false))) return rc;
+      if ((rc = ritz_step(s, two, 2 * p - c, p, false))) return rc;
     }
     for (int sl : cont) s->slot[sl].it += 1;
   }

@@ -39,7 +39,7 @@ class BlOpts(ctypes.Structure):
                 ("coarse_fuse", c_int32), ("tiled_sweeps", c_int32),
                 ("tol", c_double), ("mu", c_double), ("zero_rel", c_double),
                 ("engine_streams", c_int32), ("tol_abs", c_int32), ("tol_floor", c_int32),
-                ("nested_start", c_int32), ("nested_tol", c_double)]
+                ("nested_start", c_int32), ("nested_tol", c_double), ("lock_rel", c_double)]
 
 
 class BlInfo(ctypes.Structure):
@@ -49,7 +49,7 @@ class BlInfo(ctypes.Structure):
                 ("kernel_launches", c_int64), ("edge_smooth_shape", c_int32 * 3),
                 ("nodal_smooth_shape", c_int32 * 3), ("rr_tile", c_int32),
                 ("fused_edge_level", c_int32), ("fused_nodal_level", c_int32), ("reserved", c_int32),
-                ("autotune_ms", c_double)]
+                ("autotune_ms", c_double), ("locked_columns", c_int64)]
 
 
 class BlProblem(ctypes.Structure):

@@ -329,6 +329,37 @@ def test_short_path_matches_oracle_path(precision):
     assert np.median(r["iterations"][2:]) < r["iterations"][0]
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_soft_locking_keeps_the_results(precision):
+    """Soft locking (no V-cycle direction for the converged leading pairs) changes the basis
+    of later iterations only: the path's eigenvalues still match the dense solve at the
+    stated tolerance, the locked run takes about as many iterations (within 10%: the dropped
+    directions of a pair locked just below tol can cost it an extra iteration), and it did
+    lock."""
+    n = 32
+    eps = synth.eps_disc_lattice(n, n, 1.0, 1.0, 12.0, 0.3)
+    ks = synth.path_gxmg(3)[:5]
+    nev, nthrow = 8, 4
+    start = synth.start_block(2 * n * n, nev + nthrow, 2)
+    from paper_2304_00337_amd import Solver
+    from paper_2304_00337_amd.native import BlochError
+    runs = {}
+    for lock in (0.0, 1.0):
+        s = Solver(n, n, 1.0, 1.0, eps, nev=nev, nthrow=nthrow, mu=10.0, precision=precision,
+                   tol=1e-9, max_iter=300, lock_rel=lock)
+        runs[lock] = (s.solve_path(ks, start=start), s.info()["locked_columns"])
+    assert runs[0.0][1] == 0 and runs[1.0][1] > 0
+    tol = 1e-9 if precision == "fp64" else 1e-6
+    for lock, (r, _) in runs.items():
+        assert r["converged"], lock
+        for t, k in enumerate(ks):
+            ref, _, _ = dense_eigs(fem.Discretization(n, n, 1.0, 1.0, eps, *k), nev)
+            assert np.max(np.abs(r["evals"][t] - ref) / ref) < tol, (lock, t)
+    assert np.sum(runs[1.0][0]["iterations"]) <= 1.1 * np.sum(runs[0.0][0]["iterations"]) + 2
+    with pytest.raises(BlochError):
+        Solver(n, n, 1.0, 1.0, eps, nev=nev, nthrow=nthrow, lock_rel=1.5)
+
+
 def test_mixed_equals_fp64_and_alone_equals_repeat():
     prob = synth.config_c1()
     s64 = _solver(prob, "fp64", levels=3, nthrow=4, max_iter=300)
