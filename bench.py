@@ -541,7 +541,7 @@ def main():
         "config": {"workload": "1024x1024 unit cell, smoothed random two-phase eps {1, 11.4} (seed 2), 61 k on "
                                "Gamma-X-M-Gamma (20 per leg), nev 32 (+16), rel. residual tol 1e-6, 8-level MG; "
                                "one step = one leg (legs in turn), nested start per leg (Section 6, levels to 1e-2), "
-                               "extrapolation within, soft locking of converged leading pairs",
+                               "extrapolation within, soft locking of converged pairs",
                    "n": prob.n, "nk": len(prob.ks), "nev": prob.nev, "p": prob.p, "legs": [20, 20, 21],
                    "lock_rel": LOCK_REL},
         "eigenpairs_counted": good, "eigenpairs_solved": total,

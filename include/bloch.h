@@ -125,12 +125,14 @@ typedef struct bl_opts {
   double nested_tol;    /* relative residual to which the levels below the finest are
                            iterated in the nested start; 0 selects 1e-2                    */
   double lock_rel;      /* soft locking of converged pairs (gradient variant): after a
-                           round, the leading pairs whose stopping measure is at most
-                           lock_rel * tol in every slot of the round get no preconditioned
-                           direction in the next basis [E, C] (their vectors stay in it, so
-                           the Ritz step still refines them, and a pair that drifts back
-                           above the bound is unlocked in the next round); the stopping test
-                           over all nev pairs is unchanged.  0 = off, at most 1 (0)         */
+                           round, the wanted pairs whose stopping measure is at most
+                           lock_rel * tol get no preconditioned direction in the next basis
+                           [E, C] (their vectors stay in it, so the Ritz step still refines
+                           them, and a pair that drifts back above the bound is unlocked in
+                           the next round); in a round of several slots, a slot with more
+                           locked pairs than another keeps some of them unlocked, so that
+                           all slots share one column count.  The stopping test over all nev
+                           pairs is unchanged.  0 = off, at most 1 (0)                      */
 } bl_opts;
 
 /* Read-only facts about a solver handle. */

@@ -451,4 +451,47 @@ void block_combine(View<const double> S, int q, const double* Y, int want, int64
   else go(std::integral_constant<int, 3>{});
 }
 
+// ------------------------------------------------------------------------------------------
+// In-place column compaction: column k of the view receives column src[k] (k < ncols,
+// src[k] >= k, strictly increasing per slot).  Every thread owns one 16-byte position of
+// all columns, so threads never touch each other's data; a thread loads a chunk of source
+// columns before it stores them (a destination may be the source of a later column of the
+// chunk), and a later chunk's sources lie above every earlier destination.
+template <typename T>
+__global__ void k_compact_cols(View<T> v, int64_t len, const int* __restrict__ src, int src_stride, int ncols,
+                               const int* __restrict__ slots) {
+  using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+  constexpr int CH = 8;
+  const int z = blockIdx.y;
+  const int sl = slots ? slots[z] : z;
+  const int* sk = src + (int64_t)z * src_stride;
+  const int64_t nvec = 2 * len * (int64_t)sizeof(T) / (int64_t)sizeof(V);
+  V* base = reinterpret_cast<V*>(v.p + ((int64_t)sl * v.cps + v.off) * 2 * len);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvec; i += (int64_t)gridDim.x * blockDim.x) {
+    for (int k0 = 0; k0 < ncols; k0 += CH) {
+      V buf[CH];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int k = k0 + u;
+        if (k < ncols && sk[k] != k) buf[u] = base[(int64_t)sk[k] * nvec + i];
+      }
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int k = k0 + u;
+        if (k < ncols && sk[k] != k) base[(int64_t)k * nvec + i] = buf[u];
+      }
+    }
+  }
+}
+template <typename T>
+void compact_cols(View<T> v, int64_t len, const int* src, int src_stride, int ncols, const Launch& L) {
+  if (L.nact <= 0 || ncols <= 0) return;
+  const int64_t nvec = 2 * len * (int64_t)sizeof(T) / 16;
+  int64_t nb = (nvec + 255) / 256;
+  if (nb > 2048) nb = 2048;
+  k_compact_cols<T><<<dim3((unsigned)nb, (unsigned)L.nact), 256, 0, L.st>>>(v, len, src, src_stride, ncols, L.slots);
+}
+template void compact_cols<float>(View<float>, int64_t, const int*, int, int, const Launch&);
+template void compact_cols<double>(View<double>, int64_t, const int*, int, int, const Launch&);
+
 }  // namespace bl

@@ -64,6 +64,7 @@ struct SlotState {
   double kappa_max = 1.0;   // largest 1/eps of the slot's permittivity (residual floor)
   bool e_start = false;     // E holds the start block of the task's first point (nested start)
   int lock = 0;             // leading pairs within the soft-locking bound after the last round
+  std::vector<char> lockmask;   // pairs within the soft-locking bound after the last round
   std::vector<double> res_rows;
 };
 
@@ -161,6 +162,8 @@ struct bl_solver {
   // slot lists: pinned host staging and device copies, recycled after each synchronisation
   int* lists_h = nullptr;
   int* lists_d = nullptr;
+  int* colidx_h = nullptr;   // soft locking: per slot of a round, the source of each kept column
+  int* colidx_d = nullptr;   // (nslots * p)
   int lists_used = 0;
   // read-back of the residual round (pinned)
   double* norms_h = nullptr;

@@ -208,6 +208,12 @@ void axpy(View<T> y, View<const T> x, int64_t len, const Launch& L);
 template <typename T>
 void sub_cols(View<const T> a, View<const T> b, View<T> out, int64_t len, const Launch& L);
 
+// Column k of v (columns of length len, k < ncols) receives column src[z * src_stride + k]
+// of the same slot (z the launch's slot index), in place; per slot src[k] >= k and strictly
+// increasing.  Columns with src[k] == k are not touched.
+template <typename T>
+void compact_cols(View<T> v, int64_t len, const int* src, int src_stride, int ncols, const Launch& L);
+
 template <typename T>
 void fill_zero(T* p, int64_t count, hipStream_t st);
 template <typename T>

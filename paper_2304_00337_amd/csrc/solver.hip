@@ -1142,7 +1142,9 @@ int engine_create(const bl_grid* grid, const bl_opts* opts, int nslots, hipStrea
   if ((rc = dalloc_t(s, &s->pc_inv64, (size_t)2 * s->ncn * s->ncn * S))) return fail(rc);
   if ((rc = dalloc_t(s, &s->pc_inv32, (size_t)2 * s->ncn * s->ncn * S))) return fail(rc);
   if ((rc = dalloc_t(s, &s->lists_d, (size_t)kMaxLists * S))) return fail(rc);
+  if ((rc = dalloc_t(s, &s->colidx_d, (size_t)S * p))) return fail(rc);
   if (hipHostMalloc((void**)&s->lists_h, (size_t)kMaxLists * S * sizeof(int), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&s->colidx_h, (size_t)S * p * sizeof(int), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&s->norms_h, s->readback_bytes, hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc(&s->param_h, (size_t)S * (sizeof(Phase) + 8 + sizeof(PlaneWave)), hipHostMallocDefault) != hipSuccess)
     return fail(set_error(BL_ENOMEM, "pinned host allocation failed%s"));
@@ -1192,6 +1194,7 @@ void engine_destroy(bl_solver* s) {
                  (double)s->locked_cols / (double)s->rounds);
   for (void* p : s->allocs) (void)hipFree(p);
   if (s->lists_h) (void)hipHostFree(s->lists_h);
+  if (s->colidx_h) (void)hipHostFree(s->colidx_h);
   if (s->norms_h) (void)hipHostFree(s->norms_h);   // lam_h and count_h point into it
   if (s->param_h) (void)hipHostFree(s->param_h);
   for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
@@ -1358,11 +1361,13 @@ int engine_finish(bl_solver* s) {
     }
     bool conv = true;
     int lead = 0;   // leading pairs within the locking bound
+    ss.lockmask.assign(p, 0);
     for (int j = 0; j < t->nev; ++j) {
       ss.res_rows.push_back(rel[j]);
       const double tol_j = std::max(s->opts.tol, lam[j] != 0.0 ? floor_num / std::fabs(lam[j]) : 0.0);
       conv = conv && (rel[j] <= tol_j);
-      if (lead == j && rel[j] <= s->opts.lock_rel * tol_j) ++lead;
+      ss.lockmask[j] = rel[j] <= s->opts.lock_rel * tol_j;
+      if (lead == j && ss.lockmask[j]) ++lead;
     }
     if (conv || ss.it >= s->opts.max_iter) {
       if ((rc = retire_point(s, sl, conv, lam, rel))) return rc;
@@ -1377,17 +1382,58 @@ int engine_finish(bl_solver* s) {
     const bool lob = s->opts.variant == 1;
     Level& L0 = s->lv[0];
     Launch L = make_launch(s, cont, p);
-    // soft locking (gradient variant): the first c columns, within the locking bound in every
-    // continuing slot, get no preconditioned direction; the V-cycle, the projection and the
-    // Ritz step run on the other p - c (c < nev: an unconverged slot has a pair above tol)
-    int c = p;
-    for (int sl : cont) c = std::min(c, s->slot[sl].lock);
-    if (lob || !(s->opts.lock_rel > 0)) c = 0;
-    s->locked_cols += (int64_t)c * (int64_t)cont.size();
+    // soft locking (gradient variant): the pairs within the locking bound get no
+    // preconditioned direction.  The c leading columns locked in every continuing slot are
+    // skipped through the views' offset; further locked columns are squeezed out of the
+    // residual block in place, so that the V-cycle, the projection and the Ritz step run on
+    // the a columns from c on (a = p minus the fewest locked columns of a slot; a slot with
+    // more locked columns keeps its highest locked ones to that width).  c < nev and a > 0:
+    // an unconverged slot has a pair above tol, and the throw-away vectors are never locked.
+    int c = 0, a = p;
+    bool moved = false;
+    if (!lob && s->opts.lock_rel > 0) {
+      c = p;
+      int fewest = p;
+      for (int sl : cont) {
+        const SlotState& ss = s->slot[sl];
+        c = std::min(c, ss.lock);
+        int nl = 0;
+        for (int j = 0; j < p; ++j) nl += ss.lockmask[j] ? 1 : 0;
+        fewest = std::min(fewest, nl);
+      }
+      a = p - fewest;
+      for (size_t z = 0; z < cont.size(); ++z) {
+        const SlotState& ss = s->slot[cont[z]];
+        std::vector<char> keep(p, 0);
+        int nk = 0;
+        for (int j = c; j < p; ++j)
+          if (!ss.lockmask[j]) keep[j] = 1, ++nk;
+        for (int j = p - 1; j >= c && nk < a; --j)
+          if (!keep[j]) keep[j] = 1, ++nk;
+        int k = 0;
+        for (int j = c; j < p; ++j)
+          if (keep[j]) {
+            s->colidx_h[z * p + k] = j - c;
+            moved = moved || j - c != k;
+            ++k;
+          }
+      }
+      if (moved)
+        HIP_OK(hipMemcpyAsync(s->colidx_d, s->colidx_h, cont.size() * p * sizeof(int), hipMemcpyHostToDevice, s->st));
+    }
+    s->locked_cols += (int64_t)(p - a) * (int64_t)cont.size();
     Launch Lc = L;
-    Lc.ncps = p - c;
-    if (ip) vcycle_edge<float>(s, 0, cview(static_cast<const float*>(L0.eb[1]), L0.ecap[1], c), view(static_cast<float*>(L0.ex[1]), L0.ecap[1], c), Lc);
-    else vcycle_edge<double>(s, 0, cview(static_cast<const double*>(L0.eb[0]), L0.ecap[0], c), view(static_cast<double*>(L0.ex[0]), L0.ecap[0], c), Lc);
+    Lc.ncps = a;
+    if (ip) {
+      const View<float> R = view(static_cast<float*>(L0.eb[1]), L0.ecap[1], c);
+      if (moved) compact_cols<float>(R, L0.g.ne, s->colidx_d, p, a, L);
+      vcycle_edge<float>(s, 0, cv(R), view(static_cast<float*>(L0.ex[1]), L0.ecap[1], c), Lc);
+    } else {
+      const View<double> R = view(static_cast<double*>(L0.eb[0]), L0.ecap[0], c);
+      if (moved) compact_cols<double>(R, L0.g.ne, s->colidx_d, p, a, L);
+      vcycle_edge<double>(s, 0, cv(R), view(static_cast<double*>(L0.ex[0]), L0.ecap[0], c), Lc);
+    }
+    s->launches += moved ? 1 : 0;
     // LOBPCG (Section 4): from the second iteration of a point on, the basis also holds the
     // previous block's direction D = E_prev - E (E^* M E_prev); the gradient variant, and the
     // first iteration, use [E, C]
@@ -1410,10 +1456,10 @@ int engine_finish(bl_solver* s) {
       if ((rc = ritz_step(s, three, 3 * p, p, false))) return rc;
     }
     if (!two.empty()) {
-      if ((rc = project(s, {{s->E, p, 0, 0, p}, {L0.ex[ip], L0.ecap[ip], c, ip, p - c}}, view(s->Sb, s->qmax), two)))
+      if ((rc = project(s, {{s->E, p, 0, 0, p}, {L0.ex[ip], L0.ecap[ip], c, ip, a}}, view(s->Sb, s->qmax), two)))
         return rc;
       if (lob) sub_cols<double>(cview(s->E, p), none, view(s->Eprev, p), L0.g.ne, make_launch(s, two, p));
-      if ((rc = ritz_step(s, two, 2 * p - c, p, false))) return rc;
+      if ((rc = ritz_step(s, two, p + a, p, false))) return rc;
     }
     for (int sl : cont) s->slot[sl].it += 1;
   }

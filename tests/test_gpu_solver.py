@@ -331,8 +331,9 @@ def test_short_path_matches_oracle_path(precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_soft_locking_keeps_the_results(precision):
-    """Soft locking (no V-cycle direction for the converged leading pairs) changes the basis
-    of later iterations only: the path's eigenvalues still match the dense solve at the
+    """Soft locking (no V-cycle direction for the converged pairs: a leading run skipped by
+    the column offset, pairs further in squeezed out of the residual block in place) changes
+    the basis of later iterations only: the path's eigenvalues still match the dense solve at the
     stated tolerance, the locked run takes about as many iterations (within 10%: the dropped
     directions of a pair locked just below tol can cost it an extra iteration), and it did
     lock."""
