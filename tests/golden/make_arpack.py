@@ -5,12 +5,13 @@ last point before Gamma); with --z2, of the band-structure experiment's cell (ep
 the disc of radius 0.18, 16 pairs) at 256 x 256 on its kappa = 30 raster at the two points
 next to Gamma, (i, j) = (14, 14) and (15, 14); with --c3, of the 1024 x 1024 random
 two-phase workload (32 pairs) at its first point after Gamma and at X; with --c4small, of
-the six problems of synth.config_c4_small (n 64..128, nev 4..16).  Source:
+the six problems of synth.config_c4_small (n 64..128, nev 4..16); with --c3 --add i,j, the
+listed path points of the 1024 x 1024 workload, merged into its existing file.  Source:
 oracle.dense.gradient_free_eigs (ARPACK on the pencil restricted to the complement of the
 null space by exact sparse projections; the kernel cluster of dimension nm would defeat the
 plain shift-invert certificate).  Calls only oracle/ and the input generators.
 
-Run from the repository root:  python tests/golden/make_arpack.py [--z2 | --c3 | --c4small]
+Run from the repository root:  python tests/golden/make_arpack.py [--z2 | --c3 [--add i,j] | --c4small]
 """
 import json
 import os
@@ -68,6 +69,30 @@ def main():
                "source": "oracle.dense.gradient_free_eigs (ARPACK on the complement of the null space)",
                "points": pts}
         name = "arpack_z2_256.json"
+    elif "--c3" in sys.argv and "--add" in sys.argv:
+        # further points of the 1024 x 1024 path, merged into the stored file under a lock
+        # (several of these runs may go in parallel, one point each)
+        import fcntl
+        prob = synth.config_c3()
+        idx = [int(v) for v in sys.argv[sys.argv.index("--add") + 1].split(",")]
+        pts = run(prob, idx, 32)
+        path = os.path.join(here, "arpack_c3_1024.json")
+        with open(path + ".lock", "w") as lk:
+            fcntl.flock(lk, fcntl.LOCK_EX)
+            with open(path) as f:
+                out = json.load(f)
+            have = {p["index"]: p for p in out["points"]}
+            for pt in pts:
+                have[pt["index"]] = pt
+            out["points"] = [have[i] for i in sorted(have)]
+            with open(path, "w") as f:
+                json.dump(out, f, indent=1)
+        try:
+            os.remove(path + ".lock")
+        except FileNotFoundError:   # the other run removed it first
+            pass
+        print(f"merged points {idx} into {path}")
+        return
     elif "--c3" in sys.argv:
         prob = synth.config_c3()
         out = {"workload": "1024x1024, a=b=1, smoothed random field {1, 11.4} (seed 2), 61 points "
