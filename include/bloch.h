@@ -133,6 +133,11 @@ typedef struct bl_opts {
                            locked pairs than another keeps some of them unlocked, so that
                            all slots share one column count.  The stopping test over all nev
                            pairs is unchanged.  0 = off, at most 1 (0)                      */
+  int32_t throw_precond; /* throw-away vectors (Section 7) that receive a preconditioned
+                            direction in each round: the first throw_precond of them (next
+                            to the wanted pairs); the others stay in the block E and are
+                            refined by the Ritz step only (gradient variant).  0 = all (0)  */
+  int32_t reserved_opts; /* must be 0                                                    */
 } bl_opts;
 
 /* Read-only facts about a solver handle. */

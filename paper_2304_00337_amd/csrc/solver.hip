@@ -129,6 +129,7 @@ int validate_opts(const bl_opts* o) {
   if (o->nested_start != 0 && o->nested_start != 1) return set_error(BL_EINVAL, "nested_start must be 0 or 1%s");
   if (!(o->nested_tol >= 0) || o->nested_tol >= 1) return set_error(BL_EINVAL, "nested_tol must be in [0, 1)%s");
   if (!(o->lock_rel >= 0) || o->lock_rel > 1) return set_error(BL_EINVAL, "lock_rel must be in [0, 1]%s");
+  if (o->throw_precond < 0 || o->reserved_opts != 0) return set_error(BL_EINVAL, "throw_precond must be >= 0%s");
   return BL_OK;
 }
 
@@ -1366,9 +1367,12 @@ int engine_finish(bl_solver* s) {
       ss.res_rows.push_back(rel[j]);
       const double tol_j = std::max(s->opts.tol, lam[j] != 0.0 ? floor_num / std::fabs(lam[j]) : 0.0);
       conv = conv && (rel[j] <= tol_j);
-      ss.lockmask[j] = rel[j] <= s->opts.lock_rel * tol_j;
+      ss.lockmask[j] = s->opts.lock_rel > 0 && rel[j] <= s->opts.lock_rel * tol_j;
       if (lead == j && ss.lockmask[j]) ++lead;
     }
+    // throw-away vectors past the first throw_precond get no preconditioned direction either
+    if (s->opts.throw_precond > 0)
+      for (int j = t->nev + s->opts.throw_precond; j < p; ++j) ss.lockmask[j] = 1;
     if (conv || ss.it >= s->opts.max_iter) {
       if ((rc = retire_point(s, sl, conv, lam, rel))) return rc;
     } else {
@@ -1382,16 +1386,16 @@ int engine_finish(bl_solver* s) {
     const bool lob = s->opts.variant == 1;
     Level& L0 = s->lv[0];
     Launch L = make_launch(s, cont, p);
-    // soft locking (gradient variant): the pairs within the locking bound get no
-    // preconditioned direction.  The c leading columns locked in every continuing slot are
-    // skipped through the views' offset; further locked columns are squeezed out of the
-    // residual block in place, so that the V-cycle, the projection and the Ritz step run on
-    // the a columns from c on (a = p minus the fewest locked columns of a slot; a slot with
-    // more locked columns keeps its highest locked ones to that width).  c < nev and a > 0:
-    // an unconverged slot has a pair above tol, and the throw-away vectors are never locked.
+    // soft locking (gradient variant): the pairs within the locking bound, and the throw-away
+    // vectors past the first throw_precond, get no preconditioned direction.  The c leading
+    // columns locked in every continuing slot are skipped through the views' offset; further
+    // locked columns are squeezed out of the residual block in place, so that the V-cycle,
+    // the projection and the Ritz step run on the a columns from c on (a = p minus the fewest
+    // locked columns of a slot; a slot with more locked columns keeps its highest locked ones
+    // to that width).  c < nev and a > 0: an unconverged slot has a wanted pair above tol.
     int c = 0, a = p;
     bool moved = false;
-    if (!lob && s->opts.lock_rel > 0) {
+    if (!lob && (s->opts.lock_rel > 0 || s->opts.throw_precond > 0)) {
       c = p;
       int fewest = p;
       for (int sl : cont) {

@@ -39,7 +39,8 @@ class BlOpts(ctypes.Structure):
                 ("coarse_fuse", c_int32), ("tiled_sweeps", c_int32),
                 ("tol", c_double), ("mu", c_double), ("zero_rel", c_double),
                 ("engine_streams", c_int32), ("tol_abs", c_int32), ("tol_floor", c_int32),
-                ("nested_start", c_int32), ("nested_tol", c_double), ("lock_rel", c_double)]
+                ("nested_start", c_int32), ("nested_tol", c_double), ("lock_rel", c_double),
+                ("throw_precond", c_int32), ("reserved_opts", c_int32)]
 
 
 class BlInfo(ctypes.Structure):

@@ -65,13 +65,13 @@ def test_batch_matches_dense_and_alone(precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_batch_with_soft_locking_matches_dense(precision):
-    """Soft locking in engines of several slots (the three 16x16 problems share one, with
+    """Soft locking, and one preconditioned throw-away vector, in engines of several slots (the three 16x16 problems share one, with
     different nev): the slots share one column count, so a slot may keep converged pairs
     unlocked; every problem still matches the dense oracle.  (Alone and in a batch may differ
     in the last bits here: the shared column count couples the slots' bases.)"""
     from paper_2304_00337_amd import batch_solve
     probs = _problems()
-    res = batch_solve(probs, precision=precision, lock_rel=1.0, **OPTS)
+    res = batch_solve(probs, precision=precision, lock_rel=1.0, throw_precond=1, **OPTS)
     tol = 1e-9 if precision == "fp64" else 1e-6
     for pr, r in zip(probs, res):
         assert r["status"] == 0, r

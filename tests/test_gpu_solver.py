@@ -361,6 +361,37 @@ def test_soft_locking_keeps_the_results(precision):
         Solver(n, n, 1.0, 1.0, eps, nev=nev, nthrow=nthrow, lock_rel=1.5)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fewer_preconditioned_throwaway_vectors_keep_the_results(precision):
+    """Only the first throw-away vector gets a preconditioned direction (throw_precond = 1),
+    the others stay in the block and are refined by the Ritz step alone: the path's
+    eigenvalues still match the dense solve at the stated tolerance, with at most a third
+    more iterations, and the option is checked."""
+    n = 32
+    eps = synth.eps_disc_lattice(n, n, 1.0, 1.0, 12.0, 0.3)
+    ks = synth.path_gxmg(3)[:5]
+    nev, nthrow = 8, 4
+    start = synth.start_block(2 * n * n, nev + nthrow, 6)
+    from paper_2304_00337_amd import Solver
+    from paper_2304_00337_amd.native import BlochError
+    its = {}
+    tol = 1e-9 if precision == "fp64" else 1e-6
+    for tp in (0, 1):
+        s = Solver(n, n, 1.0, 1.0, eps, nev=nev, nthrow=nthrow, mu=10.0, precision=precision,
+                   tol=1e-9, max_iter=300, throw_precond=tp)
+        r = s.solve_path(ks, start=start)
+        assert r["converged"], tp
+        for t, k in enumerate(ks):
+            ref, _, _ = dense_eigs(fem.Discretization(n, n, 1.0, 1.0, eps, *k), nev)
+            assert np.max(np.abs(r["evals"][t] - ref) / ref) < tol, (tp, t)
+        its[tp] = int(np.sum(r["iterations"]))
+        if tp:
+            assert s.info()["locked_columns"] >= 3 * its[tp] - 3 * len(ks)
+    assert its[1] <= 1.35 * its[0] + 2
+    with pytest.raises(BlochError):
+        Solver(n, n, 1.0, 1.0, eps, nev=nev, nthrow=nthrow, throw_precond=-1)
+
+
 def test_mixed_equals_fp64_and_alone_equals_repeat():
     prob = synth.config_c1()
     s64 = _solver(prob, "fp64", levels=3, nthrow=4, max_iter=300)
