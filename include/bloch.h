@@ -155,8 +155,10 @@ typedef struct bl_info {
   int32_t fused_nodal_level;  /* same for the nodal V-cycle (cycle precision)            */
   int32_t reserved;
   double autotune_ms;   /* time spent tuning at creation (0 when cached or off)        */
-  int64_t locked_columns; /* soft-locked columns (bl_opts.lock_rel) summed over the
-                             iterations and slots since creation                        */
+  int64_t locked_columns; /* columns left without a preconditioned direction (soft
+                             locking, bl_opts.lock_rel, and the throw-away vectors past
+                             bl_opts.throw_precond), summed over the iterations and slots
+                             since creation                                             */
 } bl_info;
 
 /* Fill *opts with the defaults for `nev` wanted eigenpairs (nthrow = nev/2). */

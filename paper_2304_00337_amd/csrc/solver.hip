@@ -1191,7 +1191,7 @@ void engine_destroy(bl_solver* s) {
   if (s->st) (void)hipStreamSynchronize(s->st);
   else (void)hipDeviceSynchronize();
   if (s->debug && s->rounds > 0)
-    std::fprintf(stderr, "bloch: %lld rounds, %.2f soft-locked columns per round\n", (long long)s->rounds,
+    std::fprintf(stderr, "bloch: %lld rounds, %.2f columns per round without a preconditioned direction\n", (long long)s->rounds,
                  (double)s->locked_cols / (double)s->rounds);
   for (void* p : s->allocs) (void)hipFree(p);
   if (s->lists_h) (void)hipHostFree(s->lists_h);
