@@ -5,7 +5,7 @@ last point before Gamma); with --z2, of the band-structure experiment's cell (ep
 the disc of radius 0.18, 16 pairs) at 256 x 256 on its kappa = 30 raster at the two points
 next to Gamma, (i, j) = (14, 14) and (15, 14); with --c3, of the 1024 x 1024 random
 two-phase workload (32 pairs) at its first point after Gamma and at X (the stored file also
-holds the last point before Gamma, index 59, added with --add 59); with --c4small, of
+holds M and the last point before Gamma, indices 40 and 59, added with --add); with --c4small, of
 the six problems of synth.config_c4_small (n 64..128, nev 4..16); with --c3 --add i,j, the
 listed path points of the 1024 x 1024 workload, merged into its existing file.  Source:
 oracle.dense.gradient_free_eigs (ARPACK on the pencil restricted to the complement of the

@@ -24,7 +24,7 @@ and sweep tiles (32 x 32 plus halo) away from the periodic seam need n >= 192 an
   Gamma, and a 512 x 512 point closer still): mixed equals FP64 to 1e-6 and the oracle's
   ARPACK values;
 * the 1024 x 1024 headline workload (32 + 16 vectors, tolerance 1e-6, nested start) at the
-  first point after Gamma, at X and at the last point before Gamma, mixed precision, against
+  first point after Gamma, at X, at M and at the last point before Gamma, mixed precision, against
   the oracle's ARPACK values (tests/golden/arpack_c3_1024.json) to 1e-6.
 """
 import json
@@ -314,8 +314,8 @@ def test_mixed_close_to_gamma_512():
 def test_c3_points_against_arpack():
     """The 1024 x 1024 random two-phase workload in mixed precision, each point started from
     the nested iteration as in the measured run, against the oracle's certified ARPACK
-    values at the first point after Gamma, at X and at the last point before Gamma (on the
-    diagonal leg, the smallest acoustic eigenvalue of the path): every one of the 32
+    values at the first point after Gamma, at X, at M and at the last point before Gamma (on
+    the diagonal leg, the smallest acoustic eigenvalue of the path): every one of the 32
     eigenvalues to 1e-6."""
     from paper_2304_00337_amd import Solver
     gold = _golden("arpack_c3_1024.json")
